@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark: DG time-unknowns solved per second to relative residual 1e-10.
+
+Workload (one MI355X): u' + u = f on (0, 1000], u0 = 1, N = 2^22 uniform
+slabs, DG degree p (default 3; --p), Legendre basis, f a seeded 16-mode random
+Fourier series; V-cycle (or --cycle W) with 2/2 damped block Jacobi sweeps,
+coarsening by 2 down to 2 slabs, solved from u = 0 to ||r|| <= 1e-10 ||r_0||.
+A step is one whole solve (tmg_solve) with f, u0 and u resident in HBM.
+
+Prints one JSON line with the headline number, a sweep over p = 0..3, the
+roofline of the dominant kernel (level-0 down leg: nu1 sweeps + residual +
+restriction) timed with HIP events on its launch stream, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=22)
+    ap.add_argument("--cycle", choices=["V", "W"], default="V")
+    ap.add_argument("--sweep", type=int, default=1, help="also time p = 0..3 (1) or not (0)")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-log2n", type=int, default=15)
+    return ap.parse_args()
+
+
+def gpu_solve_rate(p, log2n, cycle, steps, warmup):
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    N = 1 << log2n
+    T = 1000.0 * N / (1 << 22)          # keep tau = 1000 / 2^22 for any N
+    w = gen.config2(p, N=N, T=T)
+    inst = w.instances[0]
+    f = torch.as_tensor(inst.f, dtype=torch.float64, device="cuda")
+    u0 = torch.tensor([inst.u0], dtype=torch.float64, device="cuda")
+    u = torch.empty_like(f)
+    s = Solver([N], [T], [inst.lam], p=p, gamma=1 if cycle == "V" else 2)
+    res = None
+    for _ in range(warmup):
+        res = s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    unknowns = N * (p + 1)
+    return dict(p=p, N=N, unknowns=unknowns, ms_per_solve=dt * 1e3,
+                unknowns_per_s=unknowns / dt, cycles=res.cycles[0], relres=res.relres[0],
+                status=res.status), (s, f, u0, u)
+
+
+def kernel_roofline(p, ctx, reps):
+    """Average duration of the level-0 down kernel (nu1 = 2 sweeps, residual,
+    restriction) timed with HIP events on the stream it is launched on.
+    Algorithmic bytes per fine unknown: read u, f (16 B), write u (8 B),
+    write the restricted residual (4 B) = 28 B."""
+    import torch
+    s, f, u0, u = ctx
+    N = s.n_slabs[0]
+    P = p + 1
+    ub = torch.empty_like(u)
+    rc = torch.empty(N // 2 * P, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s.down(0, f, u, ub, rc, nsweep=2, fold_u0=u0)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        s.down(0, f, u, ub, rc, nsweep=2, fold_u0=u0)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bytes_alg = 28.0 * N * P
+    gbs = bytes_alg / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=f"k_down<P={P}> level 0, N=2^{N.bit_length() - 1}",
+                avg_us=round(ms * 1e3, 2), bytes_per_launch=bytes_alg)
+
+
+def cpu_baseline(p, log2n):
+    """FP64 oracle (plain C, single thread) multigrid solve of the first 2^log2n
+    slabs of the same workload (same tau, same f recipe), unknowns/s."""
+    from oracle import core
+    from workloads import gen
+    N = 1 << log2n
+    T = 1000.0 * N / (1 << 22)
+    inst = gen.config2(p, N=N, T=T).instances[0]
+    t0 = time.perf_counter()
+    _, k, rr, _ = core.solve(p, T, inst.lam, inst.u0, inst.f, rtol=1e-10)
+    dt = time.perf_counter() - t0
+    return dict(value=N * (p + 1) / dt, unit="unknowns/s", cores=1, kind="oracle",
+                sample=f"oracle V-cycle solve to 1e-10 of N=2^{log2n} slabs, p={p}, "
+                       f"tau=1000/2^22 ({k} cycles, {dt:.1f} s)")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solve is not "
+              "sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    head, ctx = gpu_solve_rate(a.p, a.log2n, a.cycle, a.steps, a.warmup)
+    roof = kernel_roofline(a.p, ctx, a.kernel_reps)
+    del ctx
+    sweep = []
+    if a.sweep:
+        for p in range(4):
+            if p == a.p:
+                sweep.append(head)
+                continue
+            r, c = gpu_solve_rate(p, a.log2n, a.cycle, max(2, a.steps // 2), 1)
+            del c
+            sweep.append(r)
+    cpu = cpu_baseline(a.p, a.cpu_log2n) if a.cpu_baseline else None
+    out = {
+        "metric": "DG time-unknowns solved/s to rel. residual 1e-10",
+        "value": head["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"u'+u=f, T=1000, N=2^{a.log2n} slabs, p={a.p}, "
+                               f"{a.cycle}(2,2) cycle to 1e-10, 16-mode Fourier f",
+                   "cycles": head["cycles"], "relres": head["relres"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "sweep_p": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles")}
+                    for r in sweep],
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * tmg.h -- C ABI of the MI355X (gfx950) time-multigrid library for
+ * discontinuous-Galerkin-in-time discretisations of
+ *
+ *     u'(t) + lambda u(t) = f(t),  t in (0, T],   u(0) = u0,   lambda > 0
+ *
+ * following Gander & Neumueller, "Analysis of a time multigrid algorithm for
+ * DG-discretizations in time" (arXiv:1409.5254).  The paper's model problem
+ * (section 1, eq. chap4_ordinaryDGL) has lambda = 1; the discrete operator
+ * depends on lambda and the slab length tau only through z = lambda*tau, so
+ * every statement of the paper carries over with tau -> lambda*tau.
+ *
+ * Discretisation (section 2): N uniform slabs of length tau = T/N, degree-p
+ * polynomials on each slab in the Legendre basis psi_k(t) = P_k(xi),
+ * xi = 2(t - t_{n-1})/tau - 1, k = 0..p (P = p+1 coefficients per slab).
+ * The block lower-bidiagonal system (eq. chap4_generalLinearSystemODE) is
+ *     (K + lambda M) u_n - N u_{n-1} = f_n,   n = 1..N,
+ * K[k,l] = 1 - 2[l < k, k+l odd], M = tau diag(1/(2k+1)), N = v 1^T with
+ * v[k] = (-1)^k; the initial value enters slab 1 as f_1 += u0 v.
+ *
+ * Multigrid (section 3): nu1 / nu2 damped block Jacobi sweeps
+ * (eq. chap4_ODESmoother) with the per-level optimal damping of Lemma
+ * chap4_lemma7, factor-2 restriction / prolongation (eqs.
+ * chap4_restrictionTime, chap4_prolongationTime), coarse operators
+ * rediscretised at 2 tau, applied recursively as a V (gamma = 1) or W
+ * (gamma = 2) cycle down to n_coarse slabs, where the system is solved
+ * exactly by a parallel prefix scan over the per-slab affine maps of the end
+ * values.  Iteration stops at ||f - L u||_2 <= rtol ||f - L 0||_2 per
+ * instance (the residual-reduction criterion of section 4.2).
+ *
+ * DATA LAYOUT.  Every solution / right-hand-side array is float64, on the
+ * device, contiguous, [instance][slab][k]: coefficient k of slab n of
+ * instance j at  off_j + n*P + k,  off_j = P * sum_{i<j} N_i  (int64).
+ * Load vectors f hold f_n[k] = int f(t) psi_k(t) dt over slab n WITHOUT the
+ * initial value (the library folds u0).  u0, lambda, T and per-instance
+ * outputs are arrays of length `batch`.
+ *
+ * OWNERSHIP.  The caller owns every array passed in; the library never frees
+ * or retains them beyond the call (graphs captured for a set of pointers are
+ * re-captured when the pointers change).  The handle owns its tables,
+ * hierarchy buffers, graphs and streams.  Every call is ordered on the given
+ * stream (a hipStream_t; NULL = the default stream).  tmg_solve and
+ * tmg_adjoint_solve block until the solve has finished (they read residual
+ * norms); tmg_vcycle and the tmg_op_* calls are asynchronous.  A handle must
+ * not be used from two host threads at once.
+ *
+ * ERRORS.  0 = TMG_OK; TMG_NOT_CONVERGED (> 0) when max_cycles was reached
+ * (outputs valid, relres reports how far it got); negative codes are errors
+ * and leave outputs unspecified.  Argument checks run on the host before any
+ * device work.
+ */
+#ifndef TMG_H
+#define TMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tmg_ctx *tmg_handle;
+typedef void *tmg_stream; /* hipStream_t */
+
+enum {
+    TMG_OK = 0,
+    TMG_NOT_CONVERGED = 1,
+    TMG_ERR_INVALID = -1,     /* null pointer, batch < 1, bad option value        */
+    TMG_ERR_SIZE = -2,        /* N_j not n_coarse * 2^k, or too large              */
+    TMG_ERR_OMEGA = -3,       /* fixed omega outside (0, 1]                        */
+    TMG_ERR_PARAM = -4,       /* lambda or T not finite and > 0                    */
+    TMG_ERR_OOM = -5,         /* device allocation failed                          */
+    TMG_ERR_HIP = -6,         /* a HIP call failed (see tmg_last_hip_error)        */
+    TMG_ERR_NONFINITE = -7,   /* NaN / Inf in the data or the residual             */
+    TMG_ERR_DIVERGED = -8,    /* residual grew beyond 1e3 * initial residual       */
+    TMG_ERR_UNSUPPORTED = -9  /* option combination not built into the library    */
+};
+
+typedef struct {
+    int p;            /* DG degree, 0 <= p <= TMG_MAX_DEGREE                        */
+    int nu1, nu2;     /* pre / post smoothing sweeps, 0..8 (default 2, 2)           */
+    int gamma;        /* 1 = V-cycle, 2 = W-cycle                                   */
+    int64_t n_coarse; /* coarsest slab count, 1..4096 (default 2)                   */
+    int omega_mode;   /* 0 = optimal per level (Lemma chap4_lemma7), 1 = fixed      */
+    double omega;     /* damping when omega_mode == 1, in (0, 1]                    */
+    int precision;    /* 0 = FP64; 1 = FP32 smoothing / transfers, FP64 residual,
+                         FP64 coarsest scan, FP64 outer defect correction          */
+    int schedule;     /* kernel schedule id, -1 = library default                   */
+} tmg_options;
+
+#define TMG_MAX_DEGREE 3
+
+/* Fill *opt with the defaults: p = 1, nu1 = nu2 = 2, V-cycle, n_coarse = 2,
+ * optimal damping, FP64, default schedule. */
+void tmg_default_options(tmg_options *opt);
+
+/*
+ * Build a solver for `batch` independent instances; instance j has
+ * n_slabs[j] slabs on (0, T[j]] and decay rate lambda[j] (host arrays of
+ * length batch).  Every n_slabs[j] must equal opt->n_coarse * 2^k (k >= 0).
+ * Computes the per-level tables (section 2.1 matrices, alpha = the nonzero
+ * eigenvalue of (K + lambda M)^{-1} N per Lemma chap4_theorem2, damping per
+ * Lemma chap4_lemma7, transfer matrices R_i^T = M^{-1} Mt^i of section 4.2),
+ * allocates the hierarchy (about 2x the fine-level size per array) and
+ * uploads everything on stream s.  On success *h owns all device memory.
+ */
+int tmg_setup(tmg_handle *h, int batch, const int64_t *n_slabs, const double *T,
+              const double *lambda, const tmg_options *opt, tmg_stream s);
+
+/*
+ * One multigrid cycle in place: u (device, in/out) is the initial guess and
+ * receives the result; f the load vectors, u0 the initial values (device,
+ * length batch).  The cycle of eq. chap4_errorTwoGridCycle applied
+ * recursively.  Asynchronous on s.
+ */
+int tmg_vcycle(tmg_handle h, const double *f, const double *u0, double *u, tmg_stream s);
+
+/*
+ * Solve L u = f from u = 0 with repeated cycles until every instance reaches
+ * ||f - L u||_2 <= rtol ||f||_2 (u0 folded) or max_cycles.  cycles[batch]
+ * and relres[batch] (host, may be NULL) receive per-instance counts and
+ * final relative residuals.  Blocks until done.  Returns TMG_OK,
+ * TMG_NOT_CONVERGED, TMG_ERR_NONFINITE or TMG_ERR_DIVERGED (the worst
+ * instance decides).
+ */
+int tmg_solve(tmg_handle h, const double *f, const double *u0, double *u, double rtol,
+              int max_cycles, int *cycles, double *relres, tmg_stream s);
+
+/*
+ * Adjoint solve: L^T z = g (device arrays, same layout) backward in time,
+ * (L^T z)_n = A^T z_n - 1 (v^T z_{n+1}), by the same multigrid cycle applied
+ * to L^T (transposed block Jacobi, the same R and P, backward scan on the
+ * coarsest level), from z = 0 to ||g - L^T z|| <= rtol ||g||.  If u
+ * (the forward solution, device) is not NULL, also returns for each instance
+ *   dlambda[j] = -sum_n z_n^T M_tau u_n   and   du0[j] = v^T z_1
+ * (host arrays, may be NULL): the gradients of a loss J(u) with dJ/du = g
+ * with respect to lambda and u0; dJ/df = z itself.  Blocks until done.
+ */
+int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z, double rtol,
+                      int max_cycles, double *dlambda, double *du0, int *cycles,
+                      double *relres, tmg_stream s);
+
+/* Release every resource of h (synchronises its streams first). */
+int tmg_destroy(tmg_handle h);
+
+/* Static, NUL-terminated description of a status code. */
+const char *tmg_error_string(int code);
+
+/* The last hipError_t seen by h (0 if none). */
+int tmg_last_hip_error(tmg_handle h);
+
+/* ------------------------------------------------------------------------
+ * Level-wise entry points: the individual kernels of one cycle, on all
+ * instances of h at hierarchy level `level` (0 = finest).  Arrays are device
+ * arrays laid out like the level: [instance][slab][k] with instance j holding
+ * n_slabs[j] >> level slabs (instances whose hierarchy is shorter are
+ * skipped).  `trans` = 1 selects the transposed (adjoint, backward-in-time)
+ * operator.  Used for kernel-by-kernel verification and timing; all are
+ * asynchronous on s.
+ * --------------------------------------------------------------------- */
+
+/* Number of levels of instance j (level 0 .. n-1), its slab count and
+ * the alpha / omega used there; returns the level count or an error. */
+int tmg_level_info(tmg_handle h, int j, int level, int64_t *n_slabs, double *alpha,
+                   double *omega);
+
+/* Total coefficients (sum over instances of (n_slabs[j] >> level) * P). */
+int64_t tmg_level_size(tmg_handle h, int level);
+
+/*
+ * Down leg: nsweep damped block Jacobi sweeps u_out = S^nsweep u_in for
+ * L_level u = f (u_in == NULL: zero initial guess), then the residual
+ * r = f - L u_out and its restriction rc = R r (eq. chap4_restrictionTime)
+ * into the next level's layout (rc may be NULL to skip).  If fold_u0 != NULL
+ * (level 0 only), the initial values are folded into slab 1 of f on the fly.
+ */
+int tmg_op_down(tmg_handle h, int level, int trans, int nsweep, const double *f,
+                const double *fold_u0, const double *u_in, double *u_out, double *rc,
+                tmg_stream s);
+
+/*
+ * Up leg: u_out = S^nsweep (u_in + P e) (eq. chap4_prolongationTime) with e
+ * in the next level's layout; fold_u0 as for tmg_op_down.
+ */
+int tmg_op_up(tmg_handle h, int level, int trans, int nsweep, const double *f,
+              const double *fold_u0, const double *u_in, const double *e, double *u_out,
+              tmg_stream s);
+
+/* Exact solve L_level e = r on every instance by the parallel affine prefix
+ * scan (forward in time; backward for trans = 1).  Requires
+ * n_slabs[j] >> level <= 4096. */
+int tmg_op_coarse_solve(tmg_handle h, int level, int trans, const double *r, double *e,
+                        tmg_stream s);
+
+/* Per-instance residual norms ||f - L u||_2 at level 0 (host output array of
+ * length batch; blocks).  fold_u0 as above. */
+int tmg_op_residual_norm(tmg_handle h, int trans, const double *f, const double *fold_u0,
+                         const double *u, double *norms, tmg_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMG_H */

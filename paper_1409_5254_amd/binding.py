@@ -1,0 +1,229 @@
+"""ctypes binding of ``libtmg.so`` (the C ABI declared in ``include/tmg.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Tensors are passed as device pointers (float64, contiguous, on the current
+HIP device); the stream is torch's current stream.  There is no CPU
+fallback: if the library is not built, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libtmg.so")
+
+TMG_OK = 0
+TMG_NOT_CONVERGED = 1
+ERRORS = {
+    -1: "TMG_ERR_INVALID", -2: "TMG_ERR_SIZE", -3: "TMG_ERR_OMEGA", -4: "TMG_ERR_PARAM",
+    -5: "TMG_ERR_OOM", -6: "TMG_ERR_HIP", -7: "TMG_ERR_NONFINITE", -8: "TMG_ERR_DIVERGED",
+    -9: "TMG_ERR_UNSUPPORTED",
+}
+MAX_DEGREE = 3
+
+# every symbol the header declares
+SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",
+           "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
+           "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_coarse_solve",
+           "tmg_op_residual_norm"]
+
+
+class TmgError(RuntimeError):
+    def __init__(self, code: int, where: str, hip: int = 0):
+        self.code = code
+        msg = f"{where}: {ERRORS.get(code, code)} ({error_string(code)})"
+        if hip:
+            msg += f", hipError {hip}"
+        super().__init__(msg)
+
+
+class Options(ctypes.Structure):
+    """Mirror of ``tmg_options``."""
+    _fields_ = [("p", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("gamma", ctypes.c_int), ("n_coarse", ctypes.c_int64),
+                ("omega_mode", ctypes.c_int), ("omega", ctypes.c_double),
+                ("precision", ctypes.c_int), ("schedule", ctypes.c_int)]
+
+    @classmethod
+    def make(cls, **kw) -> "Options":
+        o = cls()
+        lib().tmg_default_options(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise AttributeError(k)
+            setattr(o, k, v)
+        return o
+
+
+_lib = None
+_i, _i64, _d, _vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {_LIB_PATH} "
+                               "(run python -m paper_1409_5254_amd.build)")
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        sig = {
+            "tmg_default_options": (None, [_vp]),
+            "tmg_setup": (_i, [P(_vp), _i, P(_i64), P(_d), P(_d), _vp, _vp]),
+            "tmg_vcycle": (_i, [_vp, _vp, _vp, _vp, _vp]),
+            "tmg_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d), _vp]),
+            "tmg_adjoint_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_d), P(_d), P(_i), P(_d),
+                                       _vp]),
+            "tmg_destroy": (_i, [_vp]),
+            "tmg_error_string": (ctypes.c_char_p, [_i]),
+            "tmg_last_hip_error": (_i, [_vp]),
+            "tmg_level_info": (_i, [_vp, _i, _i, P(_i64), P(_d), P(_d)]),
+            "tmg_level_size": (_i64, [_vp, _i]),
+            "tmg_op_down": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_op_up": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_op_coarse_solve": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+            "tmg_op_residual_norm": (_i, [_vp, _i, _vp, _vp, _vp, P(_d), _vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().tmg_error_string(code).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class SolveResult:
+    u: torch.Tensor
+    cycles: list
+    relres: list
+    status: int
+
+
+class Solver:
+    """One handle: `batch` instances with n_slabs[j] slabs on (0, T[j]] and
+    decay rate lam[j].  Arrays are flat float64 device tensors laid out
+    [instance][slab][k]."""
+
+    def __init__(self, n_slabs, T, lam, **opts):
+        n_slabs = [int(n) for n in n_slabs]
+        self.batch = len(n_slabs)
+        self.n_slabs = n_slabs
+        self.T = [float(x) for x in T]
+        self.lam = [float(x) for x in lam]
+        self.opts = Options.make(**opts)
+        self.P = self.opts.p + 1
+        self.size = sum(n_slabs) * self.P
+        self.offsets = [0]
+        for n in n_slabs:
+            self.offsets.append(self.offsets[-1] + n * self.P)
+        h = ctypes.c_void_p()
+        arr64 = (ctypes.c_int64 * self.batch)(*n_slabs)
+        arrT = (ctypes.c_double * self.batch)(*self.T)
+        arrL = (ctypes.c_double * self.batch)(*self.lam)
+        rc = lib().tmg_setup(ctypes.byref(h), self.batch, arr64, arrT, arrL,
+                             ctypes.byref(self.opts), _stream())
+        if rc != TMG_OK:
+            raise TmgError(rc, "tmg_setup")
+        self._h = h
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, where):
+        if rc < 0:
+            raise TmgError(rc, where, lib().tmg_last_hip_error(self._h))
+        return rc
+
+    # -- whole solves ----------------------------------------------------
+    def solve(self, f, u0, u=None, rtol=1e-10, max_cycles=100) -> SolveResult:
+        if u is None:
+            u = torch.empty_like(f)
+        cyc = (ctypes.c_int * self.batch)()
+        rr = (ctypes.c_double * self.batch)()
+        rc = lib().tmg_solve(self._h, _ptr(f), _ptr(u0), _ptr(u), rtol, max_cycles, cyc, rr,
+                             _stream())
+        self._check(rc, "tmg_solve")
+        return SolveResult(u, list(cyc), list(rr), rc)
+
+    def vcycle(self, f, u0, u):
+        self._check(lib().tmg_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),
+                    "tmg_vcycle")
+        return u
+
+    def adjoint_solve(self, g, u=None, z=None, rtol=1e-10, max_cycles=100):
+        """Returns (z, dlambda[batch], du0[batch], cycles, relres, status)."""
+        if z is None:
+            z = torch.empty_like(g)
+        dl = (ctypes.c_double * self.batch)()
+        du = (ctypes.c_double * self.batch)()
+        cyc = (ctypes.c_int * self.batch)()
+        rr = (ctypes.c_double * self.batch)()
+        rc = lib().tmg_adjoint_solve(self._h, _ptr(g), _ptr(u), _ptr(z), rtol, max_cycles, dl, du,
+                                     cyc, rr, _stream())
+        self._check(rc, "tmg_adjoint_solve")
+        return z, list(dl), list(du), list(cyc), list(rr), rc
+
+    # -- level-wise kernels ----------------------------------------------
+    def level_info(self, j: int, level: int):
+        n = ctypes.c_int64()
+        a = ctypes.c_double()
+        w = ctypes.c_double()
+        rc = lib().tmg_level_info(self._h, j, level, ctypes.byref(n), ctypes.byref(a),
+                                  ctypes.byref(w))
+        self._check(rc, "tmg_level_info")
+        return rc, n.value, a.value, w.value
+
+    def level_size(self, level: int) -> int:
+        return int(lib().tmg_level_size(self._h, level))
+
+    def down(self, level, f, u_in=None, u_out=None, rc=None, nsweep=2, trans=False,
+             fold_u0=None):
+        r = lib().tmg_op_down(self._h, level, int(trans), nsweep, _ptr(f), _ptr(fold_u0),
+                              _ptr(u_in), _ptr(u_out), _ptr(rc), _stream())
+        self._check(r, "tmg_op_down")
+
+    def up(self, level, f, u_in, e=None, u_out=None, nsweep=2, trans=False, fold_u0=None):
+        r = lib().tmg_op_up(self._h, level, int(trans), nsweep, _ptr(f), _ptr(fold_u0),
+                            _ptr(u_in), _ptr(e), _ptr(u_out), _stream())
+        self._check(r, "tmg_op_up")
+
+    def coarse_solve(self, level, r, e, trans=False):
+        rc = lib().tmg_op_coarse_solve(self._h, level, int(trans), _ptr(r), _ptr(e), _stream())
+        self._check(rc, "tmg_op_coarse_solve")
+
+    def residual_norm(self, f, u, fold_u0=None, trans=False):
+        out = (ctypes.c_double * self.batch)()
+        rc = lib().tmg_op_residual_norm(self._h, int(trans), _ptr(f), _ptr(fold_u0), _ptr(u),
+                                        out, _stream())
+        self._check(rc, "tmg_op_residual_norm")
+        return list(out)

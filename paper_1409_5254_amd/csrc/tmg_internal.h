@@ -1,0 +1,112 @@
+// Internal declarations shared by the host driver (tmg_capi.cpp), the table
+// builder (tmg_tables.cpp) and the HIP kernels (tmg_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmg {
+
+constexpr int kMaxP = 4;        // P = p + 1 coefficients per slab
+constexpr int kThreads = 256;   // work-group size of the streaming kernels
+constexpr int kMaxSweeps = 8;
+constexpr int64_t kMaxCoarse = 4096;
+
+// Slabs held by one thread of a streaming kernel (even, so that the two fine
+// slabs of a coarse slab always sit in the same thread).  S*P doubles per
+// array and thread.
+constexpr int slabs_per_thread(int P) { return P == 1 ? 8 : (P == 2 ? 4 : 2); }
+constexpr int tile_slabs(int P) { return kThreads * slabs_per_thread(P); }
+
+// Per-(instance, level) table block, doubles, for P coefficients per slab.
+// Aop is the diagonal block of the operator (A = K + lambda M, or A^T for the
+// transposed system); c the end-value functional (w = c^T u), v the
+// injection vector (r = f + v w_left - Aop u).
+struct TabLayout {
+    int P;
+    __host__ __device__ constexpr TabLayout(int P_) : P(P_) {}
+    __host__ __device__ constexpr int A() const { return 0; }             // P*P  Aop
+    __host__ __device__ constexpr int G() const { return P * P; }         // P*P  omega Aop^{-1}
+    __host__ __device__ constexpr int H() const { return 2 * P * P; }     // P    omega Aop^{-1} v
+    __host__ __device__ constexpr int C() const { return 2 * P * P + P; } // P    c
+    __host__ __device__ constexpr int V() const { return 2 * P * P + 2 * P; } // P  v
+    __host__ __device__ constexpr int Q() const { return 2 * P * P + 3 * P; } // P  Aop^{-1} v
+    __host__ __device__ constexpr int AI() const { return 2 * P * P + 4 * P; } // P*P Aop^{-1}
+    __host__ __device__ constexpr int OMC() const { return 3 * P * P + 4 * P; } // 1 - omega
+    __host__ __device__ constexpr int ALPHA() const { return 3 * P * P + 4 * P + 1; }
+    __host__ __device__ constexpr int stride() const { return ((3 * P * P + 4 * P + 2 + 3) / 4) * 4; }
+};
+
+// Per-instance solve state, written by the finalize kernels.
+struct InstState {
+    double r0sq;   // ||r_0||^2
+    double rsq;    // ||r_k||^2 of the last completed cycle
+    int cycles;    // completed cycles
+    int done;      // 0 running, 1 converged, 2 max cycles, 3 non-finite, 4 diverged
+};
+
+struct Control {
+    double rtol2;  // rtol^2
+    int max_cycles;
+    int pad;
+};
+
+// Arguments of the streaming kernels (one level, all participating
+// instances).  Logical slab m of an instance is physical slab m (forward) or
+// N-1-m (backward, transposed system).
+struct LevelArgs {
+    const double *f;         // level right-hand side
+    const double *u0;        // fold values (level 0, forward) or null
+    const double *u_in;      // null: zero initial guess
+    double *u_out;           // null: no store
+    double *rc;              // down: restricted residual (next level), may be null
+    const double *e;         // up: coarse correction (next level), null: none
+    const double *tab;       // table blocks, instance j at tab + j*tab_stride
+    const double *R;         // R1T (P*P) then R2T (P*P), swapped for backward
+    const int64_t *slab_off; // [batch+1] slab offsets of this level
+    const int64_t *cslab_off;// [batch+1] slab offsets of the next level
+    const int64_t *tile_off; // [batch+1] tile offsets of this launch
+    const int64_t *norm_off; // [batch+1] partial-sum slots (null: no norm)
+    const InstState *st;     // per-instance early exit when st[j].done (may be null)
+    double *partial;         // per-tile sum of squared residuals
+    int batch;
+    int nsweep;
+    int halo;
+    int tile_out;
+    int tab_stride;
+};
+
+struct CoarseArgs {
+    const double *r;
+    const double *u0;        // fold values (level 0, forward) or null
+    double *e;
+    const double *tab;
+    const int64_t *slab_off;
+    const int *inst;         // participating instance ids, one work-group each
+    const InstState *st;     // may be null
+    int tab_stride;
+};
+
+// Host-side launchers (tmg_kernels.hip).  `backward` selects the transposed
+// system's backward-in-time indexing.  Return hipSuccess or the launch error.
+hipError_t launch_down(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s);
+hipError_t launch_up(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s);
+hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
+hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
+                         int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
+                         int batch, double *partial, int64_t ntiles, hipStream_t s);
+hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
+                           InstState *st, const Control *ctl, int is_r0, hipStream_t s);
+// out[2j] = -sum_n z_n^T M_tau u_n, out[2j+1] = v^T z_1 (tau[j]: fine slab length).
+hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,
+                       const int64_t *slab_off, int batch, double *out, hipStream_t s);
+
+// Host table builder (tmg_tables.cpp).  Fills one table block for a slab of
+// step z = lambda*tau (operator K + z diag(1/(2k+1))), transposed if trans.
+// omega_mode 0: optimal damping; 1: omega_fixed.  Returns alpha.
+double build_level_table(int P, double z, int omega_mode, double omega_fixed, bool trans,
+                         double *out);
+// R1T, R2T (P*P each, row-major) of the factor-2 transfer.
+void build_transfer(int P, double *R1T, double *R2T);
+
+}  // namespace tmg

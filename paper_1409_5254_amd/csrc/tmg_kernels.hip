@@ -1,0 +1,640 @@
+// HIP kernels (gfx950) of the time-multigrid cycle for DG-in-time
+// discretisations of u' + lambda u = f.
+//
+// All cycle kernels are HBM-bound streaming kernels (well under 1 flop/byte;
+// no MFMA).  A work-group of 256 threads owns a tile of consecutive slabs of
+// one instance, each thread S consecutive slabs (S*P doubles per array in
+// registers), and runs several steps on the tile without leaving registers:
+//
+//   k_down : nsweep damped block Jacobi sweeps (eq. chap4_ODESmoother), the
+//            residual r = f - L u and its factor-2 restriction
+//            (eq. chap4_restrictionTime);
+//   k_up   : prolongation and correction (eq. chap4_prolongationTime),
+//            nsweep sweeps, optionally the squared residual norm.
+//
+// A Jacobi sweep of slab n needs only the end value w_{n-1} = c^T u_{n-1} of
+// the *old* left neighbour: one double per slab, passed thread to thread
+// with a wavefront shuffle and wave to wave through LDS.  Dependencies run
+// one way in time, so a tile carries a left halo of `halo` slabs (>= sweeps
+// + 1) that is recomputed and discarded (temporal blocking); tiles write to
+// a buffer other than the one they read (ping-pong), so no tile can see a
+// neighbour's new values.
+//
+//   k_coarse : exact solve on the coarsest level as a parallel prefix scan
+//              over the per-slab affine maps w_n = alpha w_{n-1} + c^T A^{-1} r_n;
+//   k_norm_f, k_finalize : deterministic per-instance norms and the device
+//              side convergence state;
+//   k_grad   : adjoint gradient reductions.
+//
+// The transposed (adjoint) system runs the same kernels backward in time:
+// logical slab m is physical slab N-1-m, with A^T, c = v, v = 1 and R_1 / R_2
+// swapped in the tables passed by the host.
+#include <hip/hip_runtime.h>
+
+#include "tmg_internal.h"
+
+namespace tmg {
+namespace {
+
+constexpr int kWaves = kThreads / 64;
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Instance owning a tile: largest j with off[j] <= tile (off[0] = 0).
+__device__ __forceinline__ int find_instance(const int64_t *__restrict__ off, int batch,
+                                             int64_t tile)
+{
+    int lo = 0, hi = batch;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// End value of the left neighbour of this thread's first slab, for the
+// current sweep.  Double-buffered LDS slots (phase) need one barrier per call.
+__device__ __forceinline__ double left_value(double mine_last, double (*xchg)[kWaves], int &phase)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v = __shfl_up(mine_last, 1, 64);
+    if (lane == 63) xchg[phase][wave] = mine_last;
+    __syncthreads();
+    if (lane == 0) v = wave ? xchg[phase][wave - 1] : 0.0;
+    phase ^= 1;
+    return v;
+}
+
+// Sum over the work-group (fixed reduction tree); the result is valid in
+// thread 0.
+__device__ __forceinline__ double block_sum(double x, double *red)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kWaves; ++w) s += red[w];
+    return s;
+}
+
+// Load logical slabs [m0, m0+S) of an instance level with N slabs (zeros
+// outside [0, N)).  Backward: logical m is physical N-1-m.
+template <int P, int S, bool BW>
+__device__ __forceinline__ void load_chunk(const double *__restrict__ base, int64_t m0, int64_t N,
+                                           double (&x)[S][P])
+{
+    if (m0 >= 0 && m0 + S <= N) {
+        const int64_t plo = BW ? (N - m0 - S) : m0;
+        const double *src = base + plo * P;
+        double tmp[S * P];
+        if constexpr ((S * P) % 2 == 0) {
+            if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+                const d2 *vs = reinterpret_cast<const d2 *>(src);
+#pragma unroll
+                for (int i = 0; i < S * P / 2; ++i) {
+                    d2 t = vs[i];
+                    tmp[2 * i] = t.x;
+                    tmp[2 * i + 1] = t.y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < S * P; ++i) tmp[i] = src[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < S * P; ++i) tmp[i] = src[i];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) x[s][k] = tmp[(BW ? S - 1 - s : s) * P + k];
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t m = m0 + s;
+            const bool ok = m >= 0 && m < N;
+            const int64_t pm = BW ? N - 1 - m : m;
+#pragma unroll
+            for (int k = 0; k < P; ++k) x[s][k] = ok ? base[pm * P + k] : 0.0;
+        }
+    }
+}
+
+// Store logical slabs [m0, m0+S) whose tile-local index (li0 + s) is >= lo
+// and whose logical index is < N.
+template <int P, int S, bool BW>
+__device__ __forceinline__ void store_chunk(double *__restrict__ base, int64_t m0, int64_t N,
+                                            const double (&x)[S][P], int li0, int lo)
+{
+    if (li0 >= lo && m0 >= 0 && m0 + S <= N) {
+        const int64_t plo = BW ? (N - m0 - S) : m0;
+        double *dst = base + plo * P;
+        double tmp[S * P];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) tmp[(BW ? S - 1 - s : s) * P + k] = x[s][k];
+        if constexpr ((S * P) % 2 == 0) {
+            if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                d2 *vd = reinterpret_cast<d2 *>(dst);
+#pragma unroll
+                for (int i = 0; i < S * P / 2; ++i) {
+                    d2 t;
+                    t.x = tmp[2 * i];
+                    t.y = tmp[2 * i + 1];
+                    vd[i] = t;
+                }
+                return;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < S * P; ++i) dst[i] = tmp[i];
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t m = m0 + s;
+            if (li0 + s >= lo && m >= 0 && m < N) {
+                const int64_t pm = BW ? N - 1 - m : m;
+#pragma unroll
+                for (int k = 0; k < P; ++k) base[pm * P + k] = x[s][k];
+            }
+        }
+    }
+}
+
+// Level operator tables held in registers (uniform across the work-group).
+template <int P>
+struct Ops {
+    double A[P * P], G[P * P], h[P], c[P], v[P], omc;
+    __device__ __forceinline__ void load(const double *__restrict__ tab)
+    {
+        constexpr TabLayout L(P);
+#pragma unroll
+        for (int i = 0; i < P * P; ++i) {
+            A[i] = tab[L.A() + i];
+            G[i] = tab[L.G() + i];
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            h[k] = tab[L.H() + k];
+            c[k] = tab[L.C() + k];
+            v[k] = tab[L.V() + k];
+        }
+        omc = tab[L.OMC()];
+    }
+};
+
+// Fold the initial value into logical slab 0 (forward system, level 0):
+// f_1 += u0 v.
+template <int P, int S>
+__device__ __forceinline__ void fold_u0(double (&f)[S][P], int64_t m0, double u0, const Ops<P> &op)
+{
+    // branch-free select keeps f in registers (no dynamic indexing)
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const double a = (m0 + s == 0) ? u0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) f[s][k] += a * op.v[k];
+    }
+}
+
+// nsweep damped block Jacobi sweeps in registers:
+//   u_n <- (1 - omega) u_n + omega A^{-1} f_n + omega A^{-1} v w_{n-1},
+// the same update as u + omega D^{-1} (f - L u), with g = omega A^{-1} f
+// precomputed.
+template <int P, int S>
+__device__ __forceinline__ void sweeps(double (&u)[S][P], const double (&g)[S][P], const Ops<P> &op,
+                                       int nsweep, double (*xchg)[kWaves], int &phase)
+{
+    for (int sw = 0; sw < nsweep; ++sw) {
+        double w[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
+            w[s] = t;
+        }
+        const double wl = left_value(w[S - 1], xchg, phase);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double wn = s == 0 ? wl : w[s - 1];
+#pragma unroll
+            for (int k = 0; k < P; ++k) u[s][k] = op.omc * u[s][k] + g[s][k] + op.h[k] * wn;
+        }
+    }
+}
+
+// r_n = f_n + v w_{n-1} - A u_n.
+template <int P, int S>
+__device__ __forceinline__ void residual(double (&r)[S][P], const double (&u)[S][P],
+                                         const double (&f)[S][P], const Ops<P> &op,
+                                         double (*xchg)[kWaves], int &phase)
+{
+    double w[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
+        w[s] = t;
+    }
+    const double wl = left_value(w[S - 1], xchg, phase);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const double wn = s == 0 ? wl : w[s - 1];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double t = f[s][k] + op.v[k] * wn;
+#pragma unroll
+            for (int l = 0; l < P; ++l) t -= op.A[k * P + l] * u[s][l];
+            r[s][k] = t;
+        }
+    }
+}
+
+template <int P, int S>
+__device__ __forceinline__ void apply_G(double (&g)[S][P], const double (&f)[S][P], const Ops<P> &op)
+{
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = 0; l < P; ++l) t += op.G[k * P + l] * f[s][l];
+            g[s][k] = t;
+        }
+}
+
+template <int P, bool BW>
+__global__ __launch_bounds__(kThreads) void k_down(LevelArgs a)
+{
+    constexpr int S = slabs_per_thread(P);
+    __shared__ double xchg[2][kWaves];
+    __shared__ double red[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int j = find_instance(a.tile_off, a.batch, tile);
+    if (a.st && a.st[j].done) return;
+    const int64_t t = tile - a.tile_off[j];
+    const int64_t off = a.slab_off[j];
+    const int64_t N = a.slab_off[j + 1] - off;
+    Ops<P> op;
+    op.load(a.tab + (int64_t)j * a.tab_stride);
+
+    const int li0 = threadIdx.x * S;
+    const int64_t m0 = t * a.tile_out - a.halo + li0;
+    double f[S][P], u[S][P], g[S][P];
+    load_chunk<P, S, BW>(a.f + off * P, m0, N, f);
+    if (a.u0) fold_u0<P, S>(f, m0, a.u0[j], op);
+    if (a.u_in) {
+        load_chunk<P, S, BW>(a.u_in + off * P, m0, N, u);
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) u[s][k] = 0.0;
+    }
+    apply_G<P, S>(g, f, op);
+    int phase = 0;
+    sweeps<P, S>(u, g, op, a.nsweep, xchg, phase);
+
+    if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
+    if (!a.rc && !a.partial) return;
+
+    double r[S][P];
+    residual<P, S>(r, u, f, op, xchg, phase);
+    if (a.partial) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (li0 + s >= a.halo && m0 + s < N)
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
+    }
+    if (a.rc) {
+        const double *R1T = a.R, *R2T = a.R + P * P;
+        double rc[S / 2][P];
+#pragma unroll
+        for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s1 = 0.0;
+#pragma unroll
+                for (int l = 0; l < P; ++l)
+                    s1 += R1T[l * P + k] * r[2 * i][l] + R2T[l * P + k] * r[2 * i + 1][l];
+                rc[i][k] = s1;
+            }
+        const int64_t coff = a.cslab_off[j];
+        const int64_t Nc = a.cslab_off[j + 1] - coff;
+        store_chunk<P, S / 2, BW>(a.rc + coff * P, m0 / 2, Nc, rc, li0 / 2, a.halo / 2);
+    }
+}
+
+template <int P, bool BW>
+__global__ __launch_bounds__(kThreads) void k_up(LevelArgs a)
+{
+    constexpr int S = slabs_per_thread(P);
+    __shared__ double xchg[2][kWaves];
+    __shared__ double red[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int j = find_instance(a.tile_off, a.batch, tile);
+    if (a.st && a.st[j].done) return;
+    const int64_t t = tile - a.tile_off[j];
+    const int64_t off = a.slab_off[j];
+    const int64_t N = a.slab_off[j + 1] - off;
+    Ops<P> op;
+    op.load(a.tab + (int64_t)j * a.tab_stride);
+
+    const int li0 = threadIdx.x * S;
+    const int64_t m0 = t * a.tile_out - a.halo + li0;
+    double f[S][P], u[S][P], g[S][P];
+    load_chunk<P, S, BW>(a.f + off * P, m0, N, f);
+    if (a.u0) fold_u0<P, S>(f, m0, a.u0[j], op);
+    load_chunk<P, S, BW>(a.u_in + off * P, m0, N, u);
+    if (a.e) {
+        const int64_t coff = a.cslab_off[j];
+        const int64_t Nc = a.cslab_off[j + 1] - coff;
+        double e[S / 2][P];
+        load_chunk<P, S / 2, BW>(a.e + coff * P, m0 / 2, Nc, e);
+        const double *R1T = a.R, *R2T = a.R + P * P;
+#pragma unroll
+        for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    s1 += R1T[k * P + l] * e[i][l];
+                    s2 += R2T[k * P + l] * e[i][l];
+                }
+                u[2 * i][k] += s1;
+                u[2 * i + 1][k] += s2;
+            }
+    }
+    apply_G<P, S>(g, f, op);
+    int phase = 0;
+    sweeps<P, S>(u, g, op, a.nsweep, xchg, phase);
+    if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
+    if (a.partial) {
+        double r[S][P];
+        residual<P, S>(r, u, f, op, xchg, phase);
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (li0 + s >= a.halo && m0 + s < N)
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
+    }
+}
+
+// Exact solve of L e = r on one instance per work-group.  With
+// d_n = A^{-1} r_n and b_n = c^T d_n the end values obey the affine
+// recurrence w_n = alpha w_{n-1} + b_n (alpha = c^T A^{-1} v, w_{-1} = 0);
+// the maps x -> alpha x + b_n are composed by a work-group prefix scan
+// (wavefront shuffles, then LDS across waves), 256 slabs per pass with the
+// last end value carried, and e_n = d_n + A^{-1} v w_{n-1}.
+template <int P, bool BW>
+__global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
+{
+    constexpr TabLayout L(P);
+    __shared__ double wa[kWaves], wb[kWaves];
+    __shared__ double wend[kThreads];
+    const int j = a.inst[blockIdx.x];
+    if (a.st && a.st[j].done) return;
+    const int64_t off = a.slab_off[j];
+    const int64_t N = a.slab_off[j + 1] - off;
+    const double *tab = a.tab + (int64_t)j * a.tab_stride;
+    double AI[P * P], q[P], c[P], v[P];
+#pragma unroll
+    for (int i = 0; i < P * P; ++i) AI[i] = tab[L.AI() + i];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        q[k] = tab[L.Q() + k];
+        c[k] = tab[L.C() + k];
+        v[k] = tab[L.V() + k];
+    }
+    const double alpha = tab[L.ALPHA()];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double carry = 0.0;
+    for (int64_t base = 0; base < N; base += kThreads) {
+        const int64_t m = base + threadIdx.x;
+        const bool ok = m < N;
+        const int64_t pm = BW ? N - 1 - m : m;
+        double r[P], d[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) r[k] = ok ? a.r[(off + pm) * P + k] : 0.0;
+        if (a.u0 && m == 0) {
+            const double u0 = a.u0[j];
+#pragma unroll
+            for (int k = 0; k < P; ++k) r[k] += u0 * v[k];
+        }
+        double b = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = 0; l < P; ++l) t += AI[k * P + l] * r[l];
+            d[k] = t;
+            b += c[k] * t;
+        }
+        // inclusive scan of (A, B) ~ x -> A x + B in slab order
+        double A = ok ? alpha : 1.0, B = ok ? b : 0.0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const double Ao = __shfl_up(A, o, 64), Bo = __shfl_up(B, o, 64);
+            if (lane >= o) {
+                B = A * Bo + B;
+                A = A * Ao;
+            }
+        }
+        if (lane == 63) {
+            wa[wave] = A;
+            wb[wave] = B;
+        }
+        __syncthreads();
+        // compose the totals of the earlier waves and the carried end value
+        double Bp = carry;
+        for (int w = 0; w < wave; ++w) Bp = wa[w] * Bp + wb[w];
+        const double wm = A * Bp + B;   // end value of slab m
+        wend[threadIdx.x] = wm;
+        __syncthreads();
+        const double wprev = threadIdx.x == 0 ? carry : wend[threadIdx.x - 1];
+        if (ok)
+#pragma unroll
+            for (int k = 0; k < P; ++k) a.e[(off + pm) * P + k] = d[k] + q[k] * wprev;
+        const int64_t nlast = (N - base < kThreads) ? (N - base) : kThreads;
+        carry = wend[nlast - 1];
+        __syncthreads();
+    }
+}
+
+// Per-tile sum of squares of the folded load vector (the initial residual).
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_norm_f(const double *__restrict__ f,
+                                                     const double *__restrict__ u0,
+                                                     const double *__restrict__ tab, int tab_stride,
+                                                     const int64_t *__restrict__ slab_off,
+                                                     const int64_t *__restrict__ tile_off, int batch,
+                                                     double *__restrict__ partial)
+{
+    constexpr int S = slabs_per_thread(P);
+    constexpr TabLayout L(P);
+    __shared__ double red[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int j = find_instance(tile_off, batch, tile);
+    const int64_t t = tile - tile_off[j];
+    const int64_t off = slab_off[j];
+    const int64_t N = slab_off[j + 1] - off;
+    const int64_t m0 = t * tile_slabs(P) + threadIdx.x * S;
+    double x[S][P];
+    load_chunk<P, S, false>(f + off * P, m0, N, x);
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double y = x[s][k];
+            if (u0 && m0 + s == 0) y += u0[j] * tab[(int64_t)j * tab_stride + L.V() + k];
+            acc += y * y;
+        }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[tile] = acc;
+}
+
+// One work-group per instance: sum its partials in a fixed order and update
+// the convergence state (relative residual criterion of section 4.2).
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partial,
+                                                       const int64_t *__restrict__ norm_off,
+                                                       InstState *__restrict__ st,
+                                                       const Control *__restrict__ ctl, int is_r0)
+{
+    __shared__ double red[kWaves];
+    const int j = blockIdx.x;
+    if (!is_r0 && st[j].done) return;
+    const int64_t lo = norm_off[j], hi = norm_off[j + 1];
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) acc += partial[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        InstState s = st[j];
+        if (is_r0) {
+            s.r0sq = acc;
+            s.rsq = acc;
+            s.cycles = 0;
+            s.done = !isfinite(acc) ? 3 : (acc == 0.0 ? 1 : 0);
+        } else {
+            s.cycles += 1;
+            s.rsq = acc;
+            if (!isfinite(acc)) s.done = 3;
+            else if (acc <= ctl->rtol2 * s.r0sq) s.done = 1;
+            else if (acc > 1e6 * s.r0sq) s.done = 4;
+            else if (s.cycles >= ctl->max_cycles) s.done = 2;
+        }
+        st[j] = s;
+    }
+}
+
+// dlambda_j = -sum_n z_n^T M_tau u_n (M_tau = tau diag(1/(2k+1))),
+// du0_j = v^T z_1 (v[k] = (-1)^k): one work-group per instance.
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_grad(const double *__restrict__ u,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ tau,
+                                                   const int64_t *__restrict__ slab_off,
+                                                   double *__restrict__ out)
+{
+    __shared__ double red[kWaves];
+    const int j = blockIdx.x;
+    const int64_t off = slab_off[j];
+    const int64_t n = (slab_off[j + 1] - off) * P;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+        const int k = (int)(i % P);
+        acc += z[off * P + i] * u[off * P + i] / (2.0 * k + 1.0);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int k = 0; k < P; ++k) d += ((k & 1) ? -1.0 : 1.0) * z[off * P + k];
+        out[2 * j] = -tau[j] * acc;
+        out[2 * j + 1] = d;
+    }
+}
+
+}  // namespace
+
+#define TMG_DISPATCH_P(P, ...)                        \
+    switch (P) {                                      \
+    case 1: { constexpr int PP = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int PP = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int PP = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int PP = 4; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;             \
+    }
+
+hipError_t launch_down(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    TMG_DISPATCH_P(P, {
+        if (backward) hipLaunchKernelGGL((k_down<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_down<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+    })
+    return hipGetLastError();
+}
+
+hipError_t launch_up(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    TMG_DISPATCH_P(P, {
+        if (backward) hipLaunchKernelGGL((k_up<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_up<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+    })
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s)
+{
+    if (ninst <= 0) return hipSuccess;
+    TMG_DISPATCH_P(P, {
+        if (backward) hipLaunchKernelGGL((k_coarse<PP, true>), dim3(ninst), dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_coarse<PP, false>), dim3(ninst), dim3(kThreads), 0, s, a);
+    })
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
+                         int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
+                         int batch, double *partial, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    TMG_DISPATCH_P(P, {
+        hipLaunchKernelGGL((k_norm_f<PP>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, f, u0, tab,
+                           tab_stride, slab_off, tile_off, batch, partial);
+    })
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
+                           InstState *st, const Control *ctl, int is_r0, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kThreads), 0, s, partial, norm_off, st, ctl,
+                       is_r0);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,
+                       const int64_t *slab_off, int batch, double *out, hipStream_t s)
+{
+    TMG_DISPATCH_P(P, {
+        hipLaunchKernelGGL((k_grad<PP>), dim3(batch), dim3(kThreads), 0, s, u, z, tau, slab_off, out);
+    })
+    return hipGetLastError();
+}
+
+}  // namespace tmg
