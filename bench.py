@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-log2n", type=int, default=15)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="first run one plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -124,6 +126,13 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.copy_probe:
+        # a plain copy of known size: 512 MiB read + 512 MiB written
+        x = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     head, ctx = gpu_solve_rate(a.p, a.log2n, a.cycle, a.steps, a.warmup)
     roof = kernel_roofline(a.p, ctx, a.kernel_reps)
     del ctx

@@ -25,7 +25,7 @@ using namespace tmg;
 
 namespace {
 
-enum TileKind { kDeep = 0, kAll = 1, kSingle = 2 };
+enum TileKind { kDeep = 0, kAll = 1, kHasNext = 2 };
 
 struct TileList {
     int64_t ntiles = 0;
@@ -65,9 +65,14 @@ struct tmg_ctx {
     int64_t partial_cap = 0;
     double *tau_d = nullptr, *grad_d = nullptr, *grad_host = nullptr;
     std::map<std::tuple<int, int, int>, TileList> tiles;
-    std::vector<int *> coarse_inst_d;             // per level: instances whose coarsest level it is
-    std::vector<int> coarse_n;
-    std::vector<int> deep_n;                      // per level: instances with L_j - 1 > level
+    std::vector<int> lb;                          // first level of the bottom kernel, per instance
+    std::vector<int *> bot_visit_d, bot_coarse_d; // per level: bottom lists (visit / exact solve only)
+    std::vector<int> bot_visit_n, bot_coarse_n;
+    std::vector<int> deep_n;                      // per level: instances with level < lb[j]
+    int *lb_d = nullptr, *nlev_d = nullptr;
+    double **fl_d = nullptr, **ua_d = nullptr, **ub_d = nullptr;
+    int64_t **slab_off_dd = nullptr;
+    int64_t bottom_max = 0;
     std::map<std::tuple<int, int>, std::pair<int *, int>> op_coarse;  // (level, unused) -> list
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipStream_t cap = nullptr;
@@ -108,8 +113,8 @@ int dalloc(tmg_ctx *c, T **p, size_t n)
 bool participates(const tmg_ctx *c, int j, int level, int kind)
 {
     if (level >= c->L[j]) return false;
-    if (kind == kDeep) return c->L[j] - 1 > level;
-    if (kind == kSingle) return c->L[j] == 1 && level == 0;
+    if (kind == kDeep) return level < c->lb[j];      // streaming kernels in the cycle
+    if (kind == kHasNext) return level + 1 < c->L[j];  // level-wise entry points
     return true;
 }
 
@@ -218,69 +223,69 @@ int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, hipStream_t s)
     return TMG_OK;
 }
 
-int enqueue_coarse(tmg_ctx *c, const CycleIO &io, int level, hipStream_t s)
+// Bottom kernel for the instances whose single-work-group part starts at
+// `level`: exact solve only (coarse list) or a full visit (visit list).
+int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, bool visits, bool zero,
+                   hipStream_t s)
 {
-    if (c->coarse_n[level] == 0) return TMG_OK;
-    CoarseArgs a{};
-    a.r = level == 0 ? io.f : c->fl[level];
-    a.u0 = (level == 0 && !io.trans) ? io.u0 : nullptr;
-    a.e = level == 0 ? io.u : c->ua[level];
-    a.tab = tab_of(c, level, io.trans);
-    a.slab_off = c->slab_off_d[level];
-    a.inst = c->coarse_inst_d[level];
+    const int n = visits ? c->bot_visit_n[level] : c->bot_coarse_n[level];
+    if (n == 0) return TMG_OK;
+    BottomArgs a{};
+    a.fl = c->fl_d;
+    a.ua = c->ua_d;
+    a.ub = c->ub_d;
+    a.slab_off = c->slab_off_dd;
+    a.tab = io.trans ? c->tab_adj : c->tab_fwd;
+    a.R = io.trans ? c->R_adj : c->R_fwd;
+    a.inst = visits ? c->bot_visit_d[level] : c->bot_coarse_d[level];
+    a.lb = c->lb_d;
+    a.nlev = c->nlev_d;
+    a.f0 = io.f;
+    a.u0 = io.trans ? nullptr : io.u0;
+    a.u = io.u;
     a.st = io.use_state ? c->st : nullptr;
+    if (level == 0 && io.use_state) {
+        TileList *nl;
+        int rc = get_tiles(c, 0, kAll, c->TO_up(), s, &nl);
+        if (rc) return rc;
+        a.partial = c->partial;
+        a.norm_off = nl->d_off;
+    }
+    a.batch = c->batch;
     a.tab_stride = c->tab_stride;
-    HIPCHK(c, launch_coarse(c->P, io.trans, a, c->coarse_n[level], s));
+    a.nu1 = c->opt.nu1;
+    a.nu2 = c->opt.nu2;
+    a.gamma = c->opt.gamma;
+    a.zero = zero ? 1 : 0;
+    HIPCHK(c, launch_bottom(c->P, io.trans, a, n, s));
     return TMG_OK;
 }
 
-// Multigrid visit of `level` for the instances that have a coarser level:
-// nu1 sweeps + residual + restriction, the coarse problem (exact when the
-// next level is an instance's coarsest, else gamma visits from zero), then
+// Multigrid visit of `level` for the instances that run this level with the
+// streaming kernels (level < lb[j]): nu1 sweeps + residual + restriction,
+// gamma visits of the next level from zero (bottom kernel or recursion; an
+// exact solve once when the next level is an instance's coarsest), then
 // prolongation + correction + nu2 sweeps.
 int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero_init, hipStream_t s)
 {
     int rc = enqueue_down(c, io, level, zero_init, s);
     if (rc) return rc;
-    rc = enqueue_coarse(c, io, level + 1, s);
-    if (rc) return rc;
-    if (level + 1 < c->Lmax && c->deep_n[level + 1] > 0)
-        for (int g = 0; g < c->opt.gamma; ++g) {
-            rc = enqueue_visit(c, io, level + 1, g == 0, s);
-            if (rc) return rc;
-        }
+    if ((rc = enqueue_bottom(c, io, level + 1, false, true, s))) return rc;
+    for (int g = 0; g < c->opt.gamma; ++g) {
+        if ((rc = enqueue_bottom(c, io, level + 1, true, g == 0, s))) return rc;
+        if (level + 1 < c->Lmax && c->deep_n[level + 1] > 0)
+            if ((rc = enqueue_visit(c, io, level + 1, g == 0, s))) return rc;
+    }
     return enqueue_up(c, io, level, s);
 }
 
 int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
 {
     int rc;
-    if (c->coarse_n[0] > 0) {
-        // instances with a single level: the cycle is the exact solve
-        rc = enqueue_coarse(c, io, 0, s);
-        if (rc) return rc;
-        if (io.use_state) {
-            TileList *tl, *nl;
-            if ((rc = get_tiles(c, 0, kSingle, c->TO_up(), s, &tl))) return rc;
-            if ((rc = get_tiles(c, 0, kAll, c->TO_up(), s, &nl))) return rc;
-            LevelArgs a = base_args(c, 0, io.trans);
-            a.f = io.f;
-            a.u0 = io.trans ? nullptr : io.u0;
-            a.u_in = io.u;
-            a.tile_off = tl->d_off;
-            a.norm_off = nl->d_off;
-            a.partial = c->partial;
-            a.st = c->st;
-            a.nsweep = 0;
-            a.halo = c->H_up();
-            a.tile_out = c->TO_up();
-            HIPCHK(c, launch_up(c->P, io.trans, a, tl->ntiles, s));
-        }
-    }
-    if (c->deep_n[0] > 0) {
-        rc = enqueue_visit(c, io, 0, io.first, s);
-        if (rc) return rc;
-    }
+    if ((rc = enqueue_bottom(c, io, 0, false, io.first, s))) return rc;
+    if ((rc = enqueue_bottom(c, io, 0, true, io.first, s))) return rc;
+    if (c->deep_n[0] > 0)
+        if ((rc = enqueue_visit(c, io, 0, io.first, s))) return rc;
     if (io.use_state) {
         TileList *nl;
         if ((rc = get_tiles(c, 0, kAll, c->TO_up(), s, &nl))) return rc;
@@ -310,7 +315,6 @@ int get_graph(tmg_ctx *c, const CycleIO &io, hipGraphExec_t *out)
             if ((rc = get_tiles(c, l, kDeep, c->TO_up(), c->cap, &tl))) return rc;
         }
         if ((rc = get_tiles(c, 0, kAll, c->TO_up(), c->cap, &tl))) return rc;
-        if ((rc = get_tiles(c, 0, kSingle, c->TO_up(), c->cap, &tl))) return rc;
     }
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
@@ -518,29 +522,48 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     c->fl.assign(Lm, nullptr);
     c->ua.assign(Lm, nullptr);
     c->ub.assign(Lm, nullptr);
-    c->coarse_n.assign(Lm, 0);
+    // levels of at most bottom_max slabs run inside the single-work-group
+    // bottom kernel (schedule >= 0: bottom_max = 2^schedule, capped)
+    const int64_t cap_bottom = (int64_t)kBottomThreads * slabs_per_thread(P);
+    c->bottom_max = o.schedule < 0 ? cap_bottom
+                                   : std::min<int64_t>(cap_bottom, int64_t(1) << std::min(o.schedule, 40));
+    c->lb.assign(batch, 0);
+    for (int j = 0; j < batch; ++j) {
+        int l = 0;
+        while (l < L[j] - 1 && (c->N[j] >> l) > c->bottom_max) ++l;
+        c->lb[j] = l;
+    }
     c->deep_n.assign(Lm, 0);
-    c->coarse_inst_d.assign(Lm, nullptr);
+    c->bot_visit_n.assign(Lm, 0);
+    c->bot_coarse_n.assign(Lm, 0);
+    c->bot_visit_d.assign(Lm, nullptr);
+    c->bot_coarse_d.assign(Lm, nullptr);
+    auto upload_list = [&](const std::vector<int> &v, int **d) -> int {
+        if (v.empty()) return TMG_OK;
+        int r = dalloc(c, d, v.size());
+        if (r) return r;
+        if (hipMemcpyAsync(*d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return TMG_ERR_HIP;
+        return TMG_OK;
+    };
     for (int l = 0; l < Lm; ++l) {
         auto &off = c->slab_off_h[l];
-        std::vector<int> cl;
+        std::vector<int> bv, bc;
         for (int j = 0; j < batch; ++j) {
             off[j + 1] = off[j] + (l < L[j] ? (c->N[j] >> l) : 0);
-            if (L[j] - 1 == l) cl.push_back(j);
-            if (L[j] - 1 > l) c->deep_n[l]++;
+            if (c->lb[j] == l) (c->lb[j] == L[j] - 1 ? bc : bv).push_back(j);
+            if (l < c->lb[j]) c->deep_n[l]++;
         }
         c->level_size[l] = off[batch] * P;
-        c->coarse_n[l] = (int)cl.size();
+        c->bot_visit_n[l] = (int)bv.size();
+        c->bot_coarse_n[l] = (int)bc.size();
         if ((rc = dalloc(c, &c->slab_off_d[l], batch + 1))) return fail(rc);
         if (hipMemcpyAsync(c->slab_off_d[l], off.data(), sizeof(int64_t) * (batch + 1),
                            hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(TMG_ERR_HIP);
-        if (!cl.empty()) {
-            if ((rc = dalloc(c, &c->coarse_inst_d[l], cl.size()))) return fail(rc);
-            if (hipMemcpyAsync(c->coarse_inst_d[l], cl.data(), sizeof(int) * cl.size(),
-                               hipMemcpyHostToDevice, s) != hipSuccess)
-                return fail(TMG_ERR_HIP);
-        }
+        if ((rc = upload_list(bv, &c->bot_visit_d[l]))) return fail(rc);
+        if ((rc = upload_list(bc, &c->bot_coarse_d[l]))) return fail(rc);
         if (hipStreamSynchronize(s) != hipSuccess) return fail(TMG_ERR_HIP);
         // buffers: level 0 needs only the ping-pong partner of the user's u
         if (l > 0) {
@@ -550,6 +573,23 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         if (l + 1 < Lm) {
             if ((rc = dalloc(c, &c->ub[l], c->level_size[l]))) return fail(rc);
         }
+    }
+    // per-level pointer arrays and per-instance level data for the bottom kernel
+    {
+        std::vector<int> nlev(L.begin(), L.end());
+        if ((rc = dalloc(c, &c->lb_d, batch)) || (rc = dalloc(c, &c->nlev_d, batch)) ||
+            (rc = dalloc(c, &c->fl_d, Lm)) || (rc = dalloc(c, &c->ua_d, Lm)) ||
+            (rc = dalloc(c, &c->ub_d, Lm)) || (rc = dalloc(c, &c->slab_off_dd, Lm)))
+            return fail(rc);
+        if (hipMemcpyAsync(c->lb_d, c->lb.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->nlev_d, nlev.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->fl_d, c->fl.data(), sizeof(double *) * Lm, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->ua_d, c->ua.data(), sizeof(double *) * Lm, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->ub_d, c->ub.data(), sizeof(double *) * Lm, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->slab_off_dd, c->slab_off_d.data(), sizeof(int64_t *) * Lm,
+                           hipMemcpyHostToDevice, s) ||
+            hipStreamSynchronize(s))
+            return fail(TMG_ERR_HIP);
     }
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
@@ -678,7 +718,7 @@ int tmg_op_down(tmg_handle c, int level, int trans, int nsweep, const double *f,
     hipStream_t s = (hipStream_t)stream;
     const int H = even_up(nsweep + 1), TO = tile_slabs(c->P) - H;
     TileList *tl;
-    if ((rc = get_tiles(c, level, rcout ? kDeep : kAll, TO, s, &tl))) return rc;
+    if ((rc = get_tiles(c, level, rcout ? kHasNext : kAll, TO, s, &tl))) return rc;
     LevelArgs a = base_args(c, level, trans != 0);
     a.f = f;
     a.u0 = fold_u0;
@@ -705,7 +745,7 @@ int tmg_op_up(tmg_handle c, int level, int trans, int nsweep, const double *f,
     hipStream_t s = (hipStream_t)stream;
     const int H = even_up(nsweep + 1), TO = tile_slabs(c->P) - H;
     TileList *tl;
-    if ((rc = get_tiles(c, level, e ? kDeep : kAll, TO, s, &tl))) return rc;
+    if ((rc = get_tiles(c, level, e ? kHasNext : kAll, TO, s, &tl))) return rc;
     LevelArgs a = base_args(c, level, trans != 0);
     a.f = f;
     a.u0 = fold_u0;

@@ -11,6 +11,7 @@ constexpr int kMaxP = 4;        // P = p + 1 coefficients per slab
 constexpr int kThreads = 256;   // work-group size of the streaming kernels
 constexpr int kMaxSweeps = 8;
 constexpr int64_t kMaxCoarse = 4096;
+constexpr int kBottomThreads = 512;    // work-group of the bottom-of-hierarchy kernel
 
 // Slabs held by one thread of a streaming kernel (even, so that the two fine
 // slabs of a coarse slab always sit in the same thread).  S*P doubles per
@@ -87,11 +88,33 @@ struct CoarseArgs {
     int tab_stride;
 };
 
+// One multigrid visit of levels lb[j] .. nlev[j]-1 of instance j per
+// work-group (see k_bottom).  Level arrays are device arrays of per-level
+// pointers; level 0 uses the caller's f0 / u / u0.
+struct BottomArgs {
+    double *const *fl;              // [Lmax] level right-hand sides (fl[0] unused)
+    double *const *ua;              // [Lmax] level solutions / corrections (ua[0] unused)
+    double *const *ub;              // [Lmax] smoothed iterates of the down leg
+    const int64_t *const *slab_off; // [Lmax] -> [batch+1] slab offsets
+    const double *tab;              // tables, block (l, j) at (l * batch + j) * tab_stride
+    const double *R;
+    const int *inst;                // instances handled, one work-group each
+    const int *lb;                  // [batch] first level handled here
+    const int *nlev;                // [batch] levels of each instance
+    const double *f0, *u0;          // caller's level-0 data (u0 may be null)
+    double *u;
+    const InstState *st;
+    double *partial;                // level-0 residual norm slots (null: none)
+    const int64_t *norm_off;
+    int batch, tab_stride, nu1, nu2, gamma, zero;
+};
+
 // Host-side launchers (tmg_kernels.hip).  `backward` selects the transposed
 // system's backward-in-time indexing.  Return hipSuccess or the launch error.
 hipError_t launch_down(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_up(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
+hipError_t launch_bottom(int P, bool backward, const BottomArgs &a, int ninst, hipStream_t s);
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          int batch, double *partial, int64_t ntiles, hipStream_t s);

@@ -55,7 +55,8 @@ __device__ __forceinline__ int find_instance(const int64_t *__restrict__ off, in
 
 // End value of the left neighbour of this thread's first slab, for the
 // current sweep.  Double-buffered LDS slots (phase) need one barrier per call.
-__device__ __forceinline__ double left_value(double mine_last, double (*xchg)[kWaves], int &phase)
+template <int NW>
+__device__ __forceinline__ double left_value(double mine_last, double (*xchg)[NW], int &phase)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double v = __shfl_up(mine_last, 1, 64);
@@ -67,7 +68,8 @@ __device__ __forceinline__ double left_value(double mine_last, double (*xchg)[kW
 }
 
 // Sum over the work-group (fixed reduction tree); the result is valid in
-// thread 0.
+// thread 0.  Ends with a barrier, so `red` may be reused right away.
+template <int NW>
 __device__ __forceinline__ double block_sum(double x, double *red)
 {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -75,7 +77,8 @@ __device__ __forceinline__ double block_sum(double x, double *red)
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < kWaves; ++w) s += red[w];
+        for (int w = 0; w < NW; ++w) s += red[w];
+    __syncthreads();
     return s;
 }
 
@@ -204,9 +207,9 @@ __device__ __forceinline__ void fold_u0(double (&f)[S][P], int64_t m0, double u0
 //   u_n <- (1 - omega) u_n + omega A^{-1} f_n + omega A^{-1} v w_{n-1},
 // the same update as u + omega D^{-1} (f - L u), with g = omega A^{-1} f
 // precomputed.
-template <int P, int S>
+template <int P, int S, int NW>
 __device__ __forceinline__ void sweeps(double (&u)[S][P], const double (&g)[S][P], const Ops<P> &op,
-                                       int nsweep, double (*xchg)[kWaves], int &phase)
+                                       int nsweep, double (*xchg)[NW], int &phase)
 {
     for (int sw = 0; sw < nsweep; ++sw) {
         double w[S];
@@ -217,7 +220,7 @@ __device__ __forceinline__ void sweeps(double (&u)[S][P], const double (&g)[S][P
             for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
             w[s] = t;
         }
-        const double wl = left_value(w[S - 1], xchg, phase);
+        const double wl = left_value<NW>(w[S - 1], xchg, phase);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const double wn = s == 0 ? wl : w[s - 1];
@@ -228,10 +231,10 @@ __device__ __forceinline__ void sweeps(double (&u)[S][P], const double (&g)[S][P
 }
 
 // r_n = f_n + v w_{n-1} - A u_n.
-template <int P, int S>
+template <int P, int S, int NW>
 __device__ __forceinline__ void residual(double (&r)[S][P], const double (&u)[S][P],
                                          const double (&f)[S][P], const Ops<P> &op,
-                                         double (*xchg)[kWaves], int &phase)
+                                         double (*xchg)[NW], int &phase)
 {
     double w[S];
 #pragma unroll
@@ -241,7 +244,7 @@ __device__ __forceinline__ void residual(double (&r)[S][P], const double (&u)[S]
         for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
         w[s] = t;
     }
-    const double wl = left_value(w[S - 1], xchg, phase);
+    const double wl = left_value<NW>(w[S - 1], xchg, phase);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double wn = s == 0 ? wl : w[s - 1];
@@ -299,13 +302,13 @@ __global__ __launch_bounds__(kThreads) void k_down(LevelArgs a)
     }
     apply_G<P, S>(g, f, op);
     int phase = 0;
-    sweeps<P, S>(u, g, op, a.nsweep, xchg, phase);
+    sweeps<P, S, kWaves>(u, g, op, a.nsweep, xchg, phase);
 
     if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
     if (!a.rc && !a.partial) return;
 
     double r[S][P];
-    residual<P, S>(r, u, f, op, xchg, phase);
+    residual<P, S, kWaves>(r, u, f, op, xchg, phase);
     if (a.partial) {
         double acc = 0.0;
 #pragma unroll
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_down(LevelArgs a)
             if (li0 + s >= a.halo && m0 + s < N)
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
-        acc = block_sum(acc, red);
+        acc = block_sum<kWaves>(acc, red);
         if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
     }
     if (a.rc) {
@@ -378,39 +381,41 @@ __global__ __launch_bounds__(kThreads) void k_up(LevelArgs a)
     }
     apply_G<P, S>(g, f, op);
     int phase = 0;
-    sweeps<P, S>(u, g, op, a.nsweep, xchg, phase);
+    sweeps<P, S, kWaves>(u, g, op, a.nsweep, xchg, phase);
     if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
     if (a.partial) {
         double r[S][P];
-        residual<P, S>(r, u, f, op, xchg, phase);
+        residual<P, S, kWaves>(r, u, f, op, xchg, phase);
         double acc = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s)
             if (li0 + s >= a.halo && m0 + s < N)
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
-        acc = block_sum(acc, red);
+        acc = block_sum<kWaves>(acc, red);
         if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
     }
 }
 
-// Exact solve of L e = r on one instance per work-group.  With
-// d_n = A^{-1} r_n and b_n = c^T d_n the end values obey the affine
-// recurrence w_n = alpha w_{n-1} + b_n (alpha = c^T A^{-1} v, w_{-1} = 0);
-// the maps x -> alpha x + b_n are composed by a work-group prefix scan
-// (wavefront shuffles, then LDS across waves), 256 slabs per pass with the
-// last end value carried, and e_n = d_n + A^{-1} v w_{n-1}.
-template <int P, bool BW>
-__global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
+// Exact solve of L e = r for one instance by the whole work-group (NT
+// threads).  With d_n = A^{-1} r_n and b_n = c^T d_n the end values obey the
+// affine recurrence w_n = alpha w_{n-1} + b_n (alpha = c^T A^{-1} v,
+// w_{-1} = 0); the maps x -> alpha x + b_n are composed by a work-group
+// prefix scan (wavefront shuffles, then LDS across waves), NT slabs per pass
+// with the last end value carried, and e_n = d_n + A^{-1} v w_{n-1}.
+// u0 != 0 folds the initial value into slab 0 (forward system, level 0).
+template <int NT>
+struct ScanSmem {
+    double wa[NT / 64], wb[NT / 64];
+    double wend[NT];
+};
+
+template <int P, bool BW, int NT>
+__device__ __forceinline__ void coarse_scan(const double *__restrict__ r_base, double u0,
+                                            double *__restrict__ e_base, int64_t N,
+                                            const double *__restrict__ tab, ScanSmem<NT> &sm)
 {
     constexpr TabLayout L(P);
-    __shared__ double wa[kWaves], wb[kWaves];
-    __shared__ double wend[kThreads];
-    const int j = a.inst[blockIdx.x];
-    if (a.st && a.st[j].done) return;
-    const int64_t off = a.slab_off[j];
-    const int64_t N = a.slab_off[j + 1] - off;
-    const double *tab = a.tab + (int64_t)j * a.tab_stride;
     double AI[P * P], q[P], c[P], v[P];
 #pragma unroll
     for (int i = 0; i < P * P; ++i) AI[i] = tab[L.AI() + i];
@@ -423,18 +428,16 @@ __global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
     const double alpha = tab[L.ALPHA()];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double carry = 0.0;
-    for (int64_t base = 0; base < N; base += kThreads) {
+    for (int64_t base = 0; base < N; base += NT) {
         const int64_t m = base + threadIdx.x;
         const bool ok = m < N;
         const int64_t pm = BW ? N - 1 - m : m;
         double r[P], d[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) r[k] = ok ? a.r[(off + pm) * P + k] : 0.0;
-        if (a.u0 && m == 0) {
-            const double u0 = a.u0[j];
+        for (int k = 0; k < P; ++k) r[k] = ok ? r_base[pm * P + k] : 0.0;
+        const double a0 = (m == 0) ? u0 : 0.0;
 #pragma unroll
-            for (int k = 0; k < P; ++k) r[k] += u0 * v[k];
-        }
+        for (int k = 0; k < P; ++k) r[k] += a0 * v[k];
         double b = 0.0;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -454,23 +457,226 @@ __global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
             }
         }
         if (lane == 63) {
-            wa[wave] = A;
-            wb[wave] = B;
+            sm.wa[wave] = A;
+            sm.wb[wave] = B;
         }
         __syncthreads();
         // compose the totals of the earlier waves and the carried end value
         double Bp = carry;
-        for (int w = 0; w < wave; ++w) Bp = wa[w] * Bp + wb[w];
+        for (int w = 0; w < wave; ++w) Bp = sm.wa[w] * Bp + sm.wb[w];
         const double wm = A * Bp + B;   // end value of slab m
-        wend[threadIdx.x] = wm;
+        sm.wend[threadIdx.x] = wm;
         __syncthreads();
-        const double wprev = threadIdx.x == 0 ? carry : wend[threadIdx.x - 1];
+        const double wprev = threadIdx.x == 0 ? carry : sm.wend[threadIdx.x - 1];
         if (ok)
 #pragma unroll
-            for (int k = 0; k < P; ++k) a.e[(off + pm) * P + k] = d[k] + q[k] * wprev;
-        const int64_t nlast = (N - base < kThreads) ? (N - base) : kThreads;
-        carry = wend[nlast - 1];
+            for (int k = 0; k < P; ++k) e_base[pm * P + k] = d[k] + q[k] * wprev;
+        const int64_t nlast = (N - base < NT) ? (N - base) : NT;
+        carry = sm.wend[nlast - 1];
         __syncthreads();
+    }
+}
+
+template <int P, bool BW>
+__global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
+{
+    __shared__ ScanSmem<kThreads> sm;
+    const int j = a.inst[blockIdx.x];
+    if (a.st && a.st[j].done) return;
+    const int64_t off = a.slab_off[j];
+    const int64_t N = a.slab_off[j + 1] - off;
+    coarse_scan<P, BW, kThreads>(a.r + off * P, a.u0 ? a.u0[j] : 0.0, a.e + off * P, N,
+                                 a.tab + (int64_t)j * a.tab_stride, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Bottom of the hierarchy: one work-group of kBottomThreads runs a whole
+// multigrid visit of the levels lb(j) .. L_j - 1 of instance j (V or W,
+// gamma visits of each coarser level), holding a full level in registers
+// (S slabs per thread, so no halo) and passing data between levels through
+// the hierarchy buffers, which stay in L2 at these sizes.  Replaces two
+// latency-bound launches per small level by one launch.
+// ---------------------------------------------------------------------------
+
+template <int P, bool BW>
+struct BottomCtx {
+    static constexpr int NT = kBottomThreads;
+    static constexpr int NW = NT / 64;
+    static constexpr int S = slabs_per_thread(P);
+    const BottomArgs &a;
+    int j;
+    double (*xchg)[NW];
+    double *red;
+    ScanSmem<NT> &scan;
+
+    __device__ const double *tab(int l) const
+    {
+        return a.tab + ((int64_t)l * a.batch + j) * a.tab_stride;
+    }
+    __device__ int64_t off(int l) const { return a.slab_off[l][j]; }
+    __device__ int64_t nslab(int l) const { return a.slab_off[l][j + 1] - a.slab_off[l][j]; }
+    __device__ const double *rhs(int l) const { return l == 0 ? a.f0 : a.fl[l]; }
+    __device__ double fold(int l) const { return (l == 0 && a.u0) ? a.u0[j] : 0.0; }
+    __device__ double *sol(int l) const { return l == 0 ? a.u : a.ua[l]; }
+
+    // nu1 sweeps from u (zero if `zero`), residual, restriction; stores the
+    // smoothed iterate in ub[l] and the restricted residual in fl[l+1].
+    __device__ void down(int l, bool zero) const
+    {
+        Ops<P> op;
+        op.load(tab(l));
+        const int64_t N = nslab(l), o = off(l);
+        const int64_t m0 = (int64_t)threadIdx.x * S;
+        double f[S][P], u[S][P], g[S][P], r[S][P];
+        load_chunk<P, S, BW>(rhs(l) + o * P, m0, N, f);
+        fold_u0<P, S>(f, m0, fold(l), op);
+        if (zero) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k = 0; k < P; ++k) u[s][k] = 0.0;
+        } else {
+            load_chunk<P, S, BW>(sol(l) + o * P, m0, N, u);
+        }
+        apply_G<P, S>(g, f, op);
+        int phase = 0;
+        sweeps<P, S, NW>(u, g, op, a.nu1, xchg, phase);
+        store_chunk<P, S, BW>(a.ub[l] + o * P, m0, N, u, 0, 0);
+        residual<P, S, NW>(r, u, f, op, xchg, phase);
+        const double *R1T = a.R, *R2T = a.R + P * P;
+        double rc[S / 2][P];
+#pragma unroll
+        for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s1 = 0.0;
+#pragma unroll
+                for (int q = 0; q < P; ++q)
+                    s1 += R1T[q * P + k] * r[2 * i][q] + R2T[q * P + k] * r[2 * i + 1][q];
+                rc[i][k] = s1;
+            }
+        store_chunk<P, S / 2, BW>(a.fl[l + 1] + off(l + 1) * P, m0 / 2, nslab(l + 1), rc, 0, 0);
+        __syncthreads();
+    }
+
+    // u = S^nu2 (ub[l] + P e), e = sol(l+1); result in sol(l); at level 0
+    // also the squared residual norm of the result.
+    __device__ void up(int l) const
+    {
+        Ops<P> op;
+        op.load(tab(l));
+        const int64_t N = nslab(l), o = off(l);
+        const int64_t m0 = (int64_t)threadIdx.x * S;
+        double f[S][P], u[S][P], g[S][P], e[S / 2][P];
+        load_chunk<P, S, BW>(rhs(l) + o * P, m0, N, f);
+        fold_u0<P, S>(f, m0, fold(l), op);
+        load_chunk<P, S, BW>(a.ub[l] + o * P, m0, N, u);
+        load_chunk<P, S / 2, BW>(sol(l + 1) + off(l + 1) * P, m0 / 2, nslab(l + 1), e);
+        const double *R1T = a.R, *R2T = a.R + P * P;
+#pragma unroll
+        for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    s1 += R1T[k * P + q] * e[i][q];
+                    s2 += R2T[k * P + q] * e[i][q];
+                }
+                u[2 * i][k] += s1;
+                u[2 * i + 1][k] += s2;
+            }
+        apply_G<P, S>(g, f, op);
+        int phase = 0;
+        sweeps<P, S, NW>(u, g, op, a.nu2, xchg, phase);
+        store_chunk<P, S, BW>(sol(l) + o * P, m0, N, u, 0, 0);
+        if (l == 0 && a.partial) norm_out(u, f, op, phase);
+        __syncthreads();
+    }
+
+    __device__ void norm_out(const double (&u)[S][P], const double (&f)[S][P], const Ops<P> &op,
+                             int &phase) const
+    {
+        double r[S][P];
+        residual<P, S, NW>(r, u, f, op, xchg, phase);
+        const int64_t N = nslab(0), m0 = (int64_t)threadIdx.x * S;
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (m0 + s < N)   // slabs past the end see a nonzero left neighbour
+#pragma unroll
+                for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
+        acc = block_sum<NW>(acc, red);
+        if (threadIdx.x == 0) red[0] = acc;
+        __syncthreads();
+        acc = red[0];
+        // the instance's whole sum goes to its first slot, the others are zeroed
+        const int64_t lo = a.norm_off[j], hi = a.norm_off[j + 1];
+        for (int64_t i = lo + threadIdx.x; i < hi; i += NT) a.partial[i] = i == lo ? acc : 0.0;
+    }
+
+    // exact solve on the coarsest level l (and, at level 0, its residual norm)
+    __device__ void coarse(int l) const
+    {
+        coarse_scan<P, BW, NT>(rhs(l) + off(l) * P, fold(l), sol(l) + off(l) * P, nslab(l), tab(l),
+                               scan);
+        __syncthreads();
+        if (l == 0 && a.partial) {
+            Ops<P> op;
+            op.load(tab(0));
+            const int64_t N = nslab(0), o = off(0);
+            const int64_t m0 = (int64_t)threadIdx.x * S;
+            double f[S][P], u[S][P];
+            load_chunk<P, S, BW>(rhs(0) + o * P, m0, N, f);
+            fold_u0<P, S>(f, m0, fold(0), op);
+            load_chunk<P, S, BW>(sol(0) + o * P, m0, N, u);
+            int phase = 0;
+            norm_out(u, f, op, phase);
+            __syncthreads();
+        }
+    }
+};
+
+template <int P, bool BW>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
+{
+    using C = BottomCtx<P, BW>;
+    __shared__ double xchg[2][C::NW];
+    __shared__ double red[C::NW];
+    __shared__ ScanSmem<C::NT> scan;
+    const int j = a.inst[blockIdx.x];
+    if (a.st && a.st[j].done) return;
+    C c{a, j, xchg, red, scan};
+    const int lb = a.lb[j], Lc = a.nlev[j] - 1;
+    if (lb == Lc) {
+        c.coarse(lb);
+        return;
+    }
+    // visit(l) = down(l); [coarse(l+1) | gamma x visit(l+1)]; up(l),
+    // iteratively; bit l of `again` marks that visit(l) runs once more.
+    uint64_t again = 0;
+    int l = lb;
+    c.down(l, a.zero != 0);
+    while (true) {
+        if (l + 1 == Lc) {
+            c.coarse(l + 1);
+            c.up(l);
+            // visit(l) is complete: repeat it, or finish its parent
+            while (true) {
+                if (l == lb) return;
+                if (a.gamma > 1 && !((again >> l) & 1)) {
+                    again |= (uint64_t)1 << l;
+                    c.down(l, false);
+                    break;
+                }
+                again &= ~((uint64_t)1 << l);
+                --l;
+                c.up(l);
+            }
+        } else {
+            ++l;
+            c.down(l, true);
+        }
     }
 }
 
@@ -503,24 +709,35 @@ __global__ __launch_bounds__(kThreads) void k_norm_f(const double *__restrict__ 
             if (u0 && m0 + s == 0) y += u0[j] * tab[(int64_t)j * tab_stride + L.V() + k];
             acc += y * y;
         }
-    acc = block_sum(acc, red);
+    acc = block_sum<kWaves>(acc, red);
     if (threadIdx.x == 0) partial[tile] = acc;
 }
 
 // One work-group per instance: sum its partials in a fixed order and update
 // the convergence state (relative residual criterion of section 4.2).
-__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partial,
-                                                       const int64_t *__restrict__ norm_off,
-                                                       InstState *__restrict__ st,
-                                                       const Control *__restrict__ ctl, int is_r0)
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restrict__ partial,
+                                                          const int64_t *__restrict__ norm_off,
+                                                          InstState *__restrict__ st,
+                                                          const Control *__restrict__ ctl, int is_r0)
 {
-    __shared__ double red[kWaves];
+    __shared__ double red[kFinThreads / 64];
     const int j = blockIdx.x;
     if (!is_r0 && st[j].done) return;
     const int64_t lo = norm_off[j], hi = norm_off[j + 1];
+    // eight independent loads in flight per thread, summed in a fixed order
     double acc = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) acc += partial[i];
-    acc = block_sum(acc, red);
+    for (int64_t b = lo; b < hi; b += 8 * kFinThreads) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = b + q * kFinThreads + threadIdx.x;
+            v[q] = i < hi ? partial[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q];
+    }
+    acc = block_sum<kFinThreads / 64>(acc, red);
     if (threadIdx.x == 0) {
         InstState s = st[j];
         if (is_r0) {
@@ -558,7 +775,7 @@ __global__ __launch_bounds__(kThreads) void k_grad(const double *__restrict__ u,
         const int k = (int)(i % P);
         acc += z[off * P + i] * u[off * P + i] / (2.0 * k + 1.0);
     }
-    acc = block_sum(acc, red);
+    acc = block_sum<kWaves>(acc, red);
     if (threadIdx.x == 0) {
         double d = 0.0;
         for (int k = 0; k < P; ++k) d += ((k & 1) ? -1.0 : 1.0) * z[off * P + k];
@@ -608,6 +825,16 @@ hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, h
     return hipGetLastError();
 }
 
+hipError_t launch_bottom(int P, bool backward, const BottomArgs &a, int ninst, hipStream_t s)
+{
+    if (ninst <= 0) return hipSuccess;
+    TMG_DISPATCH_P(P, {
+        if (backward) hipLaunchKernelGGL((k_bottom<PP, true>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_bottom<PP, false>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
+    })
+    return hipGetLastError();
+}
+
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          int batch, double *partial, int64_t ntiles, hipStream_t s)
@@ -623,7 +850,7 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
                            InstState *st, const Control *ctl, int is_r0, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kThreads), 0, s, partial, norm_off, st, ctl,
+    hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kFinThreads), 0, s, partial, norm_off, st, ctl,
                        is_r0);
     return hipGetLastError();
 }

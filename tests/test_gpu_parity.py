@@ -162,13 +162,16 @@ def test_unit_damping_nilpotent(p):
 
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
 @pytest.mark.parametrize("gamma", [1, 2])
-def test_cycles_match_oracle(p, gamma):
+@pytest.mark.parametrize("schedule", [-1, 0, 5])
+def test_cycles_match_oracle(p, gamma, schedule):
     """k consecutive cycles from a random start (tmg_vcycle) equal the
     oracle's reference cycles (eq. chap4_errorTwoGridCycle applied
-    recursively, V or W)."""
+    recursively, V or W), whatever the split between the streaming kernels
+    and the single-work-group bottom kernel (schedule = log2 of the largest
+    level run inside one work-group; 0: only the coarsest solve there)."""
     rng = np.random.default_rng(40 + p)
-    N, T, lam, u0 = 1024, 10.0, 1.3, 0.5
-    s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
+    N, T, lam, u0 = 4096, 10.0, 1.3, 0.5
+    s = B().Solver([N], [T], [lam], p=p, gamma=gamma, schedule=schedule)
     P = p + 1
     f, u = rand(rng, N * P), rand(rng, N * P)
     du = dev(u)
@@ -207,7 +210,9 @@ def test_config1_end_to_end():
     assert relerr(host(res.u), uo) <= TOL
 
 
-def test_batched_uneven():
+@pytest.mark.parametrize("schedule", [-1, 0, 3])
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_batched_uneven(schedule, gamma):
     """Several instances of different length and lambda in one handle,
     including one with a single level (N = n_coarse: the cycle is the exact
     solve); each equals its own oracle solve."""
@@ -218,11 +223,11 @@ def test_batched_uneven():
     Ts = [1.0, 2.0, 10.0, 1.0, 5.0, 100.0]
     u0 = rng.uniform(-1, 1, len(Ns))
     fs = [rand(rng, n * (p + 1)) * 0.1 for n in Ns]
-    s = B().Solver(Ns, Ts, lams, p=p)
+    s = B().Solver(Ns, Ts, lams, p=p, schedule=schedule, gamma=gamma)
     res = s.solve(dev(np.concatenate(fs)), dev(u0), rtol=1e-10)
     U = host(res.u)
     for j, n in enumerate(Ns):
-        uo, k, rr, _ = core.solve(p, Ts[j], lams[j], u0[j], fs[j])
+        uo, k, rr, _ = core.solve(p, Ts[j], lams[j], u0[j], fs[j], opts=core.Opts(gamma=gamma))
         assert res.cycles[j] == k
         assert relerr(U[s.offsets[j]:s.offsets[j + 1]], uo) <= TOL
 
