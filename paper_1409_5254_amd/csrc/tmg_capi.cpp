@@ -1,12 +1,28 @@
 // C ABI and host driver of the time-multigrid library (see include/tmg.h).
 //
 // The driver owns the level hierarchy of every instance, the per-level
-// tables, the tile schedules and the captured cycle graphs.  One cycle is a
-// fixed sequence of kernel launches (down legs, coarsest scans, up legs,
-// norm finalisation) that is recorded once into a hipGraph per
-// (first-cycle, direction, user pointers) and replayed; kernels read the
-// per-instance convergence state and return at once for finished
-// instances, so the host only synchronises every few cycles to read it.
+// tables, the tile schedules and the captured cycle graphs.
+//
+// One cycle, for an instance whose levels 0 .. lb-1 run on the streaming
+// kernel and lb .. L-1 inside the single-work-group bottom kernel:
+//   level 0   : the down leg of this cycle was already done by the previous
+//               cycle's fused level-0 pass (or by a separate down leg in the
+//               first cycle);
+//   1 .. lb-1 : down legs (pre-smoothing + residual + restriction; nothing
+//               but the restricted residual is stored);
+//   lb        : bottom kernel (gamma visits for a W-cycle);
+//   .. 1      : up legs, which recompute the pre-smoothing from the level's
+//               right-hand side instead of reading a stored iterate;
+//   level 0   : one fused pass: recomputed pre-smoothing, correction,
+//               post-smoothing, the residual norm, and the next cycle's
+//               pre-smoothing, residual and restriction.
+// The level-0 iterate is updated in place; each tile takes its left halo
+// from a small per-tile buffer written by the previous pass, so no tile ever
+// reads slabs another tile of the same pass writes.  Three graphs (first,
+// odd, even: the halo buffers alternate) are captured once per
+// (direction, user pointers) and replayed; kernels read the per-instance
+// convergence state and return at once for finished instances, so the host
+// only synchronises every few cycles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,31 +49,40 @@ struct TileList {
 };
 
 struct GraphKey {
-    int first, trans;
+    int kind, trans;
     const void *f, *u0, *u;
     bool operator<(const GraphKey &o) const
     {
-        return std::tie(first, trans, f, u0, u) < std::tie(o.first, o.trans, o.f, o.u0, o.u);
+        return std::tie(kind, trans, f, u0, u) < std::tie(o.kind, o.trans, o.f, o.u0, o.u);
     }
 };
 
-int even_up(int x) { return (x + 1) & ~1; }
+// graph kinds: the first cycle of a solve, and later cycles by halo parity
+enum { kFirst = 0, kEven = 1, kOdd = 2 };
 
 }  // namespace
 
 struct tmg_ctx {
-    int batch = 0, P = 0, Lmax = 0;
+    int batch = 0, P = 0, S = 0, Lmax = 0;
     tmg_options opt{};
     std::vector<int64_t> N;
     std::vector<double> T, lam;
     std::vector<int> L;                           // levels of each instance
+    std::vector<int> lb;                          // first level of the bottom kernel
     std::vector<std::vector<int64_t>> slab_off_h; // [Lmax][batch+1]
     std::vector<int64_t *> slab_off_d;
-    std::vector<double *> fl, ua, ub;             // level buffers (fl[0], ua[0] are the user's)
+    std::vector<double *> fl;                     // level right-hand sides (level >= 1)
+    std::vector<double *> xa, xb;                 // level iterates, two per level (level >= 1)
     std::vector<int64_t> level_size;              // doubles per level
+    double *hb[2] = {nullptr, nullptr};           // level-0 halo buffers
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
     int tab_stride = 0;
+    int *nlev_d = nullptr;
+    std::vector<int *> bot_d;                     // per level: instances with lb == level
+    std::vector<int> bot_n;
+    std::vector<int> deep_n;                      // per level: instances with level < lb
+    int64_t bottom_cap = 0;
     InstState *st = nullptr, *st_ops = nullptr;
     InstState *st_host = nullptr;                 // pinned
     Control *ctl = nullptr, *ctl_host = nullptr;  // device / pinned
@@ -65,35 +90,35 @@ struct tmg_ctx {
     int64_t partial_cap = 0;
     double *tau_d = nullptr, *grad_d = nullptr, *grad_host = nullptr;
     std::map<std::tuple<int, int, int>, TileList> tiles;
-    std::vector<int> lb;                          // first level of the bottom kernel, per instance
-    std::vector<int *> bot_visit_d, bot_coarse_d; // per level: bottom lists (visit / exact solve only)
-    std::vector<int> bot_visit_n, bot_coarse_n;
-    std::vector<int> deep_n;                      // per level: instances with level < lb[j]
-    int *lb_d = nullptr, *nlev_d = nullptr;
-    double **fl_d = nullptr, **ua_d = nullptr, **ub_d = nullptr;
-    int64_t **slab_off_dd = nullptr;
-    int64_t bottom_max = 0;
-    std::map<std::tuple<int, int>, std::pair<int *, int>> op_coarse;  // (level, unused) -> list
+    std::map<int, std::pair<int *, int>> op_coarse;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    std::vector<int> cur;                         // capture-time: which iterate buffer is current
     hipStream_t cap = nullptr;
     int last_hip = 0;
     std::vector<void *> allocs;
 
-    int H_down() const { return even_up(opt.nu1 + 1); }
-    int H_up() const { return even_up(opt.nu2 + 1); }
-    int TO_down() const { return tile_slabs(P) - H_down(); }
-    int TO_up() const { return tile_slabs(P) - H_up(); }
+    // halo (even and a multiple of S) and output slabs per tile of each pass
+    int rs(int x) const
+    {
+        const int q = S < 2 ? 2 : S;
+        return ((x + q - 1) / q) * q;
+    }
+    int H_down() const { return rs(opt.nu1 + 1); }
+    int H_up() const { return rs(opt.nu1 + opt.nu2); }
+    int H_fused() const { return rs(2 * opt.nu1 + opt.nu2 + 1); }
+    int TO(int H) const { return tile_slabs(P) - H; }
+    double *x(int l, int which) const { return which ? xb[l] : xa[l]; }
 };
 
 namespace {
 
-#define HIPCHK(ctx, expr)                           \
-    do {                                            \
-        hipError_t e_ = (expr);                     \
-        if (e_ != hipSuccess) {                     \
-            (ctx)->last_hip = (int)e_;              \
-            return e_ == hipErrorOutOfMemory ? TMG_ERR_OOM : TMG_ERR_HIP; \
-        }                                           \
+#define HIPCHK(ctx, expr)                                                  \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) {                                            \
+            (ctx)->last_hip = (int)e_;                                     \
+            return e_ == hipErrorOutOfMemory ? TMG_ERR_OOM : TMG_ERR_HIP;  \
+        }                                                                  \
     } while (0)
 
 template <typename T>
@@ -113,8 +138,8 @@ int dalloc(tmg_ctx *c, T **p, size_t n)
 bool participates(const tmg_ctx *c, int j, int level, int kind)
 {
     if (level >= c->L[j]) return false;
-    if (kind == kDeep) return level < c->lb[j];      // streaming kernels in the cycle
-    if (kind == kHasNext) return level + 1 < c->L[j];  // level-wise entry points
+    if (kind == kDeep) return level < c->lb[j];       // streaming kernels in the cycle
+    if (kind == kHasNext) return level + 1 < c->L[j]; // level-wise entry points
     return true;
 }
 
@@ -149,20 +174,32 @@ int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, Tile
     return TMG_OK;
 }
 
+int64_t tiles_of(const tmg_ctx *c, int level, int kind, int tile_out)
+{
+    int64_t n = 0;
+    for (int j = 0; j < c->batch; ++j)
+        if (participates(c, j, level, kind)) n += ((c->N[j] >> level) + tile_out - 1) / tile_out;
+    return n;
+}
+
 const double *tab_of(const tmg_ctx *c, int level, bool trans)
 {
     return (trans ? c->tab_adj : c->tab_fwd) + (int64_t)level * c->batch * c->tab_stride;
 }
 
-LevelArgs base_args(const tmg_ctx *c, int level, bool trans)
+LegArgs leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl, int H)
 {
-    LevelArgs a{};
+    LegArgs a{};
     a.tab = tab_of(c, level, trans);
     a.R = trans ? c->R_adj : c->R_fwd;
     a.slab_off = c->slab_off_d[level];
     a.cslab_off = level + 1 < c->Lmax ? c->slab_off_d[level + 1] : nullptr;
+    a.tile_off = tl->d_off;
+    a.n0 = c->N[0] >> level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
+    a.halo = H;
+    a.tile_out = c->TO(H);
     return a;
 }
 
@@ -171,154 +208,207 @@ LevelArgs base_args(const tmg_ctx *c, int level, bool trans)
 struct CycleIO {
     const double *f, *u0;
     double *u;
-    bool trans, first, use_state;
+    bool trans, use_state;
+    int kind;      // kFirst / kEven / kOdd (solve); -1: a single warm-started cycle
 };
 
-int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero_init, hipStream_t s);
+const double *fold_of(const CycleIO &io) { return io.trans ? nullptr : io.u0; }
 
-int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero_init, hipStream_t s)
-{
-    TileList *tl;
-    int rc = get_tiles(c, level, kDeep, c->TO_down(), s, &tl);
-    if (rc) return rc;
-    LevelArgs a = base_args(c, level, io.trans);
-    a.f = level == 0 ? io.f : c->fl[level];
-    a.u0 = (level == 0 && !io.trans) ? io.u0 : nullptr;
-    a.u_in = zero_init ? nullptr : (level == 0 ? io.u : c->ua[level]);
-    a.u_out = c->ub[level];
-    a.rc = c->fl[level + 1];
-    a.tile_off = tl->d_off;
-    a.st = io.use_state ? c->st : nullptr;
-    a.nsweep = c->opt.nu1;
-    a.halo = c->H_down();
-    a.tile_out = c->TO_down();
-    HIPCHK(c, launch_down(c->P, io.trans, a, tl->ntiles, s));
-    return TMG_OK;
-}
-
-int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, hipStream_t s)
-{
-    TileList *tl;
-    int rc = get_tiles(c, level, kDeep, c->TO_up(), s, &tl);
-    if (rc) return rc;
-    LevelArgs a = base_args(c, level, io.trans);
-    a.f = level == 0 ? io.f : c->fl[level];
-    a.u0 = (level == 0 && !io.trans) ? io.u0 : nullptr;
-    a.u_in = c->ub[level];
-    a.e = c->ua[level + 1];
-    a.u_out = level == 0 ? io.u : c->ua[level];
-    a.tile_off = tl->d_off;
-    a.st = io.use_state ? c->st : nullptr;
-    a.nsweep = c->opt.nu2;
-    a.halo = c->H_up();
-    a.tile_out = c->TO_up();
-    if (level == 0 && io.use_state) {
-        TileList *nl;
-        rc = get_tiles(c, 0, kAll, c->TO_up(), s, &nl);
-        if (rc) return rc;
-        a.partial = c->partial;
-        a.norm_off = nl->d_off;
-    }
-    HIPCHK(c, launch_up(c->P, io.trans, a, tl->ntiles, s));
-    return TMG_OK;
-}
-
-// Bottom kernel for the instances whose single-work-group part starts at
-// `level`: exact solve only (coarse list) or a full visit (visit list).
-int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, bool visits, bool zero,
+// Bottom kernel for the instances whose bottom part starts at `level`.
+int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const double *x_in, double *x_out,
                    hipStream_t s)
 {
-    const int n = visits ? c->bot_visit_n[level] : c->bot_coarse_n[level];
-    if (n == 0) return TMG_OK;
+    if (c->bot_n[level] == 0) return TMG_OK;
     BottomArgs a{};
-    a.fl = c->fl_d;
-    a.ua = c->ua_d;
-    a.ub = c->ub_d;
-    a.slab_off = c->slab_off_dd;
+    a.f = level == 0 ? io.f : c->fl[level];
+    a.u0 = level == 0 ? fold_of(io) : nullptr;
+    a.x_in = x_in;
+    a.x_out = x_out;
+    a.slab_off = c->slab_off_d[level];
     a.tab = io.trans ? c->tab_adj : c->tab_fwd;
     a.R = io.trans ? c->R_adj : c->R_fwd;
-    a.inst = visits ? c->bot_visit_d[level] : c->bot_coarse_d[level];
-    a.lb = c->lb_d;
+    a.inst = c->bot_d[level];
     a.nlev = c->nlev_d;
-    a.f0 = io.f;
-    a.u0 = io.trans ? nullptr : io.u0;
-    a.u = io.u;
     a.st = io.use_state ? c->st : nullptr;
     if (level == 0 && io.use_state) {
         TileList *nl;
-        int rc = get_tiles(c, 0, kAll, c->TO_up(), s, &nl);
+        int rc = get_tiles(c, 0, kAll, c->TO(c->H_fused()), s, &nl);
         if (rc) return rc;
         a.partial = c->partial;
         a.norm_off = nl->d_off;
     }
+    a.level = level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
     a.nu1 = c->opt.nu1;
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
-    a.zero = zero ? 1 : 0;
-    HIPCHK(c, launch_bottom(c->P, io.trans, a, n, s));
+    HIPCHK(c, launch_bottom(c->P, io.trans, a, c->bot_n[level], s));
     return TMG_OK;
 }
 
-// Multigrid visit of `level` for the instances that run this level with the
-// streaming kernels (level < lb[j]): nu1 sweeps + residual + restriction,
-// gamma visits of the next level from zero (bottom kernel or recursion; an
-// exact solve once when the next level is an instance's coarsest), then
-// prolongation + correction + nu2 sweeps.
-int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero_init, hipStream_t s)
+// Down leg (streaming instances): nu1 sweeps from the current iterate (zero
+// on a first visit), residual, restriction into the next level.
+int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
 {
-    int rc = enqueue_down(c, io, level, zero_init, s);
+    TileList *tl;
+    const int H = c->H_down();
+    int rc = get_tiles(c, level, kDeep, c->TO(H), s, &tl);
     if (rc) return rc;
-    if ((rc = enqueue_bottom(c, io, level + 1, false, true, s))) return rc;
+    LegArgs a = leg_args(c, level, io.trans, tl, H);
+    a.f = level == 0 ? io.f : c->fl[level];
+    a.u0 = level == 0 ? fold_of(io) : nullptr;
+    a.u_in = zero ? nullptr : (level == 0 ? io.u : c->x(level, c->cur[level]));
+    a.rc = c->fl[level + 1];
+    a.st = io.use_state ? c->st : nullptr;
+    a.pre = c->opt.nu1;
+    HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+// Up leg at `level` >= 1: the pre-smoothing recomputed from the visit's
+// initial iterate, correction with the next level's result, nu2 sweeps.
+// A first visit writes the current buffer (nothing is read from it); a
+// repeated visit (W-cycle) writes the other one and makes it current.
+int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
+{
+    TileList *tl;
+    const int H = c->H_up();
+    int rc = get_tiles(c, level, kDeep, c->TO(H), s, &tl);
+    if (rc) return rc;
+    LegArgs a = leg_args(c, level, io.trans, tl, H);
+    const int cur = c->cur[level];
+    a.f = c->fl[level];
+    a.u_in = zero ? nullptr : c->x(level, cur);
+    a.e = c->x(level + 1, c->cur[level + 1]);
+    a.u_out = zero ? c->x(level, cur) : c->x(level, cur ^ 1);
+    a.st = io.use_state ? c->st : nullptr;
+    a.pre = c->opt.nu1;
+    a.post = c->opt.nu2;
+    HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+    if (!zero) c->cur[level] ^= 1;
+    return TMG_OK;
+}
+
+int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s);
+
+int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
+{
+    int rc = enqueue_down(c, io, level, zero, s);
+    if (rc) return rc;
+    if ((rc = enqueue_coarse_visits(c, io, level + 1, s))) return rc;
+    return enqueue_up(c, io, level, zero, s);
+}
+
+// gamma visits of level l >= 1 from zero: bottom-kernel instances and,
+// recursively, the streaming ones.  (When l is an instance's coarsest
+// level its visit is the exact solve; repeating it changes nothing.)
+int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s)
+{
+    int rc;
+    c->cur[l] = 0;
     for (int g = 0; g < c->opt.gamma; ++g) {
-        if ((rc = enqueue_bottom(c, io, level + 1, true, g == 0, s))) return rc;
-        if (level + 1 < c->Lmax && c->deep_n[level + 1] > 0)
-            if ((rc = enqueue_visit(c, io, level + 1, g == 0, s))) return rc;
+        const int cur = c->cur[l];
+        // bottom instances: a first visit starts from zero in place, a repeated
+        // one reads the current buffer and writes the other (like enqueue_up)
+        if ((rc = enqueue_bottom(c, io, l, g == 0 ? nullptr : c->x(l, cur),
+                                 g == 0 ? c->x(l, cur) : c->x(l, cur ^ 1), s)))
+            return rc;
+        if (c->deep_n[l] > 0) {
+            if ((rc = enqueue_visit(c, io, l, g == 0, s))) return rc;
+        } else if (g > 0) {
+            c->cur[l] ^= 1;
+        }
     }
-    return enqueue_up(c, io, level, s);
+    return TMG_OK;
 }
 
 int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
 {
     int rc;
-    if ((rc = enqueue_bottom(c, io, 0, false, io.first, s))) return rc;
-    if ((rc = enqueue_bottom(c, io, 0, true, io.first, s))) return rc;
-    if (c->deep_n[0] > 0)
-        if ((rc = enqueue_visit(c, io, 0, io.first, s))) return rc;
+    const bool first = io.kind == kFirst;
+    c->cur.assign(c->Lmax + 1, 0);
+    // instances that fit the bottom kernel entirely: the cycle is one launch
+    if ((rc = enqueue_bottom(c, io, 0, first ? nullptr : io.u, io.u, s))) return rc;
+    if (c->deep_n[0] > 0) {
+        TileList *tl;
+        const bool solve = io.kind >= 0;
+        if (!solve) {
+            // warm start: seed the halo buffer from the caller's iterate
+            const int H = c->H_up();
+            if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+            LegArgs a = leg_args(c, 0, io.trans, tl, H);
+            a.f = io.f;
+            a.u_in = io.u;
+            a.halo_out = c->hb[0];
+            HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+        }
+        if (!solve || first)
+            if ((rc = enqueue_down(c, io, 0, first, s))) return rc;
+        if ((rc = enqueue_coarse_visits(c, io, 1, s))) return rc;
+        // fused level-0 pass
+        const int H = solve ? c->H_fused() : c->H_up();
+        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+        LegArgs a = leg_args(c, 0, io.trans, tl, H);
+        a.f = io.f;
+        a.u0 = fold_of(io);
+        a.u_in = first ? nullptr : io.u;
+        a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]);
+        a.e = c->x(1, c->cur[1]);
+        a.u_out = io.u;
+        a.st = io.use_state ? c->st : nullptr;
+        a.pre = c->opt.nu1;
+        a.post = c->opt.nu2;
+        if (solve) {
+            a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
+            a.rc = c->fl[1];
+            a.next = c->opt.nu1;
+            TileList *nl;
+            if ((rc = get_tiles(c, 0, kAll, c->TO(H), s, &nl))) return rc;
+            a.partial = c->partial;
+            a.norm_off = nl->d_off;
+        }
+        HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+    }
     if (io.use_state) {
         TileList *nl;
-        if ((rc = get_tiles(c, 0, kAll, c->TO_up(), s, &nl))) return rc;
+        if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_fused()), s, &nl))) return rc;
         HIPCHK(c, launch_finalize(c->partial, nl->d_off, c->batch, c->st, c->ctl, 0, s));
     }
     return TMG_OK;
 }
 
+// Every tile list a cycle uses, created outside graph capture.
+int make_tiles(tmg_ctx *c, hipStream_t s)
+{
+    TileList *tl;
+    int rc;
+    for (int l = 0; l < c->Lmax; ++l) {
+        if ((rc = get_tiles(c, l, kDeep, c->TO(c->H_down()), s, &tl))) return rc;
+        if ((rc = get_tiles(c, l, kDeep, c->TO(c->H_up()), s, &tl))) return rc;
+    }
+    if ((rc = get_tiles(c, 0, kDeep, c->TO(c->H_fused()), s, &tl))) return rc;
+    if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_fused()), s, &tl))) return rc;
+    return TMG_OK;
+}
+
 int get_graph(tmg_ctx *c, const CycleIO &io, hipGraphExec_t *out)
 {
-    GraphKey key{io.first, io.trans, io.f, io.u0, io.u};
+    GraphKey key{io.kind, io.trans, io.f, io.u0, io.u};
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
         return TMG_OK;
     }
-    if (c->graphs.size() >= 16) {
+    if (c->graphs.size() >= 24) {
         for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
         c->graphs.clear();
     }
-    // make sure every tile list exists before capture (no memcpy inside)
-    {
-        TileList *tl;
-        int rc;
-        for (int l = 0; l < c->Lmax; ++l) {
-            if ((rc = get_tiles(c, l, kDeep, c->TO_down(), c->cap, &tl))) return rc;
-            if ((rc = get_tiles(c, l, kDeep, c->TO_up(), c->cap, &tl))) return rc;
-        }
-        if ((rc = get_tiles(c, 0, kAll, c->TO_up(), c->cap, &tl))) return rc;
-    }
+    int rc = make_tiles(c, c->cap);
+    if (rc) return rc;
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_cycle(c, io, c->cap);
+    rc = enqueue_cycle(c, io, c->cap);
     hipError_t ee = hipStreamEndCapture(c->cap, &g);
     if (rc) return rc;
     HIPCHK(c, ee);
@@ -365,15 +455,14 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
                             c->slab_off_d[0], tl->d_off, c->batch, c->partial, tl->ntiles, s));
     HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 1, s));
 
-    CycleIO io{f, u0, u, trans, true, true};
-    hipGraphExec_t g_first, g_next;
-    if ((rc = get_graph(c, io, &g_first))) return rc;
-    io.first = false;
-    if ((rc = get_graph(c, io, &g_next))) return rc;
-
+    hipGraphExec_t g[3];
+    for (int k = 0; k < 3; ++k) {
+        CycleIO io{f, u0, u, trans, true, k};
+        if ((rc = get_graph(c, io, &g[k]))) return rc;
+    }
     int launched = 0;
     if (max_cycles > 0) {
-        HIPCHK(c, hipGraphLaunch(g_first, s));
+        HIPCHK(c, hipGraphLaunch(g[kFirst], s));
         launched = 1;
     }
     std::vector<double> prev_rsq(c->batch, -1.0);
@@ -402,8 +491,11 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         }
         if (all || launched >= max_cycles) break;
         need = std::min(need, max_cycles - launched);
-        for (int k = 0; k < need; ++k) HIPCHK(c, hipGraphLaunch(g_next, s));
-        launched += need;
+        for (int k = 0; k < need; ++k) {
+            // cycle n >= 2 reads the halo buffer cycle n-1 wrote
+            HIPCHK(c, hipGraphLaunch(g[(launched % 2 == 1) ? kEven : kOdd], s));
+            ++launched;
+        }
     }
     int status = TMG_OK;
     for (int j = 0; j < c->batch; ++j) {
@@ -491,18 +583,35 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         if (n != o.n_coarse) return TMG_ERR_SIZE;
         L[j] = lev;
     }
+    // levels of at most bottom_cap slabs run inside the single-work-group
+    // bottom kernel (schedule >= 0: bottom_cap = 2^schedule, capped); an
+    // instance's coarsest level always does
+    const int P = o.p + 1;
+    const int64_t bottom_cap =
+        o.schedule < 0 ? (int64_t)bottom_max(P)
+                       : std::min<int64_t>(bottom_max(P), int64_t(1) << std::min(o.schedule, 40));
+    std::vector<int> lbv(batch, 0);
+    for (int j = 0; j < batch; ++j) {
+        int l = 0;
+        while (l < L[j] - 1 && (n_slabs[j] >> l) > bottom_cap) ++l;
+        if (L[j] - l > kBottomMaxLevels) return TMG_ERR_SIZE;
+        lbv[j] = l;
+    }
     tmg_ctx *c = new (std::nothrow) tmg_ctx;
     if (!c) return TMG_ERR_OOM;
     hipStream_t s = (hipStream_t)stream;
     c->batch = batch;
-    c->P = o.p + 1;
+    c->P = P;
+    c->S = slabs_per_thread(P);
     c->opt = o;
     c->N.assign(n_slabs, n_slabs + batch);
     c->T.assign(T, T + batch);
     c->lam.assign(lambda, lambda + batch);
     c->L = L;
+    c->lb = lbv;
+    c->bottom_cap = bottom_cap;
     c->Lmax = *std::max_element(L.begin(), L.end());
-    const int P = c->P, Lm = c->Lmax;
+    const int Lm = c->Lmax;
     const TabLayout TL(P);
     c->tab_stride = TL.stride();
 
@@ -515,81 +624,50 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
         return fail(TMG_ERR_HIP);
 
-    // level layouts
     c->slab_off_h.assign(Lm, std::vector<int64_t>(batch + 1, 0));
     c->slab_off_d.assign(Lm, nullptr);
     c->level_size.assign(Lm, 0);
-    c->fl.assign(Lm, nullptr);
-    c->ua.assign(Lm, nullptr);
-    c->ub.assign(Lm, nullptr);
-    // levels of at most bottom_max slabs run inside the single-work-group
-    // bottom kernel (schedule >= 0: bottom_max = 2^schedule, capped)
-    const int64_t cap_bottom = (int64_t)kBottomThreads * slabs_per_thread(P);
-    c->bottom_max = o.schedule < 0 ? cap_bottom
-                                   : std::min<int64_t>(cap_bottom, int64_t(1) << std::min(o.schedule, 40));
-    c->lb.assign(batch, 0);
-    for (int j = 0; j < batch; ++j) {
-        int l = 0;
-        while (l < L[j] - 1 && (c->N[j] >> l) > c->bottom_max) ++l;
-        c->lb[j] = l;
-    }
-    c->deep_n.assign(Lm, 0);
-    c->bot_visit_n.assign(Lm, 0);
-    c->bot_coarse_n.assign(Lm, 0);
-    c->bot_visit_d.assign(Lm, nullptr);
-    c->bot_coarse_d.assign(Lm, nullptr);
-    auto upload_list = [&](const std::vector<int> &v, int **d) -> int {
-        if (v.empty()) return TMG_OK;
-        int r = dalloc(c, d, v.size());
-        if (r) return r;
-        if (hipMemcpyAsync(*d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-            return TMG_ERR_HIP;
-        return TMG_OK;
-    };
+    c->fl.assign(Lm + 1, nullptr);
+    c->xa.assign(Lm + 1, nullptr);
+    c->xb.assign(Lm + 1, nullptr);
+    c->deep_n.assign(Lm + 1, 0);
+    c->bot_n.assign(Lm + 1, 0);
+    c->bot_d.assign(Lm + 1, nullptr);
     for (int l = 0; l < Lm; ++l) {
         auto &off = c->slab_off_h[l];
-        std::vector<int> bv, bc;
+        std::vector<int> bl;
         for (int j = 0; j < batch; ++j) {
             off[j + 1] = off[j] + (l < L[j] ? (c->N[j] >> l) : 0);
-            if (c->lb[j] == l) (c->lb[j] == L[j] - 1 ? bc : bv).push_back(j);
+            if (c->lb[j] == l) bl.push_back(j);
             if (l < c->lb[j]) c->deep_n[l]++;
         }
         c->level_size[l] = off[batch] * P;
-        c->bot_visit_n[l] = (int)bv.size();
-        c->bot_coarse_n[l] = (int)bc.size();
+        c->bot_n[l] = (int)bl.size();
         if ((rc = dalloc(c, &c->slab_off_d[l], batch + 1))) return fail(rc);
         if (hipMemcpyAsync(c->slab_off_d[l], off.data(), sizeof(int64_t) * (batch + 1),
                            hipMemcpyHostToDevice, s) != hipSuccess)
             return fail(TMG_ERR_HIP);
-        if ((rc = upload_list(bv, &c->bot_visit_d[l]))) return fail(rc);
-        if ((rc = upload_list(bc, &c->bot_coarse_d[l]))) return fail(rc);
-        if (hipStreamSynchronize(s) != hipSuccess) return fail(TMG_ERR_HIP);
-        // buffers: level 0 needs only the ping-pong partner of the user's u
-        if (l > 0) {
-            if ((rc = dalloc(c, &c->fl[l], c->level_size[l]))) return fail(rc);
-            if ((rc = dalloc(c, &c->ua[l], c->level_size[l]))) return fail(rc);
+        if (!bl.empty()) {
+            if ((rc = dalloc(c, &c->bot_d[l], bl.size()))) return fail(rc);
+            if (hipMemcpyAsync(c->bot_d[l], bl.data(), sizeof(int) * bl.size(),
+                               hipMemcpyHostToDevice, s) != hipSuccess)
+                return fail(TMG_ERR_HIP);
         }
-        if (l + 1 < Lm) {
-            if ((rc = dalloc(c, &c->ub[l], c->level_size[l]))) return fail(rc);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(TMG_ERR_HIP);
+        if (l > 0) {
+            if ((rc = dalloc(c, &c->fl[l], c->level_size[l])) ||
+                (rc = dalloc(c, &c->xa[l], c->level_size[l])) ||
+                (rc = dalloc(c, &c->xb[l], c->level_size[l])))
+                return fail(rc);
         }
     }
-    // per-level pointer arrays and per-instance level data for the bottom kernel
+    // level-0 halo buffers: one slot of H x P doubles per tile
     {
-        std::vector<int> nlev(L.begin(), L.end());
-        if ((rc = dalloc(c, &c->lb_d, batch)) || (rc = dalloc(c, &c->nlev_d, batch)) ||
-            (rc = dalloc(c, &c->fl_d, Lm)) || (rc = dalloc(c, &c->ua_d, Lm)) ||
-            (rc = dalloc(c, &c->ub_d, Lm)) || (rc = dalloc(c, &c->slab_off_dd, Lm)))
+        const int Hs[2] = {c->H_fused(), c->H_up()};
+        int64_t hsize = 0;
+        for (int H : Hs) hsize = std::max(hsize, tiles_of(c, 0, kDeep, c->TO(H)) * H * P);
+        if ((rc = dalloc(c, &c->hb[0], hsize)) || (rc = dalloc(c, &c->hb[1], hsize)))
             return fail(rc);
-        if (hipMemcpyAsync(c->lb_d, c->lb.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s) ||
-            hipMemcpyAsync(c->nlev_d, nlev.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s) ||
-            hipMemcpyAsync(c->fl_d, c->fl.data(), sizeof(double *) * Lm, hipMemcpyHostToDevice, s) ||
-            hipMemcpyAsync(c->ua_d, c->ua.data(), sizeof(double *) * Lm, hipMemcpyHostToDevice, s) ||
-            hipMemcpyAsync(c->ub_d, c->ub.data(), sizeof(double *) * Lm, hipMemcpyHostToDevice, s) ||
-            hipMemcpyAsync(c->slab_off_dd, c->slab_off_d.data(), sizeof(int64_t *) * Lm,
-                           hipMemcpyHostToDevice, s) ||
-            hipStreamSynchronize(s))
-            return fail(TMG_ERR_HIP);
     }
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
@@ -612,20 +690,16 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     }
     std::vector<double> tau(batch);
     for (int j = 0; j < batch; ++j) tau[j] = T[j] / (double)c->N[j];
+    std::vector<int> nlev(L.begin(), L.end());
     if ((rc = dalloc(c, &c->tab_fwd, tf.size())) || (rc = dalloc(c, &c->tab_adj, ta.size())) ||
         (rc = dalloc(c, &c->R_fwd, Rf.size())) || (rc = dalloc(c, &c->R_adj, Ra.size())) ||
         (rc = dalloc(c, &c->st, batch)) || (rc = dalloc(c, &c->st_ops, batch)) ||
         (rc = dalloc(c, &c->ctl, 1)) || (rc = dalloc(c, &c->tau_d, batch)) ||
-        (rc = dalloc(c, &c->grad_d, 2 * batch)))
+        (rc = dalloc(c, &c->grad_d, 2 * batch)) || (rc = dalloc(c, &c->nlev_d, batch)))
         return fail(rc);
     // partial sums: one slot per level-0 tile at the smallest tile size in use
-    int64_t maxtiles = 0;
-    for (int j = 0; j < batch; ++j) {
-        int tmin = tile_slabs(P) - even_up(kMaxSweeps + 1);
-        maxtiles += (c->N[j] + tmin - 1) / tmin;
-    }
-    c->partial_cap = maxtiles;
-    if ((rc = dalloc(c, &c->partial, maxtiles))) return fail(rc);
+    c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 2));
+    if ((rc = dalloc(c, &c->partial, c->partial_cap))) return fail(rc);
     if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
         hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess)
@@ -635,8 +709,9 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         hipMemcpyAsync(c->R_fwd, Rf.data(), Rf.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->R_adj, Ra.data(), Ra.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->tau_d, tau.data(), tau.size() * 8, hipMemcpyHostToDevice, s) ||
-        hipMemsetAsync(c->st, 0, sizeof(InstState) * batch, s) ||
-        hipStreamSynchronize(s))
+        hipMemcpyAsync(c->nlev_d, nlev.data(), nlev.size() * sizeof(int), hipMemcpyHostToDevice,
+                       s) ||
+        hipMemsetAsync(c->st, 0, sizeof(InstState) * batch, s) || hipStreamSynchronize(s))
         return fail(TMG_ERR_HIP);
     *hp = c;
     return TMG_OK;
@@ -654,8 +729,11 @@ int tmg_destroy(tmg_handle h)
 int tmg_vcycle(tmg_handle c, const double *f, const double *u0, double *u, tmg_stream stream)
 {
     if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
-    CycleIO io{f, u0, u, false, false, false};
-    return enqueue_cycle(c, io, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = make_tiles(c, s);
+    if (rc) return rc;
+    CycleIO io{f, u0, u, false, false, -1};
+    return enqueue_cycle(c, io, s);
 }
 
 int tmg_solve(tmg_handle c, const double *f, const double *u0, double *u, double rtol,
@@ -716,20 +794,17 @@ int tmg_op_down(tmg_handle c, int level, int trans, int nsweep, const double *f,
         (fold_u0 && (level != 0 || trans)))
         return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    const int H = even_up(nsweep + 1), TO = tile_slabs(c->P) - H;
+    const int H = c->rs(nsweep + 1);
     TileList *tl;
-    if ((rc = get_tiles(c, level, rcout ? kHasNext : kAll, TO, s, &tl))) return rc;
-    LevelArgs a = base_args(c, level, trans != 0);
+    if ((rc = get_tiles(c, level, rcout ? kHasNext : kAll, c->TO(H), s, &tl))) return rc;
+    LegArgs a = leg_args(c, level, trans != 0, tl, H);
     a.f = f;
     a.u0 = fold_u0;
     a.u_in = u_in;
     a.u_out = u_out;
     a.rc = rcout;
-    a.tile_off = tl->d_off;
-    a.nsweep = nsweep;
-    a.halo = H;
-    a.tile_out = TO;
-    HIPCHK(c, launch_down(c->P, trans != 0, a, tl->ntiles, s));
+    a.pre = nsweep;
+    HIPCHK(c, launch_leg(c->P, trans != 0, a, tl->ntiles, s));
     return TMG_OK;
 }
 
@@ -743,20 +818,17 @@ int tmg_op_up(tmg_handle c, int level, int trans, int nsweep, const double *f,
         (fold_u0 && (level != 0 || trans)))
         return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    const int H = even_up(nsweep + 1), TO = tile_slabs(c->P) - H;
+    const int H = c->rs(nsweep);
     TileList *tl;
-    if ((rc = get_tiles(c, level, e ? kHasNext : kAll, TO, s, &tl))) return rc;
-    LevelArgs a = base_args(c, level, trans != 0);
+    if ((rc = get_tiles(c, level, e ? kHasNext : kAll, c->TO(H), s, &tl))) return rc;
+    LegArgs a = leg_args(c, level, trans != 0, tl, H);
     a.f = f;
     a.u0 = fold_u0;
     a.u_in = u_in;
     a.e = e;
     a.u_out = u_out;
-    a.tile_off = tl->d_off;
-    a.nsweep = nsweep;
-    a.halo = H;
-    a.tile_out = TO;
-    HIPCHK(c, launch_up(c->P, trans != 0, a, tl->ntiles, s));
+    a.post = nsweep;
+    HIPCHK(c, launch_leg(c->P, trans != 0, a, tl->ntiles, s));
     return TMG_OK;
 }
 
@@ -767,8 +839,7 @@ int tmg_op_coarse_solve(tmg_handle c, int level, int trans, const double *r, dou
     if (rc) return rc;
     if (!r || !e) return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    auto key = std::make_tuple(level, 0);
-    auto it = c->op_coarse.find(key);
+    auto it = c->op_coarse.find(level);
     if (it == c->op_coarse.end()) {
         std::vector<int> list;
         for (int j = 0; j < c->batch; ++j)
@@ -781,7 +852,7 @@ int tmg_op_coarse_solve(tmg_handle c, int level, int trans, const double *r, dou
         HIPCHK(c, hipMemcpyAsync(d, list.data(), sizeof(int) * list.size(),
                                  hipMemcpyHostToDevice, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        it = c->op_coarse.emplace(key, std::make_pair(d, (int)list.size())).first;
+        it = c->op_coarse.emplace(level, std::make_pair(d, (int)list.size())).first;
     }
     CoarseArgs a{};
     a.r = r;
@@ -799,22 +870,18 @@ int tmg_op_residual_norm(tmg_handle c, int trans, const double *f, const double 
 {
     if (!c || !f || !u || !norms || (fold_u0 && trans)) return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    const int H = 2, TO = tile_slabs(c->P) - H;
+    const int H = c->rs(1);
     TileList *tl;
-    int rc = get_tiles(c, 0, kAll, TO, s, &tl);
+    int rc = get_tiles(c, 0, kAll, c->TO(H), s, &tl);
     if (rc) return rc;
     if (tl->ntiles > c->partial_cap) return TMG_ERR_INVALID;
-    LevelArgs a = base_args(c, 0, trans != 0);
+    LegArgs a = leg_args(c, 0, trans != 0, tl, H);
     a.f = f;
     a.u0 = fold_u0;
     a.u_in = u;
-    a.tile_off = tl->d_off;
     a.norm_off = tl->d_off;
     a.partial = c->partial;
-    a.nsweep = 0;
-    a.halo = H;
-    a.tile_out = TO;
-    HIPCHK(c, launch_up(c->P, trans != 0, a, tl->ntiles, s));
+    HIPCHK(c, launch_leg(c->P, trans != 0, a, tl->ntiles, s));
     HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st_ops, c->ctl, 1, s));
     HIPCHK(c, hipMemcpyAsync(c->st_host, c->st_ops, sizeof(InstState) * c->batch,
                              hipMemcpyDeviceToHost, s));

@@ -11,13 +11,19 @@ constexpr int kMaxP = 4;        // P = p + 1 coefficients per slab
 constexpr int kThreads = 256;   // work-group size of the streaming kernels
 constexpr int kMaxSweeps = 8;
 constexpr int64_t kMaxCoarse = 4096;
-constexpr int kBottomThreads = 512;    // work-group of the bottom-of-hierarchy kernel
+constexpr int kBottomThreads = 512;   // work-group of the bottom-of-hierarchy kernel
 
-// Slabs held by one thread of a streaming kernel (even, so that the two fine
-// slabs of a coarse slab always sit in the same thread).  S*P doubles per
-// array and thread.
-constexpr int slabs_per_thread(int P) { return P == 1 ? 8 : (P == 2 ? 4 : 2); }
+// Slabs held by one thread of a streaming kernel: 32-48 bytes per array and
+// thread keeps the most loads in flight per byte on HBM3E.  With S = 1 the
+// two fine slabs of a coarse slab sit in neighbouring lanes; otherwise S is
+// even and they sit in the same thread.
+constexpr int slabs_per_thread(int P) { return P == 1 ? 4 : 2; }
 constexpr int tile_slabs(int P) { return kThreads * slabs_per_thread(P); }
+// Slabs per thread of the bottom kernel (even), the largest level (slabs) it
+// holds, and the most levels it can hold (log2(bottom_max) + 1).
+constexpr int bottom_slabs(int P) { return P == 1 ? 8 : (P == 2 ? 4 : 2); }
+constexpr int bottom_max(int P) { return kBottomThreads * bottom_slabs(P); }
+constexpr int kBottomMaxLevels = 13;
 
 // Per-(instance, level) table block, doubles, for P coefficients per slab.
 // Aop is the diagonal block of the operator (A = K + lambda M, or A^T for the
@@ -52,29 +58,38 @@ struct Control {
     int pad;
 };
 
-// Arguments of the streaming kernels (one level, all participating
-// instances).  Logical slab m of an instance is physical slab m (forward) or
-// N-1-m (backward, transposed system).
-struct LevelArgs {
-    const double *f;         // level right-hand side
+// Arguments of the streaming "leg" kernel (one level, all participating
+// instances).  Logical slab m of an instance is physical slab N-1-m for the
+// transposed system (backward in time).  In order, a leg:
+//   loads f (u0 folded at level 0) and the iterate u_in (zero if null; the
+//   left halo of a tile from halo_in if given),
+//   runs `pre` sweeps, adds the prolongation of e (if e), runs `post` sweeps,
+//   stores the tile's output slabs to u_out (and its last `halo` slabs to
+//   halo_out), accumulates the squared residual (partial), and, if rc,
+//   runs `next` sweeps and stores the restricted residual.
+struct LegArgs {
+    const double *f;
     const double *u0;        // fold values (level 0, forward) or null
     const double *u_in;      // null: zero initial guess
+    const double *halo_in;   // null, or per-tile halo slabs written by the previous pass
+    const double *e;         // null: no prolongation
     double *u_out;           // null: no store
-    double *rc;              // down: restricted residual (next level), may be null
-    const double *e;         // up: coarse correction (next level), null: none
+    double *halo_out;        // null, or per-tile copy of the last `halo` output slabs
+    double *rc;              // null: no restriction
+    double *partial;         // null: no residual norm
+    const int64_t *norm_off; // [batch+1] partial-sum slots
     const double *tab;       // table blocks, instance j at tab + j*tab_stride
     const double *R;         // R1T (P*P) then R2T (P*P), swapped for backward
     const int64_t *slab_off; // [batch+1] slab offsets of this level
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
-    const int64_t *norm_off; // [batch+1] partial-sum slots (null: no norm)
     const InstState *st;     // per-instance early exit when st[j].done (may be null)
-    double *partial;         // per-tile sum of squared residuals
+    int64_t n0;              // slabs of instance 0 at this level (used when batch == 1)
     int batch;
-    int nsweep;
-    int halo;
-    int tile_out;
     int tab_stride;
+    int halo;                // left halo slabs per tile (even, a multiple of S)
+    int tile_out;            // output slabs per tile
+    int pre, post, next;     // sweep counts
 };
 
 struct CoarseArgs {
@@ -88,31 +103,27 @@ struct CoarseArgs {
     int tab_stride;
 };
 
-// One multigrid visit of levels lb[j] .. nlev[j]-1 of instance j per
-// work-group (see k_bottom).  Level arrays are device arrays of per-level
-// pointers; level 0 uses the caller's f0 / u / u0.
+// One multigrid visit of the levels `level` .. nlev[j]-1 of instance j per
+// work-group (see k_bottom), all levels resident in LDS.
 struct BottomArgs {
-    double *const *fl;              // [Lmax] level right-hand sides (fl[0] unused)
-    double *const *ua;              // [Lmax] level solutions / corrections (ua[0] unused)
-    double *const *ub;              // [Lmax] smoothed iterates of the down leg
-    const int64_t *const *slab_off; // [Lmax] -> [batch+1] slab offsets
-    const double *tab;              // tables, block (l, j) at (l * batch + j) * tab_stride
+    const double *f;         // right-hand side of level `level` (caller's f at level 0)
+    const double *u0;        // fold values (level 0, forward) or null
+    const double *x_in;      // initial guess at `level` (null: zero)
+    double *x_out;           // result at `level` (may equal x_in)
+    const int64_t *slab_off; // [batch+1] slab offsets of level `level`
+    const double *tab;       // tables, block (l, j) at (l * batch + j) * tab_stride
     const double *R;
-    const int *inst;                // instances handled, one work-group each
-    const int *lb;                  // [batch] first level handled here
-    const int *nlev;                // [batch] levels of each instance
-    const double *f0, *u0;          // caller's level-0 data (u0 may be null)
-    double *u;
+    const int *inst;         // instances handled, one work-group each
+    const int *nlev;         // [batch] levels of each instance
     const InstState *st;
-    double *partial;                // level-0 residual norm slots (null: none)
+    double *partial;         // level-0 residual norm slots (null: none)
     const int64_t *norm_off;
-    int batch, tab_stride, nu1, nu2, gamma, zero;
+    int level, batch, tab_stride, nu1, nu2, gamma;
 };
 
 // Host-side launchers (tmg_kernels.hip).  `backward` selects the transposed
 // system's backward-in-time indexing.  Return hipSuccess or the launch error.
-hipError_t launch_down(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s);
-hipError_t launch_up(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s);
+hipError_t launch_leg(int P, bool backward, const LegArgs &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
 hipError_t launch_bottom(int P, bool backward, const BottomArgs &a, int ninst, hipStream_t s);
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,

@@ -272,44 +272,110 @@ __device__ __forceinline__ void apply_G(double (&g)[S][P], const double (&f)[S][
         }
 }
 
+// The streaming leg (see LegArgs).  Every step runs on the tile in
+// registers; the tile's first `halo` slabs are recomputed copies of the left
+// neighbour's last output slabs and are never stored.  With one slab per
+// thread (S = 1) the two fine slabs of a coarse slab sit in neighbouring
+// lanes (the tile starts at an even slab) and meet through a lane shuffle.
 template <int P, bool BW>
-__global__ __launch_bounds__(kThreads) void k_down(LevelArgs a)
+__global__ __launch_bounds__(kThreads) void k_leg(LegArgs a)
 {
     constexpr int S = slabs_per_thread(P);
+    constexpr int TS = tile_slabs(P);
+    constexpr int SC = S >= 2 ? S / 2 : 1;  // coarse slabs touched per thread
     __shared__ double xchg[2][kWaves];
     __shared__ double red[kWaves];
     const int64_t tile = blockIdx.x;
-    const int j = find_instance(a.tile_off, a.batch, tile);
-    if (a.st && a.st[j].done) return;
-    const int64_t t = tile - a.tile_off[j];
-    const int64_t off = a.slab_off[j];
-    const int64_t N = a.slab_off[j + 1] - off;
-    Ops<P> op;
-    op.load(a.tab + (int64_t)j * a.tab_stride);
-
+    int j = 0;
+    int64_t t = tile, off = 0, N = a.n0, coff = 0, Nc = a.n0 / 2;
+    if (a.batch > 1) {
+        j = find_instance(a.tile_off, a.batch, tile);
+        t = tile - a.tile_off[j];
+        off = a.slab_off[j];
+        N = a.slab_off[j + 1] - off;
+        if (a.cslab_off) {
+            coff = a.cslab_off[j];
+            Nc = a.cslab_off[j + 1] - coff;
+        }
+    }
+    // every load is issued before the early-exit test: data first, then
+    // the state flag and the level tables
     const int li0 = threadIdx.x * S;
     const int64_t m0 = t * a.tile_out - a.halo + li0;
-    double f[S][P], u[S][P], g[S][P];
+    double f[S][P], u[S][P], g[S][P], e[SC][P];
     load_chunk<P, S, BW>(a.f + off * P, m0, N, f);
-    if (a.u0) fold_u0<P, S>(f, m0, a.u0[j], op);
     if (a.u_in) {
-        load_chunk<P, S, BW>(a.u_in + off * P, m0, N, u);
+        if (a.halo_in && li0 < a.halo) {
+            // left halo: the previous tile's last output slabs of the last pass
+            const double *hb = a.halo_in + (tile - 1) * (int64_t)a.halo * P + (int64_t)li0 * P;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k = 0; k < P; ++k) u[s][k] = t > 0 ? hb[s * P + k] : 0.0;
+        } else {
+            load_chunk<P, S, BW>(a.u_in + off * P, m0, N, u);
+        }
     } else {
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int k = 0; k < P; ++k) u[s][k] = 0.0;
     }
+    if (a.e) {
+        // coarse slab of this thread's slabs (floor division; -1 is outside)
+        const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+        load_chunk<P, SC, BW>(a.e + coff * P, cm0, Nc, e);
+    }
+    const int done = a.st ? a.st[j].done : 0;
+    Ops<P> op;
+    op.load(a.tab + (int64_t)j * a.tab_stride);
+    if (done) return;
+    if (a.u0) fold_u0<P, S>(f, m0, a.u0[j], op);
     apply_G<P, S>(g, f, op);
     int phase = 0;
-    sweeps<P, S, kWaves>(u, g, op, a.nsweep, xchg, phase);
-
+    sweeps<P, S, kWaves>(u, g, op, a.pre, xchg, phase);
+    if (a.e) {
+        const double *R1T = a.R, *R2T = a.R + P * P;
+        if constexpr (S >= 2) {
+#pragma unroll
+            for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                    for (int l = 0; l < P; ++l) {
+                        s1 += R1T[k * P + l] * e[i][l];
+                        s2 += R2T[k * P + l] * e[i][l];
+                    }
+                    u[2 * i][k] += s1;
+                    u[2 * i + 1][k] += s2;
+                }
+        } else {
+            const bool second = (m0 & 1) != 0;  // second fine slab of its coarse slab
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    s1 += R1T[k * P + l] * e[0][l];
+                    s2 += R2T[k * P + l] * e[0][l];
+                }
+                u[0][k] += second ? s2 : s1;
+            }
+        }
+    }
+    sweeps<P, S, kWaves>(u, g, op, a.post, xchg, phase);
     if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
-    if (!a.rc && !a.partial) return;
-
+    if (a.halo_out && li0 >= TS - a.halo) {
+        double *hb = a.halo_out + tile * (int64_t)a.halo * P + (int64_t)(li0 - (TS - a.halo)) * P;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) hb[s * P + k] = u[s][k];
+    }
     double r[S][P];
-    residual<P, S, kWaves>(r, u, f, op, xchg, phase);
     if (a.partial) {
+        residual<P, S, kWaves>(r, u, f, op, xchg, phase);
         double acc = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -320,80 +386,39 @@ __global__ __launch_bounds__(kThreads) void k_down(LevelArgs a)
         if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
     }
     if (a.rc) {
-        const double *R1T = a.R, *R2T = a.R + P * P;
-        double rc[S / 2][P];
-#pragma unroll
-        for (int i = 0; i < S / 2; ++i)
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double s1 = 0.0;
-#pragma unroll
-                for (int l = 0; l < P; ++l)
-                    s1 += R1T[l * P + k] * r[2 * i][l] + R2T[l * P + k] * r[2 * i + 1][l];
-                rc[i][k] = s1;
-            }
-        const int64_t coff = a.cslab_off[j];
-        const int64_t Nc = a.cslab_off[j + 1] - coff;
-        store_chunk<P, S / 2, BW>(a.rc + coff * P, m0 / 2, Nc, rc, li0 / 2, a.halo / 2);
-    }
-}
-
-template <int P, bool BW>
-__global__ __launch_bounds__(kThreads) void k_up(LevelArgs a)
-{
-    constexpr int S = slabs_per_thread(P);
-    __shared__ double xchg[2][kWaves];
-    __shared__ double red[kWaves];
-    const int64_t tile = blockIdx.x;
-    const int j = find_instance(a.tile_off, a.batch, tile);
-    if (a.st && a.st[j].done) return;
-    const int64_t t = tile - a.tile_off[j];
-    const int64_t off = a.slab_off[j];
-    const int64_t N = a.slab_off[j + 1] - off;
-    Ops<P> op;
-    op.load(a.tab + (int64_t)j * a.tab_stride);
-
-    const int li0 = threadIdx.x * S;
-    const int64_t m0 = t * a.tile_out - a.halo + li0;
-    double f[S][P], u[S][P], g[S][P];
-    load_chunk<P, S, BW>(a.f + off * P, m0, N, f);
-    if (a.u0) fold_u0<P, S>(f, m0, a.u0[j], op);
-    load_chunk<P, S, BW>(a.u_in + off * P, m0, N, u);
-    if (a.e) {
-        const int64_t coff = a.cslab_off[j];
-        const int64_t Nc = a.cslab_off[j + 1] - coff;
-        double e[S / 2][P];
-        load_chunk<P, S / 2, BW>(a.e + coff * P, m0 / 2, Nc, e);
-        const double *R1T = a.R, *R2T = a.R + P * P;
-#pragma unroll
-        for (int i = 0; i < S / 2; ++i)
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                for (int l = 0; l < P; ++l) {
-                    s1 += R1T[k * P + l] * e[i][l];
-                    s2 += R2T[k * P + l] * e[i][l];
-                }
-                u[2 * i][k] += s1;
-                u[2 * i + 1][k] += s2;
-            }
-    }
-    apply_G<P, S>(g, f, op);
-    int phase = 0;
-    sweeps<P, S, kWaves>(u, g, op, a.nsweep, xchg, phase);
-    if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
-    if (a.partial) {
-        double r[S][P];
+        sweeps<P, S, kWaves>(u, g, op, a.next, xchg, phase);
         residual<P, S, kWaves>(r, u, f, op, xchg, phase);
-        double acc = 0.0;
+        const double *R1T = a.R, *R2T = a.R + P * P;
+        if constexpr (S >= 2) {
+            double rc[S / 2][P];
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            if (li0 + s >= a.halo && m0 + s < N)
+            for (int i = 0; i < S / 2; ++i)
 #pragma unroll
-                for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
-        acc = block_sum<kWaves>(acc, red);
-        if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
+                for (int k = 0; k < P; ++k) {
+                    double s1 = 0.0;
+#pragma unroll
+                    for (int l = 0; l < P; ++l)
+                        s1 += R1T[l * P + k] * r[2 * i][l] + R2T[l * P + k] * r[2 * i + 1][l];
+                    rc[i][k] = s1;
+                }
+            store_chunk<P, S / 2, BW>(a.rc + coff * P, m0 / 2, Nc, rc, li0 / 2, a.halo / 2);
+        } else {
+            // the first slab of each pair takes its partner's residual from the next lane
+            double rn[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[0][k], 1, 64);
+            if (!(m0 & 1) && li0 >= a.halo && m0 >= 0 && m0 < N) {
+                double rc[1][P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    double s1 = 0.0;
+#pragma unroll
+                    for (int l = 0; l < P; ++l) s1 += R1T[l * P + k] * r[0][l] + R2T[l * P + k] * rn[l];
+                    rc[0][k] = s1;
+                }
+                store_chunk<P, 1, BW>(a.rc + coff * P, m0 / 2, Nc, rc, 0, 0);
+            }
+        }
     }
 }
 
@@ -491,59 +516,69 @@ __global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
 
 // ---------------------------------------------------------------------------
 // Bottom of the hierarchy: one work-group of kBottomThreads runs a whole
-// multigrid visit of the levels lb(j) .. L_j - 1 of instance j (V or W,
-// gamma visits of each coarser level), holding a full level in registers
-// (S slabs per thread, so no halo) and passing data between levels through
-// the hierarchy buffers, which stay in L2 at these sizes.  Replaces two
-// latency-bound launches per small level by one launch.
+// multigrid visit of levels `level` .. L_j - 1 of instance j (V or W, gamma
+// visits of each coarser level, exact scan on the coarsest), with every
+// level's right-hand side and iterate resident in LDS and every level held
+// in registers (S slabs per thread, so no halo).  The pre-smoothed iterate
+// of the down leg is recomputed in the up leg instead of stored.
 // ---------------------------------------------------------------------------
 
+template <int P>
+struct BottomLds {
+    static constexpr int BMAX = bottom_max(P);
+    static constexpr int STRIDE = TabLayout(P).stride();
+    double f[2 * BMAX * P];
+    double x[2 * BMAX * P];
+    double tab[kBottomMaxLevels * STRIDE];
+    double xchg[2][kBottomThreads / 64];
+    double red[kBottomThreads / 64];
+    ScanSmem<kBottomThreads> scan;
+};
+
 template <int P, bool BW>
-struct BottomCtx {
+struct Bottom {
     static constexpr int NT = kBottomThreads;
     static constexpr int NW = NT / 64;
-    static constexpr int S = slabs_per_thread(P);
-    const BottomArgs &a;
-    int j;
-    double (*xchg)[NW];
-    double *red;
-    ScanSmem<NT> &scan;
+    static constexpr int S = bottom_slabs(P);
+    static constexpr int STRIDE = TabLayout(P).stride();
+    BottomLds<P> &sm;
+    int lb;        // first level of this visit
+    int64_t Nlb;   // its slab count
 
-    __device__ const double *tab(int l) const
-    {
-        return a.tab + ((int64_t)l * a.batch + j) * a.tab_stride;
-    }
-    __device__ int64_t off(int l) const { return a.slab_off[l][j]; }
-    __device__ int64_t nslab(int l) const { return a.slab_off[l][j + 1] - a.slab_off[l][j]; }
-    __device__ const double *rhs(int l) const { return l == 0 ? a.f0 : a.fl[l]; }
-    __device__ double fold(int l) const { return (l == 0 && a.u0) ? a.u0[j] : 0.0; }
-    __device__ double *sol(int l) const { return l == 0 ? a.u : a.ua[l]; }
+    __device__ int64_t nslab(int l) const { return Nlb >> (l - lb); }
+    // offset (doubles) of level l in the f / x regions
+    __device__ int64_t loff(int l) const { return (2 * Nlb - 2 * nslab(l)) * P; }
+    __device__ const double *tab(int l) const { return sm.tab + (l - lb) * STRIDE; }
 
-    // nu1 sweeps from u (zero if `zero`), residual, restriction; stores the
-    // smoothed iterate in ub[l] and the restricted residual in fl[l+1].
-    __device__ void down(int l, bool zero) const
+    __device__ void load_ops(Ops<P> &op, int l) const { op.load(tab(l)); }
+
+    // nu1 sweeps from x_l (zero if `zero`), residual, restriction into f_{l+1}
+    __device__ void down(int l, bool zero, int nu1) const
     {
         Ops<P> op;
-        op.load(tab(l));
-        const int64_t N = nslab(l), o = off(l);
-        const int64_t m0 = (int64_t)threadIdx.x * S;
+        load_ops(op, l);
+        const int64_t N = nslab(l), m0 = (int64_t)threadIdx.x * S;
         double f[S][P], u[S][P], g[S][P], r[S][P];
-        load_chunk<P, S, BW>(rhs(l) + o * P, m0, N, f);
-        fold_u0<P, S>(f, m0, fold(l), op);
+        load_chunk<P, S, BW>(sm.f + loff(l), m0, N, f);
         if (zero) {
 #pragma unroll
             for (int s = 0; s < S; ++s)
 #pragma unroll
                 for (int k = 0; k < P; ++k) u[s][k] = 0.0;
         } else {
-            load_chunk<P, S, BW>(sol(l) + o * P, m0, N, u);
+            load_chunk<P, S, BW>(sm.x + loff(l), m0, N, u);
         }
         apply_G<P, S>(g, f, op);
         int phase = 0;
-        sweeps<P, S, NW>(u, g, op, a.nu1, xchg, phase);
-        store_chunk<P, S, BW>(a.ub[l] + o * P, m0, N, u, 0, 0);
-        residual<P, S, NW>(r, u, f, op, xchg, phase);
-        const double *R1T = a.R, *R2T = a.R + P * P;
+        sweeps<P, S, NW>(u, g, op, nu1, sm.xchg, phase);
+        residual<P, S, NW>(r, u, f, op, sm.xchg, phase);
+        restrict_store(r, l);
+        __syncthreads();
+    }
+
+    __device__ void restrict_store(const double (&r)[S][P], int l) const
+    {
+        const double *R1T = R, *R2T = R + P * P;
         double rc[S / 2][P];
 #pragma unroll
         for (int i = 0; i < S / 2; ++i)
@@ -555,24 +590,32 @@ struct BottomCtx {
                     s1 += R1T[q * P + k] * r[2 * i][q] + R2T[q * P + k] * r[2 * i + 1][q];
                 rc[i][k] = s1;
             }
-        store_chunk<P, S / 2, BW>(a.fl[l + 1] + off(l + 1) * P, m0 / 2, nslab(l + 1), rc, 0, 0);
-        __syncthreads();
+        const int64_t m0 = (int64_t)threadIdx.x * S;
+        store_chunk<P, S / 2, BW>(sm.f + loff(l + 1), m0 / 2, nslab(l + 1), rc, 0, 0);
     }
 
-    // u = S^nu2 (ub[l] + P e), e = sol(l+1); result in sol(l); at level 0
-    // also the squared residual norm of the result.
-    __device__ void up(int l) const
+    // x_l <- S^nu2 (S^nu1 x_l + P x_{l+1}), the pre-smoothing recomputed
+    // from x_l (or zero) exactly as in the down leg.
+    __device__ void up(int l, bool zero, int nu1, int nu2) const
     {
         Ops<P> op;
-        op.load(tab(l));
-        const int64_t N = nslab(l), o = off(l);
-        const int64_t m0 = (int64_t)threadIdx.x * S;
+        load_ops(op, l);
+        const int64_t N = nslab(l), m0 = (int64_t)threadIdx.x * S;
         double f[S][P], u[S][P], g[S][P], e[S / 2][P];
-        load_chunk<P, S, BW>(rhs(l) + o * P, m0, N, f);
-        fold_u0<P, S>(f, m0, fold(l), op);
-        load_chunk<P, S, BW>(a.ub[l] + o * P, m0, N, u);
-        load_chunk<P, S / 2, BW>(sol(l + 1) + off(l + 1) * P, m0 / 2, nslab(l + 1), e);
-        const double *R1T = a.R, *R2T = a.R + P * P;
+        load_chunk<P, S, BW>(sm.f + loff(l), m0, N, f);
+        if (zero) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k = 0; k < P; ++k) u[s][k] = 0.0;
+        } else {
+            load_chunk<P, S, BW>(sm.x + loff(l), m0, N, u);
+        }
+        load_chunk<P, S / 2, BW>(sm.x + loff(l + 1), m0 / 2, nslab(l + 1), e);
+        apply_G<P, S>(g, f, op);
+        int phase = 0;
+        sweeps<P, S, NW>(u, g, op, nu1, sm.xchg, phase);
+        const double *R1T = R, *R2T = R + P * P;
 #pragma unroll
         for (int i = 0; i < S / 2; ++i)
 #pragma unroll
@@ -586,97 +629,142 @@ struct BottomCtx {
                 u[2 * i][k] += s1;
                 u[2 * i + 1][k] += s2;
             }
-        apply_G<P, S>(g, f, op);
-        int phase = 0;
-        sweeps<P, S, NW>(u, g, op, a.nu2, xchg, phase);
-        store_chunk<P, S, BW>(sol(l) + o * P, m0, N, u, 0, 0);
-        if (l == 0 && a.partial) norm_out(u, f, op, phase);
+        sweeps<P, S, NW>(u, g, op, nu2, sm.xchg, phase);
+        // every thread owns the slabs it writes, so the update is in place
+        store_chunk<P, S, BW>(sm.x + loff(l), m0, N, u, 0, 0);
         __syncthreads();
     }
 
-    __device__ void norm_out(const double (&u)[S][P], const double (&f)[S][P], const Ops<P> &op,
-                             int &phase) const
+    __device__ void coarse(int l) const
     {
-        double r[S][P];
-        residual<P, S, NW>(r, u, f, op, xchg, phase);
-        const int64_t N = nslab(0), m0 = (int64_t)threadIdx.x * S;
+        coarse_scan<P, BW, NT>(sm.f + loff(l), 0.0, sm.x + loff(l), nslab(l), tab(l), sm.scan);
+        __syncthreads();
+    }
+
+    const double *R;
+};
+
+template <int P, bool BW>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
+{
+    using B = Bottom<P, BW>;
+    constexpr int NT = B::NT, S = B::S, STRIDE = B::STRIDE;
+    __shared__ BottomLds<P> sm;
+    const int j = a.inst[blockIdx.x];
+    if (a.st && a.st[j].done) return;
+    const int lb = a.level, Lc = a.nlev[j] - 1;
+    const int64_t off = a.slab_off[j];
+    const int64_t N = a.slab_off[j + 1] - off;
+    if (lb == Lc) {
+        // a single level (any size up to the largest coarsest level): the
+        // exact solve, directly in global memory
+        const double *tab = a.tab + ((int64_t)lb * a.batch + j) * a.tab_stride;
+        const double u0 = (lb == 0 && a.u0) ? a.u0[j] : 0.0;
+        coarse_scan<P, BW, NT>(a.f + off * P, u0, a.x_out + off * P, N, tab, sm.scan);
+        if (lb == 0 && a.partial) {
+            // squared residual of the result, one slab per thread and pass
+            constexpr TabLayout L(P);
+            const double *x = a.x_out + off * P, *f = a.f + off * P;
+            double acc = 0.0;
+            for (int64_t m = threadIdx.x; m < N; m += NT) {
+                const int64_t pm = BW ? N - 1 - m : m;
+                double w = 0.0;
+                if (m > 0) {
+                    const int64_t pl = BW ? pm + 1 : pm - 1;
+#pragma unroll
+                    for (int k = 0; k < P; ++k) w += tab[L.C() + k] * x[pl * P + k];
+                }
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    double r = f[pm * P + k] + tab[L.V() + k] * (w + (m == 0 ? u0 : 0.0));
+#pragma unroll
+                    for (int q = 0; q < P; ++q) r -= tab[L.A() + k * P + q] * x[pm * P + q];
+                    acc += r * r;
+                }
+            }
+            acc = block_sum<B::NW>(acc, sm.red);
+            if (threadIdx.x == 0) sm.red[0] = acc;
+            __syncthreads();
+            acc = sm.red[0];
+            const int64_t lo = a.norm_off[j], hi = a.norm_off[j + 1];
+            for (int64_t i = lo + threadIdx.x; i < hi; i += NT) a.partial[i] = i == lo ? acc : 0.0;
+        }
+        return;
+    }
+    B b{sm, lb, N, a.R};
+    // tables of levels lb .. Lc, the right-hand side and the initial guess
+    for (int l = lb; l <= Lc; ++l)
+        for (int i = threadIdx.x; i < STRIDE; i += NT)
+            sm.tab[(l - lb) * STRIDE + i] = a.tab[((int64_t)l * a.batch + j) * a.tab_stride + i];
+    for (int64_t i = threadIdx.x; i < N * P; i += NT) {
+        sm.f[i] = a.f[off * P + i];
+        sm.x[i] = a.x_in ? a.x_in[off * P + i] : 0.0;
+    }
+    __syncthreads();
+    if (a.u0 && threadIdx.x < P) {
+        // fold u0 into the first slab in time (physical slab 0, forward only)
+        constexpr TabLayout L(P);
+        sm.f[threadIdx.x] += a.u0[j] * sm.tab[L.V() + threadIdx.x];
+    }
+    __syncthreads();
+    const bool zero = a.x_in == nullptr;
+    {
+        // visit(l) = down(l); [exact solve at l+1 | gamma x visit(l+1)]; up(l),
+        // iteratively; bit l of `again` marks the second visit of level l.
+        uint64_t again = 0;
+        int l = lb;
+        b.down(l, zero, a.nu1);
+        while (true) {
+            if (l + 1 == Lc) {
+                b.coarse(l + 1);
+                b.up(l, l == lb ? zero : !((again >> l) & 1), a.nu1, a.nu2);
+                bool done = false;
+                while (true) {
+                    if (l == lb) {
+                        done = true;
+                        break;
+                    }
+                    if (a.gamma > 1 && !((again >> l) & 1)) {
+                        again |= (uint64_t)1 << l;
+                        b.down(l, false, a.nu1);
+                        break;
+                    }
+                    again &= ~((uint64_t)1 << l);
+                    --l;
+                    b.up(l, l == lb ? zero : !((again >> l) & 1), a.nu1, a.nu2);
+                }
+                if (done) break;
+            } else {
+                ++l;
+                b.down(l, true, a.nu1);
+            }
+        }
+    }
+    // result of level lb back to global memory
+    for (int64_t i = threadIdx.x; i < N * P; i += NT) a.x_out[off * P + i] = sm.x[i];
+    if (lb == 0 && a.partial) {
+        // squared residual of the result (level 0 of this instance)
+        Ops<P> op;
+        b.load_ops(op, 0);
+        const int64_t m0 = (int64_t)threadIdx.x * S;
+        double f[S][P], u[S][P], r[S][P];
+        load_chunk<P, S, BW>(sm.f, m0, N, f);
+        load_chunk<P, S, BW>(sm.x, m0, N, u);
+        int phase = 0;
+        residual<P, S, B::NW>(r, u, f, op, sm.xchg, phase);
         double acc = 0.0;
 #pragma unroll
         for (int s = 0; s < S; ++s)
             if (m0 + s < N)   // slabs past the end see a nonzero left neighbour
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
-        acc = block_sum<NW>(acc, red);
-        if (threadIdx.x == 0) red[0] = acc;
+        acc = block_sum<B::NW>(acc, sm.red);
+        if (threadIdx.x == 0) sm.red[0] = acc;
         __syncthreads();
-        acc = red[0];
+        acc = sm.red[0];
         // the instance's whole sum goes to its first slot, the others are zeroed
         const int64_t lo = a.norm_off[j], hi = a.norm_off[j + 1];
         for (int64_t i = lo + threadIdx.x; i < hi; i += NT) a.partial[i] = i == lo ? acc : 0.0;
-    }
-
-    // exact solve on the coarsest level l (and, at level 0, its residual norm)
-    __device__ void coarse(int l) const
-    {
-        coarse_scan<P, BW, NT>(rhs(l) + off(l) * P, fold(l), sol(l) + off(l) * P, nslab(l), tab(l),
-                               scan);
-        __syncthreads();
-        if (l == 0 && a.partial) {
-            Ops<P> op;
-            op.load(tab(0));
-            const int64_t N = nslab(0), o = off(0);
-            const int64_t m0 = (int64_t)threadIdx.x * S;
-            double f[S][P], u[S][P];
-            load_chunk<P, S, BW>(rhs(0) + o * P, m0, N, f);
-            fold_u0<P, S>(f, m0, fold(0), op);
-            load_chunk<P, S, BW>(sol(0) + o * P, m0, N, u);
-            int phase = 0;
-            norm_out(u, f, op, phase);
-            __syncthreads();
-        }
-    }
-};
-
-template <int P, bool BW>
-__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
-{
-    using C = BottomCtx<P, BW>;
-    __shared__ double xchg[2][C::NW];
-    __shared__ double red[C::NW];
-    __shared__ ScanSmem<C::NT> scan;
-    const int j = a.inst[blockIdx.x];
-    if (a.st && a.st[j].done) return;
-    C c{a, j, xchg, red, scan};
-    const int lb = a.lb[j], Lc = a.nlev[j] - 1;
-    if (lb == Lc) {
-        c.coarse(lb);
-        return;
-    }
-    // visit(l) = down(l); [coarse(l+1) | gamma x visit(l+1)]; up(l),
-    // iteratively; bit l of `again` marks that visit(l) runs once more.
-    uint64_t again = 0;
-    int l = lb;
-    c.down(l, a.zero != 0);
-    while (true) {
-        if (l + 1 == Lc) {
-            c.coarse(l + 1);
-            c.up(l);
-            // visit(l) is complete: repeat it, or finish its parent
-            while (true) {
-                if (l == lb) return;
-                if (a.gamma > 1 && !((again >> l) & 1)) {
-                    again |= (uint64_t)1 << l;
-                    c.down(l, false);
-                    break;
-                }
-                again &= ~((uint64_t)1 << l);
-                --l;
-                c.up(l);
-            }
-        } else {
-            ++l;
-            c.down(l, true);
-        }
     }
 }
 
@@ -795,22 +883,12 @@ __global__ __launch_bounds__(kThreads) void k_grad(const double *__restrict__ u,
     default: return hipErrorInvalidValue;             \
     }
 
-hipError_t launch_down(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s)
+hipError_t launch_leg(int P, bool backward, const LegArgs &a, int64_t ntiles, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_down<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_down<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
-    })
-    return hipGetLastError();
-}
-
-hipError_t launch_up(int P, bool backward, const LevelArgs &a, int64_t ntiles, hipStream_t s)
-{
-    if (ntiles <= 0) return hipSuccess;
-    TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_up<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_up<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        if (backward) hipLaunchKernelGGL((k_leg<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_leg<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
     })
     return hipGetLastError();
 }
