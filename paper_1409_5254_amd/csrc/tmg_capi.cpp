@@ -60,6 +60,13 @@ struct GraphKey {
 // graph kinds: the first cycle of a solve, and later cycles by halo parity
 enum { kFirst = 0, kEven = 1, kOdd = 2 };
 
+// Level buffers of one precision: right-hand side and two iterates per level.
+template <typename T>
+struct LevelStore {
+    std::vector<T *> f, xa, xb;
+    T *x(int l, int which) const { return which ? xb[l] : xa[l]; }
+};
+
 }  // namespace
 
 struct tmg_ctx {
@@ -71,12 +78,15 @@ struct tmg_ctx {
     std::vector<int> lb;                          // first level of the bottom kernel
     std::vector<std::vector<int64_t>> slab_off_h; // [Lmax][batch+1]
     std::vector<int64_t *> slab_off_d;
-    std::vector<double *> fl;                     // level right-hand sides (level >= 1)
-    std::vector<double *> xa, xb;                 // level iterates, two per level (level >= 1)
-    std::vector<int64_t> level_size;              // doubles per level
+    LevelStore<double> d;                         // FP64 hierarchy (plain method)
+    LevelStore<float> s;                          // FP32 hierarchy (mixed precision)
+    std::vector<int64_t> level_size;              // coefficients per level
     double *hb[2] = {nullptr, nullptr};           // level-0 halo buffers
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
+    float *tab32_fwd = nullptr, *tab32_adj = nullptr;  // the same tables rounded to FP32
+    float *R32_fwd = nullptr, *R32_adj = nullptr;
+    bool mixed = false;
     int tab_stride = 0;
     int *nlev_d = nullptr;
     std::vector<int *> bot_d;                     // per level: instances with lb == level
@@ -106,8 +116,12 @@ struct tmg_ctx {
     int H_down() const { return rs(opt.nu1 + 1); }
     int H_up() const { return rs(opt.nu1 + opt.nu2); }
     int H_fused() const { return rs(2 * opt.nu1 + opt.nu2 + 1); }
+    // mixed precision, level 0: first down pass, fused pass, single cycle
+    int H_mixd() const { return rs(opt.nu1 + 2); }
+    int H_mix() const { return rs(2 * opt.nu1 + opt.nu2 + 3); }
+    int H_mixv() const { return rs(opt.nu1 + opt.nu2 + 1); }
+    int H_norm() const { return mixed ? H_mix() : H_fused(); }
     int TO(int H) const { return tile_slabs(P) - H; }
-    double *x(int l, int which) const { return which ? xb[l] : xa[l]; }
 };
 
 namespace {
@@ -187,11 +201,30 @@ const double *tab_of(const tmg_ctx *c, int level, bool trans)
     return (trans ? c->tab_adj : c->tab_fwd) + (int64_t)level * c->batch * c->tab_stride;
 }
 
-LegArgs leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl, int H)
+template <typename T> LevelStore<T> &store(tmg_ctx *c);
+template <> LevelStore<double> &store<double>(tmg_ctx *c) { return c->d; }
+template <> LevelStore<float> &store<float>(tmg_ctx *c) { return c->s; }
+
+template <typename T> const T *tabT_of(const tmg_ctx *c, int level, bool trans);
+template <> const double *tabT_of<double>(const tmg_ctx *c, int level, bool trans)
 {
-    LegArgs a{};
+    return tab_of(c, level, trans);
+}
+template <> const float *tabT_of<float>(const tmg_ctx *c, int level, bool trans)
+{
+    return (trans ? c->tab32_adj : c->tab32_fwd) + (int64_t)level * c->batch * c->tab_stride;
+}
+template <typename T> const T *R_of(const tmg_ctx *c, bool trans);
+template <> const double *R_of<double>(const tmg_ctx *c, bool trans) { return trans ? c->R_adj : c->R_fwd; }
+template <> const float *R_of<float>(const tmg_ctx *c, bool trans) { return trans ? c->R32_adj : c->R32_fwd; }
+
+template <typename T = double>
+LegArgsT<T> leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl, int H)
+{
+    LegArgsT<T> a{};
     a.tab = tab_of(c, level, trans);
-    a.R = trans ? c->R_adj : c->R_fwd;
+    a.tabT = tabT_of<T>(c, level, trans);
+    a.R = R_of<T>(c, trans);
     a.slab_off = c->slab_off_d[level];
     a.cslab_off = level + 1 < c->Lmax ? c->slab_off_d[level + 1] : nullptr;
     a.tile_off = tl->d_off;
@@ -214,13 +247,15 @@ struct CycleIO {
 
 const double *fold_of(const CycleIO &io) { return io.trans ? nullptr : io.u0; }
 
-// Bottom kernel for the instances whose bottom part starts at `level`.
-int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const double *x_in, double *x_out,
+// Bottom kernel for the instances whose bottom part starts at `level`
+// (level 0: the caller's FP64 arrays; otherwise the level buffers of T).
+template <typename T>
+int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x_out,
                    hipStream_t s)
 {
     if (c->bot_n[level] == 0) return TMG_OK;
-    BottomArgs a{};
-    a.f = level == 0 ? io.f : c->fl[level];
+    BottomArgsT<T> a{};
+    a.f = level == 0 ? reinterpret_cast<const T *>(io.f) : store<T>(c).f[level];
     a.u0 = level == 0 ? fold_of(io) : nullptr;
     a.x_in = x_in;
     a.x_out = x_out;
@@ -232,7 +267,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const double *x_in,
     a.st = io.use_state ? c->st : nullptr;
     if (level == 0 && io.use_state) {
         TileList *nl;
-        int rc = get_tiles(c, 0, kAll, c->TO(c->H_fused()), s, &nl);
+        int rc = get_tiles(c, 0, kAll, c->TO(c->H_norm()), s, &nl);
         if (rc) return rc;
         a.partial = c->partial;
         a.norm_off = nl->d_off;
@@ -243,26 +278,28 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const double *x_in,
     a.nu1 = c->opt.nu1;
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
-    HIPCHK(c, launch_bottom(c->P, io.trans, a, c->bot_n[level], s));
+    HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, c->bot_n[level], s));
     return TMG_OK;
 }
 
 // Down leg (streaming instances): nu1 sweeps from the current iterate (zero
 // on a first visit), residual, restriction into the next level.
+template <typename T>
 int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
 {
     TileList *tl;
     const int H = c->H_down();
     int rc = get_tiles(c, level, kDeep, c->TO(H), s, &tl);
     if (rc) return rc;
-    LegArgs a = leg_args(c, level, io.trans, tl, H);
-    a.f = level == 0 ? io.f : c->fl[level];
+    LevelStore<T> &L = store<T>(c);
+    LegArgsT<T> a = leg_args<T>(c, level, io.trans, tl, H);
+    a.f = level == 0 ? reinterpret_cast<const T *>(io.f) : L.f[level];
     a.u0 = level == 0 ? fold_of(io) : nullptr;
-    a.u_in = zero ? nullptr : (level == 0 ? io.u : c->x(level, c->cur[level]));
-    a.rc = c->fl[level + 1];
+    a.u_in = zero ? nullptr : (level == 0 ? reinterpret_cast<const T *>(io.u) : L.x(level, c->cur[level]));
+    a.rc = L.f[level + 1];
     a.st = io.use_state ? c->st : nullptr;
     a.pre = c->opt.nu1;
-    HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+    HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
     return TMG_OK;
 }
 
@@ -270,56 +307,130 @@ int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_
 // initial iterate, correction with the next level's result, nu2 sweeps.
 // A first visit writes the current buffer (nothing is read from it); a
 // repeated visit (W-cycle) writes the other one and makes it current.
+template <typename T>
 int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
 {
     TileList *tl;
     const int H = c->H_up();
     int rc = get_tiles(c, level, kDeep, c->TO(H), s, &tl);
     if (rc) return rc;
-    LegArgs a = leg_args(c, level, io.trans, tl, H);
+    LevelStore<T> &L = store<T>(c);
+    LegArgsT<T> a = leg_args<T>(c, level, io.trans, tl, H);
     const int cur = c->cur[level];
-    a.f = c->fl[level];
-    a.u_in = zero ? nullptr : c->x(level, cur);
-    a.e = c->x(level + 1, c->cur[level + 1]);
-    a.u_out = zero ? c->x(level, cur) : c->x(level, cur ^ 1);
+    a.f = L.f[level];
+    a.u_in = zero ? nullptr : L.x(level, cur);
+    a.e = L.x(level + 1, c->cur[level + 1]);
+    a.u_out = zero ? L.x(level, cur) : L.x(level, cur ^ 1);
     a.st = io.use_state ? c->st : nullptr;
     a.pre = c->opt.nu1;
     a.post = c->opt.nu2;
-    HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+    HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
     if (!zero) c->cur[level] ^= 1;
     return TMG_OK;
 }
 
+template <typename T>
 int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s);
 
+template <typename T>
 int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
 {
-    int rc = enqueue_down(c, io, level, zero, s);
+    int rc = enqueue_down<T>(c, io, level, zero, s);
     if (rc) return rc;
-    if ((rc = enqueue_coarse_visits(c, io, level + 1, s))) return rc;
-    return enqueue_up(c, io, level, zero, s);
+    if ((rc = enqueue_coarse_visits<T>(c, io, level + 1, s))) return rc;
+    return enqueue_up<T>(c, io, level, zero, s);
 }
 
 // gamma visits of level l >= 1 from zero: bottom-kernel instances and,
 // recursively, the streaming ones.  (When l is an instance's coarsest
 // level its visit is the exact solve; repeating it changes nothing.)
+template <typename T>
 int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s)
 {
     int rc;
+    LevelStore<T> &L = store<T>(c);
     c->cur[l] = 0;
     for (int g = 0; g < c->opt.gamma; ++g) {
         const int cur = c->cur[l];
         // bottom instances: a first visit starts from zero in place, a repeated
         // one reads the current buffer and writes the other (like enqueue_up)
-        if ((rc = enqueue_bottom(c, io, l, g == 0 ? nullptr : c->x(l, cur),
-                                 g == 0 ? c->x(l, cur) : c->x(l, cur ^ 1), s)))
+        if ((rc = enqueue_bottom<T>(c, io, l, g == 0 ? nullptr : L.x(l, cur),
+                                    g == 0 ? L.x(l, cur) : L.x(l, cur ^ 1), s)))
             return rc;
         if (c->deep_n[l] > 0) {
-            if ((rc = enqueue_visit(c, io, l, g == 0, s))) return rc;
+            if ((rc = enqueue_visit<T>(c, io, l, g == 0, s))) return rc;
         } else if (g > 0) {
             c->cur[l] ^= 1;
         }
     }
+    return TMG_OK;
+}
+
+// Level-0 part of a cycle of the FP32-inner defect correction (streaming
+// instances): see k_mix.
+int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
+{
+    int rc;
+    TileList *tl;
+    const bool solve = io.kind >= 0, first = io.kind == kFirst;
+    auto margs = [&](int H, TileList *t) {
+        MixArgs a{};
+        a.f = io.f;
+        a.u0 = fold_of(io);
+        a.tab = tab_of(c, 0, io.trans);
+        a.tab32 = tabT_of<float>(c, 0, io.trans);
+        a.R32 = R_of<float>(c, io.trans);
+        a.slab_off = c->slab_off_d[0];
+        a.cslab_off = c->slab_off_d[1];
+        a.tile_off = t->d_off;
+        a.st = io.use_state ? c->st : nullptr;
+        a.n0 = c->N[0];
+        a.batch = c->batch;
+        a.tab_stride = c->tab_stride;
+        a.halo = H;
+        a.tile_out = c->TO(H);
+        a.pre = c->opt.nu1;
+        a.post = c->opt.nu2;
+        a.next = c->opt.nu1;
+        return a;
+    };
+    if (!solve) {
+        // warm start: seed the halo buffer from the caller's iterate
+        const int H = c->H_mixv();
+        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+        LegArgs a = leg_args(c, 0, io.trans, tl, H);
+        a.f = io.f;
+        a.u_in = io.u;
+        a.halo_out = c->hb[0];
+        HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
+    }
+    if (!solve || first) {
+        // first inner down leg: residual of the iterate, FP32 sweeps, restriction
+        const int H = c->H_mixd();
+        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+        MixArgs a = margs(H, tl);
+        a.u_in = first ? nullptr : io.u;
+        a.rc = c->s.f[1];
+        HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
+    }
+    if ((rc = enqueue_coarse_visits<float>(c, io, 1, s))) return rc;
+    const int H = solve ? c->H_mix() : c->H_mixv();
+    if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+    MixArgs a = margs(H, tl);
+    a.up = 1;
+    a.u_in = first ? nullptr : io.u;
+    a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]);
+    a.e = c->s.x(1, c->cur[1]);
+    a.u_out = io.u;
+    if (solve) {
+        a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
+        a.rc = c->s.f[1];
+        TileList *nl;
+        if ((rc = get_tiles(c, 0, kAll, c->TO(H), s, &nl))) return rc;
+        a.partial = c->partial;
+        a.norm_off = nl->d_off;
+    }
+    HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
     return TMG_OK;
 }
 
@@ -329,8 +440,11 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     const bool first = io.kind == kFirst;
     c->cur.assign(c->Lmax + 1, 0);
     // instances that fit the bottom kernel entirely: the cycle is one launch
-    if ((rc = enqueue_bottom(c, io, 0, first ? nullptr : io.u, io.u, s))) return rc;
-    if (c->deep_n[0] > 0) {
+    // (FP64 in both precision modes)
+    if ((rc = enqueue_bottom<double>(c, io, 0, first ? nullptr : io.u, io.u, s))) return rc;
+    if (c->deep_n[0] > 0 && c->mixed) {
+        if ((rc = enqueue_mixed_level0(c, io, s))) return rc;
+    } else if (c->deep_n[0] > 0) {
         TileList *tl;
         const bool solve = io.kind >= 0;
         if (!solve) {
@@ -341,11 +455,11 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             a.f = io.f;
             a.u_in = io.u;
             a.halo_out = c->hb[0];
-            HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+            HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
         }
         if (!solve || first)
-            if ((rc = enqueue_down(c, io, 0, first, s))) return rc;
-        if ((rc = enqueue_coarse_visits(c, io, 1, s))) return rc;
+            if ((rc = enqueue_down<double>(c, io, 0, first, s))) return rc;
+        if ((rc = enqueue_coarse_visits<double>(c, io, 1, s))) return rc;
         // fused level-0 pass
         const int H = solve ? c->H_fused() : c->H_up();
         if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
@@ -354,25 +468,25 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.u0 = fold_of(io);
         a.u_in = first ? nullptr : io.u;
         a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]);
-        a.e = c->x(1, c->cur[1]);
+        a.e = c->d.x(1, c->cur[1]);
         a.u_out = io.u;
         a.st = io.use_state ? c->st : nullptr;
         a.pre = c->opt.nu1;
         a.post = c->opt.nu2;
         if (solve) {
             a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
-            a.rc = c->fl[1];
+            a.rc = c->d.f[1];
             a.next = c->opt.nu1;
             TileList *nl;
             if ((rc = get_tiles(c, 0, kAll, c->TO(H), s, &nl))) return rc;
             a.partial = c->partial;
             a.norm_off = nl->d_off;
         }
-        HIPCHK(c, launch_leg(c->P, io.trans, a, tl->ntiles, s));
+        HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
     }
     if (io.use_state) {
         TileList *nl;
-        if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_fused()), s, &nl))) return rc;
+        if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_norm()), s, &nl))) return rc;
         HIPCHK(c, launch_finalize(c->partial, nl->d_off, c->batch, c->st, c->ctl, 0, s));
     }
     return TMG_OK;
@@ -387,8 +501,10 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
         if ((rc = get_tiles(c, l, kDeep, c->TO(c->H_down()), s, &tl))) return rc;
         if ((rc = get_tiles(c, l, kDeep, c->TO(c->H_up()), s, &tl))) return rc;
     }
-    if ((rc = get_tiles(c, 0, kDeep, c->TO(c->H_fused()), s, &tl))) return rc;
-    if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_fused()), s, &tl))) return rc;
+    const int H0[5] = {c->H_fused(), c->H_mixd(), c->H_mix(), c->H_mixv(), c->H_up()};
+    for (int H : H0)
+        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+    if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_norm()), s, &tl))) return rc;
     return TMG_OK;
 }
 
@@ -567,7 +683,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         o.n_coarse > kMaxCoarse || (o.omega_mode != 0 && o.omega_mode != 1))
         return TMG_ERR_INVALID;
     if (o.omega_mode == 1 && !(o.omega > 0.0 && o.omega <= 1.0)) return TMG_ERR_OMEGA;
-    if (o.precision != 0) return TMG_ERR_UNSUPPORTED;
+    if (o.precision != 0 && o.precision != 1) return TMG_ERR_UNSUPPORTED;
     std::vector<int> L(batch);
     for (int j = 0; j < batch; ++j) {
         if (!(std::isfinite(T[j]) && T[j] > 0.0 && std::isfinite(lambda[j]) && lambda[j] > 0.0))
@@ -627,9 +743,13 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     c->slab_off_h.assign(Lm, std::vector<int64_t>(batch + 1, 0));
     c->slab_off_d.assign(Lm, nullptr);
     c->level_size.assign(Lm, 0);
-    c->fl.assign(Lm + 1, nullptr);
-    c->xa.assign(Lm + 1, nullptr);
-    c->xb.assign(Lm + 1, nullptr);
+    c->mixed = o.precision == 1;
+    c->d.f.assign(Lm + 1, nullptr);
+    c->d.xa.assign(Lm + 1, nullptr);
+    c->d.xb.assign(Lm + 1, nullptr);
+    c->s.f.assign(Lm + 1, nullptr);
+    c->s.xa.assign(Lm + 1, nullptr);
+    c->s.xb.assign(Lm + 1, nullptr);
     c->deep_n.assign(Lm + 1, 0);
     c->bot_n.assign(Lm + 1, 0);
     c->bot_d.assign(Lm + 1, nullptr);
@@ -654,16 +774,23 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                 return fail(TMG_ERR_HIP);
         }
         if (hipStreamSynchronize(s) != hipSuccess) return fail(TMG_ERR_HIP);
-        if (l > 0) {
-            if ((rc = dalloc(c, &c->fl[l], c->level_size[l])) ||
-                (rc = dalloc(c, &c->xa[l], c->level_size[l])) ||
-                (rc = dalloc(c, &c->xb[l], c->level_size[l])))
+        // coarse-level buffers in the precision of the cycle below level 0
+        if (l > 0 && !c->mixed) {
+            if ((rc = dalloc(c, &c->d.f[l], c->level_size[l])) ||
+                (rc = dalloc(c, &c->d.xa[l], c->level_size[l])) ||
+                (rc = dalloc(c, &c->d.xb[l], c->level_size[l])))
+                return fail(rc);
+        }
+        if (l > 0 && c->mixed) {
+            if ((rc = dalloc(c, &c->s.f[l], c->level_size[l])) ||
+                (rc = dalloc(c, &c->s.xa[l], c->level_size[l])) ||
+                (rc = dalloc(c, &c->s.xb[l], c->level_size[l])))
                 return fail(rc);
         }
     }
     // level-0 halo buffers: one slot of H x P doubles per tile
     {
-        const int Hs[2] = {c->H_fused(), c->H_up()};
+        const int Hs[5] = {c->H_fused(), c->H_up(), c->H_mix(), c->H_mixv(), c->H_mixd()};
         int64_t hsize = 0;
         for (int H : Hs) hsize = std::max(hsize, tiles_of(c, 0, kDeep, c->TO(H)) * H * P);
         if ((rc = dalloc(c, &c->hb[0], hsize)) || (rc = dalloc(c, &c->hb[1], hsize)))
@@ -698,7 +825,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         (rc = dalloc(c, &c->grad_d, 2 * batch)) || (rc = dalloc(c, &c->nlev_d, batch)))
         return fail(rc);
     // partial sums: one slot per level-0 tile at the smallest tile size in use
-    c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 2));
+    c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
     if ((rc = dalloc(c, &c->partial, c->partial_cap))) return fail(rc);
     if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
@@ -713,6 +840,21 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                        s) ||
         hipMemsetAsync(c->st, 0, sizeof(InstState) * batch, s) || hipStreamSynchronize(s))
         return fail(TMG_ERR_HIP);
+    if (c->mixed) {
+        // FP32 copies of the tables for the inner cycle
+        std::vector<float> tf32(tf.begin(), tf.end()), ta32(ta.begin(), ta.end()),
+            Rf32(Rf.begin(), Rf.end()), Ra32(Ra.begin(), Ra.end());
+        if ((rc = dalloc(c, &c->tab32_fwd, tf32.size())) ||
+            (rc = dalloc(c, &c->tab32_adj, ta32.size())) ||
+            (rc = dalloc(c, &c->R32_fwd, Rf32.size())) || (rc = dalloc(c, &c->R32_adj, Ra32.size())))
+            return fail(rc);
+        if (hipMemcpyAsync(c->tab32_fwd, tf32.data(), tf32.size() * 4, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->tab32_adj, ta32.data(), ta32.size() * 4, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->R32_fwd, Rf32.data(), Rf32.size() * 4, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->R32_adj, Ra32.data(), Ra32.size() * 4, hipMemcpyHostToDevice, s) ||
+            hipStreamSynchronize(s))
+            return fail(TMG_ERR_HIP);
+    }
     *hp = c;
     return TMG_OK;
 }
@@ -804,7 +946,7 @@ int tmg_op_down(tmg_handle c, int level, int trans, int nsweep, const double *f,
     a.u_out = u_out;
     a.rc = rcout;
     a.pre = nsweep;
-    HIPCHK(c, launch_leg(c->P, trans != 0, a, tl->ntiles, s));
+    HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
     return TMG_OK;
 }
 
@@ -828,7 +970,7 @@ int tmg_op_up(tmg_handle c, int level, int trans, int nsweep, const double *f,
     a.e = e;
     a.u_out = u_out;
     a.post = nsweep;
-    HIPCHK(c, launch_leg(c->P, trans != 0, a, tl->ntiles, s));
+    HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
     return TMG_OK;
 }
 
@@ -881,7 +1023,7 @@ int tmg_op_residual_norm(tmg_handle c, int trans, const double *f, const double 
     a.u_in = u;
     a.norm_off = tl->d_off;
     a.partial = c->partial;
-    HIPCHK(c, launch_leg(c->P, trans != 0, a, tl->ntiles, s));
+    HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
     HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st_ops, c->ctl, 1, s));
     HIPCHK(c, hipMemcpyAsync(c->st_host, c->st_ops, sizeof(InstState) * c->batch,
                              hipMemcpyDeviceToHost, s));

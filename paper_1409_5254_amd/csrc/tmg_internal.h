@@ -67,19 +67,21 @@ struct Control {
 //   stores the tile's output slabs to u_out (and its last `halo` slabs to
 //   halo_out), accumulates the squared residual (partial), and, if rc,
 //   runs `next` sweeps and stores the restricted residual.
-struct LegArgs {
-    const double *f;
+template <typename T>
+struct LegArgsT {
+    const T *f;
     const double *u0;        // fold values (level 0, forward) or null
-    const double *u_in;      // null: zero initial guess
-    const double *halo_in;   // null, or per-tile halo slabs written by the previous pass
-    const double *e;         // null: no prolongation
-    double *u_out;           // null: no store
-    double *halo_out;        // null, or per-tile copy of the last `halo` output slabs
-    double *rc;              // null: no restriction
+    const T *u_in;           // null: zero initial guess
+    const T *halo_in;        // null, or per-tile halo slabs written by the previous pass
+    const T *e;              // null: no prolongation
+    T *u_out;                // null: no store
+    T *halo_out;             // null, or per-tile copy of the last `halo` output slabs
+    T *rc;                   // null: no restriction
     double *partial;         // null: no residual norm
     const int64_t *norm_off; // [batch+1] partial-sum slots
-    const double *tab;       // table blocks, instance j at tab + j*tab_stride
-    const double *R;         // R1T (P*P) then R2T (P*P), swapped for backward
+    const double *tab;       // FP64 table blocks, instance j at tab + j*tab_stride
+    const T *tabT;           // the same tables in T
+    const T *R;              // R1T (P*P) then R2T (P*P), swapped for backward, in T
     const int64_t *slab_off; // [batch+1] slab offsets of this level
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
@@ -90,6 +92,31 @@ struct LegArgs {
     int halo;                // left halo slabs per tile (even, a multiple of S)
     int tile_out;            // output slabs per tile
     int pre, post, next;     // sweep counts
+};
+using LegArgs = LegArgsT<double>;
+
+// Fused level-0 pass of the FP32-inner defect correction (k_mix).
+struct MixArgs {
+    const double *f;
+    const double *u0;
+    const double *u_in;      // FP64 iterate (null: zero)
+    const double *halo_in;
+    const float *e;          // inner correction of level 1
+    double *u_out;
+    double *halo_out;
+    float *rc;               // inner restricted residual for level 1 (null: none)
+    double *partial;
+    const int64_t *norm_off;
+    const double *tab;
+    const float *tab32;
+    const float *R32;
+    const int64_t *slab_off;
+    const int64_t *cslab_off;
+    const int64_t *tile_off;
+    const InstState *st;
+    int64_t n0;
+    int batch, tab_stride, halo, tile_out, pre, post, next;
+    int up;                  // 1: residual, inner up leg and update before the rest
 };
 
 struct CoarseArgs {
@@ -104,12 +131,14 @@ struct CoarseArgs {
 };
 
 // One multigrid visit of the levels `level` .. nlev[j]-1 of instance j per
-// work-group (see k_bottom), all levels resident in LDS.
-struct BottomArgs {
-    const double *f;         // right-hand side of level `level` (caller's f at level 0)
+// work-group (see k_bottom), all levels resident in LDS and computed in
+// FP64; TIO is the type of the level's arrays in global memory.
+template <typename TIO>
+struct BottomArgsT {
+    const TIO *f;            // right-hand side of level `level` (caller's f at level 0)
     const double *u0;        // fold values (level 0, forward) or null
-    const double *x_in;      // initial guess at `level` (null: zero)
-    double *x_out;           // result at `level` (may equal x_in)
+    const TIO *x_in;         // initial guess at `level` (null: zero)
+    TIO *x_out;              // result at `level` (may equal x_in)
     const int64_t *slab_off; // [batch+1] slab offsets of level `level`
     const double *tab;       // tables, block (l, j) at (l * batch + j) * tab_stride
     const double *R;
@@ -120,12 +149,16 @@ struct BottomArgs {
     const int64_t *norm_off;
     int level, batch, tab_stride, nu1, nu2, gamma;
 };
+using BottomArgs = BottomArgsT<double>;
 
 // Host-side launchers (tmg_kernels.hip).  `backward` selects the transposed
 // system's backward-in-time indexing.  Return hipSuccess or the launch error.
-hipError_t launch_leg(int P, bool backward, const LegArgs &a, int64_t ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles, hipStream_t s);
+hipError_t launch_mix(int P, bool backward, const MixArgs &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
-hipError_t launch_bottom(int P, bool backward, const BottomArgs &a, int ninst, hipStream_t s);
+template <typename TIO>
+hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s);
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          int batch, double *partial, int64_t ntiles, hipStream_t s);

@@ -38,7 +38,6 @@ namespace {
 
 constexpr int kWaves = kThreads / 64;
 
-typedef double d2 __attribute__((ext_vector_type(2)));
 
 // Instance owning a tile: largest j with off[j] <= tile (off[0] = 0).
 __device__ __forceinline__ int find_instance(const int64_t *__restrict__ off, int batch,
@@ -55,14 +54,14 @@ __device__ __forceinline__ int find_instance(const int64_t *__restrict__ off, in
 
 // End value of the left neighbour of this thread's first slab, for the
 // current sweep.  Double-buffered LDS slots (phase) need one barrier per call.
-template <int NW>
-__device__ __forceinline__ double left_value(double mine_last, double (*xchg)[NW], int &phase)
+template <int NW, typename T>
+__device__ __forceinline__ T left_value(T mine_last, double (*xchg)[NW], int &phase)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double v = __shfl_up(mine_last, 1, 64);
-    if (lane == 63) xchg[phase][wave] = mine_last;
+    T v = __shfl_up(mine_last, 1, 64);
+    if (lane == 63) xchg[phase][wave] = (double)mine_last;
     __syncthreads();
-    if (lane == 0) v = wave ? xchg[phase][wave - 1] : 0.0;
+    if (lane == 0) v = wave ? (T)xchg[phase][wave - 1] : (T)0;
     phase ^= 1;
     return v;
 }
@@ -82,24 +81,31 @@ __device__ __forceinline__ double block_sum(double x, double *red)
     return s;
 }
 
+// 16-byte vector of T
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); static constexpr int n = 4; };
+
 // Load logical slabs [m0, m0+S) of an instance level with N slabs (zeros
 // outside [0, N)).  Backward: logical m is physical N-1-m.
-template <int P, int S, bool BW>
-__device__ __forceinline__ void load_chunk(const double *__restrict__ base, int64_t m0, int64_t N,
-                                           double (&x)[S][P])
+template <int P, int S, bool BW, typename T>
+__device__ __forceinline__ void load_chunk(const T *__restrict__ base, int64_t m0, int64_t N,
+                                           T (&x)[S][P])
 {
+    constexpr int VN = Vec16<T>::n;
     if (m0 >= 0 && m0 + S <= N) {
         const int64_t plo = BW ? (N - m0 - S) : m0;
-        const double *src = base + plo * P;
-        double tmp[S * P];
-        if constexpr ((S * P) % 2 == 0) {
+        const T *src = base + plo * P;
+        T tmp[S * P];
+        if constexpr ((S * P) % VN == 0) {
             if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
-                const d2 *vs = reinterpret_cast<const d2 *>(src);
+                typedef typename Vec16<T>::type V;
+                const V *vs = reinterpret_cast<const V *>(src);
 #pragma unroll
-                for (int i = 0; i < S * P / 2; ++i) {
-                    d2 t = vs[i];
-                    tmp[2 * i] = t.x;
-                    tmp[2 * i + 1] = t.y;
+                for (int i = 0; i < S * P / VN; ++i) {
+                    V t = vs[i];
+#pragma unroll
+                    for (int q = 0; q < VN; ++q) tmp[VN * i + q] = t[q];
                 }
             } else {
 #pragma unroll
@@ -120,33 +126,35 @@ __device__ __forceinline__ void load_chunk(const double *__restrict__ base, int6
             const bool ok = m >= 0 && m < N;
             const int64_t pm = BW ? N - 1 - m : m;
 #pragma unroll
-            for (int k = 0; k < P; ++k) x[s][k] = ok ? base[pm * P + k] : 0.0;
+            for (int k = 0; k < P; ++k) x[s][k] = ok ? base[pm * P + k] : (T)0;
         }
     }
 }
 
 // Store logical slabs [m0, m0+S) whose tile-local index (li0 + s) is >= lo
 // and whose logical index is < N.
-template <int P, int S, bool BW>
-__device__ __forceinline__ void store_chunk(double *__restrict__ base, int64_t m0, int64_t N,
-                                            const double (&x)[S][P], int li0, int lo)
+template <int P, int S, bool BW, typename T>
+__device__ __forceinline__ void store_chunk(T *__restrict__ base, int64_t m0, int64_t N,
+                                            const T (&x)[S][P], int li0, int lo)
 {
+    constexpr int VN = Vec16<T>::n;
     if (li0 >= lo && m0 >= 0 && m0 + S <= N) {
         const int64_t plo = BW ? (N - m0 - S) : m0;
-        double *dst = base + plo * P;
-        double tmp[S * P];
+        T *dst = base + plo * P;
+        T tmp[S * P];
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int k = 0; k < P; ++k) tmp[(BW ? S - 1 - s : s) * P + k] = x[s][k];
-        if constexpr ((S * P) % 2 == 0) {
+        if constexpr ((S * P) % VN == 0) {
             if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-                d2 *vd = reinterpret_cast<d2 *>(dst);
+                typedef typename Vec16<T>::type V;
+                V *vd = reinterpret_cast<V *>(dst);
 #pragma unroll
-                for (int i = 0; i < S * P / 2; ++i) {
-                    d2 t;
-                    t.x = tmp[2 * i];
-                    t.y = tmp[2 * i + 1];
+                for (int i = 0; i < S * P / VN; ++i) {
+                    V t;
+#pragma unroll
+                    for (int q = 0; q < VN; ++q) t[q] = tmp[VN * i + q];
                     vd[i] = t;
                 }
                 return;
@@ -168,72 +176,77 @@ __device__ __forceinline__ void store_chunk(double *__restrict__ base, int64_t m
 }
 
 // Level operator tables held in registers (uniform across the work-group).
-template <int P>
+// Smoothing runs in T (tables rounded to T); the residual always runs in
+// FP64 arithmetic (A, v, c from the FP64 table).
+template <int P, typename T = double>
 struct Ops {
-    double A[P * P], G[P * P], h[P], c[P], v[P], omc;
-    __device__ __forceinline__ void load(const double *__restrict__ tab)
+    T G[P * P], h[P], c[P], omc;
+    double A[P * P], v[P], cd[P];
+    __device__ __forceinline__ void load(const double *__restrict__ tab, const T *__restrict__ tabT)
     {
         constexpr TabLayout L(P);
 #pragma unroll
         for (int i = 0; i < P * P; ++i) {
             A[i] = tab[L.A() + i];
-            G[i] = tab[L.G() + i];
+            G[i] = tabT[L.G() + i];
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            h[k] = tab[L.H() + k];
-            c[k] = tab[L.C() + k];
+            h[k] = tabT[L.H() + k];
+            c[k] = tabT[L.C() + k];
             v[k] = tab[L.V() + k];
+            cd[k] = tab[L.C() + k];
         }
-        omc = tab[L.OMC()];
+        omc = tabT[L.OMC()];
     }
+    __device__ __forceinline__ void load(const double *__restrict__ tab) { load(tab, tab); }
 };
 
 // Fold the initial value into logical slab 0 (forward system, level 0):
 // f_1 += u0 v.
-template <int P, int S>
-__device__ __forceinline__ void fold_u0(double (&f)[S][P], int64_t m0, double u0, const Ops<P> &op)
+template <int P, int S, typename T>
+__device__ __forceinline__ void fold_u0(T (&f)[S][P], int64_t m0, double u0, const Ops<P, T> &op)
 {
     // branch-free select keeps f in registers (no dynamic indexing)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double a = (m0 + s == 0) ? u0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) f[s][k] += a * op.v[k];
+        for (int k = 0; k < P; ++k) f[s][k] += (T)(a * op.v[k]);
     }
 }
 
-// nsweep damped block Jacobi sweeps in registers:
+// nsweep damped block Jacobi sweeps in registers (arithmetic in T):
 //   u_n <- (1 - omega) u_n + omega A^{-1} f_n + omega A^{-1} v w_{n-1},
 // the same update as u + omega D^{-1} (f - L u), with g = omega A^{-1} f
 // precomputed.
-template <int P, int S, int NW>
-__device__ __forceinline__ void sweeps(double (&u)[S][P], const double (&g)[S][P], const Ops<P> &op,
+template <int P, int S, int NW, typename T>
+__device__ __forceinline__ void sweeps(T (&u)[S][P], const T (&g)[S][P], const Ops<P, T> &op,
                                        int nsweep, double (*xchg)[NW], int &phase)
 {
     for (int sw = 0; sw < nsweep; ++sw) {
-        double w[S];
+        T w[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            double t = 0.0;
+            T t = 0;
 #pragma unroll
             for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
             w[s] = t;
         }
-        const double wl = left_value<NW>(w[S - 1], xchg, phase);
+        const T wl = left_value<NW, T>(w[S - 1], xchg, phase);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const double wn = s == 0 ? wl : w[s - 1];
+            const T wn = s == 0 ? wl : w[s - 1];
 #pragma unroll
             for (int k = 0; k < P; ++k) u[s][k] = op.omc * u[s][k] + g[s][k] + op.h[k] * wn;
         }
     }
 }
 
-// r_n = f_n + v w_{n-1} - A u_n.
-template <int P, int S, int NW>
-__device__ __forceinline__ void residual(double (&r)[S][P], const double (&u)[S][P],
-                                         const double (&f)[S][P], const Ops<P> &op,
+// r_n = f_n + v w_{n-1} - A u_n in FP64 arithmetic (operands of type TU, TF).
+template <int P, int S, int NW, typename TU, typename TF, typename T>
+__device__ __forceinline__ void residual(double (&r)[S][P], const TU (&u)[S][P],
+                                         const TF (&f)[S][P], const Ops<P, T> &op,
                                          double (*xchg)[NW], int &phase)
 {
     double w[S];
@@ -241,184 +254,324 @@ __device__ __forceinline__ void residual(double (&r)[S][P], const double (&u)[S]
     for (int s = 0; s < S; ++s) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
+        for (int k = 0; k < P; ++k) t += op.cd[k] * (double)u[s][k];
         w[s] = t;
     }
-    const double wl = left_value<NW>(w[S - 1], xchg, phase);
+    const double wl = left_value<NW, double>(w[S - 1], xchg, phase);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double wn = s == 0 ? wl : w[s - 1];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            double t = f[s][k] + op.v[k] * wn;
+            double t = (double)f[s][k] + op.v[k] * wn;
 #pragma unroll
-            for (int l = 0; l < P; ++l) t -= op.A[k * P + l] * u[s][l];
+            for (int l = 0; l < P; ++l) t -= op.A[k * P + l] * (double)u[s][l];
             r[s][k] = t;
         }
     }
 }
 
-template <int P, int S>
-__device__ __forceinline__ void apply_G(double (&g)[S][P], const double (&f)[S][P], const Ops<P> &op)
+template <int P, int S, typename T>
+__device__ __forceinline__ void apply_G(T (&g)[S][P], const T (&f)[S][P], const Ops<P, T> &op)
 {
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            double t = 0.0;
+            T t = 0;
 #pragma unroll
             for (int l = 0; l < P; ++l) t += op.G[k * P + l] * f[s][l];
             g[s][k] = t;
         }
 }
 
-// The streaming leg (see LegArgs).  Every step runs on the tile in
-// registers; the tile's first `halo` slabs are recomputed copies of the left
-// neighbour's last output slabs and are never stored.  With one slab per
-// thread (S = 1) the two fine slabs of a coarse slab sit in neighbouring
-// lanes (the tile starts at an even slab) and meet through a lane shuffle.
-template <int P, bool BW>
-__global__ __launch_bounds__(kThreads) void k_leg(LegArgs a)
+// u_{2i} += R_1^T e_i, u_{2i+1} += R_2^T e_i (in T); with S = 1 each lane
+// adds the half that belongs to its own slab.
+template <int P, int S, typename T>
+__device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? S / 2 : 1][P],
+                                            const T *__restrict__ R, int64_t m0)
 {
-    constexpr int S = slabs_per_thread(P);
-    constexpr int TS = tile_slabs(P);
-    constexpr int SC = S >= 2 ? S / 2 : 1;  // coarse slabs touched per thread
-    __shared__ double xchg[2][kWaves];
-    __shared__ double red[kWaves];
-    const int64_t tile = blockIdx.x;
-    int j = 0;
-    int64_t t = tile, off = 0, N = a.n0, coff = 0, Nc = a.n0 / 2;
-    if (a.batch > 1) {
-        j = find_instance(a.tile_off, a.batch, tile);
-        t = tile - a.tile_off[j];
-        off = a.slab_off[j];
-        N = a.slab_off[j + 1] - off;
-        if (a.cslab_off) {
-            coff = a.cslab_off[j];
-            Nc = a.cslab_off[j + 1] - coff;
+    const T *R1T = R, *R2T = R + P * P;
+    if constexpr (S >= 2) {
+#pragma unroll
+        for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                T s1 = 0, s2 = 0;
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    s1 += R1T[k * P + l] * e[i][l];
+                    s2 += R2T[k * P + l] * e[i][l];
+                }
+                u[2 * i][k] += s1;
+                u[2 * i + 1][k] += s2;
+            }
+    } else {
+        const bool second = (m0 & 1) != 0;  // second fine slab of its coarse slab
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T s1 = 0, s2 = 0;
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                s1 += R1T[k * P + l] * e[0][l];
+                s2 += R2T[k * P + l] * e[0][l];
+            }
+            u[0][k] += second ? s2 : s1;
         }
     }
-    // every load is issued before the early-exit test: data first, then
-    // the state flag and the level tables
-    const int li0 = threadIdx.x * S;
-    const int64_t m0 = t * a.tile_out - a.halo + li0;
-    double f[S][P], u[S][P], g[S][P], e[SC][P];
-    load_chunk<P, S, BW>(a.f + off * P, m0, N, f);
-    if (a.u_in) {
-        if (a.halo_in && li0 < a.halo) {
-            // left halo: the previous tile's last output slabs of the last pass
-            const double *hb = a.halo_in + (tile - 1) * (int64_t)a.halo * P + (int64_t)li0 * P;
+}
+
+// Restrict the residual r (rounded to T) of this thread's slabs and store
+// the coarse slabs of output pairs: rc_m = R_1 r_{2m} + R_2 r_{2m+1}.
+template <int P, int S, bool BW, typename T>
+__device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T *__restrict__ R,
+                                               T *__restrict__ rc_base, int64_t m0, int64_t N,
+                                               int64_t Nc, int li0, int halo)
+{
+    const T *R1T = R, *R2T = R + P * P;
+    if constexpr (S >= 2) {
+        T rc[S / 2][P];
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+        for (int i = 0; i < S / 2; ++i)
 #pragma unroll
-                for (int k = 0; k < P; ++k) u[s][k] = t > 0 ? hb[s * P + k] : 0.0;
+            for (int k = 0; k < P; ++k) {
+                T s1 = 0;
+#pragma unroll
+                for (int l = 0; l < P; ++l)
+                    s1 += R1T[l * P + k] * (T)r[2 * i][l] + R2T[l * P + k] * (T)r[2 * i + 1][l];
+                rc[i][k] = s1;
+            }
+        store_chunk<P, S / 2, BW, T>(rc_base, m0 / 2, Nc, rc, li0 / 2, halo / 2);
+    } else {
+        // the first slab of each pair takes its partner's residual from the next lane
+        double rn[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[0][k], 1, 64);
+        if (!(m0 & 1) && li0 >= halo && m0 >= 0 && m0 < N) {
+            T rc[1][P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                T s1 = 0;
+#pragma unroll
+                for (int l = 0; l < P; ++l)
+                    s1 += R1T[l * P + k] * (T)r[0][l] + R2T[l * P + k] * (T)rn[l];
+                rc[0][k] = s1;
+            }
+            store_chunk<P, 1, BW, T>(rc_base, m0 / 2, Nc, rc, 0, 0);
+        }
+    }
+}
+
+// Instance, tile and sizes of the work-group's tile.
+struct TileRef {
+    int j;
+    int64_t t, off, N, coff, Nc;
+};
+
+template <typename A>
+__device__ __forceinline__ TileRef tile_ref(const A &a)
+{
+    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2};
+    if (a.batch > 1) {
+        r.j = find_instance(a.tile_off, a.batch, r.t);
+        r.t = (int64_t)blockIdx.x - a.tile_off[r.j];
+        r.off = a.slab_off[r.j];
+        r.N = a.slab_off[r.j + 1] - r.off;
+        if (a.cslab_off) {
+            r.coff = a.cslab_off[r.j];
+            r.Nc = a.cslab_off[r.j + 1] - r.coff;
+        }
+    }
+    return r;
+}
+
+// Iterate of the tile: zero, the left halo from the previous pass's halo
+// buffer, or the array itself.
+template <int P, int S, bool BW, typename T>
+__device__ __forceinline__ void load_iterate(T (&u)[S][P], const T *u_in, const T *halo_in,
+                                             const TileRef &tr, int64_t m0, int li0, int halo)
+{
+    if (u_in) {
+        if (halo_in && li0 < halo) {
+            // left halo: the previous tile's last output slabs of the last
+            // pass (the first tile of an instance starts at slab 0: zeros)
+            if (tr.t > 0) {
+                const T *hb =
+                    halo_in + ((int64_t)blockIdx.x - 1) * (int64_t)halo * P + (int64_t)li0 * P;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int k = 0; k < P; ++k) u[s][k] = hb[s * P + k];
+            } else {
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int k = 0; k < P; ++k) u[s][k] = (T)0;
+            }
         } else {
-            load_chunk<P, S, BW>(a.u_in + off * P, m0, N, u);
+            load_chunk<P, S, BW, T>(u_in + tr.off * P, m0, tr.N, u);
         }
     } else {
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int k = 0; k < P; ++k) u[s][k] = 0.0;
+            for (int k = 0; k < P; ++k) u[s][k] = (T)0;
     }
-    if (a.e) {
-        // coarse slab of this thread's slabs (floor division; -1 is outside)
-        const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
-        load_chunk<P, SC, BW>(a.e + coff * P, cm0, Nc, e);
-    }
-    const int done = a.st ? a.st[j].done : 0;
-    Ops<P> op;
-    op.load(a.tab + (int64_t)j * a.tab_stride);
-    if (done) return;
-    if (a.u0) fold_u0<P, S>(f, m0, a.u0[j], op);
-    apply_G<P, S>(g, f, op);
-    int phase = 0;
-    sweeps<P, S, kWaves>(u, g, op, a.pre, xchg, phase);
-    if (a.e) {
-        const double *R1T = a.R, *R2T = a.R + P * P;
-        if constexpr (S >= 2) {
-#pragma unroll
-            for (int i = 0; i < S / 2; ++i)
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int l = 0; l < P; ++l) {
-                        s1 += R1T[k * P + l] * e[i][l];
-                        s2 += R2T[k * P + l] * e[i][l];
-                    }
-                    u[2 * i][k] += s1;
-                    u[2 * i + 1][k] += s2;
-                }
-        } else {
-            const bool second = (m0 & 1) != 0;  // second fine slab of its coarse slab
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                for (int l = 0; l < P; ++l) {
-                    s1 += R1T[k * P + l] * e[0][l];
-                    s2 += R2T[k * P + l] * e[0][l];
-                }
-                u[0][k] += second ? s2 : s1;
-            }
-        }
-    }
-    sweeps<P, S, kWaves>(u, g, op, a.post, xchg, phase);
-    if (a.u_out) store_chunk<P, S, BW>(a.u_out + off * P, m0, N, u, li0, a.halo);
-    if (a.halo_out && li0 >= TS - a.halo) {
-        double *hb = a.halo_out + tile * (int64_t)a.halo * P + (int64_t)(li0 - (TS - a.halo)) * P;
+}
+
+template <int P, int S, typename T>
+__device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int li0, int halo)
+{
+    constexpr int TS = kThreads * S;
+    if (halo_out && li0 >= TS - halo) {
+        T *hb = halo_out + (int64_t)blockIdx.x * (int64_t)halo * P + (int64_t)(li0 - (TS - halo)) * P;
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int k = 0; k < P; ++k) hb[s * P + k] = u[s][k];
     }
+}
+
+template <int P, int S, int NW>
+__device__ __forceinline__ void norm_partial(const double (&r)[S][P], double *partial,
+                                             const int64_t *norm_off, const TileRef &tr, int64_t m0,
+                                             int li0, int halo, double *red)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (li0 + s >= halo && m0 + s < tr.N)
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
+    acc = block_sum<NW>(acc, red);
+    if (threadIdx.x == 0) partial[norm_off[tr.j] + tr.t] = acc;
+}
+
+// The streaming leg (see LegArgsT), storage and smoothing in T, residual in
+// FP64 arithmetic.  Every step runs on the tile in registers; the tile's
+// first `halo` slabs are recomputed copies of the left neighbour's last
+// output slabs and are never stored.  With one slab per thread (S = 1) the
+// two fine slabs of a coarse slab sit in neighbouring lanes (tiles start at
+// an even slab) and meet through a lane shuffle.
+template <int P, bool BW, typename T>
+__global__ __launch_bounds__(kThreads) void k_leg(LegArgsT<T> a)
+{
+    constexpr int S = slabs_per_thread(P);
+    constexpr int SC = S >= 2 ? S / 2 : 1;  // coarse slabs touched per thread
+    __shared__ double xchg[2][kWaves];
+    __shared__ double red[kWaves];
+    const TileRef tr = tile_ref(a);
+    const int li0 = threadIdx.x * S;
+    const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
+    // every load is issued before the early-exit test: data first, then the
+    // state flag and the level tables
+    T f[S][P], u[S][P], g[S][P], e[SC][P];
+    load_chunk<P, S, BW, T>(a.f + tr.off * P, m0, tr.N, f);
+    load_iterate<P, S, BW, T>(u, a.u_in, a.halo_in, tr, m0, li0, a.halo);
+    if (a.e) {
+        // coarse slab of this thread's slabs (floor division; -1 is outside)
+        const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+        load_chunk<P, SC, BW, T>(a.e + tr.coff * P, cm0, tr.Nc, e);
+    }
+    const int done = a.st ? a.st[tr.j].done : 0;
+    Ops<P, T> op;
+    op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tabT + (int64_t)tr.j * a.tab_stride);
+    if (done) return;
+    if (a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
+    apply_G<P, S, T>(g, f, op);
+    int phase = 0;
+    sweeps<P, S, kWaves, T>(u, g, op, a.pre, xchg, phase);
+    if (a.e) prolong_add<P, S, T>(u, e, a.R, m0);
+    sweeps<P, S, kWaves, T>(u, g, op, a.post, xchg, phase);
+    if (a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
+    store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
     double r[S][P];
     if (a.partial) {
         residual<P, S, kWaves>(r, u, f, op, xchg, phase);
-        double acc = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-            if (li0 + s >= a.halo && m0 + s < N)
-#pragma unroll
-                for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
-        acc = block_sum<kWaves>(acc, red);
-        if (threadIdx.x == 0) a.partial[a.norm_off[j] + t] = acc;
+        norm_partial<P, S, kWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
     }
     if (a.rc) {
-        sweeps<P, S, kWaves>(u, g, op, a.next, xchg, phase);
+        sweeps<P, S, kWaves, T>(u, g, op, a.next, xchg, phase);
         residual<P, S, kWaves>(r, u, f, op, xchg, phase);
-        const double *R1T = a.R, *R2T = a.R + P * P;
-        if constexpr (S >= 2) {
-            double rc[S / 2][P];
+        restrict_store<P, S, BW, T>(r, a.R, a.rc + tr.coff * P, m0, tr.N, tr.Nc, li0, a.halo);
+    }
+}
+
+// Fused level-0 pass of the FP32-inner defect correction (see MixArgs).
+// With u_k the FP64 iterate (in place):
+//   up:   r_k = f - L u_k (FP64) -> FP32; the inner level-0 up leg on
+//         L e = r_k: pre sweeps from e = 0 recomputed, prolongation of the
+//         level-1 correction, post sweeps (FP32); u_{k+1} = u_k + e (FP64);
+//   norm: ||f - L u_{k+1}||^2 (FP64);
+//   next: the next inner down leg: r_{k+1} -> FP32, next sweeps from zero
+//         (FP32), inner residual in FP64 arithmetic, restriction (FP32).
+template <int P, bool BW>
+__global__ __launch_bounds__(kThreads) void k_mix(MixArgs a)
+{
+    constexpr int S = slabs_per_thread(P);
+    constexpr int SC = S >= 2 ? S / 2 : 1;
+    __shared__ double xchg[2][kWaves];
+    __shared__ double red[kWaves];
+    const TileRef tr = tile_ref(a);
+    const int li0 = threadIdx.x * S;
+    const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
+    double f[S][P], u[S][P], r[S][P];
+    float e[SC][P];
+    load_chunk<P, S, BW, double>(a.f + tr.off * P, m0, tr.N, f);
+    load_iterate<P, S, BW, double>(u, a.u_in, a.halo_in, tr, m0, li0, a.halo);
+    if (a.up) {
+        const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+        load_chunk<P, SC, BW, float>(a.e + tr.coff * P, cm0, tr.Nc, e);
+    }
+    const int done = a.st ? a.st[tr.j].done : 0;
+    Ops<P, float> op;
+    op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tab32 + (int64_t)tr.j * a.tab_stride);
+    if (done) return;
+    if (a.u0) {
+        // fold in FP64
 #pragma unroll
-            for (int i = 0; i < S / 2; ++i)
+        for (int s = 0; s < S; ++s) {
+            const double w = (m0 + s == 0) ? a.u0[tr.j] : 0.0;
 #pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double s1 = 0.0;
-#pragma unroll
-                    for (int l = 0; l < P; ++l)
-                        s1 += R1T[l * P + k] * r[2 * i][l] + R2T[l * P + k] * r[2 * i + 1][l];
-                    rc[i][k] = s1;
-                }
-            store_chunk<P, S / 2, BW>(a.rc + coff * P, m0 / 2, Nc, rc, li0 / 2, a.halo / 2);
-        } else {
-            // the first slab of each pair takes its partner's residual from the next lane
-            double rn[P];
-#pragma unroll
-            for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[0][k], 1, 64);
-            if (!(m0 & 1) && li0 >= a.halo && m0 >= 0 && m0 < N) {
-                double rc[1][P];
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double s1 = 0.0;
-#pragma unroll
-                    for (int l = 0; l < P; ++l) s1 += R1T[l * P + k] * r[0][l] + R2T[l * P + k] * rn[l];
-                    rc[0][k] = s1;
-                }
-                store_chunk<P, 1, BW>(a.rc + coff * P, m0 / 2, Nc, rc, 0, 0);
-            }
+            for (int k = 0; k < P; ++k) f[s][k] += w * op.v[k];
         }
+    }
+    int phase = 0;
+    float rf[S][P], g[S][P], ei[S][P];
+    if (a.up) {
+        residual<P, S, kWaves>(r, u, f, op, xchg, phase);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                rf[s][k] = (float)r[s][k];
+                ei[s][k] = 0.0f;
+            }
+        apply_G<P, S, float>(g, rf, op);
+        sweeps<P, S, kWaves, float>(ei, g, op, a.pre, xchg, phase);
+        prolong_add<P, S, float>(ei, e, a.R32, m0);
+        sweeps<P, S, kWaves, float>(ei, g, op, a.post, xchg, phase);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) u[s][k] += (double)ei[s][k];
+        if (a.u_out) store_chunk<P, S, BW, double>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
+        store_halo<P, S, double>(a.halo_out, u, li0, a.halo);
+    }
+    residual<P, S, kWaves>(r, u, f, op, xchg, phase);
+    if (a.partial) norm_partial<P, S, kWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
+    if (a.rc) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                rf[s][k] = (float)r[s][k];
+                ei[s][k] = 0.0f;
+            }
+        apply_G<P, S, float>(g, rf, op);
+        sweeps<P, S, kWaves, float>(ei, g, op, a.next, xchg, phase);
+        residual<P, S, kWaves>(r, ei, rf, op, xchg, phase);
+        restrict_store<P, S, BW, float>(r, a.R32, a.rc + tr.coff * P, m0, tr.N, tr.Nc, li0, a.halo);
     }
 }
 
@@ -435,9 +588,9 @@ struct ScanSmem {
     double wend[NT];
 };
 
-template <int P, bool BW, int NT>
-__device__ __forceinline__ void coarse_scan(const double *__restrict__ r_base, double u0,
-                                            double *__restrict__ e_base, int64_t N,
+template <int P, bool BW, int NT, typename TR, typename TE>
+__device__ __forceinline__ void coarse_scan(const TR *__restrict__ r_base, double u0,
+                                            TE *__restrict__ e_base, int64_t N,
                                             const double *__restrict__ tab, ScanSmem<NT> &sm)
 {
     constexpr TabLayout L(P);
@@ -459,7 +612,7 @@ __device__ __forceinline__ void coarse_scan(const double *__restrict__ r_base, d
         const int64_t pm = BW ? N - 1 - m : m;
         double r[P], d[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) r[k] = ok ? r_base[pm * P + k] : 0.0;
+        for (int k = 0; k < P; ++k) r[k] = ok ? (double)r_base[pm * P + k] : 0.0;
         const double a0 = (m == 0) ? u0 : 0.0;
 #pragma unroll
         for (int k = 0; k < P; ++k) r[k] += a0 * v[k];
@@ -495,7 +648,7 @@ __device__ __forceinline__ void coarse_scan(const double *__restrict__ r_base, d
         const double wprev = threadIdx.x == 0 ? carry : sm.wend[threadIdx.x - 1];
         if (ok)
 #pragma unroll
-            for (int k = 0; k < P; ++k) e_base[pm * P + k] = d[k] + q[k] * wprev;
+            for (int k = 0; k < P; ++k) e_base[pm * P + k] = (TE)(d[k] + q[k] * wprev);
         const int64_t nlast = (N - base < NT) ? (N - base) : NT;
         carry = sm.wend[nlast - 1];
         __syncthreads();
@@ -510,8 +663,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
     if (a.st && a.st[j].done) return;
     const int64_t off = a.slab_off[j];
     const int64_t N = a.slab_off[j + 1] - off;
-    coarse_scan<P, BW, kThreads>(a.r + off * P, a.u0 ? a.u0[j] : 0.0, a.e + off * P, N,
-                                 a.tab + (int64_t)j * a.tab_stride, sm);
+    coarse_scan<P, BW, kThreads, double, double>(a.r + off * P, a.u0 ? a.u0[j] : 0.0, a.e + off * P,
+                                                 N, a.tab + (int64_t)j * a.tab_stride, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,15 +790,16 @@ struct Bottom {
 
     __device__ void coarse(int l) const
     {
-        coarse_scan<P, BW, NT>(sm.f + loff(l), 0.0, sm.x + loff(l), nslab(l), tab(l), sm.scan);
+        coarse_scan<P, BW, NT, double, double>(sm.f + loff(l), 0.0, sm.x + loff(l), nslab(l), tab(l),
+                                               sm.scan);
         __syncthreads();
     }
 
     const double *R;
 };
 
-template <int P, bool BW>
-__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
+template <int P, bool BW, typename TIO>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
 {
     using B = Bottom<P, BW>;
     constexpr int NT = B::NT, S = B::S, STRIDE = B::STRIDE;
@@ -660,11 +814,11 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
         // exact solve, directly in global memory
         const double *tab = a.tab + ((int64_t)lb * a.batch + j) * a.tab_stride;
         const double u0 = (lb == 0 && a.u0) ? a.u0[j] : 0.0;
-        coarse_scan<P, BW, NT>(a.f + off * P, u0, a.x_out + off * P, N, tab, sm.scan);
+        coarse_scan<P, BW, NT, TIO, TIO>(a.f + off * P, u0, a.x_out + off * P, N, tab, sm.scan);
         if (lb == 0 && a.partial) {
             // squared residual of the result, one slab per thread and pass
             constexpr TabLayout L(P);
-            const double *x = a.x_out + off * P, *f = a.f + off * P;
+            const TIO *x = a.x_out + off * P, *f = a.f + off * P;
             double acc = 0.0;
             for (int64_t m = threadIdx.x; m < N; m += NT) {
                 const int64_t pm = BW ? N - 1 - m : m;
@@ -697,8 +851,8 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
         for (int i = threadIdx.x; i < STRIDE; i += NT)
             sm.tab[(l - lb) * STRIDE + i] = a.tab[((int64_t)l * a.batch + j) * a.tab_stride + i];
     for (int64_t i = threadIdx.x; i < N * P; i += NT) {
-        sm.f[i] = a.f[off * P + i];
-        sm.x[i] = a.x_in ? a.x_in[off * P + i] : 0.0;
+        sm.f[i] = (double)a.f[off * P + i];
+        sm.x[i] = a.x_in ? (double)a.x_in[off * P + i] : 0.0;
     }
     __syncthreads();
     if (a.u0 && threadIdx.x < P) {
@@ -741,7 +895,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs a)
         }
     }
     // result of level lb back to global memory
-    for (int64_t i = threadIdx.x; i < N * P; i += NT) a.x_out[off * P + i] = sm.x[i];
+    for (int64_t i = threadIdx.x; i < N * P; i += NT) a.x_out[off * P + i] = (TIO)sm.x[i];
     if (lb == 0 && a.partial) {
         // squared residual of the result (level 0 of this instance)
         Ops<P> op;
@@ -883,12 +1037,25 @@ __global__ __launch_bounds__(kThreads) void k_grad(const double *__restrict__ u,
     default: return hipErrorInvalidValue;             \
     }
 
-hipError_t launch_leg(int P, bool backward, const LegArgs &a, int64_t ntiles, hipStream_t s)
+template <typename T>
+hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_leg<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_leg<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        if (backward) hipLaunchKernelGGL((k_leg<PP, true, T>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_leg<PP, false, T>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+    })
+    return hipGetLastError();
+}
+template hipError_t launch_leg<double>(int, bool, const LegArgsT<double> &, int64_t, hipStream_t);
+template hipError_t launch_leg<float>(int, bool, const LegArgsT<float> &, int64_t, hipStream_t);
+
+hipError_t launch_mix(int P, bool backward, const MixArgs &a, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    TMG_DISPATCH_P(P, {
+        if (backward) hipLaunchKernelGGL((k_mix<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_mix<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
     })
     return hipGetLastError();
 }
@@ -903,15 +1070,18 @@ hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, h
     return hipGetLastError();
 }
 
-hipError_t launch_bottom(int P, bool backward, const BottomArgs &a, int ninst, hipStream_t s)
+template <typename TIO>
+hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s)
 {
     if (ninst <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_bottom<PP, true>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_bottom<PP, false>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
+        if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_bottom<PP, false, TIO>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
     })
     return hipGetLastError();
 }
+template hipError_t launch_bottom<double>(int, bool, const BottomArgsT<double> &, int, hipStream_t);
+template hipError_t launch_bottom<float>(int, bool, const BottomArgsT<float> &, int, hipStream_t);
 
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
