@@ -1,21 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark: DG time-unknowns solved per second to relative residual 1e-10.
 
-Workload (one MI355X): u' + u = f on (0, 1000], u0 = 1, N = 2^22 uniform
-slabs, DG degree p (default 3; --p), Legendre basis, f a seeded 16-mode random
-Fourier series; V-cycle (or --cycle W) with 2/2 damped block Jacobi sweeps,
+Default workload (one MI355X; `--config 2`): u' + u = f on (0, 1000],
+u0 = 1, N = 2^22 uniform slabs, DG degree p (default 3; --p), Legendre basis,
+f a seeded 16-mode random Fourier series; V(2,2) cycle (or --cycle W),
 coarsening by 2 down to 2 slabs, solved from u = 0 to ||r|| <= 1e-10 ||r_0||.
 A step is one whole solve (tmg_solve) with f, u0 and u resident in HBM.
 
-Prints one JSON line with the headline number, a sweep over p = 0..3, the
-roofline of the dominant kernel (level-0 down leg: nu1 sweeps + residual +
-restriction) timed with HIP events on its launch stream, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+One JSON line: the headline number, a sweep over p = 0..3, the roofline of
+the dominant kernel (the fused level-0 pass of a cycle) timed with HIP events
+on its launch stream, the FP64 CPU oracle timed on a bounded sample of the
+same workload, and the FP32-inner defect correction against the plain FP64
+cycle on the large scalar workload (N = 2^24, p = 3).
+
+Other configurations (`--config`):
+  3  4096 eigenmode instances of uneven length (batched, one handle);
+  4  256 instances, N = 2^20, p = 2: forward solve + adjoint solve +
+     gradients (the backward pass of the autograd function);
+  5  N = 2^24, p = 3, FP64 cycle against FP32-inner defect correction, scalar
+     and a batch of 64.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -31,72 +40,93 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
     ap.add_argument("--sweep", type=int, default=1, help="also time p = 0..3 (1) or not (0)")
+    ap.add_argument("--mixed", type=int, default=1, help="include the N=2^24 mixed-precision comparison")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-log2n", type=int, default=15)
+    ap.add_argument("--batch", type=int, default=0, help="instances for --config 3/4/5 (0: default)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
-def gpu_solve_rate(p, log2n, cycle, steps, warmup):
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def time_solves(fn, steps, warmup):
+    res = None
+    for _ in range(warmup):
+        res = fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = fn()
+    sync()
+    return (time.perf_counter() - t0) / steps, res
+
+
+# ---------------------------------------------------------------------------
+# config 2: scalar, lambda = 1
+# ---------------------------------------------------------------------------
+
+def config2_case(p, log2n, cycle, steps, warmup, precision=0):
     import torch
     from paper_1409_5254_amd.binding import Solver
     from workloads import gen
     N = 1 << log2n
-    T = 1000.0 * N / (1 << 22)          # keep tau = 1000 / 2^22 for any N
-    w = gen.config2(p, N=N, T=T)
-    inst = w.instances[0]
-    f = torch.as_tensor(inst.f, dtype=torch.float64, device="cuda")
-    u0 = torch.tensor([inst.u0], dtype=torch.float64, device="cuda")
+    T = 1000.0 * N / (1 << 22)          # tau = 1000 / 2^22 for any N
+    import numpy as np
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal(16)
+    phi = rng.uniform(0.0, 2.0 * math.pi, 16)
+    f = gen.fourier_load_torch(p, N, T, a, phi, device="cuda")
+    u0 = torch.tensor([1.0], dtype=torch.float64, device="cuda")
     u = torch.empty_like(f)
-    s = Solver([N], [T], [inst.lam], p=p, gamma=1 if cycle == "V" else 2)
-    res = None
-    for _ in range(warmup):
-        res = s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        res = s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    s = Solver([N], [T], [1.0], p=p, gamma=1 if cycle == "V" else 2, precision=precision)
+    dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
     unknowns = N * (p + 1)
     return dict(p=p, N=N, unknowns=unknowns, ms_per_solve=dt * 1e3,
                 unknowns_per_s=unknowns / dt, cycles=res.cycles[0], relres=res.relres[0],
                 status=res.status), (s, f, u0, u)
 
 
-def kernel_roofline(p, ctx, reps):
-    """Average duration of the level-0 down kernel (nu1 = 2 sweeps, residual,
-    restriction) timed with HIP events on the stream it is launched on.
-    Algorithmic bytes per fine unknown: read u, f (16 B), write u (8 B),
-    write the restricted residual (4 B) = 28 B."""
+def fused_pass_roofline(p, ctx, reps):
+    """Average duration of the dominant kernel, the fused level-0 pass of a
+    cycle (tmg_op_fused: recomputed pre-sweeps, correction, post-sweeps, next
+    cycle's pre-sweeps, residual, restriction), timed with HIP events on the
+    stream it is launched on.  Algorithmic bytes per fine unknown: read u, f
+    (16 B) and the level-1 correction (4 B), write u (8 B) and the restricted
+    residual (4 B) = 32 B; one launch processes N*P unknowns."""
     import torch
     s, f, u0, u = ctx
     N = s.n_slabs[0]
     P = p + 1
     ub = torch.empty_like(u)
     rc = torch.empty(N // 2 * P, dtype=torch.float64, device="cuda")
-    for _ in range(3):
-        s.down(0, f, u, ub, rc, nsweep=2, fold_u0=u0)
+    e = torch.zeros(N // 2 * P, dtype=torch.float64, device="cuda")
     st = torch.cuda.current_stream()
+    for _ in range(3):
+        s.fused(f, u, e, ub, rc, fold_u0=u0)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
-        s.down(0, f, u, ub, rc, nsweep=2, fold_u0=u0)
+        s.fused(f, u, e, ub, rc, fold_u0=u0)
     e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    bytes_alg = 28.0 * N * P
+    bytes_alg = 32.0 * N * P
     gbs = bytes_alg / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"k_down<P={P}> level 0, N=2^{N.bit_length() - 1}",
+                kernel=f"k_leg<P={P}> fused level-0 pass, N=2^{N.bit_length() - 1}",
                 avg_us=round(ms * 1e3, 2), bytes_per_launch=bytes_alg)
 
 
@@ -112,8 +142,121 @@ def cpu_baseline(p, log2n):
     _, k, rr, _ = core.solve(p, T, inst.lam, inst.u0, inst.f, rtol=1e-10)
     dt = time.perf_counter() - t0
     return dict(value=N * (p + 1) / dt, unit="unknowns/s", cores=1, kind="oracle",
-                sample=f"oracle V-cycle solve to 1e-10 of N=2^{log2n} slabs, p={p}, "
-                       f"tau=1000/2^22 ({k} cycles, {dt:.1f} s)")
+                sample=f"oracle V-cycle solve to 1e-10 of the first 2^{log2n} slabs "
+                       f"(tau = 1000/2^22, p={p}; {k} cycles, {dt:.1f} s)")
+
+
+# ---------------------------------------------------------------------------
+# config 5: FP64 cycle against FP32-inner defect correction
+# ---------------------------------------------------------------------------
+
+def config5_compare(B, log2n, steps, warmup):
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    p = 3
+    N = 1 << log2n
+    T = 1e4 * N / (1 << 24)
+    params = gen.config5_params(B)
+    P = p + 1
+    f = torch.empty(B * N * P, dtype=torch.float64, device="cuda")
+    for j, (lam, a, phi) in enumerate(params):
+        gen.fourier_load_torch(p, N, T, a, phi, out=f[j * N * P:(j + 1) * N * P])
+    u0 = torch.ones(B, dtype=torch.float64, device="cuda")
+    lams = [q[0] for q in params]
+    out = {}
+    sols = {}
+    for name, prec in (("fp64", 0), ("fp32_inner", 1)):
+        s = Solver([N] * B, [T] * B, lams, p=p, precision=prec)
+        u = torch.empty_like(f)
+        dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps,
+                              warmup)
+        out[name] = dict(unknowns_per_s=B * N * P / dt, ms_per_solve=dt * 1e3,
+                         cycles=max(res.cycles), relres=max(res.relres), status=res.status)
+        sols[name] = u
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    d = (sols["fp32_inner"] - sols["fp64"]).abs().max().item() / sols["fp64"].abs().max().item()
+    out["rel_diff_fp32_inner_vs_fp64"] = d
+    out["speedup_fp32_inner"] = out["fp32_inner"]["unknowns_per_s"] / out["fp64"]["unknowns_per_s"]
+    out["workload"] = (f"{B} x (u'+lam u=f, T={T:g}, N=2^{log2n}, p=3, lam ~ U(0.5,50)), "
+                       "V(2,2) to 1e-10")
+    out["fp64_steps"] = ("FP64 in fp32_inner mode: level-0 residual and update, every intra-cycle "
+                         "residual (arithmetic), levels inside the bottom work-group incl. the "
+                         "coarsest scan")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# config 3: batched eigenmodes
+# ---------------------------------------------------------------------------
+
+def config3_run(n_inst, steps, warmup, precision=0):
+    import numpy as np
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    lam, Ns = gen.config3_sizes(n_inst)
+    Ns = [int(n) for n in Ns]
+    P = 2
+    total = sum(Ns) * P
+    g = torch.Generator(device="cuda").manual_seed(3)
+    c = torch.randn(total, dtype=torch.float64, device="cuda", generator=g)
+    # load vector M_tau c per instance: tau_j / (2k+1)
+    scale = torch.empty(total, dtype=torch.float64, device="cuda")
+    off = 0
+    tau = torch.tensor([1.0 / n for n in Ns], dtype=torch.float64, device="cuda")
+    counts = torch.tensor([n * P for n in Ns], device="cuda")
+    scale = torch.repeat_interleave(tau, counts)
+    kk = torch.arange(total, device="cuda") % P
+    f = c * scale / (2.0 * kk.to(torch.float64) + 1.0)
+    del c, scale, kk
+    u0 = torch.ones(n_inst, dtype=torch.float64, device="cuda")
+    s = Solver(Ns, [1.0] * n_inst, list(lam), p=1, precision=precision)
+    u = torch.empty_like(f)
+    dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
+    cyc = np.array(res.cycles)
+    return dict(unknowns_per_s=total / dt, ms_per_solve=dt * 1e3, instances=n_inst,
+                unknowns=total, cycles_min=int(cyc.min()), cycles_max=int(cyc.max()),
+                cycles_mean=float(cyc.mean()), max_relres=max(res.relres), status=res.status,
+                workload=f"{n_inst} instances, lambda_j = pi^2 j^2 kappa, N_j = 2^U{{12..18}}, "
+                         "T=1, p=1, Gaussian Legendre coefficients (torch generator, seed 3)")
+
+
+# ---------------------------------------------------------------------------
+# config 4: adjoint / gradients
+# ---------------------------------------------------------------------------
+
+def config4_run(B, steps, warmup):
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    p, N, T = 2, 1 << 20, 100.0
+    P = p + 1
+    params, rng = gen.config4_params(B)
+    f = torch.empty(B * N * P, dtype=torch.float64, device="cuda")
+    for j, (lam, a, phi) in enumerate(params):
+        gen.fourier_load_torch(p, N, T, a, phi, out=f[j * N * P:(j + 1) * N * P])
+    g = torch.Generator(device="cuda").manual_seed(4)
+    y = torch.randn(B * N, dtype=torch.float64, device="cuda", generator=g)
+    u0 = torch.ones(B, dtype=torch.float64, device="cuda")
+    s = Solver([N] * B, [T] * B, [q[0] for q in params], p=p)
+    u = torch.empty_like(f)
+    z = torch.empty_like(f)
+
+    def step():
+        fw = s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200)
+        # dJ/du of J = 1/2 sum (w_n - y_n)^2, w_n = sum_k u_n[k]
+        w = u.view(-1, P).sum(dim=1)
+        gr = (w - y).repeat_interleave(P)
+        return fw, s.adjoint_solve(gr, u=u, z=z, rtol=1e-10, max_cycles=200)
+
+    dt, (fw, adj) = time_solves(step, steps, warmup)
+    return dict(unknowns_per_s=B * N * P / dt, ms_per_forward_backward=dt * 1e3,
+                forward_cycles=max(fw.cycles), adjoint_cycles=max(adj[3]),
+                max_relres_adjoint=max(adj[4]), status=adj[5],
+                workload=f"{B} x (N=2^20, p=2, T=100, lambda ~ U(0.1,10)), loss 1/2 sum(w_n-y_n)^2")
 
 
 def main():
@@ -133,32 +276,46 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    head, ctx = gpu_solve_rate(a.p, a.log2n, a.cycle, a.steps, a.warmup)
-    roof = kernel_roofline(a.p, ctx, a.kernel_reps)
+    base = {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "unit": "unknowns/s", "metric": "DG time-unknowns solved/s to rel. residual 1e-10"}
+    if a.config == 3:
+        r = config3_run(a.batch or 4096, a.steps, a.warmup)
+        print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
+                          "config": {"workload": r["workload"]}, "result": r}))
+        return
+    if a.config == 4:
+        r = config4_run(a.batch or 256, a.steps, a.warmup)
+        print(json.dumps({**base, "value": r["unknowns_per_s"],
+                          "ms_per_step": r["ms_per_forward_backward"],
+                          "config": {"workload": r["workload"]}, "result": r}))
+        return
+    if a.config == 5:
+        r1 = config5_compare(1, 24, a.steps, a.warmup)
+        rb = config5_compare(a.batch or 64, 24, max(1, a.steps // 3), 1)
+        print(json.dumps({**base, "value": rb["fp32_inner"]["unknowns_per_s"],
+                          "ms_per_step": rb["fp32_inner"]["ms_per_solve"],
+                          "config": {"workload": rb["workload"]}, "scalar": r1, "batch": rb}))
+        return
+    head, ctx = config2_case(a.p, a.log2n, a.cycle, a.steps, a.warmup)
+    roof = fused_pass_roofline(a.p, ctx, a.kernel_reps)
     del ctx
+    torch.cuda.empty_cache()
     sweep = []
     if a.sweep:
         for p in range(4):
             if p == a.p:
                 sweep.append(head)
                 continue
-            r, c = gpu_solve_rate(p, a.log2n, a.cycle, max(2, a.steps // 2), 1)
+            r, c = config2_case(p, a.log2n, a.cycle, max(2, a.steps // 2), 1)
             del c
             sweep.append(r)
+    mixed = config5_compare(1, 24, max(2, a.steps // 3), 1) if a.mixed else None
     cpu = cpu_baseline(a.p, a.cpu_log2n) if a.cpu_baseline else None
     out = {
-        "metric": "DG time-unknowns solved/s to rel. residual 1e-10",
+        **base,
         "value": head["unknowns_per_s"],
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
         "ms_per_step": head["ms_per_solve"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
         "config": {"workload": f"u'+u=f, T=1000, N=2^{a.log2n} slabs, p={a.p}, "
                                f"{a.cycle}(2,2) cycle to 1e-10, 16-mode Fourier f",
                    "cycles": head["cycles"], "relres": head["relres"]},
@@ -166,6 +323,7 @@ def main():
         "cpu_baseline": cpu,
         "sweep_p": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles")}
                     for r in sweep],
+        "fp32_inner_vs_fp64": mixed,
     }
     print(json.dumps(out))
 

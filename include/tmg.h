@@ -185,6 +185,18 @@ int tmg_op_up(tmg_handle h, int level, int trans, int nsweep, const double *f,
               const double *fold_u0, const double *u_in, const double *e, double *u_out,
               tmg_stream s);
 
+/*
+ * The fused level-0 pass of a cycle (forward or transposed): starting from
+ * u_in, nu1 damped block Jacobi sweeps (recomputing the pre-smoothing), the
+ * correction u += P e with e in level 1's layout, nu2 sweeps -> u_out; then,
+ * continuing from u_out, nu1 sweeps of the next cycle, the residual and its
+ * restriction -> rc (level 1's layout).  This is the pass every cycle after
+ * the first runs at level 0 (there with u updated in place).  u_in and u_out
+ * must not overlap.  fold_u0 as for tmg_op_down.
+ */
+int tmg_op_fused(tmg_handle h, int trans, const double *f, const double *fold_u0,
+                 const double *u_in, const double *e, double *u_out, double *rc, tmg_stream s);
+
 /* Exact solve L_level e = r on every instance by the parallel affine prefix
  * scan (forward in time; backward for trans = 1).  Requires
  * n_slabs[j] >> level <= 4096. */

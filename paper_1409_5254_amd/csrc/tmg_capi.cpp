@@ -974,6 +974,31 @@ int tmg_op_up(tmg_handle c, int level, int trans, int nsweep, const double *f,
     return TMG_OK;
 }
 
+int tmg_op_fused(tmg_handle c, int trans, const double *f, const double *fold_u0,
+                 const double *u_in, const double *e, double *u_out, double *rcout,
+                 tmg_stream stream)
+{
+    if (!c || !f || !u_in || !e || !u_out || !rcout || c->Lmax < 2 || (fold_u0 && trans))
+        return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const int H = c->H_fused();
+    TileList *tl;
+    int rc = get_tiles(c, 0, kHasNext, c->TO(H), s, &tl);
+    if (rc) return rc;
+    LegArgs a = leg_args(c, 0, trans != 0, tl, H);
+    a.f = f;
+    a.u0 = fold_u0;
+    a.u_in = u_in;
+    a.e = e;
+    a.u_out = u_out;
+    a.rc = rcout;
+    a.pre = c->opt.nu1;
+    a.post = c->opt.nu2;
+    a.next = c->opt.nu1;
+    HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
 int tmg_op_coarse_solve(tmg_handle c, int level, int trans, const double *r, double *e,
                         tmg_stream stream)
 {

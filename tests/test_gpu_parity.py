@@ -297,3 +297,29 @@ def test_warm_start_resume():
     for _ in range(5):
         s2.vcycle(f, dev([1.0]), c)
     assert np.array_equal(host(c), host(a))
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("trans", [False, True])
+def test_fused_level0_pass(p, trans):
+    """tmg_op_fused: the pass every cycle after the first runs at level 0 --
+    recomputed nu1 sweeps, correction, nu2 sweeps (u_out), then nu1 sweeps,
+    residual and restriction (rc)."""
+    rng = np.random.default_rng(70 + p)
+    N, z = 4096, 0.02
+    s = B().Solver([N], [z * N], [1.0], p=p)
+    P = p + 1
+    f, u, e = rand(rng, N * P), rand(rng, N * P), rand(rng, N // 2 * P)
+    u0 = None if trans else 0.3
+    ff = f if trans else core.fold(p, u0, f)
+    post = core.sweeps(p, z, 1.0, ff, core.prolong_add(p, e, core.sweeps(p, z, 1.0, ff, u, 2,
+                                                                         trans=trans)), 2,
+                       trans=trans)
+    nxt = core.sweeps(p, z, 1.0, ff, post, 2, trans=trans)
+    ref_rc = core.restrict(p, core.residual(p, z, 1.0, ff, nxt, trans=trans))
+    d_out = torch.empty(N * P, dtype=torch.float64, device=DEV)
+    d_rc = torch.empty(N // 2 * P, dtype=torch.float64, device=DEV)
+    s.fused(dev(f), dev(u), dev(e), d_out, d_rc, trans=trans,
+            fold_u0=None if trans else dev([u0]))
+    assert relerr(host(d_out), post) <= TOL
+    assert relerr(host(d_rc), ref_rc) <= TOL

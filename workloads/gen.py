@@ -26,9 +26,10 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Instance", "Workload", "sph_jn", "fourier_load", "quadrature_load",
+__all__ = ["Instance", "Workload", "sph_jn", "fourier_load", "fourier_load_torch",
+           "quadrature_load",
            "gaussian_legendre_load", "config1", "config2", "config3", "config4", "config5",
-           "fourier_batch"]
+           "fourier_batch", "fourier_params", "config3_sizes", "config4_params", "config5_params"]
 
 
 def sph_jn(m: int, x: np.ndarray) -> np.ndarray:
@@ -65,6 +66,28 @@ def fourier_load(p: int, N: int, T: float, a, phi) -> np.ndarray:
             jm = float(sph_jn(m, np.array([k * tau / 2.0]))[0])
             trig = (s, co, -s, -co)[m % 4]
             f[:, m] += tau * ak * jm * trig
+    return f.reshape(-1)
+
+
+def fourier_load_torch(p: int, N: int, T: float, a, phi, device="cuda", out=None):
+    """The same load vector as :func:`fourier_load`, evaluated with torch on
+    `device` (for large workloads); returns a flat float64 tensor, or fills
+    `out` (a flat view of N*(p+1) elements)."""
+    import torch
+    P = p + 1
+    tau = T / N
+    c = (torch.arange(N, dtype=torch.float64, device=device) + 0.5) * tau
+    f = out.view(N, P) if out is not None else torch.zeros((N, P), dtype=torch.float64,
+                                                            device=device)
+    if out is not None:
+        f.zero_()
+    for k, (ak, pk) in enumerate(zip(a, phi), start=1):
+        th = c * k + float(pk)
+        s, co = torch.sin(th), torch.cos(th)
+        for m in range(P):
+            jm = float(sph_jn(m, np.array([k * tau / 2.0]))[0])
+            trig = (s, co, -s, -co)[m % 4]
+            f[:, m] += (tau * float(ak) * jm) * trig
     return f.reshape(-1)
 
 
@@ -153,6 +176,36 @@ def fourier_batch(name: str, p: int, N: int, T: float, lam: np.ndarray, rng, mod
         phi = rng.uniform(0.0, 2.0 * math.pi, modes)
         inst.append(Instance(p, N, T, float(lb), 1.0, fourier_load(p, N, T, a, phi)))
     return Workload(name, p, inst)
+
+
+def fourier_params(lam: np.ndarray, rng, modes: int = 16):
+    """Per-instance (lambda, a, phi) draws of a Fourier batch, without load
+    vectors (for generation on the GPU with fourier_load_torch)."""
+    out = []
+    for lb in lam:
+        a = rng.standard_normal(modes)
+        phi = rng.uniform(0.0, 2.0 * math.pi, modes)
+        out.append((float(lb), a, phi))
+    return out
+
+
+def config4_params(B: int = 256, seed: int = 4):
+    rng = np.random.default_rng(seed)
+    return fourier_params(rng.uniform(0.1, 10.0, B), rng), rng
+
+
+def config5_params(B: int = 1, seed: int = 5):
+    rng = np.random.default_rng(seed)
+    return fourier_params(rng.uniform(0.5, 50.0, B), rng)
+
+
+def config3_sizes(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3):
+    """(lambda_j, N_j) of the eigenmode batch, drawn as in config3."""
+    rng = np.random.default_rng(seed)
+    kappa = rng.uniform(0.01, 1.0)
+    lam = (math.pi ** 2) * (np.arange(1, n_inst + 1, dtype=np.float64) ** 2) * kappa
+    Ns = 2 ** rng.integers(log2_range[0], log2_range[1], size=n_inst)
+    return lam, Ns
 
 
 def config4(B: int = 256, N: int = 1 << 20, T: float = 100.0, seed: int = 4) -> Workload:
