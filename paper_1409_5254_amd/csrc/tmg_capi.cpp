@@ -120,7 +120,6 @@ struct tmg_ctx {
     int H_mixd() const { return rs(opt.nu1 + 2); }
     int H_mix() const { return rs(2 * opt.nu1 + opt.nu2 + 3); }
     int H_mixv() const { return rs(opt.nu1 + opt.nu2 + 1); }
-    int H_norm() const { return mixed ? H_mix() : H_fused(); }
     int TO(int H) const { return tile_slabs(P) - H; }
 };
 
@@ -265,13 +264,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.inst = c->bot_d[level];
     a.nlev = c->nlev_d;
     a.st = io.use_state ? c->st : nullptr;
-    if (level == 0 && io.use_state) {
-        TileList *nl;
-        int rc = get_tiles(c, 0, kAll, c->TO(c->H_norm()), s, &nl);
-        if (rc) return rc;
-        a.partial = c->partial;
-        a.norm_off = nl->d_off;
-    }
+    a.ctl = c->ctl;
     a.level = level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
@@ -425,12 +418,12 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     if (solve) {
         a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
         a.rc = c->s.f[1];
-        TileList *nl;
-        if ((rc = get_tiles(c, 0, kAll, c->TO(H), s, &nl))) return rc;
         a.partial = c->partial;
-        a.norm_off = nl->d_off;
+        a.norm_off = tl->d_off;
     }
     HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
+    if (solve && io.use_state)
+        HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
     return TMG_OK;
 }
 
@@ -477,17 +470,12 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
             a.rc = c->d.f[1];
             a.next = c->opt.nu1;
-            TileList *nl;
-            if ((rc = get_tiles(c, 0, kAll, c->TO(H), s, &nl))) return rc;
             a.partial = c->partial;
-            a.norm_off = nl->d_off;
+            a.norm_off = tl->d_off;
         }
         HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
-    }
-    if (io.use_state) {
-        TileList *nl;
-        if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_norm()), s, &nl))) return rc;
-        HIPCHK(c, launch_finalize(c->partial, nl->d_off, c->batch, c->st, c->ctl, 0, s));
+        if (solve && io.use_state)
+            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
     }
     return TMG_OK;
 }
@@ -504,7 +492,6 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
     const int H0[5] = {c->H_fused(), c->H_mixd(), c->H_mix(), c->H_mixv(), c->H_up()};
     for (int H : H0)
         if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
-    if ((rc = get_tiles(c, 0, kAll, c->TO(c->H_norm()), s, &tl))) return rc;
     return TMG_OK;
 }
 

@@ -8,7 +8,12 @@
 namespace tmg {
 
 constexpr int kMaxP = 4;        // P = p + 1 coefficients per slab
-constexpr int kThreads = 256;   // work-group size of the streaming kernels
+constexpr int kThreads = 256;   // work-group size of the scan and reduction kernels
+// Work-group size of the streaming (tile) kernels.  Four wavefronts: one
+// wavefront per work-group (barrier-free exchange) measured slower on the
+// level-0 pass, whose halo share grows fourfold, and no faster on the small
+// levels, whose time is launch and memory latency.
+constexpr int kLegThreads = 256;
 constexpr int kMaxSweeps = 8;
 constexpr int64_t kMaxCoarse = 4096;
 constexpr int kBottomThreads = 512;   // work-group of the bottom-of-hierarchy kernel
@@ -18,7 +23,7 @@ constexpr int kBottomThreads = 512;   // work-group of the bottom-of-hierarchy k
 // two fine slabs of a coarse slab sit in neighbouring lanes; otherwise S is
 // even and they sit in the same thread.
 constexpr int slabs_per_thread(int P) { return P == 1 ? 4 : 2; }
-constexpr int tile_slabs(int P) { return kThreads * slabs_per_thread(P); }
+constexpr int tile_slabs(int P) { return kLegThreads * slabs_per_thread(P); }
 // Slabs per thread of the bottom kernel (even), the largest level (slabs) it
 // holds, and the most levels it can hold (log2(bottom_max) + 1).
 constexpr int bottom_slabs(int P) { return P == 1 ? 8 : (P == 2 ? 4 : 2); }
@@ -144,9 +149,8 @@ struct BottomArgsT {
     const double *R;
     const int *inst;         // instances handled, one work-group each
     const int *nlev;         // [batch] levels of each instance
-    const InstState *st;
-    double *partial;         // level-0 residual norm slots (null: none)
-    const int64_t *norm_off;
+    InstState *st;           // level 0: the work-group also finishes its instance's cycle
+    const Control *ctl;
     int level, batch, tab_stride, nu1, nu2, gamma;
 };
 using BottomArgs = BottomArgsT<double>;

@@ -37,6 +37,7 @@ namespace tmg {
 namespace {
 
 constexpr int kWaves = kThreads / 64;
+constexpr int kLegWaves = kLegThreads / 64;
 
 
 // Instance owning a tile: largest j with off[j] <= tile (off[0] = 0).
@@ -52,13 +53,27 @@ __device__ __forceinline__ int find_instance(const int64_t *__restrict__ off, in
     return lo;
 }
 
+// Value of lane - 1 (lane 0 receives 0): a DPP whole-wavefront shift by one
+// lane, which stays in the VALU (no LDS round trip).
+__device__ __forceinline__ float lane_shr1(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_shr1(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 // End value of the left neighbour of this thread's first slab, for the
 // current sweep.  Double-buffered LDS slots (phase) need one barrier per call.
 template <int NW, typename T>
 __device__ __forceinline__ T left_value(T mine_last, double (*xchg)[NW], int &phase)
 {
+    if constexpr (NW == 1) return lane_shr1(mine_last);  // one wavefront: no LDS, no barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    T v = __shfl_up(mine_last, 1, 64);
+    T v = lane_shr1(mine_last);
     if (lane == 63) xchg[phase][wave] = (double)mine_last;
     __syncthreads();
     if (lane == 0) v = wave ? (T)xchg[phase][wave - 1] : (T)0;
@@ -72,6 +87,7 @@ template <int NW>
 __device__ __forceinline__ double block_sum(double x, double *red)
 {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if constexpr (NW == 1) return x;
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
     double s = 0.0;
@@ -79,6 +95,24 @@ __device__ __forceinline__ double block_sum(double x, double *red)
         for (int w = 0; w < NW; ++w) s += red[w];
     __syncthreads();
     return s;
+}
+
+// Orders LDS accesses of one wavefront that exchange data between its lanes
+// (the LDS executes a wavefront's operations in order; the fences only keep
+// the compiler from moving them).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Barrier over the NW wavefronts taking part (NW = 1: the first wavefront).
+template <int NW>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (NW == 1) wave_sync();
+    else __syncthreads();
 }
 
 // 16-byte vector of T
@@ -422,7 +456,7 @@ __device__ __forceinline__ void load_iterate(T (&u)[S][P], const T *u_in, const 
 template <int P, int S, typename T>
 __device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int li0, int halo)
 {
-    constexpr int TS = kThreads * S;
+    constexpr int TS = kLegThreads * S;
     if (halo_out && li0 >= TS - halo) {
         T *hb = halo_out + (int64_t)blockIdx.x * (int64_t)halo * P + (int64_t)(li0 - (TS - halo)) * P;
 #pragma unroll
@@ -432,6 +466,22 @@ __device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int 
     }
 }
 
+// Convergence state after a cycle whose squared residual norm is acc
+// (relative residual criterion of section 4.2).
+__device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, const Control *ctl)
+{
+    InstState s = st[j];
+    s.cycles += 1;
+    s.rsq = acc;
+    if (!isfinite(acc)) s.done = 3;
+    else if (acc <= ctl->rtol2 * s.r0sq) s.done = 1;
+    else if (acc > 1e6 * s.r0sq) s.done = 4;
+    else if (s.cycles >= ctl->max_cycles) s.done = 2;
+    st[j] = s;
+}
+
+// Squared residual of the tile's output slabs into its partial slot (summed
+// per instance in a fixed order by k_finalize).
 template <int P, int S, int NW>
 __device__ __forceinline__ void norm_partial(const double (&r)[S][P], double *partial,
                                              const int64_t *norm_off, const TileRef &tr, int64_t m0,
@@ -454,12 +504,12 @@ __device__ __forceinline__ void norm_partial(const double (&r)[S][P], double *pa
 // two fine slabs of a coarse slab sit in neighbouring lanes (tiles start at
 // an even slab) and meet through a lane shuffle.
 template <int P, bool BW, typename T>
-__global__ __launch_bounds__(kThreads) void k_leg(LegArgsT<T> a)
+__global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
 {
     constexpr int S = slabs_per_thread(P);
     constexpr int SC = S >= 2 ? S / 2 : 1;  // coarse slabs touched per thread
-    __shared__ double xchg[2][kWaves];
-    __shared__ double red[kWaves];
+    __shared__ double xchg[2][kLegWaves];
+    __shared__ double red[kLegWaves];
     const TileRef tr = tile_ref(a);
     const int li0 = threadIdx.x * S;
     const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
@@ -480,19 +530,19 @@ __global__ __launch_bounds__(kThreads) void k_leg(LegArgsT<T> a)
     if (a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
     apply_G<P, S, T>(g, f, op);
     int phase = 0;
-    sweeps<P, S, kWaves, T>(u, g, op, a.pre, xchg, phase);
+    sweeps<P, S, kLegWaves, T>(u, g, op, a.pre, xchg, phase);
     if (a.e) prolong_add<P, S, T>(u, e, a.R, m0);
-    sweeps<P, S, kWaves, T>(u, g, op, a.post, xchg, phase);
+    sweeps<P, S, kLegWaves, T>(u, g, op, a.post, xchg, phase);
     if (a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
     store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
     double r[S][P];
     if (a.partial) {
-        residual<P, S, kWaves>(r, u, f, op, xchg, phase);
-        norm_partial<P, S, kWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
+        residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
+        norm_partial<P, S, kLegWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
     }
     if (a.rc) {
-        sweeps<P, S, kWaves, T>(u, g, op, a.next, xchg, phase);
-        residual<P, S, kWaves>(r, u, f, op, xchg, phase);
+        sweeps<P, S, kLegWaves, T>(u, g, op, a.next, xchg, phase);
+        residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
         restrict_store<P, S, BW, T>(r, a.R, a.rc + tr.coff * P, m0, tr.N, tr.Nc, li0, a.halo);
     }
 }
@@ -506,12 +556,12 @@ __global__ __launch_bounds__(kThreads) void k_leg(LegArgsT<T> a)
 //   next: the next inner down leg: r_{k+1} -> FP32, next sweeps from zero
 //         (FP32), inner residual in FP64 arithmetic, restriction (FP32).
 template <int P, bool BW>
-__global__ __launch_bounds__(kThreads) void k_mix(MixArgs a)
+__global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
 {
     constexpr int S = slabs_per_thread(P);
     constexpr int SC = S >= 2 ? S / 2 : 1;
-    __shared__ double xchg[2][kWaves];
-    __shared__ double red[kWaves];
+    __shared__ double xchg[2][kLegWaves];
+    __shared__ double red[kLegWaves];
     const TileRef tr = tile_ref(a);
     const int li0 = threadIdx.x * S;
     const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
@@ -539,7 +589,7 @@ __global__ __launch_bounds__(kThreads) void k_mix(MixArgs a)
     int phase = 0;
     float rf[S][P], g[S][P], ei[S][P];
     if (a.up) {
-        residual<P, S, kWaves>(r, u, f, op, xchg, phase);
+        residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -548,9 +598,9 @@ __global__ __launch_bounds__(kThreads) void k_mix(MixArgs a)
                 ei[s][k] = 0.0f;
             }
         apply_G<P, S, float>(g, rf, op);
-        sweeps<P, S, kWaves, float>(ei, g, op, a.pre, xchg, phase);
+        sweeps<P, S, kLegWaves, float>(ei, g, op, a.pre, xchg, phase);
         prolong_add<P, S, float>(ei, e, a.R32, m0);
-        sweeps<P, S, kWaves, float>(ei, g, op, a.post, xchg, phase);
+        sweeps<P, S, kLegWaves, float>(ei, g, op, a.post, xchg, phase);
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -558,8 +608,9 @@ __global__ __launch_bounds__(kThreads) void k_mix(MixArgs a)
         if (a.u_out) store_chunk<P, S, BW, double>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
         store_halo<P, S, double>(a.halo_out, u, li0, a.halo);
     }
-    residual<P, S, kWaves>(r, u, f, op, xchg, phase);
-    if (a.partial) norm_partial<P, S, kWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
+    residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
+    if (a.partial)
+        norm_partial<P, S, kLegWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
     if (a.rc) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -569,8 +620,8 @@ __global__ __launch_bounds__(kThreads) void k_mix(MixArgs a)
                 ei[s][k] = 0.0f;
             }
         apply_G<P, S, float>(g, rf, op);
-        sweeps<P, S, kWaves, float>(ei, g, op, a.next, xchg, phase);
-        residual<P, S, kWaves>(r, ei, rf, op, xchg, phase);
+        sweeps<P, S, kLegWaves, float>(ei, g, op, a.next, xchg, phase);
+        residual<P, S, kLegWaves>(r, ei, rf, op, xchg, phase);
         restrict_store<P, S, BW, float>(r, a.R32, a.rc + tr.coff * P, m0, tr.N, tr.Nc, li0, a.halo);
     }
 }
@@ -588,10 +639,11 @@ struct ScanSmem {
     double wend[NT];
 };
 
+// NT = 64 runs in one wavefront with shuffles only (sm unused, may be null).
 template <int P, bool BW, int NT, typename TR, typename TE>
 __device__ __forceinline__ void coarse_scan(const TR *__restrict__ r_base, double u0,
                                             TE *__restrict__ e_base, int64_t N,
-                                            const double *__restrict__ tab, ScanSmem<NT> &sm)
+                                            const double *__restrict__ tab, ScanSmem<NT> *sm)
 {
     constexpr TabLayout L(P);
     double AI[P * P], q[P], c[P], v[P];
@@ -634,24 +686,34 @@ __device__ __forceinline__ void coarse_scan(const TR *__restrict__ r_base, doubl
                 A = A * Ao;
             }
         }
-        if (lane == 63) {
-            sm.wa[wave] = A;
-            sm.wb[wave] = B;
-        }
-        __syncthreads();
-        // compose the totals of the earlier waves and the carried end value
-        double Bp = carry;
-        for (int w = 0; w < wave; ++w) Bp = sm.wa[w] * Bp + sm.wb[w];
-        const double wm = A * Bp + B;   // end value of slab m
-        sm.wend[threadIdx.x] = wm;
-        __syncthreads();
-        const double wprev = threadIdx.x == 0 ? carry : sm.wend[threadIdx.x - 1];
-        if (ok)
-#pragma unroll
-            for (int k = 0; k < P; ++k) e_base[pm * P + k] = (TE)(d[k] + q[k] * wprev);
         const int64_t nlast = (N - base < NT) ? (N - base) : NT;
-        carry = sm.wend[nlast - 1];
-        __syncthreads();
+        if constexpr (NT == 64) {
+            const double wm = A * carry + B;   // end value of slab m
+            const double wl = __shfl_up(wm, 1, 64);
+            const double wprev = lane == 0 ? carry : wl;
+            if (ok)
+#pragma unroll
+                for (int k = 0; k < P; ++k) e_base[pm * P + k] = (TE)(d[k] + q[k] * wprev);
+            carry = __shfl(wm, (int)nlast - 1, 64);
+        } else {
+            if (lane == 63) {
+                sm->wa[wave] = A;
+                sm->wb[wave] = B;
+            }
+            __syncthreads();
+            // compose the totals of the earlier waves and the carried end value
+            double Bp = carry;
+            for (int w = 0; w < wave; ++w) Bp = sm->wa[w] * Bp + sm->wb[w];
+            const double wm = A * Bp + B;   // end value of slab m
+            sm->wend[threadIdx.x] = wm;
+            __syncthreads();
+            const double wprev = threadIdx.x == 0 ? carry : sm->wend[threadIdx.x - 1];
+            if (ok)
+#pragma unroll
+                for (int k = 0; k < P; ++k) e_base[pm * P + k] = (TE)(d[k] + q[k] * wprev);
+            carry = sm->wend[nlast - 1];
+            __syncthreads();
+        }
     }
 }
 
@@ -664,7 +726,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
     const int64_t off = a.slab_off[j];
     const int64_t N = a.slab_off[j + 1] - off;
     coarse_scan<P, BW, kThreads, double, double>(a.r + off * P, a.u0 ? a.u0[j] : 0.0, a.e + off * P,
-                                                 N, a.tab + (int64_t)j * a.tab_stride, sm);
+                                                 N, a.tab + (int64_t)j * a.tab_stride, &sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,9 +756,14 @@ struct Bottom {
     static constexpr int NW = NT / 64;
     static constexpr int S = bottom_slabs(P);
     static constexpr int STRIDE = TabLayout(P).stride();
+    static constexpr int WAVE_SLABS = 64 * S;   // largest level one wavefront holds
     BottomLds<P> &sm;
     int lb;        // first level of this visit
     int64_t Nlb;   // its slab count
+    int Lc;        // coarsest level
+    int lw;        // first level with at most WAVE_SLABS slabs
+    int nu1, nu2, gamma;
+    const double *R;
 
     __device__ int64_t nslab(int l) const { return Nlb >> (l - lb); }
     // offset (doubles) of level l in the f / x regions
@@ -704,9 +771,14 @@ struct Bottom {
     __device__ const double *tab(int l) const { return sm.tab + (l - lb) * STRIDE; }
 
     __device__ void load_ops(Ops<P> &op, int l) const { op.load(tab(l)); }
+    // exchange slots for G wavefronts (unused by a single wavefront)
+    template <int G>
+    __device__ double (*xchg() const)[G] { return reinterpret_cast<double (*)[G]>(sm.xchg); }
 
-    // nu1 sweeps from x_l (zero if `zero`), residual, restriction into f_{l+1}
-    __device__ void down(int l, bool zero, int nu1) const
+    // nu1 sweeps from x_l (zero if `zero`), residual, restriction into
+    // f_{l+1}; run by the first G wavefronts (G = NW or 1)
+    template <int G>
+    __device__ __forceinline__ void down(int l, bool zero) const
     {
         Ops<P> op;
         load_ops(op, l);
@@ -723,14 +795,8 @@ struct Bottom {
         }
         apply_G<P, S>(g, f, op);
         int phase = 0;
-        sweeps<P, S, NW>(u, g, op, nu1, sm.xchg, phase);
-        residual<P, S, NW>(r, u, f, op, sm.xchg, phase);
-        restrict_store(r, l);
-        __syncthreads();
-    }
-
-    __device__ void restrict_store(const double (&r)[S][P], int l) const
-    {
+        sweeps<P, S, G>(u, g, op, nu1, xchg<G>(), phase);
+        residual<P, S, G>(r, u, f, op, xchg<G>(), phase);
         const double *R1T = R, *R2T = R + P * P;
         double rc[S / 2][P];
 #pragma unroll
@@ -743,13 +809,14 @@ struct Bottom {
                     s1 += R1T[q * P + k] * r[2 * i][q] + R2T[q * P + k] * r[2 * i + 1][q];
                 rc[i][k] = s1;
             }
-        const int64_t m0 = (int64_t)threadIdx.x * S;
         store_chunk<P, S / 2, BW>(sm.f + loff(l + 1), m0 / 2, nslab(l + 1), rc, 0, 0);
+        group_sync<G>();
     }
 
     // x_l <- S^nu2 (S^nu1 x_l + P x_{l+1}), the pre-smoothing recomputed
     // from x_l (or zero) exactly as in the down leg.
-    __device__ void up(int l, bool zero, int nu1, int nu2) const
+    template <int G>
+    __device__ __forceinline__ void up(int l, bool zero) const
     {
         Ops<P> op;
         load_ops(op, l);
@@ -767,7 +834,7 @@ struct Bottom {
         load_chunk<P, S / 2, BW>(sm.x + loff(l + 1), m0 / 2, nslab(l + 1), e);
         apply_G<P, S>(g, f, op);
         int phase = 0;
-        sweeps<P, S, NW>(u, g, op, nu1, sm.xchg, phase);
+        sweeps<P, S, G>(u, g, op, nu1, xchg<G>(), phase);
         const double *R1T = R, *R2T = R + P * P;
 #pragma unroll
         for (int i = 0; i < S / 2; ++i)
@@ -782,20 +849,74 @@ struct Bottom {
                 u[2 * i][k] += s1;
                 u[2 * i + 1][k] += s2;
             }
-        sweeps<P, S, NW>(u, g, op, nu2, sm.xchg, phase);
+        sweeps<P, S, G>(u, g, op, nu2, xchg<G>(), phase);
         // every thread owns the slabs it writes, so the update is in place
         store_chunk<P, S, BW>(sm.x + loff(l), m0, N, u, 0, 0);
-        __syncthreads();
+        group_sync<G>();
     }
 
-    __device__ void coarse(int l) const
+    template <int G>
+    __device__ __forceinline__ void coarse(int l) const
     {
-        coarse_scan<P, BW, NT, double, double>(sm.f + loff(l), 0.0, sm.x + loff(l), nslab(l), tab(l),
-                                               sm.scan);
-        __syncthreads();
+        if constexpr (G == 1)
+            coarse_scan<P, BW, 64, double, double>(sm.f + loff(l), 0.0, sm.x + loff(l), nslab(l),
+                                                   tab(l), (ScanSmem<64> *)nullptr);
+        else
+            coarse_scan<P, BW, NT, double, double>(sm.f + loff(l), 0.0, sm.x + loff(l), nslab(l),
+                                                   tab(l), &sm.scan);
+        group_sync<G>();
     }
 
-    const double *R;
+    // One visit of level `top` (top < Lc): down(top); then, until the
+    // coarsest level, gamma visits of each coarser level (the exact scan on
+    // the coarsest); up(top).  `zero`: the iterate of `top` starts at zero.
+    // Bit l of `again` marks the second visit of level l.  With G = NW, the
+    // levels from lw on are handed to the first wavefront as whole visits.
+    template <int G>
+    __device__ __forceinline__ void visit(int top, bool zero) const
+    {
+        uint64_t again = 0;
+        int l = top;
+        down<G>(l, zero);
+        while (true) {
+            bool descend = false;
+            if (l + 1 == Lc) {
+                coarse<G>(l + 1);
+            } else if constexpr (G > 1) {
+                if (l + 1 >= lw) {
+                    if (threadIdx.x < 64)
+                        for (int rep = 0; rep < gamma; ++rep) visit<1>(l + 1, rep == 0);
+                    __syncthreads();
+                } else {
+                    descend = true;
+                }
+            } else {
+                descend = true;
+            }
+            if (descend) {
+                ++l;
+                down<G>(l, true);
+                continue;
+            }
+            // the coarser levels of l are done: climb
+            bool finished = false;
+            while (true) {
+                up<G>(l, l == top ? zero : !((again >> l) & 1));
+                if (l == top) {
+                    finished = true;
+                    break;
+                }
+                if (gamma > 1 && !((again >> l) & 1)) {
+                    again |= (uint64_t)1 << l;
+                    down<G>(l, false);
+                    break;
+                }
+                again &= ~((uint64_t)1 << l);
+                --l;
+            }
+            if (finished) break;
+        }
+    }
 };
 
 template <int P, bool BW, typename TIO>
@@ -814,8 +935,8 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
         // exact solve, directly in global memory
         const double *tab = a.tab + ((int64_t)lb * a.batch + j) * a.tab_stride;
         const double u0 = (lb == 0 && a.u0) ? a.u0[j] : 0.0;
-        coarse_scan<P, BW, NT, TIO, TIO>(a.f + off * P, u0, a.x_out + off * P, N, tab, sm.scan);
-        if (lb == 0 && a.partial) {
+        coarse_scan<P, BW, NT, TIO, TIO>(a.f + off * P, u0, a.x_out + off * P, N, tab, &sm.scan);
+        if (lb == 0 && a.st) {
             // squared residual of the result, one slab per thread and pass
             constexpr TabLayout L(P);
             const TIO *x = a.x_out + off * P, *f = a.f + off * P;
@@ -837,15 +958,13 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
                 }
             }
             acc = block_sum<B::NW>(acc, sm.red);
-            if (threadIdx.x == 0) sm.red[0] = acc;
-            __syncthreads();
-            acc = sm.red[0];
-            const int64_t lo = a.norm_off[j], hi = a.norm_off[j + 1];
-            for (int64_t i = lo + threadIdx.x; i < hi; i += NT) a.partial[i] = i == lo ? acc : 0.0;
+            if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl);
         }
         return;
     }
-    B b{sm, lb, N, a.R};
+    int lw = lb;
+    while ((N >> (lw - lb)) > B::WAVE_SLABS) ++lw;
+    const B b{sm, lb, N, Lc, lw, a.nu1, a.nu2, a.gamma, a.R};
     // tables of levels lb .. Lc, the right-hand side and the initial guess
     for (int l = lb; l <= Lc; ++l)
         for (int i = threadIdx.x; i < STRIDE; i += NT)
@@ -862,42 +981,18 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
     }
     __syncthreads();
     const bool zero = a.x_in == nullptr;
-    {
-        // visit(l) = down(l); [exact solve at l+1 | gamma x visit(l+1)]; up(l),
-        // iteratively; bit l of `again` marks the second visit of level l.
-        uint64_t again = 0;
-        int l = lb;
-        b.down(l, zero, a.nu1);
-        while (true) {
-            if (l + 1 == Lc) {
-                b.coarse(l + 1);
-                b.up(l, l == lb ? zero : !((again >> l) & 1), a.nu1, a.nu2);
-                bool done = false;
-                while (true) {
-                    if (l == lb) {
-                        done = true;
-                        break;
-                    }
-                    if (a.gamma > 1 && !((again >> l) & 1)) {
-                        again |= (uint64_t)1 << l;
-                        b.down(l, false, a.nu1);
-                        break;
-                    }
-                    again &= ~((uint64_t)1 << l);
-                    --l;
-                    b.up(l, l == lb ? zero : !((again >> l) & 1), a.nu1, a.nu2);
-                }
-                if (done) break;
-            } else {
-                ++l;
-                b.down(l, true, a.nu1);
-            }
-        }
+    if (lb >= lw) {
+        // the whole visit fits one wavefront
+        if (threadIdx.x < 64) b.template visit<1>(lb, zero);
+        __syncthreads();
+    } else {
+        b.template visit<B::NW>(lb, zero);
     }
     // result of level lb back to global memory
     for (int64_t i = threadIdx.x; i < N * P; i += NT) a.x_out[off * P + i] = (TIO)sm.x[i];
-    if (lb == 0 && a.partial) {
-        // squared residual of the result (level 0 of this instance)
+    if (lb == 0 && a.st) {
+        // squared residual of the result (level 0 of this instance): the
+        // work-group finishes the cycle of its instance itself
         Ops<P> op;
         b.load_ops(op, 0);
         const int64_t m0 = (int64_t)threadIdx.x * S;
@@ -913,18 +1008,13 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
         acc = block_sum<B::NW>(acc, sm.red);
-        if (threadIdx.x == 0) sm.red[0] = acc;
-        __syncthreads();
-        acc = sm.red[0];
-        // the instance's whole sum goes to its first slot, the others are zeroed
-        const int64_t lo = a.norm_off[j], hi = a.norm_off[j + 1];
-        for (int64_t i = lo + threadIdx.x; i < hi; i += NT) a.partial[i] = i == lo ? acc : 0.0;
+        if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl);
     }
 }
 
 // Per-tile sum of squares of the folded load vector (the initial residual).
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_norm_f(const double *__restrict__ f,
+__global__ __launch_bounds__(kLegThreads) void k_norm_f(const double *__restrict__ f,
                                                      const double *__restrict__ u0,
                                                      const double *__restrict__ tab, int tab_stride,
                                                      const int64_t *__restrict__ slab_off,
@@ -933,7 +1023,7 @@ __global__ __launch_bounds__(kThreads) void k_norm_f(const double *__restrict__ 
 {
     constexpr int S = slabs_per_thread(P);
     constexpr TabLayout L(P);
-    __shared__ double red[kWaves];
+    __shared__ double red[kLegWaves];
     const int64_t tile = blockIdx.x;
     const int j = find_instance(tile_off, batch, tile);
     const int64_t t = tile - tile_off[j];
@@ -951,12 +1041,15 @@ __global__ __launch_bounds__(kThreads) void k_norm_f(const double *__restrict__ 
             if (u0 && m0 + s == 0) y += u0[j] * tab[(int64_t)j * tab_stride + L.V() + k];
             acc += y * y;
         }
-    acc = block_sum<kWaves>(acc, red);
+    acc = block_sum<kLegWaves>(acc, red);
     if (threadIdx.x == 0) partial[tile] = acc;
 }
 
 // One work-group per instance: sum its partials in a fixed order and update
-// the convergence state (relative residual criterion of section 4.2).
+// the convergence state (relative residual criterion of section 4.2).  After
+// a cycle, instances without partials (no tile in the level-0 pass: their
+// whole hierarchy ran in the bottom kernel, which updated their state) are
+// left alone.
 constexpr int kFinThreads = 1024;
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restrict__ partial,
                                                           const int64_t *__restrict__ norm_off,
@@ -965,8 +1058,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
 {
     __shared__ double red[kFinThreads / 64];
     const int j = blockIdx.x;
-    if (!is_r0 && st[j].done) return;
     const int64_t lo = norm_off[j], hi = norm_off[j + 1];
+    if (!is_r0 && (st[j].done || lo == hi)) return;
     // eight independent loads in flight per thread, summed in a fixed order
     double acc = 0.0;
     for (int64_t b = lo; b < hi; b += 8 * kFinThreads) {
@@ -980,23 +1073,17 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
         for (int q = 0; q < 8; ++q) acc += v[q];
     }
     acc = block_sum<kFinThreads / 64>(acc, red);
-    if (threadIdx.x == 0) {
-        InstState s = st[j];
-        if (is_r0) {
-            s.r0sq = acc;
-            s.rsq = acc;
-            s.cycles = 0;
-            s.done = !isfinite(acc) ? 3 : (acc == 0.0 ? 1 : 0);
-        } else {
-            s.cycles += 1;
-            s.rsq = acc;
-            if (!isfinite(acc)) s.done = 3;
-            else if (acc <= ctl->rtol2 * s.r0sq) s.done = 1;
-            else if (acc > 1e6 * s.r0sq) s.done = 4;
-            else if (s.cycles >= ctl->max_cycles) s.done = 2;
-        }
-        st[j] = s;
+    if (threadIdx.x != 0) return;
+    if (!is_r0) {
+        finish_cycle(st, j, acc, ctl);
+        return;
     }
+    InstState s = st[j];
+    s.r0sq = acc;
+    s.rsq = acc;
+    s.cycles = 0;
+    s.done = !isfinite(acc) ? 3 : (acc == 0.0 ? 1 : 0);
+    st[j] = s;
 }
 
 // dlambda_j = -sum_n z_n^T M_tau u_n (M_tau = tau diag(1/(2k+1))),
@@ -1042,8 +1129,8 @@ hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_leg<PP, true, T>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_leg<PP, false, T>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        if (backward) hipLaunchKernelGGL((k_leg<PP, true, T>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_leg<PP, false, T>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, a);
     })
     return hipGetLastError();
 }
@@ -1054,8 +1141,8 @@ hipError_t launch_mix(int P, bool backward, const MixArgs &a, int64_t ntiles, hi
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_mix<PP, true>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_mix<PP, false>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a);
+        if (backward) hipLaunchKernelGGL((k_mix<PP, true>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_mix<PP, false>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, a);
     })
     return hipGetLastError();
 }
@@ -1089,7 +1176,7 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        hipLaunchKernelGGL((k_norm_f<PP>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, f, u0, tab,
+        hipLaunchKernelGGL((k_norm_f<PP>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, f, u0, tab,
                            tab_stride, slab_off, tile_off, batch, partial);
     })
     return hipGetLastError();

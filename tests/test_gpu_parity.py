@@ -232,6 +232,39 @@ def test_batched_uneven(schedule, gamma):
         assert relerr(U[s.offsets[j]:s.offsets[j + 1]], uo) <= TOL
 
 
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("trans", [False, True])
+def test_bottom_wavefront_levels(p, gamma, trans):
+    """The bottom kernel runs levels of at most 64 * S slabs (S slabs per
+    thread) in its first wavefront alone.  Instances whose bottom visit
+    starts just above, at and below that size, plus a tiny one, solved in one
+    handle (forward, or the adjoint system backward in time), each equal the
+    oracle's solve with the same cycle count."""
+    S = {0: 8, 1: 4}.get(p, 2)
+    wave = 64 * S
+    Ns = [4 * wave, 2 * wave, wave, wave // 2, 4]
+    P = p + 1
+    rng = np.random.default_rng(70 + p)
+    lams = rng.uniform(0.2, 5.0, len(Ns))
+    Ts = [float(n) / 64.0 for n in Ns]
+    gs = [rand(rng, n * P) * 0.1 for n in Ns]
+    s = B().Solver(Ns, Ts, list(lams), p=p, gamma=gamma)
+    g = dev(np.concatenate(gs))
+    if trans:
+        z, _, _, cyc, _, st = s.adjoint_solve(g, rtol=1e-10)
+    else:
+        res = s.solve(g, dev(np.zeros(len(Ns))), rtol=1e-10)
+        z, cyc, st = res.u, res.cycles, res.status
+    assert st == 0
+    Z = host(z)
+    for j, n in enumerate(Ns):
+        zo, k, _, _ = core.solve_folded(p, Ts[j], lams[j], gs[j], rtol=1e-10, trans=trans,
+                                        opts=core.Opts(gamma=gamma))
+        assert cyc[j] == k
+        assert relerr(Z[s.offsets[j]:s.offsets[j + 1]], zo) <= TOL
+
+
 @pytest.mark.parametrize("p", [1, 2])
 def test_adjoint_solve_and_gradients(p):
     """tmg_adjoint_solve equals the oracle's multigrid solve of L^T z = g and
