@@ -41,7 +41,9 @@ using namespace tmg;
 
 namespace {
 
-enum TileKind { kDeep = 0, kAll = 1, kHasNext = 2 };
+// kDeep: streaming levels (level < lb_j); kDeepNext: the next level streams
+// too (level + 1 < lb_j); kDeepLast: the next level is in the bottom kernel.
+enum TileKind { kDeep = 0, kAll = 1, kHasNext = 2, kDeepNext = 3, kDeepLast = 4 };
 
 struct TileList {
     int64_t ntiles = 0;
@@ -82,6 +84,7 @@ struct tmg_ctx {
     LevelStore<float> s;                          // FP32 hierarchy (mixed precision)
     std::vector<int64_t> level_size;              // coefficients per level
     double *hb[2] = {nullptr, nullptr};           // level-0 halo buffers
+    int64_t hb_last_off = 0;                      // slots of the one-level pass next to a two-level one
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
     float *tab32_fwd = nullptr, *tab32_adj = nullptr;  // the same tables rounded to FP32
@@ -116,6 +119,11 @@ struct tmg_ctx {
     int H_down() const { return rs(opt.nu1 + 1); }
     int H_up() const { return rs(opt.nu1 + opt.nu2); }
     int H_fused() const { return rs(2 * opt.nu1 + opt.nu2 + 1); }
+    // fused pass that also runs level 1's up leg: level 1's first nu1 + nu2
+    // coarse slabs are wrong, 2 (nu1 + nu2) fine slabs, then nu2 + nu1 + 1
+    int H_fused2() const { return rs(3 * (opt.nu1 + opt.nu2) + 1); }
+    // V-cycle solves in FP64 fuse level 1's up leg into the level-0 pass
+    bool fuse_up1() const { return opt.gamma == 1 && !mixed; }
     // mixed precision, level 0: first down pass, fused pass, single cycle
     int H_mixd() const { return rs(opt.nu1 + 2); }
     int H_mix() const { return rs(2 * opt.nu1 + opt.nu2 + 3); }
@@ -153,6 +161,8 @@ bool participates(const tmg_ctx *c, int j, int level, int kind)
     if (level >= c->L[j]) return false;
     if (kind == kDeep) return level < c->lb[j];       // streaming kernels in the cycle
     if (kind == kHasNext) return level + 1 < c->L[j]; // level-wise entry points
+    if (kind == kDeepNext) return level + 1 < c->lb[j];
+    if (kind == kDeepLast) return level < c->lb[j] && level + 1 >= c->lb[j];
     return true;
 }
 
@@ -323,22 +333,24 @@ int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t 
 }
 
 template <typename T>
-int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s);
+int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, bool skip_up = false);
 
+// skip_up: the up leg of this level runs inside the level-0 pass instead
 template <typename T>
-int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
+int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s,
+                  bool skip_up = false)
 {
     int rc = enqueue_down<T>(c, io, level, zero, s);
     if (rc) return rc;
     if ((rc = enqueue_coarse_visits<T>(c, io, level + 1, s))) return rc;
-    return enqueue_up<T>(c, io, level, zero, s);
+    return skip_up ? TMG_OK : enqueue_up<T>(c, io, level, zero, s);
 }
 
 // gamma visits of level l >= 1 from zero: bottom-kernel instances and,
 // recursively, the streaming ones.  (When l is an instance's coarsest
 // level its visit is the exact solve; repeating it changes nothing.)
 template <typename T>
-int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s)
+int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, bool skip_up)
 {
     int rc;
     LevelStore<T> &L = store<T>(c);
@@ -351,7 +363,7 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s)
                                     g == 0 ? L.x(l, cur) : L.x(l, cur ^ 1), s)))
             return rc;
         if (c->deep_n[l] > 0) {
-            if ((rc = enqueue_visit<T>(c, io, l, g == 0, s))) return rc;
+            if ((rc = enqueue_visit<T>(c, io, l, g == 0, s, skip_up))) return rc;
         } else if (g > 0) {
             c->cur[l] ^= 1;
         }
@@ -452,30 +464,48 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         }
         if (!solve || first)
             if ((rc = enqueue_down<double>(c, io, 0, first, s))) return rc;
-        if ((rc = enqueue_coarse_visits<double>(c, io, 1, s))) return rc;
-        // fused level-0 pass
-        const int H = solve ? c->H_fused() : c->H_up();
-        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
-        LegArgs a = leg_args(c, 0, io.trans, tl, H);
-        a.f = io.f;
-        a.u0 = fold_of(io);
-        a.u_in = first ? nullptr : io.u;
-        a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]);
-        a.e = c->d.x(1, c->cur[1]);
-        a.u_out = io.u;
-        a.st = io.use_state ? c->st : nullptr;
-        a.pre = c->opt.nu1;
-        a.post = c->opt.nu2;
-        if (solve) {
-            a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
-            a.rc = c->d.f[1];
-            a.next = c->opt.nu1;
-            a.partial = c->partial;
-            a.norm_off = tl->d_off;
+        // with fuse2, the instances whose level 1 streams (kDeepNext) run
+        // level 1's up leg inside their level-0 pass; the others
+        // (kDeepLast) take level 1's correction from the bottom kernel
+        const bool fuse2 = solve && c->fuse_up1() && c->deep_n[1] > 0;
+        if ((rc = enqueue_coarse_visits<double>(c, io, 1, s, fuse2))) return rc;
+        // fused level-0 pass(es)
+        for (int pass = fuse2 ? 0 : 1; pass < 2; ++pass) {
+            const bool two = pass == 0;
+            const int H = two ? c->H_fused2() : (solve ? c->H_fused() : c->H_up());
+            const int kind = fuse2 ? (two ? kDeepNext : kDeepLast) : kDeep;
+            if ((rc = get_tiles(c, 0, kind, c->TO(H), s, &tl))) return rc;
+            if (tl->ntiles == 0) continue;
+            const int64_t hoff = fuse2 && !two ? c->hb_last_off : 0;
+            LegArgs a = leg_args(c, 0, io.trans, tl, H);
+            a.f = io.f;
+            a.u0 = fold_of(io);
+            a.u_in = first ? nullptr : io.u;
+            a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]) + hoff;
+            if (two) {
+                a.f1 = c->d.f[1];
+                a.e2 = c->d.x(2, c->cur[2]);
+                a.tab1 = tab_of(c, 1, io.trans);
+                a.tab1T = a.tab1;
+                a.c2slab_off = c->slab_off_d[2];
+            } else {
+                a.e = c->d.x(1, c->cur[1]);
+            }
+            a.u_out = io.u;
+            a.st = io.use_state ? c->st : nullptr;
+            a.pre = c->opt.nu1;
+            a.post = c->opt.nu2;
+            if (solve) {
+                a.halo_out = (io.kind == kEven ? c->hb[1] : c->hb[0]) + hoff;
+                a.rc = c->d.f[1];
+                a.next = c->opt.nu1;
+                a.partial = c->partial;
+                a.norm_off = tl->d_off;
+            }
+            HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
+            if (solve && io.use_state)
+                HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
         }
-        HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
-        if (solve && io.use_state)
-            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
     }
     return TMG_OK;
 }
@@ -492,6 +522,9 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
     const int H0[5] = {c->H_fused(), c->H_mixd(), c->H_mix(), c->H_mixv(), c->H_up()};
     for (int H : H0)
         if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+    if ((rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_fused2()), s, &tl)) ||
+        (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_fused()), s, &tl)))
+        return rc;
     return TMG_OK;
 }
 
@@ -780,6 +813,11 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         const int Hs[5] = {c->H_fused(), c->H_up(), c->H_mix(), c->H_mixv(), c->H_mixd()};
         int64_t hsize = 0;
         for (int H : Hs) hsize = std::max(hsize, tiles_of(c, 0, kDeep, c->TO(H)) * H * P);
+        // two-level passes (kDeepNext) and one-level passes (kDeepLast) of
+        // one cycle use disjoint slots
+        c->hb_last_off = tiles_of(c, 0, kDeepNext, c->TO(c->H_fused2())) * c->H_fused2() * P;
+        hsize = std::max(hsize, c->hb_last_off +
+                                    tiles_of(c, 0, kDeepLast, c->TO(c->H_fused())) * c->H_fused() * P);
         if ((rc = dalloc(c, &c->hb[0], hsize)) || (rc = dalloc(c, &c->hb[1], hsize)))
             return fail(rc);
     }

@@ -91,6 +91,15 @@ struct LegArgsT {
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
     const InstState *st;     // per-instance early exit when st[j].done (may be null)
+    // Two-level up leg (level 0 only): with e2 != null the correction of
+    // level 1 is not read from e but computed in the tile as level 1's
+    // first-visit up leg: pre sweeps from zero on f1, prolongation of the
+    // level-2 correction e2, post sweeps.
+    const T *f1;             // level-1 right-hand side
+    const T *e2;             // level-2 correction (null: one-level pass)
+    const double *tab1;      // level-1 tables (FP64 and in T)
+    const T *tab1T;
+    const int64_t *c2slab_off; // [batch+1] slab offsets of level 2
     int64_t n0;              // slabs of instance 0 at this level (used when batch == 1)
     int batch;
     int tab_stride;
@@ -119,6 +128,7 @@ struct MixArgs {
     const int64_t *cslab_off;
     const int64_t *tile_off;
     const InstState *st;
+    const int64_t *c2slab_off; // unused (null)
     int64_t n0;
     int batch, tab_stride, halo, tile_out, pre, post, next;
     int up;                  // 1: residual, inner up leg and update before the rest

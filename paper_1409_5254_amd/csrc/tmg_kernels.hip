@@ -399,13 +399,13 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
 // Instance, tile and sizes of the work-group's tile.
 struct TileRef {
     int j;
-    int64_t t, off, N, coff, Nc;
+    int64_t t, off, N, coff, Nc, c2off, Nc2;   // levels l, l+1, l+2 of instance j
 };
 
 template <typename A>
 __device__ __forceinline__ TileRef tile_ref(const A &a)
 {
-    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2};
+    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2, 0, a.n0 / 4};
     if (a.batch > 1) {
         r.j = find_instance(a.tile_off, a.batch, r.t);
         r.t = (int64_t)blockIdx.x - a.tile_off[r.j];
@@ -414,6 +414,10 @@ __device__ __forceinline__ TileRef tile_ref(const A &a)
         if (a.cslab_off) {
             r.coff = a.cslab_off[r.j];
             r.Nc = a.cslab_off[r.j + 1] - r.coff;
+        }
+        if (a.c2slab_off) {
+            r.c2off = a.c2slab_off[r.j];
+            r.Nc2 = a.c2slab_off[r.j + 1] - r.c2off;
         }
     }
     return r;
@@ -515,23 +519,45 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
     // every load is issued before the early-exit test: data first, then the
     // state flag and the level tables
+    constexpr int SC2 = SC >= 2 ? SC / 2 : 1;  // level-2 slabs touched per thread
     T f[S][P], u[S][P], g[S][P], e[SC][P];
+    T f1[SC][P], e2[SC2][P];
+    // coarse slab of this thread's slabs (floor division; -1 is outside)
+    const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+    const int64_t c2m0 = SC >= 2 ? cm0 / 2 : (cm0 >> 1);
     load_chunk<P, S, BW, T>(a.f + tr.off * P, m0, tr.N, f);
     load_iterate<P, S, BW, T>(u, a.u_in, a.halo_in, tr, m0, li0, a.halo);
-    if (a.e) {
-        // coarse slab of this thread's slabs (floor division; -1 is outside)
-        const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+    if (a.e2) {
+        load_chunk<P, SC, BW, T>(a.f1 + tr.coff * P, cm0, tr.Nc, f1);
+        load_chunk<P, SC2, BW, T>(a.e2 + tr.c2off * P, c2m0, tr.Nc2, e2);
+    } else if (a.e) {
         load_chunk<P, SC, BW, T>(a.e + tr.coff * P, cm0, tr.Nc, e);
     }
     const int done = a.st ? a.st[tr.j].done : 0;
     Ops<P, T> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tabT + (int64_t)tr.j * a.tab_stride);
     if (done) return;
+    int phase = 0;
+    if (a.e2) {
+        // level 1's up leg on the tile's coarse slabs: its first slabs
+        // (pre + post - 1 of them) see a zero left neighbour and are wrong,
+        // which the level-0 halo absorbs
+        Ops<P, T> op1;
+        op1.load(a.tab1 + (int64_t)tr.j * a.tab_stride, a.tab1T + (int64_t)tr.j * a.tab_stride);
+        T g1[SC][P];
+        apply_G<P, SC, T>(g1, f1, op1);
+#pragma unroll
+        for (int s = 0; s < SC; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) e[s][k] = (T)0;
+        sweeps<P, SC, kLegWaves, T>(e, g1, op1, a.pre, xchg, phase);
+        prolong_add<P, SC, T>(e, e2, a.R, cm0);
+        sweeps<P, SC, kLegWaves, T>(e, g1, op1, a.post, xchg, phase);
+    }
     if (a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
     apply_G<P, S, T>(g, f, op);
-    int phase = 0;
     sweeps<P, S, kLegWaves, T>(u, g, op, a.pre, xchg, phase);
-    if (a.e) prolong_add<P, S, T>(u, e, a.R, m0);
+    if (a.e || a.e2) prolong_add<P, S, T>(u, e, a.R, m0);
     sweeps<P, S, kLegWaves, T>(u, g, op, a.post, xchg, phase);
     if (a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
     store_halo<P, S, T>(a.halo_out, u, li0, a.halo);

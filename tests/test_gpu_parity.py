@@ -215,12 +215,14 @@ def test_config1_end_to_end():
 def test_batched_uneven(schedule, gamma):
     """Several instances of different length and lambda in one handle,
     including one with a single level (N = n_coarse: the cycle is the exact
-    solve); each equals its own oracle solve."""
+    solve) and, with schedule 3, instances whose level 1 runs in the bottom
+    kernel (N = 16) next to ones whose level-1 up leg runs inside the
+    level-0 pass; each equals its own oracle solve."""
     rng = np.random.default_rng(5)
     p = 1
-    Ns = [2, 64, 1024, 4096, 512, 2048]
-    lams = [3.0, 0.5, 1.0, 2000.0, 7.0, 1e-3]
-    Ts = [1.0, 2.0, 10.0, 1.0, 5.0, 100.0]
+    Ns = [2, 64, 1024, 4096, 512, 2048, 16]
+    lams = [3.0, 0.5, 1.0, 2000.0, 7.0, 1e-3, 0.3]
+    Ts = [1.0, 2.0, 10.0, 1.0, 5.0, 100.0, 0.5]
     u0 = rng.uniform(-1, 1, len(Ns))
     fs = [rand(rng, n * (p + 1)) * 0.1 for n in Ns]
     s = B().Solver(Ns, Ts, lams, p=p, schedule=schedule, gamma=gamma)
