@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--mixed", type=int, default=1, help="include the N=2^24 mixed-precision comparison")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-log2n", type=int, default=15)
+    ap.add_argument("--cpu-log2n", type=int, default=21)
     ap.add_argument("--batch", type=int, default=0, help="instances for --config 3/4/5 (0: default)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one plain 512 MiB device copy (counter calibration)")
@@ -98,36 +98,63 @@ def config2_case(p, log2n, cycle, steps, warmup, precision=0):
 
 
 def fused_pass_roofline(p, ctx, reps):
-    """Average duration of the dominant kernel, the fused level-0 pass of a
-    cycle (tmg_op_fused: recomputed pre-sweeps, correction, post-sweeps, next
-    cycle's pre-sweeps, residual, restriction), timed with HIP events on the
-    stream it is launched on.  Algorithmic bytes per fine unknown: read u, f
-    (16 B) and the level-1 correction (4 B), write u (8 B) and the restricted
-    residual (4 B) = 32 B; one launch processes N*P unknowns."""
+    """Average duration of the dominant kernel, the fused level-0 pass that
+    every cycle after the first of an FP64 V-cycle solve runs (tmg_op_fused2:
+    level 1's up leg in the tiles, then at level 0 the recomputed pre-sweeps,
+    correction, post-sweeps, next cycle's pre-sweeps, residual, restriction),
+    timed with HIP events on the stream it is launched on.  Algorithmic bytes
+    per fine unknown: read u, f (16 B), level 1's right-hand side (4 B) and
+    level 2's correction (2 B), write u (8 B) and the restricted residual
+    (4 B) = 34 B; one launch processes N*P unknowns.  The solve runs the same
+    kernel in place (u_in = u_out, left halos from a per-tile buffer); the
+    timed launch writes a second array."""
     import torch
     s, f, u0, u = ctx
     N = s.n_slabs[0]
     P = p + 1
     ub = torch.empty_like(u)
     rc = torch.empty(N // 2 * P, dtype=torch.float64, device="cuda")
-    e = torch.zeros(N // 2 * P, dtype=torch.float64, device="cuda")
+    f1 = torch.zeros(N // 2 * P, dtype=torch.float64, device="cuda")
+    e2 = torch.zeros(N // 4 * P, dtype=torch.float64, device="cuda")
     st = torch.cuda.current_stream()
     for _ in range(3):
-        s.fused(f, u, e, ub, rc, fold_u0=u0)
+        s.fused2(f, u, f1, e2, ub, rc, fold_u0=u0)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
-        s.fused(f, u, e, ub, rc, fold_u0=u0)
+        s.fused2(f, u, f1, e2, ub, rc, fold_u0=u0)
     e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    bytes_alg = 32.0 * N * P
+    bytes_alg = 34.0 * N * P
     gbs = bytes_alg / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"k_leg<P={P}> fused level-0 pass, N=2^{N.bit_length() - 1}",
+                kernel=f"k_leg<P={P}> two-level fused level-0 pass, N=2^{N.bit_length() - 1}",
                 avg_us=round(ms * 1e3, 2), bytes_per_launch=bytes_alg)
+
+
+COUNTERS = os.path.join(HERE, "profiles", "k_leg_fused2_p3_n2e22_hbm_counters.md")
+KERNEL_SRC = os.path.join(HERE, "paper_1409_5254_amd", "csrc", "tmg_kernels.hip")
+
+
+def measured_traffic(p, log2n):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary (p = 3, N = 2^22 only), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    if (p, log2n) != (3, 22) or not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    for line in open(COUNTERS):
+        if ":" in line:
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(p, log2n):
@@ -299,6 +326,7 @@ def main():
         return
     head, ctx = config2_case(a.p, a.log2n, a.cycle, a.steps, a.warmup)
     roof = fused_pass_roofline(a.p, ctx, a.kernel_reps)
+    roof["traffic"] = measured_traffic(a.p, a.log2n)
     del ctx
     torch.cuda.empty_cache()
     sweep = []

@@ -27,7 +27,8 @@ MAX_DEGREE = 3
 # every symbol the header declares
 SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",
            "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
-           "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_coarse_solve",
+           "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
+           "tmg_op_coarse_solve",
            "tmg_op_residual_norm"]
 
 
@@ -86,6 +87,7 @@ def lib():
             "tmg_op_down": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_up": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_fused": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_op_fused2": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_coarse_solve": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
             "tmg_op_residual_norm": (_i, [_vp, _i, _vp, _vp, _vp, P(_d), _vp]),
         }
@@ -222,6 +224,11 @@ class Solver:
         r = lib().tmg_op_fused(self._h, int(trans), _ptr(f), _ptr(fold_u0), _ptr(u_in), _ptr(e),
                                _ptr(u_out), _ptr(rc), _stream())
         self._check(r, "tmg_op_fused")
+
+    def fused2(self, f, u_in, f1, e2, u_out, rc, trans=False, fold_u0=None):
+        r = lib().tmg_op_fused2(self._h, int(trans), _ptr(f), _ptr(fold_u0), _ptr(u_in), _ptr(f1),
+                                _ptr(e2), _ptr(u_out), _ptr(rc), _stream())
+        self._check(r, "tmg_op_fused2")
 
     def coarse_solve(self, level, r, e, trans=False):
         rc = lib().tmg_op_coarse_solve(self._h, level, int(trans), _ptr(r), _ptr(e), _stream())

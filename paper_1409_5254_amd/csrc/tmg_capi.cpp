@@ -43,7 +43,8 @@ namespace {
 
 // kDeep: streaming levels (level < lb_j); kDeepNext: the next level streams
 // too (level + 1 < lb_j); kDeepLast: the next level is in the bottom kernel.
-enum TileKind { kDeep = 0, kAll = 1, kHasNext = 2, kDeepNext = 3, kDeepLast = 4 };
+// kHasNext2: instances with two more levels (level-wise two-level pass).
+enum TileKind { kDeep = 0, kAll = 1, kHasNext = 2, kDeepNext = 3, kDeepLast = 4, kHasNext2 = 5 };
 
 struct TileList {
     int64_t ntiles = 0;
@@ -161,6 +162,7 @@ bool participates(const tmg_ctx *c, int j, int level, int kind)
     if (level >= c->L[j]) return false;
     if (kind == kDeep) return level < c->lb[j];       // streaming kernels in the cycle
     if (kind == kHasNext) return level + 1 < c->L[j]; // level-wise entry points
+    if (kind == kHasNext2) return level + 2 < c->L[j];
     if (kind == kDeepNext) return level + 1 < c->lb[j];
     if (kind == kDeepLast) return level < c->lb[j] && level + 1 >= c->lb[j];
     return true;
@@ -1015,6 +1017,35 @@ int tmg_op_fused(tmg_handle c, int trans, const double *f, const double *fold_u0
     a.u0 = fold_u0;
     a.u_in = u_in;
     a.e = e;
+    a.u_out = u_out;
+    a.rc = rcout;
+    a.pre = c->opt.nu1;
+    a.post = c->opt.nu2;
+    a.next = c->opt.nu1;
+    HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+int tmg_op_fused2(tmg_handle c, int trans, const double *f, const double *fold_u0,
+                  const double *u_in, const double *f1, const double *e2, double *u_out,
+                  double *rcout, tmg_stream stream)
+{
+    if (!c || !f || !u_in || !f1 || !e2 || !u_out || !rcout || c->Lmax < 3 || (fold_u0 && trans))
+        return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const int H = c->H_fused2();
+    TileList *tl;
+    int rc = get_tiles(c, 0, kHasNext2, c->TO(H), s, &tl);
+    if (rc) return rc;
+    LegArgs a = leg_args(c, 0, trans != 0, tl, H);
+    a.f = f;
+    a.u0 = fold_u0;
+    a.u_in = u_in;
+    a.f1 = f1;
+    a.e2 = e2;
+    a.tab1 = tab_of(c, 1, trans != 0);
+    a.tab1T = a.tab1;
+    a.c2slab_off = c->slab_off_d[2];
     a.u_out = u_out;
     a.rc = rcout;
     a.pre = c->opt.nu1;

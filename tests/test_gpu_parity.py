@@ -358,3 +358,32 @@ def test_fused_level0_pass(p, trans):
             fold_u0=None if trans else dev([u0]))
     assert relerr(host(d_out), post) <= TOL
     assert relerr(host(d_rc), ref_rc) <= TOL
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("trans", [False, True])
+def test_fused2_level0_pass(p, trans):
+    """tmg_op_fused2: level 1's correction computed in the tiles as level
+    1's first-visit up leg (nu1 sweeps from zero on f1, correction with the
+    level-2 e2, nu2 sweeps at tau_1 = 2 tau), then the pass of tmg_op_fused."""
+    rng = np.random.default_rng(80 + p)
+    N, z = 4096, 0.02
+    s = B().Solver([N], [z * N], [1.0], p=p)
+    P = p + 1
+    f, u = rand(rng, N * P), rand(rng, N * P)
+    f1, e2 = rand(rng, N // 2 * P), rand(rng, N // 4 * P)
+    u0 = None if trans else 0.3
+    ff = f if trans else core.fold(p, u0, f)
+    e1 = core.sweeps(p, 2 * z, 1.0, f1, np.zeros(N // 2 * P), 2, trans=trans)
+    e1 = core.sweeps(p, 2 * z, 1.0, f1, core.prolong_add(p, e2, e1), 2, trans=trans)
+    post = core.sweeps(p, z, 1.0, ff, core.prolong_add(p, e1, core.sweeps(p, z, 1.0, ff, u, 2,
+                                                                          trans=trans)), 2,
+                       trans=trans)
+    nxt = core.sweeps(p, z, 1.0, ff, post, 2, trans=trans)
+    ref_rc = core.restrict(p, core.residual(p, z, 1.0, ff, nxt, trans=trans))
+    d_out = torch.empty(N * P, dtype=torch.float64, device=DEV)
+    d_rc = torch.empty(N // 2 * P, dtype=torch.float64, device=DEV)
+    s.fused2(dev(f), dev(u), dev(f1), dev(e2), d_out, d_rc, trans=trans,
+             fold_u0=None if trans else dev([u0]))
+    assert relerr(host(d_out), post) <= TOL
+    assert relerr(host(d_rc), ref_rc) <= TOL
