@@ -44,7 +44,13 @@ namespace {
 // kDeep: streaming levels (level < lb_j); kDeepNext: the next level streams
 // too (level + 1 < lb_j); kDeepLast: the next level is in the bottom kernel.
 // kHasNext2: instances with two more levels (level-wise two-level pass).
-enum TileKind { kDeep = 0, kAll = 1, kHasNext = 2, kDeepNext = 3, kDeepLast = 4, kHasNext2 = 5 };
+// V-cycles group an instance's streaming levels g, g+1, ... (g = 1 or 2)
+// into pairs run by two-level launches: kPair<g> marks the first level of a
+// pair, kSingle<g> a last level left without a partner.
+enum TileKind {
+    kDeep = 0, kAll = 1, kHasNext = 2, kDeepNext = 3, kDeepLast = 4, kHasNext2 = 5,
+    kPair1 = 6, kSingle1 = 7, kPair2 = 8, kSingle2 = 9
+};
 
 struct TileList {
     int64_t ntiles = 0;
@@ -120,6 +126,16 @@ struct tmg_ctx {
     int H_down() const { return rs(opt.nu1 + 1); }
     int H_up() const { return rs(opt.nu1 + opt.nu2); }
     int H_fused() const { return rs(2 * opt.nu1 + opt.nu2 + 1); }
+    // two-level launches of V-cycle first visits (levels l, l+1): the down
+    // pair loses nu1 slabs at l and nu1 + 1 coarse ones at l+1 and restricts
+    // level-(l+1) pairs (a multiple of 4); the up pair loses nu1 + nu2 - 1
+    // coarse slabs at l+1, then nu2 at l
+    int H_dpair() const
+    {
+        const int q = S < 4 ? 4 : S;
+        return ((3 * opt.nu1 + 2 + q - 1) / q) * q;
+    }
+    int H_upair() const { return rs(2 * (opt.nu1 + opt.nu2) + opt.nu2); }
     // fused pass that also runs level 1's up leg: level 1's first nu1 + nu2
     // coarse slabs are wrong, 2 (nu1 + nu2) fine slabs, then nu2 + nu1 + 1
     int H_fused2() const { return rs(3 * (opt.nu1 + opt.nu2) + 1); }
@@ -163,6 +179,11 @@ bool participates(const tmg_ctx *c, int j, int level, int kind)
     if (kind == kDeep) return level < c->lb[j];       // streaming kernels in the cycle
     if (kind == kHasNext) return level + 1 < c->L[j]; // level-wise entry points
     if (kind == kHasNext2) return level + 2 < c->L[j];
+    if (kind >= kPair1) {
+        const int g = kind <= kSingle1 ? 1 : 2;
+        if (level < g || ((level - g) & 1)) return false;
+        return (kind == kPair1 || kind == kPair2) ? level + 1 < c->lb[j] : level + 1 == c->lb[j];
+    }
     if (kind == kDeepNext) return level + 1 < c->lb[j];
     if (kind == kDeepLast) return level < c->lb[j] && level + 1 >= c->lb[j];
     return true;
@@ -290,12 +311,14 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
 // Down leg (streaming instances): nu1 sweeps from the current iterate (zero
 // on a first visit), residual, restriction into the next level.
 template <typename T>
-int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
+int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s,
+                 int kind = kDeep)
 {
     TileList *tl;
     const int H = c->H_down();
-    int rc = get_tiles(c, level, kDeep, c->TO(H), s, &tl);
+    int rc = get_tiles(c, level, kind, c->TO(H), s, &tl);
     if (rc) return rc;
+    if (tl->ntiles == 0) return TMG_OK;
     LevelStore<T> &L = store<T>(c);
     LegArgsT<T> a = leg_args<T>(c, level, io.trans, tl, H);
     a.f = level == 0 ? reinterpret_cast<const T *>(io.f) : L.f[level];
@@ -313,12 +336,14 @@ int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_
 // A first visit writes the current buffer (nothing is read from it); a
 // repeated visit (W-cycle) writes the other one and makes it current.
 template <typename T>
-int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s)
+int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s,
+               int kind = kDeep)
 {
     TileList *tl;
     const int H = c->H_up();
-    int rc = get_tiles(c, level, kDeep, c->TO(H), s, &tl);
+    int rc = get_tiles(c, level, kind, c->TO(H), s, &tl);
     if (rc) return rc;
+    if (tl->ntiles == 0) return TMG_OK;
     LevelStore<T> &L = store<T>(c);
     LegArgsT<T> a = leg_args<T>(c, level, io.trans, tl, H);
     const int cur = c->cur[level];
@@ -373,6 +398,62 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
     return TMG_OK;
 }
 
+// Two-level launches of a V-cycle (first visits from zero) at levels l, l+1.
+template <typename T>
+int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, hipStream_t s)
+{
+    TileList *tl;
+    const int H = down ? c->H_dpair() : c->H_upair();
+    int rc = get_tiles(c, level, kind, c->TO(H), s, &tl);
+    if (rc) return rc;
+    if (tl->ntiles == 0) return TMG_OK;
+    LevelStore<T> &L = store<T>(c);
+    LegArgsT<T> a = leg_args<T>(c, level, io.trans, tl, H);
+    a.f = L.f[level];
+    a.tab1 = tab_of(c, level + 1, io.trans);
+    a.tab1T = tabT_of<T>(c, level + 1, io.trans);
+    a.c2slab_off = c->slab_off_d[level + 2];
+    a.st = io.use_state ? c->st : nullptr;
+    a.pre = c->opt.nu1;
+    if (down) {
+        a.rc = L.f[level + 1];
+        a.f2 = L.f[level + 2];
+    } else {
+        a.f1 = L.f[level + 1];
+        a.e2 = L.x(level + 2, 0);
+        a.u_out = L.x(level, 0);
+        a.post = c->opt.nu2;
+    }
+    HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+// Levels >= 1 of a V-cycle (every visit a first visit from zero): all down
+// legs from the top, the bottom kernels, all up legs from the bottom, with
+// consecutive streaming levels paired into two-level launches.  Up legs start
+// at level up_first (2 when level 1's up leg runs inside the level-0 pass).
+template <typename T>
+int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int up_first, hipStream_t s)
+{
+    int rc;
+    LevelStore<T> &L = store<T>(c);
+    c->cur.assign(c->Lmax + 1, 0);
+    for (int l = 1; l < c->Lmax; ++l) {
+        if ((rc = enqueue_pair<T>(c, io, l, true, kPair1, s)) ||
+            (rc = enqueue_down<T>(c, io, l, true, s, kSingle1)))
+            return rc;
+    }
+    for (int l = 1; l < c->Lmax; ++l)
+        if ((rc = enqueue_bottom<T>(c, io, l, nullptr, L.x(l, 0), s))) return rc;
+    const int kp = up_first == 1 ? kPair1 : kPair2, ks = up_first == 1 ? kSingle1 : kSingle2;
+    for (int l = c->Lmax - 1; l >= up_first; --l) {
+        if ((rc = enqueue_pair<T>(c, io, l, false, kp, s)) ||
+            (rc = enqueue_up<T>(c, io, l, true, s, ks)))
+            return rc;
+    }
+    return TMG_OK;
+}
+
 // Level-0 part of a cycle of the FP32-inner defect correction (streaming
 // instances): see k_mix.
 int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
@@ -420,7 +501,9 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.rc = c->s.f[1];
         HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
     }
-    if ((rc = enqueue_coarse_visits<float>(c, io, 1, s))) return rc;
+    if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<float>(c, io, 1, s)
+                                : enqueue_coarse_visits<float>(c, io, 1, s)))
+        return rc;
     const int H = solve ? c->H_mix() : c->H_mixv();
     if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
     MixArgs a = margs(H, tl);
@@ -470,7 +553,9 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         // level 1's up leg inside their level-0 pass; the others
         // (kDeepLast) take level 1's correction from the bottom kernel
         const bool fuse2 = solve && c->fuse_up1() && c->deep_n[1] > 0;
-        if ((rc = enqueue_coarse_visits<double>(c, io, 1, s, fuse2))) return rc;
+        if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<double>(c, io, fuse2 ? 2 : 1, s)
+                                    : enqueue_coarse_visits<double>(c, io, 1, s, fuse2)))
+            return rc;
         // fused level-0 pass(es)
         for (int pass = fuse2 ? 0 : 1; pass < 2; ++pass) {
             const bool two = pass == 0;
@@ -527,6 +612,14 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
     if ((rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_fused2()), s, &tl)) ||
         (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_fused()), s, &tl)))
         return rc;
+    for (int l = 1; l < c->Lmax; ++l)
+        if ((rc = get_tiles(c, l, kPair1, c->TO(c->H_dpair()), s, &tl)) ||
+            (rc = get_tiles(c, l, kSingle1, c->TO(c->H_down()), s, &tl)) ||
+            (rc = get_tiles(c, l, kPair1, c->TO(c->H_upair()), s, &tl)) ||
+            (rc = get_tiles(c, l, kSingle1, c->TO(c->H_up()), s, &tl)) ||
+            (rc = get_tiles(c, l, kPair2, c->TO(c->H_upair()), s, &tl)) ||
+            (rc = get_tiles(c, l, kSingle2, c->TO(c->H_up()), s, &tl)))
+            return rc;
     return TMG_OK;
 }
 

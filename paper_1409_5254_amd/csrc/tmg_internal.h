@@ -91,15 +91,18 @@ struct LegArgsT {
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
     const InstState *st;     // per-instance early exit when st[j].done (may be null)
-    // Two-level up leg (level 0 only): with e2 != null the correction of
-    // level 1 is not read from e but computed in the tile as level 1's
-    // first-visit up leg: pre sweeps from zero on f1, prolongation of the
-    // level-2 correction e2, post sweeps.
-    const T *f1;             // level-1 right-hand side
-    const T *e2;             // level-2 correction (null: one-level pass)
-    const double *tab1;      // level-1 tables (FP64 and in T)
+    // Two-level launches (levels l and l+1 of a V-cycle's first visits).
+    // Up: with e2 != null the correction of level l+1 is not read from e but
+    // computed in the tile as level l+1's up leg: pre sweeps from zero on
+    // f1, prolongation of the level-(l+2) correction e2, post sweeps.
+    // Down: with rc and f2 != null, level l+1's down leg (next sweeps from
+    // zero on the restricted residual, residual) follows, restricted into f2.
+    const T *f1;             // level-(l+1) right-hand side
+    const T *e2;             // level-(l+2) correction (null: one-level up leg)
+    T *f2;                   // level-(l+2) right-hand side (null: one-level down leg)
+    const double *tab1;      // level-(l+1) tables (FP64 and in T)
     const T *tab1T;
-    const int64_t *c2slab_off; // [batch+1] slab offsets of level 2
+    const int64_t *c2slab_off; // [batch+1] slab offsets of level l+2
     int64_t n0;              // slabs of instance 0 at this level (used when batch == 1)
     int batch;
     int tab_stride;

@@ -357,6 +357,23 @@ __device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? 
 
 // Restrict the residual r (rounded to T) of this thread's slabs and store
 // the coarse slabs of output pairs: rc_m = R_1 r_{2m} + R_2 r_{2m+1}.
+template <int P, int S, typename T>
+__device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const T *__restrict__ R,
+                                               T (&rc)[S / 2][P])
+{
+    const T *R1T = R, *R2T = R + P * P;
+#pragma unroll
+    for (int i = 0; i < S / 2; ++i)
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T s1 = 0;
+#pragma unroll
+            for (int l = 0; l < P; ++l)
+                s1 += R1T[l * P + k] * (T)r[2 * i][l] + R2T[l * P + k] * (T)r[2 * i + 1][l];
+            rc[i][k] = s1;
+        }
+}
+
 template <int P, int S, bool BW, typename T>
 __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T *__restrict__ R,
                                                T *__restrict__ rc_base, int64_t m0, int64_t N,
@@ -365,16 +382,7 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
     const T *R1T = R, *R2T = R + P * P;
     if constexpr (S >= 2) {
         T rc[S / 2][P];
-#pragma unroll
-        for (int i = 0; i < S / 2; ++i)
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                T s1 = 0;
-#pragma unroll
-                for (int l = 0; l < P; ++l)
-                    s1 += R1T[l * P + k] * (T)r[2 * i][l] + R2T[l * P + k] * (T)r[2 * i + 1][l];
-                rc[i][k] = s1;
-            }
+        restrict_pairs<P, S, T>(r, R, rc);
         store_chunk<P, S / 2, BW, T>(rc_base, m0 / 2, Nc, rc, li0 / 2, halo / 2);
     } else {
         // the first slab of each pair takes its partner's residual from the next lane
@@ -538,12 +546,13 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tabT + (int64_t)tr.j * a.tab_stride);
     if (done) return;
     int phase = 0;
-    if (a.e2) {
-        // level 1's up leg on the tile's coarse slabs: its first slabs
-        // (pre + post - 1 of them) see a zero left neighbour and are wrong,
-        // which the level-0 halo absorbs
-        Ops<P, T> op1;
+    Ops<P, T> op1;   // the next level (two-level launches)
+    if (a.e2 || a.f2)
         op1.load(a.tab1 + (int64_t)tr.j * a.tab_stride, a.tab1T + (int64_t)tr.j * a.tab_stride);
+    if (a.e2) {
+        // the next level's up leg on the tile's coarse slabs: its first slabs
+        // (pre + post - 1 of them) see a zero left neighbour and are wrong,
+        // which the halo absorbs
         T g1[SC][P];
         apply_G<P, SC, T>(g1, f1, op1);
 #pragma unroll
@@ -567,9 +576,28 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
         norm_partial<P, S, kLegWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
     }
     if (a.rc) {
+        static_assert(S >= 2, "streaming tiles hold whole coarse slabs per thread");
         sweeps<P, S, kLegWaves, T>(u, g, op, a.next, xchg, phase);
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
-        restrict_store<P, S, BW, T>(r, a.R, a.rc + tr.coff * P, m0, tr.N, tr.Nc, li0, a.halo);
+        T rc1[SC][P];
+        restrict_pairs<P, S, T>(r, a.R, rc1);
+        store_chunk<P, SC, BW, T>(a.rc + tr.coff * P, cm0, tr.Nc, rc1, li0 / 2, a.halo / 2);
+        if (a.f2) {
+            // the next level's down leg of a first visit on the restricted
+            // residual: sweeps from zero, residual, restriction (its first
+            // coarse slabs are wrong; the halo absorbs them)
+            T g1[SC][P], x1[SC][P];
+            apply_G<P, SC, T>(g1, rc1, op1);
+#pragma unroll
+            for (int s = 0; s < SC; ++s)
+#pragma unroll
+                for (int k = 0; k < P; ++k) x1[s][k] = (T)0;
+            sweeps<P, SC, kLegWaves, T>(x1, g1, op1, a.pre, xchg, phase);
+            double r1[SC][P];
+            residual<P, SC, kLegWaves>(r1, x1, rc1, op1, xchg, phase);
+            restrict_store<P, SC, BW, T>(r1, a.R, a.f2 + tr.c2off * P, cm0, tr.Nc, tr.Nc2, li0 / 2,
+                                         a.halo / 2);
+        }
     }
 }
 
