@@ -209,44 +209,136 @@ __device__ __forceinline__ void store_chunk(T *__restrict__ base, int64_t m0, in
     }
 }
 
-// Level operator tables held in registers (uniform across the work-group).
-// Smoothing runs in T (tables rounded to T); the residual always runs in
-// FP64 arithmetic (A, v, c from the FP64 table).
+// The pointer as a value the compiler cannot see through: loads through it
+// are issued where they are written and not merged with, or hoisted to, the
+// same loads elsewhere.  The level tables are uniform, so they live in scalar
+// registers; loading each group where it is used (from the scalar cache)
+// keeps a few dozen of them live instead of all of them, which would spill
+// into vector-register lanes.
+// The tables are read-only for the whole launch, so they are read through
+// the constant address space (scalar loads).
+template <typename X>
+using ConstPtr = const __attribute__((address_space(4))) X *;
+
+template <typename X>
+__device__ __forceinline__ ConstPtr<X> opaque(const X *p)
+{
+    // uniform by construction (one instance per work-group); say so
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    ConstPtr<X> q = (ConstPtr<X>)(((uint64_t)hi << 32) | lo);
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
+// Groups of a level's operator table.  Smoothing runs in T (tables rounded
+// to T); the residual always runs in FP64 arithmetic (A, v, c from the FP64
+// table).
+template <int P, typename T>
+struct SweepTab {
+    T h[P], c[P], omc;
+};
+template <int P>
+struct ResidTab {
+    double A[P * P], v[P], cd[P];
+};
+template <int P, typename T>
+struct GTab {
+    T G[P * P];
+};
+
+// Level tables read where they are used (streaming kernels: the tables of
+// two levels and the transfer matrices would not fit the scalar registers).
+template <int P, typename T = double>
+struct LazyOps {
+    const double *tab;
+    const T *tabT;
+    __device__ __forceinline__ void load(const double *t, const T *tT)
+    {
+        tab = t;
+        tabT = tT;
+    }
+    __device__ __forceinline__ SweepTab<P, T> sw() const
+    {
+        constexpr TabLayout L(P);
+        const auto q = opaque(tabT);
+        SweepTab<P, T> r;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            r.h[k] = q[L.H() + k];
+            r.c[k] = q[L.C() + k];
+        }
+        r.omc = q[L.OMC()];
+        return r;
+    }
+    __device__ __forceinline__ ResidTab<P> res() const
+    {
+        constexpr TabLayout L(P);
+        const auto q = opaque(tab);
+        ResidTab<P> r;
+#pragma unroll
+        for (int i = 0; i < P * P; ++i) r.A[i] = q[L.A() + i];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            r.v[k] = q[L.V() + k];
+            r.cd[k] = q[L.C() + k];
+        }
+        return r;
+    }
+    __device__ __forceinline__ GTab<P, T> gm() const
+    {
+        constexpr TabLayout L(P);
+        const auto q = opaque(tabT);
+        GTab<P, T> r;
+#pragma unroll
+        for (int i = 0; i < P * P; ++i) r.G[i] = q[L.G() + i];
+        return r;
+    }
+};
+
+// Level tables held in registers (the bottom kernel: tables in LDS, one
+// level at a time).
 template <int P, typename T = double>
 struct Ops {
-    T G[P * P], h[P], c[P], omc;
-    double A[P * P], v[P], cd[P];
+    SweepTab<P, T> s;
+    ResidTab<P> r;
+    GTab<P, T> g;
     __device__ __forceinline__ void load(const double *__restrict__ tab, const T *__restrict__ tabT)
     {
         constexpr TabLayout L(P);
 #pragma unroll
         for (int i = 0; i < P * P; ++i) {
-            A[i] = tab[L.A() + i];
-            G[i] = tabT[L.G() + i];
+            r.A[i] = tab[L.A() + i];
+            g.G[i] = tabT[L.G() + i];
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            h[k] = tabT[L.H() + k];
-            c[k] = tabT[L.C() + k];
-            v[k] = tab[L.V() + k];
-            cd[k] = tab[L.C() + k];
+            s.h[k] = tabT[L.H() + k];
+            s.c[k] = tabT[L.C() + k];
+            r.v[k] = tab[L.V() + k];
+            r.cd[k] = tab[L.C() + k];
         }
-        omc = tabT[L.OMC()];
+        s.omc = tabT[L.OMC()];
     }
     __device__ __forceinline__ void load(const double *__restrict__ tab) { load(tab, tab); }
+    __device__ __forceinline__ const SweepTab<P, T> &sw() const { return s; }
+    __device__ __forceinline__ const ResidTab<P> &res() const { return r; }
+    __device__ __forceinline__ const GTab<P, T> &gm() const { return g; }
 };
 
 // Fold the initial value into logical slab 0 (forward system, level 0):
 // f_1 += u0 v.
-template <int P, int S, typename T>
-__device__ __forceinline__ void fold_u0(T (&f)[S][P], int64_t m0, double u0, const Ops<P, T> &op)
+template <int P, int S, typename T, class OP>
+__device__ __forceinline__ void fold_u0(T (&f)[S][P], int64_t m0, double u0, const OP &op)
 {
+    const auto &t = op.res();
     // branch-free select keeps f in registers (no dynamic indexing)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double a = (m0 + s == 0) ? u0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) f[s][k] += (T)(a * op.v[k]);
+        for (int k = 0; k < P; ++k) f[s][k] += (T)(a * t.v[k]);
     }
 }
 
@@ -254,17 +346,19 @@ __device__ __forceinline__ void fold_u0(T (&f)[S][P], int64_t m0, double u0, con
 //   u_n <- (1 - omega) u_n + omega A^{-1} f_n + omega A^{-1} v w_{n-1},
 // the same update as u + omega D^{-1} (f - L u), with g = omega A^{-1} f
 // precomputed.
-template <int P, int S, int NW, typename T>
-__device__ __forceinline__ void sweeps(T (&u)[S][P], const T (&g)[S][P], const Ops<P, T> &op,
+template <int P, int S, int NW, typename T, class OP>
+__device__ __forceinline__ void sweeps(T (&u)[S][P], const T (&g)[S][P], const OP &op,
                                        int nsweep, double (*xchg)[NW], int &phase)
 {
+    if (nsweep <= 0) return;
+    const auto &tb = op.sw();
     for (int sw = 0; sw < nsweep; ++sw) {
         T w[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             T t = 0;
 #pragma unroll
-            for (int k = 0; k < P; ++k) t += op.c[k] * u[s][k];
+            for (int k = 0; k < P; ++k) t += tb.c[k] * u[s][k];
             w[s] = t;
         }
         const T wl = left_value<NW, T>(w[S - 1], xchg, phase);
@@ -272,23 +366,24 @@ __device__ __forceinline__ void sweeps(T (&u)[S][P], const T (&g)[S][P], const O
         for (int s = 0; s < S; ++s) {
             const T wn = s == 0 ? wl : w[s - 1];
 #pragma unroll
-            for (int k = 0; k < P; ++k) u[s][k] = op.omc * u[s][k] + g[s][k] + op.h[k] * wn;
+            for (int k = 0; k < P; ++k) u[s][k] = tb.omc * u[s][k] + g[s][k] + tb.h[k] * wn;
         }
     }
 }
 
 // r_n = f_n + v w_{n-1} - A u_n in FP64 arithmetic (operands of type TU, TF).
-template <int P, int S, int NW, typename TU, typename TF, typename T>
+template <int P, int S, int NW, typename TU, typename TF, class OP>
 __device__ __forceinline__ void residual(double (&r)[S][P], const TU (&u)[S][P],
-                                         const TF (&f)[S][P], const Ops<P, T> &op,
+                                         const TF (&f)[S][P], const OP &op,
                                          double (*xchg)[NW], int &phase)
 {
+    const auto &tb = op.res();
     double w[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) t += op.cd[k] * (double)u[s][k];
+        for (int k = 0; k < P; ++k) t += tb.cd[k] * (double)u[s][k];
         w[s] = t;
     }
     const double wl = left_value<NW, double>(w[S - 1], xchg, phase);
@@ -297,24 +392,25 @@ __device__ __forceinline__ void residual(double (&r)[S][P], const TU (&u)[S][P],
         const double wn = s == 0 ? wl : w[s - 1];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            double t = (double)f[s][k] + op.v[k] * wn;
+            double t = (double)f[s][k] + tb.v[k] * wn;
 #pragma unroll
-            for (int l = 0; l < P; ++l) t -= op.A[k * P + l] * (double)u[s][l];
+            for (int l = 0; l < P; ++l) t -= tb.A[k * P + l] * (double)u[s][l];
             r[s][k] = t;
         }
     }
 }
 
-template <int P, int S, typename T>
-__device__ __forceinline__ void apply_G(T (&g)[S][P], const T (&f)[S][P], const Ops<P, T> &op)
+template <int P, int S, typename T, class OP>
+__device__ __forceinline__ void apply_G(T (&g)[S][P], const T (&f)[S][P], const OP &op)
 {
+    const auto &tb = op.gm();
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             T t = 0;
 #pragma unroll
-            for (int l = 0; l < P; ++l) t += op.G[k * P + l] * f[s][l];
+            for (int l = 0; l < P; ++l) t += tb.G[k * P + l] * f[s][l];
             g[s][k] = t;
         }
 }
@@ -325,7 +421,8 @@ template <int P, int S, typename T>
 __device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? S / 2 : 1][P],
                                             const T *__restrict__ R, int64_t m0)
 {
-    const T *R1T = R, *R2T = R + P * P;
+    const auto R1T = opaque(R);
+    const auto R2T = R1T + P * P;
     if constexpr (S >= 2) {
 #pragma unroll
         for (int i = 0; i < S / 2; ++i)
@@ -361,7 +458,8 @@ template <int P, int S, typename T>
 __device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const T *__restrict__ R,
                                                T (&rc)[S / 2][P])
 {
-    const T *R1T = R, *R2T = R + P * P;
+    const auto R1T = opaque(R);
+    const auto R2T = R1T + P * P;
 #pragma unroll
     for (int i = 0; i < S / 2; ++i)
 #pragma unroll
@@ -379,7 +477,8 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
                                                T *__restrict__ rc_base, int64_t m0, int64_t N,
                                                int64_t Nc, int li0, int halo)
 {
-    const T *R1T = R, *R2T = R + P * P;
+    const auto R1T = opaque(R);
+    const auto R2T = R1T + P * P;
     if constexpr (S >= 2) {
         T rc[S / 2][P];
         restrict_pairs<P, S, T>(r, R, rc);
@@ -542,13 +641,12 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
         load_chunk<P, SC, BW, T>(a.e + tr.coff * P, cm0, tr.Nc, e);
     }
     const int done = a.st ? a.st[tr.j].done : 0;
-    Ops<P, T> op;
+    LazyOps<P, T> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tabT + (int64_t)tr.j * a.tab_stride);
     if (done) return;
     int phase = 0;
-    Ops<P, T> op1;   // the next level (two-level launches)
-    if (a.e2 || a.f2)
-        op1.load(a.tab1 + (int64_t)tr.j * a.tab_stride, a.tab1T + (int64_t)tr.j * a.tab_stride);
+    LazyOps<P, T> op1;   // the next level (two-level launches)
+    op1.load(a.tab1 + (int64_t)tr.j * a.tab_stride, a.tab1T + (int64_t)tr.j * a.tab_stride);
     if (a.e2) {
         // the next level's up leg on the tile's coarse slabs: its first slabs
         // (pre + post - 1 of them) see a zero left neighbour and are wrong,
@@ -628,18 +726,10 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
         load_chunk<P, SC, BW, float>(a.e + tr.coff * P, cm0, tr.Nc, e);
     }
     const int done = a.st ? a.st[tr.j].done : 0;
-    Ops<P, float> op;
+    LazyOps<P, float> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tab32 + (int64_t)tr.j * a.tab_stride);
     if (done) return;
-    if (a.u0) {
-        // fold in FP64
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const double w = (m0 + s == 0) ? a.u0[tr.j] : 0.0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) f[s][k] += w * op.v[k];
-        }
-    }
+    if (a.u0) fold_u0<P, S, double>(f, m0, a.u0[tr.j], op);   // in FP64
     int phase = 0;
     float rf[S][P], g[S][P], ei[S][P];
     if (a.up) {
