@@ -232,6 +232,21 @@ __device__ __forceinline__ ConstPtr<X> opaque(const X *p)
     return q;
 }
 
+// N entries of a read-only table, stride `stride`, loaded at the point of use.
+template <int N, typename X>
+struct Vals {
+    X v[N];
+};
+template <int N, int STRIDE = 1, typename X>
+__device__ __forceinline__ Vals<N, X> load_vals(const X *p, int off)
+{
+    const auto q = opaque(p);
+    Vals<N, X> r;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.v[i] = q[off + i * STRIDE];
+    return r;
+}
+
 // Groups of a level's operator table.  Smoothing runs in T (tables rounded
 // to T); the residual always runs in FP64 arithmetic (A, v, c from the FP64
 // table).
@@ -295,6 +310,18 @@ struct LazyOps {
         for (int i = 0; i < P * P; ++i) r.G[i] = q[L.G() + i];
         return r;
     }
+    // single rows, for steps that use one row at a time
+    __device__ __forceinline__ Vals<P, T> g_row(int k) const
+    {
+        return load_vals<P>(tabT, TabLayout(P).G() + k * P);
+    }
+    __device__ __forceinline__ Vals<P, double> a_row(int k) const
+    {
+        return load_vals<P>(tab, TabLayout(P).A() + k * P);
+    }
+    __device__ __forceinline__ Vals<P, double> cd() const { return load_vals<P>(tab, TabLayout(P).C()); }
+    __device__ __forceinline__ Vals<P, double> v() const { return load_vals<P>(tab, TabLayout(P).V()); }
+    static constexpr bool kRows = true;
 };
 
 // Level tables held in registers (the bottom kernel: tables in LDS, one
@@ -325,6 +352,7 @@ struct Ops {
     __device__ __forceinline__ const SweepTab<P, T> &sw() const { return s; }
     __device__ __forceinline__ const ResidTab<P> &res() const { return r; }
     __device__ __forceinline__ const GTab<P, T> &gm() const { return g; }
+    static constexpr bool kRows = false;
 };
 
 // Fold the initial value into logical slab 0 (forward system, level 0):
@@ -332,13 +360,21 @@ struct Ops {
 template <int P, int S, typename T, class OP>
 __device__ __forceinline__ void fold_u0(T (&f)[S][P], int64_t m0, double u0, const OP &op)
 {
-    const auto &t = op.res();
+    double v[P];
+    if constexpr (OP::kRows) {
+        const auto t = op.v();
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = t.v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = op.res().v[k];
+    }
     // branch-free select keeps f in registers (no dynamic indexing)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double a = (m0 + s == 0) ? u0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) f[s][k] += (T)(a * t.v[k]);
+        for (int k = 0; k < P; ++k) f[s][k] += (T)(a * v[k]);
     }
 }
 
@@ -377,25 +413,51 @@ __device__ __forceinline__ void residual(double (&r)[S][P], const TU (&u)[S][P],
                                          const TF (&f)[S][P], const OP &op,
                                          double (*xchg)[NW], int &phase)
 {
-    const auto &tb = op.res();
-    double w[S];
+    if constexpr (OP::kRows) {
+        const auto cd = op.cd();
+        double w[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        double t = 0.0;
+        for (int s = 0; s < S; ++s) {
+            double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) t += tb.cd[k] * (double)u[s][k];
-        w[s] = t;
-    }
-    const double wl = left_value<NW, double>(w[S - 1], xchg, phase);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const double wn = s == 0 ? wl : w[s - 1];
+            for (int k = 0; k < P; ++k) t += cd.v[k] * (double)u[s][k];
+            w[s] = t;
+        }
+        const double wl = left_value<NW, double>(w[S - 1], xchg, phase);
+        const auto v = op.v();
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            double t = (double)f[s][k] + tb.v[k] * wn;
+            const auto a = op.a_row(k);
 #pragma unroll
-            for (int l = 0; l < P; ++l) t -= tb.A[k * P + l] * (double)u[s][l];
-            r[s][k] = t;
+            for (int s = 0; s < S; ++s) {
+                const double wn = s == 0 ? wl : w[s - 1];
+                double t = (double)f[s][k] + v.v[k] * wn;
+#pragma unroll
+                for (int l = 0; l < P; ++l) t -= a.v[l] * (double)u[s][l];
+                r[s][k] = t;
+            }
+        }
+    } else {
+        const auto &tb = op.res();
+        double w[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) t += tb.cd[k] * (double)u[s][k];
+            w[s] = t;
+        }
+        const double wl = left_value<NW, double>(w[S - 1], xchg, phase);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const double wn = s == 0 ? wl : w[s - 1];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double t = (double)f[s][k] + tb.v[k] * wn;
+#pragma unroll
+                for (int l = 0; l < P; ++l) t -= tb.A[k * P + l] * (double)u[s][l];
+                r[s][k] = t;
+            }
         }
     }
 }
@@ -403,16 +465,30 @@ __device__ __forceinline__ void residual(double (&r)[S][P], const TU (&u)[S][P],
 template <int P, int S, typename T, class OP>
 __device__ __forceinline__ void apply_G(T (&g)[S][P], const T (&f)[S][P], const OP &op)
 {
-    const auto &tb = op.gm();
-#pragma unroll
-    for (int s = 0; s < S; ++s)
+    if constexpr (OP::kRows) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            T t = 0;
+            const auto G = op.g_row(k);
 #pragma unroll
-            for (int l = 0; l < P; ++l) t += tb.G[k * P + l] * f[s][l];
-            g[s][k] = t;
+            for (int s = 0; s < S; ++s) {
+                T t = 0;
+#pragma unroll
+                for (int l = 0; l < P; ++l) t += G.v[l] * f[s][l];
+                g[s][k] = t;
+            }
         }
+    } else {
+        const auto &tb = op.gm();
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                T t = 0;
+#pragma unroll
+                for (int l = 0; l < P; ++l) t += tb.G[k * P + l] * f[s][l];
+                g[s][k] = t;
+            }
+    }
 }
 
 // u_{2i} += R_1^T e_i, u_{2i+1} += R_2^T e_i (in T); with S = 1 each lane
@@ -421,31 +497,33 @@ template <int P, int S, typename T>
 __device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? S / 2 : 1][P],
                                             const T *__restrict__ R, int64_t m0)
 {
-    const auto R1T = opaque(R);
-    const auto R2T = R1T + P * P;
+    // row k of R_1^T and of R_2^T, loaded per row
     if constexpr (S >= 2) {
 #pragma unroll
-        for (int i = 0; i < S / 2; ++i)
+        for (int k = 0; k < P; ++k) {
+            const auto r1 = load_vals<P>(R, k * P), r2 = load_vals<P>(R, P * P + k * P);
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
+            for (int i = 0; i < S / 2; ++i) {
                 T s1 = 0, s2 = 0;
 #pragma unroll
                 for (int l = 0; l < P; ++l) {
-                    s1 += R1T[k * P + l] * e[i][l];
-                    s2 += R2T[k * P + l] * e[i][l];
+                    s1 += r1.v[l] * e[i][l];
+                    s2 += r2.v[l] * e[i][l];
                 }
                 u[2 * i][k] += s1;
                 u[2 * i + 1][k] += s2;
             }
+        }
     } else {
         const bool second = (m0 & 1) != 0;  // second fine slab of its coarse slab
 #pragma unroll
         for (int k = 0; k < P; ++k) {
+            const auto r1 = load_vals<P>(R, k * P), r2 = load_vals<P>(R, P * P + k * P);
             T s1 = 0, s2 = 0;
 #pragma unroll
             for (int l = 0; l < P; ++l) {
-                s1 += R1T[k * P + l] * e[0][l];
-                s2 += R2T[k * P + l] * e[0][l];
+                s1 += r1.v[l] * e[0][l];
+                s2 += r2.v[l] * e[0][l];
             }
             u[0][k] += second ? s2 : s1;
         }
@@ -458,18 +536,18 @@ template <int P, int S, typename T>
 __device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const T *__restrict__ R,
                                                T (&rc)[S / 2][P])
 {
-    const auto R1T = opaque(R);
-    const auto R2T = R1T + P * P;
+    // column k of R_1^T and of R_2^T, loaded per column
 #pragma unroll
-    for (int i = 0; i < S / 2; ++i)
+    for (int k = 0; k < P; ++k) {
+        const auto c1 = load_vals<P, P>(R, k), c2 = load_vals<P, P>(R, P * P + k);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
+        for (int i = 0; i < S / 2; ++i) {
             T s1 = 0;
 #pragma unroll
-            for (int l = 0; l < P; ++l)
-                s1 += R1T[l * P + k] * (T)r[2 * i][l] + R2T[l * P + k] * (T)r[2 * i + 1][l];
+            for (int l = 0; l < P; ++l) s1 += c1.v[l] * (T)r[2 * i][l] + c2.v[l] * (T)r[2 * i + 1][l];
             rc[i][k] = s1;
         }
+    }
 }
 
 template <int P, int S, bool BW, typename T>
@@ -477,8 +555,6 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
                                                T *__restrict__ rc_base, int64_t m0, int64_t N,
                                                int64_t Nc, int li0, int halo)
 {
-    const auto R1T = opaque(R);
-    const auto R2T = R1T + P * P;
     if constexpr (S >= 2) {
         T rc[S / 2][P];
         restrict_pairs<P, S, T>(r, R, rc);
@@ -492,10 +568,10 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
             T rc[1][P];
 #pragma unroll
             for (int k = 0; k < P; ++k) {
+                const auto c1 = load_vals<P, P>(R, k), c2 = load_vals<P, P>(R, P * P + k);
                 T s1 = 0;
 #pragma unroll
-                for (int l = 0; l < P; ++l)
-                    s1 += R1T[l * P + k] * (T)r[0][l] + R2T[l * P + k] * (T)rn[l];
+                for (int l = 0; l < P; ++l) s1 += c1.v[l] * (T)r[0][l] + c2.v[l] * (T)rn[l];
                 rc[0][k] = s1;
             }
             store_chunk<P, 1, BW, T>(rc_base, m0 / 2, Nc, rc, 0, 0);
