@@ -491,17 +491,51 @@ __device__ __forceinline__ void apply_G(T (&g)[S][P], const T (&f)[S][P], const 
     }
 }
 
+// Rows and columns of the transfer matrices R_1^T (i = 0) and R_2^T (i = 1):
+// from global memory, loaded where used (streaming kernels), or from a copy
+// in LDS (bottom kernel).
+template <int P, typename T>
+struct RGlob {
+    const T *R;
+    __device__ __forceinline__ Vals<P, T> row(int i, int k) const
+    {
+        return load_vals<P>(R, i * P * P + k * P);
+    }
+    __device__ __forceinline__ Vals<P, T> col(int i, int k) const
+    {
+        return load_vals<P, P>(R, i * P * P + k);
+    }
+};
+template <int P>
+struct RLds {
+    const double *R;
+    __device__ __forceinline__ Vals<P, double> row(int i, int k) const
+    {
+        Vals<P, double> r;
+#pragma unroll
+        for (int l = 0; l < P; ++l) r.v[l] = R[i * P * P + k * P + l];
+        return r;
+    }
+    __device__ __forceinline__ Vals<P, double> col(int i, int k) const
+    {
+        Vals<P, double> r;
+#pragma unroll
+        for (int l = 0; l < P; ++l) r.v[l] = R[i * P * P + l * P + k];
+        return r;
+    }
+};
+
 // u_{2i} += R_1^T e_i, u_{2i+1} += R_2^T e_i (in T); with S = 1 each lane
 // adds the half that belongs to its own slab.
-template <int P, int S, typename T>
+template <int P, int S, typename T, class RA>
 __device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? S / 2 : 1][P],
-                                            const T *__restrict__ R, int64_t m0)
+                                            const RA &ra, int64_t m0)
 {
     // row k of R_1^T and of R_2^T, loaded per row
     if constexpr (S >= 2) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const auto r1 = load_vals<P>(R, k * P), r2 = load_vals<P>(R, P * P + k * P);
+            const auto r1 = ra.row(0, k), r2 = ra.row(1, k);
 #pragma unroll
             for (int i = 0; i < S / 2; ++i) {
                 T s1 = 0, s2 = 0;
@@ -518,7 +552,7 @@ __device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? 
         const bool second = (m0 & 1) != 0;  // second fine slab of its coarse slab
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            const auto r1 = load_vals<P>(R, k * P), r2 = load_vals<P>(R, P * P + k * P);
+            const auto r1 = ra.row(0, k), r2 = ra.row(1, k);
             T s1 = 0, s2 = 0;
 #pragma unroll
             for (int l = 0; l < P; ++l) {
@@ -530,16 +564,23 @@ __device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? 
     }
 }
 
+template <int P, int S, typename T>
+__device__ __forceinline__ void prolong_add(T (&u)[S][P], const T (&e)[S >= 2 ? S / 2 : 1][P],
+                                            const T *__restrict__ R, int64_t m0)
+{
+    prolong_add<P, S, T>(u, e, RGlob<P, T>{R}, m0);
+}
+
 // Restrict the residual r (rounded to T) of this thread's slabs and store
 // the coarse slabs of output pairs: rc_m = R_1 r_{2m} + R_2 r_{2m+1}.
-template <int P, int S, typename T>
-__device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const T *__restrict__ R,
+template <int P, int S, typename T, class RA>
+__device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const RA &ra,
                                                T (&rc)[S / 2][P])
 {
     // column k of R_1^T and of R_2^T, loaded per column
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-        const auto c1 = load_vals<P, P>(R, k), c2 = load_vals<P, P>(R, P * P + k);
+        const auto c1 = ra.col(0, k), c2 = ra.col(1, k);
 #pragma unroll
         for (int i = 0; i < S / 2; ++i) {
             T s1 = 0;
@@ -548,6 +589,13 @@ __device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const T 
             rc[i][k] = s1;
         }
     }
+}
+
+template <int P, int S, typename T>
+__device__ __forceinline__ void restrict_pairs(const double (&r)[S][P], const T *__restrict__ R,
+                                               T (&rc)[S / 2][P])
+{
+    restrict_pairs<P, S, T>(r, RGlob<P, T>{R}, rc);
 }
 
 template <int P, int S, bool BW, typename T>
@@ -965,6 +1013,7 @@ struct BottomLds {
     double f[2 * BMAX * P];
     double x[2 * BMAX * P];
     double tab[kBottomMaxLevels * STRIDE];
+    double R[2 * P * P];     // R_1^T, R_2^T
     double xchg[2][kBottomThreads / 64];
     double red[kBottomThreads / 64];
     ScanSmem<kBottomThreads> scan;
@@ -983,7 +1032,6 @@ struct Bottom {
     int Lc;        // coarsest level
     int lw;        // first level with at most WAVE_SLABS slabs
     int nu1, nu2, gamma;
-    const double *R;
 
     __device__ int64_t nslab(int l) const { return Nlb >> (l - lb); }
     // offset (doubles) of level l in the f / x regions
@@ -1017,18 +1065,8 @@ struct Bottom {
         int phase = 0;
         sweeps<P, S, G>(u, g, op, nu1, xchg<G>(), phase);
         residual<P, S, G>(r, u, f, op, xchg<G>(), phase);
-        const double *R1T = R, *R2T = R + P * P;
         double rc[S / 2][P];
-#pragma unroll
-        for (int i = 0; i < S / 2; ++i)
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double s1 = 0.0;
-#pragma unroll
-                for (int q = 0; q < P; ++q)
-                    s1 += R1T[q * P + k] * r[2 * i][q] + R2T[q * P + k] * r[2 * i + 1][q];
-                rc[i][k] = s1;
-            }
+        restrict_pairs<P, S, double>(r, RLds<P>{sm.R}, rc);
         store_chunk<P, S / 2, BW>(sm.f + loff(l + 1), m0 / 2, nslab(l + 1), rc, 0, 0);
         group_sync<G>();
     }
@@ -1055,20 +1093,7 @@ struct Bottom {
         apply_G<P, S>(g, f, op);
         int phase = 0;
         sweeps<P, S, G>(u, g, op, nu1, xchg<G>(), phase);
-        const double *R1T = R, *R2T = R + P * P;
-#pragma unroll
-        for (int i = 0; i < S / 2; ++i)
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    s1 += R1T[k * P + q] * e[i][q];
-                    s2 += R2T[k * P + q] * e[i][q];
-                }
-                u[2 * i][k] += s1;
-                u[2 * i + 1][k] += s2;
-            }
+        prolong_add<P, S, double>(u, e, RLds<P>{sm.R}, m0);
         sweeps<P, S, G>(u, g, op, nu2, xchg<G>(), phase);
         // every thread owns the slabs it writes, so the update is in place
         store_chunk<P, S, BW>(sm.x + loff(l), m0, N, u, 0, 0);
@@ -1184,14 +1209,51 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
     }
     int lw = lb;
     while ((N >> (lw - lb)) > B::WAVE_SLABS) ++lw;
-    const B b{sm, lb, N, Lc, lw, a.nu1, a.nu2, a.gamma, a.R};
-    // tables of levels lb .. Lc, the right-hand side and the initial guess
-    for (int l = lb; l <= Lc; ++l)
-        for (int i = threadIdx.x; i < STRIDE; i += NT)
-            sm.tab[(l - lb) * STRIDE + i] = a.tab[((int64_t)l * a.batch + j) * a.tab_stride + i];
-    for (int64_t i = threadIdx.x; i < N * P; i += NT) {
-        sm.f[i] = (double)a.f[off * P + i];
-        sm.x[i] = a.x_in ? (double)a.x_in[off * P + i] : 0.0;
+    const B b{sm, lb, N, Lc, lw, a.nu1, a.nu2, a.gamma};
+    {
+        // tables of levels lb .. Lc and the transfer matrices into LDS, and
+        // the right-hand side and initial guess of level lb (S slabs per
+        // thread, physical order): every load issued before any LDS store
+        constexpr int NTAB = kBottomMaxLevels * STRIDE + 2 * P * P;
+        constexpr int TPT = (NTAB + NT - 1) / NT;
+        const int ntab = (Lc - lb + 1) * STRIDE;
+        double tv[TPT];
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            const int i = threadIdx.x + q * NT;
+            tv[q] = 0.0;
+            if (i < ntab)
+                tv[q] = a.tab[((int64_t)(lb + i / STRIDE) * a.batch + j) * a.tab_stride + i % STRIDE];
+            else if (i < ntab + 2 * P * P)
+                tv[q] = a.R[i - ntab];
+        }
+        const int64_t m0 = (int64_t)threadIdx.x * S;
+        TIO fv[S][P], xv[S][P];
+        load_chunk<P, S, false, TIO>(a.f + off * P, m0, N, fv);
+        if (a.x_in) {
+            load_chunk<P, S, false, TIO>(a.x_in + off * P, m0, N, xv);
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int k = 0; k < P; ++k) xv[s][k] = (TIO)0;
+        }
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            const int i = threadIdx.x + q * NT;
+            if (i < ntab) sm.tab[i] = tv[q];
+            else if (i < ntab + 2 * P * P) sm.R[i - ntab] = tv[q];
+        }
+        double fd[S][P], xd[S][P];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                fd[s][k] = (double)fv[s][k];
+                xd[s][k] = (double)xv[s][k];
+            }
+        store_chunk<P, S, false, double>(sm.f, m0, N, fd, 0, 0);
+        store_chunk<P, S, false, double>(sm.x, m0, N, xd, 0, 0);
     }
     __syncthreads();
     if (a.u0 && threadIdx.x < P) {
@@ -1208,8 +1270,18 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
     } else {
         b.template visit<B::NW>(lb, zero);
     }
-    // result of level lb back to global memory
-    for (int64_t i = threadIdx.x; i < N * P; i += NT) a.x_out[off * P + i] = (TIO)sm.x[i];
+    {
+        // result of level lb back to global memory
+        const int64_t m0 = (int64_t)threadIdx.x * S;
+        double xd[S][P];
+        TIO xo[S][P];
+        load_chunk<P, S, false, double>(sm.x, m0, N, xd);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) xo[s][k] = (TIO)xd[s][k];
+        store_chunk<P, S, false, TIO>(a.x_out + off * P, m0, N, xo, 0, 0);
+    }
     if (lb == 0 && a.st) {
         // squared residual of the result (level 0 of this instance): the
         // work-group finishes the cycle of its instance itself
