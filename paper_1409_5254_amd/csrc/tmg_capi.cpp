@@ -104,7 +104,7 @@ struct tmg_ctx {
     std::vector<int> deep_n;                      // per level: instances with level < lb
     int64_t bottom_cap = 0;
     InstState *st = nullptr, *st_ops = nullptr;
-    InstState *st_host = nullptr;                 // pinned
+    InstState *st_host = nullptr;                 // pinned, two snapshots of batch states
     Control *ctl = nullptr, *ctl_host = nullptr;  // device / pinned
     double *partial = nullptr;
     int64_t partial_cap = 0;
@@ -691,31 +691,55 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         CycleIO io{f, u0, u, trans, true, k};
         if ((rc = get_graph(c, io, &g[k]))) return rc;
     }
+    // The first two cycles run before the host looks at the state: a
+    // snapshot after each gives the contraction rate, from which the cycles
+    // still needed are launched in one go (cycles launched after an
+    // instance converged are no-ops for it).  Every look at the state stops
+    // the GPU for a host round trip, so there are few of them.
+    InstState *snap0 = c->st_host, *snap1 = c->st_host + c->batch;
+    const size_t stb = sizeof(InstState) * c->batch;
     int launched = 0;
+    std::vector<double> prev_rsq(c->batch, -1.0);
+    std::vector<int> prev_cyc(c->batch, 0);
     if (max_cycles > 0) {
         HIPCHK(c, hipGraphLaunch(g[kFirst], s));
         launched = 1;
+        if (max_cycles > 1) {
+            HIPCHK(c, hipMemcpyAsync(snap1, c->st, stb, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipGraphLaunch(g[kEven], s));
+            launched = 2;
+        }
     }
-    std::vector<double> prev_rsq(c->batch, -1.0);
-    std::vector<int> prev_cyc(c->batch, 0);
+    bool have_prev = launched == 2;
     while (true) {
-        HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(InstState) * c->batch,
-                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(snap0, c->st, stb, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
+        if (have_prev) {
+            // state after the first cycle
+            for (int j = 0; j < c->batch; ++j) {
+                if (snap1[j].done || snap1[j].cycles == 0) continue;
+                prev_rsq[j] = snap1[j].rsq;
+                prev_cyc[j] = snap1[j].cycles;
+            }
+            have_prev = false;
+        }
         bool all = true;
         int need = 1;
         for (int j = 0; j < c->batch; ++j) {
-            const InstState &q = c->st_host[j];
+            const InstState &q = snap0[j];
             if (q.done) continue;
             all = false;
             // cycles still needed at the contraction rate observed since the
-            // previous check (launched cycles are no-ops once converged)
+            // previous look
             const int dc = q.cycles - prev_cyc[j];
             if (prev_rsq[j] > 0.0 && dc > 0 && q.rsq > 0.0 && q.rsq < prev_rsq[j]) {
                 const double lrate = 0.5 * std::log(q.rsq / prev_rsq[j]) / dc;
                 const double lgoal = 0.5 * std::log(c->ctl_host->rtol2 * q.r0sq / q.rsq);
-                const int k = (int)std::ceil(lgoal / lrate);
-                need = std::max(need, std::min(std::max(k, 1), 8));
+                // one short of the estimate for longer runs: an extra look
+                // costs less than a cycle launched after convergence
+                int k = (int)std::ceil(lgoal / lrate);
+                if (k > 4) k -= 1;
+                need = std::max(need, std::min(std::max(k, 1), 32));
             }
             prev_rsq[j] = q.rsq;
             prev_cyc[j] = q.cycles;
@@ -730,7 +754,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     }
     int status = TMG_OK;
     for (int j = 0; j < c->batch; ++j) {
-        const InstState &q = c->st_host[j];
+        const InstState &q = snap0[j];
         if (q.cycles == 0) {
             // no cycle ran for it (r_0 = 0 or max_cycles = 0): the iterate is u = 0
             HIPCHK(c, hipMemsetAsync(u + c->slab_off_h[0][j] * c->P, 0,
@@ -947,7 +971,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     // partial sums: one slot per level-0 tile at the smallest tile size in use
     c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
     if ((rc = dalloc(c, &c->partial, c->partial_cap))) return fail(rc);
-    if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
+    if (hipHostMalloc((void **)&c->st_host, 2 * sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
         hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess)
         return fail(TMG_ERR_OOM);
