@@ -101,13 +101,14 @@ def fused_pass_roofline(p, ctx, reps):
     """Average duration of the dominant kernel, the fused level-0 pass that
     every cycle after the first of an FP64 V-cycle solve runs (tmg_op_fused2:
     level 1's up leg in the tiles, then at level 0 the recomputed pre-sweeps,
-    correction, post-sweeps, next cycle's pre-sweeps, residual, restriction),
-    timed with HIP events on the stream it is launched on.  Algorithmic bytes
-    per fine unknown: read u, f (16 B), level 1's right-hand side (4 B) and
-    level 2's correction (2 B), write u (8 B) and the restricted residual
-    (4 B) = 34 B; one launch processes N*P unknowns.  The solve runs the same
-    kernel in place (u_in = u_out, left halos from a per-tile buffer); the
-    timed launch writes a second array."""
+    correction, post-sweeps, next cycle's pre-sweeps, residual, restriction,
+    and level 1's next down leg), timed with HIP events on the stream it is
+    launched on.  Algorithmic bytes per fine unknown: read u, f (16 B), level
+    1's right-hand side (4 B) and level 2's correction (2 B), write u (8 B),
+    level 1's next right-hand side (4 B) and level 2's (2 B) = 36 B; one launch
+    processes N*P unknowns.  The solve runs the same kernel in place (u_in =
+    u_out, left halos from a per-tile buffer); the timed launch writes a
+    second array."""
     import torch
     s, f, u0, u = ctx
     N = s.n_slabs[0]
@@ -116,18 +117,19 @@ def fused_pass_roofline(p, ctx, reps):
     rc = torch.empty(N // 2 * P, dtype=torch.float64, device="cuda")
     f1 = torch.zeros(N // 2 * P, dtype=torch.float64, device="cuda")
     e2 = torch.zeros(N // 4 * P, dtype=torch.float64, device="cuda")
+    f2 = torch.empty(N // 4 * P, dtype=torch.float64, device="cuda")
     st = torch.cuda.current_stream()
     for _ in range(3):
-        s.fused2(f, u, f1, e2, ub, rc, fold_u0=u0)
+        s.fused2(f, u, f1, e2, ub, rc, f2=f2, fold_u0=u0)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
-        s.fused2(f, u, f1, e2, ub, rc, fold_u0=u0)
+        s.fused2(f, u, f1, e2, ub, rc, f2=f2, fold_u0=u0)
     e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    bytes_alg = 34.0 * N * P
+    bytes_alg = 36.0 * N * P
     gbs = bytes_alg / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,

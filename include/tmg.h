@@ -203,13 +203,17 @@ int tmg_op_fused(tmg_handle h, int trans, const double *f, const double *fold_u0
  * is not read but computed tile by tile as level 1's up leg of a first visit
  * (nu1 sweeps from zero on f1, the correction u1 += P e2 with e2 in level
  * 2's layout, nu2 sweeps; eqs. chap4_ODESmoother, chap4_prolongationTime),
- * then the level-0 work of tmg_op_fused.  f1 is level 1's right-hand side,
- * e2 level 2's correction; instances with fewer than three levels are
- * skipped.  u_in and u_out must not overlap; fold_u0 as for tmg_op_down.
+ * then the level-0 work of tmg_op_fused, which writes level 1's next
+ * right-hand side rc.  If f2 != NULL, level 1's next down leg follows in the
+ * same tiles (nu1 sweeps from zero on rc, residual, restriction; eq.
+ * chap4_restrictionTime) into f2 (level 2's layout).  f1 is level 1's
+ * right-hand side, e2 level 2's correction; instances with fewer than three
+ * levels are skipped.  u_in and u_out must not overlap, nor f1 and rc;
+ * fold_u0 as for tmg_op_down.
  */
 int tmg_op_fused2(tmg_handle h, int trans, const double *f, const double *fold_u0,
                   const double *u_in, const double *f1, const double *e2, double *u_out,
-                  double *rc, tmg_stream s);
+                  double *rc, double *f2, tmg_stream s);
 
 /* Exact solve L_level e = r on every instance by the parallel affine prefix
  * scan (forward in time; backward for trans = 1).  Requires

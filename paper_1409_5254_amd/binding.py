@@ -87,7 +87,7 @@ def lib():
             "tmg_op_down": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_up": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_fused": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-            "tmg_op_fused2": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_op_fused2": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_coarse_solve": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
             "tmg_op_residual_norm": (_i, [_vp, _i, _vp, _vp, _vp, P(_d), _vp]),
         }
@@ -225,9 +225,9 @@ class Solver:
                                _ptr(u_out), _ptr(rc), _stream())
         self._check(r, "tmg_op_fused")
 
-    def fused2(self, f, u_in, f1, e2, u_out, rc, trans=False, fold_u0=None):
+    def fused2(self, f, u_in, f1, e2, u_out, rc, f2=None, trans=False, fold_u0=None):
         r = lib().tmg_op_fused2(self._h, int(trans), _ptr(f), _ptr(fold_u0), _ptr(u_in), _ptr(f1),
-                                _ptr(e2), _ptr(u_out), _ptr(rc), _stream())
+                                _ptr(e2), _ptr(u_out), _ptr(rc), _ptr(f2), _stream())
         self._check(r, "tmg_op_fused2")
 
     def coarse_solve(self, level, r, e, trans=False):

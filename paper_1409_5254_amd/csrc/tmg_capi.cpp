@@ -92,6 +92,7 @@ struct tmg_ctx {
     std::vector<int64_t> level_size;              // coefficients per level
     double *hb[2] = {nullptr, nullptr};           // level-0 halo buffers
     int64_t hb_last_off = 0;                      // slots of the one-level pass next to a two-level one
+    double *f1b = nullptr;                        // second level-1 right-hand side (two-level passes)
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
     float *tab32_fwd = nullptr, *tab32_adj = nullptr;  // the same tables rounded to FP32
@@ -136,9 +137,15 @@ struct tmg_ctx {
         return ((3 * opt.nu1 + 2 + q - 1) / q) * q;
     }
     int H_upair() const { return rs(2 * (opt.nu1 + opt.nu2) + opt.nu2); }
-    // fused pass that also runs level 1's up leg: level 1's first nu1 + nu2
-    // coarse slabs are wrong, 2 (nu1 + nu2) fine slabs, then nu2 + nu1 + 1
-    int H_fused2() const { return rs(3 * (opt.nu1 + opt.nu2) + 1); }
+    // fused pass that also runs level 1's up leg and level 1's next down
+    // leg: level 1's first nu1 + nu2 coarse slabs are wrong, 2 (nu1 + nu2)
+    // fine slabs, then nu2 + nu1 + 1 at level 0 and 2 nu1 for level 1's
+    // down leg; a multiple of 4 so that level-2 pairs stay inside a tile
+    int H_fused2() const
+    {
+        const int q = S < 4 ? 4 : S;
+        return ((3 * (opt.nu1 + opt.nu2) + 1 + 2 * opt.nu1 + q - 1) / q) * q;
+    }
     // V-cycle solves in FP64 fuse level 1's up leg into the level-0 pass
     bool fuse_up1() const { return opt.gamma == 1 && !mixed; }
     // mixed precision, level 0: first down pass, fused pass, single cycle
@@ -409,7 +416,8 @@ int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, 
     if (tl->ntiles == 0) return TMG_OK;
     LevelStore<T> &L = store<T>(c);
     LegArgsT<T> a = leg_args<T>(c, level, io.trans, tl, H);
-    a.f = L.f[level];
+    a.f = level == 0 ? reinterpret_cast<const T *>(io.f) : L.f[level];
+    a.u0 = level == 0 ? fold_of(io) : nullptr;
     a.tab1 = tab_of(c, level + 1, io.trans);
     a.tab1T = tabT_of<T>(c, level + 1, io.trans);
     a.c2slab_off = c->slab_off_d[level + 2];
@@ -430,17 +438,20 @@ int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, 
 
 // Levels >= 1 of a V-cycle (every visit a first visit from zero): all down
 // legs from the top, the bottom kernels, all up legs from the bottom, with
-// consecutive streaming levels paired into two-level launches.  Up legs start
-// at level up_first (2 when level 1's up leg runs inside the level-0 pass).
+// consecutive streaming levels paired into two-level launches.  Down and up
+// legs start at level down_first / up_first (2 when level 1's legs run
+// inside the level-0 pass).
 template <typename T>
-int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int up_first, hipStream_t s)
+int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_first,
+                          hipStream_t s)
 {
     int rc;
     LevelStore<T> &L = store<T>(c);
     c->cur.assign(c->Lmax + 1, 0);
-    for (int l = 1; l < c->Lmax; ++l) {
-        if ((rc = enqueue_pair<T>(c, io, l, true, kPair1, s)) ||
-            (rc = enqueue_down<T>(c, io, l, true, s, kSingle1)))
+    const int dp = down_first == 1 ? kPair1 : kPair2, ds = down_first == 1 ? kSingle1 : kSingle2;
+    for (int l = down_first; l < c->Lmax; ++l) {
+        if ((rc = enqueue_pair<T>(c, io, l, true, dp, s)) ||
+            (rc = enqueue_down<T>(c, io, l, true, s, ds)))
             return rc;
     }
     for (int l = 1; l < c->Lmax; ++l)
@@ -501,7 +512,7 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.rc = c->s.f[1];
         HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
     }
-    if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<float>(c, io, 1, s)
+    if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<float>(c, io, 1, 1, s)
                                 : enqueue_coarse_visits<float>(c, io, 1, s)))
         return rc;
     const int H = solve ? c->H_mix() : c->H_mixv();
@@ -547,14 +558,25 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             a.halo_out = c->hb[0];
             HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
         }
-        if (!solve || first)
-            if ((rc = enqueue_down<double>(c, io, 0, first, s))) return rc;
-        // with fuse2, the instances whose level 1 streams (kDeepNext) run
-        // level 1's up leg inside their level-0 pass; the others
-        // (kDeepLast) take level 1's correction from the bottom kernel
+        // With fuse2 the instances whose level 1 streams (kDeepNext) run
+        // level 1's up leg and next down leg inside their level-0 pass (and
+        // the first cycle runs levels 0 and 1 down in one launch); the others
+        // (kDeepLast) take level 1's correction from the bottom kernel.
+        // Level 1's right-hand side then alternates between two buffers:
+        // the pass reads it for this cycle's up leg and writes the next one.
         const bool fuse2 = solve && c->fuse_up1() && c->deep_n[1] > 0;
-        if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<double>(c, io, fuse2 ? 2 : 1, s)
-                                    : enqueue_coarse_visits<double>(c, io, 1, s, fuse2)))
+        double *f1_in = io.kind == kEven ? c->f1b : c->d.f[1];
+        double *f1_out = io.kind == kEven ? c->d.f[1] : c->f1b;
+        if (fuse2 && first) {
+            if ((rc = enqueue_pair<double>(c, io, 0, true, kDeepNext, s)) ||
+                (rc = enqueue_down<double>(c, io, 0, true, s, kDeepLast)))
+                return rc;
+        } else if (!solve || first) {
+            if ((rc = enqueue_down<double>(c, io, 0, first, s))) return rc;
+        }
+        if ((rc = c->opt.gamma == 1
+                      ? enqueue_vcycle_levels<double>(c, io, fuse2 ? 2 : 1, fuse2 ? 2 : 1, s)
+                      : enqueue_coarse_visits<double>(c, io, 1, s)))
             return rc;
         // fused level-0 pass(es)
         for (int pass = fuse2 ? 0 : 1; pass < 2; ++pass) {
@@ -570,7 +592,7 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             a.u_in = first ? nullptr : io.u;
             a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]) + hoff;
             if (two) {
-                a.f1 = c->d.f[1];
+                a.f1 = f1_in;
                 a.e2 = c->d.x(2, c->cur[2]);
                 a.tab1 = tab_of(c, 1, io.trans);
                 a.tab1T = a.tab1;
@@ -584,7 +606,8 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             a.post = c->opt.nu2;
             if (solve) {
                 a.halo_out = (io.kind == kEven ? c->hb[1] : c->hb[0]) + hoff;
-                a.rc = c->d.f[1];
+                a.rc = two ? f1_out : c->d.f[1];
+                a.f2 = two && c->opt.gamma == 1 ? c->d.f[2] : nullptr;
                 a.next = c->opt.nu1;
                 a.partial = c->partial;
                 a.norm_off = tl->d_off;
@@ -612,8 +635,13 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
     if ((rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_fused2()), s, &tl)) ||
         (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_fused()), s, &tl)))
         return rc;
+    if ((rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_dpair()), s, &tl)) ||
+        (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_down()), s, &tl)))
+        return rc;
     for (int l = 1; l < c->Lmax; ++l)
         if ((rc = get_tiles(c, l, kPair1, c->TO(c->H_dpair()), s, &tl)) ||
+            (rc = get_tiles(c, l, kPair2, c->TO(c->H_dpair()), s, &tl)) ||
+            (rc = get_tiles(c, l, kSingle2, c->TO(c->H_down()), s, &tl)) ||
             (rc = get_tiles(c, l, kSingle1, c->TO(c->H_down()), s, &tl)) ||
             (rc = get_tiles(c, l, kPair1, c->TO(c->H_upair()), s, &tl)) ||
             (rc = get_tiles(c, l, kSingle1, c->TO(c->H_up()), s, &tl)) ||
@@ -939,6 +967,8 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                                     tiles_of(c, 0, kDeepLast, c->TO(c->H_fused())) * c->H_fused() * P);
         if ((rc = dalloc(c, &c->hb[0], hsize)) || (rc = dalloc(c, &c->hb[1], hsize)))
             return fail(rc);
+        if (c->fuse_up1() && c->deep_n[1] > 0 && (rc = dalloc(c, &c->f1b, c->level_size[1])))
+            return fail(rc);
     }
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
@@ -1145,7 +1175,7 @@ int tmg_op_fused(tmg_handle c, int trans, const double *f, const double *fold_u0
 
 int tmg_op_fused2(tmg_handle c, int trans, const double *f, const double *fold_u0,
                   const double *u_in, const double *f1, const double *e2, double *u_out,
-                  double *rcout, tmg_stream stream)
+                  double *rcout, double *f2, tmg_stream stream)
 {
     if (!c || !f || !u_in || !f1 || !e2 || !u_out || !rcout || c->Lmax < 3 || (fold_u0 && trans))
         return TMG_ERR_INVALID;
@@ -1165,6 +1195,7 @@ int tmg_op_fused2(tmg_handle c, int trans, const double *f, const double *fold_u
     a.c2slab_off = c->slab_off_d[2];
     a.u_out = u_out;
     a.rc = rcout;
+    a.f2 = f2;
     a.pre = c->opt.nu1;
     a.post = c->opt.nu2;
     a.next = c->opt.nu1;

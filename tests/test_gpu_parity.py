@@ -365,7 +365,8 @@ def test_fused_level0_pass(p, trans):
 def test_fused2_level0_pass(p, trans):
     """tmg_op_fused2: level 1's correction computed in the tiles as level
     1's first-visit up leg (nu1 sweeps from zero on f1, correction with the
-    level-2 e2, nu2 sweeps at tau_1 = 2 tau), then the pass of tmg_op_fused."""
+    level-2 e2, nu2 sweeps at tau_1 = 2 tau), then the pass of tmg_op_fused,
+    then level 1's next down leg into f2."""
     rng = np.random.default_rng(80 + p)
     N, z = 4096, 0.02
     s = B().Solver([N], [z * N], [1.0], p=p)
@@ -381,9 +382,15 @@ def test_fused2_level0_pass(p, trans):
                        trans=trans)
     nxt = core.sweeps(p, z, 1.0, ff, post, 2, trans=trans)
     ref_rc = core.restrict(p, core.residual(p, z, 1.0, ff, nxt, trans=trans))
+    # level 1's next down leg on rc (tau_1 = 2 tau): sweeps from zero,
+    # residual, restriction
+    x1 = core.sweeps(p, 2 * z, 1.0, ref_rc, np.zeros(N // 2 * P), 2, trans=trans)
+    ref_f2 = core.restrict(p, core.residual(p, 2 * z, 1.0, ref_rc, x1, trans=trans))
     d_out = torch.empty(N * P, dtype=torch.float64, device=DEV)
     d_rc = torch.empty(N // 2 * P, dtype=torch.float64, device=DEV)
-    s.fused2(dev(f), dev(u), dev(f1), dev(e2), d_out, d_rc, trans=trans,
+    d_f2 = torch.empty(N // 4 * P, dtype=torch.float64, device=DEV)
+    s.fused2(dev(f), dev(u), dev(f1), dev(e2), d_out, d_rc, f2=d_f2, trans=trans,
              fold_u0=None if trans else dev([u0]))
     assert relerr(host(d_out), post) <= TOL
     assert relerr(host(d_rc), ref_rc) <= TOL
+    assert relerr(host(d_f2), ref_f2) <= TOL
