@@ -33,6 +33,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+AUTOTUNE = True   # pick each handle's schedule with tmg_autotune before timing
+
+
+def tune(s, f, u0, u):
+    """Schedule chosen by the library's autotuner (not timed), or None."""
+    if not AUTOTUNE:
+        return None
+    cap, pairs = s.autotune(f, u0, u)
+    return {"bottom_cap": cap, "two_level_launches": pairs}
 
 
 def parse():
@@ -48,6 +57,8 @@ def parse():
     ap.add_argument("--mixed", type=int, default=1, help="include the N=2^24 mixed-precision comparison")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick each handle's schedule with tmg_autotune before timing (1) or not")
     ap.add_argument("--cpu-log2n", type=int, default=21)
     ap.add_argument("--batch", type=int, default=0, help="instances for --config 3/4/5 (0: default)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -90,11 +101,12 @@ def config2_case(p, log2n, cycle, steps, warmup, precision=0):
     u0 = torch.tensor([1.0], dtype=torch.float64, device="cuda")
     u = torch.empty_like(f)
     s = Solver([N], [T], [1.0], p=p, gamma=1 if cycle == "V" else 2, precision=precision)
+    sched = tune(s, f, u0, u)
     dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
     unknowns = N * (p + 1)
     return dict(p=p, N=N, unknowns=unknowns, ms_per_solve=dt * 1e3,
                 unknowns_per_s=unknowns / dt, cycles=res.cycles[0], relres=res.relres[0],
-                status=res.status), (s, f, u0, u)
+                status=res.status, schedule=sched), (s, f, u0, u)
 
 
 def fused_pass_roofline(p, ctx, reps):
@@ -198,10 +210,12 @@ def config5_compare(B, log2n, steps, warmup):
     for name, prec in (("fp64", 0), ("fp32_inner", 1)):
         s = Solver([N] * B, [T] * B, lams, p=p, precision=prec)
         u = torch.empty_like(f)
+        sched = tune(s, f, u0, u)
         dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps,
                               warmup)
         out[name] = dict(unknowns_per_s=B * N * P / dt, ms_per_solve=dt * 1e3,
-                         cycles=max(res.cycles), relres=max(res.relres), status=res.status)
+                         cycles=max(res.cycles), relres=max(res.relres), status=res.status,
+                         schedule=sched)
         sols[name] = u
         s.close()
         del s
@@ -244,9 +258,10 @@ def config3_run(n_inst, steps, warmup, precision=0):
     u0 = torch.ones(n_inst, dtype=torch.float64, device="cuda")
     s = Solver(Ns, [1.0] * n_inst, list(lam), p=1, precision=precision)
     u = torch.empty_like(f)
+    sched = tune(s, f, u0, u)
     dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
     cyc = np.array(res.cycles)
-    return dict(unknowns_per_s=total / dt, ms_per_solve=dt * 1e3, instances=n_inst,
+    return dict(unknowns_per_s=total / dt, ms_per_solve=dt * 1e3, instances=n_inst, schedule=sched,
                 unknowns=total, cycles_min=int(cyc.min()), cycles_max=int(cyc.max()),
                 cycles_mean=float(cyc.mean()), max_relres=max(res.relres), status=res.status,
                 workload=f"{n_inst} instances, lambda_j = pi^2 j^2 kappa, N_j = 2^U{{12..18}}, "
@@ -273,6 +288,7 @@ def config4_run(B, steps, warmup):
     s = Solver([N] * B, [T] * B, [q[0] for q in params], p=p)
     u = torch.empty_like(f)
     z = torch.empty_like(f)
+    sched = tune(s, f, u0, u)
 
     def step():
         fw = s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200)
@@ -282,7 +298,7 @@ def config4_run(B, steps, warmup):
         return fw, s.adjoint_solve(gr, u=u, z=z, rtol=1e-10, max_cycles=200)
 
     dt, (fw, adj) = time_solves(step, steps, warmup)
-    return dict(unknowns_per_s=B * N * P / dt, ms_per_forward_backward=dt * 1e3,
+    return dict(unknowns_per_s=B * N * P / dt, ms_per_forward_backward=dt * 1e3, schedule=sched,
                 forward_cycles=max(fw.cycles), adjoint_cycles=max(adj[3]),
                 max_relres_adjoint=max(adj[4]), status=adj[5],
                 workload=f"{B} x (N=2^20, p=2, T=100, lambda ~ U(0.1,10)), loss 1/2 sum(w_n-y_n)^2")
@@ -290,6 +306,8 @@ def config4_run(B, steps, warmup):
 
 def main():
     a = parse()
+    global AUTOTUNE
+    AUTOTUNE = bool(a.autotune)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solve is not "
               "sharded across GPUs in this build.", file=sys.stderr)
@@ -348,10 +366,11 @@ def main():
         "ms_per_step": head["ms_per_solve"],
         "config": {"workload": f"u'+u=f, T=1000, N=2^{a.log2n} slabs, p={a.p}, "
                                f"{a.cycle}(2,2) cycle to 1e-10, 16-mode Fourier f",
-                   "cycles": head["cycles"], "relres": head["relres"]},
+                   "cycles": head["cycles"], "relres": head["relres"],
+                   "schedule": head["schedule"]},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "sweep_p": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles")}
+        "sweep_p": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles", "schedule")}
                     for r in sweep],
         "fp32_inner_vs_fp64": mixed,
     }

@@ -139,6 +139,22 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
                       int max_cycles, double *dlambda, double *du0, int *cycles,
                       double *relres, tmg_stream s);
 
+/*
+ * Schedule autotuner.  Installs in h the fastest of a few schedules, timed on
+ * this hardware with the caller's data: for each candidate it runs three
+ * cycles of the solve of L u = f (u0 folded) and measures them with HIP
+ * events.  A schedule is the size up to which an instance's levels run inside
+ * the single-work-group bottom kernel (bottom_cap, the largest the bottom
+ * kernel holds divided by 1, 2, ..., 32) and, for V-cycles, whether
+ * consecutive levels share two-level launches.  The solution is
+ * the same under every schedule (up to rounding order); only the kernel
+ * split changes.  u (device, same layout as f) is used as scratch and
+ * overwritten.  *bottom_cap and *pairs (host, may be NULL) receive the
+ * choice.  Blocks until done.
+ */
+int tmg_autotune(tmg_handle h, const double *f, const double *u0, double *u, int64_t *bottom_cap,
+                 int *pairs, tmg_stream s);
+
 /* Release every resource of h (synchronises its streams first). */
 int tmg_destroy(tmg_handle h);
 

@@ -93,6 +93,8 @@ struct tmg_ctx {
     double *hb[2] = {nullptr, nullptr};           // level-0 halo buffers
     int64_t hb_last_off = 0;                      // slots of the one-level pass next to a two-level one
     double *f1b = nullptr;                        // second level-1 right-hand side (two-level passes)
+    int64_t hb_cap = 0;                           // doubles allocated per halo buffer
+    bool pairs = true;                            // two-level launches in V-cycles (schedule)
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
     float *tab32_fwd = nullptr, *tab32_adj = nullptr;  // the same tables rounded to FP32
@@ -146,8 +148,8 @@ struct tmg_ctx {
         const int q = S < 4 ? 4 : S;
         return ((3 * (opt.nu1 + opt.nu2) + 1 + 2 * opt.nu1 + q - 1) / q) * q;
     }
-    // V-cycle solves in FP64 fuse level 1's up leg into the level-0 pass
-    bool fuse_up1() const { return opt.gamma == 1 && !mixed; }
+    // V-cycle solves in FP64 fuse level 1's legs into the level-0 pass
+    bool fuse_up1() const { return opt.gamma == 1 && !mixed && pairs; }
     // mixed precision, level 0: first down pass, fused pass, single cycle
     int H_mixd() const { return rs(opt.nu1 + 2); }
     int H_mix() const { return rs(2 * opt.nu1 + opt.nu2 + 3); }
@@ -178,6 +180,19 @@ int dalloc(tmg_ctx *c, T **p, size_t n)
     }
     c->allocs.push_back(*p);
     return TMG_OK;
+}
+
+// Free one allocation made by dalloc (null: nothing).
+void dfree(tmg_ctx *c, void *p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < c->allocs.size(); ++i)
+        if (c->allocs[i] == p) {
+            c->allocs[i] = c->allocs.back();
+            c->allocs.pop_back();
+            break;
+        }
+    (void)hipFree(p);
 }
 
 bool participates(const tmg_ctx *c, int j, int level, int kind)
@@ -450,6 +465,10 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
     c->cur.assign(c->Lmax + 1, 0);
     const int dp = down_first == 1 ? kPair1 : kPair2, ds = down_first == 1 ? kSingle1 : kSingle2;
     for (int l = down_first; l < c->Lmax; ++l) {
+        if (!c->pairs) {
+            if ((rc = enqueue_down<T>(c, io, l, true, s))) return rc;
+            continue;
+        }
         if ((rc = enqueue_pair<T>(c, io, l, true, dp, s)) ||
             (rc = enqueue_down<T>(c, io, l, true, s, ds)))
             return rc;
@@ -458,6 +477,10 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
         if ((rc = enqueue_bottom<T>(c, io, l, nullptr, L.x(l, 0), s))) return rc;
     const int kp = up_first == 1 ? kPair1 : kPair2, ks = up_first == 1 ? kSingle1 : kSingle2;
     for (int l = c->Lmax - 1; l >= up_first; --l) {
+        if (!c->pairs) {
+            if ((rc = enqueue_up<T>(c, io, l, true, s))) return rc;
+            continue;
+        }
         if ((rc = enqueue_pair<T>(c, io, l, false, kp, s)) ||
             (rc = enqueue_up<T>(c, io, l, true, s, ks)))
             return rc;
@@ -801,6 +824,86 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     return status;
 }
 
+// The bottom cap of a schedule id (-1: the largest the bottom kernel holds).
+int64_t schedule_cap(int P, int schedule)
+{
+    return schedule < 0 ? (int64_t)bottom_max(P)
+                        : std::min<int64_t>(bottom_max(P), int64_t(1) << std::min(schedule, 40));
+}
+
+// First bottom-kernel level of every instance for a bottom cap: the first
+// level of at most `cap` slabs (the coarsest level at the latest).
+int plan_levels(const std::vector<int> &L, const int64_t *n_slabs, int64_t cap,
+                std::vector<int> *lb)
+{
+    lb->assign(L.size(), 0);
+    for (size_t j = 0; j < L.size(); ++j) {
+        int l = 0;
+        while (l < L[j] - 1 && (n_slabs[j] >> l) > cap) ++l;
+        if (L[j] - l > kBottomMaxLevels) return TMG_ERR_SIZE;
+        (*lb)[j] = l;
+    }
+    return TMG_OK;
+}
+
+// Install a schedule: the split of every hierarchy between the streaming
+// kernels and the bottom kernel (bottom cap) and whether V-cycles use
+// two-level launches.  Drops the captured graphs and tile lists of the old
+// schedule and sizes the buffers that depend on it.
+int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, hipStream_t s)
+{
+    std::vector<int> lbv;
+    int rc = plan_levels(c->L, c->N.data(), cap, &lbv);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (auto &kv : c->tiles) dfree(c, kv.second.d_off);
+    c->tiles.clear();
+    for (int *p : c->bot_d) dfree(c, p);
+    const int Lm = c->Lmax, batch = c->batch, P = c->P;
+    c->lb = lbv;
+    c->bottom_cap = cap;
+    c->pairs = pairs;
+    c->deep_n.assign(Lm + 1, 0);
+    c->bot_n.assign(Lm + 1, 0);
+    c->bot_d.assign(Lm + 1, nullptr);
+    for (int l = 0; l < Lm; ++l) {
+        std::vector<int> bl;
+        for (int j = 0; j < batch; ++j) {
+            if (c->lb[j] == l) bl.push_back(j);
+            if (l < c->lb[j]) c->deep_n[l]++;
+        }
+        c->bot_n[l] = (int)bl.size();
+        if (!bl.empty()) {
+            if ((rc = dalloc(c, &c->bot_d[l], bl.size()))) return rc;
+            HIPCHK(c, hipMemcpyAsync(c->bot_d[l], bl.data(), sizeof(int) * bl.size(),
+                                     hipMemcpyHostToDevice, s));
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    // level-0 halo buffers: one slot of H x P doubles per tile
+    const int Hs[5] = {c->H_fused(), c->H_up(), c->H_mix(), c->H_mixv(), c->H_mixd()};
+    int64_t hsize = 0;
+    for (int H : Hs) hsize = std::max(hsize, tiles_of(c, 0, kDeep, c->TO(H)) * H * P);
+    // two-level passes (kDeepNext) and one-level passes (kDeepLast) of one
+    // cycle use disjoint slots
+    c->hb_last_off = tiles_of(c, 0, kDeepNext, c->TO(c->H_fused2())) * c->H_fused2() * P;
+    hsize = std::max(hsize, c->hb_last_off +
+                                tiles_of(c, 0, kDeepLast, c->TO(c->H_fused())) * c->H_fused() * P);
+    if (hsize > c->hb_cap) {
+        dfree(c, c->hb[0]);
+        dfree(c, c->hb[1]);
+        c->hb[0] = c->hb[1] = nullptr;
+        if ((rc = dalloc(c, &c->hb[0], hsize)) || (rc = dalloc(c, &c->hb[1], hsize))) return rc;
+        c->hb_cap = hsize;
+    }
+    if (c->fuse_up1() && c->deep_n[1] > 0 && !c->f1b &&
+        (rc = dalloc(c, &c->f1b, c->level_size[1])))
+        return rc;
+    return TMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -870,15 +973,10 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     // bottom kernel (schedule >= 0: bottom_cap = 2^schedule, capped); an
     // instance's coarsest level always does
     const int P = o.p + 1;
-    const int64_t bottom_cap =
-        o.schedule < 0 ? (int64_t)bottom_max(P)
-                       : std::min<int64_t>(bottom_max(P), int64_t(1) << std::min(o.schedule, 40));
-    std::vector<int> lbv(batch, 0);
-    for (int j = 0; j < batch; ++j) {
-        int l = 0;
-        while (l < L[j] - 1 && (n_slabs[j] >> l) > bottom_cap) ++l;
-        if (L[j] - l > kBottomMaxLevels) return TMG_ERR_SIZE;
-        lbv[j] = l;
+    const int64_t bottom_cap = schedule_cap(P, o.schedule);
+    {
+        std::vector<int> lbv;
+        if (plan_levels(L, n_slabs, bottom_cap, &lbv)) return TMG_ERR_SIZE;
     }
     tmg_ctx *c = new (std::nothrow) tmg_ctx;
     if (!c) return TMG_ERR_OOM;
@@ -891,8 +989,6 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     c->T.assign(T, T + batch);
     c->lam.assign(lambda, lambda + batch);
     c->L = L;
-    c->lb = lbv;
-    c->bottom_cap = bottom_cap;
     c->Lmax = *std::max_element(L.begin(), L.end());
     const int Lm = c->Lmax;
     const TabLayout TL(P);
@@ -917,30 +1013,15 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     c->s.f.assign(Lm + 1, nullptr);
     c->s.xa.assign(Lm + 1, nullptr);
     c->s.xb.assign(Lm + 1, nullptr);
-    c->deep_n.assign(Lm + 1, 0);
-    c->bot_n.assign(Lm + 1, 0);
-    c->bot_d.assign(Lm + 1, nullptr);
     for (int l = 0; l < Lm; ++l) {
         auto &off = c->slab_off_h[l];
-        std::vector<int> bl;
-        for (int j = 0; j < batch; ++j) {
-            off[j + 1] = off[j] + (l < L[j] ? (c->N[j] >> l) : 0);
-            if (c->lb[j] == l) bl.push_back(j);
-            if (l < c->lb[j]) c->deep_n[l]++;
-        }
+        for (int j = 0; j < batch; ++j) off[j + 1] = off[j] + (l < L[j] ? (c->N[j] >> l) : 0);
         c->level_size[l] = off[batch] * P;
-        c->bot_n[l] = (int)bl.size();
         if ((rc = dalloc(c, &c->slab_off_d[l], batch + 1))) return fail(rc);
         if (hipMemcpyAsync(c->slab_off_d[l], off.data(), sizeof(int64_t) * (batch + 1),
-                           hipMemcpyHostToDevice, s) != hipSuccess)
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
             return fail(TMG_ERR_HIP);
-        if (!bl.empty()) {
-            if ((rc = dalloc(c, &c->bot_d[l], bl.size()))) return fail(rc);
-            if (hipMemcpyAsync(c->bot_d[l], bl.data(), sizeof(int) * bl.size(),
-                               hipMemcpyHostToDevice, s) != hipSuccess)
-                return fail(TMG_ERR_HIP);
-        }
-        if (hipStreamSynchronize(s) != hipSuccess) return fail(TMG_ERR_HIP);
         // coarse-level buffers in the precision of the cycle below level 0
         if (l > 0 && !c->mixed) {
             if ((rc = dalloc(c, &c->d.f[l], c->level_size[l])) ||
@@ -955,21 +1036,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                 return fail(rc);
         }
     }
-    // level-0 halo buffers: one slot of H x P doubles per tile
-    {
-        const int Hs[5] = {c->H_fused(), c->H_up(), c->H_mix(), c->H_mixv(), c->H_mixd()};
-        int64_t hsize = 0;
-        for (int H : Hs) hsize = std::max(hsize, tiles_of(c, 0, kDeep, c->TO(H)) * H * P);
-        // two-level passes (kDeepNext) and one-level passes (kDeepLast) of
-        // one cycle use disjoint slots
-        c->hb_last_off = tiles_of(c, 0, kDeepNext, c->TO(c->H_fused2())) * c->H_fused2() * P;
-        hsize = std::max(hsize, c->hb_last_off +
-                                    tiles_of(c, 0, kDeepLast, c->TO(c->H_fused())) * c->H_fused() * P);
-        if ((rc = dalloc(c, &c->hb[0], hsize)) || (rc = dalloc(c, &c->hb[1], hsize)))
-            return fail(rc);
-        if (c->fuse_up1() && c->deep_n[1] > 0 && (rc = dalloc(c, &c->f1b, c->level_size[1])))
-            return fail(rc);
-    }
+    if ((rc = apply_plan(c, bottom_cap, true, s))) return fail(rc);
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
         ta((size_t)Lm * batch * c->tab_stride, 0.0);
@@ -1078,6 +1145,60 @@ int tmg_adjoint_solve(tmg_handle c, const double *g, const double *u, double *z,
         }
     }
     return st;
+}
+
+int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int64_t *cap_out,
+                 int *pairs_out, tmg_stream stream)
+{
+    if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    struct Cand {
+        int64_t cap;
+        bool pairs;
+    };
+    std::vector<Cand> cands;
+    for (int k = 0; k <= 5; ++k) {
+        const int64_t cap = (int64_t)bottom_max(c->P) >> k;
+        if (cap < c->opt.n_coarse) break;
+        cands.push_back({cap, true});
+        if (c->opt.gamma == 1) cands.push_back({cap, false});
+    }
+    const Cand old{c->bottom_cap, c->pairs};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int rc = TMG_OK;
+    float best = -1.0f;
+    Cand pick = old;
+    constexpr int kCycles = 3;
+    for (const Cand &cd : cands) {
+        if (apply_plan(c, cd.cap, cd.pairs, s) != TMG_OK) continue;
+        // a run that captures the graphs, then a timed one (rtol 0: every
+        // instance runs kCycles cycles)
+        rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
+        if (rc < 0) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = TMG_ERR_HIP; break; }
+        rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
+        if (rc < 0) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = TMG_ERR_HIP;
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            pick = cd;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int rc2 = apply_plan(c, pick.cap, pick.pairs, s);
+    if (rc < 0) return rc;
+    if (rc2 != TMG_OK) return rc2;
+    if (cap_out) *cap_out = pick.cap;
+    if (pairs_out) *pairs_out = pick.pairs ? 1 : 0;
+    return TMG_OK;
 }
 
 int tmg_level_info(tmg_handle c, int j, int level, int64_t *n, double *alpha, double *omega)
