@@ -93,6 +93,7 @@ struct tmg_ctx {
     double *hb[2] = {nullptr, nullptr};           // level-0 halo buffers
     int64_t hb_last_off = 0;                      // slots of the one-level pass next to a two-level one
     double *f1b = nullptr;                        // second level-1 right-hand side (two-level passes)
+    float *f1b32 = nullptr;                       // the same for the FP32-inner cycle
     int64_t hb_cap = 0;                           // doubles allocated per halo buffer
     bool pairs = true;                            // two-level launches in V-cycles (schedule)
     double *tab_fwd = nullptr, *tab_adj = nullptr;
@@ -150,10 +151,20 @@ struct tmg_ctx {
     }
     // V-cycle solves in FP64 fuse level 1's legs into the level-0 pass
     bool fuse_up1() const { return opt.gamma == 1 && !mixed && pairs; }
+    // the same for the FP32-inner defect correction
+    bool fuse_mix() const { return opt.gamma == 1 && mixed && pairs; }
     // mixed precision, level 0: first down pass, fused pass, single cycle
     int H_mixd() const { return rs(opt.nu1 + 2); }
     int H_mix() const { return rs(2 * opt.nu1 + opt.nu2 + 3); }
     int H_mixv() const { return rs(opt.nu1 + opt.nu2 + 1); }
+    // their two-level forms (level 1's inner legs in the tiles; multiples of 4)
+    int r4(int x) const
+    {
+        const int q = S < 4 ? 4 : S;
+        return ((x + q - 1) / q) * q;
+    }
+    int H_mixd2() const { return r4(opt.nu1 + 2 + 2 * opt.nu1); }
+    int H_mix2() const { return r4(2 * opt.nu1 + opt.nu2 + 3 + 2 * (opt.nu1 + opt.nu2) + 2 * opt.nu1); }
     int TO(int H) const { return tile_slabs(P) - H; }
 };
 
@@ -526,35 +537,70 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.halo_out = c->hb[0];
         HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
     }
+    // two-level passes (as in the FP64 cycle): instances whose level 1
+    // streams run level 1's inner legs inside their level-0 passes, with
+    // level 1's right-hand side alternating between two buffers
+    const bool fuse = solve && c->fuse_mix() && c->deep_n[1] > 0;
+    float *f1_in = io.kind == kEven ? c->f1b32 : c->s.f[1];
+    float *f1_out = io.kind == kEven ? c->s.f[1] : c->f1b32;
+    auto two_level = [&](MixArgs &a) {
+        a.tab1 = tab_of(c, 1, io.trans);
+        a.tab1_32 = tabT_of<float>(c, 1, io.trans);
+        a.c2slab_off = c->slab_off_d[2];
+    };
     if (!solve || first) {
         // first inner down leg: residual of the iterate, FP32 sweeps, restriction
-        const int H = c->H_mixd();
-        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
-        MixArgs a = margs(H, tl);
-        a.u_in = first ? nullptr : io.u;
-        a.rc = c->s.f[1];
-        HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
+        for (int pass = fuse ? 0 : 1; pass < 2; ++pass) {
+            const bool two = pass == 0;
+            const int H = two ? c->H_mixd2() : c->H_mixd();
+            if ((rc = get_tiles(c, 0, fuse ? (two ? kDeepNext : kDeepLast) : kDeep, c->TO(H), s,
+                                &tl)))
+                return rc;
+            if (tl->ntiles == 0) continue;
+            MixArgs a = margs(H, tl);
+            a.u_in = first ? nullptr : io.u;
+            a.rc = c->s.f[1];
+            if (two) {
+                two_level(a);
+                a.f2 = c->s.f[2];
+            }
+            HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
+        }
     }
-    if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<float>(c, io, 1, 1, s)
-                                : enqueue_coarse_visits<float>(c, io, 1, s)))
+    if ((rc = c->opt.gamma == 1
+                  ? enqueue_vcycle_levels<float>(c, io, fuse ? 2 : 1, fuse ? 2 : 1, s)
+                  : enqueue_coarse_visits<float>(c, io, 1, s)))
         return rc;
-    const int H = solve ? c->H_mix() : c->H_mixv();
-    if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
-    MixArgs a = margs(H, tl);
-    a.up = 1;
-    a.u_in = first ? nullptr : io.u;
-    a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]);
-    a.e = c->s.x(1, c->cur[1]);
-    a.u_out = io.u;
-    if (solve) {
-        a.halo_out = io.kind == kEven ? c->hb[1] : c->hb[0];
-        a.rc = c->s.f[1];
-        a.partial = c->partial;
-        a.norm_off = tl->d_off;
+    for (int pass = fuse ? 0 : 1; pass < 2; ++pass) {
+        const bool two = pass == 0;
+        const int H = two ? c->H_mix2() : (solve ? c->H_mix() : c->H_mixv());
+        if ((rc = get_tiles(c, 0, fuse ? (two ? kDeepNext : kDeepLast) : kDeep, c->TO(H), s, &tl)))
+            return rc;
+        if (tl->ntiles == 0) continue;
+        const int64_t hoff = fuse && !two ? c->hb_last_off : 0;
+        MixArgs a = margs(H, tl);
+        a.up = 1;
+        a.u_in = first ? nullptr : io.u;
+        a.halo_in = first ? nullptr : (io.kind == kOdd ? c->hb[1] : c->hb[0]) + hoff;
+        if (two) {
+            two_level(a);
+            a.f1 = f1_in;
+            a.e2 = c->s.x(2, c->cur[2]);
+        } else {
+            a.e = c->s.x(1, c->cur[1]);
+        }
+        a.u_out = io.u;
+        if (solve) {
+            a.halo_out = (io.kind == kEven ? c->hb[1] : c->hb[0]) + hoff;
+            a.rc = two ? f1_out : c->s.f[1];
+            a.f2 = two ? c->s.f[2] : nullptr;
+            a.partial = c->partial;
+            a.norm_off = tl->d_off;
+        }
+        HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
+        if (solve && io.use_state)
+            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
     }
-    HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
-    if (solve && io.use_state)
-        HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
     return TMG_OK;
 }
 
@@ -659,7 +705,11 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
         (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_fused()), s, &tl)))
         return rc;
     if ((rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_dpair()), s, &tl)) ||
-        (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_down()), s, &tl)))
+        (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_down()), s, &tl)) ||
+        (rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_mixd2()), s, &tl)) ||
+        (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_mixd()), s, &tl)) ||
+        (rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_mix2()), s, &tl)) ||
+        (rc = get_tiles(c, 0, kDeepLast, c->TO(c->H_mix()), s, &tl)))
         return rc;
     for (int l = 1; l < c->Lmax; ++l)
         if ((rc = get_tiles(c, l, kPair1, c->TO(c->H_dpair()), s, &tl)) ||
@@ -888,9 +938,9 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, hipStream_t s)
     for (int H : Hs) hsize = std::max(hsize, tiles_of(c, 0, kDeep, c->TO(H)) * H * P);
     // two-level passes (kDeepNext) and one-level passes (kDeepLast) of one
     // cycle use disjoint slots
-    c->hb_last_off = tiles_of(c, 0, kDeepNext, c->TO(c->H_fused2())) * c->H_fused2() * P;
-    hsize = std::max(hsize, c->hb_last_off +
-                                tiles_of(c, 0, kDeepLast, c->TO(c->H_fused())) * c->H_fused() * P);
+    const int Hn = c->mixed ? c->H_mix2() : c->H_fused2(), Hl = c->mixed ? c->H_mix() : c->H_fused();
+    c->hb_last_off = tiles_of(c, 0, kDeepNext, c->TO(Hn)) * Hn * P;
+    hsize = std::max(hsize, c->hb_last_off + tiles_of(c, 0, kDeepLast, c->TO(Hl)) * Hl * P);
     if (hsize > c->hb_cap) {
         dfree(c, c->hb[0]);
         dfree(c, c->hb[1]);
@@ -900,6 +950,9 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, hipStream_t s)
     }
     if (c->fuse_up1() && c->deep_n[1] > 0 && !c->f1b &&
         (rc = dalloc(c, &c->f1b, c->level_size[1])))
+        return rc;
+    if (c->fuse_mix() && c->deep_n[1] > 0 && !c->f1b32 &&
+        (rc = dalloc(c, &c->f1b32, c->level_size[1])))
         return rc;
     return TMG_OK;
 }

@@ -131,7 +131,15 @@ struct MixArgs {
     const int64_t *cslab_off;
     const int64_t *tile_off;
     const InstState *st;
-    const int64_t *c2slab_off; // unused (null)
+    // two-level pass (as in LegArgsT): level 1's inner up leg computed in the
+    // tile from f1 and the level-2 inner correction e2 instead of reading e,
+    // and level 1's next inner down leg restricted into f2
+    const float *f1;
+    const float *e2;
+    float *f2;
+    const double *tab1;      // level-1 tables, FP64 and FP32
+    const float *tab1_32;
+    const int64_t *c2slab_off; // [batch+1] slab offsets of level 2
     int64_t n0;
     int batch, tab_stride, halo, tile_out, pre, post, next;
     int up;                  // 1: residual, inner up leg and update before the rest

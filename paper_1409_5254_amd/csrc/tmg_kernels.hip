@@ -841,21 +841,41 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
     const TileRef tr = tile_ref(a);
     const int li0 = threadIdx.x * S;
     const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
+    constexpr int SC2 = SC >= 2 ? SC / 2 : 1;
     double f[S][P], u[S][P], r[S][P];
-    float e[SC][P];
+    float e[SC][P], f1[SC][P], e2[SC2][P];
+    const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+    const int64_t c2m0 = SC >= 2 ? cm0 / 2 : (cm0 >> 1);
     load_chunk<P, S, BW, double>(a.f + tr.off * P, m0, tr.N, f);
     load_iterate<P, S, BW, double>(u, a.u_in, a.halo_in, tr, m0, li0, a.halo);
-    if (a.up) {
-        const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
+    if (a.up && a.e2) {
+        load_chunk<P, SC, BW, float>(a.f1 + tr.coff * P, cm0, tr.Nc, f1);
+        load_chunk<P, SC2, BW, float>(a.e2 + tr.c2off * P, c2m0, tr.Nc2, e2);
+    } else if (a.up) {
         load_chunk<P, SC, BW, float>(a.e + tr.coff * P, cm0, tr.Nc, e);
     }
     const int done = a.st ? a.st[tr.j].done : 0;
     LazyOps<P, float> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tab32 + (int64_t)tr.j * a.tab_stride);
+    LazyOps<P, float> op1;   // level 1 (two-level pass)
+    op1.load(a.tab1 + (int64_t)tr.j * a.tab_stride, a.tab1_32 + (int64_t)tr.j * a.tab_stride);
     if (done) return;
     if (a.u0) fold_u0<P, S, double>(f, m0, a.u0[tr.j], op);   // in FP64
     int phase = 0;
     float rf[S][P], g[S][P], ei[S][P];
+    if (a.up && a.e2) {
+        // level 1's inner up leg on the tile's coarse slabs (FP32; its first
+        // slabs see a zero left neighbour, the halo absorbs them)
+        float g1[SC][P];
+        apply_G<P, SC, float>(g1, f1, op1);
+#pragma unroll
+        for (int s = 0; s < SC; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) e[s][k] = 0.0f;
+        sweeps<P, SC, kLegWaves, float>(e, g1, op1, a.pre, xchg, phase);
+        prolong_add<P, SC, float>(e, e2, a.R32, cm0);
+        sweeps<P, SC, kLegWaves, float>(e, g1, op1, a.post, xchg, phase);
+    }
     if (a.up) {
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
 #pragma unroll
@@ -890,7 +910,25 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
         apply_G<P, S, float>(g, rf, op);
         sweeps<P, S, kLegWaves, float>(ei, g, op, a.next, xchg, phase);
         residual<P, S, kLegWaves>(r, ei, rf, op, xchg, phase);
-        restrict_store<P, S, BW, float>(r, a.R32, a.rc + tr.coff * P, m0, tr.N, tr.Nc, li0, a.halo);
+        static_assert(S >= 2, "streaming tiles hold whole coarse slabs per thread");
+        float rc1[SC][P];
+        restrict_pairs<P, S, float>(r, a.R32, rc1);
+        store_chunk<P, SC, BW, float>(a.rc + tr.coff * P, cm0, tr.Nc, rc1, li0 / 2, a.halo / 2);
+        if (a.f2) {
+            // level 1's next inner down leg (FP32 sweeps from zero, residual
+            // in FP64 arithmetic) restricted into f2
+            float g1[SC][P], x1[SC][P];
+            apply_G<P, SC, float>(g1, rc1, op1);
+#pragma unroll
+            for (int s = 0; s < SC; ++s)
+#pragma unroll
+                for (int k = 0; k < P; ++k) x1[s][k] = 0.0f;
+            sweeps<P, SC, kLegWaves, float>(x1, g1, op1, a.pre, xchg, phase);
+            double r1[SC][P];
+            residual<P, SC, kLegWaves>(r1, x1, rc1, op1, xchg, phase);
+            restrict_store<P, SC, BW, float>(r1, a.R32, a.f2 + tr.c2off * P, cm0, tr.Nc, tr.Nc2,
+                                             li0 / 2, a.halo / 2);
+        }
     }
 }
 
