@@ -67,7 +67,9 @@ struct GraphKey {
 };
 
 // graph kinds: the first cycle of a solve, and later cycles by halo parity
-enum { kFirst = 0, kEven = 1, kOdd = 2 };
+// kEvenOdd / kEvenOdd2: one / two pairs of an even and an odd cycle in one
+// graph (each graph launch costs the GPU ~8 us between cycles)
+enum { kFirst = 0, kEven = 1, kOdd = 2, kEvenOdd = 3, kEvenOdd2 = 4 };
 
 // Level buffers of one precision: right-hand side and two iterates per level.
 template <typename T>
@@ -732,15 +734,21 @@ int get_graph(tmg_ctx *c, const CycleIO &io, hipGraphExec_t *out)
         *out = it->second;
         return TMG_OK;
     }
-    if (c->graphs.size() >= 24) {
-        for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-        c->graphs.clear();
-    }
     int rc = make_tiles(c, c->cap);
     if (rc) return rc;
     hipGraph_t g;
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_cycle(c, io, c->cap);
+    if (io.kind == kEvenOdd || io.kind == kEvenOdd2) {
+        CycleIO e = io, o = io;
+        e.kind = kEven;
+        o.kind = kOdd;
+        for (int r = 0; r < (io.kind == kEvenOdd2 ? 2 : 1) && !rc; ++r) {
+            rc = enqueue_cycle(c, e, c->cap);
+            if (!rc) rc = enqueue_cycle(c, o, c->cap);
+        }
+    } else {
+        rc = enqueue_cycle(c, io, c->cap);
+    }
     hipError_t ee = hipStreamEndCapture(c->cap, &g);
     if (rc) return rc;
     HIPCHK(c, ee);
@@ -787,8 +795,19 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
                             c->slab_off_d[0], tl->d_off, c->batch, c->partial, tl->ntiles, s));
     HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 1, s));
 
-    hipGraphExec_t g[3];
-    for (int k = 0; k < 3; ++k) {
+    // graphs are kept per set of arrays; a full cache is emptied before the
+    // five graphs of this solve are fetched, never between them
+    hipGraphExec_t g[5];
+    if (c->graphs.size() + 5 > 30) {
+        bool have = true;
+        for (int k = 0; k < 5; ++k)
+            have = have && c->graphs.count(GraphKey{k, trans, f, u0, u}) > 0;
+        if (!have) {
+            for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+            c->graphs.clear();
+        }
+    }
+    for (int k = 0; k < 5; ++k) {
         CycleIO io{f, u0, u, trans, true, k};
         if ((rc = get_graph(c, io, &g[k]))) return rc;
     }
@@ -847,10 +866,22 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         }
         if (all || launched >= max_cycles) break;
         need = std::min(need, max_cycles - launched);
-        for (int k = 0; k < need; ++k) {
-            // cycle n >= 2 reads the halo buffer cycle n-1 wrote
-            HIPCHK(c, hipGraphLaunch(g[(launched % 2 == 1) ? kEven : kOdd], s));
-            ++launched;
+        for (int k = 0; k < need;) {
+            // cycle n >= 2 reads the halo buffer cycle n-1 wrote; an even and
+            // the following odd cycle share one graph launch
+            if (launched % 2 == 1 && need - k >= 4) {
+                HIPCHK(c, hipGraphLaunch(g[kEvenOdd2], s));
+                launched += 4;
+                k += 4;
+            } else if (launched % 2 == 1 && need - k >= 2) {
+                HIPCHK(c, hipGraphLaunch(g[kEvenOdd], s));
+                launched += 2;
+                k += 2;
+            } else {
+                HIPCHK(c, hipGraphLaunch(g[(launched % 2 == 1) ? kEven : kOdd], s));
+                ++launched;
+                ++k;
+            }
         }
     }
     int status = TMG_OK;

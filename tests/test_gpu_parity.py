@@ -394,3 +394,18 @@ def test_fused2_level0_pass(p, trans):
     assert relerr(host(d_out), post) <= TOL
     assert relerr(host(d_rc), ref_rc) <= TOL
     assert relerr(host(d_f2), ref_f2) <= TOL
+
+
+def test_many_array_sets_on_one_handle():
+    """Solves on more distinct (f, u) arrays than the handle keeps graphs
+    for: each solve still equals the oracle (the graph cache is emptied only
+    between solves, never between the graphs one solve launches)."""
+    rng = np.random.default_rng(11)
+    p, N, T, lam = 1, 512, 3.0, 0.7
+    s = B().Solver([N], [T], [lam], p=p)
+    for i in range(9):
+        f = rand(rng, N * (p + 1)) * 0.1
+        res = s.solve(dev(f), dev([0.5]), rtol=1e-10)
+        uo, k, _, _ = core.solve(p, T, lam, 0.5, f)
+        assert res.status == 0 and res.cycles[0] == k
+        assert relerr(host(res.u), uo) <= TOL
