@@ -267,16 +267,18 @@ def test_bottom_wavefront_levels(p, gamma, trans):
         assert relerr(Z[s.offsets[j]:s.offsets[j + 1]], zo) <= TOL
 
 
-@pytest.mark.parametrize("p", [1, 2])
-def test_adjoint_solve_and_gradients(p):
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("schedule", [-1, 4])
+def test_adjoint_solve_and_gradients(p, schedule):
     """tmg_adjoint_solve equals the oracle's multigrid solve of L^T z = g and
     its gradients equal the oracle's (which are pinned to finite
-    differences)."""
+    differences).  Schedule 4 (levels of more than 16 slabs stream) runs the
+    backward two-level level-0 pass and the paired levels."""
     rng = np.random.default_rng(60 + p)
-    N, T, lam, u0 = 1024, 4.0, 1.7, 0.9
+    N, T, lam, u0 = 4096, 16.0, 1.7, 0.9
     f = rand(rng, N * (p + 1)) * 0.1
     y = rng.standard_normal(N)
-    s = B().Solver([N], [T], [lam], p=p)
+    s = B().Solver([N], [T], [lam], p=p, schedule=schedule)
     fw = s.solve(dev(f), dev([u0]), rtol=1e-12)
     u = host(fw.u)
     g, _ = core.adjoint_rhs(p, u, y)
