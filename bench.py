@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: DG time-unknowns solved per second to relative residual 1e-10.
 
-Default workload (one MI355X; `--config 2`): u' + u = f on (0, 1000],
+Default workload (one MI355X; `--workload scalar`): u' + u = f on (0, 1000],
 u0 = 1, N = 2^22 uniform slabs, DG degree p (default 3; --p), Legendre basis,
 f a seeded 16-mode random Fourier series; V(2,2) cycle (or --cycle W),
 coarsening by 2 down to 2 slabs, solved from u = 0 to ||r|| <= 1e-10 ||r_0||.
@@ -13,12 +13,12 @@ on its launch stream, the FP64 CPU oracle timed on a bounded sample of the
 same workload, and the FP32-inner defect correction against the plain FP64
 cycle on the large scalar workload (N = 2^24, p = 3).
 
-Other configurations (`--config`):
-  3  4096 eigenmode instances of uneven length (batched, one handle);
-  4  256 instances, N = 2^20, p = 2: forward solve + adjoint solve +
-     gradients (the backward pass of the autograd function);
-  5  N = 2^24, p = 3, FP64 cycle against FP32-inner defect correction, scalar
-     and a batch of 64.
+Other workloads (`--workload`):
+  eigenmodes  4096 eigenmode instances of uneven length (batched, one handle);
+  adjoint     256 instances, N = 2^20, p = 2: forward solve + adjoint solve +
+              gradients (the backward pass of the autograd function);
+  long        N = 2^24, p = 3, T = 1e4: FP64 cycle against FP32-inner defect
+              correction, one instance and a batch of 64.
 """
 from __future__ import annotations
 
@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
+    ap.add_argument("--workload", default="scalar", choices=["scalar", "eigenmodes", "adjoint", "long"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick each handle's schedule with tmg_autotune before timing (1) or not")
     ap.add_argument("--cpu-log2n", type=int, default=21)
-    ap.add_argument("--batch", type=int, default=0, help="instances for --config 3/4/5 (0: default)")
+    ap.add_argument("--batch", type=int, default=0, help="instances of the batched workloads (0: default)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -84,10 +84,10 @@ def time_solves(fn, steps, warmup):
 
 
 # ---------------------------------------------------------------------------
-# config 2: scalar, lambda = 1
+# scalar Fourier load, lambda = 1
 # ---------------------------------------------------------------------------
 
-def config2_case(p, log2n, cycle, steps, warmup, precision=0):
+def scalar_case(p, log2n, cycle, steps, warmup, precision=0):
     import torch
     from paper_1409_5254_amd.binding import Solver
     from workloads import gen
@@ -178,7 +178,7 @@ def cpu_baseline(p, log2n):
     from workloads import gen
     N = 1 << log2n
     T = 1000.0 * N / (1 << 22)
-    inst = gen.config2(p, N=N, T=T).instances[0]
+    inst = gen.fourier_scalar(p, N=N, T=T).instances[0]
     t0 = time.perf_counter()
     _, k, rr, _ = core.solve(p, T, inst.lam, inst.u0, inst.f, rtol=1e-10)
     dt = time.perf_counter() - t0
@@ -188,17 +188,17 @@ def cpu_baseline(p, log2n):
 
 
 # ---------------------------------------------------------------------------
-# config 5: FP64 cycle against FP32-inner defect correction
+# long horizon: FP64 cycle against FP32-inner defect correction
 # ---------------------------------------------------------------------------
 
-def config5_compare(B, log2n, steps, warmup):
+def long_horizon_compare(B, log2n, steps, warmup):
     import torch
     from paper_1409_5254_amd.binding import Solver
     from workloads import gen
     p = 3
     N = 1 << log2n
     T = 1e4 * N / (1 << 24)
-    params = gen.config5_params(B)
+    params = gen.long_horizon_params(B)
     P = p + 1
     f = torch.empty(B * N * P, dtype=torch.float64, device="cuda")
     for j, (lam, a, phi) in enumerate(params):
@@ -232,15 +232,15 @@ def config5_compare(B, log2n, steps, warmup):
 
 
 # ---------------------------------------------------------------------------
-# config 3: batched eigenmodes
+# batched eigenmodes
 # ---------------------------------------------------------------------------
 
-def config3_run(n_inst, steps, warmup, precision=0):
+def eigenmode_run(n_inst, steps, warmup, precision=0):
     import numpy as np
     import torch
     from paper_1409_5254_amd.binding import Solver
     from workloads import gen
-    lam, Ns = gen.config3_sizes(n_inst)
+    lam, Ns = gen.eigenmode_sizes(n_inst)
     Ns = [int(n) for n in Ns]
     P = 2
     total = sum(Ns) * P
@@ -269,16 +269,16 @@ def config3_run(n_inst, steps, warmup, precision=0):
 
 
 # ---------------------------------------------------------------------------
-# config 4: adjoint / gradients
+# adjoint / gradients
 # ---------------------------------------------------------------------------
 
-def config4_run(B, steps, warmup):
+def adjoint_run(B, steps, warmup):
     import torch
     from paper_1409_5254_amd.binding import Solver
     from workloads import gen
     p, N, T = 2, 1 << 20, 100.0
     P = p + 1
-    params, rng = gen.config4_params(B)
+    params, rng = gen.adjoint_params(B)
     f = torch.empty(B * N * P, dtype=torch.float64, device="cuda")
     for j, (lam, a, phi) in enumerate(params):
         gen.fourier_load_torch(p, N, T, a, phi, out=f[j * N * P:(j + 1) * N * P])
@@ -326,25 +326,25 @@ def main():
     base = {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "unit": "unknowns/s", "metric": "DG time-unknowns solved/s to rel. residual 1e-10"}
-    if a.config == 3:
-        r = config3_run(a.batch or 4096, a.steps, a.warmup)
+    if a.workload == "eigenmodes":
+        r = eigenmode_run(a.batch or 4096, a.steps, a.warmup)
         print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
                           "config": {"workload": r["workload"]}, "result": r}))
         return
-    if a.config == 4:
-        r = config4_run(a.batch or 256, a.steps, a.warmup)
+    if a.workload == "adjoint":
+        r = adjoint_run(a.batch or 256, a.steps, a.warmup)
         print(json.dumps({**base, "value": r["unknowns_per_s"],
                           "ms_per_step": r["ms_per_forward_backward"],
                           "config": {"workload": r["workload"]}, "result": r}))
         return
-    if a.config == 5:
-        r1 = config5_compare(1, 24, a.steps, a.warmup)
-        rb = config5_compare(a.batch or 64, 24, max(1, a.steps // 3), 1)
+    if a.workload == "long":
+        r1 = long_horizon_compare(1, 24, a.steps, a.warmup)
+        rb = long_horizon_compare(a.batch or 64, 24, max(1, a.steps // 3), 1)
         print(json.dumps({**base, "value": rb["fp32_inner"]["unknowns_per_s"],
                           "ms_per_step": rb["fp32_inner"]["ms_per_solve"],
                           "config": {"workload": rb["workload"]}, "scalar": r1, "batch": rb}))
         return
-    head, ctx = config2_case(a.p, a.log2n, a.cycle, a.steps, a.warmup)
+    head, ctx = scalar_case(a.p, a.log2n, a.cycle, a.steps, a.warmup)
     roof = fused_pass_roofline(a.p, ctx, a.kernel_reps)
     roof["traffic"] = measured_traffic(a.p, a.log2n)
     del ctx
@@ -355,10 +355,10 @@ def main():
             if p == a.p:
                 sweep.append(head)
                 continue
-            r, c = config2_case(p, a.log2n, a.cycle, max(2, a.steps // 2), 1)
+            r, c = scalar_case(p, a.log2n, a.cycle, max(2, a.steps // 2), 1)
             del c
             sweep.append(r)
-    mixed = config5_compare(1, 24, max(2, a.steps // 3), 1) if a.mixed else None
+    mixed = long_horizon_compare(1, 24, max(2, a.steps // 3), 1) if a.mixed else None
     cpu = cpu_baseline(a.p, a.cpu_log2n) if a.cpu_baseline else None
     out = {
         **base,

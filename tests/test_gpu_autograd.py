@@ -2,7 +2,7 @@
 multigrid solve) against finite differences and torch.autograd.gradcheck.
 
 The loss is J = 1/2 sum_n (w_n - y_n)^2 with w_n = u_n(t_n^-) = sum_k u_n[k]
-(config 4's loss).  Forward solves for the differences run to a relative
+(the adjoint batch's loss).  Forward solves for the differences run to a relative
 residual of 1e-13 so that solve error times J/h stays below the check."""
 import numpy as np
 import pytest

@@ -49,7 +49,7 @@ def relerr(a, b):
 @pytest.mark.parametrize("schedule", [-1, 0])
 @pytest.mark.parametrize("gamma", [1, 2])
 def test_mixed_solve(p, schedule, gamma):
-    w = gen.config5(B=1, N=1 << 12, T=1e4 * 2 ** -12)
+    w = gen.long_horizon(B=1, N=1 << 12, T=1e4 * 2 ** -12)
     inst = w.instances[0]
     r = np.random.default_rng(5)
     f = gen.fourier_load(p, inst.N, inst.T, r.standard_normal(16), r.uniform(0, 2 * np.pi, 16))

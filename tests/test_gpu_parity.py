@@ -200,9 +200,9 @@ def test_solve_matches_oracle(p, opts):
     assert relerr(host(res.u), ud) <= 1e-8
 
 
-def test_config1_end_to_end():
+def test_fourier_small_end_to_end():
     """Config 1: u' + u = f on (0, 10], p = 1, N = 1024, V(2,2) to 1e-10."""
-    inst = gen.config1().instances[0]
+    inst = gen.fourier_small().instances[0]
     s = B().Solver([inst.N], [inst.T], [inst.lam], p=1)
     res = s.solve(dev(inst.f), dev([inst.u0]), rtol=1e-10)
     uo, k, rr, _ = core.solve(1, inst.T, inst.lam, inst.u0, inst.f)

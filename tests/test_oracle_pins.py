@@ -290,7 +290,7 @@ def test_optimal_damping_and_smoothing_bound(golden_dir):
                 assert np.max(np.abs(np.linalg.eigvals(S))) <= lemma8 + 1e-12
 
 
-def test_levels_and_damping_config1():
+def test_levels_and_damping_fourier_small():
     """Per-level alpha_l = R(-lam tau_l) and omega_l = omega*(alpha_l) on the
     hierarchy N, N/2, ..., 2 (config-1 sizes)."""
     al, om = core.levels(1, 1024, 10.0, 1.0)
@@ -358,11 +358,11 @@ def test_measured_two_grid_contraction(p, z, nu):
 # Multigrid solve, adjoint and mixed precision
 # --------------------------------------------------------------------------
 
-def test_vcycle_solve_config1():
+def test_vcycle_solve_fourier_small():
     """Stopping rule of section 4.2 (relative residual reduction): the V-cycle
     reaches 1e-10 and the result is within the residual bound of the direct
     solve."""
-    inst = gen.config1().instances[0]
+    inst = gen.fourier_small().instances[0]
     ud = core.direct_solve(1, inst.T, inst.lam, inst.u0, inst.f)
     u, k, rr, hist = core.solve(1, inst.T, inst.lam, inst.u0, inst.f)
     assert rr <= 1e-10 and 5 <= k <= 20
@@ -425,7 +425,7 @@ def test_mixed_precision_reference():
     """FP32 inner cycle with FP64 residual / coarsest solve / outer update
     reaches 1e-10 with (about) as many cycles as FP64 and the same solution
     to the tolerance."""
-    w = gen.config5(B=1, N=1 << 12, T=1e4 * 2 ** -12)
+    w = gen.long_horizon(B=1, N=1 << 12, T=1e4 * 2 ** -12)
     inst = w.instances[0]
     u64, k64, rr64, _ = core.solve(3, inst.T, inst.lam, inst.u0, inst.f)
     um, km, rrm, _ = core.solve_mixed(3, inst.T, inst.lam, inst.u0, inst.f)

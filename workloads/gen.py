@@ -6,16 +6,17 @@ The load vector of slab n (length tau, midpoint c_n) is
 for the unnormalised Legendre basis; the initial value u0 is *not* folded in
 (the solver adds it to slab 0).  Layout: float64, [instance][slab][m].
 
-Recipes (seed = configuration number, draws in the order listed):
-  1  u'+u=f on (0,10], u0=1, p=1, N=1024; f = sum_{k=1..8} a_k sin(k t + phi_k),
+Recipes (name, seed; draws in the order listed):
+  fourier_small (1)      u'+u=f on (0,10], u0=1, p=1, N=1024; f = sum_{k=1..8} a_k sin(k t + phi_k),
      a = standard_normal(8), then phi = uniform(0, 2pi, 8).
-  2  lambda=1, T=1000, u0=1, N=2^22, p in {0..3}; same form with 16 modes.
-  3  4096 instances: kappa = uniform(0.01, 1) (one draw), lambda_j = pi^2 j^2 kappa,
+  fourier_scalar (2)     lambda=1, T=1000, u0=1, N=2^22, p in {0..3}; same
+     form with 16 modes.
+  eigenmode_batch (3)    4096 instances: kappa = uniform(0.01, 1) (one draw), lambda_j = pi^2 j^2 kappa,
      N_j = 2^integers(12, 19), T_j = 1, p = 1, u0 = 1; load vector M_tau c with
      c ~ standard_normal per (slab, coefficient), drawn instance by instance.
-  4  256 instances, N = 2^20, p = 2, T = 100: lambda_b = uniform(0.1, 10, 256),
+  adjoint_batch (4)      256 instances, N = 2^20, p = 2, T = 100: lambda_b = uniform(0.1, 10, 256),
      then per instance a (16), phi (16); then targets y ~ standard_normal(256 x N).
-  5  N = 2^24, p = 3, T = 1e4: lambda = uniform(0.5, 50, B) (B = 1 or 64), then
+  long_horizon (5)       N = 2^24, p = 3, T = 1e4: lambda = uniform(0.5, 50, B) (B = 1 or 64), then
      per instance a (16), phi (16).
 Smaller N (same recipe) serve the parity tests.
 """
@@ -28,8 +29,8 @@ import numpy as np
 
 __all__ = ["Instance", "Workload", "sph_jn", "fourier_load", "fourier_load_torch",
            "quadrature_load",
-           "gaussian_legendre_load", "config1", "config2", "config3", "config4", "config5",
-           "fourier_batch", "fourier_params", "config3_sizes", "config4_params", "config5_params"]
+           "gaussian_legendre_load", "fourier_small", "fourier_scalar", "eigenmode_batch", "adjoint_batch", "long_horizon",
+           "fourier_batch", "fourier_params", "eigenmode_sizes", "adjoint_params", "long_horizon_params"]
 
 
 def sph_jn(m: int, x: np.ndarray) -> np.ndarray:
@@ -127,30 +128,30 @@ class Workload:
     name: str
     p: int
     instances: list = field(default_factory=list)
-    targets: list | None = None     # per-instance y (config 4)
+    targets: list | None = None     # per-instance targets y (adjoint batch)
 
     @property
     def unknowns(self) -> int:
         return sum(i.N * (i.p + 1) for i in self.instances)
 
 
-def config1(N: int = 1024, seed: int = 1) -> Workload:
+def fourier_small(N: int = 1024, seed: int = 1) -> Workload:
     rng = np.random.default_rng(seed)
     a = rng.standard_normal(8)
     phi = rng.uniform(0.0, 2.0 * math.pi, 8)
-    return Workload("cfg1", 1, [Instance(1, N, 10.0, 1.0, 1.0, fourier_load(1, N, 10.0, a, phi))])
+    return Workload("fourier_small", 1, [Instance(1, N, 10.0, 1.0, 1.0, fourier_load(1, N, 10.0, a, phi))])
 
 
-def config2(p: int, N: int = 1 << 22, T: float = 1000.0, seed: int = 2) -> Workload:
+def fourier_scalar(p: int, N: int = 1 << 22, T: float = 1000.0, seed: int = 2) -> Workload:
     """Scalar, lambda = 1.  The default T keeps tau = 1000 / 2^22 also when a
     smaller N is asked for only if T is scaled by the caller."""
     rng = np.random.default_rng(seed)
     a = rng.standard_normal(16)
     phi = rng.uniform(0.0, 2.0 * math.pi, 16)
-    return Workload(f"cfg2_p{p}", p, [Instance(p, N, T, 1.0, 1.0, fourier_load(p, N, T, a, phi))])
+    return Workload(f"fourier_scalar_p{p}", p, [Instance(p, N, T, 1.0, 1.0, fourier_load(p, N, T, a, phi))])
 
 
-def config3(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3, take=None) -> Workload:
+def eigenmode_batch(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3, take=None) -> Workload:
     """Eigenmode batch.  `take` (an iterable of instance indices) keeps a
     subset; draws for all n_inst instances are still made in order so that a
     subset equals the corresponding instances of the full batch."""
@@ -166,7 +167,7 @@ def config3(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3, take=None) -
             inst.append(Instance(1, int(Ns[j]), 1.0, float(lam[j]), 1.0, f))
         else:
             rng.standard_normal(int(Ns[j]) * 2)   # keep the stream aligned
-    return Workload("cfg3", 1, inst)
+    return Workload("eigenmode_batch", 1, inst)
 
 
 def fourier_batch(name: str, p: int, N: int, T: float, lam: np.ndarray, rng, modes: int = 16):
@@ -189,18 +190,18 @@ def fourier_params(lam: np.ndarray, rng, modes: int = 16):
     return out
 
 
-def config4_params(B: int = 256, seed: int = 4):
+def adjoint_params(B: int = 256, seed: int = 4):
     rng = np.random.default_rng(seed)
     return fourier_params(rng.uniform(0.1, 10.0, B), rng), rng
 
 
-def config5_params(B: int = 1, seed: int = 5):
+def long_horizon_params(B: int = 1, seed: int = 5):
     rng = np.random.default_rng(seed)
     return fourier_params(rng.uniform(0.5, 50.0, B), rng)
 
 
-def config3_sizes(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3):
-    """(lambda_j, N_j) of the eigenmode batch, drawn as in config3."""
+def eigenmode_sizes(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3):
+    """(lambda_j, N_j) of the eigenmode batch, drawn as in eigenmode_batch."""
     rng = np.random.default_rng(seed)
     kappa = rng.uniform(0.01, 1.0)
     lam = (math.pi ** 2) * (np.arange(1, n_inst + 1, dtype=np.float64) ** 2) * kappa
@@ -208,15 +209,15 @@ def config3_sizes(n_inst: int = 4096, log2_range=(12, 19), seed: int = 3):
     return lam, Ns
 
 
-def config4(B: int = 256, N: int = 1 << 20, T: float = 100.0, seed: int = 4) -> Workload:
+def adjoint_batch(B: int = 256, N: int = 1 << 20, T: float = 100.0, seed: int = 4) -> Workload:
     rng = np.random.default_rng(seed)
     lam = rng.uniform(0.1, 10.0, B)
-    w = fourier_batch("cfg4", 2, N, T, lam, rng)
+    w = fourier_batch("adjoint_batch", 2, N, T, lam, rng)
     w.targets = [rng.standard_normal(N) for _ in range(B)]
     return w
 
 
-def config5(B: int = 1, N: int = 1 << 24, T: float = 1e4, seed: int = 5) -> Workload:
+def long_horizon(B: int = 1, N: int = 1 << 24, T: float = 1e4, seed: int = 5) -> Workload:
     rng = np.random.default_rng(seed)
     lam = rng.uniform(0.5, 50.0, B)
-    return fourier_batch(f"cfg5_b{B}", 3, N, T, lam, rng)
+    return fourier_batch(f"long_horizon_b{B}", 3, N, T, lam, rng)
