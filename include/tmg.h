@@ -40,9 +40,14 @@
  * re-captured when the pointers change).  The handle owns its tables,
  * hierarchy buffers, graphs and streams.  Every call is ordered on the given
  * stream (a hipStream_t; NULL = the default stream).  tmg_solve and
- * tmg_adjoint_solve block until the solve has finished (they read residual
- * norms); tmg_vcycle and the tmg_op_* calls are asynchronous.  A handle must
- * not be used from two host threads at once.
+ * tmg_adjoint_solve return once every instance's outcome is known: the
+ * device copies each instance's state into pinned host memory after every
+ * cycle and the host follows it there while the stream runs.  Their result
+ * is complete in stream order (work enqueued later on the stream sees it;
+ * host reads need a synchronisation of the stream); cycles queued past
+ * convergence may still be in the stream and change nothing.
+ * tmg_vcycle and the tmg_op_* calls are asynchronous.  A handle must not be
+ * used from two host threads at once.
  *
  * ERRORS.  0 = TMG_OK; TMG_NOT_CONVERGED (> 0) when max_cycles was reached
  * (outputs valid, relres reports how far it got); negative codes are errors
@@ -118,7 +123,8 @@ int tmg_vcycle(tmg_handle h, const double *f, const double *u0, double *u, tmg_s
  * Solve L u = f from u = 0 with repeated cycles until every instance reaches
  * ||f - L u||_2 <= rtol ||f||_2 (u0 folded) or max_cycles.  cycles[batch]
  * and relres[batch] (host, may be NULL) receive per-instance counts and
- * final relative residuals.  Blocks until done.  Returns TMG_OK,
+ * final relative residuals.  Returns once every instance has finished (see
+ * the stream note above): TMG_OK,
  * TMG_NOT_CONVERGED, TMG_ERR_NONFINITE or TMG_ERR_DIVERGED (the worst
  * instance decides).
  */
@@ -133,7 +139,8 @@ int tmg_solve(tmg_handle h, const double *f, const double *u0, double *u, double
  * (the forward solution, device) is not NULL, also returns for each instance
  *   dlambda[j] = -sum_n z_n^T M_tau u_n   and   du0[j] = v^T z_1
  * (host arrays, may be NULL): the gradients of a loss J(u) with dJ/du = g
- * with respect to lambda and u0; dJ/df = z itself.  Blocks until done.
+ * with respect to lambda and u0; dJ/df = z itself.  Returns as tmg_solve
+ * does; blocks until done when gradients are asked for.
  */
 int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z, double rtol,
                       int max_cycles, double *dlambda, double *du0, int *cycles,
@@ -146,14 +153,27 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
  * events.  A schedule is the size up to which an instance's levels run inside
  * the single-work-group bottom kernel (bottom_cap, the largest the bottom
  * kernel holds divided by 1, 2, ..., 32) and, for V-cycles, whether
- * consecutive levels share two-level launches.  The solution is
- * the same under every schedule (up to rounding order); only the kernel
- * split changes.  u (device, same layout as f) is used as scratch and
- * overwritten.  *bottom_cap and *pairs (host, may be NULL) receive the
- * choice.  Blocks until done.
+ * consecutive levels share two-level launches; then, for the fastest of
+ * those, whether the cycles after the first of a solve are launched kernel
+ * by kernel instead of as captured graphs (a graph launch idles the GPU for
+ * several microseconds; direct launches pay when the host enqueues a cycle
+ * faster than the GPU runs it).  The solution is the same under every
+ * schedule (up to rounding order); only the kernel split and launch mode
+ * change.  u (device, same layout as f) is used as scratch and overwritten.
+ * *bottom_cap, *pairs and *direct (host, may be NULL) receive the choice.
+ * Blocks until done.
  */
 int tmg_autotune(tmg_handle h, const double *f, const double *u0, double *u, int64_t *bottom_cap,
-                 int *pairs, tmg_stream s);
+                 int *pairs, int *direct, tmg_stream s);
+
+/*
+ * Install a schedule (as chosen by tmg_autotune, e.g. on another handle of
+ * the same shape) without timing anything: bottom_cap in [n_coarse, the
+ * largest level the bottom kernel holds], pairs and direct as there.
+ * Returns TMG_ERR_INVALID for a bottom_cap out of that range.  Blocks until
+ * done.
+ */
+int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int direct, tmg_stream s);
 
 /* Release every resource of h (synchronises its streams first). */
 int tmg_destroy(tmg_handle h);

@@ -26,7 +26,7 @@ MAX_DEGREE = 3
 
 # every symbol the header declares
 SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",
-           "tmg_autotune",
+           "tmg_autotune", "tmg_set_schedule",
            "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
            "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
            "tmg_op_coarse_solve",
@@ -80,7 +80,8 @@ def lib():
             "tmg_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d), _vp]),
             "tmg_adjoint_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_d), P(_d), P(_i), P(_d),
                                        _vp]),
-            "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), _vp]),
+            "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), P(_i), _vp]),
+            "tmg_set_schedule": (_i, [_vp, _i64, _i, _i, _vp]),
             "tmg_destroy": (_i, [_vp]),
             "tmg_error_string": (ctypes.c_char_p, [_i]),
             "tmg_last_hip_error": (_i, [_vp]),
@@ -182,12 +183,19 @@ class Solver:
 
     def autotune(self, f, u0, u):
         """Pick the fastest schedule on (f, u0); u is overwritten.  Returns
-        (bottom_cap, pairs)."""
+        (bottom_cap, pairs, direct)."""
         cap = ctypes.c_int64()
         pairs = ctypes.c_int()
+        direct = ctypes.c_int()
         self._check(lib().tmg_autotune(self._h, _ptr(f), _ptr(u0), _ptr(u), ctypes.byref(cap),
-                                       ctypes.byref(pairs), _stream()), "tmg_autotune")
-        return cap.value, bool(pairs.value)
+                                       ctypes.byref(pairs), ctypes.byref(direct), _stream()),
+                    "tmg_autotune")
+        return cap.value, bool(pairs.value), bool(direct.value)
+
+    def set_schedule(self, bottom_cap, pairs=True, direct=False):
+        """Install a schedule without timing (see autotune)."""
+        self._check(lib().tmg_set_schedule(self._h, int(bottom_cap), int(bool(pairs)),
+                                           int(bool(direct)), _stream()), "tmg_set_schedule")
 
     def vcycle(self, f, u0, u):
         self._check(lib().tmg_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),

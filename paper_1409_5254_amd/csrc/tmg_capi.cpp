@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -98,6 +99,7 @@ struct tmg_ctx {
     float *f1b32 = nullptr;                       // the same for the FP32-inner cycle
     int64_t hb_cap = 0;                           // doubles allocated per halo buffer
     bool pairs = true;                            // two-level launches in V-cycles (schedule)
+    bool direct = false;                          // cycles after the first launched kernel by kernel
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
     float *tab32_fwd = nullptr, *tab32_adj = nullptr;  // the same tables rounded to FP32
@@ -110,8 +112,12 @@ struct tmg_ctx {
     std::vector<int> deep_n;                      // per level: instances with level < lb
     int64_t bottom_cap = 0;
     InstState *st = nullptr, *st_ops = nullptr;
-    InstState *st_host = nullptr;                 // pinned, two snapshots of batch states
+    InstState *st_host = nullptr;                 // pinned, batch states of the op calls
     Control *ctl = nullptr, *ctl_host = nullptr;  // device / pinned
+    HostState *mirror = nullptr, *mirror_d = nullptr;  // coherent pinned; host / device address
+    int epoch = 0;                                // solves started
+    hipEvent_t drain_ev = nullptr;                // recorded after the last launch of a solve
+    bool drain_pending = false;
     double *partial = nullptr;
     int64_t partial_cap = 0;
     double *tau_d = nullptr, *grad_d = nullptr, *grad_host = nullptr;
@@ -333,6 +339,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.nlev = c->nlev_d;
     a.st = io.use_state ? c->st : nullptr;
     a.ctl = c->ctl;
+    a.mirror = io.use_state ? c->mirror_d : nullptr;
     a.level = level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
@@ -601,7 +608,7 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         }
         HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
         if (solve && io.use_state)
-            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
+            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror_d, 0, s));
     }
     return TMG_OK;
 }
@@ -685,7 +692,7 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             }
             HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
             if (solve && io.use_state)
-                HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 0, s));
+                HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror_d, 0, s));
         }
     }
     return TMG_OK;
@@ -767,8 +774,19 @@ int check_level_args(tmg_ctx *c, int level)
     return TMG_OK;
 }
 
+// Waits for the cycles a solve left queued (launched past convergence; they
+// do nothing but read the state) before graphs or buffers they name go away.
+int drain(tmg_ctx *c)
+{
+    if (!c->drain_pending) return TMG_OK;
+    c->drain_pending = false;
+    HIPCHK(c, hipEventSynchronize(c->drain_ev));
+    return TMG_OK;
+}
+
 void free_all(tmg_ctx *c)
 {
+    (void)drain(c);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     for (void *p : c->allocs) (void)hipFree(p);
@@ -776,24 +794,44 @@ void free_all(tmg_ctx *c)
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->ctl_host) (void)hipHostFree(c->ctl_host);
     if (c->grad_host) (void)hipHostFree(c->grad_host);
+    if (c->mirror) (void)hipHostFree(c->mirror);
+    if (c->drain_ev) (void)hipEventDestroy(c->drain_ev);
     if (c->cap) (void)hipStreamDestroy(c->cap);
 }
 
 // Solve loop shared by tmg_solve and tmg_adjoint_solve.
+// A consistent copy of instance j's host-side state (HostState), or false
+// while the device is writing it.
+bool read_state(const HostState *h, HostState *out)
+{
+    const long long v1 = __atomic_load_n(&h->ver, __ATOMIC_ACQUIRE);
+    if (v1 & 1) return false;
+    out->cycles = __atomic_load_n(&h->cycles, __ATOMIC_RELAXED);
+    out->done = __atomic_load_n(&h->done, __ATOMIC_RELAXED);
+    __atomic_load(&h->r0sq, &out->r0sq, __ATOMIC_RELAXED);
+    __atomic_load(&h->rsq, &out->rsq, __ATOMIC_RELAXED);
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    const long long v2 = __atomic_load_n(&h->ver, __ATOMIC_RELAXED);
+    out->ver = v1;
+    return v1 == v2;
+}
+
 int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool trans, double rtol,
               int max_cycles, int *cycles, double *relres, hipStream_t s)
 {
     TileList *tl;
     int rc = get_tiles(c, 0, kAll, tile_slabs(c->P), s, &tl);
     if (rc) return rc;
+    c->epoch = c->epoch % (1 << 20) + 1;
+    const long long epoch = c->epoch;
     c->ctl_host->rtol2 = rtol * rtol;
     c->ctl_host->max_cycles = max_cycles;
-    c->ctl_host->pad = 0;
+    c->ctl_host->epoch = c->epoch;
     HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Control), hipMemcpyHostToDevice, s));
     // initial residual r_0 = f (u0 folded), u = 0
     HIPCHK(c, launch_norm_f(c->P, f, trans ? nullptr : u0, tab_of(c, 0, trans), c->tab_stride,
                             c->slab_off_d[0], tl->d_off, c->batch, c->partial, tl->ntiles, s));
-    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, 1, s));
+    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror_d, 1, s));
 
     // graphs are kept per set of arrays; a full cache is emptied before the
     // five graphs of this solve are fetched, never between them
@@ -803,90 +841,146 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         for (int k = 0; k < 5; ++k)
             have = have && c->graphs.count(GraphKey{k, trans, f, u0, u}) > 0;
         if (!have) {
+            if ((rc = drain(c))) return rc;
             for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
             c->graphs.clear();
         }
     }
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < (c->direct ? 1 : 5); ++k) {
         CycleIO io{f, u0, u, trans, true, k};
         if ((rc = get_graph(c, io, &g[k]))) return rc;
     }
-    // The first two cycles run before the host looks at the state: a
-    // snapshot after each gives the contraction rate, from which the cycles
-    // still needed are launched in one go (cycles launched after an
-    // instance converged are no-ops for it).  Every look at the state stops
-    // the GPU for a host round trip, so there are few of them.
-    InstState *snap0 = c->st_host, *snap1 = c->st_host + c->batch;
-    const size_t stb = sizeof(InstState) * c->batch;
     int launched = 0;
-    std::vector<double> prev_rsq(c->batch, -1.0);
-    std::vector<int> prev_cyc(c->batch, 0);
-    if (max_cycles > 0) {
-        HIPCHK(c, hipGraphLaunch(g[kFirst], s));
-        launched = 1;
-        if (max_cycles > 1) {
-            HIPCHK(c, hipMemcpyAsync(snap1, c->st, stb, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipGraphLaunch(g[kEven], s));
-            launched = 2;
-        }
-    }
-    bool have_prev = launched == 2;
-    while (true) {
-        HIPCHK(c, hipMemcpyAsync(snap0, c->st, stb, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        if (have_prev) {
-            // state after the first cycle
-            for (int j = 0; j < c->batch; ++j) {
-                if (snap1[j].done || snap1[j].cycles == 0) continue;
-                prev_rsq[j] = snap1[j].rsq;
-                prev_cyc[j] = snap1[j].cycles;
-            }
-            have_prev = false;
-        }
-        bool all = true;
-        int need = 1;
-        for (int j = 0; j < c->batch; ++j) {
-            const InstState &q = snap0[j];
-            if (q.done) continue;
-            all = false;
-            // cycles still needed at the contraction rate observed since the
-            // previous look
-            const int dc = q.cycles - prev_cyc[j];
-            if (prev_rsq[j] > 0.0 && dc > 0 && q.rsq > 0.0 && q.rsq < prev_rsq[j]) {
-                const double lrate = 0.5 * std::log(q.rsq / prev_rsq[j]) / dc;
-                const double lgoal = 0.5 * std::log(c->ctl_host->rtol2 * q.r0sq / q.rsq);
-                // one short of the estimate for longer runs: an extra look
-                // costs less than a cycle launched after convergence
-                int k = (int)std::ceil(lgoal / lrate);
-                if (k > 4) k -= 1;
-                need = std::max(need, std::min(std::max(k, 1), 32));
-            }
-            prev_rsq[j] = q.rsq;
-            prev_cyc[j] = q.cycles;
-        }
-        if (all || launched >= max_cycles) break;
-        need = std::min(need, max_cycles - launched);
-        for (int k = 0; k < need;) {
-            // cycle n >= 2 reads the halo buffer cycle n-1 wrote; an even and
-            // the following odd cycle share one graph launch
-            if (launched % 2 == 1 && need - k >= 4) {
+    // cycle 1 has its own graph; cycle n >= 2 reads the halo buffer cycle n-1
+    // wrote, and an even cycle with the following odd one (or two such
+    // pairs) share one graph launch.  A graph launch leaves the GPU idle for
+    // several microseconds at its start; with `direct` the cycles after the
+    // first are launched kernel by kernel instead, which pays when the host
+    // enqueues a cycle faster than the GPU runs it.
+    auto launch = [&](int n) -> int {
+        while (n > 0) {
+            if (c->direct && launched > 0) {
+                CycleIO io{f, u0, u, trans, true, (launched % 2 == 1) ? kEven : kOdd};
+                if ((rc = enqueue_cycle(c, io, s))) return rc;
+                launched += 1;
+                n -= 1;
+            } else if (launched == 0) {
+                HIPCHK(c, hipGraphLaunch(g[kFirst], s));
+                launched = 1;
+                n -= 1;
+            } else if (launched % 2 == 1 && n >= 4) {
                 HIPCHK(c, hipGraphLaunch(g[kEvenOdd2], s));
                 launched += 4;
-                k += 4;
-            } else if (launched % 2 == 1 && need - k >= 2) {
+                n -= 4;
+            } else if (launched % 2 == 1 && n >= 2) {
                 HIPCHK(c, hipGraphLaunch(g[kEvenOdd], s));
                 launched += 2;
-                k += 2;
+                n -= 2;
             } else {
                 HIPCHK(c, hipGraphLaunch(g[(launched % 2 == 1) ? kEven : kOdd], s));
-                ++launched;
-                ++k;
+                launched += 1;
+                n -= 1;
+            }
+        }
+        return TMG_OK;
+    };
+
+    // The kernel that finishes a cycle copies each instance's state into
+    // pinned host memory.  The host follows it there while the stream runs:
+    // cycles are queued ahead from the contraction rate seen so far, and no
+    // look at the state stops the GPU.  Cycles queued after an instance
+    // converged do nothing for it.
+    const int B = c->batch;
+    std::vector<HostState> cur(B);
+    std::vector<int> seen(B, -1);            // cycles of the last state read (-1: none yet)
+    std::vector<double> prev_rsq(B, -1.0);   // the state read before it
+    std::vector<int> prev_cyc(B, -1);
+    std::vector<int> est(B, 0);              // estimated total cycles (0: no estimate)
+    auto finished = [&](int j) {
+        return seen[j] >= 0 && (cur[j].done || cur[j].cycles >= max_cycles);
+    };
+    const int head = std::min(max_cycles, 3);
+    if ((rc = launch(head))) return rc;
+    long polls = 0;
+    constexpr std::chrono::microseconds kQuiet(2000);
+    auto since = std::chrono::steady_clock::now();
+    while (true) {
+        bool fresh = false, all = true;
+        int lo = INT_MAX;                    // fewest cycles seen among running instances
+        for (int j = 0; j < B; ++j) {
+            HostState q;
+            if (read_state(c->mirror + j, &q) && ((q.ver - 2) >> 33) == epoch &&
+                q.cycles > seen[j]) {
+                // rates from cycle 1 on (the first cycle starts from zero)
+                if (seen[j] >= 1 && !cur[j].done && q.cycles > cur[j].cycles) {
+                    prev_rsq[j] = cur[j].rsq;
+                    prev_cyc[j] = cur[j].cycles;
+                }
+                cur[j] = q;
+                seen[j] = q.cycles;
+                fresh = true;
+                // total cycles at the contraction rate between the last two
+                // states read
+                est[j] = 0;
+                const int dc = q.cycles - prev_cyc[j];
+                if (!q.done && prev_cyc[j] >= 0 && dc > 0 && q.rsq > 0.0 && q.rsq < prev_rsq[j]) {
+                    const double lrate = 0.5 * std::log(q.rsq / prev_rsq[j]) / dc;
+                    const double lgoal = 0.5 * std::log(c->ctl_host->rtol2 * q.r0sq / q.rsq);
+                    est[j] = q.cycles + std::min(std::max((int)std::ceil(lgoal / lrate), 1), 64);
+                }
+            }
+            if (!finished(j)) {
+                all = false;
+                lo = std::min(lo, std::max(seen[j], 0));
+            }
+        }
+        if (all) break;
+        if (fresh) {
+            // queue up to the largest estimate, one short of it while more
+            // than three cycles are still ahead (a later state refines it);
+            // two cycles past the last state read of an instance without one
+            int want = 0;
+            for (int j = 0; j < B; ++j) {
+                if (finished(j)) continue;
+                if (est[j] == 0) want = std::max(want, std::max(seen[j], 0) + 2);
+                else want = std::max(want, est[j] - lo > 3 ? est[j] - 1 : est[j]);
+            }
+            want = std::min(want, max_cycles);
+            if (want > launched && (rc = launch(want - launched))) return rc;
+            since = std::chrono::steady_clock::now();
+            continue;
+        }
+        // nothing new for a while: if the stream has drained, every state it
+        // will write is there, so one more read decides (queried rarely: a
+        // query is not free for the stream)
+        if (++polls % 4096 == 0 && std::chrono::steady_clock::now() - since > kQuiet) {
+            since = std::chrono::steady_clock::now();
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                bool again = false;
+                for (int j = 0; j < B; ++j) {
+                    HostState r;
+                    if (read_state(c->mirror + j, &r) && ((r.ver - 2) >> 33) == epoch &&
+                        r.cycles > seen[j])
+                        again = true;
+                }
+                if (!again) {
+                    // a drained stream with a running instance: queue one
+                    // more cycle, or give up when none is left
+                    if (launched >= max_cycles) return TMG_ERR_HIP;
+                    if ((rc = launch(1))) return rc;
+                }
+            } else if (q != hipErrorNotReady) {
+                c->last_hip = (int)q;
+                return TMG_ERR_HIP;
             }
         }
     }
+    HIPCHK(c, hipEventRecord(c->drain_ev, s));
+    c->drain_pending = true;
     int status = TMG_OK;
     for (int j = 0; j < c->batch; ++j) {
-        const InstState &q = snap0[j];
+        const HostState &q = cur[j];
         if (q.cycles == 0) {
             // no cycle ran for it (r_0 = 0 or max_cycles = 0): the iterate is u = 0
             HIPCHK(c, hipMemsetAsync(u + c->slab_off_h[0][j] * c->P, 0,
@@ -901,7 +995,6 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         if (sj < 0) status = std::min(status, sj);
         else if (sj > 0 && status == TMG_OK) status = sj;
     }
-    HIPCHK(c, hipStreamSynchronize(s));
     return status;
 }
 
@@ -936,6 +1029,7 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, hipStream_t s)
     std::vector<int> lbv;
     int rc = plan_levels(c->L, c->N.data(), cap, &lbv);
     if (rc) return rc;
+    if ((rc = drain(c))) return rc;
     HIPCHK(c, hipStreamSynchronize(s));
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
@@ -1152,10 +1246,16 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     // partial sums: one slot per level-0 tile at the smallest tile size in use
     c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
     if ((rc = dalloc(c, &c->partial, c->partial_cap))) return fail(rc);
-    if (hipHostMalloc((void **)&c->st_host, 2 * sizeof(InstState) * batch) != hipSuccess ||
+    if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
-        hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess)
+        hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess ||
+        hipHostMalloc((void **)&c->mirror, sizeof(HostState) * batch,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(TMG_ERR_OOM);
+    std::memset(c->mirror, 0, sizeof(HostState) * batch);
+    if (hipHostGetDevicePointer((void **)&c->mirror_d, c->mirror, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&c->drain_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(TMG_ERR_HIP);
     if (hipMemcpyAsync(c->tab_fwd, tf.data(), tf.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->tab_adj, ta.data(), ta.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->R_fwd, Rf.data(), Rf.size() * 8, hipMemcpyHostToDevice, s) ||
@@ -1232,7 +1332,7 @@ int tmg_adjoint_solve(tmg_handle c, const double *g, const double *u, double *z,
 }
 
 int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int64_t *cap_out,
-                 int *pairs_out, tmg_stream stream)
+                 int *pairs_out, int *direct_out, tmg_stream stream)
 {
     if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
@@ -1248,40 +1348,66 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
         if (c->opt.gamma == 1) cands.push_back({cap, false});
     }
     const Cand old{c->bottom_cap, c->pairs};
+    c->direct = false;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     int rc = TMG_OK;
     float best = -1.0f;
     Cand pick = old;
-    constexpr int kCycles = 3;
-    for (const Cand &cd : cands) {
-        if (apply_plan(c, cd.cap, cd.pairs, s) != TMG_OK) continue;
-        // a run that captures the graphs, then a timed one (rtol 0: every
-        // instance runs kCycles cycles)
+    constexpr int kCycles = 4;
+    // a run that captures the graphs, then a timed one (rtol 0: every
+    // instance runs kCycles cycles); milliseconds, or < 0 on an error
+    auto timed = [&]() -> float {
         rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
-        if (rc < 0) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { rc = TMG_ERR_HIP; break; }
+        if (rc < 0) return -1.0f;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = TMG_ERR_HIP; return -1.0f; }
         rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
-        if (rc < 0) break;
+        if (rc < 0) return -1.0f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = TMG_ERR_HIP;
-            break;
+            return -1.0f;
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    for (const Cand &cd : cands) {
+        if (apply_plan(c, cd.cap, cd.pairs, s) != TMG_OK) continue;
+        const float ms = timed();
+        if (ms < 0.0f) break;
         if (best < 0.0f || ms < best) {
             best = ms;
             pick = cd;
         }
     }
+    int rc2 = apply_plan(c, pick.cap, pick.pairs, s);
+    // then the same schedule with the cycles after the first launched kernel
+    // by kernel
+    bool direct = false;
+    if (rc >= 0 && rc2 == TMG_OK && best >= 0.0f) {
+        c->direct = true;
+        const float ms = timed();
+        direct = ms >= 0.0f && ms < best;
+        c->direct = direct;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    const int rc2 = apply_plan(c, pick.cap, pick.pairs, s);
     if (rc < 0) return rc;
     if (rc2 != TMG_OK) return rc2;
     if (cap_out) *cap_out = pick.cap;
     if (pairs_out) *pairs_out = pick.pairs ? 1 : 0;
+    if (direct_out) *direct_out = direct ? 1 : 0;
+    return TMG_OK;
+}
+
+int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int direct, tmg_stream stream)
+{
+    if (!c || bottom_cap < c->opt.n_coarse || bottom_cap > (int64_t)bottom_max(c->P))
+        return TMG_ERR_INVALID;
+    const int rc = apply_plan(c, bottom_cap, pairs != 0, (hipStream_t)stream);
+    if (rc) return rc;
+    c->direct = direct != 0;
     return TMG_OK;
 }
 
@@ -1458,7 +1584,7 @@ int tmg_op_residual_norm(tmg_handle c, int trans, const double *f, const double 
     a.norm_off = tl->d_off;
     a.partial = c->partial;
     HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
-    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st_ops, c->ctl, 1, s));
+    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st_ops, c->ctl, nullptr, 1, s));
     HIPCHK(c, hipMemcpyAsync(c->st_host, c->st_ops, sizeof(InstState) * c->batch,
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));

@@ -60,7 +60,20 @@ struct InstState {
 struct Control {
     double rtol2;  // rtol^2
     int max_cycles;
-    int pad;
+    int epoch;     // solve number (tags the host copies of the state)
+};
+
+// Host-visible copy of an instance's state in fine-grained pinned host
+// memory, written by the kernel that finishes a cycle so that the host can
+// follow a solve without stopping the stream.  `ver` is a sequence lock:
+// 2X + 1 while the fields are written, 2X + 2 after, X = epoch * 2^32 +
+// cycles.
+struct HostState {
+    long long ver;
+    int cycles;
+    int done;
+    double r0sq;
+    double rsq;
 };
 
 // Arguments of the streaming "leg" kernel (one level, all participating
@@ -172,6 +185,7 @@ struct BottomArgsT {
     const int *nlev;         // [batch] levels of each instance
     InstState *st;           // level 0: the work-group also finishes its instance's cycle
     const Control *ctl;
+    HostState *mirror;       // host copy of the state after such a cycle (may be null)
     int level, batch, tab_stride, nu1, nu2, gamma;
 };
 using BottomArgs = BottomArgsT<double>;
@@ -188,7 +202,8 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          int batch, double *partial, int64_t ntiles, hipStream_t s);
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
-                           InstState *st, const Control *ctl, int is_r0, hipStream_t s);
+                           InstState *st, const Control *ctl, HostState *mirror, int is_r0,
+                           hipStream_t s);
 // out[2j] = -sum_n z_n^T M_tau u_n, out[2j+1] = v^T z_1 (tau[j]: fine slab length).
 hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,
                        const int64_t *slab_off, int batch, double *out, hipStream_t s);

@@ -701,9 +701,26 @@ __device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int 
     }
 }
 
+// Copy of instance j's state into host memory (see HostState).  The
+// system-scope fences order the sequence-lock stores around the fields.
+__device__ __forceinline__ void publish(HostState *mirror, int j, const InstState &s, int epoch)
+{
+    if (!mirror) return;
+    HostState *h = mirror + j;
+    const long long x = ((long long)epoch << 32) | (unsigned)s.cycles;
+    __hip_atomic_store(&h->ver, 2 * x + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __hip_atomic_store(&h->cycles, s.cycles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->done, s.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->r0sq, s.r0sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->rsq, s.rsq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&h->ver, 2 * x + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Convergence state after a cycle whose squared residual norm is acc
 // (relative residual criterion of section 4.2).
-__device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, const Control *ctl)
+__device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, const Control *ctl,
+                                             HostState *mirror)
 {
     InstState s = st[j];
     s.cycles += 1;
@@ -713,6 +730,7 @@ __device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, c
     else if (acc > 1e6 * s.r0sq) s.done = 4;
     else if (s.cycles >= ctl->max_cycles) s.done = 2;
     st[j] = s;
+    publish(mirror, j, s, ctl->epoch);
 }
 
 // Squared residual of the tile's output slabs into its partial slot (summed
@@ -1241,7 +1259,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
                 }
             }
             acc = block_sum<B::NW>(acc, sm.red);
-            if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl);
+            if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl, a.mirror);
         }
         return;
     }
@@ -1338,7 +1356,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
         acc = block_sum<B::NW>(acc, sm.red);
-        if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl);
+        if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl, a.mirror);
     }
 }
 
@@ -1384,7 +1402,8 @@ constexpr int kFinThreads = 1024;
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restrict__ partial,
                                                           const int64_t *__restrict__ norm_off,
                                                           InstState *__restrict__ st,
-                                                          const Control *__restrict__ ctl, int is_r0)
+                                                          const Control *__restrict__ ctl,
+                                                          HostState *__restrict__ mirror, int is_r0)
 {
     __shared__ double red[kFinThreads / 64];
     const int j = blockIdx.x;
@@ -1405,7 +1424,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
     acc = block_sum<kFinThreads / 64>(acc, red);
     if (threadIdx.x != 0) return;
     if (!is_r0) {
-        finish_cycle(st, j, acc, ctl);
+        finish_cycle(st, j, acc, ctl, mirror);
         return;
     }
     InstState s = st[j];
@@ -1414,6 +1433,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
     s.cycles = 0;
     s.done = !isfinite(acc) ? 3 : (acc == 0.0 ? 1 : 0);
     st[j] = s;
+    publish(mirror, j, s, ctl->epoch);
 }
 
 // dlambda_j = -sum_n z_n^T M_tau u_n (M_tau = tau diag(1/(2k+1))),
@@ -1513,10 +1533,11 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
 }
 
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
-                           InstState *st, const Control *ctl, int is_r0, hipStream_t s)
+                           InstState *st, const Control *ctl, HostState *mirror, int is_r0,
+                           hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kFinThreads), 0, s, partial, norm_off, st, ctl,
-                       is_r0);
+                       mirror, is_r0);
     return hipGetLastError();
 }
 
