@@ -306,6 +306,7 @@ LegArgsT<T> leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl
     a.tab_stride = c->tab_stride;
     a.halo = H;
     a.tile_out = c->TO(H);
+    a.touch = level > 0;
     return a;
 }
 

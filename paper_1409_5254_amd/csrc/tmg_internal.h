@@ -118,6 +118,7 @@ struct LegArgsT {
     const int64_t *c2slab_off; // [batch+1] slab offsets of level l+2
     int64_t n0;              // slabs of instance 0 at this level (used when batch == 1)
     int batch;
+    int touch;               // 1: bring every table into the scalar cache at entry
     int tab_stride;
     int halo;                // left halo slabs per tile (even, a multiple of S)
     int tile_out;            // output slabs per tile

@@ -232,6 +232,30 @@ __device__ __forceinline__ ConstPtr<X> opaque(const X *p)
     return q;
 }
 
+// Brings `bytes` of a read-only table into the scalar cache: one load per
+// 64-byte line, all issued at once and their values dropped.  A small
+// (latency-bound) launch calls it for every table it will read, before the
+// wait for its state flag, so that the first use of each table hits the
+// cache instead of waiting for memory in turn; in a launch that streams HBM
+// the extra wait at entry costs more than it saves.
+__device__ __forceinline__ void touch_table(const void *p, int bytes)
+{
+    if (!p) return;
+    const auto q = opaque(reinterpret_cast<const uint32_t *>(p));
+    // dwords 64 bytes apart from the start, then the last dword (the region
+    // need not start on a line); nothing outside [p, p + bytes) is read
+    constexpr int kMaxLines = 12;
+    uint32_t v[kMaxLines + 1];
+#pragma unroll
+    for (int i = 0; i < kMaxLines; ++i)
+        if (i * 64 < bytes) v[i] = q[i * 16];
+    v[kMaxLines] = q[bytes / 4 - 1];
+#pragma unroll
+    for (int i = 0; i < kMaxLines; ++i)
+        if (i * 64 < bytes) asm volatile("" ::"s"(v[i]));
+    asm volatile("" ::"s"(v[kMaxLines]));
+}
+
 // N entries of a read-only table, stride `stride`, loaded at the point of use.
 template <int N, typename X>
 struct Vals {
@@ -756,7 +780,10 @@ __device__ __forceinline__ void norm_partial(const double (&r)[S][P], double *pa
 // output slabs and are never stored.  With one slab per thread (S = 1) the
 // two fine slabs of a coarse slab sit in neighbouring lanes (tiles start at
 // an even slab) and meet through a lane shuffle.
-template <int P, bool BW, typename T>
+// TOUCH (a.touch): the tables are brought into the scalar cache at entry
+// (small launches); a separate instantiation, as even an untaken branch
+// costs the level-0 pass registers.
+template <int P, bool BW, typename T, bool TOUCH>
 __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
 {
     constexpr int S = slabs_per_thread(P);
@@ -785,6 +812,17 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     const int done = a.st ? a.st[tr.j].done : 0;
     LazyOps<P, T> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tabT + (int64_t)tr.j * a.tab_stride);
+    if constexpr (TOUCH) {
+        const int tb = TabLayout(P).stride() * 8, tbT = TabLayout(P).stride() * (int)sizeof(T);
+        touch_table(op.tab, tb);
+        if ((const void *)op.tabT != (const void *)op.tab) touch_table(op.tabT, tbT);
+        if (a.tab1) {
+            touch_table(a.tab1 + (int64_t)tr.j * a.tab_stride, tb);
+            if ((const void *)a.tab1T != (const void *)a.tab1)
+                touch_table(a.tab1T + (int64_t)tr.j * a.tab_stride, tbT);
+        }
+        touch_table(a.R, 2 * P * P * (int)sizeof(T));
+    }
     if (done) return;
     int phase = 0;
     LazyOps<P, T> op1;   // the next level (two-level launches)
@@ -1479,8 +1517,14 @@ hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_leg<PP, true, T>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_leg<PP, false, T>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, a);
+        const dim3 grid((unsigned)ntiles), block(kLegThreads);
+        if (a.touch) {
+            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_leg<PP, false, T, true>), grid, block, 0, s, a);
+        } else {
+            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_leg<PP, false, T, false>), grid, block, 0, s, a);
+        }
     })
     return hipGetLastError();
 }
