@@ -40,8 +40,7 @@ def tune(s, f, u0, u):
     """Schedule chosen by the library's autotuner (not timed), or None."""
     if not AUTOTUNE:
         return None
-    cap, pairs, direct = s.autotune(f, u0, u)
-    return {"bottom_cap": cap, "two_level_launches": pairs, "direct_launches": direct}
+    return s.autotune(f, u0, u)
 
 
 def parse():

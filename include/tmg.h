@@ -153,27 +153,32 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
  * events.  A schedule is the size up to which an instance's levels run inside
  * the single-work-group bottom kernel (bottom_cap, the largest the bottom
  * kernel holds divided by 1, 2, ..., 32) and, for V-cycles, whether
- * consecutive levels share two-level launches; then, for the fastest of
+ * consecutive levels share two-level launches, and whether the levels
+ * after the first `span_after` such pairs run in spans of `span` levels per
+ * launch (3 or 4; 0: no spans; V-cycles only); then, for the fastest of
  * those, whether the cycles after the first of a solve are launched kernel
  * by kernel instead of as captured graphs (a graph launch idles the GPU for
  * several microseconds; direct launches pay when the host enqueues a cycle
  * faster than the GPU runs it).  The solution is the same under every
  * schedule (up to rounding order); only the kernel split and launch mode
  * change.  u (device, same layout as f) is used as scratch and overwritten.
- * *bottom_cap, *pairs and *direct (host, may be NULL) receive the choice.
- * Blocks until done.
+ * *bottom_cap, *pairs, *span, *span_after and *direct (host, may be NULL)
+ * receive the choice.  Blocks until done.
  */
 int tmg_autotune(tmg_handle h, const double *f, const double *u0, double *u, int64_t *bottom_cap,
-                 int *pairs, int *direct, tmg_stream s);
+                 int *pairs, int *span, int *span_after, int *direct, tmg_stream s);
 
 /*
  * Install a schedule (as chosen by tmg_autotune, e.g. on another handle of
  * the same shape) without timing anything: bottom_cap in [n_coarse, the
- * largest level the bottom kernel holds], pairs and direct as there.
- * Returns TMG_ERR_INVALID for a bottom_cap out of that range.  Blocks until
+ * largest level the bottom kernel holds], pairs, span, span_after and
+ * direct as there.  Returns TMG_ERR_INVALID for a bottom_cap out of that
+ * range, or a span other than 0 without pairs, for a W-cycle, too deep for
+ * the halo the sweep counts need, or with span_after < 1.  Blocks until
  * done.
  */
-int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int direct, tmg_stream s);
+int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int span, int span_after,
+                     int direct, tmg_stream s);
 
 /* Release every resource of h (synchronises its streams first). */
 int tmg_destroy(tmg_handle h);

@@ -80,8 +80,8 @@ def lib():
             "tmg_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d), _vp]),
             "tmg_adjoint_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_d), P(_d), P(_i), P(_d),
                                        _vp]),
-            "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), P(_i), _vp]),
-            "tmg_set_schedule": (_i, [_vp, _i64, _i, _i, _vp]),
+            "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), P(_i), P(_i), P(_i), _vp]),
+            "tmg_set_schedule": (_i, [_vp, _i64, _i, _i, _i, _i, _vp]),
             "tmg_destroy": (_i, [_vp]),
             "tmg_error_string": (ctypes.c_char_p, [_i]),
             "tmg_last_hip_error": (_i, [_vp]),
@@ -183,19 +183,24 @@ class Solver:
 
     def autotune(self, f, u0, u):
         """Pick the fastest schedule on (f, u0); u is overwritten.  Returns
-        (bottom_cap, pairs, direct)."""
+        dict(bottom_cap, pairs, span, span_after, direct)."""
         cap = ctypes.c_int64()
         pairs = ctypes.c_int()
+        span = ctypes.c_int()
+        after = ctypes.c_int()
         direct = ctypes.c_int()
         self._check(lib().tmg_autotune(self._h, _ptr(f), _ptr(u0), _ptr(u), ctypes.byref(cap),
-                                       ctypes.byref(pairs), ctypes.byref(direct), _stream()),
+                                       ctypes.byref(pairs), ctypes.byref(span),
+                                       ctypes.byref(after), ctypes.byref(direct), _stream()),
                     "tmg_autotune")
-        return cap.value, bool(pairs.value), bool(direct.value)
+        return dict(bottom_cap=cap.value, pairs=bool(pairs.value), span=span.value,
+                    span_after=after.value, direct=bool(direct.value))
 
-    def set_schedule(self, bottom_cap, pairs=True, direct=False):
+    def set_schedule(self, bottom_cap, pairs=True, span=0, span_after=1, direct=False):
         """Install a schedule without timing (see autotune)."""
-        self._check(lib().tmg_set_schedule(self._h, int(bottom_cap), int(bool(pairs)),
-                                           int(bool(direct)), _stream()), "tmg_set_schedule")
+        self._check(lib().tmg_set_schedule(self._h, int(bottom_cap), int(bool(pairs)), int(span),
+                                           int(span_after), int(bool(direct)), _stream()),
+                    "tmg_set_schedule")
 
     def vcycle(self, f, u0, u):
         self._check(lib().tmg_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),

@@ -100,6 +100,9 @@ struct tmg_ctx {
     int64_t hb_cap = 0;                           // doubles allocated per halo buffer
     bool pairs = true;                            // two-level launches in V-cycles (schedule)
     bool direct = false;                          // cycles after the first launched kernel by kernel
+    int span = 0;                                 // >= 3: levels after the first pairs in spans of it
+    int span_after = 1;                           // two-level launches before the spans
+    int *lb_d = nullptr;                          // [batch] lb on the device (spans)
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
     float *tab32_fwd = nullptr, *tab32_adj = nullptr;  // the same tables rounded to FP32
@@ -174,6 +177,38 @@ struct tmg_ctx {
     int H_mixd2() const { return r4(opt.nu1 + 2 + 2 * opt.nu1); }
     int H_mix2() const { return r4(2 * opt.nu1 + opt.nu2 + 3 + 2 * (opt.nu1 + opt.nu2) + 2 * opt.nu1); }
     int TO(int H) const { return tile_slabs(P) - H; }
+    // spans of K levels (k_span, one top-level slab per thread): the down
+    // legs lose nu1 + 1 slabs at the top level and, at each level below,
+    // half the wrong slabs restricted from above plus nu1 + 1 (the last
+    // restriction halves them once more); the up legs lose nu1 + nu2 at the
+    // deepest level and twice the wrong slabs prolonged from below plus
+    // nu1 + nu2 at each level above.  In top-level slabs, rounded up to a
+    // multiple of 2^K so that no coarse slab straddles two tiles.
+    int H_sdown(int K) const
+    {
+        int w = opt.nu1 + 1, h = w;
+        for (int k = 1; k < K; ++k) {
+            w = (w + 1) / 2 + opt.nu1 + 1;
+            h = std::max(h, w << k);
+        }
+        h = std::max(h, ((w + 1) / 2) << K);
+        return ((h + (1 << K) - 1) >> K) << K;
+    }
+    int H_sup(int K) const
+    {
+        int w = opt.nu1 + opt.nu2, h = w << (K - 1);
+        for (int k = K - 2; k >= 0; --k) {
+            w = 2 * w + opt.nu1 + opt.nu2;
+            h = std::max(h, w << k);
+        }
+        return ((h + (1 << K) - 1) >> K) << K;
+    }
+    // spans of depth K fit a tile with room for output
+    bool span_fits(int K) const
+    {
+        return K >= 3 && K <= kMaxSpan && H_sup(K) <= kSpanThreads - (1 << K) &&
+               H_sdown(K) <= kSpanThreads - (1 << K);
+    }
 };
 
 namespace {
@@ -442,6 +477,44 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
 }
 
 // Two-level launches of a V-cycle (first visits from zero) at levels l, l+1.
+// The down or up legs of levels level .. level+K-1 in one launch (k_span),
+// for every instance that streams `level` (each stops at its bottom level).
+template <typename T>
+int enqueue_span(tmg_ctx *c, const CycleIO &io, int level, int K, bool down, hipStream_t s)
+{
+    TileList *tl;
+    const int H = down ? c->H_sdown(K) : c->H_sup(K);
+    int rc = get_tiles(c, level, kDeep, kSpanThreads - H, s, &tl);
+    if (rc) return rc;
+    if (tl->ntiles == 0) return TMG_OK;
+    LevelStore<T> &L = store<T>(c);
+    SpanArgsT<T> a{};
+    for (int k = 0; k <= K && level + k < c->Lmax; ++k) {
+        a.f[k] = L.f[level + k];
+        a.x[k] = L.x(level + k, 0);
+        a.slab_off[k] = c->slab_off_d[level + k];
+    }
+    a.tab = tab_of(c, level, io.trans);
+    a.tabT = tabT_of<T>(c, level, io.trans);
+    a.tab_level = (int64_t)c->batch * c->tab_stride;
+    a.R = R_of<T>(c, io.trans);
+    a.tile_off = tl->d_off;
+    a.st = io.use_state ? c->st : nullptr;
+    a.lb = c->lb_d;
+    a.n0 = c->N[0] >> level;
+    a.batch = c->batch;
+    a.tab_stride = c->tab_stride;
+    a.level = level;
+    a.K = K;
+    a.halo = H;
+    a.tile_out = kSpanThreads - H;
+    a.nu1 = c->opt.nu1;
+    a.nu2 = c->opt.nu2;
+    a.up = down ? 0 : 1;
+    HIPCHK(c, launch_span<T>(c->P, io.trans, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
 template <typename T>
 int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, hipStream_t s)
 {
@@ -472,9 +545,18 @@ int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, 
     return TMG_OK;
 }
 
+// First level run in spans: after the first span_after pairs of levels
+// (spans pay only where a launch is latency-bound; the larger levels stay
+// in two-level launches), or none (Lmax).
+int span_start(const tmg_ctx *c, int first)
+{
+    return c->pairs && c->span_fits(c->span) ? first + 2 * c->span_after : c->Lmax;
+}
+
 // Levels >= 1 of a V-cycle (every visit a first visit from zero): all down
 // legs from the top, the bottom kernels, all up legs from the bottom, with
-// consecutive streaming levels paired into two-level launches.  Down and up
+// consecutive streaming levels paired into two-level launches (or, with a
+// span schedule, the levels after the first pair in spans).  Down and up
 // legs start at level down_first / up_first (2 when level 1's legs run
 // inside the level-0 pass).
 template <typename T>
@@ -485,7 +567,8 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
     LevelStore<T> &L = store<T>(c);
     c->cur.assign(c->Lmax + 1, 0);
     const int dp = down_first == 1 ? kPair1 : kPair2, ds = down_first == 1 ? kSingle1 : kSingle2;
-    for (int l = down_first; l < c->Lmax; ++l) {
+    const int sd = std::min(span_start(c, down_first), c->Lmax);
+    for (int l = down_first; l < sd; ++l) {
         if (!c->pairs) {
             if ((rc = enqueue_down<T>(c, io, l, true, s))) return rc;
             continue;
@@ -494,10 +577,16 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
             (rc = enqueue_down<T>(c, io, l, true, s, ds)))
             return rc;
     }
+    for (int l = sd; l < c->Lmax; l += c->span)
+        if ((rc = enqueue_span<T>(c, io, l, c->span, true, s))) return rc;
     for (int l = 1; l < c->Lmax; ++l)
         if ((rc = enqueue_bottom<T>(c, io, l, nullptr, L.x(l, 0), s))) return rc;
+    if (sd < c->Lmax)
+        for (int l = sd + (c->Lmax - 1 - sd) / c->span * c->span; l >= sd; l -= c->span)
+            if ((rc = enqueue_span<T>(c, io, l, c->span, false, s))) return rc;
+    const int su = std::min(span_start(c, up_first), c->Lmax);
     const int kp = up_first == 1 ? kPair1 : kPair2, ks = up_first == 1 ? kSingle1 : kSingle2;
-    for (int l = c->Lmax - 1; l >= up_first; --l) {
+    for (int l = su - 1; l >= up_first; --l) {
         if (!c->pairs) {
             if ((rc = enqueue_up<T>(c, io, l, true, s))) return rc;
             continue;
@@ -731,6 +820,11 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
             (rc = get_tiles(c, l, kPair2, c->TO(c->H_upair()), s, &tl)) ||
             (rc = get_tiles(c, l, kSingle2, c->TO(c->H_up()), s, &tl)))
             return rc;
+    if (c->span_fits(c->span))
+        for (int l = 1; l < c->Lmax; ++l)
+            if ((rc = get_tiles(c, l, kDeep, kSpanThreads - c->H_sdown(c->span), s, &tl)) ||
+                (rc = get_tiles(c, l, kDeep, kSpanThreads - c->H_sup(c->span), s, &tl)))
+                return rc;
     return TMG_OK;
 }
 
@@ -1025,7 +1119,7 @@ int plan_levels(const std::vector<int> &L, const int64_t *n_slabs, int64_t cap,
 // kernels and the bottom kernel (bottom cap) and whether V-cycles use
 // two-level launches.  Drops the captured graphs and tile lists of the old
 // schedule and sizes the buffers that depend on it.
-int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, hipStream_t s)
+int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hipStream_t s)
 {
     std::vector<int> lbv;
     int rc = plan_levels(c->L, c->N.data(), cap, &lbv);
@@ -1041,6 +1135,10 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, hipStream_t s)
     c->lb = lbv;
     c->bottom_cap = cap;
     c->pairs = pairs;
+    c->span = c->span_fits(span) ? span : 0;
+    c->span_after = std::max(span_after, 1);
+    if (!c->lb_d && (rc = dalloc(c, &c->lb_d, batch))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->lb_d, c->lb.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
     c->deep_n.assign(Lm + 1, 0);
     c->bot_n.assign(Lm + 1, 0);
     c->bot_d.assign(Lm + 1, nullptr);
@@ -1215,7 +1313,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                 return fail(rc);
         }
     }
-    if ((rc = apply_plan(c, bottom_cap, true, s))) return fail(rc);
+    if ((rc = apply_plan(c, bottom_cap, true, 0, 1, s))) return fail(rc);
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
         ta((size_t)Lm * batch * c->tab_stride, 0.0);
@@ -1333,22 +1431,26 @@ int tmg_adjoint_solve(tmg_handle c, const double *g, const double *u, double *z,
 }
 
 int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int64_t *cap_out,
-                 int *pairs_out, int *direct_out, tmg_stream stream)
+                 int *pairs_out, int *span_out, int *span_after_out, int *direct_out,
+                 tmg_stream stream)
 {
     if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     struct Cand {
         int64_t cap;
         bool pairs;
+        int span, after;
     };
+    // in stages, each from the best of the one before: the bottom cap (with
+    // two-level launches), then how the streaming levels are launched at
+    // that cap, then the launch mode
     std::vector<Cand> cands;
     for (int k = 0; k <= 5; ++k) {
         const int64_t cap = (int64_t)bottom_max(c->P) >> k;
         if (cap < c->opt.n_coarse) break;
-        cands.push_back({cap, true});
-        if (c->opt.gamma == 1) cands.push_back({cap, false});
+        cands.push_back({cap, true, 0, 1});
     }
-    const Cand old{c->bottom_cap, c->pairs};
+    const Cand old{c->bottom_cap, c->pairs, c->span, c->span_after};
     c->direct = false;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1373,16 +1475,27 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
         (void)hipEventElapsedTime(&ms, e0, e1);
         return ms;
     };
-    for (const Cand &cd : cands) {
-        if (apply_plan(c, cd.cap, cd.pairs, s) != TMG_OK) continue;
-        const float ms = timed();
-        if (ms < 0.0f) break;
-        if (best < 0.0f || ms < best) {
-            best = ms;
-            pick = cd;
+    auto run_stage = [&]() {
+        for (const Cand &cd : cands) {
+            if (apply_plan(c, cd.cap, cd.pairs, cd.span, cd.after, s) != TMG_OK) continue;
+            const float ms = timed();
+            if (ms < 0.0f) return;
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                pick = cd;
+            }
         }
+    };
+    run_stage();
+    if (rc >= 0 && c->opt.gamma == 1 && best >= 0.0f) {
+        cands.clear();
+        cands.push_back({pick.cap, false, 0, 1});
+        for (int K = 3; K <= kMaxSpan; ++K)
+            for (int after = 1; after <= 3; ++after)
+                if (c->span_fits(K)) cands.push_back({pick.cap, true, K, after});
+        run_stage();
     }
-    int rc2 = apply_plan(c, pick.cap, pick.pairs, s);
+    int rc2 = apply_plan(c, pick.cap, pick.pairs, pick.span, pick.after, s);
     // then the same schedule with the cycles after the first launched kernel
     // by kernel
     bool direct = false;
@@ -1398,15 +1511,20 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     if (rc2 != TMG_OK) return rc2;
     if (cap_out) *cap_out = pick.cap;
     if (pairs_out) *pairs_out = pick.pairs ? 1 : 0;
+    if (span_out) *span_out = c->span;
+    if (span_after_out) *span_after_out = c->span_after;
     if (direct_out) *direct_out = direct ? 1 : 0;
     return TMG_OK;
 }
 
-int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int direct, tmg_stream stream)
+int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int span, int span_after,
+                     int direct, tmg_stream stream)
 {
     if (!c || bottom_cap < c->opt.n_coarse || bottom_cap > (int64_t)bottom_max(c->P))
         return TMG_ERR_INVALID;
-    const int rc = apply_plan(c, bottom_cap, pairs != 0, (hipStream_t)stream);
+    if (span != 0 && (!pairs || c->opt.gamma != 1 || !c->span_fits(span) || span_after < 1))
+        return TMG_ERR_INVALID;
+    const int rc = apply_plan(c, bottom_cap, pairs != 0, span, span_after, (hipStream_t)stream);
     if (rc) return rc;
     c->direct = direct != 0;
     return TMG_OK;

@@ -126,6 +126,29 @@ struct LegArgsT {
 };
 using LegArgs = LegArgsT<double>;
 
+// A span: the down legs (or the up legs) of up to kMaxSpan consecutive
+// levels l .. l+K-1 of a V-cycle's first visits in one launch (see k_span).
+// Instance j runs min(K, lb[j] - l) of them.  Level l+k's arrays and tables:
+// f[k], x[k], slab_off[k], tab + k * tab_level.
+constexpr int kMaxSpan = 4;
+constexpr int kSpanThreads = 256;   // one slab of level l per thread
+template <typename T>
+struct SpanArgsT {
+    T *f[kMaxSpan + 1];      // right-hand sides (down: f[0] read, f[1..K] written; up: read)
+    T *x[kMaxSpan + 1];      // up: x[K_j] the correction from below (read), x[0] the result
+    const int64_t *slab_off[kMaxSpan + 1];
+    const double *tab;       // FP64 tables of level l (level l+k at + k * tab_level)
+    const T *tabT;
+    int64_t tab_level;
+    const T *R;
+    const int64_t *tile_off;
+    const InstState *st;
+    const int *lb;           // [batch] first bottom-kernel level of each instance
+    int64_t n0;              // slabs of instance 0 at level l (used when batch == 1)
+    int batch, tab_stride, level, K, halo, tile_out, nu1, nu2;
+    int up;                  // 0: down legs, 1: up legs
+};
+
 // Fused level-0 pass of the FP32-inner defect correction (k_mix).
 struct MixArgs {
     const double *f;
@@ -196,6 +219,8 @@ using BottomArgs = BottomArgsT<double>;
 template <typename T>
 hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_mix(int P, bool backward, const MixArgs &a, int64_t ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_span(int P, bool backward, const SpanArgsT<T> &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
 template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s);

@@ -879,6 +879,274 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     }
 }
 
+// ---- spans: several small levels per launch ------------------------------
+//
+// The small streaming levels are latency-bound: a launch spends most of its
+// time starting up, waiting for data the previous launch wrote and draining,
+// not computing.  A span runs the legs of up to four consecutive levels of a
+// V-cycle's first visits in one launch.  Every thread holds one slab of the
+// top level l; at level l+k the tile's slabs are 2^k times fewer and each is
+// held (and computed, identically) by the 2^k neighbouring lanes that held
+// its fine slabs.  The left neighbour is then 2^k lanes back, and the two
+// fine slabs of a coarse slab are 2^k lanes apart.  Each step computes what
+// the pair and single launches compute, in the same order, so a span gives
+// the same iterate to the last bit; its tile's left halo is sized for the
+// wrong leading slabs of all its levels.
+
+// Value of lane `lane - d` (d < 64; lanes below d receive their own value).
+__device__ __forceinline__ double lane_back(double x, int d)
+{
+    const int lane = threadIdx.x & 63;
+    const int src = (lane >= d ? lane - d : lane) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(x));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_back(float x, int d)
+{
+    const int lane = threadIdx.x & 63;
+    const int src = (lane >= d ? lane - d : lane) << 2;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(x)));
+}
+// Value of lane `lane ^ d` (d a power of two below 64).
+__device__ __forceinline__ double lane_xor(double x, int d)
+{
+    const int src = ((threadIdx.x & 63) ^ d) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(x));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// End value of the left neighbour of this lane's slab when each slab is held
+// by d neighbouring lanes (the tile's first slab sees zero); one barrier.
+template <int NW, typename T>
+__device__ __forceinline__ T left_value_d(T mine, int d, double (*xchg)[NW], int &phase)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T v = lane_back(mine, d);
+    if (lane == 63) xchg[phase][wave] = (double)mine;
+    __syncthreads();
+    if (lane < d) v = wave ? (T)xchg[phase][wave - 1] : (T)0;
+    phase ^= 1;
+    return v;
+}
+
+// Sweeps and residual of one slab per lane (as sweeps / residual with S = 1).
+template <int P, int NW, typename T, class OP>
+__device__ __forceinline__ void sweeps_d(T (&u)[P], const T (&g)[P], const OP &op, int nsweep,
+                                         int d, double (*xchg)[NW], int &phase)
+{
+    if (nsweep <= 0) return;
+    const auto &tb = op.sw();
+    for (int sw = 0; sw < nsweep; ++sw) {
+        T w = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) w += tb.c[k] * u[k];
+        const T wn = left_value_d<NW, T>(w, d, xchg, phase);
+#pragma unroll
+        for (int k = 0; k < P; ++k) u[k] = tb.omc * u[k] + g[k] + tb.h[k] * wn;
+    }
+}
+
+template <int P, int NW, typename T, class OP>
+__device__ __forceinline__ void residual_d(double (&r)[P], const T (&u)[P], const T (&f)[P],
+                                           const OP &op, int d, double (*xchg)[NW], int &phase)
+{
+    const auto cd = op.cd();
+    double w = 0.0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) w += cd.v[k] * (double)u[k];
+    const double wn = left_value_d<NW, double>(w, d, xchg, phase);
+    const auto v = op.v();
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const auto a = op.a_row(k);
+        double t = (double)f[k] + v.v[k] * wn;
+#pragma unroll
+        for (int l = 0; l < P; ++l) t -= a.v[l] * (double)u[l];
+        r[k] = t;
+    }
+}
+
+template <int P, typename T, class OP>
+__device__ __forceinline__ void apply_G1(T (&g)[P], const T (&f)[P], const OP &op)
+{
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const auto G = op.g_row(k);
+        T t = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) t += G.v[l] * f[l];
+        g[k] = t;
+    }
+}
+
+// Restriction of a pair of slabs held d lanes apart: every lane of the pair
+// gets the coarse slab rc_m = R_1 r_{2m} + R_2 r_{2m+1}.
+template <int P, typename T>
+__device__ __forceinline__ void restrict_d(const double (&r)[P], bool second, int d,
+                                           const T *R, T (&rc)[P])
+{
+    double rp[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) rp[k] = lane_xor(r[k], d);
+    const RGlob<P, T> ra{R};
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const auto c1 = ra.col(0, k), c2 = ra.col(1, k);
+        T s1 = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            const double r0 = second ? rp[l] : r[l], r1 = second ? r[l] : rp[l];
+            s1 += c1.v[l] * (T)r0 + c2.v[l] * (T)r1;
+        }
+        rc[k] = s1;
+    }
+}
+
+// u += R_1^T e or R_2^T e (the half for this slab's position in its pair).
+template <int P, typename T>
+__device__ __forceinline__ void prolong_d(T (&u)[P], const T (&e)[P], bool second, const T *R)
+{
+    const RGlob<P, T> ra{R};
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const auto r1 = ra.row(0, k), r2 = ra.row(1, k);
+        T s1 = 0, s2 = 0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            s1 += r1.v[l] * e[l];
+            s2 += r2.v[l] * e[l];
+        }
+        u[k] += second ? s2 : s1;
+    }
+}
+
+template <int P, bool BW, typename T>
+__global__ __launch_bounds__(kSpanThreads) void k_span(SpanArgsT<T> a)
+{
+    constexpr int NW = kSpanThreads / 64;
+    __shared__ double xchg[2][NW];
+    const int t = threadIdx.x;
+    int j = 0;
+    int64_t tile = blockIdx.x;
+    if (a.batch > 1) {
+        j = find_instance(a.tile_off, a.batch, tile);
+        tile -= a.tile_off[j];
+    }
+    const int K = min(a.K, a.lb[j] - a.level);
+    // first slab of the tile at level l (a multiple of 2^K: no coarse slab
+    // of the span straddles two tiles)
+    const int64_t s0 = tile * a.tile_out - a.halo;
+    int64_t off[kMaxSpan + 1], N[kMaxSpan + 1];
+#pragma unroll
+    for (int k = 0; k <= kMaxSpan; ++k) {
+        if (k > K) break;
+        if (a.batch > 1) {
+            off[k] = a.slab_off[k][j];
+            N[k] = a.slab_off[k][j + 1] - off[k];
+        } else {
+            off[k] = 0;
+            N[k] = a.n0 >> k;
+        }
+    }
+    // every load is issued before the wait for the state flag and the tables
+    T f[kMaxSpan][P], e[P];
+    if (a.up) {
+#pragma unroll
+        for (int k = 0; k < kMaxSpan; ++k) {
+            if (k >= K) break;
+            T tmp[1][P];
+            load_chunk<P, 1, BW, T>(a.f[k] + off[k] * P, (s0 >> k) + (t >> k), N[k], tmp);
+#pragma unroll
+            for (int q = 0; q < P; ++q) f[k][q] = tmp[0][q];
+        }
+        // the correction of level l+K (K is per instance: read its arrays
+        // from the argument block, not from the per-level copies above)
+        const int64_t offK = a.batch > 1 ? a.slab_off[K][j] : 0;
+        const int64_t NK = a.batch > 1 ? a.slab_off[K][j + 1] - offK : a.n0 >> K;
+        T tmp[1][P];
+        load_chunk<P, 1, BW, T>(a.x[K] + offK * P, (s0 >> K) + (t >> K), NK, tmp);
+#pragma unroll
+        for (int q = 0; q < P; ++q) e[q] = tmp[0][q];
+    } else {
+        T tmp[1][P];
+        load_chunk<P, 1, BW, T>(a.f[0] + off[0] * P, s0 + t, N[0], tmp);
+#pragma unroll
+        for (int q = 0; q < P; ++q) f[0][q] = tmp[0][q];
+    }
+    const int done = a.st ? a.st[j].done : 0;
+    const int tb = TabLayout(P).stride() * 8, tbT = TabLayout(P).stride() * (int)sizeof(T);
+    for (int k = 0; k < K; ++k) {
+        const double *tk = a.tab + k * a.tab_level + (int64_t)j * a.tab_stride;
+        const T *tkT = a.tabT + k * a.tab_level + (int64_t)j * a.tab_stride;
+        touch_table(tk, tb);
+        if ((const void *)tkT != (const void *)tk) touch_table(tkT, tbT);
+    }
+    touch_table(a.R, 2 * P * P * (int)sizeof(T));
+    if (done) return;
+    int phase = 0;
+    if (!a.up) {
+        // down legs from the top: sweeps from zero, residual, restriction
+#pragma unroll
+        for (int k = 0; k < kMaxSpan; ++k) {
+            if (k >= K) break;
+            LazyOps<P, T> op;
+            op.load(a.tab + k * a.tab_level + (int64_t)j * a.tab_stride,
+                    a.tabT + k * a.tab_level + (int64_t)j * a.tab_stride);
+            const int d = 1 << k;
+            const int64_t m = (s0 >> k) + (t >> k);
+            T g[P], x[P];
+            apply_G1<P, T>(g, f[k], op);
+#pragma unroll
+            for (int q = 0; q < P; ++q) x[q] = (T)0;
+            sweeps_d<P, NW, T>(x, g, op, a.nu1, d, xchg, phase);
+            double r[P];
+            residual_d<P, NW, T>(r, x, f[k], op, d, xchg, phase);
+            T rc[P];
+            restrict_d<P, T>(r, (m & 1) != 0, d, a.R, rc);
+            // one lane per coarse slab stores it, outside the halo
+            const int lc = t >> (k + 1);
+            if ((t & (2 * d - 1)) == 0) {
+                T tmp[1][P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) tmp[0][q] = rc[q];
+                store_chunk<P, 1, BW, T>(a.f[k + 1] + off[k + 1] * P, (s0 >> (k + 1)) + lc,
+                                         N[k + 1], tmp, lc, a.halo >> (k + 1));
+            }
+            if (k + 1 < kMaxSpan) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) f[k + 1][q] = rc[q];
+            }
+        }
+    } else {
+        // up legs from the bottom: pre sweeps from zero recomputed,
+        // correction from the level below, post sweeps
+#pragma unroll
+        for (int k = kMaxSpan - 1; k >= 0; --k) {
+            if (k >= K) continue;
+            LazyOps<P, T> op;
+            op.load(a.tab + k * a.tab_level + (int64_t)j * a.tab_stride,
+                    a.tabT + k * a.tab_level + (int64_t)j * a.tab_stride);
+            const int d = 1 << k;
+            const int64_t m = (s0 >> k) + (t >> k);
+            T g[P], x[P];
+            apply_G1<P, T>(g, f[k], op);
+#pragma unroll
+            for (int q = 0; q < P; ++q) x[q] = (T)0;
+            sweeps_d<P, NW, T>(x, g, op, a.nu1, d, xchg, phase);
+            prolong_d<P, T>(x, e, (m & 1) != 0, a.R);
+            sweeps_d<P, NW, T>(x, g, op, a.nu2, d, xchg, phase);
+#pragma unroll
+            for (int q = 0; q < P; ++q) e[q] = x[q];
+        }
+        T tmp[1][P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) tmp[0][q] = e[q];
+        store_chunk<P, 1, BW, T>(a.x[0] + off[0] * P, s0 + t, N[0], tmp, t, a.halo);
+    }
+}
+
 // Fused level-0 pass of the FP32-inner defect correction (see MixArgs).
 // With u_k the FP64 iterate (in place):
 //   up:   r_k = f - L u_k (FP64) -> FP32; the inner level-0 up leg on
@@ -1530,6 +1798,19 @@ hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles
 }
 template hipError_t launch_leg<double>(int, bool, const LegArgsT<double> &, int64_t, hipStream_t);
 template hipError_t launch_leg<float>(int, bool, const LegArgsT<float> &, int64_t, hipStream_t);
+
+template <typename T>
+hipError_t launch_span(int P, bool backward, const SpanArgsT<T> &a, int64_t ntiles, hipStream_t s)
+{
+    TMG_DISPATCH_P(P, {
+        const dim3 grid((unsigned)ntiles), block(kSpanThreads);
+        if (backward) hipLaunchKernelGGL((k_span<PP, true, T>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_span<PP, false, T>), grid, block, 0, s, a);
+    })
+    return hipGetLastError();
+}
+template hipError_t launch_span<double>(int, bool, const SpanArgsT<double> &, int64_t, hipStream_t);
+template hipError_t launch_span<float>(int, bool, const SpanArgsT<float> &, int64_t, hipStream_t);
 
 hipError_t launch_mix(int P, bool backward, const MixArgs &a, int64_t ntiles, hipStream_t s)
 {

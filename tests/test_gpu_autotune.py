@@ -41,10 +41,11 @@ def test_autotune_then_solve(gamma, precision):
     f, d0 = dev(np.concatenate(fs)), dev(u0)
     before = s.solve(f, d0, rtol=1e-10)
     U0 = host(before.u).copy()
-    cap, pairs, direct = s.autotune(f, d0, torch.empty_like(f))
-    assert cap >= 2
+    sch = s.autotune(f, d0, torch.empty_like(f))
+    assert sch["bottom_cap"] >= 2
     if gamma == 2:
-        assert pairs  # two-level launches are a V-cycle schedule only
+        # two-level launches and spans are V-cycle schedules only
+        assert sch["pairs"] and sch["span"] == 0
     after = s.solve(f, d0, rtol=1e-10)
     U1 = host(after.u)
     assert after.status == 0
@@ -102,3 +103,62 @@ def test_set_schedule_rejects_bad_cap():
         s.set_schedule(1, pairs=True)
     with pytest.raises(B.TmgError):
         s.set_schedule(1 << 30, pairs=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("span", [3, 4])
+@pytest.mark.parametrize("cap", [8, 64])
+def test_span_schedule_matches_pairs(precision, span, cap):
+    """Spans compute every step of the pair and single launches in the same
+    order: the same iterate to the last bit, forward and adjoint, also for
+    instances whose bottom level falls inside a span."""
+    from paper_1409_5254_amd import binding as B
+    rng = np.random.default_rng(11 * span + cap)
+    p = 3
+    # lb = log2(N / cap) levels stream: 3 .. 11, so spans end at and before
+    # every instance's bottom level
+    Ns = [cap << 3, cap << 5, cap << 7, cap << 11, cap << 6, 2]
+    lams = [1.0, 4.0, 0.5, 2.0, 9.0, 1.0]
+    Ts = [4.0, 20.0, 60.0, 900.0, 30.0, 1.0]
+    u0 = rng.uniform(-1, 1, len(Ns))
+    fh = np.concatenate([rng.standard_normal(n * (p + 1)) for n in Ns])
+    f, d0 = dev(fh), dev(u0)
+    s = B.Solver(Ns, Ts, lams, p=p, precision=precision)
+    res = {}
+    for sp, after in ((0, 1), (span, 1), (span, 2)):
+        s.set_schedule(cap, pairs=True, span=sp, span_after=after)
+        r = s.solve(f, d0, rtol=1e-10)
+        assert r.status == 0
+        u = host(r.u).copy()
+        g = dev(u - 0.5)
+        z, dl, du, cz, _, st = s.adjoint_solve(g, u=r.u)
+        assert st == 0
+        res[(sp, after)] = (u, list(r.cycles), host(z).copy(), cz, dl, du)
+    a = res[(0, 1)]
+    for key in ((span, 1), (span, 2)):
+        b = res[key]
+        assert a[1] == b[1] and a[3] == b[3]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+        assert a[4] == b[4] and a[5] == b[5]
+    b = res[(span, 1)]
+    if precision == 0:
+        for j, n in enumerate(Ns):
+            seg = slice(s.offsets[j], s.offsets[j + 1])
+            uo, k, _, _ = core.solve(p, Ts[j], lams[j], u0[j], fh[seg])
+            assert b[1][j] == k
+            assert relerr(b[0][seg], uo) <= 1e-12
+
+
+def test_span_schedule_rejected_where_it_cannot_run():
+    from paper_1409_5254_amd import binding as B
+    s = B.Solver([4096], [1.0], [1.0], p=1, gamma=2)
+    with pytest.raises(B.TmgError):
+        s.set_schedule(64, pairs=True, span=4)
+    s = B.Solver([4096], [1.0], [1.0], p=1)
+    with pytest.raises(B.TmgError):
+        s.set_schedule(64, pairs=False, span=4)
+    with pytest.raises(B.TmgError):
+        s.set_schedule(64, pairs=True, span=5)
+    with pytest.raises(B.TmgError):
+        s.set_schedule(64, pairs=True, span=4, span_after=0)
+    s.set_schedule(64, pairs=True, span=4, span_after=2)
