@@ -115,9 +115,13 @@ struct tmg_ctx {
     std::vector<int> deep_n;                      // per level: instances with level < lb
     int64_t bottom_cap = 0;
     InstState *st = nullptr, *st_ops = nullptr;
-    InstState *st_host = nullptr;                 // pinned, batch states of the op calls
+    InstState *st_host = nullptr;                 // pinned, batch states (results, op calls)
     Control *ctl = nullptr, *ctl_host = nullptr;  // device / pinned
-    HostState *mirror = nullptr, *mirror_d = nullptr;  // coherent pinned; host / device address
+    HostHead *mirror = nullptr, *mirror_d = nullptr;   // coherent pinned; host / device address
+    unsigned *pubn_d = nullptr;                   // copies of a batch's states made (k_publish)
+    // the kernels that finish a cycle write the host copy themselves for a
+    // single instance; a batch is copied by k_publish after the cycle
+    HostHead *mirror1() const { return batch == 1 ? mirror_d : nullptr; }
     int epoch = 0;                                // solves started
     hipEvent_t drain_ev = nullptr;                // recorded after the last launch of a solve
     bool drain_pending = false;
@@ -375,7 +379,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.nlev = c->nlev_d;
     a.st = io.use_state ? c->st : nullptr;
     a.ctl = c->ctl;
-    a.mirror = io.use_state ? c->mirror_d : nullptr;
+    a.mirror = io.use_state ? c->mirror1() : nullptr;
     a.level = level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
@@ -698,7 +702,7 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         }
         HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
         if (solve && io.use_state)
-            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror_d, 0, s));
+            HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 0, s));
     }
     return TMG_OK;
 }
@@ -782,9 +786,11 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             }
             HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
             if (solve && io.use_state)
-                HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror_d, 0, s));
+                HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 0, s));
         }
     }
+    if (io.kind >= 0 && io.use_state && c->batch > 1)
+        HIPCHK(c, launch_publish(c->st, c->batch, c->ctl, c->mirror_d, c->pubn_d, s));
     return TMG_OK;
 }
 
@@ -895,20 +901,23 @@ void free_all(tmg_ctx *c)
 }
 
 // Solve loop shared by tmg_solve and tmg_adjoint_solve.
-// A consistent copy of instance j's host-side state (HostState), or false
-// while the device is writing it.
-bool read_state(const HostState *h, HostState *out)
+// A consistent copy of the host-side summary (see HostHead) and its
+// version, or false while the device is writing it.
+bool read_summary(const HostHead *h, HostSum *out, long long *ver)
 {
-    const long long v1 = __atomic_load_n(&h->ver, __ATOMIC_ACQUIRE);
-    if (v1 & 1) return false;
-    out->cycles = __atomic_load_n(&h->cycles, __ATOMIC_RELAXED);
-    out->done = __atomic_load_n(&h->done, __ATOMIC_RELAXED);
-    __atomic_load(&h->r0sq, &out->r0sq, __ATOMIC_RELAXED);
-    __atomic_load(&h->rsq, &out->rsq, __ATOMIC_RELAXED);
+    const long long e = __atomic_load_n(&h->end, __ATOMIC_ACQUIRE);
+    const HostSum *m = reinterpret_cast<const HostSum *>(h + 1);
+    out->running = __atomic_load_n(&m->running, __ATOMIC_RELAXED);
+    out->want = __atomic_load_n(&m->want, __ATOMIC_RELAXED);
+    out->cycles = __atomic_load_n(&m->cycles, __ATOMIC_RELAXED);
+    out->done = __atomic_load_n(&m->done, __ATOMIC_RELAXED);
+    __atomic_load(&m->r0sq, &out->r0sq, __ATOMIC_RELAXED);
+    __atomic_load(&m->rsq, &out->rsq, __ATOMIC_RELAXED);
+    __atomic_load(&m->prev_rsq, &out->prev_rsq, __ATOMIC_RELAXED);
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    const long long v2 = __atomic_load_n(&h->ver, __ATOMIC_RELAXED);
-    out->ver = v1;
-    return v1 == v2;
+    const long long b = __atomic_load_n(&h->begin, __ATOMIC_RELAXED);
+    *ver = e;
+    return b == e;
 }
 
 int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool trans, double rtol,
@@ -926,7 +935,9 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // initial residual r_0 = f (u0 folded), u = 0
     HIPCHK(c, launch_norm_f(c->P, f, trans ? nullptr : u0, tab_of(c, 0, trans), c->tab_stride,
                             c->slab_off_d[0], tl->d_off, c->batch, c->partial, tl->ntiles, s));
-    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror_d, 1, s));
+    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 1, s));
+    if (c->batch > 1)
+        HIPCHK(c, launch_publish(c->st, c->batch, c->ctl, c->mirror_d, c->pubn_d, s));
 
     // graphs are kept per set of arrays; a full cache is emptied before the
     // five graphs of this solve are fetched, never between them
@@ -980,102 +991,82 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         return TMG_OK;
     };
 
-    // The kernel that finishes a cycle copies each instance's state into
-    // pinned host memory.  The host follows it there while the stream runs:
-    // cycles are queued ahead from the contraction rate seen so far, and no
-    // look at the state stops the GPU.  Cycles queued after an instance
+    // After each cycle the device writes a summary into pinned host memory
+    // (instances still running, cycles to have queued; see HostHead).  The
+    // host follows it there while the stream runs and tops up the queue, so
+    // no look at the state stops the GPU.  Cycles queued after an instance
     // converged do nothing for it.
-    const int B = c->batch;
-    std::vector<HostState> cur(B);
-    std::vector<int> seen(B, -1);            // cycles of the last state read (-1: none yet)
-    std::vector<double> prev_rsq(B, -1.0);   // the state read before it
-    std::vector<int> prev_cyc(B, -1);
-    std::vector<int> est(B, 0);              // estimated total cycles (0: no estimate)
-    auto finished = [&](int j) {
-        return seen[j] >= 0 && (cur[j].done || cur[j].cycles >= max_cycles);
-    };
     const int head = std::min(max_cycles, 3);
     if ((rc = launch(head))) return rc;
+    HostSum sum{};
+    long long last_ver = -1;
     long polls = 0;
     constexpr std::chrono::microseconds kQuiet(2000);
     auto since = std::chrono::steady_clock::now();
     while (true) {
-        bool fresh = false, all = true;
-        int lo = INT_MAX;                    // fewest cycles seen among running instances
-        for (int j = 0; j < B; ++j) {
-            HostState q;
-            if (read_state(c->mirror + j, &q) && ((q.ver - 2) >> 33) == epoch &&
-                q.cycles > seen[j]) {
-                // rates from cycle 1 on (the first cycle starts from zero)
-                if (seen[j] >= 1 && !cur[j].done && q.cycles > cur[j].cycles) {
-                    prev_rsq[j] = cur[j].rsq;
-                    prev_cyc[j] = cur[j].cycles;
-                }
-                cur[j] = q;
-                seen[j] = q.cycles;
-                fresh = true;
-                // total cycles at the contraction rate between the last two
-                // states read
-                est[j] = 0;
-                const int dc = q.cycles - prev_cyc[j];
-                if (!q.done && prev_cyc[j] >= 0 && dc > 0 && q.rsq > 0.0 && q.rsq < prev_rsq[j]) {
-                    const double lrate = 0.5 * std::log(q.rsq / prev_rsq[j]) / dc;
-                    const double lgoal = 0.5 * std::log(c->ctl_host->rtol2 * q.r0sq / q.rsq);
-                    est[j] = q.cycles + std::min(std::max((int)std::ceil(lgoal / lrate), 1), 64);
+        long long ver = 0;
+        HostSum q;
+        if (__atomic_load_n(&c->mirror->end, __ATOMIC_ACQUIRE) != last_ver &&
+            read_summary(c->mirror, &q, &ver) && (ver >> 32) == epoch && ver != last_ver) {
+            last_ver = ver;
+            sum = q;
+            if (c->batch == 1) {
+                // the device's running / want_cycles rule for one instance
+                sum.running = !q.done && q.cycles < max_cycles;
+                sum.want = q.cycles + 2;
+                if (q.prev_rsq > 0.0 && q.rsq > 0.0 && q.rsq < q.prev_rsq) {
+                    const double k = std::log(c->ctl_host->rtol2 * q.r0sq / q.rsq) /
+                                     std::log(q.rsq / q.prev_rsq);
+                    const int n = (int)std::fmin(std::fmax(std::ceil(k), 1.0), 64.0);
+                    sum.want = q.cycles + (n > 3 ? n - 1 : n);
                 }
             }
-            if (!finished(j)) {
-                all = false;
-                lo = std::min(lo, std::max(seen[j], 0));
-            }
-        }
-        if (all) break;
-        if (fresh) {
-            // queue up to the largest estimate, one short of it while more
-            // than three cycles are still ahead (a later state refines it);
-            // two cycles past the last state read of an instance without one
-            int want = 0;
-            for (int j = 0; j < B; ++j) {
-                if (finished(j)) continue;
-                if (est[j] == 0) want = std::max(want, std::max(seen[j], 0) + 2);
-                else want = std::max(want, est[j] - lo > 3 ? est[j] - 1 : est[j]);
-            }
-            want = std::min(want, max_cycles);
+            if (sum.running == 0) break;
+            const int want = std::min(std::max(sum.want, 1), max_cycles);
             if (want > launched && (rc = launch(want - launched))) return rc;
             since = std::chrono::steady_clock::now();
             continue;
         }
-        // nothing new for a while: if the stream has drained, every state it
-        // will write is there, so one more read decides (queried rarely: a
-        // query is not free for the stream)
+        // nothing new for a while: if the stream has drained, every summary
+        // it will write is there, so one more read decides (queried rarely:
+        // a query is not free for the stream)
         if (++polls % 4096 == 0 && std::chrono::steady_clock::now() - since > kQuiet) {
             since = std::chrono::steady_clock::now();
-            const hipError_t q = hipStreamQuery(s);
-            if (q == hipSuccess) {
-                bool again = false;
-                for (int j = 0; j < B; ++j) {
-                    HostState r;
-                    if (read_state(c->mirror + j, &r) && ((r.ver - 2) >> 33) == epoch &&
-                        r.cycles > seen[j])
-                        again = true;
-                }
+            const hipError_t qs = hipStreamQuery(s);
+            if (qs == hipSuccess) {
+                long long v = 0;
+                HostSum r;
+                const bool again =
+                    !read_summary(c->mirror, &r, &v) || (v >> 32) != epoch || v != last_ver;
                 if (!again) {
                     // a drained stream with a running instance: queue one
                     // more cycle, or give up when none is left
                     if (launched >= max_cycles) return TMG_ERR_HIP;
                     if ((rc = launch(1))) return rc;
                 }
-            } else if (q != hipErrorNotReady) {
-                c->last_hip = (int)q;
+            } else if (qs != hipErrorNotReady) {
+                c->last_hip = (int)qs;
                 return TMG_ERR_HIP;
             }
         }
     }
     HIPCHK(c, hipEventRecord(c->drain_ev, s));
     c->drain_pending = true;
+    // per-instance results: the summary holds a single instance's; a batch
+    // reads its states once (after the cycles still queued)
+    if (c->batch > 1) {
+        HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(InstState) * c->batch,
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    } else {
+        c->st_host[0].cycles = sum.cycles;
+        c->st_host[0].done = sum.done;
+        c->st_host[0].r0sq = sum.r0sq;
+        c->st_host[0].rsq = sum.rsq;
+    }
     int status = TMG_OK;
     for (int j = 0; j < c->batch; ++j) {
-        const HostState &q = cur[j];
+        const InstState &q = c->st_host[j];
         if (q.cycles == 0) {
             // no cycle ran for it (r_0 = 0 or max_cycles = 0): the iterate is u = 0
             HIPCHK(c, hipMemsetAsync(u + c->slab_off_h[0][j] * c->P, 0,
@@ -1348,10 +1339,13 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
         hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess ||
-        hipHostMalloc((void **)&c->mirror, sizeof(HostState) * batch,
+        hipHostMalloc((void **)&c->mirror, sizeof(HostHead) + sizeof(HostSum),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(TMG_ERR_OOM);
-    std::memset(c->mirror, 0, sizeof(HostState) * batch);
+    std::memset(c->mirror, 0, sizeof(HostHead) + sizeof(HostSum));
+    if ((rc = dalloc(c, &c->pubn_d, 1)) ||
+        hipMemsetAsync(c->pubn_d, 0, sizeof(unsigned), s) != hipSuccess)
+        return fail(rc ? rc : TMG_ERR_HIP);
     if (hipHostGetDevicePointer((void **)&c->mirror_d, c->mirror, 0) != hipSuccess ||
         hipEventCreateWithFlags(&c->drain_ev, hipEventDisableTiming) != hipSuccess)
         return fail(TMG_ERR_HIP);

@@ -53,6 +53,7 @@ struct TabLayout {
 struct InstState {
     double r0sq;   // ||r_0||^2
     double rsq;    // ||r_k||^2 of the last completed cycle
+    double prev_rsq; // ||r_{k-1}||^2 (k >= 2; else -1)
     int cycles;    // completed cycles
     int done;      // 0 running, 1 converged, 2 max cycles, 3 non-finite, 4 diverged
 };
@@ -63,17 +64,28 @@ struct Control {
     int epoch;     // solve number (tags the host copies of the state)
 };
 
-// Host-visible copy of an instance's state in fine-grained pinned host
-// memory, written by the kernel that finishes a cycle so that the host can
-// follow a solve without stopping the stream.  `ver` is a sequence lock:
-// 2X + 1 while the fields are written, 2X + 2 after, X = epoch * 2^32 +
-// cycles.
-struct HostState {
-    long long ver;
-    int cycles;
+// What the host needs to follow a solve without stopping the stream, in
+// fine-grained pinned host memory (a HostHead, then a HostSum), written
+// after each cycle: how many instances still run, and how many cycles to
+// have queued (the largest count an instance reaches when it converges at
+// the rate of its last two cycles).  For a single instance it holds that
+// instance's state instead, from which the host works out the same (off the
+// GPU's critical path).  begin and end are a sequence lock: the writer
+// stores begin = V, the summary, then end = V, with V = epoch * 2^32 + n
+// (n differs for every copy of a solve); a reader that finds
+// end == begin == V after reading the summary has a consistent copy.
+struct HostHead {
+    long long begin;
+    long long end;
+};
+struct HostSum {
+    int running;   // batch: instances not finished
+    int want;      // batch: cycles to have queued
+    int cycles;    // single instance: its state
     int done;
     double r0sq;
     double rsq;
+    double prev_rsq;
 };
 
 // Arguments of the streaming "leg" kernel (one level, all participating
@@ -209,7 +221,7 @@ struct BottomArgsT {
     const int *nlev;         // [batch] levels of each instance
     InstState *st;           // level 0: the work-group also finishes its instance's cycle
     const Control *ctl;
-    HostState *mirror;       // host copy of the state after such a cycle (may be null)
+    HostHead *mirror;        // one instance: its host copy after such a cycle (else null)
     int level, batch, tab_stride, nu1, nu2, gamma;
 };
 using BottomArgs = BottomArgsT<double>;
@@ -228,8 +240,12 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          int batch, double *partial, int64_t ntiles, hipStream_t s);
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
-                           InstState *st, const Control *ctl, HostState *mirror, int is_r0,
+                           InstState *st, const Control *ctl, HostHead *mirror, int is_r0,
                            hipStream_t s);
+// Writes the summary of st[0 .. batch) into the host copy (count: the copies
+// made so far).
+hipError_t launch_publish(const InstState *st, int batch, const Control *ctl, HostHead *mirror,
+                          unsigned *count, hipStream_t s);
 // out[2j] = -sum_n z_n^T M_tau u_n, out[2j+1] = v^T z_1 (tau[j]: fine slab length).
 hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,
                        const int64_t *slab_off, int batch, double *out, hipStream_t s);

@@ -725,28 +725,62 @@ __device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int 
     }
 }
 
-// Copy of instance j's state into host memory (see HostState).  The
-// system-scope fences order the sequence-lock stores around the fields.
-__device__ __forceinline__ void publish(HostState *mirror, int j, const InstState &s, int epoch)
+// An instance still running after its last cycle.
+__device__ __forceinline__ bool running(const InstState &s, const Control *ctl)
 {
-    if (!mirror) return;
-    HostState *h = mirror + j;
-    const long long x = ((long long)epoch << 32) | (unsigned)s.cycles;
-    __hip_atomic_store(&h->ver, 2 * x + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return !s.done && s.cycles < ctl->max_cycles;
+}
+
+// Cycles to have queued for a running instance: the count at which it
+// converges at the rate of its last two cycles (the first cycle, from zero,
+// gives no rate), one short of it while more than three cycles are ahead (a
+// later summary refines it); two past its count while it has no rate.
+__device__ __forceinline__ int want_cycles(const InstState &s, const Control *ctl)
+{
+    if (s.prev_rsq > 0.0 && s.rsq > 0.0 && s.rsq < s.prev_rsq) {
+        const double k = log(ctl->rtol2 * s.r0sq / s.rsq) / log(s.rsq / s.prev_rsq);
+        const int n = (int)fmin(fmax(ceil(k), 1.0), 64.0);
+        return s.cycles + (n > 3 ? n - 1 : n);
+    }
+    return s.cycles + 2;
+}
+
+// Writes the host copy (see HostHead) from one thread.  A system-scope
+// release fence is an L2 writeback here: one pair per copy.
+__device__ __forceinline__ void put_summary(HostHead *h, long long v, int nrun, int want,
+                                            const InstState *one)
+{
+    HostSum *m = reinterpret_cast<HostSum *>(h + 1);
+    __hip_atomic_store(&h->begin, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-    __hip_atomic_store(&h->cycles, s.cycles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&h->done, s.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&h->r0sq, s.r0sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&h->rsq, s.rsq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&h->ver, 2 * x + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&m->running, nrun, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&m->want, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (one) {
+        __hip_atomic_store(&m->cycles, one->cycles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&m->done, one->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&m->r0sq, one->r0sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&m->rsq, one->rsq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&m->prev_rsq, one->prev_rsq, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __hip_atomic_store(&h->end, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Host copy for a single instance, by the thread that finished its cycle:
+// its state (batches: k_publish after the cycle).
+__device__ __forceinline__ void publish(HostHead *h, const InstState &s, const Control *ctl)
+{
+    if (!h) return;
+    put_summary(h, ((long long)ctl->epoch << 32) | (unsigned)s.cycles, 0, 0, &s);
 }
 
 // Convergence state after a cycle whose squared residual norm is acc
 // (relative residual criterion of section 4.2).
 __device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, const Control *ctl,
-                                             HostState *mirror)
+                                             HostHead *mirror)
 {
     InstState s = st[j];
+    s.prev_rsq = s.cycles >= 1 ? s.rsq : -1.0;
     s.cycles += 1;
     s.rsq = acc;
     if (!isfinite(acc)) s.done = 3;
@@ -754,7 +788,7 @@ __device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, c
     else if (acc > 1e6 * s.r0sq) s.done = 4;
     else if (s.cycles >= ctl->max_cycles) s.done = 2;
     st[j] = s;
-    publish(mirror, j, s, ctl->epoch);
+    publish(mirror, s, ctl);
 }
 
 // Squared residual of the tile's output slabs into its partial slot (summed
@@ -1709,7 +1743,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
                                                           const int64_t *__restrict__ norm_off,
                                                           InstState *__restrict__ st,
                                                           const Control *__restrict__ ctl,
-                                                          HostState *__restrict__ mirror, int is_r0)
+                                                          HostHead *__restrict__ mirror, int is_r0)
 {
     __shared__ double red[kFinThreads / 64];
     const int j = blockIdx.x;
@@ -1736,10 +1770,49 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
     InstState s = st[j];
     s.r0sq = acc;
     s.rsq = acc;
+    s.prev_rsq = -1.0;
     s.cycles = 0;
     s.done = !isfinite(acc) ? 3 : (acc == 0.0 ? 1 : 0);
     st[j] = s;
-    publish(mirror, j, s, ctl->epoch);
+    publish(mirror, s, ctl);
+}
+
+// Host copy for a batch (see HostHead): the number of running instances and
+// the most cycles any of them wants queued, reduced over the batch by one
+// work-group.
+__global__ __launch_bounds__(kFinThreads) void k_publish(const InstState *__restrict__ st,
+                                                         int batch,
+                                                         const Control *__restrict__ ctl,
+                                                         HostHead *__restrict__ h,
+                                                         unsigned *__restrict__ count)
+{
+    constexpr int NW = kFinThreads / 64;
+    __shared__ int rn[NW], rw[NW];
+    int nrun = 0, want = 0;
+    for (int j = threadIdx.x; j < batch; j += kFinThreads) {
+        const InstState s = st[j];
+        if (running(s, ctl)) {
+            ++nrun;
+            want = max(want, want_cycles(s, ctl));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nrun += __shfl_down(nrun, off, 64);
+        want = max(want, __shfl_down(want, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rn[threadIdx.x >> 6] = nrun;
+        rw[threadIdx.x >> 6] = want;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < NW; ++w) {
+        nrun += rn[w];
+        want = max(want, rw[w]);
+    }
+    const unsigned n = *count + 1;
+    *count = n;
+    put_summary(h, ((long long)ctl->epoch << 32) | n, nrun, want, nullptr);
 }
 
 // dlambda_j = -sum_n z_n^T M_tau u_n (M_tau = tau diag(1/(2k+1))),
@@ -1858,11 +1931,18 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
 }
 
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
-                           InstState *st, const Control *ctl, HostState *mirror, int is_r0,
+                           InstState *st, const Control *ctl, HostHead *mirror, int is_r0,
                            hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kFinThreads), 0, s, partial, norm_off, st, ctl,
                        mirror, is_r0);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const InstState *st, int batch, const Control *ctl, HostHead *mirror,
+                          unsigned *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(kFinThreads), 0, s, st, batch, ctl, mirror, count);
     return hipGetLastError();
 }
 
