@@ -926,16 +926,21 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     TileList *tl;
     int rc = get_tiles(c, 0, kAll, tile_slabs(c->P), s, &tl);
     if (rc) return rc;
+    // cycles the previous solve left queued (on its stream) stay no-ops only
+    // while the state they read says finished: this solve resets that state,
+    // so its stream waits for them first (nothing to wait for on one stream)
+    if (c->drain_pending) HIPCHK(c, hipStreamWaitEvent(s, c->drain_ev, 0));
     c->epoch = c->epoch % (1 << 20) + 1;
     const long long epoch = c->epoch;
     c->ctl_host->rtol2 = rtol * rtol;
     c->ctl_host->max_cycles = max_cycles;
     c->ctl_host->epoch = c->epoch;
-    HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(Control), hipMemcpyHostToDevice, s));
-    // initial residual r_0 = f (u0 folded), u = 0
+    // initial residual r_0 = f (u0 folded), u = 0; the launch that finishes
+    // it also installs this solve's control block on the device
     HIPCHK(c, launch_norm_f(c->P, f, trans ? nullptr : u0, tab_of(c, 0, trans), c->tab_stride,
                             c->slab_off_d[0], tl->d_off, c->batch, c->partial, tl->ntiles, s));
-    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 1, s));
+    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 1, s,
+                              c->ctl, c->ctl_host));
     if (c->batch > 1)
         HIPCHK(c, launch_publish(c->st, c->batch, c->ctl, c->mirror_d, c->pubn_d, s));
 

@@ -239,9 +239,12 @@ hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ni
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          int batch, double *partial, int64_t ntiles, hipStream_t s);
+// With ctl_set (is_r0 only) the launch also writes *val to ctl_set and uses
+// it instead of ctl.
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
                            InstState *st, const Control *ctl, HostHead *mirror, int is_r0,
-                           hipStream_t s);
+                           hipStream_t s, Control *ctl_set = nullptr,
+                           const Control *val = nullptr);
 // Writes the summary of st[0 .. batch) into the host copy (count: the copies
 // made so far).
 hipError_t launch_publish(const InstState *st, int batch, const Control *ctl, HostHead *mirror,

@@ -1737,16 +1737,24 @@ __global__ __launch_bounds__(kLegThreads) void k_norm_f(const double *__restrict
 // the convergence state (relative residual criterion of section 4.2).  After
 // a cycle, instances without partials (no tile in the level-0 pass: their
 // whole hierarchy ran in the bottom kernel, which updated their state) are
-// left alone.
+// left alone.  A solve's first launch (is_r0 with ctl_set) also installs
+// the solve's control block `val` at ctl_set for the kernels after it (one
+// launch instead of a host-to-device copy).
 constexpr int kFinThreads = 1024;
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restrict__ partial,
                                                           const int64_t *__restrict__ norm_off,
                                                           InstState *__restrict__ st,
                                                           const Control *__restrict__ ctl,
-                                                          HostHead *__restrict__ mirror, int is_r0)
+                                                          HostHead *__restrict__ mirror, int is_r0,
+                                                          Control *__restrict__ ctl_set,
+                                                          Control val)
 {
     __shared__ double red[kFinThreads / 64];
     const int j = blockIdx.x;
+    if (ctl_set) {
+        if (j == 0 && threadIdx.x == 0) *ctl_set = val;
+        ctl = &val;
+    }
     const int64_t lo = norm_off[j], hi = norm_off[j + 1];
     if (!is_r0 && (st[j].done || lo == hi)) return;
     // eight independent loads in flight per thread, summed in a fixed order
@@ -1932,10 +1940,12 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
 
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,
                            InstState *st, const Control *ctl, HostHead *mirror, int is_r0,
-                           hipStream_t s)
+                           hipStream_t s, Control *ctl_set, const Control *val)
 {
+    Control v{};
+    if (val) v = *val;
     hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kFinThreads), 0, s, partial, norm_off, st, ctl,
-                       mirror, is_r0);
+                       mirror, is_r0, ctl_set, v);
     return hipGetLastError();
 }
 

@@ -120,3 +120,28 @@ def test_uneven_convergence_in_one_batch():
         assert r.cycles[j] == k
         assert relerr(U[seg], uo) <= 1e-12
     assert max(ks) > min(ks)
+
+
+def test_solves_on_two_streams_in_turn():
+    """A solve may return with cycles still queued on its stream (they do
+    nothing once its instances finished).  A following solve on another
+    stream resets the state those cycles read, so it must wait for them:
+    both results stay the oracle's."""
+    p, Ns = 3, [8192]
+    lams, Ts, u0, fs = _case(34, Ns, p)
+    s = B().Solver(Ns, Ts, lams, p=p)
+    f1, d0 = dev(fs[0]), dev(u0)
+    f2 = dev(fs[0][::-1].copy())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ref1, k1, _, _ = core.solve(p, Ts[0], lams[0], u0[0], fs[0], rtol=1e-4)
+    ref2, k2, _, _ = core.solve(p, Ts[0], lams[0], u0[0], fs[0][::-1].copy(), rtol=1e-10)
+    torch.cuda.synchronize()   # inputs made on the default stream
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            r1 = s.solve(f1, d0, rtol=1e-4)
+        with torch.cuda.stream(s2):
+            r2 = s.solve(f2, d0, rtol=1e-10)
+        torch.cuda.synchronize()
+        assert r1.cycles[0] == k1 and r2.cycles[0] == k2
+        assert relerr(host(r1.u), ref1) <= 1e-12
+        assert relerr(host(r2.u), ref2) <= 1e-12
