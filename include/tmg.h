@@ -148,11 +148,12 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
 
 /*
  * Schedule autotuner.  Installs in h the fastest of a few schedules, timed on
- * this hardware with the caller's data: for each candidate it runs three
- * cycles of the solve of L u = f (u0 folded) and measures them with HIP
- * events.  A schedule is the size up to which an instance's levels run inside
- * the single-work-group bottom kernel (bottom_cap, the largest the bottom
- * kernel holds divided by 1, 2, ..., 32) and, for V-cycles, whether
+ * this hardware with the caller's data: for each candidate it runs four
+ * cycles of the solve of L u = f (u0 folded) and keeps the faster of two
+ * runs timed with HIP events.  A schedule is the size up to which an
+ * instance's levels run inside the single-work-group bottom kernel
+ * (bottom_cap, the largest the bottom kernel holds divided by 1, 2, ...,
+ * 32) and, for V-cycles, whether
  * consecutive levels share two-level launches, and whether the levels
  * after the first `span_after` such pairs run in spans of `span` levels per
  * launch (3 or 4; 0: no spans; V-cycles only); then, for the fastest of

@@ -1458,21 +1458,26 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     float best = -1.0f;
     Cand pick = old;
     constexpr int kCycles = 4;
-    // a run that captures the graphs, then a timed one (rtol 0: every
-    // instance runs kCycles cycles); milliseconds, or < 0 on an error
+    // a run that captures the graphs, then the faster of two timed ones
+    // (rtol 0: every instance runs kCycles cycles); milliseconds, or < 0 on
+    // an error
     auto timed = [&]() -> float {
         rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
         if (rc < 0) return -1.0f;
-        if (hipEventRecord(e0, s) != hipSuccess) { rc = TMG_ERR_HIP; return -1.0f; }
-        rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
-        if (rc < 0) return -1.0f;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            rc = TMG_ERR_HIP;
-            return -1.0f;
+        float best_ms = -1.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = TMG_ERR_HIP; return -1.0f; }
+            rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
+            if (rc < 0) return -1.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = TMG_ERR_HIP;
+                return -1.0f;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (best_ms < 0.0f || ms < best_ms) best_ms = ms;
         }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        return ms;
+        return best_ms;
     };
     auto run_stage = [&]() {
         for (const Cand &cd : cands) {
