@@ -816,10 +816,14 @@ __device__ __forceinline__ void norm_partial(const double (&r)[S][P], double *pa
 // an even slab) and meet through a lane shuffle.
 // TOUCH (a.touch): the tables are brought into the scalar cache at entry
 // (small launches); a separate instantiation, as even an untaken branch
-// costs the level-0 pass registers.
-template <int P, bool BW, typename T, bool TOUCH>
+// costs the level-0 pass registers.  LEG: 0 any leg; 1 down legs and 2 up
+// legs of a first visit from zero (the levels below 0 of a V-cycle), with
+// the paths they do not take compiled out, which frees registers for more
+// work-groups per CU.
+template <int P, bool BW, typename T, bool TOUCH, int LEG>
 __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
 {
+    constexpr bool kAny = LEG == 0, kDown = LEG == 1, kUp = LEG == 2;
     constexpr int S = slabs_per_thread(P);
     constexpr int SC = S >= 2 ? S / 2 : 1;  // coarse slabs touched per thread
     __shared__ double xchg[2][kLegWaves];
@@ -836,12 +840,21 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     const int64_t cm0 = S >= 2 ? m0 / 2 : (m0 >> 1);
     const int64_t c2m0 = SC >= 2 ? cm0 / 2 : (cm0 >> 1);
     load_chunk<P, S, BW, T>(a.f + tr.off * P, m0, tr.N, f);
-    load_iterate<P, S, BW, T>(u, a.u_in, a.halo_in, tr, m0, li0, a.halo);
-    if (a.e2) {
-        load_chunk<P, SC, BW, T>(a.f1 + tr.coff * P, cm0, tr.Nc, f1);
-        load_chunk<P, SC2, BW, T>(a.e2 + tr.c2off * P, c2m0, tr.Nc2, e2);
-    } else if (a.e) {
-        load_chunk<P, SC, BW, T>(a.e + tr.coff * P, cm0, tr.Nc, e);
+    if constexpr (kAny) {
+        load_iterate<P, S, BW, T>(u, a.u_in, a.halo_in, tr, m0, li0, a.halo);
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int k = 0; k < P; ++k) u[s][k] = (T)0;
+    }
+    if constexpr (!kDown) {
+        if (a.e2) {
+            load_chunk<P, SC, BW, T>(a.f1 + tr.coff * P, cm0, tr.Nc, f1);
+            load_chunk<P, SC2, BW, T>(a.e2 + tr.c2off * P, c2m0, tr.Nc2, e2);
+        } else if (a.e) {
+            load_chunk<P, SC, BW, T>(a.e + tr.coff * P, cm0, tr.Nc, e);
+        }
     }
     const int done = a.st ? a.st[tr.j].done : 0;
     LazyOps<P, T> op;
@@ -861,7 +874,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     int phase = 0;
     LazyOps<P, T> op1;   // the next level (two-level launches)
     op1.load(a.tab1 + (int64_t)tr.j * a.tab_stride, a.tab1T + (int64_t)tr.j * a.tab_stride);
-    if (a.e2) {
+    if (!kDown && a.e2) {
         // the next level's up leg on the tile's coarse slabs: its first slabs
         // (pre + post - 1 of them) see a zero left neighbour and are wrong,
         // which the halo absorbs
@@ -875,19 +888,19 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
         prolong_add<P, SC, T>(e, e2, a.R, cm0);
         sweeps<P, SC, kLegWaves, T>(e, g1, op1, a.post, xchg, phase);
     }
-    if (a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
+    if (kAny && a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
     apply_G<P, S, T>(g, f, op);
     sweeps<P, S, kLegWaves, T>(u, g, op, a.pre, xchg, phase);
-    if (a.e || a.e2) prolong_add<P, S, T>(u, e, a.R, m0);
-    sweeps<P, S, kLegWaves, T>(u, g, op, a.post, xchg, phase);
-    if (a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
-    store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
+    if (!kDown && (a.e || a.e2)) prolong_add<P, S, T>(u, e, a.R, m0);
+    if constexpr (!kDown) sweeps<P, S, kLegWaves, T>(u, g, op, a.post, xchg, phase);
+    if (!kDown && a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
+    if constexpr (kAny) store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
     double r[S][P];
-    if (a.partial) {
+    if (kAny && a.partial) {
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
         norm_partial<P, S, kLegWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
     }
-    if (a.rc) {
+    if (!kUp && a.rc) {
         static_assert(S >= 2, "streaming tiles hold whole coarse slabs per thread");
         sweeps<P, S, kLegWaves, T>(u, g, op, a.next, xchg, phase);
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
@@ -1867,12 +1880,24 @@ hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
         const dim3 grid((unsigned)ntiles), block(kLegThreads);
-        if (a.touch) {
-            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_leg<PP, false, T, true>), grid, block, 0, s, a);
+        // legs of a first visit from zero below level 0: the pruned forms
+        const bool plain = a.touch && !a.u_in && !a.halo_in && !a.halo_out && !a.partial &&
+                           !a.u0 && a.next == 0;
+        const int leg = !plain ? 0
+                        : (a.rc && !a.e && !a.e2 && !a.u_out && a.post == 0) ? 1
+                        : (!a.rc && (a.e || a.e2)) ? 2 : 0;
+        if (!a.touch) {
+            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, false, 0>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_leg<PP, false, T, false, 0>), grid, block, 0, s, a);
+        } else if (leg == 1) {
+            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, true, 1>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_leg<PP, false, T, true, 1>), grid, block, 0, s, a);
+        } else if (leg == 2) {
+            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, true, 2>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_leg<PP, false, T, true, 2>), grid, block, 0, s, a);
         } else {
-            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, false>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_leg<PP, false, T, false>), grid, block, 0, s, a);
+            if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, true, 0>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_leg<PP, false, T, true, 0>), grid, block, 0, s, a);
         }
     })
     return hipGetLastError();
