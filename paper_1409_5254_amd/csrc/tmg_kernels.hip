@@ -775,11 +775,10 @@ __device__ __forceinline__ void publish(HostHead *h, const InstState &s, const C
 }
 
 // Convergence state after a cycle whose squared residual norm is acc
-// (relative residual criterion of section 4.2).
-__device__ __forceinline__ void finish_cycle(InstState *st, int j, double acc, const Control *ctl,
-                                             HostHead *mirror)
+// (relative residual criterion of section 4.2); s is st[j] before it.
+__device__ __forceinline__ void finish_cycle(InstState *st, int j, InstState s, double acc,
+                                             const Control *ctl, HostHead *mirror)
 {
-    InstState s = st[j];
     s.prev_rsq = s.cycles >= 1 ? s.rsq : -1.0;
     s.cycles += 1;
     s.rsq = acc;
@@ -1612,7 +1611,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
                 }
             }
             acc = block_sum<B::NW>(acc, sm.red);
-            if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl, a.mirror);
+            if (threadIdx.x == 0) finish_cycle(a.st, j, a.st[j], acc, a.ctl, a.mirror);
         }
         return;
     }
@@ -1709,7 +1708,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
 #pragma unroll
                 for (int k = 0; k < P; ++k) acc += r[s][k] * r[s][k];
         acc = block_sum<B::NW>(acc, sm.red);
-        if (threadIdx.x == 0) finish_cycle(a.st, j, acc, a.ctl, a.mirror);
+        if (threadIdx.x == 0) finish_cycle(a.st, j, a.st[j], acc, a.ctl, a.mirror);
     }
 }
 
@@ -1769,7 +1768,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
         ctl = &val;
     }
     const int64_t lo = norm_off[j], hi = norm_off[j + 1];
-    if (!is_r0 && (st[j].done || lo == hi)) return;
+    // the state is read once, here, so that its load overlaps the partials'
+    const InstState s0 = st[j];
+    if (!is_r0 && (s0.done || lo == hi)) return;
     // eight independent loads in flight per thread, summed in a fixed order
     double acc = 0.0;
     for (int64_t b = lo; b < hi; b += 8 * kFinThreads) {
@@ -1785,10 +1786,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
     acc = block_sum<kFinThreads / 64>(acc, red);
     if (threadIdx.x != 0) return;
     if (!is_r0) {
-        finish_cycle(st, j, acc, ctl, mirror);
+        finish_cycle(st, j, s0, acc, ctl, mirror);
         return;
     }
-    InstState s = st[j];
+    InstState s = s0;
     s.r0sq = acc;
     s.rsq = acc;
     s.prev_rsq = -1.0;
