@@ -155,8 +155,9 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
  * (bottom_cap, the largest the bottom kernel holds divided by 1, 2, ...,
  * 32) and, for V-cycles, whether
  * consecutive levels share two-level launches, and whether the levels
- * after the first `span_after` such pairs run in spans of `span` levels per
- * launch (3 or 4; 0: no spans; V-cycles only); then, for the fastest of
+ * after the first `span_after` streaming levels below level 1 (in pairs, an
+ * odd one out alone) run in spans of `span` levels per launch (3 or 4; 0:
+ * no spans; V-cycles only); then, for the fastest of
  * those, whether the cycles after the first of a solve are launched kernel
  * by kernel instead of as captured graphs (a graph launch idles the GPU for
  * several microseconds; direct launches pay when the host enqueues a cycle

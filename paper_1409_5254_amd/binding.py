@@ -196,7 +196,7 @@ class Solver:
         return dict(bottom_cap=cap.value, pairs=bool(pairs.value), span=span.value,
                     span_after=after.value, direct=bool(direct.value))
 
-    def set_schedule(self, bottom_cap, pairs=True, span=0, span_after=1, direct=False):
+    def set_schedule(self, bottom_cap, pairs=True, span=0, span_after=2, direct=False):
         """Install a schedule without timing (see autotune)."""
         self._check(lib().tmg_set_schedule(self._h, int(bottom_cap), int(bool(pairs)), int(span),
                                            int(span_after), int(bool(direct)), _stream()),

@@ -101,7 +101,7 @@ struct tmg_ctx {
     bool pairs = true;                            // two-level launches in V-cycles (schedule)
     bool direct = false;                          // cycles after the first launched kernel by kernel
     int span = 0;                                 // >= 3: levels after the first pairs in spans of it
-    int span_after = 1;                           // two-level launches before the spans
+    int span_after = 2;                           // streaming levels before the spans
     int *lb_d = nullptr;                          // [batch] lb on the device (spans)
     double *tab_fwd = nullptr, *tab_adj = nullptr;
     double *R_fwd = nullptr, *R_adj = nullptr;
@@ -549,12 +549,13 @@ int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, 
     return TMG_OK;
 }
 
-// First level run in spans: after the first span_after pairs of levels
+// First level run in spans: after the first span_after streaming levels
 // (spans pay only where a launch is latency-bound; the larger levels stay
-// in two-level launches), or none (Lmax).
+// in two-level launches, an odd one out in a one-level launch), or none
+// (Lmax).
 int span_start(const tmg_ctx *c, int first)
 {
-    return c->pairs && c->span_fits(c->span) ? first + 2 * c->span_after : c->Lmax;
+    return c->pairs && c->span_fits(c->span) ? first + c->span_after : c->Lmax;
 }
 
 // Levels >= 1 of a V-cycle (every visit a first visit from zero): all down
@@ -572,14 +573,20 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
     c->cur.assign(c->Lmax + 1, 0);
     const int dp = down_first == 1 ? kPair1 : kPair2, ds = down_first == 1 ? kSingle1 : kSingle2;
     const int sd = std::min(span_start(c, down_first), c->Lmax);
-    for (int l = down_first; l < sd; ++l) {
-        if (!c->pairs) {
+    if (!c->pairs) {
+        for (int l = down_first; l < sd; ++l)
             if ((rc = enqueue_down<T>(c, io, l, true, s))) return rc;
-            continue;
+    } else {
+        for (int l = down_first; l < sd; l += 2) {
+            if (l + 1 == sd) {
+                // a lone level before the spans: one leg for every instance
+                if ((rc = enqueue_down<T>(c, io, l, true, s))) return rc;
+                break;
+            }
+            if ((rc = enqueue_pair<T>(c, io, l, true, dp, s)) ||
+                (rc = enqueue_down<T>(c, io, l, true, s, ds)))
+                return rc;
         }
-        if ((rc = enqueue_pair<T>(c, io, l, true, dp, s)) ||
-            (rc = enqueue_down<T>(c, io, l, true, s, ds)))
-            return rc;
     }
     for (int l = sd; l < c->Lmax; l += c->span)
         if ((rc = enqueue_span<T>(c, io, l, c->span, true, s))) return rc;
@@ -590,11 +597,17 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
             if ((rc = enqueue_span<T>(c, io, l, c->span, false, s))) return rc;
     const int su = std::min(span_start(c, up_first), c->Lmax);
     const int kp = up_first == 1 ? kPair1 : kPair2, ks = up_first == 1 ? kSingle1 : kSingle2;
-    for (int l = su - 1; l >= up_first; --l) {
-        if (!c->pairs) {
+    if (!c->pairs) {
+        for (int l = su - 1; l >= up_first; --l)
             if ((rc = enqueue_up<T>(c, io, l, true, s))) return rc;
-            continue;
-        }
+        return TMG_OK;
+    }
+    int top = su - 1;   // the highest level below the spans
+    if (su < c->Lmax && ((su - up_first) & 1)) {
+        if ((rc = enqueue_up<T>(c, io, top, true, s))) return rc;
+        --top;
+    }
+    for (int l = top; l >= up_first; --l) {
         if ((rc = enqueue_pair<T>(c, io, l, false, kp, s)) ||
             (rc = enqueue_up<T>(c, io, l, true, s, ks)))
             return rc;
@@ -1132,7 +1145,7 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
     c->bottom_cap = cap;
     c->pairs = pairs;
     c->span = c->span_fits(span) ? span : 0;
-    c->span_after = std::max(span_after, 1);
+    c->span_after = std::max(span_after, 1);   // levels
     if (!c->lb_d && (rc = dalloc(c, &c->lb_d, batch))) return rc;
     HIPCHK(c, hipMemcpyAsync(c->lb_d, c->lb.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
     c->deep_n.assign(Lm + 1, 0);
@@ -1309,7 +1322,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                 return fail(rc);
         }
     }
-    if ((rc = apply_plan(c, bottom_cap, true, 0, 1, s))) return fail(rc);
+    if ((rc = apply_plan(c, bottom_cap, true, 0, 2, s))) return fail(rc);
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
         ta((size_t)Lm * batch * c->tab_stride, 0.0);
@@ -1447,7 +1460,7 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     for (int k = 0; k <= 5; ++k) {
         const int64_t cap = (int64_t)bottom_max(c->P) >> k;
         if (cap < c->opt.n_coarse) break;
-        cands.push_back({cap, true, 0, 1});
+        cands.push_back({cap, true, 0, 2});
     }
     const Cand old{c->bottom_cap, c->pairs, c->span, c->span_after};
     c->direct = false;
@@ -1493,9 +1506,9 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     run_stage();
     if (rc >= 0 && c->opt.gamma == 1 && best >= 0.0f) {
         cands.clear();
-        cands.push_back({pick.cap, false, 0, 1});
+        cands.push_back({pick.cap, false, 0, 2});
         for (int K = 3; K <= kMaxSpan; ++K)
-            for (int after = 1; after <= 3; ++after)
+            for (int after = 1; after <= 6; ++after)
                 if (c->span_fits(K)) cands.push_back({pick.cap, true, K, after});
         run_stage();
     }

@@ -125,7 +125,9 @@ def test_span_schedule_matches_pairs(precision, span, cap):
     f, d0 = dev(fh), dev(u0)
     s = B.Solver(Ns, Ts, lams, p=p, precision=precision)
     res = {}
-    for sp, after in ((0, 1), (span, 1), (span, 2)):
+    # span_after counts streaming levels below level 1 before the spans:
+    # 1 (a lone level), 2 (a pair), 3 (a pair and a lone level)
+    for sp, after in ((0, 2), (span, 1), (span, 2), (span, 3)):
         s.set_schedule(cap, pairs=True, span=sp, span_after=after)
         r = s.solve(f, d0, rtol=1e-10)
         assert r.status == 0
@@ -134,8 +136,8 @@ def test_span_schedule_matches_pairs(precision, span, cap):
         z, dl, du, cz, _, st = s.adjoint_solve(g, u=r.u)
         assert st == 0
         res[(sp, after)] = (u, list(r.cycles), host(z).copy(), cz, dl, du)
-    a = res[(0, 1)]
-    for key in ((span, 1), (span, 2)):
+    a = res[(0, 2)]
+    for key in ((span, 1), (span, 2), (span, 3)):
         b = res[key]
         assert a[1] == b[1] and a[3] == b[3]
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
