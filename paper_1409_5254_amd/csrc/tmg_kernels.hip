@@ -828,6 +828,9 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     __shared__ double xchg[2][kLegWaves];
     __shared__ double red[kLegWaves];
     const TileRef tr = tile_ref(a);
+    // a batch: the tiles of finished instances leave before loading anything
+    // (one instance keeps its loads ahead of the flag's, for their latency)
+    if (a.batch > 1 && a.st && a.st[tr.j].done) return;
     const int li0 = threadIdx.x * S;
     const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
     // every load is issued before the early-exit test: data first, then the
@@ -855,7 +858,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
             load_chunk<P, SC, BW, T>(a.e + tr.coff * P, cm0, tr.Nc, e);
         }
     }
-    const int done = a.st ? a.st[tr.j].done : 0;
+    const int done = (a.batch == 1 && a.st) ? a.st[tr.j].done : 0;
     LazyOps<P, T> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tabT + (int64_t)tr.j * a.tab_stride);
     if constexpr (TOUCH) {
@@ -1080,6 +1083,7 @@ __global__ __launch_bounds__(kSpanThreads) void k_span(SpanArgsT<T> a)
         j = find_instance(a.tile_off, a.batch, tile);
         tile -= a.tile_off[j];
     }
+    if (a.batch > 1 && a.st && a.st[j].done) return;   // as in k_leg
     const int K = min(a.K, a.lb[j] - a.level);
     // first slab of the tile at level l (a multiple of 2^K: no coarse slab
     // of the span straddles two tiles)
@@ -1121,7 +1125,7 @@ __global__ __launch_bounds__(kSpanThreads) void k_span(SpanArgsT<T> a)
 #pragma unroll
         for (int q = 0; q < P; ++q) f[0][q] = tmp[0][q];
     }
-    const int done = a.st ? a.st[j].done : 0;
+    const int done = (a.batch == 1 && a.st) ? a.st[j].done : 0;
     const int tb = TabLayout(P).stride() * 8, tbT = TabLayout(P).stride() * (int)sizeof(T);
     for (int k = 0; k < K; ++k) {
         const double *tk = a.tab + k * a.tab_level + (int64_t)j * a.tab_stride;
@@ -1209,6 +1213,9 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
     __shared__ double xchg[2][kLegWaves];
     __shared__ double red[kLegWaves];
     const TileRef tr = tile_ref(a);
+    // a batch: the tiles of finished instances leave before loading anything
+    // (one instance keeps its loads ahead of the flag's, for their latency)
+    if (a.batch > 1 && a.st && a.st[tr.j].done) return;
     const int li0 = threadIdx.x * S;
     const int64_t m0 = tr.t * a.tile_out - a.halo + li0;
     constexpr int SC2 = SC >= 2 ? SC / 2 : 1;
@@ -1224,7 +1231,7 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
     } else if (a.up) {
         load_chunk<P, SC, BW, float>(a.e + tr.coff * P, cm0, tr.Nc, e);
     }
-    const int done = a.st ? a.st[tr.j].done : 0;
+    const int done = (a.batch == 1 && a.st) ? a.st[tr.j].done : 0;
     LazyOps<P, float> op;
     op.load(a.tab + (int64_t)tr.j * a.tab_stride, a.tab32 + (int64_t)tr.j * a.tab_stride);
     LazyOps<P, float> op1;   // level 1 (two-level pass)
