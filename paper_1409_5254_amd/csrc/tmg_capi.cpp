@@ -56,6 +56,8 @@ enum TileKind {
 struct TileList {
     int64_t ntiles = 0;
     int64_t *d_off = nullptr;  // [batch+1]
+    int *d_inst = nullptr;     // [ntiles] instance of each tile (batch > 1): one load in
+                               // place of a binary search over d_off per work-group
 };
 
 struct GraphKey {
@@ -294,6 +296,15 @@ int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, Tile
     if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(tl.d_off, off.data(), off.size() * sizeof(int64_t),
                              hipMemcpyHostToDevice, s));
+    std::vector<int> inst;
+    if (c->batch > 1 && tl.ntiles > 0) {
+        inst.resize(tl.ntiles);
+        for (int j = 0; j < c->batch; ++j)
+            for (int64_t t = off[j]; t < off[j + 1]; ++t) inst[t] = j;
+        if ((rc = dalloc(c, &tl.d_inst, inst.size()))) return rc;
+        HIPCHK(c, hipMemcpyAsync(tl.d_inst, inst.data(), inst.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, s));
+    }
     HIPCHK(c, hipStreamSynchronize(s));
     auto res = c->tiles.emplace(key, tl);
     *out = &res.first->second;
@@ -340,6 +351,7 @@ LegArgsT<T> leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl
     a.slab_off = c->slab_off_d[level];
     a.cslab_off = level + 1 < c->Lmax ? c->slab_off_d[level + 1] : nullptr;
     a.tile_off = tl->d_off;
+    a.tile_inst = tl->d_inst;
     a.n0 = c->N[0] >> level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
@@ -503,6 +515,7 @@ int enqueue_span(tmg_ctx *c, const CycleIO &io, int level, int K, bool down, hip
     a.tab_level = (int64_t)c->batch * c->tab_stride;
     a.R = R_of<T>(c, io.trans);
     a.tile_off = tl->d_off;
+    a.tile_inst = tl->d_inst;
     a.st = io.use_state ? c->st : nullptr;
     a.lb = c->lb_d;
     a.n0 = c->N[0] >> level;
@@ -632,6 +645,7 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.slab_off = c->slab_off_d[0];
         a.cslab_off = c->slab_off_d[1];
         a.tile_off = t->d_off;
+        a.tile_inst = t->d_inst;
         a.st = io.use_state ? c->st : nullptr;
         a.n0 = c->N[0];
         a.batch = c->batch;
@@ -951,7 +965,8 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // initial residual r_0 = f (u0 folded), u = 0; the launch that finishes
     // it also installs this solve's control block on the device
     HIPCHK(c, launch_norm_f(c->P, f, trans ? nullptr : u0, tab_of(c, 0, trans), c->tab_stride,
-                            c->slab_off_d[0], tl->d_off, c->batch, c->partial, tl->ntiles, s));
+                            c->slab_off_d[0], tl->d_off, tl->d_inst, c->batch, c->partial,
+                            tl->ntiles, s));
     HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 1, s,
                               c->ctl, c->ctl_host));
     if (c->batch > 1)
@@ -1137,7 +1152,10 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
     HIPCHK(c, hipStreamSynchronize(s));
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
-    for (auto &kv : c->tiles) dfree(c, kv.second.d_off);
+    for (auto &kv : c->tiles) {
+        dfree(c, kv.second.d_off);
+        dfree(c, kv.second.d_inst);
+    }
     c->tiles.clear();
     for (int *p : c->bot_d) dfree(c, p);
     const int Lm = c->Lmax, batch = c->batch, P = c->P;

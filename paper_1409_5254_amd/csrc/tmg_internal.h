@@ -115,6 +115,7 @@ struct LegArgsT {
     const int64_t *slab_off; // [batch+1] slab offsets of this level
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
+    const int *tile_inst;    // [ntiles] instance of each tile (batch > 1)
     const InstState *st;     // per-instance early exit when st[j].done (may be null)
     // Two-level launches (levels l and l+1 of a V-cycle's first visits).
     // Up: with e2 != null the correction of level l+1 is not read from e but
@@ -154,6 +155,7 @@ struct SpanArgsT {
     int64_t tab_level;
     const T *R;
     const int64_t *tile_off;
+    const int *tile_inst;    // as in LegArgsT
     const InstState *st;
     const int *lb;           // [batch] first bottom-kernel level of each instance
     int64_t n0;              // slabs of instance 0 at level l (used when batch == 1)
@@ -179,6 +181,7 @@ struct MixArgs {
     const int64_t *slab_off;
     const int64_t *cslab_off;
     const int64_t *tile_off;
+    const int *tile_inst;    // as in LegArgsT
     const InstState *st;
     // two-level pass (as in LegArgsT): level 1's inner up leg computed in the
     // tile from f1 and the level-2 inner correction e2 instead of reading e,
@@ -238,7 +241,8 @@ template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s);
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
-                         int batch, double *partial, int64_t ntiles, hipStream_t s);
+                         const int *tile_inst, int batch, double *partial, int64_t ntiles,
+                         hipStream_t s);
 // With ctl_set (is_r0 only) the launch also writes *val to ctl_set and uses
 // it instead of ctl.
 hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int batch,

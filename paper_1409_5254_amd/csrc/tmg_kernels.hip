@@ -662,7 +662,7 @@ __device__ __forceinline__ TileRef tile_ref(const A &a)
 {
     TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2, 0, a.n0 / 4};
     if (a.batch > 1) {
-        r.j = find_instance(a.tile_off, a.batch, r.t);
+        r.j = a.tile_inst ? a.tile_inst[r.t] : find_instance(a.tile_off, a.batch, r.t);
         r.t = (int64_t)blockIdx.x - a.tile_off[r.j];
         r.off = a.slab_off[r.j];
         r.N = a.slab_off[r.j + 1] - r.off;
@@ -1080,7 +1080,7 @@ __global__ __launch_bounds__(kSpanThreads) void k_span(SpanArgsT<T> a)
     int j = 0;
     int64_t tile = blockIdx.x;
     if (a.batch > 1) {
-        j = find_instance(a.tile_off, a.batch, tile);
+        j = a.tile_inst ? a.tile_inst[tile] : find_instance(a.tile_off, a.batch, tile);
         tile -= a.tile_off[j];
     }
     if (a.batch > 1 && a.st && a.st[j].done) return;   // as in k_leg
@@ -1725,14 +1725,15 @@ __global__ __launch_bounds__(kLegThreads) void k_norm_f(const double *__restrict
                                                      const double *__restrict__ u0,
                                                      const double *__restrict__ tab, int tab_stride,
                                                      const int64_t *__restrict__ slab_off,
-                                                     const int64_t *__restrict__ tile_off, int batch,
+                                                     const int64_t *__restrict__ tile_off,
+                                                     const int *__restrict__ tile_inst, int batch,
                                                      double *__restrict__ partial)
 {
     constexpr int S = slabs_per_thread(P);
     constexpr TabLayout L(P);
     __shared__ double red[kLegWaves];
     const int64_t tile = blockIdx.x;
-    const int j = find_instance(tile_off, batch, tile);
+    const int j = batch == 1 ? 0 : tile_inst ? tile_inst[tile] : find_instance(tile_off, batch, tile);
     const int64_t t = tile - tile_off[j];
     const int64_t off = slab_off[j];
     const int64_t N = slab_off[j + 1] - off;
@@ -1961,12 +1962,13 @@ template hipError_t launch_bottom<float>(int, bool, const BottomArgsT<float> &, 
 
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
-                         int batch, double *partial, int64_t ntiles, hipStream_t s)
+                         const int *tile_inst, int batch, double *partial, int64_t ntiles,
+                         hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     TMG_DISPATCH_P(P, {
         hipLaunchKernelGGL((k_norm_f<PP>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, f, u0, tab,
-                           tab_stride, slab_off, tile_off, batch, partial);
+                           tab_stride, slab_off, tile_off, tile_inst, batch, partial);
     })
     return hipGetLastError();
 }
