@@ -182,6 +182,20 @@ int tmg_autotune(tmg_handle h, const double *f, const double *u0, double *u, int
 int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int span, int span_after,
                      int direct, tmg_stream s);
 
+/*
+ * Active sets of a batch (on by default; a single instance has none).  Once
+ * the running instances of a batch hold at most three quarters of its
+ * level-0 tiles, the later cycles of a solve launch work-groups for their
+ * tiles only, and are launched kernel by kernel; the lists are rebuilt each
+ * time that share drops by as much again.  Results are bitwise the same
+ * with it on or off: an instance's tiles and every reduction over them are
+ * the same, and the cycles after an instance finished leave it untouched
+ * either way.  With it on, fewer cycles are queued ahead of the last one
+ * the host has seen finish.  Batches above 65536 instances never use it.
+ * Returns TMG_ERR_INVALID for a null handle.
+ */
+int tmg_set_active_set(tmg_handle h, int on);
+
 /* Release every resource of h (synchronises its streams first). */
 int tmg_destroy(tmg_handle h);
 

@@ -26,7 +26,7 @@ MAX_DEGREE = 3
 
 # every symbol the header declares
 SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",
-           "tmg_autotune", "tmg_set_schedule",
+           "tmg_autotune", "tmg_set_schedule", "tmg_set_active_set",
            "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
            "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
            "tmg_op_coarse_solve",
@@ -82,6 +82,7 @@ def lib():
                                        _vp]),
             "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), P(_i), P(_i), P(_i), _vp]),
             "tmg_set_schedule": (_i, [_vp, _i64, _i, _i, _i, _i, _vp]),
+            "tmg_set_active_set": (_i, [_vp, _i]),
             "tmg_destroy": (_i, [_vp]),
             "tmg_error_string": (ctypes.c_char_p, [_i]),
             "tmg_last_hip_error": (_i, [_vp]),
@@ -201,6 +202,11 @@ class Solver:
         self._check(lib().tmg_set_schedule(self._h, int(bottom_cap), int(bool(pairs)), int(span),
                                            int(span_after), int(bool(direct)), _stream()),
                     "tmg_set_schedule")
+
+    def set_active_set(self, on):
+        """Later cycles of a batch on the running instances' tiles only
+        (on by default; the results are bitwise the same either way)."""
+        self._check(lib().tmg_set_active_set(self._h, int(bool(on))), "tmg_set_active_set")
 
     def vcycle(self, f, u0, u):
         self._check(lib().tmg_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),

@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -58,6 +59,37 @@ struct TileList {
     int64_t *d_off = nullptr;  // [batch+1]
     int *d_inst = nullptr;     // [ntiles] instance of each tile (batch > 1): one load in
                                // place of a binary search over d_off per work-group
+    const int64_t *d_base = nullptr;  // active-set lists: the full list's d_off
+    std::vector<int64_t> h_off;       // full lists: d_off on the host
+};
+
+// Once most of a batch has finished, the work-groups of its finished
+// instances (which leave at once, but still cost a launch slot and a few
+// dependent loads each) dominate a cycle.  The later cycles of a solve then
+// run on lists of the running instances' tiles only, built on the host from
+// the run bits each cycle's summary carries, whenever the running share of
+// level-0 tiles has dropped to kActiveShare of the lists in use.  The lists
+// of one generation live in a device arena, copied there in stream order
+// from a pinned staging buffer (two, used in turn by generations, so that
+// the host never writes one a queued copy still reads).  They cover the
+// tile lists the cycles after the first use (recorded as they are asked
+// for); any other list is used in full.
+constexpr double kActiveShare = 0.75;
+constexpr int kActiveAhead = 2;   // cycles queued past the last summary
+struct ActiveSet {
+    bool enabled = true;
+    bool on = false;                   // the cycles being queued use `lists`
+    std::vector<unsigned> run;         // run bits the lists are built for
+    int64_t tiles = 0;                 // level-0 tiles of the lists in use
+    std::map<std::tuple<int, int, int>, TileList> lists;
+    std::vector<int *> bot;            // per level: running instances with lb == level
+    std::vector<int> bot_n;
+    char *arena = nullptr;             // device
+    char *stage[2] = {nullptr, nullptr};   // pinned host
+    size_t cap = 0;
+    int which = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr}; // after the last copy out of stage[k]
+    bool is_run(int j) const { return (run[j >> 5] >> (j & 31)) & 1u; }
 };
 
 struct GraphKey {
@@ -116,6 +148,9 @@ struct tmg_ctx {
     std::vector<int> bot_n;
     std::vector<int> deep_n;                      // per level: instances with level < lb
     int64_t bottom_cap = 0;
+    ActiveSet act;
+    std::set<std::tuple<int, int, int>> cycle_keys;   // tile lists of cycles after the first
+    bool in_cycle = false;                            // enqueue_cycle of such a cycle
     InstState *st = nullptr, *st_ops = nullptr;
     InstState *st_host = nullptr;                 // pinned, batch states (results, op calls)
     Control *ctl = nullptr, *ctl_host = nullptr;  // device / pinned
@@ -273,11 +308,16 @@ bool participates(const tmg_ctx *c, int j, int level, int kind)
 
 // Tile offsets (prefix sums of ceil(N_jl / tile_out) over participating
 // instances) for one (level, kind, tile_out), cached on the device.
+int get_active_tiles(tmg_ctx *c, const TileList &full, const std::tuple<int, int, int> &key,
+                     hipStream_t s, TileList **out);
+
 int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, TileList **out)
 {
     auto key = std::make_tuple(level, kind, tile_out);
+    if (c->in_cycle) c->cycle_keys.insert(key);
     auto it = c->tiles.find(key);
     if (it != c->tiles.end()) {
+        if (c->act.on) return get_active_tiles(c, it->second, key, s, out);
         *out = &it->second;
         return TMG_OK;
     }
@@ -306,8 +346,125 @@ int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, Tile
                                  hipMemcpyHostToDevice, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
-    auto res = c->tiles.emplace(key, tl);
+    tl.h_off = std::move(off);
+    auto res = c->tiles.emplace(key, std::move(tl));
+    if (c->act.on) return get_active_tiles(c, res.first->second, key, s, out);
     *out = &res.first->second;
+    return TMG_OK;
+}
+
+size_t a256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// The active-set form of a full tile list (the full list itself if the
+// generation has none for it: its finished instances leave at once).
+int get_active_tiles(tmg_ctx *c, const TileList &full, const std::tuple<int, int, int> &key,
+                     hipStream_t, TileList **out)
+{
+    auto it = c->act.lists.find(key);
+    *out = it != c->act.lists.end() ? &it->second : const_cast<TileList *>(&full);
+    return TMG_OK;
+}
+
+// The bottom kernel's instance list of a level (active-set form while one
+// is in use).
+void bottom_list(const tmg_ctx *c, int level, const int **inst, int *n)
+{
+    const ActiveSet &A = c->act;
+    const bool act = A.on && level < (int)A.bot_n.size();
+    *inst = act ? A.bot[level] : c->bot_d[level];
+    *n = act ? A.bot_n[level] : c->bot_n[level];
+}
+
+// Starts a generation of active-set lists for the run bits `run` (level-0
+// tiles `tiles`): every tile list the cycles of a solve use and the bottom
+// kernel's lists, built on the host and sent to the device in one copy
+// (each copy costs the stream a switch between engines).
+int act_begin(tmg_ctx *c, std::vector<unsigned> &run, int64_t tiles, hipStream_t s)
+{
+    ActiveSet &A = c->act;
+    const int B = c->batch;
+    A.run.swap(run);
+    std::vector<int> bl;
+    std::vector<int> bcount(c->Lmax, 0);
+    for (int j = 0; j < B; ++j)
+        if (A.is_run(j) && c->lb[j] < c->Lmax) bcount[c->lb[j]]++;
+    size_t need = 0;
+    for (int l = 0; l < c->Lmax; ++l) need += a256(sizeof(int) * bcount[l]);
+    std::vector<std::pair<const std::tuple<int, int, int> *, const TileList *>> keys;
+    std::vector<int64_t> nrun;
+    for (const auto &k : c->cycle_keys) {
+        auto it = c->tiles.find(k);
+        if (it == c->tiles.end()) continue;
+        const std::vector<int64_t> &fo = it->second.h_off;
+        int64_t n = 0;
+        for (int j = 0; j < B; ++j)
+            if (A.is_run(j)) n += fo[j + 1] - fo[j];
+        keys.emplace_back(&k, &it->second);
+        nrun.push_back(n);
+        need += a256(sizeof(int64_t) * (B + 1)) + a256(sizeof(int) * n);
+    }
+    if (need > A.cap) {
+        // nothing queued may still read the arena or a staging buffer
+        HIPCHK(c, hipStreamSynchronize(s));
+        dfree(c, A.arena);
+        A.arena = nullptr;
+        for (int k = 0; k < 2; ++k) {
+            if (A.stage[k]) (void)hipHostFree(A.stage[k]);
+            A.stage[k] = nullptr;
+        }
+        A.cap = 0;
+        const size_t cap = need + need / 2;
+        int rc = dalloc(c, &A.arena, cap);
+        if (rc) return rc;
+        for (int k = 0; k < 2; ++k)
+            HIPCHK(c, hipHostMalloc((void **)&A.stage[k], cap, hipHostMallocDefault));
+        A.cap = cap;
+    }
+    for (int k = 0; k < 2; ++k)
+        if (!A.ev[k]) HIPCHK(c, hipEventCreateWithFlags(&A.ev[k], hipEventDisableTiming));
+    A.which ^= 1;
+    // the copy of the generation before last read this staging buffer
+    HIPCHK(c, hipEventSynchronize(A.ev[A.which]));
+    char *const h = A.stage[A.which];
+    size_t used = 0;
+    A.lists.clear();
+    for (size_t q = 0; q < keys.size(); ++q) {
+        const std::vector<int64_t> &fo = keys[q].second->h_off;
+        int64_t *off = reinterpret_cast<int64_t *>(h + used);
+        const size_t bo = a256(sizeof(int64_t) * (B + 1));
+        int *inst = reinterpret_cast<int *>(h + used + bo);
+        off[0] = 0;
+        for (int j = 0; j < B; ++j) {
+            const int64_t m = A.is_run(j) ? fo[j + 1] - fo[j] : 0;
+            std::fill(inst + off[j], inst + off[j] + m, j);
+            off[j + 1] = off[j] + m;
+        }
+        TileList tl;
+        tl.ntiles = nrun[q];
+        tl.d_off = reinterpret_cast<int64_t *>(A.arena + used);
+        tl.d_inst = reinterpret_cast<int *>(A.arena + used + bo);
+        tl.d_base = keys[q].second->d_off;
+        A.lists.emplace(*keys[q].first, std::move(tl));
+        used += bo + a256(sizeof(int) * nrun[q]);
+    }
+    A.bot.assign(c->Lmax, nullptr);
+    A.bot_n.assign(c->Lmax, 0);
+    for (int l = 0; l < c->Lmax; ++l) {
+        if (bcount[l] == 0) continue;
+        int *b = reinterpret_cast<int *>(h + used);
+        int n = 0;
+        for (int j = 0; j < B; ++j)
+            if (c->lb[j] == l && A.is_run(j)) b[n++] = j;
+        A.bot[l] = reinterpret_cast<int *>(A.arena + used);
+        A.bot_n[l] = n;
+        used += a256(sizeof(int) * n);
+    }
+    if (used > 0) {
+        HIPCHK(c, hipMemcpyAsync(A.arena, h, used, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipEventRecord(A.ev[A.which], s));
+    }
+    A.tiles = tiles;
+    A.on = true;
     return TMG_OK;
 }
 
@@ -352,6 +509,7 @@ LegArgsT<T> leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl
     a.cslab_off = level + 1 < c->Lmax ? c->slab_off_d[level + 1] : nullptr;
     a.tile_off = tl->d_off;
     a.tile_inst = tl->d_inst;
+    a.tile_base = tl->d_base;
     a.n0 = c->N[0] >> level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
@@ -378,7 +536,10 @@ template <typename T>
 int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x_out,
                    hipStream_t s)
 {
-    if (c->bot_n[level] == 0) return TMG_OK;
+    const int *inst;
+    int ninst;
+    bottom_list(c, level, &inst, &ninst);
+    if (ninst == 0) return TMG_OK;
     BottomArgsT<T> a{};
     a.f = level == 0 ? reinterpret_cast<const T *>(io.f) : store<T>(c).f[level];
     a.u0 = level == 0 ? fold_of(io) : nullptr;
@@ -387,7 +548,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.slab_off = c->slab_off_d[level];
     a.tab = io.trans ? c->tab_adj : c->tab_fwd;
     a.R = io.trans ? c->R_adj : c->R_fwd;
-    a.inst = c->bot_d[level];
+    a.inst = inst;
     a.nlev = c->nlev_d;
     a.st = io.use_state ? c->st : nullptr;
     a.ctl = c->ctl;
@@ -398,7 +559,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.nu1 = c->opt.nu1;
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
-    HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, c->bot_n[level], s));
+    HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, ninst, s));
     return TMG_OK;
 }
 
@@ -646,6 +807,7 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.cslab_off = c->slab_off_d[1];
         a.tile_off = t->d_off;
         a.tile_inst = t->d_inst;
+        a.tile_base = t->d_base;
         a.st = io.use_state ? c->st : nullptr;
         a.n0 = c->N[0];
         a.batch = c->batch;
@@ -738,6 +900,11 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
 {
     int rc;
     const bool first = io.kind == kFirst;
+    struct InCycle {
+        bool &f;
+        ~InCycle() { f = false; }
+    } in_cycle{c->in_cycle};
+    c->in_cycle = io.kind > kFirst;
     c->cur.assign(c->Lmax + 1, 0);
     // instances that fit the bottom kernel entirely: the cycle is one launch
     // (FP64 in both precision modes)
@@ -924,6 +1091,10 @@ void free_all(tmg_ctx *c)
     if (c->grad_host) (void)hipHostFree(c->grad_host);
     if (c->mirror) (void)hipHostFree(c->mirror);
     if (c->drain_ev) (void)hipEventDestroy(c->drain_ev);
+    for (int k = 0; k < 2; ++k) {
+        if (c->act.stage[k]) (void)hipHostFree(c->act.stage[k]);
+        if (c->act.ev[k]) (void)hipEventDestroy(c->act.ev[k]);
+    }
     if (c->cap) (void)hipStreamDestroy(c->cap);
 }
 
@@ -947,12 +1118,34 @@ bool read_summary(const HostHead *h, HostSum *out, long long *ver)
     return b == e;
 }
 
+// The run bits of the summary with version ver (false: the device has
+// written a newer one meanwhile).
+bool read_run_bits(const HostHead *h, int words, long long ver, std::vector<unsigned> *out)
+{
+    const long long e = __atomic_load_n(&h->end, __ATOMIC_ACQUIRE);
+    const unsigned *b = reinterpret_cast<const unsigned *>(reinterpret_cast<const HostSum *>(h + 1) + 1);
+    out->resize(words);
+    for (int w = 0; w < words; ++w) (*out)[w] = __atomic_load_n(&b[w], __ATOMIC_RELAXED);
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    const long long bg = __atomic_load_n(&h->begin, __ATOMIC_RELAXED);
+    return e == ver && bg == ver;
+}
+
 int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool trans, double rtol,
               int max_cycles, int *cycles, double *relres, hipStream_t s)
 {
+    // active-set lists last for the cycles of this solve only
+    struct ActiveOff {
+        ActiveSet &A;
+        ~ActiveOff() { A.on = false; }
+    } act_off{c->act};
+    c->act.on = false;
     TileList *tl;
     int rc = get_tiles(c, 0, kAll, tile_slabs(c->P), s, &tl);
     if (rc) return rc;
+    const int words = c->act.enabled && c->batch > 1 ? run_words(c->batch) : 0;
+    c->act.tiles = tl->ntiles;
+    std::vector<unsigned> bits;
     // cycles the previous solve left queued (on its stream) stay no-ops only
     // while the state they read says finished: this solve resets that state,
     // so its stream waits for them first (nothing to wait for on one stream)
@@ -998,7 +1191,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // enqueues a cycle faster than the GPU runs it.
     auto launch = [&](int n) -> int {
         while (n > 0) {
-            if (c->direct && launched > 0) {
+            if ((c->direct || c->act.on) && launched > 0) {
                 CycleIO io{f, u0, u, trans, true, (launched % 2 == 1) ? kEven : kOdd};
                 if ((rc = enqueue_cycle(c, io, s))) return rc;
                 launched += 1;
@@ -1055,7 +1248,22 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
                 }
             }
             if (sum.running == 0) break;
-            const int want = std::min(std::max(sum.want, 1), max_cycles);
+            int want = std::min(std::max(sum.want, 1), max_cycles);
+            if (words > 0) {
+                // few cycles ahead, so that active-set lists apply soon; a
+                // new generation once the running share of level-0 tiles
+                // dropped far enough
+                want = std::min(want, std::max(sum.cycles + kActiveAhead, 1));
+                if (read_run_bits(c->mirror, words, ver, &bits)) {
+                    const std::vector<int64_t> &fo = tl->h_off;
+                    int64_t r = 0;
+                    for (int j = 0; j < c->batch; ++j)
+                        if ((bits[j >> 5] >> (j & 31)) & 1u) r += fo[j + 1] - fo[j];
+                    if (r > 0 && (double)r <= kActiveShare * (double)c->act.tiles &&
+                        (rc = act_begin(c, bits, r, s)))
+                        return rc;
+                }
+            }
             if (want > launched && (rc = launch(want - launched))) return rc;
             since = std::chrono::steady_clock::now();
             continue;
@@ -1157,6 +1365,7 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
         dfree(c, kv.second.d_inst);
     }
     c->tiles.clear();
+    c->cycle_keys.clear();
     for (int *p : c->bot_d) dfree(c, p);
     const int Lm = c->Lmax, batch = c->batch, P = c->P;
     c->lb = lbv;
@@ -1372,13 +1581,15 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     // partial sums: one slot per level-0 tile at the smallest tile size in use
     c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
     if ((rc = dalloc(c, &c->partial, c->partial_cap))) return fail(rc);
+    const size_t mirror_bytes =
+        sizeof(HostHead) + sizeof(HostSum) + sizeof(unsigned) * run_words(batch);
     if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
         hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess ||
-        hipHostMalloc((void **)&c->mirror, sizeof(HostHead) + sizeof(HostSum),
+        hipHostMalloc((void **)&c->mirror, mirror_bytes,
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(TMG_ERR_OOM);
-    std::memset(c->mirror, 0, sizeof(HostHead) + sizeof(HostSum));
+    std::memset(c->mirror, 0, mirror_bytes);
     if ((rc = dalloc(c, &c->pubn_d, 1)) ||
         hipMemsetAsync(c->pubn_d, 0, sizeof(unsigned), s) != hipSuccess)
         return fail(rc ? rc : TMG_ERR_HIP);
@@ -1562,6 +1773,13 @@ int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int span, int 
     const int rc = apply_plan(c, bottom_cap, pairs != 0, span, span_after, (hipStream_t)stream);
     if (rc) return rc;
     c->direct = direct != 0;
+    return TMG_OK;
+}
+
+int tmg_set_active_set(tmg_handle c, int on)
+{
+    if (!c) return TMG_ERR_INVALID;
+    c->act.enabled = on != 0;
     return TMG_OK;
 }
 

@@ -81,12 +81,16 @@ struct HostHead {
 struct HostSum {
     int running;   // batch: instances not finished
     int want;      // batch: cycles to have queued
-    int cycles;    // single instance: its state
+    int cycles;    // single instance: its state; batch: the most cycles run
     int done;
     double r0sq;
     double rsq;
     double prev_rsq;
 };
+// Batches of at most kRunBits instances: after the HostSum, one bit per
+// instance (bit j % 32 of word j / 32) that is set while it runs.
+constexpr int kRunBits = 1 << 16;
+__host__ __device__ inline int run_words(int batch) { return batch <= kRunBits ? (batch + 31) / 32 : 0; }
 
 // Arguments of the streaming "leg" kernel (one level, all participating
 // instances).  Logical slab m of an instance is physical slab N-1-m for the
@@ -116,6 +120,10 @@ struct LegArgsT {
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
     const int *tile_inst;    // [ntiles] instance of each tile (batch > 1)
+    // A list of the running instances' tiles only (tile_off then has empty
+    // ranges for the others) names the full list's offsets here: halo slots
+    // stay those of the full list.  Null: the slot of a tile is its index.
+    const int64_t *tile_base;
     const InstState *st;     // per-instance early exit when st[j].done (may be null)
     // Two-level launches (levels l and l+1 of a V-cycle's first visits).
     // Up: with e2 != null the correction of level l+1 is not read from e but
@@ -182,6 +190,7 @@ struct MixArgs {
     const int64_t *cslab_off;
     const int64_t *tile_off;
     const int *tile_inst;    // as in LegArgsT
+    const int64_t *tile_base;// as in LegArgsT
     const InstState *st;
     // two-level pass (as in LegArgsT): level 1's inner up leg computed in the
     // tile from f1 and the level-2 inner correction e2 instead of reading e,

@@ -651,19 +651,22 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
     }
 }
 
-// Instance, tile and sizes of the work-group's tile.
+// Instance, tile and sizes of the work-group's tile, and its slot in the
+// level-0 halo buffers.
 struct TileRef {
     int j;
     int64_t t, off, N, coff, Nc, c2off, Nc2;   // levels l, l+1, l+2 of instance j
+    int64_t h;
 };
 
 template <typename A>
 __device__ __forceinline__ TileRef tile_ref(const A &a)
 {
-    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2, 0, a.n0 / 4};
+    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2, 0, a.n0 / 4, (int64_t)blockIdx.x};
     if (a.batch > 1) {
         r.j = a.tile_inst ? a.tile_inst[r.t] : find_instance(a.tile_off, a.batch, r.t);
         r.t = (int64_t)blockIdx.x - a.tile_off[r.j];
+        if (a.tile_base) r.h = a.tile_base[r.j] + r.t;
         r.off = a.slab_off[r.j];
         r.N = a.slab_off[r.j + 1] - r.off;
         if (a.cslab_off) {
@@ -689,8 +692,7 @@ __device__ __forceinline__ void load_iterate(T (&u)[S][P], const T *u_in, const 
             // left halo: the previous tile's last output slabs of the last
             // pass (the first tile of an instance starts at slab 0: zeros)
             if (tr.t > 0) {
-                const T *hb =
-                    halo_in + ((int64_t)blockIdx.x - 1) * (int64_t)halo * P + (int64_t)li0 * P;
+                const T *hb = halo_in + (tr.h - 1) * (int64_t)halo * P + (int64_t)li0 * P;
 #pragma unroll
                 for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -713,11 +715,12 @@ __device__ __forceinline__ void load_iterate(T (&u)[S][P], const T *u_in, const 
 }
 
 template <int P, int S, typename T>
-__device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int li0, int halo)
+__device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], const TileRef &tr,
+                                           int li0, int halo)
 {
     constexpr int TS = kLegThreads * S;
     if (halo_out && li0 >= TS - halo) {
-        T *hb = halo_out + (int64_t)blockIdx.x * (int64_t)halo * P + (int64_t)(li0 - (TS - halo)) * P;
+        T *hb = halo_out + tr.h * (int64_t)halo * P + (int64_t)(li0 - (TS - halo)) * P;
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -896,7 +899,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     if (!kDown && (a.e || a.e2)) prolong_add<P, S, T>(u, e, a.R, m0);
     if constexpr (!kDown) sweeps<P, S, kLegWaves, T>(u, g, op, a.post, xchg, phase);
     if (!kDown && a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
-    if constexpr (kAny) store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
+    if constexpr (kAny) store_halo<P, S, T>(a.halo_out, u, tr, li0, a.halo);
     double r[S][P];
     if (kAny && a.partial) {
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
@@ -1271,7 +1274,7 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
 #pragma unroll
             for (int k = 0; k < P; ++k) u[s][k] += (double)ei[s][k];
         if (a.u_out) store_chunk<P, S, BW, double>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
-        store_halo<P, S, double>(a.halo_out, u, li0, a.halo);
+        store_halo<P, S, double>(a.halo_out, u, tr, li0, a.halo);
     }
     residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
     if (a.partial)
@@ -1807,9 +1810,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
     publish(mirror, s, ctl);
 }
 
-// Host copy for a batch (see HostHead): the number of running instances and
-// the most cycles any of them wants queued, reduced over the batch by one
-// work-group.
+// Host copy for a batch (see HostHead): the number of running instances,
+// the most cycles any of them wants queued and the most cycles run, reduced
+// over the batch by one work-group, and (batches of at most kRunBits) which
+// instances run, as bits.
 __global__ __launch_bounds__(kFinThreads) void k_publish(const InstState *__restrict__ st,
                                                          int batch,
                                                          const Control *__restrict__ ctl,
@@ -1817,32 +1821,68 @@ __global__ __launch_bounds__(kFinThreads) void k_publish(const InstState *__rest
                                                          unsigned *__restrict__ count)
 {
     constexpr int NW = kFinThreads / 64;
-    __shared__ int rn[NW], rw[NW];
-    int nrun = 0, want = 0;
-    for (int j = threadIdx.x; j < batch; j += kFinThreads) {
-        const InstState s = st[j];
-        if (running(s, ctl)) {
-            ++nrun;
-            want = max(want, want_cycles(s, ctl));
+    __shared__ int rn[NW], rw[NW], rc[NW];
+    __shared__ unsigned bits[kRunBits / 32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwords = run_words(batch);
+    int nrun = 0, want = 0, cyc = 0;
+    // every lane of a wave takes part in each round (ballot)
+    for (int j0 = 0; j0 < batch; j0 += kFinThreads) {
+        const int j = j0 + threadIdx.x;
+        bool run = false;
+        if (j < batch) {
+            const InstState s = st[j];
+            cyc = max(cyc, s.cycles);
+            run = running(s, ctl);
+            if (run) {
+                ++nrun;
+                want = max(want, want_cycles(s, ctl));
+            }
         }
+        const unsigned long long m = __ballot(run);
+        const int w = (j0 + wave * 64) / 32;
+        if (lane == 0 && w < nwords) bits[w] = (unsigned)m;
+        if (lane == 1 && w + 1 < nwords) bits[w + 1] = (unsigned)(m >> 32);
     }
     for (int off = 32; off > 0; off >>= 1) {
         nrun += __shfl_down(nrun, off, 64);
         want = max(want, __shfl_down(want, off, 64));
+        cyc = max(cyc, __shfl_down(cyc, off, 64));
     }
-    if ((threadIdx.x & 63) == 0) {
-        rn[threadIdx.x >> 6] = nrun;
-        rw[threadIdx.x >> 6] = want;
+    if (lane == 0) {
+        rn[wave] = nrun;
+        rw[wave] = want;
+        rc[wave] = cyc;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (wave != 0) return;
     for (int w = 1; w < NW; ++w) {
         nrun += rn[w];
         want = max(want, rw[w]);
+        cyc = max(cyc, rc[w]);
     }
-    const unsigned n = *count + 1;
-    *count = n;
-    put_summary(h, ((long long)ctl->epoch << 32) | n, nrun, want, nullptr);
+    // the first wave writes the copy: begin, the bits (all lanes) and the
+    // counts, then end after a release fence that orders every lane's stores
+    unsigned n = 0;
+    if (lane == 0) {
+        n = *count + 1;
+        *count = n;
+    }
+    n = __shfl(n, 0, 64);
+    const long long v = ((long long)ctl->epoch << 32) | n;
+    HostSum *m = reinterpret_cast<HostSum *>(h + 1);
+    unsigned *hb = reinterpret_cast<unsigned *>(m + 1);
+    if (lane == 0) __hip_atomic_store(&h->begin, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    for (int w = lane; w < nwords; w += 64)
+        __hip_atomic_store(&hb[w], bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (lane == 0) {
+        __hip_atomic_store(&m->running, nrun, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&m->want, want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&m->cycles, cyc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0) __hip_atomic_store(&h->end, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // dlambda_j = -sum_n z_n^T M_tau u_n (M_tau = tau diag(1/(2k+1))),

@@ -145,3 +145,78 @@ def test_solves_on_two_streams_in_turn():
         assert r1.cycles[0] == k1 and r2.cycles[0] == k2
         assert relerr(host(r1.u), ref1) <= 1e-12
         assert relerr(host(r2.u), ref2) <= 1e-12
+
+
+def _uneven_batch(p, seed):
+    """Most tiles belong to instances done after two or three cycles, the
+    rest to ones that need about twelve (shuffled, so that the running
+    instances of the later cycles are scattered over the batch)."""
+    Ns = [4096] * 28 + [4096] * 6 + [1024, 2048, 1024, 2048, 1024, 2048]
+    lams = [2e5] * 28 + [2e4] * 6 + [0.5, 10.0, 0.5, 10.0, 1.0, 3.0]
+    Ts = [1.0] * 34 + [1.0, 1.0, 1.0, 1.0, 40.0, 5.0]
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(len(Ns))
+    Ns, lams, Ts = ([x[i] for i in perm] for x in (Ns, lams, Ts))
+    u0 = rng.uniform(-1, 1, len(Ns))
+    fs = [rng.standard_normal(n * (p + 1)) for n in Ns]
+    return Ns, lams, Ts, u0, fs
+
+
+@pytest.mark.parametrize("precision,direct", [(0, False), (0, True), (1, False)])
+def test_active_set_is_bitwise_the_full_lists(precision, direct):
+    """Later cycles on the running instances' tiles only give bitwise the
+    iterate, cycle counts and residuals of cycles on every tile (and the
+    oracle's solve)."""
+    p = 1
+    Ns, lams, Ts, u0, fs = _uneven_batch(p, 35)
+    s = B().Solver(Ns, Ts, lams, p=p, precision=precision)
+    s.set_schedule(256, pairs=True, direct=direct)
+    f, d0 = dev(np.concatenate(fs)), dev(u0)
+    res = {}
+    for on in (True, False, True):
+        s.set_active_set(on)
+        u = torch.full_like(f, 7.0)
+        r = s.solve(f, d0, u=u, rtol=1e-10)
+        assert r.status == 0
+        res.setdefault(on, []).append((host(u), list(r.cycles), list(r.relres)))
+    (Ua, ca, ra), (Ub, cb, rb) = res[True]
+    (Uo, co, ro), = res[False]
+    assert np.array_equal(Ua, Uo) and np.array_equal(Ub, Uo)
+    assert ca == co and cb == co and ra == ro and rb == ro
+    assert max(co) >= 10 and min(co) <= 3
+    for j in range(len(Ns)):
+        if co[j] < 10 and j % 5:
+            continue
+        seg = slice(s.offsets[j], s.offsets[j + 1])
+        if precision == 0:
+            uo, k, _, _ = core.solve(p, Ts[j], lams[j], u0[j], fs[j], rtol=1e-10)
+            assert co[j] == k, j
+            assert relerr(Uo[seg], uo) <= 1e-12
+        else:
+            _, km, _, _ = core.solve_mixed(p, Ts[j], lams[j], u0[j], fs[j], rtol=1e-10)
+            assert abs(co[j] - km) <= 1, j
+            ud = core.direct_solve(p, Ts[j], lams[j], u0[j], fs[j])
+            assert relerr(Uo[seg], ud) <= 1e-8
+
+
+def test_active_set_adjoint_is_bitwise_the_full_lists():
+    """The same for the adjoint solve (backward in time)."""
+    p = 2
+    Ns, lams, Ts, u0, fs = _uneven_batch(p, 36)
+    s = B().Solver(Ns, Ts, lams, p=p)
+    f, d0 = dev(np.concatenate(fs)), dev(u0)
+    u = torch.empty_like(f)
+    r = s.solve(f, d0, u=u, rtol=1e-10)
+    assert r.status == 0
+    g = dev(np.random.default_rng(37).standard_normal(f.numel()))
+    out = {}
+    for on in (True, False):
+        s.set_active_set(on)
+        z = torch.full_like(f, -2.0)
+        z_, dl, du, cyc, rr, st = s.adjoint_solve(g, u=u, z=z, rtol=1e-10)
+        assert st == 0
+        out[on] = (host(z), list(dl), list(du), list(cyc), list(rr))
+    zt, zf = out[True], out[False]
+    assert np.array_equal(zt[0], zf[0])
+    assert zt[1:] == zf[1:]
+    assert max(zf[3]) > 2 * min(zf[3])
