@@ -59,7 +59,6 @@ struct TileList {
     int64_t *d_off = nullptr;  // [batch+1]
     int *d_inst = nullptr;     // [ntiles] instance of each tile (batch > 1): one load in
                                // place of a binary search over d_off per work-group
-    const int64_t *d_base = nullptr;  // active-set lists: the full list's d_off
     std::vector<int64_t> h_off;       // full lists: d_off on the host
 };
 
@@ -68,7 +67,11 @@ struct TileList {
 // dependent loads each) dominate a cycle.  The later cycles of a solve then
 // run on lists of the running instances' tiles only, built on the host from
 // the run bits each cycle's summary carries, whenever the running share of
-// level-0 tiles has dropped to kActiveShare of the lists in use.  The lists
+// level-0 tiles has dropped to kActiveShare of the lists in use.  A level-0
+// pass reads the left halo of each tile from the slot the pass before
+// stored under the tile's number in its list; the first cycle on a new
+// generation re-fills those slots from the iterate under the new numbers
+// (the values are the iterate's there, so the results do not change).  The lists
 // of one generation live in a device arena, copied there in stream order
 // from a pinned staging buffer (two, used in turn by generations, so that
 // the host never writes one a queued copy still reads).  They cover the
@@ -79,6 +82,7 @@ constexpr int kActiveAhead = 2;   // cycles queued past the last summary
 struct ActiveSet {
     bool enabled = true;
     bool on = false;                   // the cycles being queued use `lists`
+    bool seed = false;                 // the next cycle re-fills the halo slots first
     std::vector<unsigned> run;         // run bits the lists are built for
     int64_t tiles = 0;                 // level-0 tiles of the lists in use
     std::map<std::tuple<int, int, int>, TileList> lists;
@@ -443,7 +447,6 @@ int act_begin(tmg_ctx *c, std::vector<unsigned> &run, int64_t tiles, hipStream_t
         tl.ntiles = nrun[q];
         tl.d_off = reinterpret_cast<int64_t *>(A.arena + used);
         tl.d_inst = reinterpret_cast<int *>(A.arena + used + bo);
-        tl.d_base = keys[q].second->d_off;
         A.lists.emplace(*keys[q].first, std::move(tl));
         used += bo + a256(sizeof(int) * nrun[q]);
     }
@@ -465,6 +468,7 @@ int act_begin(tmg_ctx *c, std::vector<unsigned> &run, int64_t tiles, hipStream_t
     }
     A.tiles = tiles;
     A.on = true;
+    A.seed = true;
     return TMG_OK;
 }
 
@@ -509,7 +513,6 @@ LegArgsT<T> leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl
     a.cslab_off = level + 1 < c->Lmax ? c->slab_off_d[level + 1] : nullptr;
     a.tile_off = tl->d_off;
     a.tile_inst = tl->d_inst;
-    a.tile_base = tl->d_base;
     a.n0 = c->N[0] >> level;
     a.batch = c->batch;
     a.tab_stride = c->tab_stride;
@@ -791,6 +794,28 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
 
 // Level-0 part of a cycle of the FP32-inner defect correction (streaming
 // instances): see k_mix.
+// The level-0 halo slots the passes of this cycle read, re-filled from the
+// iterate for the tile lists in use (first cycle on an active-set
+// generation).
+int seed_halos(tmg_ctx *c, const CycleIO &io, hipStream_t s)
+{
+    const bool fuse = c->mixed ? c->fuse_mix() && c->deep_n[1] > 0
+                               : c->fuse_up1() && c->deep_n[1] > 0;
+    for (int pass = fuse ? 0 : 1; pass < 2; ++pass) {
+        const bool two = pass == 0;
+        const int H = c->mixed ? (two ? c->H_mix2() : c->H_mix())
+                               : (two ? c->H_fused2() : c->H_fused());
+        TileList *tl;
+        int rc = get_tiles(c, 0, fuse ? (two ? kDeepNext : kDeepLast) : kDeep, c->TO(H), s, &tl);
+        if (rc) return rc;
+        const int64_t hoff = fuse && !two ? c->hb_last_off : 0;
+        double *hb = (io.kind == kOdd ? c->hb[1] : c->hb[0]) + hoff;
+        HIPCHK(c, launch_seed(c->P, io.trans, io.u, hb, tl->d_off, tl->d_inst, c->slab_off_d[0],
+                              c->batch, c->N[0], c->TO(H), H, tl->ntiles, s));
+    }
+    return TMG_OK;
+}
+
 int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
 {
     int rc;
@@ -807,7 +832,6 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.cslab_off = c->slab_off_d[1];
         a.tile_off = t->d_off;
         a.tile_inst = t->d_inst;
-        a.tile_base = t->d_base;
         a.st = io.use_state ? c->st : nullptr;
         a.n0 = c->N[0];
         a.batch = c->batch;
@@ -905,6 +929,10 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         ~InCycle() { f = false; }
     } in_cycle{c->in_cycle};
     c->in_cycle = io.kind > kFirst;
+    if (c->act.on && c->act.seed && io.kind > kFirst && c->deep_n[0] > 0) {
+        c->act.seed = false;
+        if ((rc = seed_halos(c, io, s))) return rc;
+    }
     c->cur.assign(c->Lmax + 1, 0);
     // instances that fit the bottom kernel entirely: the cycle is one launch
     // (FP64 in both precision modes)

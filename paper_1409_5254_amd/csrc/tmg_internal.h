@@ -120,10 +120,6 @@ struct LegArgsT {
     const int64_t *cslab_off;// [batch+1] slab offsets of the next level
     const int64_t *tile_off; // [batch+1] tile offsets of this launch
     const int *tile_inst;    // [ntiles] instance of each tile (batch > 1)
-    // A list of the running instances' tiles only (tile_off then has empty
-    // ranges for the others) names the full list's offsets here: halo slots
-    // stay those of the full list.  Null: the slot of a tile is its index.
-    const int64_t *tile_base;
     const InstState *st;     // per-instance early exit when st[j].done (may be null)
     // Two-level launches (levels l and l+1 of a V-cycle's first visits).
     // Up: with e2 != null the correction of level l+1 is not read from e but
@@ -190,7 +186,6 @@ struct MixArgs {
     const int64_t *cslab_off;
     const int64_t *tile_off;
     const int *tile_inst;    // as in LegArgsT
-    const int64_t *tile_base;// as in LegArgsT
     const InstState *st;
     // two-level pass (as in LegArgsT): level 1's inner up leg computed in the
     // tile from f1 and the level-2 inner correction e2 instead of reading e,
@@ -248,6 +243,11 @@ hipError_t launch_span(int P, bool backward, const SpanArgsT<T> &a, int64_t ntil
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
 template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s);
+// Level-0 halo slots of a tile list (tile_out output slabs and `halo` halo
+// slabs per tile) from the iterate u, as the level-0 pass stores them.
+hipError_t launch_seed(int P, bool backward, const double *u, double *hb, const int64_t *tile_off,
+                       const int *tile_inst, const int64_t *slab_off, int batch, int64_t n0,
+                       int tile_out, int halo, int64_t ntiles, hipStream_t s);
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
                          const int *tile_inst, int batch, double *partial, int64_t ntiles,

@@ -651,22 +651,19 @@ __device__ __forceinline__ void restrict_store(const double (&r)[S][P], const T 
     }
 }
 
-// Instance, tile and sizes of the work-group's tile, and its slot in the
-// level-0 halo buffers.
+// Instance, tile and sizes of the work-group's tile.
 struct TileRef {
     int j;
     int64_t t, off, N, coff, Nc, c2off, Nc2;   // levels l, l+1, l+2 of instance j
-    int64_t h;
 };
 
 template <typename A>
 __device__ __forceinline__ TileRef tile_ref(const A &a)
 {
-    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2, 0, a.n0 / 4, (int64_t)blockIdx.x};
+    TileRef r{0, (int64_t)blockIdx.x, 0, a.n0, 0, a.n0 / 2, 0, a.n0 / 4};
     if (a.batch > 1) {
         r.j = a.tile_inst ? a.tile_inst[r.t] : find_instance(a.tile_off, a.batch, r.t);
         r.t = (int64_t)blockIdx.x - a.tile_off[r.j];
-        if (a.tile_base) r.h = a.tile_base[r.j] + r.t;
         r.off = a.slab_off[r.j];
         r.N = a.slab_off[r.j + 1] - r.off;
         if (a.cslab_off) {
@@ -692,7 +689,8 @@ __device__ __forceinline__ void load_iterate(T (&u)[S][P], const T *u_in, const 
             // left halo: the previous tile's last output slabs of the last
             // pass (the first tile of an instance starts at slab 0: zeros)
             if (tr.t > 0) {
-                const T *hb = halo_in + (tr.h - 1) * (int64_t)halo * P + (int64_t)li0 * P;
+                const T *hb =
+                    halo_in + ((int64_t)blockIdx.x - 1) * (int64_t)halo * P + (int64_t)li0 * P;
 #pragma unroll
                 for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -715,12 +713,11 @@ __device__ __forceinline__ void load_iterate(T (&u)[S][P], const T *u_in, const 
 }
 
 template <int P, int S, typename T>
-__device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], const TileRef &tr,
-                                           int li0, int halo)
+__device__ __forceinline__ void store_halo(T *halo_out, const T (&u)[S][P], int li0, int halo)
 {
     constexpr int TS = kLegThreads * S;
     if (halo_out && li0 >= TS - halo) {
-        T *hb = halo_out + tr.h * (int64_t)halo * P + (int64_t)(li0 - (TS - halo)) * P;
+        T *hb = halo_out + (int64_t)blockIdx.x * (int64_t)halo * P + (int64_t)(li0 - (TS - halo)) * P;
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -899,7 +896,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     if (!kDown && (a.e || a.e2)) prolong_add<P, S, T>(u, e, a.R, m0);
     if constexpr (!kDown) sweeps<P, S, kLegWaves, T>(u, g, op, a.post, xchg, phase);
     if (!kDown && a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
-    if constexpr (kAny) store_halo<P, S, T>(a.halo_out, u, tr, li0, a.halo);
+    if constexpr (kAny) store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
     double r[S][P];
     if (kAny && a.partial) {
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
@@ -1274,7 +1271,7 @@ __global__ __launch_bounds__(kLegThreads) void k_mix(MixArgs a)
 #pragma unroll
             for (int k = 0; k < P; ++k) u[s][k] += (double)ei[s][k];
         if (a.u_out) store_chunk<P, S, BW, double>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
-        store_halo<P, S, double>(a.halo_out, u, tr, li0, a.halo);
+        store_halo<P, S, double>(a.halo_out, u, li0, a.halo);
     }
     residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
     if (a.partial)
@@ -1885,6 +1882,46 @@ __global__ __launch_bounds__(kFinThreads) void k_publish(const InstState *__rest
     if (lane == 0) __hip_atomic_store(&h->end, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Left halos for the in-place level-0 pass, taken from the iterate: slot g
+// of a tile list holds the last `halo` output slabs of tile g, which is
+// what the pass before wrote there when it stored them to u.  Used where a
+// batch's tile list changes between two cycles (the slots are numbered by
+// the list).  One thread per slab of a slot; slabs past the end of an
+// instance (never read) are zero.
+template <int P, bool BW>
+__global__ __launch_bounds__(kThreads) void k_seed(const double *__restrict__ u,
+                                                   double *__restrict__ hb,
+                                                   const int64_t *__restrict__ tile_off,
+                                                   const int *__restrict__ tile_inst,
+                                                   const int64_t *__restrict__ slab_off, int batch,
+                                                   int64_t n0, int tile_out, int halo,
+                                                   int64_t nslabs)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= nslabs) return;
+    const int64_t g = i / halo;
+    const int q = (int)(i - g * halo);
+    int j = 0;
+    int64_t t = g, off = 0, N = n0;
+    if (batch > 1) {
+        j = tile_inst[g];
+        t = g - tile_off[j];
+        off = slab_off[j];
+        N = slab_off[j + 1] - off;
+    }
+    const int64_t m = (t + 1) * tile_out - halo + q;   // logical slab
+    double v[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = 0.0;
+    if (m >= 0 && m < N) {
+        const double *src = u + (off + (BW ? N - 1 - m : m)) * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = src[k];
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) hb[i * P + k] = v[k];
+}
+
 // dlambda_j = -sum_n z_n^T M_tau u_n (M_tau = tau diag(1/(2k+1))),
 // du0_j = v^T z_1 (v[k] = (-1)^k): one work-group per instance.
 template <int P>
@@ -1999,6 +2036,24 @@ hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ni
 }
 template hipError_t launch_bottom<double>(int, bool, const BottomArgsT<double> &, int, hipStream_t);
 template hipError_t launch_bottom<float>(int, bool, const BottomArgsT<float> &, int, hipStream_t);
+
+hipError_t launch_seed(int P, bool backward, const double *u, double *hb, const int64_t *tile_off,
+                       const int *tile_inst, const int64_t *slab_off, int batch, int64_t n0,
+                       int tile_out, int halo, int64_t ntiles, hipStream_t s)
+{
+    const int64_t n = ntiles * halo;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + kThreads - 1) / kThreads)), block(kThreads);
+    TMG_DISPATCH_P(P, {
+        if (backward)
+            hipLaunchKernelGGL((k_seed<PP, true>), grid, block, 0, s, u, hb, tile_off, tile_inst,
+                               slab_off, batch, n0, tile_out, halo, n);
+        else
+            hipLaunchKernelGGL((k_seed<PP, false>), grid, block, 0, s, u, hb, tile_off, tile_inst,
+                               slab_off, batch, n0, tile_out, halo, n);
+    })
+    return hipGetLastError();
+}
 
 hipError_t launch_norm_f(int P, const double *f, const double *u0, const double *tab,
                          int tab_stride, const int64_t *slab_off, const int64_t *tile_off,
