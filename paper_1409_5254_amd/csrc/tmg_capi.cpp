@@ -51,7 +51,8 @@ namespace {
 // pair, kSingle<g> a last level left without a partner.
 enum TileKind {
     kDeep = 0, kAll = 1, kHasNext = 2, kDeepNext = 3, kDeepLast = 4, kHasNext2 = 5,
-    kPair1 = 6, kSingle1 = 7, kPair2 = 8, kSingle2 = 9
+    kPair1 = 6, kSingle1 = 7, kPair2 = 8, kSingle2 = 9,
+    kWhole = 10   // level 0 of the instances the bottom kernel holds whole
 };
 
 struct TileList {
@@ -297,6 +298,7 @@ void dfree(tmg_ctx *c, void *p)
 bool participates(const tmg_ctx *c, int j, int level, int kind)
 {
     if (level >= c->L[j]) return false;
+    if (kind == kWhole) return level == 0 && c->lb[j] == 0;
     if (kind == kDeep) return level < c->lb[j];       // streaming kernels in the cycle
     if (kind == kHasNext) return level + 1 < c->L[j]; // level-wise entry points
     if (kind == kHasNext2) return level + 2 < c->L[j];
@@ -312,8 +314,7 @@ bool participates(const tmg_ctx *c, int j, int level, int kind)
 
 // Tile offsets (prefix sums of ceil(N_jl / tile_out) over participating
 // instances) for one (level, kind, tile_out), cached on the device.
-int get_active_tiles(tmg_ctx *c, const TileList &full, const std::tuple<int, int, int> &key,
-                     hipStream_t s, TileList **out);
+TileList *active_tiles(tmg_ctx *c, TileList &full, const std::tuple<int, int, int> &key);
 
 int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, TileList **out)
 {
@@ -321,8 +322,7 @@ int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, Tile
     if (c->in_cycle) c->cycle_keys.insert(key);
     auto it = c->tiles.find(key);
     if (it != c->tiles.end()) {
-        if (c->act.on) return get_active_tiles(c, it->second, key, s, out);
-        *out = &it->second;
+        *out = c->act.on ? active_tiles(c, it->second, key) : &it->second;
         return TMG_OK;
     }
     std::vector<int64_t> off(c->batch + 1, 0);
@@ -352,8 +352,7 @@ int get_tiles(tmg_ctx *c, int level, int kind, int tile_out, hipStream_t s, Tile
     HIPCHK(c, hipStreamSynchronize(s));
     tl.h_off = std::move(off);
     auto res = c->tiles.emplace(key, std::move(tl));
-    if (c->act.on) return get_active_tiles(c, res.first->second, key, s, out);
-    *out = &res.first->second;
+    *out = c->act.on ? active_tiles(c, res.first->second, key) : &res.first->second;
     return TMG_OK;
 }
 
@@ -361,12 +360,10 @@ size_t a256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // The active-set form of a full tile list (the full list itself if the
 // generation has none for it: its finished instances leave at once).
-int get_active_tiles(tmg_ctx *c, const TileList &full, const std::tuple<int, int, int> &key,
-                     hipStream_t, TileList **out)
+TileList *active_tiles(tmg_ctx *c, TileList &full, const std::tuple<int, int, int> &key)
 {
     auto it = c->act.lists.find(key);
-    *out = it != c->act.lists.end() ? &it->second : const_cast<TileList *>(&full);
-    return TMG_OK;
+    return it != c->act.lists.end() ? &it->second : &full;
 }
 
 // The bottom kernel's instance list of a level (active-set form while one
@@ -533,6 +530,23 @@ struct CycleIO {
 
 const double *fold_of(const CycleIO &io) { return io.trans ? nullptr : io.u0; }
 
+// A solve's first level-0 down pass also yields the initial residual's norm
+// (r_0 = f with u0 folded, u = 0): each launch leaves its tiles' partials,
+// and a finalize launch right after it sets its instances' initial state.
+// The first finalize of a solve also installs the solve's control block.
+struct R0 {
+    bool ctl_pending = true;
+};
+
+int finalize_r0(tmg_ctx *c, R0 *r0, const TileList *tl, hipStream_t s)
+{
+    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 1, s,
+                              r0->ctl_pending ? c->ctl : nullptr,
+                              r0->ctl_pending ? c->ctl_host : nullptr));
+    r0->ctl_pending = false;
+    return TMG_OK;
+}
+
 // Bottom kernel for the instances whose bottom part starts at `level`
 // (level 0: the caller's FP64 arrays; otherwise the level buffers of T).
 template <typename T>
@@ -570,7 +584,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
 // on a first visit), residual, restriction into the next level.
 template <typename T>
 int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s,
-                 int kind = kDeep)
+                 int kind = kDeep, R0 *r0 = nullptr)
 {
     TileList *tl;
     const int H = c->H_down();
@@ -585,8 +599,14 @@ int enqueue_down(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_
     a.rc = L.f[level + 1];
     a.st = io.use_state ? c->st : nullptr;
     a.pre = c->opt.nu1;
+    if (r0) {
+        a.st = nullptr;   // the state is set after this launch
+        a.norm_f = 1;
+        a.partial = c->partial;
+        a.norm_off = tl->d_off;
+    }
     HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
-    return TMG_OK;
+    return r0 ? finalize_r0(c, r0, tl, s) : TMG_OK;
 }
 
 // Up leg at `level` >= 1: the pre-smoothing recomputed from the visit's
@@ -697,7 +717,8 @@ int enqueue_span(tmg_ctx *c, const CycleIO &io, int level, int K, bool down, hip
 }
 
 template <typename T>
-int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, hipStream_t s)
+int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, hipStream_t s,
+                 R0 *r0 = nullptr)
 {
     TileList *tl;
     const int H = down ? c->H_dpair() : c->H_upair();
@@ -722,8 +743,14 @@ int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, 
         a.u_out = L.x(level, 0);
         a.post = c->opt.nu2;
     }
+    if (r0) {
+        a.st = nullptr;   // the state is set after this launch
+        a.norm_f = 1;
+        a.partial = c->partial;
+        a.norm_off = tl->d_off;
+    }
     HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
-    return TMG_OK;
+    return r0 ? finalize_r0(c, r0, tl, s) : TMG_OK;
 }
 
 // First level run in spans: after the first span_after streaming levels
@@ -816,7 +843,9 @@ int seed_halos(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     return TMG_OK;
 }
 
-int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
+// With r0: only the solve's first level-0 down pass (with the initial
+// residual's norm).  A solve's first cycle leaves that pass out.
+int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s, R0 *r0 = nullptr)
 {
     int rc;
     TileList *tl;
@@ -864,7 +893,7 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         a.tab1_32 = tabT_of<float>(c, 1, io.trans);
         a.c2slab_off = c->slab_off_d[2];
     };
-    if (!solve || first) {
+    if (r0 || !solve) {
         // first inner down leg: residual of the iterate, FP32 sweeps, restriction
         for (int pass = fuse ? 0 : 1; pass < 2; ++pass) {
             const bool two = pass == 0;
@@ -880,9 +909,17 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
                 two_level(a);
                 a.f2 = c->s.f[2];
             }
+            if (r0) {
+                // from u = 0 the pass's residual is f itself (u0 folded)
+                a.st = nullptr;   // the state is set after this launch
+                a.partial = c->partial;
+                a.norm_off = tl->d_off;
+            }
             HIPCHK(c, launch_mix(c->P, io.trans, a, tl->ntiles, s));
+            if (r0 && (rc = finalize_r0(c, r0, tl, s))) return rc;
         }
     }
+    if (r0) return TMG_OK;
     if ((rc = c->opt.gamma == 1
                   ? enqueue_vcycle_levels<float>(c, io, fuse ? 2 : 1, fuse ? 2 : 1, s)
                   : enqueue_coarse_visits<float>(c, io, 1, s)))
@@ -918,6 +955,21 @@ int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
             HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 0, s));
     }
     return TMG_OK;
+}
+
+// A solve's first level-0 down pass in FP64, with the initial residual's
+// norm: with two-level passes, levels 0 and 1 down in one launch for the
+// instances whose level 1 streams (the others one level).
+int enqueue_first_down(tmg_ctx *c, const CycleIO &io, hipStream_t s, R0 *r0)
+{
+    int rc;
+    if (c->fuse_up1() && c->deep_n[1] > 0) {
+        if ((rc = enqueue_pair<double>(c, io, 0, true, kDeepNext, s, r0)) ||
+            (rc = enqueue_down<double>(c, io, 0, true, s, kDeepLast, r0)))
+            return rc;
+        return TMG_OK;
+    }
+    return enqueue_down<double>(c, io, 0, true, s, kDeep, r0);
 }
 
 int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
@@ -961,13 +1013,9 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
         const bool fuse2 = solve && c->fuse_up1() && c->deep_n[1] > 0;
         double *f1_in = io.kind == kEven ? c->f1b : c->d.f[1];
         double *f1_out = io.kind == kEven ? c->d.f[1] : c->f1b;
-        if (fuse2 && first) {
-            if ((rc = enqueue_pair<double>(c, io, 0, true, kDeepNext, s)) ||
-                (rc = enqueue_down<double>(c, io, 0, true, s, kDeepLast)))
-                return rc;
-        } else if (!solve || first) {
-            if ((rc = enqueue_down<double>(c, io, 0, first, s))) return rc;
-        }
+        // a solve's first level-0 down pass ran before its first cycle
+        // (enqueue_first_down); a warm-started cycle starts from u
+        if (!solve && (rc = enqueue_down<double>(c, io, 0, false, s))) return rc;
         if ((rc = c->opt.gamma == 1
                       ? enqueue_vcycle_levels<double>(c, io, fuse2 ? 2 : 1, fuse2 ? 2 : 1, s)
                       : enqueue_coarse_visits<double>(c, io, 1, s)))
@@ -1183,13 +1231,29 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     c->ctl_host->rtol2 = rtol * rtol;
     c->ctl_host->max_cycles = max_cycles;
     c->ctl_host->epoch = c->epoch;
-    // initial residual r_0 = f (u0 folded), u = 0; the launch that finishes
-    // it also installs this solve's control block on the device
-    HIPCHK(c, launch_norm_f(c->P, f, trans ? nullptr : u0, tab_of(c, 0, trans), c->tab_stride,
-                            c->slab_off_d[0], tl->d_off, tl->d_inst, c->batch, c->partial,
-                            tl->ntiles, s));
-    HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 1, s,
-                              c->ctl, c->ctl_host));
+    // initial residual r_0 = f (u0 folded), u = 0: its norm comes with the
+    // first level-0 down pass of the instances that stream level 0 (that
+    // pass is then left out of the first cycle), and from k_norm_f for the
+    // instances the bottom kernel holds whole.  The first launch that
+    // finishes a norm also installs this solve's control block.
+    {
+        const CycleIO io0{f, u0, u, trans, true, kFirst};
+        R0 r0;
+        if (c->bot_n[0] > 0) {
+            TileList *tw;
+            if ((rc = get_tiles(c, 0, kWhole, tile_slabs(c->P), s, &tw))) return rc;
+            HIPCHK(c, launch_norm_f(c->P, f, trans ? nullptr : u0, tab_of(c, 0, trans),
+                                    c->tab_stride, c->slab_off_d[0], tw->d_off, tw->d_inst,
+                                    c->batch, c->partial, tw->ntiles, s));
+            if ((rc = finalize_r0(c, &r0, tw, s))) return rc;
+        }
+        if (c->deep_n[0] > 0) {
+            c->cur.assign(c->Lmax + 1, 0);
+            if ((rc = c->mixed ? enqueue_mixed_level0(c, io0, s, &r0)
+                               : enqueue_first_down(c, io0, s, &r0)))
+                return rc;
+        }
+    }
     if (c->batch > 1)
         HIPCHK(c, launch_publish(c->st, c->batch, c->ctl, c->mirror_d, c->pubn_d, s));
 

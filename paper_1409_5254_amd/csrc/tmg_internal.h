@@ -140,6 +140,8 @@ struct LegArgsT {
     int halo;                // left halo slabs per tile (even, a multiple of S)
     int tile_out;            // output slabs per tile
     int pre, post, next;     // sweep counts
+    int norm_f;              // FP64 first visit at level 0: partial = |f|^2 per tile
+                             // (u0 folded), the initial residual's norm; no early exit
 };
 using LegArgs = LegArgsT<double>;
 

@@ -818,11 +818,13 @@ __device__ __forceinline__ void norm_partial(const double (&r)[S][P], double *pa
 // costs the level-0 pass registers.  LEG: 0 any leg; 1 down legs and 2 up
 // legs of a first visit from zero (the levels below 0 of a V-cycle), with
 // the paths they do not take compiled out, which frees registers for more
-// work-groups per CU.
+// work-groups per CU; 4 the first level-0 down pass of a solve, which also
+// leaves the norm partials of f (u0 folded), the initial residual.
 template <int P, bool BW, typename T, bool TOUCH, int LEG>
 __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
 {
-    constexpr bool kAny = LEG == 0, kDown = LEG == 1, kUp = LEG == 2;
+    constexpr bool kNormF = LEG == 4;   // a down leg from zero that also folds u0
+    constexpr bool kAny = LEG == 0, kDown = LEG == 1 || kNormF, kUp = LEG == 2;
     constexpr int S = slabs_per_thread(P);
     constexpr int SC = S >= 2 ? S / 2 : 1;  // coarse slabs touched per thread
     __shared__ double xchg[2][kLegWaves];
@@ -890,7 +892,7 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
         prolong_add<P, SC, T>(e, e2, a.R, cm0);
         sweeps<P, SC, kLegWaves, T>(e, g1, op1, a.post, xchg, phase);
     }
-    if (kAny && a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
+    if ((kAny || kNormF) && a.u0) fold_u0<P, S, T>(f, m0, a.u0[tr.j], op);
     apply_G<P, S, T>(g, f, op);
     sweeps<P, S, kLegWaves, T>(u, g, op, a.pre, xchg, phase);
     if (!kDown && (a.e || a.e2)) prolong_add<P, S, T>(u, e, a.R, m0);
@@ -898,6 +900,8 @@ __global__ __launch_bounds__(kLegThreads) void k_leg(LegArgsT<T> a)
     if (!kDown && a.u_out) store_chunk<P, S, BW, T>(a.u_out + tr.off * P, m0, tr.N, u, li0, a.halo);
     if constexpr (kAny) store_halo<P, S, T>(a.halo_out, u, li0, a.halo);
     double r[S][P];
+    if constexpr (kNormF)   // after the sweeps: its barrier waits on nothing then
+        norm_partial<P, S, kLegWaves>(f, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
     if (kAny && a.partial) {
         residual<P, S, kLegWaves>(r, u, f, op, xchg, phase);
         norm_partial<P, S, kLegWaves>(r, a.partial, a.norm_off, tr, m0, li0, a.halo, red);
@@ -1778,7 +1782,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double *__restri
     const int64_t lo = norm_off[j], hi = norm_off[j + 1];
     // the state is read once, here, so that its load overlaps the partials'
     const InstState s0 = st[j];
-    if (!is_r0 && (s0.done || lo == hi)) return;
+    // an instance outside the launch's tile list (lo == hi) is left alone
+    if (lo == hi || (!is_r0 && s0.done)) return;
     // eight independent loads in flight per thread, summed in a fixed order
     double acc = 0.0;
     for (int64_t b = lo; b < hi; b += 8 * kFinThreads) {
@@ -1972,7 +1977,14 @@ hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles
         const int leg = !plain ? 0
                         : (a.rc && !a.e && !a.e2 && !a.u_out && a.post == 0) ? 1
                         : (!a.rc && (a.e || a.e2)) ? 2 : 0;
-        if (!a.touch) {
+        if (!a.touch && a.norm_f) {
+            if constexpr (std::is_same<T, double>::value) {
+                if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, false, 4>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_leg<PP, false, T, false, 4>), grid, block, 0, s, a);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        } else if (!a.touch) {
             if (backward) hipLaunchKernelGGL((k_leg<PP, true, T, false, 0>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((k_leg<PP, false, T, false, 0>), grid, block, 0, s, a);
         } else if (leg == 1) {
