@@ -89,6 +89,8 @@ struct ActiveSet {
     std::map<std::tuple<int, int, int>, TileList> lists;
     std::vector<int *> bot;            // per level: running instances with lb == level
     std::vector<int> bot_n;
+    int *bot_all = nullptr;            // running instances with lb >= 1
+    int bot_all_n = 0;
     char *arena = nullptr;             // device
     char *stage[2] = {nullptr, nullptr};   // pinned host
     size_t cap = 0;
@@ -151,6 +153,10 @@ struct tmg_ctx {
     int *nlev_d = nullptr;
     std::vector<int *> bot_d;                     // per level: instances with lb == level
     std::vector<int> bot_n;
+    int *bot_all_d = nullptr;                     // instances with lb >= 1 (one launch for all)
+    int bot_all_n = 0;
+    int bot_levels = 0;                           // levels >= 1 with bottom-kernel instances
+    void **lvptr_d = nullptr;                     // per level: f, x (first buffer), slab offsets
     std::vector<int> deep_n;                      // per level: instances with level < lb
     int64_t bottom_cap = 0;
     ActiveSet act;
@@ -391,6 +397,9 @@ int act_begin(tmg_ctx *c, std::vector<unsigned> &run, int64_t tiles, hipStream_t
         if (A.is_run(j) && c->lb[j] < c->Lmax) bcount[c->lb[j]]++;
     size_t need = 0;
     for (int l = 0; l < c->Lmax; ++l) need += a256(sizeof(int) * bcount[l]);
+    int nall = 0;
+    for (int l = 1; l < c->Lmax; ++l) nall += bcount[l];
+    need += a256(sizeof(int) * nall);
     std::vector<std::pair<const std::tuple<int, int, int> *, const TileList *>> keys;
     std::vector<int64_t> nrun;
     for (const auto &k : c->cycle_keys) {
@@ -457,6 +466,15 @@ int act_begin(tmg_ctx *c, std::vector<unsigned> &run, int64_t tiles, hipStream_t
             if (c->lb[j] == l && A.is_run(j)) b[n++] = j;
         A.bot[l] = reinterpret_cast<int *>(A.arena + used);
         A.bot_n[l] = n;
+        used += a256(sizeof(int) * n);
+    }
+    {
+        int *b = reinterpret_cast<int *>(h + used);
+        int n = 0;
+        for (int j = 0; j < B; ++j)
+            if (c->lb[j] >= 1 && A.is_run(j)) b[n++] = j;
+        A.bot_all = reinterpret_cast<int *>(A.arena + used);
+        A.bot_all_n = n;
         used += a256(sizeof(int) * n);
     }
     if (used > 0) {
@@ -577,6 +595,38 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, ninst, s));
+    return TMG_OK;
+}
+
+// The bottom kernel for every instance with lb >= 1 in one launch, each at
+// its own first bottom level (a V-cycle's first visits, after all down legs
+// and before all up legs): the same work as one launch per level.
+template <typename T>
+int enqueue_bottom_all(tmg_ctx *c, const CycleIO &io, hipStream_t s)
+{
+    const ActiveSet &A = c->act;
+    const int *inst = A.on ? A.bot_all : c->bot_all_d;
+    const int n = A.on ? A.bot_all_n : c->bot_all_n;
+    if (n == 0) return TMG_OK;
+    const int Lm = c->Lmax;
+    BottomArgsT<T> a{};
+    a.tab = io.trans ? c->tab_adj : c->tab_fwd;
+    a.R = io.trans ? c->R_adj : c->R_fwd;
+    a.inst = inst;
+    a.nlev = c->nlev_d;
+    a.st = io.use_state ? c->st : nullptr;
+    a.ctl = c->ctl;
+    a.mirror = io.use_state ? c->mirror1() : nullptr;
+    a.batch = c->batch;
+    a.tab_stride = c->tab_stride;
+    a.nu1 = c->opt.nu1;
+    a.nu2 = c->opt.nu2;
+    a.gamma = c->opt.gamma;
+    a.lbs = c->lb_d;
+    a.f_lv = reinterpret_cast<const T *const *>(c->lvptr_d);
+    a.x_lv = reinterpret_cast<T *const *>(c->lvptr_d + Lm);
+    a.soff_lv = reinterpret_cast<const int64_t *const *>(c->lvptr_d + 2 * Lm);
+    HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, n, s));
     return TMG_OK;
 }
 
@@ -794,8 +844,12 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
     }
     for (int l = sd; l < c->Lmax; l += c->span)
         if ((rc = enqueue_span<T>(c, io, l, c->span, true, s))) return rc;
-    for (int l = 1; l < c->Lmax; ++l)
-        if ((rc = enqueue_bottom<T>(c, io, l, nullptr, L.x(l, 0), s))) return rc;
+    if (c->bot_levels >= 2) {
+        if ((rc = enqueue_bottom_all<T>(c, io, s))) return rc;
+    } else {
+        for (int l = 1; l < c->Lmax; ++l)
+            if ((rc = enqueue_bottom<T>(c, io, l, nullptr, L.x(l, 0), s))) return rc;
+    }
     if (sd < c->Lmax)
         for (int l = sd + (c->Lmax - 1 - sd) / c->span * c->span; l >= sd; l -= c->span)
             if ((rc = enqueue_span<T>(c, io, l, c->span, false, s))) return rc;
@@ -819,8 +873,6 @@ int enqueue_vcycle_levels(tmg_ctx *c, const CycleIO &io, int down_first, int up_
     return TMG_OK;
 }
 
-// Level-0 part of a cycle of the FP32-inner defect correction (streaming
-// instances): see k_mix.
 // The level-0 halo slots the passes of this cycle read, re-filled from the
 // iterate for the tile lists in use (first cycle on an active-set
 // generation).
@@ -843,8 +895,10 @@ int seed_halos(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     return TMG_OK;
 }
 
-// With r0: only the solve's first level-0 down pass (with the initial
-// residual's norm).  A solve's first cycle leaves that pass out.
+// Level-0 part of a cycle of the FP32-inner defect correction (streaming
+// instances): see k_mix.  With r0: only the solve's first level-0 down pass
+// (with the initial residual's norm); a solve's first cycle leaves that
+// pass out.
 int enqueue_mixed_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s, R0 *r0 = nullptr)
 {
     int rc;
@@ -1459,6 +1513,8 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
     c->tiles.clear();
     c->cycle_keys.clear();
     for (int *p : c->bot_d) dfree(c, p);
+    dfree(c, c->bot_all_d);
+    c->bot_all_d = nullptr;
     const int Lm = c->Lmax, batch = c->batch, P = c->P;
     c->lb = lbv;
     c->bottom_cap = cap;
@@ -1482,6 +1538,17 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
             HIPCHK(c, hipMemcpyAsync(c->bot_d[l], bl.data(), sizeof(int) * bl.size(),
                                      hipMemcpyHostToDevice, s));
         }
+    }
+    std::vector<int> ball;
+    c->bot_levels = 0;
+    for (int l = 1; l < Lm; ++l) c->bot_levels += c->bot_n[l] > 0;
+    for (int j = 0; j < batch; ++j)
+        if (c->lb[j] >= 1) ball.push_back(j);
+    c->bot_all_n = (int)ball.size();
+    if (!ball.empty()) {
+        if ((rc = dalloc(c, &c->bot_all_d, ball.size()))) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->bot_all_d, ball.data(), sizeof(int) * ball.size(),
+                                 hipMemcpyHostToDevice, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
     // level-0 halo buffers: one slot of H x P doubles per tile
@@ -1640,6 +1707,21 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
                 (rc = dalloc(c, &c->s.xb[l], c->level_size[l])))
                 return fail(rc);
         }
+    }
+    {
+        // per-level arrays of the coarse hierarchy, for one bottom launch
+        // over instances at different levels
+        std::vector<void *> t(3 * (size_t)Lm, nullptr);
+        for (int l = 0; l < Lm; ++l) {
+            t[l] = c->mixed ? (void *)c->s.f[l] : (void *)c->d.f[l];
+            t[Lm + l] = c->mixed ? (void *)c->s.xa[l] : (void *)c->d.xa[l];
+            t[2 * Lm + l] = c->slab_off_d[l];
+        }
+        if ((rc = dalloc(c, &c->lvptr_d, t.size()))) return fail(rc);
+        if (hipMemcpyAsync(c->lvptr_d, t.data(), sizeof(void *) * t.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(TMG_ERR_HIP);
     }
     if ((rc = apply_plan(c, bottom_cap, true, 0, 2, s))) return fail(rc);
     // tables, level-major: block (l, j) at (l * batch + j) * stride

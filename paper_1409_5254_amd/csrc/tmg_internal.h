@@ -232,6 +232,14 @@ struct BottomArgsT {
     const Control *ctl;
     HostHead *mirror;        // one instance: its host copy after such a cycle (else null)
     int level, batch, tab_stride, nu1, nu2, gamma;
+    // With lbs: every instance at its own first bottom level lbs[j] (>= 1,
+    // a V-cycle's first visit: x_in and u0 null), with that level's arrays
+    // f_lv[l], x_lv[l] (the result) and slab offsets soff_lv[l]; f, x_out,
+    // slab_off and level unused.
+    const int *lbs;
+    const TIO *const *f_lv;
+    TIO *const *x_lv;
+    const int64_t *const *soff_lv;
 };
 using BottomArgs = BottomArgsT<double>;
 

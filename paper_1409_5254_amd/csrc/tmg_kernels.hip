@@ -1583,7 +1583,7 @@ struct Bottom {
     }
 };
 
-template <int P, bool BW, typename TIO>
+template <int P, bool BW, typename TIO, bool MULTI>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
 {
     using B = Bottom<P, BW>;
@@ -1591,19 +1591,23 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
     __shared__ BottomLds<P> sm;
     const int j = a.inst[blockIdx.x];
     if (a.st && a.st[j].done) return;
-    const int lb = a.level, Lc = a.nlev[j] - 1;
-    const int64_t off = a.slab_off[j];
-    const int64_t N = a.slab_off[j + 1] - off;
+    // MULTI: the instances' own first bottom levels (V-cycle first visits)
+    const int lb = MULTI ? a.lbs[j] : a.level, Lc = a.nlev[j] - 1;
+    const TIO *const fl = MULTI ? a.f_lv[lb] : a.f;
+    TIO *const xl = MULTI ? a.x_lv[lb] : a.x_out;
+    const int64_t *const so = MULTI ? a.soff_lv[lb] : a.slab_off;
+    const int64_t off = so[j];
+    const int64_t N = so[j + 1] - off;
     if (lb == Lc) {
         // a single level (any size up to the largest coarsest level): the
         // exact solve, directly in global memory
         const double *tab = a.tab + ((int64_t)lb * a.batch + j) * a.tab_stride;
         const double u0 = (lb == 0 && a.u0) ? a.u0[j] : 0.0;
-        coarse_scan<P, BW, NT, TIO, TIO>(a.f + off * P, u0, a.x_out + off * P, N, tab, &sm.scan);
+        coarse_scan<P, BW, NT, TIO, TIO>(fl + off * P, u0, xl + off * P, N, tab, &sm.scan);
         if (lb == 0 && a.st) {
             // squared residual of the result, one slab per thread and pass
             constexpr TabLayout L(P);
-            const TIO *x = a.x_out + off * P, *f = a.f + off * P;
+            const TIO *x = xl + off * P, *f = fl + off * P;
             double acc = 0.0;
             for (int64_t m = threadIdx.x; m < N; m += NT) {
                 const int64_t pm = BW ? N - 1 - m : m;
@@ -1648,7 +1652,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
         }
         const int64_t m0 = (int64_t)threadIdx.x * S;
         TIO fv[S][P], xv[S][P];
-        load_chunk<P, S, false, TIO>(a.f + off * P, m0, N, fv);
+        load_chunk<P, S, false, TIO>(fl + off * P, m0, N, fv);
         if (a.x_in) {
             load_chunk<P, S, false, TIO>(a.x_in + off * P, m0, N, xv);
         } else {
@@ -1699,7 +1703,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int k = 0; k < P; ++k) xo[s][k] = (TIO)xd[s][k];
-        store_chunk<P, S, false, TIO>(a.x_out + off * P, m0, N, xo, 0, 0);
+        store_chunk<P, S, false, TIO>(xl + off * P, m0, N, xo, 0, 0);
     }
     if (lb == 0 && a.st) {
         // squared residual of the result (level 0 of this instance): the
@@ -2040,9 +2044,15 @@ template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s)
 {
     if (ninst <= 0) return hipSuccess;
+    const dim3 grid(ninst), block(kBottomThreads);
     TMG_DISPATCH_P(P, {
-        if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_bottom<PP, false, TIO>), dim3(ninst), dim3(kBottomThreads), 0, s, a);
+        if (a.lbs) {
+            if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_bottom<PP, false, TIO, true>), grid, block, 0, s, a);
+        } else {
+            if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_bottom<PP, false, TIO, false>), grid, block, 0, s, a);
+        }
     })
     return hipGetLastError();
 }
