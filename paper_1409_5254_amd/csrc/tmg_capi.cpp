@@ -72,12 +72,13 @@ struct TileList {
 // pass reads the left halo of each tile from the slot the pass before
 // stored under the tile's number in its list; the first cycle on a new
 // generation re-fills those slots from the iterate under the new numbers
-// (the values are the iterate's there, so the results do not change).  The lists
-// of one generation live in a device arena, copied there in stream order
-// from a pinned staging buffer (two, used in turn by generations, so that
-// the host never writes one a queued copy still reads).  They cover the
-// tile lists the cycles after the first use (recorded as they are asked
-// for); any other list is used in full.
+// (the values are the iterate's there, so the results do not change).
+// The lists of one generation live in a device arena, sent there in one
+// copy in stream order from a pinned staging buffer (two, used in turn by
+// generations, so that the host never writes one a queued copy still
+// reads).  They cover the tile lists the cycles after the first use
+// (recorded as they are asked for) and the bottom kernel's instance lists;
+// any other list is used in full.
 constexpr double kActiveShare = 0.75;
 constexpr int kActiveAhead = 2;   // cycles queued past the last summary
 struct ActiveSet {
