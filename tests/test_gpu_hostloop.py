@@ -220,3 +220,30 @@ def test_active_set_adjoint_is_bitwise_the_full_lists():
     assert np.array_equal(zt[0], zf[0])
     assert zt[1:] == zf[1:]
     assert max(zf[3]) > 2 * min(zf[3])
+
+
+def test_active_set_with_cycle_cap_on_two_streams():
+    """Active-set lists with a cycle cap that stops the slow instances, in
+    solves on two streams in turn: bitwise the full lists' results, and the
+    capped instances report their cap."""
+    p = 1
+    Ns, lams, Ts, u0, fs = _uneven_batch(p, 38)
+    s = B().Solver(Ns, Ts, lams, p=p)
+    s.set_schedule(256, pairs=True, direct=True)
+    f, d0 = dev(np.concatenate(fs)), dev(u0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    out = {}
+    for on, st in ((True, s1), (False, s2), (True, s2), (False, s1)):
+        s.set_active_set(on)
+        with torch.cuda.stream(st):
+            u = torch.full_like(f, 1.0)
+            r = s.solve(f, d0, u=u, rtol=1e-10, max_cycles=6)
+        torch.cuda.synchronize()
+        out.setdefault(on, []).append((host(u), list(r.cycles), list(r.relres), r.status))
+    ref = out[False][0]
+    for res in out[True] + out[False][1:]:
+        assert np.array_equal(res[0], ref[0])
+        assert res[1:] == ref[1:]
+    assert ref[3] == B().TMG_NOT_CONVERGED
+    assert max(ref[1]) == 6 and min(ref[1]) <= 3
