@@ -230,6 +230,8 @@ struct tmg_ctx {
     int H_mixd2() const { return r4(opt.nu1 + 2 + 2 * opt.nu1); }
     int H_mix2() const { return r4(2 * opt.nu1 + opt.nu2 + 3 + 2 * (opt.nu1 + opt.nu2) + 2 * opt.nu1); }
     int TO(int H) const { return tile_slabs(P) - H; }
+    // every bottom-kernel level fits one wavefront (one-wavefront work-groups)
+    bool small_bottom() const { return bottom_cap <= 64 * bottom_slabs(P); }
     // spans of K levels (k_span, one top-level slab per thread): the down
     // legs lose nu1 + 1 slabs at the top level and, at each level below,
     // half the wrong slabs restricted from above plus nu1 + 1 (the last
@@ -595,6 +597,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.nu1 = c->opt.nu1;
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
+    a.small = c->small_bottom();
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, ninst, s));
     return TMG_OK;
 }
@@ -627,6 +630,7 @@ int enqueue_bottom_all(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     a.f_lv = reinterpret_cast<const T *const *>(c->lvptr_d);
     a.x_lv = reinterpret_cast<T *const *>(c->lvptr_d + Lm);
     a.soff_lv = reinterpret_cast<const int64_t *const *>(c->lvptr_d + 2 * Lm);
+    a.small = c->small_bottom();
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, n, s));
     return TMG_OK;
 }

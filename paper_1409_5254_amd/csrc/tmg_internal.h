@@ -240,6 +240,9 @@ struct BottomArgsT {
     const TIO *const *f_lv;
     TIO *const *x_lv;
     const int64_t *const *soff_lv;
+    // 1: every instance's first bottom level has at most 64 * bottom_slabs
+    // slabs (one wavefront holds it): one-wavefront work-groups
+    int small;
 };
 using BottomArgs = BottomArgsT<double>;
 

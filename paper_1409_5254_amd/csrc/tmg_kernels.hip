@@ -1425,27 +1425,28 @@ __global__ __launch_bounds__(kThreads) void k_coarse(CoarseArgs a)
 // of the down leg is recomputed in the up leg instead of stored.
 // ---------------------------------------------------------------------------
 
-template <int P>
+// NT threads (kBottomThreads, or 64 for bottoms one wavefront holds).
+template <int P, int NT>
 struct BottomLds {
-    static constexpr int BMAX = bottom_max(P);
+    static constexpr int BMAX = NT * bottom_slabs(P);
     static constexpr int STRIDE = TabLayout(P).stride();
     double f[2 * BMAX * P];
     double x[2 * BMAX * P];
     double tab[kBottomMaxLevels * STRIDE];
     double R[2 * P * P];     // R_1^T, R_2^T
-    double xchg[2][kBottomThreads / 64];
-    double red[kBottomThreads / 64];
-    ScanSmem<kBottomThreads> scan;
+    double xchg[2][NT / 64];
+    double red[NT / 64];
+    ScanSmem<NT> scan;
 };
 
-template <int P, bool BW>
+template <int P, bool BW, int NT_ = kBottomThreads>
 struct Bottom {
-    static constexpr int NT = kBottomThreads;
+    static constexpr int NT = NT_;
     static constexpr int NW = NT / 64;
     static constexpr int S = bottom_slabs(P);
     static constexpr int STRIDE = TabLayout(P).stride();
     static constexpr int WAVE_SLABS = 64 * S;   // largest level one wavefront holds
-    BottomLds<P> &sm;
+    BottomLds<P, NT> &sm;
     int lb;        // first level of this visit
     int64_t Nlb;   // its slab count
     int Lc;        // coarsest level
@@ -1583,12 +1584,15 @@ struct Bottom {
     }
 };
 
-template <int P, bool BW, typename TIO, bool MULTI>
-__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgsT<TIO> a)
+// NT = 64 (one wavefront per instance) where every level of the launch's
+// instances fits one wavefront: a fraction of the registers and LDS, so many
+// instances share a CU.
+template <int P, bool BW, typename TIO, bool MULTI, int NT_>
+__global__ __launch_bounds__(NT_) void k_bottom(BottomArgsT<TIO> a)
 {
-    using B = Bottom<P, BW>;
+    using B = Bottom<P, BW, NT_>;
     constexpr int NT = B::NT, S = B::S, STRIDE = B::STRIDE;
-    __shared__ BottomLds<P> sm;
+    __shared__ BottomLds<P, NT> sm;
     const int j = a.inst[blockIdx.x];
     if (a.st && a.st[j].done) return;
     // MULTI: the instances' own first bottom levels (V-cycle first visits)
@@ -2044,16 +2048,23 @@ template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s)
 {
     if (ninst <= 0) return hipSuccess;
-    const dim3 grid(ninst), block(kBottomThreads);
+    const dim3 grid(ninst), block(a.small ? 64 : kBottomThreads);
+#define TMG_BOTTOM(NT)                                                                            \
+    if (a.lbs) {                                                                                  \
+        if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, true, NT>), grid, block, 0, s, a); \
+        else hipLaunchKernelGGL((k_bottom<PP, false, TIO, true, NT>), grid, block, 0, s, a);      \
+    } else {                                                                                      \
+        if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, false, NT>), grid, block, 0, s, a); \
+        else hipLaunchKernelGGL((k_bottom<PP, false, TIO, false, NT>), grid, block, 0, s, a);     \
+    }
     TMG_DISPATCH_P(P, {
-        if (a.lbs) {
-            if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_bottom<PP, false, TIO, true>), grid, block, 0, s, a);
+        if (a.small) {
+            TMG_BOTTOM(64)
         } else {
-            if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, false>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_bottom<PP, false, TIO, false>), grid, block, 0, s, a);
+            TMG_BOTTOM(kBottomThreads)
         }
     })
+#undef TMG_BOTTOM
     return hipGetLastError();
 }
 template hipError_t launch_bottom<double>(int, bool, const BottomArgsT<double> &, int, hipStream_t);
