@@ -92,7 +92,7 @@ typedef struct {
     int schedule;     /* kernel schedule id, -1 = library default                   */
 } tmg_options;
 
-#define TMG_MAX_DEGREE 3
+#define TMG_MAX_DEGREE 5
 
 /* Fill *opt with the defaults: p = 1, nu1 = nu2 = 2, V-cycle, n_coarse = 2,
  * optimal damping, FP64, default schedule. */

@@ -22,7 +22,7 @@ ERRORS = {
     -5: "TMG_ERR_OOM", -6: "TMG_ERR_HIP", -7: "TMG_ERR_NONFINITE", -8: "TMG_ERR_DIVERGED",
     -9: "TMG_ERR_UNSUPPORTED",
 }
-MAX_DEGREE = 3
+MAX_DEGREE = 5
 
 # every symbol the header declares
 SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",

@@ -7,7 +7,7 @@
 
 namespace tmg {
 
-constexpr int kMaxP = 4;        // P = p + 1 coefficients per slab
+constexpr int kMaxP = 6;        // P = p + 1 coefficients per slab
 constexpr int kThreads = 256;   // work-group size of the scan and reduction kernels
 // Work-group size of the streaming (tile) kernels.  Four wavefronts: one
 // wavefront per work-group (barrier-free exchange) measured slower on the
@@ -27,7 +27,10 @@ constexpr int tile_slabs(int P) { return kLegThreads * slabs_per_thread(P); }
 // Slabs per thread of the bottom kernel (even), the largest level (slabs) it
 // holds, and the most levels it can hold (log2(bottom_max) + 1).
 constexpr int bottom_slabs(int P) { return P == 1 ? 8 : (P == 2 ? 4 : 2); }
-constexpr int bottom_max(int P) { return kBottomThreads * bottom_slabs(P); }
+// work-group of the bottom kernel's full form: half of kBottomThreads for
+// P >= 5, whose levels would not fit the LDS otherwise
+constexpr int bottom_threads(int P) { return P >= 5 ? kBottomThreads / 2 : kBottomThreads; }
+constexpr int bottom_max(int P) { return bottom_threads(P) * bottom_slabs(P); }
 constexpr int kBottomMaxLevels = 13;
 
 // Per-(instance, level) table block, doubles, for P coefficients per slab.

@@ -1970,6 +1970,8 @@ __global__ __launch_bounds__(kThreads) void k_grad(const double *__restrict__ u,
     case 2: { constexpr int PP = 2; __VA_ARGS__; } break; \
     case 3: { constexpr int PP = 3; __VA_ARGS__; } break; \
     case 4: { constexpr int PP = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int PP = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int PP = 6; __VA_ARGS__; } break; \
     default: return hipErrorInvalidValue;             \
     }
 
@@ -2048,7 +2050,7 @@ template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s)
 {
     if (ninst <= 0) return hipSuccess;
-    const dim3 grid(ninst), block(a.small ? 64 : kBottomThreads);
+    const dim3 grid(ninst), block(a.small ? 64 : bottom_threads(P));
 #define TMG_BOTTOM(NT)                                                                            \
     if (a.lbs) {                                                                                  \
         if (backward) hipLaunchKernelGGL((k_bottom<PP, true, TIO, true, NT>), grid, block, 0, s, a); \
@@ -2061,7 +2063,7 @@ hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ni
         if (a.small) {
             TMG_BOTTOM(64)
         } else {
-            TMG_BOTTOM(kBottomThreads)
+            TMG_BOTTOM(bottom_threads(PP))
         }
     })
 #undef TMG_BOTTOM

@@ -45,7 +45,7 @@ def relerr(a, b):
     return float(np.max(np.abs(np.asarray(a) - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("schedule", [-1, 0])
 @pytest.mark.parametrize("gamma", [1, 2])
 def test_mixed_solve(p, schedule, gamma):

@@ -55,7 +55,7 @@ def rand(rng, n):
 # single kernels
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("z", [1e-3, 1.0, 40.0])
 @pytest.mark.parametrize("nsweep", [0, 1, 2, 3])
 def test_down_kernel(p, z, nsweep):
@@ -84,7 +84,7 @@ def test_down_kernel(p, z, nsweep):
         assert relerr(host(d_out), ref0) <= TOL
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("nsweep", [0, 2, 5])
 def test_up_kernel(p, nsweep):
     """k_up: prolongation + correction (eq. chap4_prolongationTime) then sweeps."""
@@ -99,7 +99,7 @@ def test_up_kernel(p, nsweep):
     assert relerr(host(out), ref) <= TOL
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("trans", [False, True])
 def test_transposed_kernels(p, trans):
     """Transposed (adjoint) system, backward in time: sweeps with D^{-T},
@@ -124,7 +124,7 @@ def test_transposed_kernels(p, trans):
                                      rel=1e-12)
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("N", [1, 2, 7, 256, 257, 1000, 4096])
 @pytest.mark.parametrize("trans", [False, True])
 def test_coarse_scan(p, N, trans):
@@ -160,7 +160,7 @@ def test_unit_damping_nilpotent(p):
 # cycles and solves
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("schedule", [-1, 0, 5])
 def test_cycles_match_oracle(p, gamma, schedule):
@@ -181,7 +181,7 @@ def test_cycles_match_oracle(p, gamma, schedule):
     assert relerr(host(du), ref) <= TOL
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("opts", [dict(), dict(nu1=1, nu2=1), dict(nu1=3, nu2=0),
                                   dict(n_coarse=8), dict(omega_mode=1, omega=0.5)])
 def test_solve_matches_oracle(p, opts):
@@ -234,7 +234,7 @@ def test_batched_uneven(schedule, gamma):
         assert relerr(U[s.offsets[j]:s.offsets[j + 1]], uo) <= TOL
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("trans", [False, True])
 def test_bottom_wavefront_levels(p, gamma, trans):
@@ -267,7 +267,7 @@ def test_bottom_wavefront_levels(p, gamma, trans):
         assert relerr(Z[s.offsets[j]:s.offsets[j + 1]], zo) <= TOL
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("schedule", [-1, 4])
 def test_adjoint_solve_and_gradients(p, schedule):
     """tmg_adjoint_solve equals the oracle's multigrid solve of L^T z = g and
@@ -336,7 +336,7 @@ def test_warm_start_resume():
     assert np.array_equal(host(c), host(a))
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("trans", [False, True])
 def test_fused_level0_pass(p, trans):
     """tmg_op_fused: the pass every cycle after the first runs at level 0 --
@@ -362,7 +362,7 @@ def test_fused_level0_pass(p, trans):
     assert relerr(host(d_rc), ref_rc) <= TOL
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("trans", [False, True])
 def test_fused2_level0_pass(p, trans):
     """tmg_op_fused2: level 1's correction computed in the tiles as level

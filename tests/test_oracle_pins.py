@@ -104,7 +104,7 @@ def test_alpha_zero_for_odd_degree():
         assert np.count_nonzero(np.diff(np.sign(al))) == 1
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_polynomial_solution_is_reproduced(p):
     """Variational problem chap4_discreteVarFormODE: if the exact solution is
     a polynomial of degree <= p, it lies in the trial space and satisfies the
@@ -125,7 +125,7 @@ def test_polynomial_solution_is_reproduced(p):
         assert np.allclose(u[n], coef, rtol=0, atol=1e-12 * max(1.0, np.max(np.abs(coef))))
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_radau_ia_collocation(p):
     """Theorem chap4_theorem1a: with the load vector taken by the left Radau
     rule with p+1 points, the DG solution satisfies the discontinuous
@@ -165,7 +165,7 @@ def test_nodal_order(p, N):
     assert abs(order - (2 * p + 1)) < 0.1
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_direct_against_dense(p):
     """Eq. chap4_generalLinearSystemODE assembled densely from the closed-form
     Legendre matrices and solved by numpy; also L u and L^T z."""
@@ -202,7 +202,7 @@ def test_operator_depends_on_lambda_tau_only():
 # Transfers (section 4.2, eqs. chap4_restrictionTime / chap4_prolongationTime)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_galerkin_identity(p):
     """R L_tau P = L_{2 tau}: for coarse trial and test functions the fine jump
     terms inside a coarse slab cancel, so the fine bilinear form restricted to
@@ -218,7 +218,7 @@ def test_galerkin_identity(p):
     assert np.allclose(G, an.dense_L(p, Nc, 2 * tau, lam), rtol=0, atol=2e-14)
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_restriction_of_load_vector(p):
     """R is the transpose of the L2-embedding, so R f_tau = f_{2 tau} exactly
     for load vectors of any f."""
@@ -229,7 +229,7 @@ def test_restriction_of_load_vector(p):
     assert np.allclose(core.restrict(p, fine), coarse, rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_prolongation_is_exact_embedding(p):
     """P maps a coarse polynomial to the same function on both fine slabs."""
     rng = np.random.default_rng(8)
@@ -316,7 +316,7 @@ def test_two_grid_closed_form_p0(golden_dir):
         assert rho <= bound
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_symbol_matches_dense_periodic_two_grid(p):
     """Theorem chap4_theorem4 is exact for the time-periodic problem: the
     largest eigenvalue modulus of the dense periodic two-grid operator equals
@@ -373,7 +373,7 @@ def test_vcycle_solve_fourier_small():
     assert np.max(np.abs(uw - ud)) <= 1e-8 * np.max(np.abs(ud))
 
 
-@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 def test_adjoint_dot_product_and_solves(p):
     """<L u, z> = <u, L^T z>; the backward substitution and the multigrid
     cycle on L^T solve the transposed system."""
