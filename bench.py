@@ -22,7 +22,13 @@ Other workloads (`--workload`):
   highdeg     the paper's own setting on one GPU at the highest degrees built:
               p = 5 (and 4), tau = 1e-6, N = 2^20 steps, lambda = 1, to a
               relative residual of 1e-8; a seeded random load from u = 0 in
-              place of f = 0 from a random start (the same error iteration).
+              place of f = 0 from a random start (the same error iteration);
+  convergence the section 4.2 study on the GPU: two-grid cycles (coarse level
+              N/2 solved exactly) on u' + u = 0 from a seeded random start,
+              N = 1024 as in the paper, tau = z in 10^-6 .. 10^6, p = 0..5,
+              nu = 1, 2, 5:
+              the measured asymptotic contraction per case and the time per
+              cycle.
 """
 from __future__ import annotations
 
@@ -53,7 +59,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="scalar",
-                    choices=["scalar", "eigenmodes", "adjoint", "long", "highdeg"])
+                    choices=["scalar", "eigenmodes", "adjoint", "long", "highdeg",
+                             "convergence"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -298,6 +305,46 @@ def highdeg_run(p, steps, warmup):
 
 
 # ---------------------------------------------------------------------------
+# the section 4.2 convergence study, two-grid cycles
+# ---------------------------------------------------------------------------
+
+def convergence_run(log2n=10):
+    import numpy as np
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    N = 1 << log2n
+    rows = []
+    t_cycles, n_cycles = 0.0, 0
+    for p in range(6):
+        P = p + 1
+        rng = np.random.default_rng(100 + p)
+        start = torch.as_tensor(rng.uniform(0.0, 1.0, N * P), device="cuda")
+        f = torch.zeros(N * P, dtype=torch.float64, device="cuda")
+        u0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for nu in (1, 2, 5):
+            for z in np.logspace(-6, 6, 13):
+                s = Solver([N], [float(z) * N], [1.0], p=p, nu1=nu, nu2=nu, n_coarse=N // 2)
+                u = start.clone()
+                r = [s.residual_norm(f, u)[0]]
+                while len(r) < 40 and r[-1] > 1e-200 * r[0]:
+                    sync()
+                    t0 = time.perf_counter()
+                    s.vcycle(f, u0, u)
+                    sync()
+                    t_cycles += time.perf_counter() - t0
+                    n_cycles += 1
+                    r.append(s.residual_norm(f, u)[0])
+                K = len(r) - 1
+                tail = ((r[K] / r[K // 2]) ** (1.0 / (K - K // 2))
+                        if r[K] > 1e-200 * r[0] and K >= 2 else 0.0)
+                rows.append({"p": p, "nu": nu, "z": float(z), "cycles": K, "contraction": tail})
+                s.close()
+    return dict(cases=rows, ms_per_cycle=t_cycles / n_cycles * 1e3, cycles=n_cycles,
+                workload=f"two-grid cycles, N=2^{log2n}, coarse N/2 exact, u'+u=0, random start "
+                         "(seed 100+p), tau in 10^-6..10^6, p=0..5, nu=1,2,5")
+
+
+# ---------------------------------------------------------------------------
 # adjoint / gradients
 # ---------------------------------------------------------------------------
 
@@ -364,6 +411,13 @@ def main():
         r = adjoint_run(a.batch or 256, a.steps, a.warmup)
         print(json.dumps({**base, "value": r["unknowns_per_s"],
                           "ms_per_step": r["ms_per_forward_backward"],
+                          "config": {"workload": r["workload"]}, "result": r}))
+        return
+    if a.workload == "convergence":
+        r = convergence_run()
+        print(json.dumps({**base, "metric": "two-grid cycles per second (convergence study)",
+                          "unit": "cycles/s", "value": 1e3 / r["ms_per_cycle"],
+                          "ms_per_step": r["ms_per_cycle"],
                           "config": {"workload": r["workload"]}, "result": r}))
         return
     if a.workload == "highdeg":

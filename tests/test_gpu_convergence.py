@@ -1,0 +1,61 @@
+"""GPU replay of the section 4.2 convergence study: the two-grid cycle (the
+coarse level N/2 solved exactly by the scan) on u' + u = 0 with N = 1024
+slabs of width tau = z, from a seeded random start in [0, 1], for p = 0..5,
+z in {1e-3, 1, 40} and nu1 = nu2 in {1, 2, 5}.  The first cycles are the
+oracle's to 1e-12 of the start; the measured asymptotic contraction (tail
+geometric mean of the residual ratios) agrees with the Fourier estimate of
+Theorem chap4_theorem4 (tests/golden/two_grid_rho.json, written from the
+oracle) within -10%/+2%.  Where the residual underflows to zero (large z,
+nu >= 2: block Jacobi is then nearly exact), the GPU must reach that too."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import core  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "two_grid_rho.json")))
+N = GOLDEN["N"]
+CASES = [(c["p"], c["z"], c["nu"], c["rho"]) for c in GOLDEN["cases"]]
+
+
+def B():
+    from paper_1409_5254_amd import binding
+    return binding
+
+
+@pytest.mark.parametrize("p,z,nu,rho", CASES)
+def test_two_grid_contraction(p, z, nu, rho):
+    rng = np.random.default_rng(100 + p)
+    u_start = rng.uniform(0.0, 1.0, N * (p + 1))
+    s = B().Solver([N], [z * N], [1.0], p=p, nu1=nu, nu2=nu, n_coarse=N // 2)
+    f = torch.zeros(N * (p + 1), dtype=torch.float64, device=DEV)
+    u0 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    u = torch.as_tensor(u_start, device=DEV).clone()
+    r = [float(s.residual_norm(f, u)[0])]
+    opts = core.Opts(nu1=nu, nu2=nu, gamma=1, n_coarse=N // 2)
+    uo = u_start.copy()
+    fo = np.zeros_like(uo)
+    while len(r) < 40 and r[-1] > 1e-200 * r[0]:
+        s.vcycle(f, u0, u)
+        r.append(float(s.residual_norm(f, u)[0]))
+        if len(r) <= 4:
+            uo = core.cycles(p, z * N, 1.0, fo, uo, 1, opts)
+            torch.cuda.synchronize()
+            err = np.max(np.abs(u.cpu().numpy() - uo))
+            assert err <= 1e-12 * np.max(np.abs(u_start)), (len(r) - 1, err)
+    K = len(r) - 1
+    if r[-1] > 1e-200 * r[0]:
+        assert K >= 8
+        tail = (r[K] / r[K // 2]) ** (1.0 / (K - K // 2))
+        assert 0.9 * rho <= tail <= 1.02 * rho, (tail, rho)
+    else:
+        # reached the underflow floor: the estimate must be tiny as well
+        assert rho < 1e-4 or K >= 8, (K, rho)
