@@ -9,7 +9,7 @@ for the unnormalised Legendre basis; the initial value u0 is *not* folded in
 Recipes (name, seed; draws in the order listed):
   fourier_small (1)      u'+u=f on (0,10], u0=1, p=1, N=1024; f = sum_{k=1..8} a_k sin(k t + phi_k),
      a = standard_normal(8), then phi = uniform(0, 2pi, 8).
-  fourier_scalar (2)     lambda=1, T=1000, u0=1, N=2^22, p in {0..3}; same
+  fourier_scalar (2)     lambda=1, T=1000, u0=1, N=2^22, p in {0..5}; same
      form with 16 modes.
   eigenmode_batch (3)    4096 instances: kappa = uniform(0.01, 1) (one draw), lambda_j = pi^2 j^2 kappa,
      N_j = 2^integers(12, 19), T_j = 1, p = 1, u0 = 1; load vector M_tau c with
