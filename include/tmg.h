@@ -149,16 +149,17 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
 /*
  * Schedule autotuner.  Installs in h the fastest of a few schedules, timed on
  * this hardware with the caller's data: for each candidate it runs four
- * cycles of the solve of L u = f (u0 folded) and keeps the faster of two
- * runs timed with HIP events.  A schedule is the size up to which an
+ * cycles of the solve of L u = f (u0 folded) and keeps the fastest of
+ * three runs timed with HIP events.  A schedule is the size up to which an
  * instance's levels run inside the single-work-group bottom kernel
  * (bottom_cap, the largest the bottom kernel holds divided by 1, 2, ...,
  * 32) and, for V-cycles, whether
  * consecutive levels share two-level launches, and whether the levels
  * after the first `span_after` streaming levels below level 1 (in pairs, an
  * odd one out alone) run in spans of `span` levels per launch (3 or 4; 0:
- * no spans; V-cycles only); then, for the fastest of
- * those, whether the cycles after the first of a solve are launched kernel
+ * no spans; V-cycles only), chosen in that order, then the caps next to
+ * the chosen one again with the chosen launch pattern; then, for the
+ * fastest of those, whether the cycles after the first of a solve are launched kernel
  * by kernel instead of as captured graphs (a graph launch idles the GPU for
  * several microseconds; direct launches pay when the host enqueues a cycle
  * faster than the GPU runs it).  The solution is the same under every

@@ -1879,14 +1879,14 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     float best = -1.0f;
     Cand pick = old;
     constexpr int kCycles = 4;
-    // a run that captures the graphs, then the faster of two timed ones
+    // a run that captures the graphs, then the fastest of three timed ones
     // (rtol 0: every instance runs kCycles cycles); milliseconds, or < 0 on
     // an error
     auto timed = [&]() -> float {
         rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
         if (rc < 0) return -1.0f;
         float best_ms = -1.0f;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             if (hipEventRecord(e0, s) != hipSuccess) { rc = TMG_ERR_HIP; return -1.0f; }
             rc = run_solve(c, f, u0, u, false, 0.0, kCycles, nullptr, nullptr, s);
             if (rc < 0) return -1.0f;
@@ -1919,6 +1919,13 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
             for (int after = 1; after <= 6; ++after)
                 if (c->span_fits(K)) cands.push_back({pick.cap, true, K, after});
         run_stage();
+        // the caps next to the first stage's pick, with the launch pattern
+        // the second stage chose for it
+        cands.clear();
+        for (int64_t cap : {pick.cap * 2, pick.cap / 2})
+            if (cap >= c->opt.n_coarse && cap <= (int64_t)bottom_max(c->P))
+                cands.push_back({cap, pick.pairs, pick.span, pick.after});
+        if (rc >= 0) run_stage();
     }
     int rc2 = apply_plan(c, pick.cap, pick.pairs, pick.span, pick.after, s);
     // then the same schedule with the cycles after the first launched kernel
