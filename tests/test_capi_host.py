@@ -49,7 +49,8 @@ def _setup(b, n, T, lam, **kw):
     ([1024], [0.0], [1.0], {}, -4),                       # T <= 0
     ([1024], [1.0], [-1.0], {}, -4),                      # lambda <= 0
     ([1024], [1.0], [float("nan")], {}, -4),
-    ([1024], [1.0], [1.0], dict(p=7), -1),                # degree not built
+    ([1024], [1.0], [1.0], dict(p=6), -1),                # degree not built (0..5)
+    ([1024], [1.0], [1.0], dict(p=7), -1),
     ([1024], [1.0], [1.0], dict(p=-1), -1),
     ([1024], [1.0], [1.0], dict(gamma=3), -1),
     ([1024], [1.0], [1.0], dict(nu1=9), -1),
@@ -71,3 +72,15 @@ def test_null_arguments():
     assert L.tmg_vcycle(None, None, None, None, None) == -1
     assert L.tmg_destroy(None) == -1
     assert L.tmg_level_size(None, 0) == -1
+    assert L.tmg_set_active_set(None, 1) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU only: --gpus N > 1 exits with a message
+    (before anything touches a GPU)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
