@@ -386,7 +386,7 @@ def main():
     AUTOTUNE = bool(a.autotune)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solve is not "
-              "sharded across GPUs in this build.", file=sys.stderr)
+              "sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
