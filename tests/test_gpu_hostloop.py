@@ -247,3 +247,26 @@ def test_active_set_with_cycle_cap_on_two_streams():
         assert res[1:] == ref[1:]
     assert ref[3] == B().TMG_NOT_CONVERGED
     assert max(ref[1]) == 6 and min(ref[1]) <= 3
+
+
+def test_batch_above_the_run_bit_limit():
+    """A batch of more than 65536 instances (no run bits in the summary, so no
+    active-set lists; k_publish reduces over many rounds of its work-group):
+    every instance converges, and sampled ones equal their oracle solves."""
+    p = 0
+    B_ = 70000
+    rng = np.random.default_rng(39)
+    Ns = [8192 if j % 1000 == 7 else (4 if j % 3 else 256) for j in range(B_)]
+    lams = list(rng.uniform(0.5, 5.0, B_))
+    Ts = list(rng.uniform(0.5, 4.0, B_))
+    u0 = rng.uniform(-1, 1, B_)
+    f = rng.standard_normal(sum(Ns) * (p + 1))
+    s = B().Solver(Ns, Ts, lams, p=p)
+    r = s.solve(dev(f), dev(u0), rtol=1e-10)
+    assert r.status == 0
+    U = host(r.u)
+    for j in list(range(0, B_, 9973)) + [7, 69007, B_ - 1]:
+        seg = slice(s.offsets[j], s.offsets[j + 1])
+        uo, k, _, _ = core.solve(p, Ts[j], lams[j], u0[j], f[seg], rtol=1e-10)
+        assert r.cycles[j] == k, j
+        assert relerr(U[seg], uo) <= 1e-12
