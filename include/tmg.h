@@ -162,7 +162,8 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
  * fastest of those, whether the cycles after the first of a solve are launched kernel
  * by kernel instead of as captured graphs (a graph launch idles the GPU for
  * several microseconds; direct launches pay when the host enqueues a cycle
- * faster than the GPU runs it).  The solution is the same under every
+ * faster than the GPU runs it), the caps next to the pick timed again in
+ * that mode.  The solution is the same under every
  * schedule (up to rounding order); only the kernel split and launch mode
  * change.  u (device, same layout as f) is used as scratch and overwritten.
  * *bottom_cap, *pairs, *span, *span_after and *direct (host, may be NULL)

@@ -1936,6 +1936,25 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
         const float ms = timed();
         direct = ms >= 0.0f && ms < best;
         c->direct = direct;
+        if (direct) {
+            // with direct launches the caps next to the pick once more (a
+            // graph boundary no longer weighs on the small levels)
+            best = ms;
+            const Cand base = pick;
+            for (int64_t cap : {base.cap * 2, base.cap / 2}) {
+                if (cap < c->opt.n_coarse || cap > (int64_t)bottom_max(c->P)) continue;
+                if (apply_plan(c, cap, base.pairs, base.span, base.after, s) != TMG_OK) continue;
+                c->direct = true;
+                const float m2 = timed();
+                if (m2 < 0.0f) break;
+                if (m2 < best) {
+                    best = m2;
+                    pick = {cap, base.pairs, base.span, base.after};
+                }
+            }
+            rc2 = apply_plan(c, pick.cap, pick.pairs, pick.span, pick.after, s);
+            c->direct = true;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
