@@ -189,3 +189,59 @@ def dense_two_grid(p: int, N: int, z: float, nu1: int, nu2: int, omega: float,
     S = np.eye(N * (p + 1)) - omega * np.linalg.solve(D, L)
     K = np.eye(N * (p + 1)) - R.T @ np.linalg.solve(Lc, R @ L)
     return np.linalg.matrix_power(S, nu2) @ K @ np.linalg.matrix_power(S, nu1)
+
+
+def level_steps(N: int, n_coarse: int):
+    """Slab counts N, N/2, ..., n_coarse of the hierarchy (N = n_coarse 2^k)."""
+    out = [N]
+    while out[-1] > n_coarse:
+        assert out[-1] % 2 == 0
+        out.append(out[-1] // 2)
+    assert out[-1] == n_coarse
+    return out
+
+
+def dense_cycle(p: int, N: int, T: float, lam: float, nu1: int, nu2: int, gamma: int,
+                n_coarse: int = 2, omega: float | None = None, trans: bool = False):
+    """Dense error propagator M_0 of one multigrid cycle on level 0.
+
+    The two-grid error propagator of eq. chap4_errorTwoGridCycle,
+    S^nu2 (I - P L_c^{-1} R L) S^nu1, with the exact coarse solve replaced by
+    gamma cycles from a zero initial guess on the coarse error equation,
+    which leaves the coarse error M_{l+1}^gamma L_{l+1}^{-1} R L e:
+
+        M_l = S_l^nu2 (I - P (I - M_{l+1}^gamma) L_{l+1}^{-1} R L_l) S_l^nu1,
+
+    M = 0 on the coarsest level (an exact solve).  L_l is rediscretised at
+    tau_l = T / N_l, S_l = I - omega_l D_l^{-1} L_l is damped block Jacobi
+    (eq. chap4_ODESmoother) with omega_l from Lemma chap4_lemma7 at
+    alpha(lam tau_l) (or the fixed omega), R the restriction of
+    eq. chap4_restrictionTime and P = R^T.  trans: the same cycle applied to
+    L^T (smoother I - omega D^{-T} L^T, the same R and P).  Every matrix comes
+    from the closed forms above, none from the C oracle."""
+    Ns = level_steps(N, n_coarse)
+    P_ = p + 1
+
+    def Lmat(Nl):
+        L = dense_L(p, Nl, T / Nl, lam)
+        return L.T if trans else L
+
+    def smoother(Nl):
+        L = Lmat(Nl)
+        _, _, _, A = slab_closed_form(p, T / Nl, lam)
+        D = np.kron(np.eye(Nl), A.T if trans else A)
+        om = omega_opt(alpha_of(p, lam * T / Nl)) if omega is None else omega
+        return np.eye(Nl * P_) - om * np.linalg.solve(D, L)
+
+    def M(l):
+        Nl = Ns[l]
+        if l == len(Ns) - 1:
+            return np.zeros((Nl * P_, Nl * P_))
+        Lf, Lc = Lmat(Nl), Lmat(Ns[l + 1])
+        R = dense_R(p, Ns[l + 1])
+        Mc = np.linalg.matrix_power(M(l + 1), gamma)
+        K = np.eye(Nl * P_) - R.T @ (np.eye(Mc.shape[0]) - Mc) @ np.linalg.solve(Lc, R @ Lf)
+        S = smoother(Nl)
+        return np.linalg.matrix_power(S, nu2) @ K @ np.linalg.matrix_power(S, nu1)
+
+    return M(0)

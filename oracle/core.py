@@ -60,8 +60,9 @@ def lib():
             "or_cycles": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _i, _pd, _pd],
             "or_solve": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _d, _i, _pd,
                          _pd, _pd],
-            "or_solve_mixed": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _pd, _d, _i, _pd,
-                               _pd, _pd],
+            "or_solve_mixed": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _d, _i,
+                               _pd, _pd, _pd],
+            "or_cycle_mixed": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _pd],
             "or_adjoint_rhs": [_i, _i64, _pd, _pd, _pd, _pd],
             "or_gradients": [_i, _i64, _d, _d, _pd, _pd, _pd, _pd],
         }
@@ -209,17 +210,30 @@ def solve(p: int, T: float, lam: float, u0: float, f, rtol: float = 1e-10,
 
 
 def solve_mixed(p: int, T: float, lam: float, u0: float, f, rtol: float = 1e-10,
-                max_cycles: int = 200, opts: Opts = Opts()):
-    """FP32-inner / FP64-outer defect-correction reference."""
+                max_cycles: int = 200, opts: Opts = Opts(), lb64: int = -1):
+    """FP32-inner / FP64-outer defect-correction reference.  lb64: first level
+    whose visits run in FP64 arithmetic from FP32 operands (-1: the coarsest
+    level only)."""
     f = fold(p, u0, f)
     u = np.empty_like(f)
     hist = np.zeros(max_cycles + 1)
     rr = _dref()
     k = lib().or_solve_mixed(p, f.size // (p + 1), T, lam, opts.nu1, opts.nu2, opts.gamma,
-                             opts.n_coarse, opts.omega_mode, opts.omega, _p(f), rtol,
+                             opts.n_coarse, opts.omega_mode, opts.omega, lb64, _p(f), rtol,
                              max_cycles, _p(u), ctypes.byref(rr), _p(hist))
     assert k >= 0
     return u, k, rr.value, hist[:k + 1].copy()
+
+
+def cycle_mixed(p: int, T: float, lam: float, r, opts: Opts = Opts(), lb64: int = -1):
+    """One FP32-inner cycle on L e = r (folded r, rounded to FP32) from e = 0:
+    the inner correction of the defect correction, returned in double."""
+    r = _c(r)
+    e = np.empty_like(r)
+    rc = lib().or_cycle_mixed(p, r.size // (p + 1), T, lam, opts.nu1, opts.nu2, opts.gamma,
+                              opts.n_coarse, opts.omega_mode, opts.omega, lb64, _p(r), _p(e))
+    assert rc == 0
+    return e
 
 
 def adjoint_rhs(p: int, u, y):

@@ -358,6 +358,7 @@ static void prolong_add(int P, const double *R1T, const double *R2T, int64_t Nc,
 typedef struct {
     int P, nlev;
     int nu1, nu2, gamma;
+    int lb64;     /* mixed-precision reference: first level run in FP64 (nlev-1 by default) */
     or_level *lv; /* lv[0] finest (the paper's level L), lv[nlev-1] coarsest */
     double R1T[OR_MAXP * OR_MAXP], R2T[OR_MAXP * OR_MAXP];
 } or_hier;
@@ -380,6 +381,7 @@ static int build_hier(or_hier *H, int p, int64_t N, double T, double lam, int nu
     H->nu1 = nu1;
     H->nu2 = nu2;
     H->gamma = gamma;
+    H->lb64 = nlev - 1;
     H->lv = calloc((size_t)nlev, sizeof(or_level));
     for (int l = 0; l < nlev; ++l) {
         int64_t Nl = N >> l;
@@ -667,18 +669,24 @@ static void jacobi32(const or_level32 *lv, const float *f, float *u)
 /*
  * Mixed-precision cycle on level l: smoothing, restriction and prolongation
  * in FP32 (storage and arithmetic); the intra-cycle residual in FP64
- * arithmetic from the FP32 operands, stored as FP32; the coarsest solve in
- * FP64 from the FP32 right-hand side, stored as FP32.
+ * arithmetic from the FP32 operands, stored as FP32.  A visit of a level
+ * l >= H->lb64 runs in FP64 arithmetic from the FP32 right-hand side and
+ * iterate and stores its result as FP32: by default (lb64 = the coarsest
+ * level) only the coarsest solve; a smaller lb64 also computes the levels
+ * above it in FP64, as a solver that keeps its small levels on chip does.
  */
 static void cycle32(const or_hier *H, const or_level32 *L32, int l, const float *f, float *u)
 {
     const or_level *lv = &H->lv[l];
     int P = H->P;
     int64_t N = lv->N;
-    if (l == H->nlev - 1) {
+    if (l >= H->lb64) {
         double *f64 = malloc(sizeof(double) * N * P), *u64 = malloc(sizeof(double) * N * P);
-        for (int64_t i = 0; i < N * P; ++i) f64[i] = (double)f[i];
-        direct(lv, 0, f64, u64);
+        for (int64_t i = 0; i < N * P; ++i) {
+            f64[i] = (double)f[i];
+            u64[i] = (double)u[i];
+        }
+        cycle(H, l, 0, f64, u64);
         for (int64_t i = 0; i < N * P; ++i) u[i] = (float)u64[i];
         free(f64);
         free(u64);
@@ -736,25 +744,70 @@ static void cycle32(const or_hier *H, const or_level32 *L32, int l, const float 
  * one FP32-inner cycle on L e = r from e = 0; u += e (FP64) }.
  * Returns the number of outer iterations (each is one cycle).
  */
-int or_solve_mixed(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamma,
-                   int64_t n_coarse, int omega_mode, double omega_fixed, const double *f,
-                   double rtol, int max_cycles, double *u, double *relres, double *hist)
+/* FP32 copies of every level of H. */
+static or_level32 *levels32(const or_hier *H)
+{
+    int P = H->P;
+    or_level32 *L32 = calloc((size_t)H->nlev, sizeof(or_level32));
+    for (int l = 0; l < H->nlev; ++l) {
+        L32[l].P = P;
+        L32[l].N = H->lv[l].N;
+        L32[l].omega = (float)H->lv[l].omega;
+        for (int i = 0; i < P * P; ++i) {
+            L32[l].A[i] = (float)H->lv[l].A[i];
+            L32[l].Nm[i] = (float)H->lv[l].Nm[i];
+        }
+    }
+    return L32;
+}
+
+/* lb64 in [0, nlev-1] selects the first level visited in FP64 (see
+ * cycle32); any other value keeps the default (the coarsest level). */
+static void set_lb64(or_hier *H, int lb64)
+{
+    if (lb64 >= 0 && lb64 < H->nlev) H->lb64 = lb64;
+}
+
+/*
+ * One FP32-inner cycle on L e = r from e = 0 (r rounded to FP32 first); the
+ * correction e is returned in double.  This is the inner step of the
+ * defect correction below.
+ */
+int or_cycle_mixed(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamma,
+                   int64_t n_coarse, int omega_mode, double omega_fixed, int lb64,
+                   const double *r, double *e)
 {
     or_hier H;
     if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
         return -1;
-    int P = H.P;
-    or_level32 *L32 = calloc((size_t)H.nlev, sizeof(or_level32));
-    for (int l = 0; l < H.nlev; ++l) {
-        L32[l].P = P;
-        L32[l].N = H.lv[l].N;
-        L32[l].omega = (float)H.lv[l].omega;
-        for (int i = 0; i < P * P; ++i) {
-            L32[l].A[i] = (float)H.lv[l].A[i];
-            L32[l].Nm[i] = (float)H.lv[l].Nm[i];
-        }
+    set_lb64(&H, lb64);
+    or_level32 *L32 = levels32(&H);
+    int64_t n = N * H.P;
+    float *r32 = malloc(sizeof(float) * n), *e32 = malloc(sizeof(float) * n);
+    for (int64_t i = 0; i < n; ++i) {
+        r32[i] = (float)r[i];
+        e32[i] = 0.0f;
     }
-    int64_t n = N * P;
+    cycle32(&H, L32, 0, r32, e32);
+    for (int64_t i = 0; i < n; ++i) e[i] = (double)e32[i];
+    free(r32);
+    free(e32);
+    free(L32);
+    free_hier(&H);
+    return 0;
+}
+
+int or_solve_mixed(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamma,
+                   int64_t n_coarse, int omega_mode, double omega_fixed, int lb64,
+                   const double *f, double rtol, int max_cycles, double *u, double *relres,
+                   double *hist)
+{
+    or_hier H;
+    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+        return -1;
+    set_lb64(&H, lb64);
+    or_level32 *L32 = levels32(&H);
+    int64_t n = N * H.P;
     double *r = malloc(sizeof(double) * n);
     float *r32 = malloc(sizeof(float) * n), *e32 = malloc(sizeof(float) * n);
     memset(u, 0, sizeof(double) * n);
