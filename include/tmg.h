@@ -77,7 +77,8 @@ enum {
     TMG_ERR_HIP = -6,         /* a HIP call failed (see tmg_last_hip_error)        */
     TMG_ERR_NONFINITE = -7,   /* NaN / Inf in the data or the residual             */
     TMG_ERR_DIVERGED = -8,    /* residual grew beyond 1e3 * initial residual       */
-    TMG_ERR_UNSUPPORTED = -9  /* option combination not built into the library    */
+    TMG_ERR_UNSUPPORTED = -9, /* option combination not built into the library    */
+    TMG_ERR_INTERNAL = -10    /* the library's own solve state is inconsistent (a bug) */
 };
 
 typedef struct {
@@ -197,6 +198,32 @@ int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int span, int 
  * Returns TMG_ERR_INVALID for a null handle.
  */
 int tmg_set_active_set(tmg_handle h, int on);
+
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * solve of tmg_solve for ONE instance (n_slabs slabs on (0, T], decay rate
+ * lambda, options *opt) without a handle.  Every buffer the solve's kernels
+ * need beyond f, u0 and u (level hierarchy, tables, tile lists, halo slots,
+ * norm partials, state) is carved out of a static device array of the
+ * library (TMG_NOALLOC_SCRATCH_BYTES per device, held from the library's
+ * load to the end of the process).  The call allocates no device or pinned
+ * host memory and creates no streams, events or graphs; it rebuilds the
+ * tables and schedule (default schedule, cycles launched kernel by kernel)
+ * on every call, and it blocks until the solve is done.
+ * f, u0 (length 1) and u are device arrays as for tmg_solve; cycles and
+ * relres (host, may be NULL) receive one value each.  Returns as tmg_solve,
+ * or TMG_ERR_SIZE when n_slabs * (p + 1) exceeds TMG_NOALLOC_MAX_UNKNOWNS.
+ * Every call on one device shares that device's array and keeps the last
+ * call's contents there: calls that overlap on one device (other host
+ * threads, or work queued on several streams at once) race and must be
+ * serialised by the caller.
+ */
+#define TMG_NOALLOC_SCRATCH_BYTES (96u << 20)
+#define TMG_NOALLOC_MAX_UNKNOWNS (1 << 21)
+int tmg_solve_noalloc(int64_t n_slabs, double T, double lambda, const tmg_options *opt,
+                      const double *f, const double *u0, double *u, double rtol, int max_cycles,
+                      int *cycles, double *relres, tmg_stream s);
 
 /* Release every resource of h (synchronises its streams first). */
 int tmg_destroy(tmg_handle h);

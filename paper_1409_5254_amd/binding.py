@@ -20,7 +20,7 @@ TMG_NOT_CONVERGED = 1
 ERRORS = {
     -1: "TMG_ERR_INVALID", -2: "TMG_ERR_SIZE", -3: "TMG_ERR_OMEGA", -4: "TMG_ERR_PARAM",
     -5: "TMG_ERR_OOM", -6: "TMG_ERR_HIP", -7: "TMG_ERR_NONFINITE", -8: "TMG_ERR_DIVERGED",
-    -9: "TMG_ERR_UNSUPPORTED",
+    -9: "TMG_ERR_UNSUPPORTED", -10: "TMG_ERR_INTERNAL",
 }
 MAX_DEGREE = 5
 
@@ -30,7 +30,7 @@ SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_a
            "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
            "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
            "tmg_op_coarse_solve",
-           "tmg_op_residual_norm"]
+           "tmg_op_residual_norm", "tmg_solve_noalloc"]
 
 
 class TmgError(RuntimeError):
@@ -94,6 +94,8 @@ def lib():
             "tmg_op_fused2": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_coarse_solve": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
             "tmg_op_residual_norm": (_i, [_vp, _i, _vp, _vp, _vp, P(_d), _vp]),
+            "tmg_solve_noalloc": (_i, [_i64, _d, _d, _vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d),
+                                       _vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -117,6 +119,22 @@ def _ptr(t):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def solve_noalloc(n_slabs, T, lam, f, u0, u=None, rtol=1e-10, max_cycles=100, **opts):
+    """One instance solved by ``tmg_solve_noalloc`` (no handle; the library's
+    static scratch holds every buffer beyond f, u0 and u).  Returns a
+    SolveResult; raises TmgError on an error code."""
+    o = Options.make(**opts)
+    if u is None:
+        u = torch.empty_like(f)
+    cyc = (ctypes.c_int * 1)()
+    rr = (ctypes.c_double * 1)()
+    rc = lib().tmg_solve_noalloc(int(n_slabs), float(T), float(lam), ctypes.byref(o), _ptr(f),
+                                 _ptr(u0), _ptr(u), rtol, max_cycles, cyc, rr, _stream())
+    if rc < 0:
+        raise TmgError(rc, "tmg_solve_noalloc")
+    return SolveResult(u, list(cyc), list(rr), rc)
 
 
 @dataclass

@@ -41,6 +41,9 @@
 
 using namespace tmg;
 
+static_assert(TMG_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size");
+static_assert(TMG_NOALLOC_MAX_UNKNOWNS == kNoAllocMaxUnknowns, "no-alloc problem limit");
+
 namespace {
 
 // kDeep: streaming levels (level < lb_j); kDeepNext: the next level streams
@@ -184,6 +187,16 @@ struct tmg_ctx {
     hipStream_t cap = nullptr;
     int last_hip = 0;
     std::vector<void *> allocs;
+    // The entry point that allocates nothing (arena != null): every device
+    // buffer is carved out of the library's static scratch array; no pinned
+    // host memory, streams, events or graphs; the host follows the solve by
+    // plain copies of the state into fx_st.
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    InstState fx_st{};
+    Control fx_ctl{};
+    double fx_grad[2] = {0.0, 0.0};
+    bool fixed() const { return arena != nullptr; }
 
     // halo (even and a multiple of S) and output slabs per tile of each pass
     int rs(int x) const
@@ -282,6 +295,14 @@ int dalloc(tmg_ctx *c, T **p, size_t n)
 {
     *p = nullptr;
     if (n == 0) n = 1;
+    if (c->arena) {
+        // bump allocation in the static scratch, 256-byte aligned
+        const size_t bytes = (n * sizeof(T) + 255) & ~size_t(255);
+        if (bytes > c->arena_cap - c->arena_used) return TMG_ERR_SIZE;
+        *p = reinterpret_cast<T *>(c->arena + c->arena_used);
+        c->arena_used += bytes;
+        return TMG_OK;
+    }
     hipError_t e = hipMalloc((void **)p, n * sizeof(T));
     if (e != hipSuccess) {
         c->last_hip = (int)e;
@@ -294,7 +315,7 @@ int dalloc(tmg_ctx *c, T **p, size_t n)
 // Free one allocation made by dalloc (null: nothing).
 void dfree(tmg_ctx *c, void *p)
 {
-    if (!p) return;
+    if (!p || c->arena) return;   // the scratch is reclaimed as a whole after the call
     for (size_t i = 0; i < c->allocs.size(); ++i)
         if (c->allocs[i] == p) {
             c->allocs[i] = c->allocs.back();
@@ -1221,6 +1242,7 @@ void free_all(tmg_ctx *c)
     c->graphs.clear();
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
+    if (c->fixed()) return;   // nothing of its own was allocated
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->ctl_host) (void)hipHostFree(c->ctl_host);
     if (c->grad_host) (void)hipHostFree(c->grad_host);
@@ -1319,7 +1341,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // graphs are kept per set of arrays; a full cache is emptied before the
     // five graphs of this solve are fetched, never between them
     hipGraphExec_t g[5];
-    if (c->graphs.size() + 5 > 30) {
+    if (!c->fixed() && c->graphs.size() + 5 > 30) {
         bool have = true;
         for (int k = 0; k < 5; ++k)
             have = have && c->graphs.count(GraphKey{k, trans, f, u0, u}) > 0;
@@ -1329,7 +1351,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
             c->graphs.clear();
         }
     }
-    for (int k = 0; k < (c->direct ? 1 : 5); ++k) {
+    for (int k = 0; k < (c->fixed() ? 0 : c->direct ? 1 : 5); ++k) {
         CycleIO io{f, u0, u, trans, true, k};
         if ((rc = get_graph(c, io, &g[k]))) return rc;
     }
@@ -1342,8 +1364,9 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // enqueues a cycle faster than the GPU runs it.
     auto launch = [&](int n) -> int {
         while (n > 0) {
-            if ((c->direct || c->act.on) && launched > 0) {
-                CycleIO io{f, u0, u, trans, true, (launched % 2 == 1) ? kEven : kOdd};
+            if (c->fixed() || ((c->direct || c->act.on) && launched > 0)) {
+                CycleIO io{f, u0, u, trans, true,
+                           launched == 0 ? kFirst : (launched % 2 == 1) ? kEven : kOdd};
                 if ((rc = enqueue_cycle(c, io, s))) return rc;
                 launched += 1;
                 n -= 1;
@@ -1376,11 +1399,34 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     const int head = std::min(max_cycles, 3);
     if ((rc = launch(head))) return rc;
     HostSum sum{};
+    // one instance with nothing of its own allocated: the host reads the
+    // state after the queued cycles (a plain copy and a wait), queues up to
+    // the count the state predicts, and repeats
+    while (c->fixed()) {
+        HIPCHK(c, hipMemcpyAsync(&c->fx_st, c->st, sizeof(InstState), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        const InstState q = c->fx_st;
+        sum.cycles = q.cycles;
+        sum.done = q.done;
+        sum.r0sq = q.r0sq;
+        sum.rsq = q.rsq;
+        if (q.done || q.cycles >= max_cycles) break;
+        int want = q.cycles + 2;
+        if (q.prev_rsq > 0.0 && q.rsq > 0.0 && q.rsq < q.prev_rsq) {
+            const double k =
+                std::log(c->ctl_host->rtol2 * q.r0sq / q.rsq) / std::log(q.rsq / q.prev_rsq);
+            want = q.cycles + (int)std::fmin(std::fmax(std::ceil(k), 1.0), 64.0);
+        }
+        want = std::min(std::max(want, launched + 1), max_cycles);
+        // every queued cycle has run, so a running instance has cycles == launched
+        if (want <= launched) return TMG_ERR_INTERNAL;
+        if ((rc = launch(want - launched))) return rc;
+    }
     long long last_ver = -1;
     long polls = 0;
     constexpr std::chrono::microseconds kQuiet(2000);
     auto since = std::chrono::steady_clock::now();
-    while (true) {
+    while (!c->fixed()) {
         long long ver = 0;
         HostSum q;
         if (__atomic_load_n(&c->mirror->end, __ATOMIC_ACQUIRE) != last_ver &&
@@ -1433,7 +1479,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
                 if (!again) {
                     // a drained stream with a running instance: queue one
                     // more cycle, or give up when none is left
-                    if (launched >= max_cycles) return TMG_ERR_HIP;
+                    if (launched >= max_cycles) return TMG_ERR_INTERNAL;
                     if ((rc = launch(1))) return rc;
                 }
             } else if (qs != hipErrorNotReady) {
@@ -1442,8 +1488,10 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
             }
         }
     }
-    HIPCHK(c, hipEventRecord(c->drain_ev, s));
-    c->drain_pending = true;
+    if (!c->fixed()) {
+        HIPCHK(c, hipEventRecord(c->drain_ev, s));
+        c->drain_pending = true;
+    }
     // per-instance results: the summary holds a single instance's; a batch
     // reads its states once (after the cycles still queued)
     if (c->batch > 1) {
@@ -1605,7 +1653,7 @@ const char *tmg_error_string(int code)
     case TMG_OK: return "ok";
     case TMG_NOT_CONVERGED: return "max_cycles reached before the residual tolerance";
     case TMG_ERR_INVALID: return "invalid argument";
-    case TMG_ERR_SIZE: return "slab count is not n_coarse * 2^k";
+    case TMG_ERR_SIZE: return "slab count is not n_coarse * 2^k, or larger than the call takes";
     case TMG_ERR_OMEGA: return "damping parameter outside (0, 1]";
     case TMG_ERR_PARAM: return "lambda and T must be finite and positive";
     case TMG_ERR_OOM: return "device memory allocation failed";
@@ -1613,18 +1661,22 @@ const char *tmg_error_string(int code)
     case TMG_ERR_NONFINITE: return "non-finite value in the data or the residual";
     case TMG_ERR_DIVERGED: return "residual grew beyond 1e3 times the initial residual";
     case TMG_ERR_UNSUPPORTED: return "option combination not supported";
+    case TMG_ERR_INTERNAL: return "internal error: the solve's own state is inconsistent";
     default: return "unknown status";
     }
 }
 
 int tmg_last_hip_error(tmg_handle h) { return h ? h->last_hip : 0; }
 
-int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T,
-              const double *lambda, const tmg_options *opt, tmg_stream stream)
+}  // extern "C"
+
+namespace {
+
+// Argument checks of a set-up (host only): options, lambda, T, and every
+// n_slabs[j] = n_coarse * 2^k; L[j] receives the level counts.
+int check_problem(int batch, const int64_t *n_slabs, const double *T, const double *lambda,
+                  const tmg_options &o, std::vector<int> *Lout)
 {
-    if (!hp || !n_slabs || !T || !lambda || !opt || batch < 1) return TMG_ERR_INVALID;
-    *hp = nullptr;
-    const tmg_options &o = *opt;
     if (o.p < 0 || o.p > TMG_MAX_DEGREE || o.nu1 < 0 || o.nu1 > kMaxSweeps || o.nu2 < 0 ||
         o.nu2 > kMaxSweeps || (o.gamma != 1 && o.gamma != 2) || o.n_coarse < 1 ||
         o.n_coarse > kMaxCoarse || (o.omega_mode != 0 && o.omega_mode != 1))
@@ -1649,15 +1701,21 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     // levels of at most bottom_cap slabs run inside the single-work-group
     // bottom kernel (schedule >= 0: bottom_cap = 2^schedule, capped); an
     // instance's coarsest level always does
+    std::vector<int> lbv;
+    if (plan_levels(L, n_slabs, schedule_cap(o.p + 1, o.schedule), &lbv)) return TMG_ERR_SIZE;
+    Lout->swap(L);
+    return TMG_OK;
+}
+
+// Everything a handle holds for the checked problem: level hierarchy,
+// tables, schedule, state, host copies.  On failure the caller releases
+// what was made (free_all).
+int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
+              const double *lambda, const tmg_options &o, const std::vector<int> &L,
+              hipStream_t s)
+{
     const int P = o.p + 1;
     const int64_t bottom_cap = schedule_cap(P, o.schedule);
-    {
-        std::vector<int> lbv;
-        if (plan_levels(L, n_slabs, bottom_cap, &lbv)) return TMG_ERR_SIZE;
-    }
-    tmg_ctx *c = new (std::nothrow) tmg_ctx;
-    if (!c) return TMG_ERR_OOM;
-    hipStream_t s = (hipStream_t)stream;
     c->batch = batch;
     c->P = P;
     c->S = slabs_per_thread(P);
@@ -1672,13 +1730,9 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
     c->tab_stride = TL.stride();
 
     int rc = TMG_OK;
-    auto fail = [&](int code) {
-        free_all(c);
-        delete c;
-        return code;
-    };
-    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
-        return fail(TMG_ERR_HIP);
+    // the capture stream of the cycle graphs (none without allocations)
+    if (!c->fixed() && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+        return TMG_ERR_HIP;
 
     c->slab_off_h.assign(Lm, std::vector<int64_t>(batch + 1, 0));
     c->slab_off_d.assign(Lm, nullptr);
@@ -1694,23 +1748,23 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         auto &off = c->slab_off_h[l];
         for (int j = 0; j < batch; ++j) off[j + 1] = off[j] + (l < L[j] ? (c->N[j] >> l) : 0);
         c->level_size[l] = off[batch] * P;
-        if ((rc = dalloc(c, &c->slab_off_d[l], batch + 1))) return fail(rc);
+        if ((rc = dalloc(c, &c->slab_off_d[l], batch + 1))) return rc;
         if (hipMemcpyAsync(c->slab_off_d[l], off.data(), sizeof(int64_t) * (batch + 1),
                            hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
-            return fail(TMG_ERR_HIP);
+            return TMG_ERR_HIP;
         // coarse-level buffers in the precision of the cycle below level 0
         if (l > 0 && !c->mixed) {
             if ((rc = dalloc(c, &c->d.f[l], c->level_size[l])) ||
                 (rc = dalloc(c, &c->d.xa[l], c->level_size[l])) ||
                 (rc = dalloc(c, &c->d.xb[l], c->level_size[l])))
-                return fail(rc);
+                return rc;
         }
         if (l > 0 && c->mixed) {
             if ((rc = dalloc(c, &c->s.f[l], c->level_size[l])) ||
                 (rc = dalloc(c, &c->s.xa[l], c->level_size[l])) ||
                 (rc = dalloc(c, &c->s.xb[l], c->level_size[l])))
-                return fail(rc);
+                return rc;
         }
     }
     {
@@ -1722,13 +1776,13 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
             t[Lm + l] = c->mixed ? (void *)c->s.xa[l] : (void *)c->d.xa[l];
             t[2 * Lm + l] = c->slab_off_d[l];
         }
-        if ((rc = dalloc(c, &c->lvptr_d, t.size()))) return fail(rc);
+        if ((rc = dalloc(c, &c->lvptr_d, t.size()))) return rc;
         if (hipMemcpyAsync(c->lvptr_d, t.data(), sizeof(void *) * t.size(), hipMemcpyHostToDevice,
                            s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
-            return fail(TMG_ERR_HIP);
+            return TMG_ERR_HIP;
     }
-    if ((rc = apply_plan(c, bottom_cap, true, 0, 2, s))) return fail(rc);
+    if ((rc = apply_plan(c, bottom_cap, true, 0, 2, s))) return rc;
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
         ta((size_t)Lm * batch * c->tab_stride, 0.0);
@@ -1756,25 +1810,31 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         (rc = dalloc(c, &c->st, batch)) || (rc = dalloc(c, &c->st_ops, batch)) ||
         (rc = dalloc(c, &c->ctl, 1)) || (rc = dalloc(c, &c->tau_d, batch)) ||
         (rc = dalloc(c, &c->grad_d, 2 * batch)) || (rc = dalloc(c, &c->nlev_d, batch)))
-        return fail(rc);
+        return rc;
     // partial sums: one slot per level-0 tile at the smallest tile size in use
     c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
-    if ((rc = dalloc(c, &c->partial, c->partial_cap))) return fail(rc);
+    if ((rc = dalloc(c, &c->partial, c->partial_cap))) return rc;
     const size_t mirror_bytes =
         sizeof(HostHead) + sizeof(HostSum) + sizeof(unsigned) * run_words(batch);
-    if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
+    if (c->fixed()) {
+        // one instance: its state, control block and gradients in the context
+        c->st_host = &c->fx_st;
+        c->ctl_host = &c->fx_ctl;
+        c->grad_host = c->fx_grad;
+    } else if (hipHostMalloc((void **)&c->st_host, sizeof(InstState) * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->ctl_host, sizeof(Control)) != hipSuccess ||
         hipHostMalloc((void **)&c->grad_host, sizeof(double) * 2 * batch) != hipSuccess ||
         hipHostMalloc((void **)&c->mirror, mirror_bytes,
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
-        return fail(TMG_ERR_OOM);
-    std::memset(c->mirror, 0, mirror_bytes);
+        return TMG_ERR_OOM;
+    if (c->mirror) std::memset(c->mirror, 0, mirror_bytes);
     if ((rc = dalloc(c, &c->pubn_d, 1)) ||
         hipMemsetAsync(c->pubn_d, 0, sizeof(unsigned), s) != hipSuccess)
-        return fail(rc ? rc : TMG_ERR_HIP);
-    if (hipHostGetDevicePointer((void **)&c->mirror_d, c->mirror, 0) != hipSuccess ||
-        hipEventCreateWithFlags(&c->drain_ev, hipEventDisableTiming) != hipSuccess)
-        return fail(TMG_ERR_HIP);
+        return rc ? rc : TMG_ERR_HIP;
+    if (!c->fixed() &&
+        (hipHostGetDevicePointer((void **)&c->mirror_d, c->mirror, 0) != hipSuccess ||
+         hipEventCreateWithFlags(&c->drain_ev, hipEventDisableTiming) != hipSuccess))
+        return TMG_ERR_HIP;
     if (hipMemcpyAsync(c->tab_fwd, tf.data(), tf.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->tab_adj, ta.data(), ta.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->R_fwd, Rf.data(), Rf.size() * 8, hipMemcpyHostToDevice, s) ||
@@ -1783,7 +1843,7 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         hipMemcpyAsync(c->nlev_d, nlev.data(), nlev.size() * sizeof(int), hipMemcpyHostToDevice,
                        s) ||
         hipMemsetAsync(c->st, 0, sizeof(InstState) * batch, s) || hipStreamSynchronize(s))
-        return fail(TMG_ERR_HIP);
+        return TMG_ERR_HIP;
     if (c->mixed) {
         // FP32 copies of the tables for the inner cycle
         std::vector<float> tf32(tf.begin(), tf.end()), ta32(ta.begin(), ta.end()),
@@ -1791,16 +1851,65 @@ int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T
         if ((rc = dalloc(c, &c->tab32_fwd, tf32.size())) ||
             (rc = dalloc(c, &c->tab32_adj, ta32.size())) ||
             (rc = dalloc(c, &c->R32_fwd, Rf32.size())) || (rc = dalloc(c, &c->R32_adj, Ra32.size())))
-            return fail(rc);
+            return rc;
         if (hipMemcpyAsync(c->tab32_fwd, tf32.data(), tf32.size() * 4, hipMemcpyHostToDevice, s) ||
             hipMemcpyAsync(c->tab32_adj, ta32.data(), ta32.size() * 4, hipMemcpyHostToDevice, s) ||
             hipMemcpyAsync(c->R32_fwd, Rf32.data(), Rf32.size() * 4, hipMemcpyHostToDevice, s) ||
             hipMemcpyAsync(c->R32_adj, Ra32.data(), Ra32.size() * 4, hipMemcpyHostToDevice, s) ||
             hipStreamSynchronize(s))
-            return fail(TMG_ERR_HIP);
+            return TMG_ERR_HIP;
+    }
+    return TMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tmg_setup(tmg_handle *hp, int batch, const int64_t *n_slabs, const double *T,
+              const double *lambda, const tmg_options *opt, tmg_stream stream)
+{
+    if (!hp || !n_slabs || !T || !lambda || !opt || batch < 1) return TMG_ERR_INVALID;
+    *hp = nullptr;
+    std::vector<int> L;
+    int rc = check_problem(batch, n_slabs, T, lambda, *opt, &L);
+    if (rc) return rc;
+    tmg_ctx *c = new (std::nothrow) tmg_ctx;
+    if (!c) return TMG_ERR_OOM;
+    if ((rc = build_ctx(c, batch, n_slabs, T, lambda, *opt, L, (hipStream_t)stream))) {
+        free_all(c);
+        delete c;
+        return rc;
     }
     *hp = c;
     return TMG_OK;
+}
+
+int tmg_solve_noalloc(int64_t n_slabs, double T, double lambda, const tmg_options *opt,
+                      const double *f, const double *u0, double *u, double rtol, int max_cycles,
+                      int *cycles, double *relres, tmg_stream stream)
+{
+    if (!opt || !f || !u0 || !u || !(rtol >= 0.0) || max_cycles < 0) return TMG_ERR_INVALID;
+    std::vector<int> L;
+    int rc = check_problem(1, &n_slabs, &T, &lambda, *opt, &L);
+    if (rc) return rc;
+    if (n_slabs * (opt->p + 1) > kNoAllocMaxUnknowns) return TMG_ERR_SIZE;
+    void *base = nullptr;
+    size_t bytes = 0;
+    const hipError_t e = noalloc_scratch(&base, &bytes);
+    if (e != hipSuccess) return TMG_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    tmg_ctx c;
+    c.arena = static_cast<char *>(base);
+    c.arena_cap = bytes;
+    // the scratch keeps the previous call's contents: the set-up clears the
+    // state it reads, and no kernel reads a buffer before a launch of the
+    // same solve has written it
+    rc = build_ctx(&c, 1, &n_slabs, &T, &lambda, *opt, L, s);
+    if (!rc) rc = run_solve(&c, f, u0, u, false, rtol, max_cycles, cycles, relres, s);
+    if (rc < 0) (void)hipStreamSynchronize(s);   // nothing queued may outlive the call
+    free_all(&c);
+    return rc;
 }
 
 int tmg_destroy(tmg_handle h)

@@ -33,6 +33,14 @@ constexpr int bottom_threads(int P) { return P >= 5 ? kBottomThreads / 2 : kBott
 constexpr int bottom_max(int P) { return bottom_threads(P) * bottom_slabs(P); }
 constexpr int kBottomMaxLevels = 13;
 
+// The entry point that allocates nothing (tmg_solve_noalloc) carves every
+// device buffer of its solve out of one static device array of this size,
+// and takes single instances of at most kNoAllocMaxUnknowns coefficients
+// (about 32 bytes of hierarchy, halo and list memory per coefficient, plus
+// tables and tile lists).
+constexpr size_t kNoAllocScratchBytes = size_t(96) << 20;
+constexpr int64_t kNoAllocMaxUnknowns = int64_t(1) << 21;
+
 // Per-(instance, level) table block, doubles, for P coefficients per slab.
 // Aop is the diagonal block of the operator (A = K + lambda M, or A^T for the
 // transposed system); c the end-value functional (w = c^T u), v the
@@ -281,6 +289,10 @@ hipError_t launch_publish(const InstState *st, int batch, const Control *ctl, Ho
 // out[2j] = -sum_n z_n^T M_tau u_n, out[2j+1] = v^T z_1 (tau[j]: fine slab length).
 hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,
                        const int64_t *slab_off, int batch, double *out, hipStream_t s);
+
+// Device address of the static scratch array on the current device (looked
+// up once per device), and its size in bytes.
+hipError_t noalloc_scratch(void **ptr, size_t *bytes);
 
 // Host table builder (tmg_tables.cpp).  Fills one table block for a slab of
 // step z = lambda*tau (operator K + z diag(1/(2k+1))), transposed if trans.

@@ -31,6 +31,8 @@
 // swapped in the tables passed by the host.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tmg_internal.h"
 
 namespace tmg {
@@ -2119,6 +2121,35 @@ hipError_t launch_publish(const InstState *st, int batch, const Control *ctl, Ho
 {
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(kFinThreads), 0, s, st, batch, ctl, mirror, count);
     return hipGetLastError();
+}
+
+// ---- the static scratch of the entry point that allocates nothing --------
+// One array per device, held from the library's load to the end of the
+// process.  Host code never names it in a launch or copy: its device
+// address, looked up once per device with that device current, is what
+// the driver hands out (the name itself is a host-side stand-in).
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr, size_t *bytes)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kNoAllocScratchBytes;
+    return hipSuccess;
 }
 
 hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,

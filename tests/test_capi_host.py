@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_error_strings():
     b = _lib()
-    for code in [0, 1, -1, -2, -3, -4, -5, -6, -7, -8, -9]:
+    for code in [0, 1, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10]:
         assert b.error_string(code)
     assert "unknown" in b.error_string(12345)
 
@@ -73,6 +73,31 @@ def test_null_arguments():
     assert L.tmg_destroy(None) == -1
     assert L.tmg_level_size(None, 0) == -1
     assert L.tmg_set_active_set(None, 1) == -1
+    o = b.Options.make(p=1)
+    assert L.tmg_solve_noalloc(1024, 1.0, 1.0, None, None, None, None, 1e-10, 10, None, None,
+                               None) == -1
+    assert L.tmg_solve_noalloc(1024, 1.0, 1.0, ctypes.byref(o), None, None, None, 1e-10, 10,
+                               None, None, None) == -1
+
+
+@pytest.mark.parametrize("n,p,kw,code", [
+    (1 << 21, 1, {}, -2),            # N * P = 2^22, above the no-alloc limit of 2^21
+    (1 << 19, 3, {}, -2),
+    (1000, 1, {}, -2),               # not n_coarse * 2^k
+    (1024, 1, dict(gamma=3), -1),
+    (1024, 1, dict(omega_mode=1, omega=2.0), -3),
+])
+def test_noalloc_rejects_before_device_work(n, p, kw, code):
+    """tmg_solve_noalloc checks its arguments and the size limit on the host
+    before it touches a device (the pointers are never dereferenced)."""
+    b = _lib()
+    o = b.Options.make(p=p, **kw)
+    fake = ctypes.c_void_p(256)
+    if (n, p) == (1 << 19, 3):
+        n = (1 << 19) + (1 << 18)   # 3 * 2^18 slabs: N * P above 2^21, n_coarse 3 * 2^k
+        o.n_coarse = 3
+    assert b.lib().tmg_solve_noalloc(n, 1.0, 1.0, ctypes.byref(o), fake, fake, fake, 1e-10, 10,
+                                     None, None, None) == code
 
 
 def test_bench_refuses_more_than_one_gpu():
