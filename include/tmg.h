@@ -186,6 +186,20 @@ int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int span, int 
                      int direct, tmg_stream s);
 
 /*
+ * New decay rates for the instances of h: lambda is a DEVICE array of length
+ * batch (e.g. a learnable parameter).  The per-level tables (section 2.1
+ * matrices with z = lambda tau, alpha and the damping of Lemma
+ * chap4_lemma7, as tmg_setup builds them, to the same bits) are rebuilt by a
+ * kernel on stream s, so nothing is read back to the host and no buffer,
+ * schedule or graph is rebuilt.  Later calls on h see the new tables in
+ * stream order (work on another stream must be ordered after s by the
+ * caller).  A lambda that is not finite and positive leaves non-finite
+ * tables: the next solve then returns TMG_ERR_NONFINITE.  Returns
+ * TMG_ERR_INVALID for a null handle or array.
+ */
+int tmg_set_lambda(tmg_handle h, const double *lambda, tmg_stream s);
+
+/*
  * Active sets of a batch (on by default; a single instance has none).  Once
  * the running instances of a batch hold at most three quarters of its
  * level-0 tiles, the later cycles of a solve launch work-groups for their
@@ -300,6 +314,27 @@ int tmg_op_fused(tmg_handle h, int trans, const double *f, const double *fold_u0
 int tmg_op_fused2(tmg_handle h, int trans, const double *f, const double *fold_u0,
                   const double *u_in, const double *f1, const double *e2, double *u_out,
                   double *rc, double *f2, tmg_stream s);
+
+/*
+ * The reduced-precision kernels of the FP32-inner defect correction
+ * (precision = 1 handles only; TMG_ERR_UNSUPPORTED otherwise), for
+ * verification against FP64: the down and up legs of tmg_op_down /
+ * tmg_op_up with float arrays (FP32 storage and sweeps, the residual in
+ * FP64 arithmetic from the FP32 operands, FP32 transfers), and the level-0
+ * pass of an outer iteration (k_mix): r = f - L u_in in FP64, rounded to
+ * FP32; the inner up leg on L e = r (nu1 sweeps from zero, the correction
+ * P e with e in level 1's layout, nu2 sweeps, FP32); u_out = u_in + e_inner
+ * in FP64; then the next inner down leg from u_out (r' = f - L u_out in FP64
+ * rounded to FP32, nu1 FP32 sweeps from zero, inner residual in FP64
+ * arithmetic, FP32 restriction) into rc (level 1's layout).  u_in and u_out
+ * must not overlap.  fold_u0 as for tmg_op_down (level 0, forward).
+ */
+int tmg_op_down32(tmg_handle h, int level, int trans, int nsweep, const float *f,
+                  const float *u_in, float *u_out, float *rc, tmg_stream s);
+int tmg_op_up32(tmg_handle h, int level, int trans, int nsweep, const float *f,
+                const float *u_in, const float *e, float *u_out, tmg_stream s);
+int tmg_op_mix(tmg_handle h, int trans, const double *f, const double *fold_u0,
+               const double *u_in, const float *e, double *u_out, float *rc, tmg_stream s);
 
 /* Exact solve L_level e = r on every instance by the parallel affine prefix
  * scan (forward in time; backward for trans = 1).  Requires

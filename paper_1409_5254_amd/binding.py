@@ -30,7 +30,8 @@ SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_a
            "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
            "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
            "tmg_op_coarse_solve",
-           "tmg_op_residual_norm", "tmg_solve_noalloc"]
+           "tmg_op_residual_norm", "tmg_solve_noalloc", "tmg_op_down32", "tmg_op_up32",
+           "tmg_op_mix", "tmg_set_lambda"]
 
 
 class TmgError(RuntimeError):
@@ -83,6 +84,7 @@ def lib():
             "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), P(_i), P(_i), P(_i), _vp]),
             "tmg_set_schedule": (_i, [_vp, _i64, _i, _i, _i, _i, _vp]),
             "tmg_set_active_set": (_i, [_vp, _i]),
+            "tmg_set_lambda": (_i, [_vp, _vp, _vp]),
             "tmg_destroy": (_i, [_vp]),
             "tmg_error_string": (ctypes.c_char_p, [_i]),
             "tmg_last_hip_error": (_i, [_vp]),
@@ -94,6 +96,9 @@ def lib():
             "tmg_op_fused2": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_coarse_solve": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
             "tmg_op_residual_norm": (_i, [_vp, _i, _vp, _vp, _vp, P(_d), _vp]),
+            "tmg_op_down32": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_op_up32": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_op_mix": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "tmg_solve_noalloc": (_i, [_i64, _d, _d, _vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d),
                                        _vp]),
         }
@@ -114,6 +119,14 @@ def _ptr(t):
         return None
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr32(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 tensor on the GPU")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -221,6 +234,13 @@ class Solver:
                                            int(span_after), int(bool(direct)), _stream()),
                     "tmg_set_schedule")
 
+    def set_lambda(self, lam):
+        """New decay rates from a float64 device tensor of length batch; the
+        tables are rebuilt on the GPU in stream order (no host read-back)."""
+        if lam.numel() != self.batch:
+            raise ValueError("lambda needs one value per instance")
+        self._check(lib().tmg_set_lambda(self._h, _ptr(lam), _stream()), "tmg_set_lambda")
+
     def set_active_set(self, on):
         """Later cycles of a batch on the running instances' tiles only
         (on by default; the results are bitwise the same either way)."""
@@ -277,6 +297,25 @@ class Solver:
         r = lib().tmg_op_fused2(self._h, int(trans), _ptr(f), _ptr(fold_u0), _ptr(u_in), _ptr(f1),
                                 _ptr(e2), _ptr(u_out), _ptr(rc), _ptr(f2), _stream())
         self._check(r, "tmg_op_fused2")
+
+    def down32(self, level, f, u_in=None, u_out=None, rc=None, nsweep=2, trans=False):
+        """FP32 down leg (precision = 1 handles); float32 tensors."""
+        r = lib().tmg_op_down32(self._h, level, int(trans), nsweep, _ptr32(f), _ptr32(u_in),
+                                _ptr32(u_out), _ptr32(rc), _stream())
+        self._check(r, "tmg_op_down32")
+
+    def up32(self, level, f, u_in, e=None, u_out=None, nsweep=2, trans=False):
+        """FP32 up leg (precision = 1 handles); float32 tensors."""
+        r = lib().tmg_op_up32(self._h, level, int(trans), nsweep, _ptr32(f), _ptr32(u_in),
+                              _ptr32(e), _ptr32(u_out), _stream())
+        self._check(r, "tmg_op_up32")
+
+    def mix(self, f, u_in, e, u_out, rc, trans=False, fold_u0=None):
+        """Level-0 pass of an FP32-inner outer iteration: f, u_in, u_out float64,
+        e and rc float32 (level 1's layout)."""
+        r = lib().tmg_op_mix(self._h, int(trans), _ptr(f), _ptr(fold_u0), _ptr(u_in), _ptr32(e),
+                             _ptr(u_out), _ptr32(rc), _stream())
+        self._check(r, "tmg_op_mix")
 
     def coarse_solve(self, level, r, e, trans=False):
         rc = lib().tmg_op_coarse_solve(self._h, level, int(trans), _ptr(r), _ptr(e), _stream())

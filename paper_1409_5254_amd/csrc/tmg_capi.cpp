@@ -38,6 +38,7 @@
 
 #include "../../include/tmg.h"
 #include "tmg_internal.h"
+#include "tmg_tables.h"
 
 using namespace tmg;
 
@@ -180,6 +181,9 @@ struct tmg_ctx {
     double *partial = nullptr;
     int64_t partial_cap = 0;
     double *tau_d = nullptr, *grad_d = nullptr, *grad_host = nullptr;
+    double *T_d = nullptr;                        // [batch] T_j and N_j: tables built on the
+    int64_t *N_d = nullptr;                       // device (tmg_set_lambda)
+    bool lam_device = false;                      // lambda last set from a device array
     std::map<std::tuple<int, int, int>, TileList> tiles;
     std::map<int, std::pair<int *, int>> op_coarse;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -1789,7 +1793,7 @@ int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
     for (int l = 0; l < Lm; ++l)
         for (int j = 0; j < batch; ++j) {
             if (l >= L[j]) continue;
-            double z = lambda[j] * T[j] / (double)(c->N[j] >> l);
+            const double z = level_z(lambda[j], T[j], c->N[j], l);
             size_t at = ((size_t)l * batch + j) * c->tab_stride;
             build_level_table(P, z, o.omega_mode, o.omega, false, &tf[at]);
             build_level_table(P, z, o.omega_mode, o.omega, true, &ta[at]);
@@ -1809,7 +1813,8 @@ int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
         (rc = dalloc(c, &c->R_fwd, Rf.size())) || (rc = dalloc(c, &c->R_adj, Ra.size())) ||
         (rc = dalloc(c, &c->st, batch)) || (rc = dalloc(c, &c->st_ops, batch)) ||
         (rc = dalloc(c, &c->ctl, 1)) || (rc = dalloc(c, &c->tau_d, batch)) ||
-        (rc = dalloc(c, &c->grad_d, 2 * batch)) || (rc = dalloc(c, &c->nlev_d, batch)))
+        (rc = dalloc(c, &c->grad_d, 2 * batch)) || (rc = dalloc(c, &c->nlev_d, batch)) ||
+        (rc = dalloc(c, &c->T_d, batch)) || (rc = dalloc(c, &c->N_d, batch)))
         return rc;
     // partial sums: one slot per level-0 tile at the smallest tile size in use
     c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
@@ -1840,6 +1845,8 @@ int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
         hipMemcpyAsync(c->R_fwd, Rf.data(), Rf.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->R_adj, Ra.data(), Ra.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->tau_d, tau.data(), tau.size() * 8, hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(c->T_d, T, sizeof(double) * batch, hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(c->N_d, n_slabs, sizeof(int64_t) * batch, hipMemcpyHostToDevice, s) ||
         hipMemcpyAsync(c->nlev_d, nlev.data(), nlev.size() * sizeof(int), hipMemcpyHostToDevice,
                        s) ||
         hipMemsetAsync(c->st, 0, sizeof(InstState) * batch, s) || hipStreamSynchronize(s))
@@ -1947,7 +1954,11 @@ int tmg_adjoint_solve(tmg_handle c, const double *g, const double *u, double *z,
     int st = run_solve(c, g, nullptr, z, true, rtol, max_cycles, cycles, relres, s);
     if (st < 0) return st;
     if (u && (dlambda || du0)) {
-        HIPCHK(c, launch_grad(c->P, u, z, c->tau_d, c->slab_off_d[0], c->batch, c->grad_d, s));
+        TileList *tl;
+        const int rc = get_tiles(c, 0, kAll, tile_slabs(c->P), s, &tl);
+        if (rc) return rc;
+        HIPCHK(c, launch_grad(c->P, u, z, c->tau_d, c->slab_off_d[0], tl->d_off, tl->d_inst,
+                              tl->ntiles, c->batch, c->partial, c->grad_d, s));
         HIPCHK(c, hipMemcpyAsync(c->grad_host, c->grad_d, sizeof(double) * 2 * c->batch,
                                  hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
@@ -2090,6 +2101,19 @@ int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int span, int 
     return TMG_OK;
 }
 
+int tmg_set_lambda(tmg_handle c, const double *lambda, tmg_stream stream)
+{
+    if (!c || !lambda) return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    // cycles a solve left queued past convergence still read the tables
+    if (c->drain_pending) HIPCHK(c, hipStreamWaitEvent(s, c->drain_ev, 0));
+    HIPCHK(c, launch_set_tables(c->P, lambda, c->T_d, c->N_d, c->nlev_d, c->batch, c->Lmax,
+                                c->opt.omega_mode, c->opt.omega, c->tab_stride, c->tab_fwd,
+                                c->tab_adj, c->tab32_fwd, c->tab32_adj, s));
+    c->lam_device = true;
+    return TMG_OK;
+}
+
 int tmg_set_active_set(tmg_handle c, int on)
 {
     if (!c) return TMG_ERR_INVALID;
@@ -2101,10 +2125,19 @@ int tmg_level_info(tmg_handle c, int j, int level, int64_t *n, double *alpha, do
 {
     if (!c || j < 0 || j >= c->batch) return TMG_ERR_INVALID;
     if (level < 0 || level >= c->L[j]) return TMG_ERR_INVALID;
-    double z = c->lam[j] * c->T[j] / (double)(c->N[j] >> level);
     std::vector<double> t(c->tab_stride);
-    double a = build_level_table(c->P, z, c->opt.omega_mode, c->opt.omega, false, t.data());
+    double a;
     const TabLayout TL(c->P);
+    if (c->lam_device) {
+        // lambda came from a device array: read the table the device built
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipMemcpy(t.data(), tab_of(c, level, false) + (int64_t)j * c->tab_stride,
+                            sizeof(double) * c->tab_stride, hipMemcpyDeviceToHost));
+        a = t[TL.ALPHA()];
+    } else {
+        const double z = level_z(c->lam[j], c->T[j], c->N[j], level);
+        a = build_level_table(c->P, z, c->opt.omega_mode, c->opt.omega, false, t.data());
+    }
     if (n) *n = c->N[j] >> level;
     if (alpha) *alpha = a;
     if (omega) *omega = 1.0 - t[TL.OMC()];
@@ -2162,6 +2195,89 @@ int tmg_op_up(tmg_handle c, int level, int trans, int nsweep, const double *f,
     a.u_out = u_out;
     a.post = nsweep;
     HIPCHK(c, launch_leg<double>(c->P, trans != 0, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+int tmg_op_down32(tmg_handle c, int level, int trans, int nsweep, const float *f,
+                  const float *u_in, float *u_out, float *rcout, tmg_stream stream)
+{
+    int rc = check_level_args(c, level);
+    if (rc) return rc;
+    if (!c->mixed) return TMG_ERR_UNSUPPORTED;
+    if (!f || nsweep < 0 || nsweep > kMaxSweeps || (rcout && level + 1 >= c->Lmax))
+        return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const int H = c->rs(nsweep + 1);
+    TileList *tl;
+    if ((rc = get_tiles(c, level, rcout ? kHasNext : kAll, c->TO(H), s, &tl))) return rc;
+    LegArgsT<float> a = leg_args<float>(c, level, trans != 0, tl, H);
+    a.f = f;
+    a.u_in = u_in;
+    a.u_out = u_out;
+    a.rc = rcout;
+    a.pre = nsweep;
+    HIPCHK(c, launch_leg<float>(c->P, trans != 0, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+int tmg_op_up32(tmg_handle c, int level, int trans, int nsweep, const float *f,
+                const float *u_in, const float *e, float *u_out, tmg_stream stream)
+{
+    int rc = check_level_args(c, level);
+    if (rc) return rc;
+    if (!c->mixed) return TMG_ERR_UNSUPPORTED;
+    if (!f || !u_in || nsweep < 0 || nsweep > kMaxSweeps || (e && level + 1 >= c->Lmax))
+        return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const int H = c->rs(nsweep);
+    TileList *tl;
+    if ((rc = get_tiles(c, level, e ? kHasNext : kAll, c->TO(H), s, &tl))) return rc;
+    LegArgsT<float> a = leg_args<float>(c, level, trans != 0, tl, H);
+    a.f = f;
+    a.u_in = u_in;
+    a.e = e;
+    a.u_out = u_out;
+    a.post = nsweep;
+    HIPCHK(c, launch_leg<float>(c->P, trans != 0, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+int tmg_op_mix(tmg_handle c, int trans, const double *f, const double *fold_u0,
+               const double *u_in, const float *e, double *u_out, float *rcout,
+               tmg_stream stream)
+{
+    if (!c || !f || !u_in || !e || !u_out || !rcout || c->Lmax < 2 || (fold_u0 && trans))
+        return TMG_ERR_INVALID;
+    if (!c->mixed) return TMG_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int H = c->H_mix();
+    TileList *tl;
+    int rc = get_tiles(c, 0, kHasNext, c->TO(H), s, &tl);
+    if (rc) return rc;
+    MixArgs a{};
+    a.f = f;
+    a.u0 = fold_u0;
+    a.u_in = u_in;
+    a.e = e;
+    a.u_out = u_out;
+    a.rc = rcout;
+    a.tab = tab_of(c, 0, trans != 0);
+    a.tab32 = tabT_of<float>(c, 0, trans != 0);
+    a.R32 = R_of<float>(c, trans != 0);
+    a.slab_off = c->slab_off_d[0];
+    a.cslab_off = c->slab_off_d[1];
+    a.tile_off = tl->d_off;
+    a.tile_inst = tl->d_inst;
+    a.n0 = c->N[0];
+    a.batch = c->batch;
+    a.tab_stride = c->tab_stride;
+    a.halo = H;
+    a.tile_out = c->TO(H);
+    a.pre = c->opt.nu1;
+    a.post = c->opt.nu2;
+    a.next = c->opt.nu1;
+    a.up = 1;
+    HIPCHK(c, launch_mix(c->P, trans != 0, a, tl->ntiles, s));
     return TMG_OK;
 }
 

@@ -286,9 +286,17 @@ hipError_t launch_finalize(const double *partial, const int64_t *norm_off, int b
 // made so far).
 hipError_t launch_publish(const InstState *st, int batch, const Control *ctl, HostHead *mirror,
                           unsigned *count, hipStream_t s);
-// out[2j] = -sum_n z_n^T M_tau u_n, out[2j+1] = v^T z_1 (tau[j]: fine slab length).
+// out[2j] = -sum_n z_n^T M_tau u_n, out[2j+1] = v^T z_1 (tau[j]: fine slab length),
+// over a level-0 tile list of kLegThreads * S slabs per tile (partial: one
+// slot per tile).
 hipError_t launch_grad(int P, const double *u, const double *z, const double *tau,
-                       const int64_t *slab_off, int batch, double *out, hipStream_t s);
+                       const int64_t *slab_off, const int64_t *tile_off, const int *tile_inst,
+                       int64_t ntiles, int batch, double *partial, double *out, hipStream_t s);
+// Rebuilds the table blocks of every level and instance from lambda (device).
+hipError_t launch_set_tables(int P, const double *lam, const double *T, const int64_t *N,
+                             const int *nlev, int batch, int Lmax, int omega_mode, double omega,
+                             int stride, double *tab_fwd, double *tab_adj, float *t32f,
+                             float *t32a, hipStream_t s);
 
 // Device address of the static scratch array on the current device (looked
 // up once per device), and its size in bytes.

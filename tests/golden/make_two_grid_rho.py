@@ -15,7 +15,10 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle import analysis as an  # noqa: E402
 
 N = 1024
-CASES = [(p, z, nu) for p in range(6) for z in (1e-3, 1.0, 40.0) for nu in (1, 2, 5)]
+# the grid of the section 4.2 figures: tau = z in 10^-6 .. 10^6 (13 points),
+# p = 0..5, nu1 = nu2 in {1, 2, 5}
+ZS = [10.0 ** e for e in range(-6, 7)]
+CASES = [(p, z, nu) for p in range(6) for z in ZS for nu in (1, 2, 5)]
 
 
 def main():

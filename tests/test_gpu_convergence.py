@@ -1,12 +1,17 @@
-"""GPU replay of the section 4.2 convergence study: the two-grid cycle (the
-coarse level N/2 solved exactly by the scan) on u' + u = 0 with N = 1024
-slabs of width tau = z, from a seeded random start in [0, 1], for p = 0..5,
-z in {1e-3, 1, 40} and nu1 = nu2 in {1, 2, 5}.  The first cycles are the
-oracle's to 1e-12 of the start; the measured asymptotic contraction (tail
-geometric mean of the residual ratios) agrees with the Fourier estimate of
-Theorem chap4_theorem4 (tests/golden/two_grid_rho.json, written from the
-oracle) within -10%/+2%.  Where the residual underflows to zero (large z,
-nu >= 2: block Jacobi is then nearly exact), the GPU must reach that too."""
+"""GPU replay of the section 4.2 convergence study over the grid of its
+figures: the two-grid cycle (the coarse level N/2 solved exactly by the
+scan) on u' + u = 0 with N = 1024 slabs of width tau = z, from a seeded
+random start in [0, 1], for p = 0..5, z = 10^-6 .. 10^6 (13 points) and
+nu1 = nu2 in {1, 2, 5}.  The first cycles are the oracle's to 1e-12 of the
+start; the measured asymptotic contraction (tail geometric mean of the
+residual ratios over the second half of up to 40 cycles) lies under the
+Fourier estimate of Theorem chap4_theorem4 (tests/golden/two_grid_rho.json,
+written from the oracle) and above 0.9 of it.  The only allowance above the
+estimate is a finite-window bias of 1e-5 relative: the last residual ratios
+oscillate about the estimate by up to 1e-5 (p = 2, z = 1e-3, nu = 1), and
+their geometric mean exceeds it by at most 6e-7 in the oracle's own replay
+of the same grid.  Where the residual underflows (large z: block Jacobi is
+then nearly exact), the estimate must be tiny as well."""
 import json
 import os
 
@@ -55,7 +60,7 @@ def test_two_grid_contraction(p, z, nu, rho):
     if r[-1] > 1e-200 * r[0]:
         assert K >= 8
         tail = (r[K] / r[K // 2]) ** (1.0 / (K - K // 2))
-        assert 0.9 * rho <= tail <= 1.02 * rho, (tail, rho)
+        assert 0.9 * rho <= tail <= (1.0 + 1e-5) * rho, (tail, rho)
     else:
         # reached the underflow floor: the estimate must be tiny as well
         assert rho < 1e-4 or K >= 8, (K, rho)

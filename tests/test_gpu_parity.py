@@ -47,6 +47,16 @@ def relerr(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+def relerr_residual(a, b, rhs):
+    """Error of a computed (restricted) residual, relative to the larger of
+    its own max-norm and the right-hand side's: r = f - L u is a difference
+    of terms of the size of f, and where the sweeps nearly solve the slabs
+    (z of 1e3 and more) r is orders of magnitude below them, so that any
+    rounding in the terms stands out against r alone."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), np.max(np.abs(rhs)), 1e-300))
+
+
 def rand(rng, n):
     return rng.standard_normal(n)
 
@@ -56,7 +66,7 @@ def rand(rng, n):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("z", [1e-3, 1.0, 40.0])
+@pytest.mark.parametrize("z", [1e-3, 1.0, 40.0, 1e3, 4e3])
 @pytest.mark.parametrize("nsweep", [0, 1, 2, 3])
 def test_down_kernel(p, z, nsweep):
     """k_down: nsweep damped block Jacobi sweeps (eq. chap4_ODESmoother), the
@@ -76,7 +86,7 @@ def test_down_kernel(p, z, nsweep):
     d_rc = torch.empty(N // 2 * P, dtype=torch.float64, device=DEV)
     s.down(0, dev(f), dev(u), d_out, d_rc, nsweep=nsweep, fold_u0=dev([u0]))
     assert relerr(host(d_out), ref_u) <= TOL
-    assert relerr(host(d_rc), ref_rc) <= TOL
+    assert relerr_residual(host(d_rc), ref_rc, ff) <= TOL
     # zero initial guess
     ref0 = core.sweeps(p, z, 1.0, ff, np.zeros(N * P), nsweep)
     s.down(0, dev(f), None, d_out, None, nsweep=nsweep, fold_u0=dev([u0]))
@@ -86,10 +96,12 @@ def test_down_kernel(p, z, nsweep):
 
 @pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("nsweep", [0, 2, 5])
-def test_up_kernel(p, nsweep):
-    """k_up: prolongation + correction (eq. chap4_prolongationTime) then sweeps."""
+@pytest.mark.parametrize("z", [0.3, 1e3, 4e3])
+def test_up_kernel(p, nsweep, z):
+    """k_up: prolongation + correction (eq. chap4_prolongationTime) then sweeps;
+    z up to the stiffest slabs of the eigenmode batch (alpha ~ -2/z, omega = 1)."""
     rng = np.random.default_rng(7 + p)
-    N, z = 2048 + 0, 0.3
+    N = 2048
     s = B().Solver([N], [z * N], [1.0], p=p)
     P = p + 1
     f, u, e = rand(rng, N * P), rand(rng, N * P), rand(rng, N // 2 * P)
@@ -172,6 +184,26 @@ def test_cycles_match_oracle(p, gamma, schedule):
     rng = np.random.default_rng(40 + p)
     N, T, lam, u0 = 4096, 10.0, 1.3, 0.5
     s = B().Solver([N], [T], [lam], p=p, gamma=gamma, schedule=schedule)
+    P = p + 1
+    f, u = rand(rng, N * P), rand(rng, N * P)
+    du = dev(u)
+    for _ in range(3):
+        s.vcycle(dev(f), dev([u0]), du)
+    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, core.Opts(gamma=gamma))
+    assert relerr(host(du), ref) <= TOL
+
+
+@pytest.mark.parametrize("p", [0, 1, 3, 5])
+@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("z", [1e3, 4e3])
+def test_cycles_stiff(p, gamma, z):
+    """Cycles at the stiff end of the eigenmode batch: the fine-level slab
+    step z = lambda tau of 1e3 and 4e3 (alpha about -2/z, so omega* = 1 on
+    every level), three cycles from a random start against the oracle."""
+    rng = np.random.default_rng(int(z) + p)
+    N, lam, u0 = 4096, 1.0, 0.5
+    T = z * N / lam
+    s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
     P = p + 1
     f, u = rand(rng, N * P), rand(rng, N * P)
     du = dev(u)
@@ -286,9 +318,15 @@ def test_adjoint_solve_and_gradients(p, schedule):
     zo, k, _, _ = core.solve_folded(p, T, lam, g, rtol=1e-12, trans=True)
     assert st == 0 and cyc[0] == k
     assert relerr(host(z), zo) <= TOL
-    dlo, du0o = core.gradients(p, T / N, lam, u, zo)
-    assert dl[0] == pytest.approx(dlo, rel=1e-11)
-    assert du0[0] == pytest.approx(du0o, rel=1e-11)
+    # gradients of the GPU's z (which equals the oracle's to 1e-12 above):
+    # dlambda is a sum of N P products in another order, so its bar is the
+    # summation bound 1e-12 |dl| + 16 eps tau sum |z_n M u_n|; du0 = v^T z_1
+    zh = host(z)
+    dlo, du0o = core.gradients(p, T / N, lam, u, zh)
+    w = np.tile(1.0 / (2.0 * np.arange(p + 1) + 1.0), N)
+    bound = 1e-12 * abs(dlo) + 16 * np.finfo(float).eps * (T / N) * np.sum(np.abs(zh * u * w))
+    assert abs(dl[0] - dlo) <= bound
+    assert du0[0] == pytest.approx(du0o, rel=1e-12)
 
 
 # ---------------------------------------------------------------------------

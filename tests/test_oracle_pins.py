@@ -337,7 +337,9 @@ def test_symbol_matches_dense_periodic_two_grid(p):
 def test_measured_two_grid_contraction(p, z, nu):
     """Section 4.2 experiment: N = 1024 slabs, f = 0, random start in [0, 1];
     the measured asymptotic residual contraction of the oracle's two-grid cycle
-    (tail geometric mean) agrees with the Fourier estimate (within -10%/+2%)."""
+    (tail geometric mean) lies under the Fourier estimate, up to a
+    finite-window bias of 1e-5 relative (the last ratios oscillate about the
+    estimate by up to that much), and above 0.9 of it."""
     N = 1024
     rng = np.random.default_rng(100 + p)
     opts = core.Opts(nu1=nu, nu2=nu, gamma=1, n_coarse=N // 2)
@@ -351,7 +353,7 @@ def test_measured_two_grid_contraction(p, z, nu):
     assert K >= 8
     tail = (r[K] / r[K // 2]) ** (1.0 / (K - K // 2))
     est = an.two_grid_rho(p, z, nu, nu, N=N)
-    assert 0.9 * est <= tail <= 1.02 * est
+    assert 0.9 * est <= tail <= (1.0 + 1e-5) * est
 
 
 # --------------------------------------------------------------------------
