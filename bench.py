@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark: DG time-unknowns solved per second to relative residual 1e-10.
 
-Default workload (one MI355X; `--workload scalar`): u' + u = f on (0, 1000],
-u0 = 1, N = 2^22 uniform slabs, DG degree p (default 3; --p), Legendre basis,
-f a seeded 16-mode random Fourier series; V(2,2) cycle (or --cycle W),
-coarsening by 2 down to 2 slabs, solved from u = 0 to ||r|| <= 1e-10 ||r_0||.
-A step is one whole solve (tmg_solve) with f, u0 and u resident in HBM.
+Default run (one MI355X): the largest single-GPU configuration, the long-
+horizon batch -- 64 instances of u' + lambda_j u = f_j on (0, 1e4],
+lambda_j ~ U(0.5, 50), u0 = 1, N = 2^24 uniform slabs each, DG degree p = 3
+(4.3e9 unknowns), f_j seeded 16-mode random Fourier series; V(2,2) cycle,
+coarsening by 2 down to 2 slabs, solved from u = 0 to ||r_j|| <= 1e-10
+||r_j,0|| for every instance.  A step is one whole batched solve (tmg_solve)
+with f, u0 and u resident in HBM.  The headline is the plain FP64 cycle;
+the FP32-inner defect correction of the same batch is reported beside it.
 
-One JSON line: the headline number, a sweep over p = 0..5, the roofline of
-the dominant kernel (the fused level-0 pass of a cycle) timed with HIP events
-on its launch stream, the FP64 CPU oracle timed on a bounded sample of the
-same workload, and the FP32-inner defect correction against the plain FP64
-cycle on the large scalar workload (N = 2^24, p = 3).
+The same JSON line carries: the roofline of the dominant kernel (the fused
+level-0 pass of a cycle) on instances of this batch, timed with HIP events
+on its launch stream; the scalar workload at N = 2^22, p = 0..5 with the
+V-cycle and p = 3 with the W-cycle; the 4096-instance eigenmode batch; the
+256-instance adjoint batch (forward solve, adjoint solve and gradients);
+and the FP64 CPU oracle timed on bounded samples of the headline workload
+(direct forward substitution and the reference multigrid solve, on one core
+and on all cores of the host).
 
 Other workloads (`--workload`):
+  scalar      the scalar workload alone (N = 2^22, --p, --cycle);
   eigenmodes  4096 eigenmode instances of uneven length (batched, one handle);
   adjoint     256 instances, N = 2^20, p = 2: forward solve + adjoint solve +
               gradients (the backward pass of the autograd function);
@@ -28,7 +35,9 @@ Other workloads (`--workload`):
               N = 1024 as in the paper, tau = z in 10^-6 .. 10^6, p = 0..5,
               nu = 1, 2, 5:
               the measured asymptotic contraction per case and the time per
-              cycle.
+              cycle;
+  roofline    only the roofline measurement of the default run (for
+              profiler runs).
 """
 from __future__ import annotations
 
@@ -58,9 +67,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scalar",
-                    choices=["scalar", "eigenmodes", "adjoint", "long", "highdeg",
-                             "convergence"])
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "scalar", "eigenmodes", "adjoint", "long", "highdeg",
+                             "convergence", "roofline"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -70,11 +79,22 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick each handle's schedule with tmg_autotune before timing (1) or not")
-    ap.add_argument("--cpu-log2n", type=int, default=21)
+    ap.add_argument("--cpu-log2n", type=int, default=20,
+                    help="slabs (log2) of the oracle multigrid sample")
+    ap.add_argument("--roof-batch", type=int, default=16,
+                    help="instances of the long-horizon batch in the roofline launch")
     ap.add_argument("--batch", type=int, default=0, help="instances of the batched workloads (0: default)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
+
+
+T_START = time.perf_counter()
+
+
+def log(msg):
+    """One progress line on stderr per finished step of the run."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def sync():
@@ -161,25 +181,45 @@ def fused_pass_roofline(p, ctx, reps):
 
 
 COUNTERS = os.path.join(HERE, "profiles", "k_leg_fused2_p3_n2e22_hbm_counters.md")
-KERNEL_SRC = os.path.join(HERE, "paper_1409_5254_amd", "csrc", "tmg_kernels.hip")
+COUNTERS_LONG = os.path.join(HERE, "profiles", "k_leg_fused2_long_b16_hbm_counters.md")
+# the dominant kernel's source: the kernel templates and the FP64 leg instantiations
+KERNEL_SRCS = [os.path.join(HERE, "paper_1409_5254_amd", "csrc", n)
+               for n in ("tmg_kernels.h", "tmg_leg64.hip")]
 
 
-def measured_traffic(p, log2n):
-    """HBM bytes per launch of the dominant kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary (p = 3, N = 2^22 only), or None when the
-    kernel source changed since the counters were taken."""
+def kernel_source_sha():
     import hashlib
-    if (p, log2n) != (3, 22) or not os.path.exists(COUNTERS):
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def counters_traffic(path):
+    """HBM bytes per launch of the dominant kernel from a committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source changed
+    since the counters were taken (or there is no summary)."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line:
             k, v = line.strip().split(":", 1)
             vals[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256") != kernel_source_sha() or \
+            "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def measured_traffic(p, log2n):
+    """Counter traffic of the scalar workload's launch (p = 3, N = 2^22 only)."""
+    return counters_traffic(COUNTERS) if (p, log2n) == (3, 22) else None
+
+
+def measured_traffic_long(nb):
+    """Counter traffic of the long-horizon batch's roofline launch (16 instances)."""
+    return counters_traffic(COUNTERS_LONG) if nb == 16 else None
 
 
 def cpu_baseline(p, log2n):
@@ -218,12 +258,16 @@ def long_horizon_compare(B, log2n, steps, warmup):
     lams = [q[0] for q in params]
     out = {}
     sols = {}
+    log(f"long-horizon batch of {B}: loads generated")
     for name, prec in (("fp64", 0), ("fp32_inner", 1)):
         s = Solver([N] * B, [T] * B, lams, p=p, precision=prec)
         u = torch.empty_like(f)
+        log(f"  {name}: set up")
         sched = tune(s, f, u0, u)
+        log(f"  {name}: schedule {sched}")
         dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps,
                               warmup)
+        log(f"  {name}: {dt * 1e3:.2f} ms per solve, {max(res.cycles)} cycles")
         out[name] = dict(unknowns_per_s=B * N * P / dt, ms_per_solve=dt * 1e3,
                          cycles=max(res.cycles), relres=max(res.relres), status=res.status,
                          schedule=sched)
@@ -231,7 +275,14 @@ def long_horizon_compare(B, log2n, steps, warmup):
         s.close()
         del s
         torch.cuda.empty_cache()
-    d = (sols["fp32_inner"] - sols["fp64"]).abs().max().item() / sols["fp64"].abs().max().item()
+    # max-norm difference in chunks (the batch's arrays are 32 GiB each)
+    a, b = sols["fp32_inner"], sols["fp64"]
+    dmax, bmax = 0.0, 0.0
+    for i in range(0, a.numel(), 1 << 28):
+        dmax = max(dmax, (a[i:i + (1 << 28)] - b[i:i + (1 << 28)]).abs().max().item())
+        bmax = max(bmax, b[i:i + (1 << 28)].abs().max().item())
+    d = dmax / bmax
+    del a, b, sols
     out["rel_diff_fp32_inner_vs_fp64"] = d
     out["speedup_fp32_inner"] = out["fp32_inner"]["unknowns_per_s"] / out["fp64"]["unknowns_per_s"]
     out["workload"] = (f"{B} x (u'+lam u=f, T={T:g}, N=2^{log2n}, p=3, lam ~ U(0.5,50)), "
@@ -380,6 +431,167 @@ def adjoint_run(B, steps, warmup):
                 workload=f"{B} x (N=2^20, p=2, T=100, lambda ~ U(0.1,10)), loss 1/2 sum(w_n-y_n)^2")
 
 
+# ---------------------------------------------------------------------------
+# the default run: the long-horizon batch and the fields beside it
+# ---------------------------------------------------------------------------
+
+LONG_T = 1e4
+
+
+def long_load(params, N, T, device="cuda"):
+    """Load vectors of the long-horizon batch (16-mode Fourier per instance),
+    generated on the GPU, flat [instance][slab][k]."""
+    import torch
+    from workloads import gen
+    P = 4
+    f = torch.empty(len(params) * N * P, dtype=torch.float64, device=device)
+    for j, (lam, a, phi) in enumerate(params):
+        gen.fourier_load_torch(3, N, T, a, phi, out=f[j * N * P:(j + 1) * N * P])
+    return f
+
+
+def batch_roofline(nb, log2n, reps):
+    """Average duration of the dominant kernel of the long-horizon batch's
+    FP64 solve, the fused level-0 pass that every cycle after the first runs
+    (tmg_op_fused2: level 1's up leg in the tiles, then at level 0 the
+    recomputed pre-sweeps, correction, post-sweeps, next cycle's pre-sweeps,
+    residual, restriction, and level 1's next down leg), launched over the
+    first `nb` instances of the batch and timed with HIP events on the stream
+    it is launched on.  Algorithmic bytes per unknown: read u, f (16 B),
+    level 1's right-hand side (4 B) and level 2's correction (2 B), write u
+    (8 B), level 1's next right-hand side (4 B) and level 2's (2 B) = 36 B;
+    one launch processes nb * N * P unknowns.  The solve runs the same kernel
+    over all 64 instances in place (left halos from a per-tile buffer); the
+    timed launch writes a second array."""
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    N, P = 1 << log2n, 4
+    T = LONG_T * N / (1 << 24)
+    params = gen.long_horizon_params(64)[:nb]
+    f = long_load(params, N, T)
+    u = f.clone()
+    ub = torch.empty_like(u)
+    n = nb * N * P
+    rc = torch.empty(n // 2, dtype=torch.float64, device="cuda")
+    f1 = torch.zeros(n // 2, dtype=torch.float64, device="cuda")
+    e2 = torch.zeros(n // 4, dtype=torch.float64, device="cuda")
+    f2 = torch.empty(n // 4, dtype=torch.float64, device="cuda")
+    u0 = torch.ones(nb, dtype=torch.float64, device="cuda")
+    s = Solver([N] * nb, [T] * nb, [q[0] for q in params], p=3)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        s.fused2(f, u, f1, e2, ub, rc, f2=f2, fold_u0=u0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        s.fused2(f, u, f1, e2, ub, rc, f2=f2, fold_u0=u0)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    bytes_alg = 36.0 * n
+    gbs = bytes_alg / (ms * 1e-3) / 1e9
+    s.close()
+    del f, u, ub, rc, f1, e2, f2, s
+    torch.cuda.empty_cache()
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                kernel=(f"k_leg<P=4> two-level fused level-0 pass over {nb} instances of the "
+                        f"long-horizon batch, N=2^{log2n} each"),
+                avg_us=round(ms * 1e3, 2), bytes_per_launch=bytes_alg, launches=reps)
+
+
+def cpu_baseline_long(log2n_mg, ncores=0):
+    """The FP64 oracle (plain C, never tuned) on bounded samples of the
+    headline workload, on this host's cores:
+      direct_1core : the plain definition, sequential forward substitution,
+                     on instance 0 of the batch (N = 2^24, p = 3), one core;
+      mg_1core     : the reference V(2,2) multigrid solve to 1e-10 of the
+                     first 2^log2n_mg slabs of instance 0 (same tau), one core;
+      all cores    : C independent direct solves at once, one per thread
+                     (the first 2^22 slabs of instances 0 .. C-1), C the
+                     cores this process may use (at most 16).
+    The reported value is the all-core direct throughput."""
+    import threading
+    import numpy as np
+    import torch
+    from oracle import core
+    from workloads import gen
+    p, P, N = 3, 4, 1 << 24
+    T = LONG_T
+    params = gen.long_horizon_params(64)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    C = ncores or max(1, min(avail, 16))
+    out = {}
+    # one core: direct solve of a whole instance
+    lam0 = params[0][0]
+    f0 = long_load(params[:1], N, T).cpu().numpy()
+    t0 = time.perf_counter()
+    core.direct_solve(p, T, lam0, 1.0, f0)
+    dt = time.perf_counter() - t0
+    out["direct_1core"] = dict(value=N * P / dt, seconds=dt, unknowns=N * P)
+    log(f"  oracle direct, one core, 2^24 slabs: {dt:.1f} s")
+    # one core: reference multigrid on the first 2^log2n_mg slabs
+    Nm = 1 << log2n_mg
+    t0 = time.perf_counter()
+    _, k, rr, _ = core.solve(p, T * Nm / N, lam0, 1.0, f0[:Nm * P], rtol=1e-10)
+    dt = time.perf_counter() - t0
+    out["mg_1core"] = dict(value=Nm * P / dt, seconds=dt, unknowns=Nm * P, cycles=k)
+    log(f"  oracle multigrid, one core, 2^{log2n_mg} slabs: {dt:.1f} s")
+    del f0
+    # all cores: C direct solves at once (ctypes releases the GIL in the oracle)
+    Nc = 1 << 22
+    fs = [long_load([params[j]], N, T)[:Nc * P].cpu().numpy() for j in range(C)]
+    torch.cuda.empty_cache()
+    ths = [threading.Thread(target=core.direct_solve,
+                            args=(p, T * Nc / N, params[j][0], 1.0, fs[j])) for j in range(C)]
+    t0 = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t0
+    allc = C * Nc * P / dt
+    out.update(value=allc, unit="unknowns/s", cores=C, kind="oracle",
+               sample=(f"oracle direct forward substitution, {C} threads at once, each the first "
+                       f"2^22 slabs of one instance of the long-horizon batch (p=3, tau=1e4/2^24), "
+                       f"{dt:.1f} s; also on one core: the whole instance 0 (2^24 slabs) directly "
+                       f"and the oracle V(2,2) multigrid to 1e-10 on its first 2^{log2n_mg} slabs"),
+               host_cpus=os.cpu_count(), usable_cpus=avail)
+    return out
+
+
+def w_cycle_case(p, log2n, steps, warmup):
+    """The scalar workload with the W(2,2)-cycle, levels up to the bottom
+    kernel's largest streaming, cycles after the first launched kernel by
+    kernel (a W-cycle is launch-bound: 2^(l-1) visits of level l)."""
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    import numpy as np
+    N = 1 << log2n
+    T = 1000.0 * N / (1 << 22)
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal(16)
+    phi = rng.uniform(0.0, 2.0 * math.pi, 16)
+    f = gen.fourier_load_torch(p, N, T, a, phi, device="cuda")
+    u0 = torch.tensor([1.0], dtype=torch.float64, device="cuda")
+    u = torch.empty_like(f)
+    s = Solver([N], [T], [1.0], p=p, gamma=2)
+    cap = {1: 4096, 2: 2048}.get(p + 1, 1024 if p + 1 <= 4 else 512)
+    s.set_schedule(cap, pairs=True, span=0, span_after=2, direct=True)
+    dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
+    unknowns = N * (p + 1)
+    s.close()
+    return dict(p=p, N=N, cycle="W", unknowns_per_s=unknowns / dt, ms_per_solve=dt * 1e3,
+                cycles=res.cycles[0], relres=res.relres[0], status=res.status,
+                schedule=dict(bottom_cap=cap, pairs=True, span=0, direct=True))
+
+
 def main():
     a = parse()
     global AUTOTUNE
@@ -434,38 +646,74 @@ def main():
                           "ms_per_step": rb["fp32_inner"]["ms_per_solve"],
                           "config": {"workload": rb["workload"]}, "scalar": r1, "batch": rb}))
         return
-    head, ctx = scalar_case(a.p, a.log2n, a.cycle, a.steps, a.warmup)
-    roof = fused_pass_roofline(a.p, ctx, a.kernel_reps)
-    roof["traffic"] = measured_traffic(a.p, a.log2n)
-    del ctx
+    if a.workload == "roofline":
+        print(json.dumps({"roofline": batch_roofline(a.roof_batch, 24, a.kernel_reps)}))
+        return
+    if a.workload == "scalar":
+        head, ctx = scalar_case(a.p, a.log2n, a.cycle, a.steps, a.warmup)
+        roof = fused_pass_roofline(a.p, ctx, a.kernel_reps)
+        roof["traffic"] = measured_traffic(a.p, a.log2n)
+        print(json.dumps({**base, "value": head["unknowns_per_s"],
+                          "ms_per_step": head["ms_per_solve"],
+                          "config": {"workload": f"u'+u=f, T=1000, N=2^{a.log2n} slabs, p={a.p}, "
+                                                 f"{a.cycle}(2,2) cycle to 1e-10, 16-mode Fourier f",
+                                     "cycles": head["cycles"], "relres": head["relres"],
+                                     "schedule": head["schedule"]},
+                          "roofline": roof}))
+        return
+    # default: the long-horizon batch (the largest single-GPU configuration)
+    B = a.batch or 64
+    head = long_horizon_compare(B, 24, a.steps, a.warmup)
     torch.cuda.empty_cache()
+    roof = batch_roofline(min(a.roof_batch, B), 24, a.kernel_reps)
+    roof["traffic"] = measured_traffic_long(min(a.roof_batch, B))
+    log(f"roofline: {roof['avg_us']} us per launch, {roof['frac']} of peak")
     sweep = []
     if a.sweep:
         for p in range(6):
-            if p == a.p:
-                sweep.append(head)
-                continue
-            r, c = scalar_case(p, a.log2n, a.cycle, max(2, a.steps // 2), 1)
+            r, c = scalar_case(p, 22, "V", max(2, a.steps // 2), 1)
             del c
+            torch.cuda.empty_cache()
             sweep.append(r)
-    mixed = long_horizon_compare(1, 24, max(2, a.steps // 3), 1) if a.mixed else None
-    cpu = cpu_baseline(a.p, a.cpu_log2n) if a.cpu_baseline else None
+            log(f"scalar N=2^22 p={p} V: {r['ms_per_solve']:.3f} ms, {r['cycles']} cycles")
+    # one timed solve: a W-cycle over 22 levels visits level l 2^(l-1) times
+    # per cycle (2^21 visits of the coarsest level), each a latency-bound
+    # step, so it takes seconds per cycle
+    wcyc = w_cycle_case(3, 22, 1, 0)
+    torch.cuda.empty_cache()
+    log(f"scalar N=2^22 p=3 W: {wcyc['ms_per_solve']:.3f} ms, {wcyc['cycles']} cycles")
+    eig = eigenmode_run(4096, max(3, a.steps // 2), 1)
+    torch.cuda.empty_cache()
+    log(f"eigenmode batch: {eig['ms_per_solve']:.3f} ms")
+    adj = adjoint_run(256, max(2, a.steps // 4), 1)
+    torch.cuda.empty_cache()
+    log(f"adjoint batch: {adj['ms_per_forward_backward']:.3f} ms")
+    cpu = cpu_baseline_long(a.cpu_log2n) if a.cpu_baseline else None
+    log("cpu baseline done")
+    h64, h32 = head["fp64"], head["fp32_inner"]
     out = {
         **base,
-        "value": head["unknowns_per_s"],
-        "ms_per_step": head["ms_per_solve"],
-        "config": {"workload": f"u'+u=f, T=1000, N=2^{a.log2n} slabs, p={a.p}, "
-                               f"{a.cycle}(2,2) cycle to 1e-10, 16-mode Fourier f",
-                   "cycles": head["cycles"], "relres": head["relres"],
-                   "schedule": head["schedule"]},
+        "value": h64["unknowns_per_s"],
+        "ms_per_step": h64["ms_per_solve"],
+        "config": {"workload": (f"long-horizon batch: {B} x (u'+lam_j u=f_j, T=1e4, N=2^24 "
+                                "slabs, p=3, lam_j ~ U(0.5,50), 16-mode Fourier f_j), "
+                                "V(2,2) cycle to 1e-10 per instance, FP64"),
+                   "instances": B, "unknowns": B * (1 << 24) * 4,
+                   "cycles": h64["cycles"], "relres": h64["relres"],
+                   "schedule": h64["schedule"]},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "sweep_p": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles", "schedule")}
-                    for r in sweep],
-        "fp32_inner_vs_fp64": mixed,
+        "fp32_inner_vs_fp64": {
+            "fp32_inner": h32, "speedup_fp32_inner": head["speedup_fp32_inner"],
+            "rel_diff_fp32_inner_vs_fp64": head["rel_diff_fp32_inner_vs_fp64"],
+            "fp64_steps": head["fp64_steps"]},
+        "scalar_2e22_V": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles",
+                                             "relres", "schedule")} for r in sweep],
+        "scalar_2e22_W": wcyc,
+        "eigenmodes": eig,
+        "adjoint": adj,
     }
     print(json.dumps(out))
-
 
 if __name__ == "__main__":
     main()
