@@ -202,7 +202,8 @@ def level_steps(N: int, n_coarse: int):
 
 
 def dense_cycle(p: int, N: int, T: float, lam: float, nu1: int, nu2: int, gamma: int,
-                n_coarse: int = 2, omega: float | None = None, trans: bool = False):
+                n_coarse: int = 2, omega: float | None = None, trans: bool = False,
+                periodic: bool = False):
     """Dense error propagator M_0 of one multigrid cycle on level 0.
 
     The two-grid error propagator of eq. chap4_errorTwoGridCycle,
@@ -217,13 +218,15 @@ def dense_cycle(p: int, N: int, T: float, lam: float, nu1: int, nu2: int, gamma:
     (eq. chap4_ODESmoother) with omega_l from Lemma chap4_lemma7 at
     alpha(lam tau_l) (or the fixed omega), R the restriction of
     eq. chap4_restrictionTime and P = R^T.  trans: the same cycle applied to
-    L^T (smoother I - omega D^{-T} L^T, the same R and P).  Every matrix comes
-    from the closed forms above, none from the C oracle."""
+    L^T (smoother I - omega D^{-T} L^T, the same R and P).  periodic: every
+    level's operator is the circulant one of
+    eq. chap4_equationLinearSystemODEPeriodic.  Every matrix comes from the
+    closed forms above, none from the C oracle."""
     Ns = level_steps(N, n_coarse)
     P_ = p + 1
 
     def Lmat(Nl):
-        L = dense_L(p, Nl, T / Nl, lam)
+        L = dense_L(p, Nl, T / Nl, lam, periodic)
         return L.T if trans else L
 
     def smoother(Nl):

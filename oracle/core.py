@@ -50,16 +50,16 @@ def lib():
         sig = {
             "or_tables": [_i, _d, _d, _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd],
             "or_fold": [_i, _i64, _d, _pd, _pd],
-            "or_apply": [_i, _i64, _d, _d, _i, _pd, _pd],
-            "or_residual": [_i, _i64, _d, _d, _i, _pd, _pd, _pd],
-            "or_sweeps": [_i, _i64, _d, _d, _i, _d, _i, _pd, _pd],
+            "or_apply": [_i, _i64, _d, _d, _i, _pd, _pd, _i],
+            "or_residual": [_i, _i64, _d, _d, _i, _pd, _pd, _pd, _i],
+            "or_sweeps": [_i, _i64, _d, _d, _i, _d, _i, _pd, _pd, _i],
             "or_restrict": [_i, _i64, _pd, _pd],
             "or_prolong_add": [_i, _i64, _pd, _pd],
-            "or_direct": [_i, _i64, _d, _d, _i, _pd, _pd],
+            "or_direct": [_i, _i64, _d, _d, _i, _pd, _pd, _i],
             "or_levels": [_i, _i64, _d, _d, _i64, _i, _d, _pd, _pd],
-            "or_cycles": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _i, _pd, _pd],
+            "or_cycles": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _i, _pd, _pd, _i],
             "or_solve": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _d, _i, _pd,
-                         _pd, _pd],
+                         _pd, _pd, _i],
             "or_solve_mixed": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _d, _i,
                                _pd, _pd, _pd],
             "or_cycle_mixed": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _pd],
@@ -117,26 +117,31 @@ def fold(p: int, u0: float, f) -> np.ndarray:
     return out
 
 
-def apply(p: int, tau: float, lam: float, u, trans: bool = False) -> np.ndarray:
+def apply(p: int, tau: float, lam: float, u, trans: bool = False,
+          periodic: bool = False) -> np.ndarray:
+    """L u (or L^T u); periodic: the circulant system u(0) = u(T)."""
     u = _c(u)
     out = np.empty_like(u)
-    lib().or_apply(p, u.size // (p + 1), tau, lam, int(trans), _p(u), _p(out))
+    lib().or_apply(p, u.size // (p + 1), tau, lam, int(trans), _p(u), _p(out), int(periodic))
     return out
 
 
-def residual(p: int, tau: float, lam: float, f, u, trans: bool = False) -> np.ndarray:
+def residual(p: int, tau: float, lam: float, f, u, trans: bool = False,
+             periodic: bool = False) -> np.ndarray:
     f, u = _c(f), _c(u)
     r = np.empty_like(f)
-    lib().or_residual(p, f.size // (p + 1), tau, lam, int(trans), _p(f), _p(u), _p(r))
+    lib().or_residual(p, f.size // (p + 1), tau, lam, int(trans), _p(f), _p(u), _p(r),
+                      int(periodic))
     return r
 
 
 def sweeps(p: int, tau: float, lam: float, f, u, nsweep: int, omega: float = 0.0,
-           trans: bool = False) -> np.ndarray:
+           trans: bool = False, periodic: bool = False) -> np.ndarray:
     """nsweep damped block Jacobi steps from u (omega <= 0: optimal omega*)."""
     f = _c(f)
     u = _c(u).copy()
-    lib().or_sweeps(p, f.size // (p + 1), tau, lam, int(trans), omega, nsweep, _p(f), _p(u))
+    lib().or_sweeps(p, f.size // (p + 1), tau, lam, int(trans), omega, nsweep, _p(f), _p(u),
+                    int(periodic))
     return u
 
 
@@ -155,12 +160,13 @@ def prolong_add(p: int, e, u) -> np.ndarray:
     return u
 
 
-def direct(p: int, tau: float, lam: float, f, trans: bool = False) -> np.ndarray:
+def direct(p: int, tau: float, lam: float, f, trans: bool = False,
+           periodic: bool = False) -> np.ndarray:
     """Exact solve of L u = f (folded f) by forward substitution, or of
-    L^T z = g by backward substitution."""
+    L^T z = g by backward substitution; periodic: of the circulant system."""
     f = _c(f)
     u = np.empty_like(f)
-    lib().or_direct(p, f.size // (p + 1), tau, lam, int(trans), _p(f), _p(u))
+    lib().or_direct(p, f.size // (p + 1), tau, lam, int(trans), _p(f), _p(u), int(periodic))
     return u
 
 
@@ -179,19 +185,19 @@ def levels(p: int, N: int, T: float, lam: float, opts: Opts = Opts()):
 
 
 def cycles(p: int, T: float, lam: float, f, u, ncyc: int, opts: Opts = Opts(),
-           trans: bool = False) -> np.ndarray:
+           trans: bool = False, periodic: bool = False) -> np.ndarray:
     """ncyc reference cycles on the folded system from initial guess u."""
     f = _c(f)
     u = _c(u).copy()
     rc = lib().or_cycles(p, f.size // (p + 1), T, lam, opts.nu1, opts.nu2, opts.gamma,
                          opts.n_coarse, opts.omega_mode, opts.omega, int(trans), ncyc, _p(f),
-                         _p(u))
+                         _p(u), int(periodic))
     assert rc == 0
     return u
 
 
 def solve_folded(p: int, T: float, lam: float, f, rtol: float = 1e-10, max_cycles: int = 200,
-                 opts: Opts = Opts(), trans: bool = False):
+                 opts: Opts = Opts(), trans: bool = False, periodic: bool = False):
     """Reference multigrid solve from zero; returns (u, cycles, relres, hist)."""
     f = _c(f)
     u = np.empty_like(f)
@@ -199,7 +205,7 @@ def solve_folded(p: int, T: float, lam: float, f, rtol: float = 1e-10, max_cycle
     rr = _dref()
     k = lib().or_solve(p, f.size // (p + 1), T, lam, opts.nu1, opts.nu2, opts.gamma,
                        opts.n_coarse, opts.omega_mode, opts.omega, int(trans), _p(f), rtol,
-                       max_cycles, _p(u), ctypes.byref(rr), _p(hist))
+                       max_cycles, _p(u), ctypes.byref(rr), _p(hist), int(periodic))
     assert k >= 0
     return u, k, rr.value, hist[:k + 1].copy()
 

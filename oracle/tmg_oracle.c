@@ -136,6 +136,7 @@ typedef struct {
     double A[OR_MAXP * OR_MAXP]; /* K + lambda*M, the diagonal block of L */
     double alpha;                /* nonzero eigenvalue of A^{-1} N */
     double omega;                /* damping used on this level */
+    int periodic;                /* u(0) = u(T): slab 0 couples to slab N-1 */
 } or_level;
 
 /*
@@ -148,6 +149,7 @@ typedef struct {
  */
 static void slab_matrices(int P, double tau, double lam, or_level *lv)
 {
+    lv->periodic = 0;
     int q = P + 2;
     double x[OR_MAXP + 2], w[OR_MAXP + 2];
     gauss_legendre(q, x, w);
@@ -235,7 +237,9 @@ static void transfer_matrices(int P, double *R1T, double *R2T)
 /* ---------------------------------------------------------------------- */
 
 /* (L u)_n = A u_n - N u_{n-1}, u_{-1} = 0 (eq. chap4_generalLinearSystemODE;
- * the initial value enters the right-hand side of the first slab). */
+ * the initial value enters the right-hand side of the first slab).  For the
+ * periodic problem u(0) = u(T) (eq. chap4_equationLinearSystemODEPeriodic)
+ * the circulant coupling of eq. chap4_circulantMatrix makes u_{-1} = u_{N-1}. */
 static void apply_L(const or_level *lv, const double *u, double *out)
 {
     int P = lv->P;
@@ -243,13 +247,14 @@ static void apply_L(const or_level *lv, const double *u, double *out)
         for (int k = 0; k < P; ++k) {
             double s = 0.0;
             for (int l = 0; l < P; ++l) s += lv->A[k * P + l] * u[n * P + l];
-            if (n > 0)
-                for (int l = 0; l < P; ++l) s -= lv->Nm[k * P + l] * u[(n - 1) * P + l];
+            int64_t left = n > 0 ? n - 1 : (lv->periodic ? lv->N - 1 : -1);
+            if (left >= 0)
+                for (int l = 0; l < P; ++l) s -= lv->Nm[k * P + l] * u[left * P + l];
             out[n * P + k] = s;
         }
 }
 
-/* (L^T z)_n = A^T z_n - N^T z_{n+1}, z_N = 0. */
+/* (L^T z)_n = A^T z_n - N^T z_{n+1}, z_N = 0 (periodic: z_N = z_0). */
 static void apply_LT(const or_level *lv, const double *z, double *out)
 {
     int P = lv->P;
@@ -257,8 +262,9 @@ static void apply_LT(const or_level *lv, const double *z, double *out)
         for (int k = 0; k < P; ++k) {
             double s = 0.0;
             for (int l = 0; l < P; ++l) s += lv->A[l * P + k] * z[n * P + l];
-            if (n + 1 < lv->N)
-                for (int l = 0; l < P; ++l) s -= lv->Nm[l * P + k] * z[(n + 1) * P + l];
+            int64_t right = n + 1 < lv->N ? n + 1 : (lv->periodic ? 0 : -1);
+            if (right >= 0)
+                for (int l = 0; l < P; ++l) s -= lv->Nm[l * P + k] * z[right * P + l];
             out[n * P + k] = s;
         }
 }
@@ -272,36 +278,72 @@ static void residual(const or_level *lv, int trans, const double *f, const doubl
     for (int64_t i = 0; i < n; ++i) r[i] = f[i] - r[i];
 }
 
-/* Exact solve by block forward substitution (trans = 0):
- *   A u_n = f_n + N u_{n-1},
+/* Block substitution (trans = 0, forward in time):
+ *   A u_n = f_n + N u_{n-1},  with u_{-1} := y for the first slab,
  * or backward substitution for the transposed system (trans = 1):
- *   A^T z_n = g_n + N^T z_{n+1}. */
-static void direct(const or_level *lv, int trans, const double *f, double *u)
+ *   A^T z_n = g_n + N^T z_{n+1},  with z_N := y for the last slab.
+ * f == NULL stands for a zero right-hand side, y == NULL for a zero
+ * coupling at the boundary. */
+static void substitute(const or_level *lv, int trans, const double *f, const double *y, double *u)
 {
     int P = lv->P;
     int64_t N = lv->N;
     double rhs[OR_MAXP];
     if (!trans) {
         for (int64_t n = 0; n < N; ++n) {
+            const double *prev = n > 0 ? u + (n - 1) * P : y;
             for (int k = 0; k < P; ++k) {
-                double s = f[n * P + k];
-                if (n > 0)
-                    for (int l = 0; l < P; ++l) s += lv->Nm[k * P + l] * u[(n - 1) * P + l];
+                double s = f ? f[n * P + k] : 0.0;
+                if (prev)
+                    for (int l = 0; l < P; ++l) s += lv->Nm[k * P + l] * prev[l];
                 rhs[k] = s;
             }
             dense_solve(P, lv->A, 0, rhs, u + n * P);
         }
     } else {
         for (int64_t n = N - 1; n >= 0; --n) {
+            const double *next = n + 1 < N ? u + (n + 1) * P : y;
             for (int k = 0; k < P; ++k) {
-                double s = f[n * P + k];
-                if (n + 1 < N)
-                    for (int l = 0; l < P; ++l) s += lv->Nm[l * P + k] * u[(n + 1) * P + l];
+                double s = f ? f[n * P + k] : 0.0;
+                if (next)
+                    for (int l = 0; l < P; ++l) s += lv->Nm[l * P + k] * next[l];
                 rhs[k] = s;
             }
             dense_solve(P, lv->A, 1, rhs, u + n * P);
         }
     }
+}
+
+/* Exact solve.  Initial-value problem: the substitution itself.  Periodic
+ * problem (eq. chap4_equationLinearSystemODEPeriodic): the substitution is
+ * affine in the coupled boundary slab y (u_{N-1} that slab 0 sees, or z_0
+ * that slab N-1 sees for the transposed system): the slab it ends on is
+ * Phi y + psi, psi from the substitution with y = 0 and column k of Phi from
+ * the substitution of the homogeneous system with y = e_k.  The periodic
+ * solution has y = Phi y + psi, so y solves (I - Phi) y = psi, and one more
+ * substitution with that y gives it. */
+static void direct(const or_level *lv, int trans, const double *f, double *u)
+{
+    if (!lv->periodic) {
+        substitute(lv, trans, f, NULL, u);
+        return;
+    }
+    int P = lv->P;
+    int64_t N = lv->N;
+    const int64_t end = trans ? 0 : N - 1;   /* the slab the substitution ends on */
+    double Phi[OR_MAXP * OR_MAXP], psi[OR_MAXP], e[OR_MAXP], y[OR_MAXP];
+    double IminusPhi[OR_MAXP * OR_MAXP];
+    substitute(lv, trans, f, NULL, u);
+    for (int k = 0; k < P; ++k) psi[k] = u[end * P + k];
+    for (int c = 0; c < P; ++c) {
+        for (int k = 0; k < P; ++k) e[k] = (k == c) ? 1.0 : 0.0;
+        substitute(lv, trans, NULL, e, u);
+        for (int k = 0; k < P; ++k) Phi[k * P + c] = u[end * P + k];
+    }
+    for (int k = 0; k < P; ++k)
+        for (int c = 0; c < P; ++c) IminusPhi[k * P + c] = (k == c ? 1.0 : 0.0) - Phi[k * P + c];
+    dense_solve(P, IminusPhi, 0, psi, y);
+    substitute(lv, trans, f, y, u);
 }
 
 /* One damped block Jacobi step (eq. chap4_ODESmoother):
@@ -365,7 +407,8 @@ typedef struct {
 
 /* Level sizes N, N/2, ..., n_coarse.  Returns -1 unless N = n_coarse * 2^k. */
 static int build_hier(or_hier *H, int p, int64_t N, double T, double lam, int nu1, int nu2,
-                      int gamma, int64_t n_coarse, int omega_mode, double omega_fixed)
+                      int gamma, int64_t n_coarse, int omega_mode, double omega_fixed,
+                      int periodic)
 {
     if (p < 0 || p + 1 > OR_MAXP || N < 1 || n_coarse < 1 || T <= 0.0) return -1;
     int nlev = 1;
@@ -388,6 +431,7 @@ static int build_hier(or_hier *H, int p, int64_t N, double T, double lam, int nu
         slab_matrices(p + 1, T / (double)Nl, lam, &H->lv[l]);
         H->lv[l].N = Nl;
         H->lv[l].omega = omega_mode == 0 ? omega_star(H->lv[l].alpha) : omega_fixed;
+        H->lv[l].periodic = periodic;
     }
     transfer_matrices(p + 1, H->R1T, H->R2T);
     return 0;
@@ -476,12 +520,15 @@ int or_fold(int p, int64_t N, double u0, const double *f, double *f_out)
     return 0;
 }
 
-/* out = L u (trans = 0) or L^T u (trans = 1) on N slabs of length tau. */
-int or_apply(int p, int64_t N, double tau, double lam, int trans, const double *u, double *out)
+/* out = L u (trans = 0) or L^T u (trans = 1) on N slabs of length tau;
+ * periodic: the circulant system of eq. chap4_equationLinearSystemODEPeriodic. */
+int or_apply(int p, int64_t N, double tau, double lam, int trans, const double *u, double *out,
+             int periodic)
 {
     or_level lv;
     slab_matrices(p + 1, tau, lam, &lv);
     lv.N = N;
+    lv.periodic = periodic;
     if (trans) apply_LT(&lv, u, out);
     else apply_L(&lv, u, out);
     return 0;
@@ -489,22 +536,24 @@ int or_apply(int p, int64_t N, double tau, double lam, int trans, const double *
 
 /* r = f - L u (or g - L^T z). */
 int or_residual(int p, int64_t N, double tau, double lam, int trans, const double *f,
-                const double *u, double *r)
+                const double *u, double *r, int periodic)
 {
     or_level lv;
     slab_matrices(p + 1, tau, lam, &lv);
     lv.N = N;
+    lv.periodic = periodic;
     residual(&lv, trans, f, u, r);
     return 0;
 }
 
 /* nsweep damped block Jacobi steps in place on u (omega <= 0: optimal omega). */
 int or_sweeps(int p, int64_t N, double tau, double lam, int trans, double omega, int nsweep,
-              const double *f, double *u)
+              const double *f, double *u, int periodic)
 {
     or_level lv;
     slab_matrices(p + 1, tau, lam, &lv);
     lv.N = N;
+    lv.periodic = periodic;
     if (omega <= 0.0) omega = omega_star(lv.alpha);
     for (int s = 0; s < nsweep; ++s) jacobi(&lv, trans, omega, f, u);
     return 0;
@@ -526,12 +575,15 @@ int or_prolong_add(int p, int64_t Nc, const double *e, double *u)
     return 0;
 }
 
-/* Exact solve of L u = f (trans = 0, forward) or L^T z = g (trans = 1, backward). */
-int or_direct(int p, int64_t N, double tau, double lam, int trans, const double *f, double *u)
+/* Exact solve of L u = f (trans = 0, forward) or L^T z = g (trans = 1, backward);
+ * periodic: of the circulant system. */
+int or_direct(int p, int64_t N, double tau, double lam, int trans, const double *f, double *u,
+              int periodic)
 {
     or_level lv;
     slab_matrices(p + 1, tau, lam, &lv);
     lv.N = N;
+    lv.periodic = periodic;
     direct(&lv, trans, f, u);
     return 0;
 }
@@ -541,7 +593,7 @@ int or_levels(int p, int64_t N, double T, double lam, int64_t n_coarse, int omeg
               double omega_fixed, double *alpha, double *omega)
 {
     or_hier H;
-    if (build_hier(&H, p, N, T, lam, 2, 2, 1, n_coarse, omega_mode, omega_fixed)) return -1;
+    if (build_hier(&H, p, N, T, lam, 2, 2, 1, n_coarse, omega_mode, omega_fixed, 0)) return -1;
     for (int l = 0; l < H.nlev; ++l) {
         alpha[l] = H.lv[l].alpha;
         omega[l] = H.lv[l].omega;
@@ -554,10 +606,11 @@ int or_levels(int p, int64_t N, double T, double lam, int64_t n_coarse, int omeg
 /* ncyc cycles in place on u for L u = f (already folded) or L^T z = g. */
 int or_cycles(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamma,
               int64_t n_coarse, int omega_mode, double omega_fixed, int trans, int ncyc,
-              const double *f, double *u)
+              const double *f, double *u, int periodic)
 {
     or_hier H;
-    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed,
+                   periodic))
         return -1;
     for (int c = 0; c < ncyc; ++c) cycle(&H, 0, trans, f, u);
     free_hier(&H);
@@ -572,10 +625,11 @@ int or_cycles(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamm
  */
 int or_solve(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamma,
              int64_t n_coarse, int omega_mode, double omega_fixed, int trans, const double *f,
-             double rtol, int max_cycles, double *u, double *relres, double *hist)
+             double rtol, int max_cycles, double *u, double *relres, double *hist, int periodic)
 {
     or_hier H;
-    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed,
+                   periodic))
         return -1;
     int64_t n = N * (p + 1);
     double *r = malloc(sizeof(double) * n);
@@ -778,7 +832,7 @@ int or_cycle_mixed(int p, int64_t N, double T, double lam, int nu1, int nu2, int
                    const double *r, double *e)
 {
     or_hier H;
-    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed, 0))
         return -1;
     set_lb64(&H, lb64);
     or_level32 *L32 = levels32(&H);
@@ -803,7 +857,7 @@ int or_solve_mixed(int p, int64_t N, double T, double lam, int nu1, int nu2, int
                    double *hist)
 {
     or_hier H;
-    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+    if (build_hier(&H, p, N, T, lam, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed, 0))
         return -1;
     set_lb64(&H, lb64);
     or_level32 *L32 = levels32(&H);
