@@ -91,12 +91,21 @@ typedef struct {
     int precision;    /* 0 = FP64; 1 = FP32 smoothing / transfers, FP64 residual,
                          FP64 coarsest scan, FP64 outer defect correction          */
     int schedule;     /* kernel schedule id, -1 = library default                   */
+    int periodic;     /* 0 = initial-value problem u(0) = u0; 1 = time-periodic
+                         u(0) = u(T) (section 3, eq. chap4_periodicBC: the block
+                         system with the circulant coupling of eq.
+                         chap4_circulantMatrix; u0 is ignored, the coarsest
+                         level is solved by the cyclic affine recurrence)       */
 } tmg_options;
 
-#define TMG_MAX_DEGREE 5
+/* Degrees 0 .. 5 run on register-resident tuned kernels; degrees 6 .. 20, and
+ * every periodic problem, on generic kernels (one slab per thread, operators
+ * in LDS; every level except the coarsest streams, FP64 only). */
+#define TMG_MAX_DEGREE 20
+#define TMG_MAX_TUNED_DEGREE 5
 
 /* Fill *opt with the defaults: p = 1, nu1 = nu2 = 2, V-cycle, n_coarse = 2,
- * optimal damping, FP64, default schedule. */
+ * optimal damping, FP64, default schedule, initial-value problem. */
 void tmg_default_options(tmg_options *opt);
 
 /*

@@ -22,7 +22,8 @@ ERRORS = {
     -5: "TMG_ERR_OOM", -6: "TMG_ERR_HIP", -7: "TMG_ERR_NONFINITE", -8: "TMG_ERR_DIVERGED",
     -9: "TMG_ERR_UNSUPPORTED", -10: "TMG_ERR_INTERNAL",
 }
-MAX_DEGREE = 5
+MAX_DEGREE = 20
+MAX_TUNED_DEGREE = 5
 
 # every symbol the header declares
 SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",
@@ -48,7 +49,8 @@ class Options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("gamma", ctypes.c_int), ("n_coarse", ctypes.c_int64),
                 ("omega_mode", ctypes.c_int), ("omega", ctypes.c_double),
-                ("precision", ctypes.c_int), ("schedule", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("schedule", ctypes.c_int),
+                ("periodic", ctypes.c_int)]
 
     @classmethod
     def make(cls, **kw) -> "Options":

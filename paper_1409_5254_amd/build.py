@@ -17,9 +17,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libtmg.so")
-# (source, extra flags, object name); the bottom kernel is compiled once per
-# P.  Largest translation units first, so that they start first.
+# (source, extra flags, object name); the bottom kernel and the generic
+# kernels are compiled once per P.  Largest translation units first, so that they start first.
 SOURCES = ([("tmg_bottom.hip", [f"-DTMG_BOTTOM_P={p}"], f"tmg_bottom_p{p}") for p in (6, 5, 4, 3, 2, 1)]
+           + [("tmg_generic.hip", [f"-DTMG_GEN_P={p}"], f"tmg_generic_p{p}") for p in range(21, 0, -1)]
            + [(s, [], os.path.splitext(s)[0]) for s in
               ("tmg_leg64.hip", "tmg_leg32.hip", "tmg_span.hip", "tmg_mix.hip", "tmg_capi.cpp",
                "tmg_kernels.hip", "tmg_tables.cpp")])

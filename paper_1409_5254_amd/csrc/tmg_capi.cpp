@@ -44,6 +44,8 @@ using namespace tmg;
 
 static_assert(TMG_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "scratch size");
 static_assert(TMG_NOALLOC_MAX_UNKNOWNS == kNoAllocMaxUnknowns, "no-alloc problem limit");
+static_assert(TMG_MAX_DEGREE + 1 == kMaxP, "largest degree");
+static_assert(TMG_MAX_TUNED_DEGREE + 1 == kMaxTunedP, "largest degree of the tuned kernels");
 
 namespace {
 
@@ -129,6 +131,11 @@ struct LevelStore {
 
 struct tmg_ctx {
     int batch = 0, P = 0, S = 0, Lmax = 0;
+    // the generic kernels (one slab per thread, tables in LDS): P above the
+    // tuned kernels' limit, or the periodic problem; level 0 then runs as a
+    // down leg into x0 and an up leg from it, out of place
+    bool generic = false;
+    double *x0 = nullptr;
     tmg_options opt{};
     std::vector<int64_t> N;
     std::vector<double> T, lam;
@@ -246,7 +253,11 @@ struct tmg_ctx {
     }
     int H_mixd2() const { return r4(opt.nu1 + 2 + 2 * opt.nu1); }
     int H_mix2() const { return r4(2 * opt.nu1 + opt.nu2 + 3 + 2 * (opt.nu1 + opt.nu2) + 2 * opt.nu1); }
-    int TO(int H) const { return tile_slabs(P) - H; }
+    // slabs per tile of the streaming launches, and output slabs per tile
+    int ts() const { return generic ? kGenThreads : tile_slabs(P); }
+    int TO(int H) const { return ts() - H; }
+    // generic level-0 up leg with the residual norm: one more slab of halo
+    int H_gup0() const { return rs(opt.nu1 + opt.nu2 + 1); }
     // every bottom-kernel level fits one wavefront (one-wavefront work-groups)
     bool small_bottom() const { return bottom_cap <= 64 * bottom_slabs(P); }
     // spans of K levels (k_span, one top-level slab per thread): the down
@@ -558,6 +569,8 @@ LegArgsT<T> leg_args(const tmg_ctx *c, int level, bool trans, const TileList *tl
     a.tile_inst = tl->d_inst;
     a.n0 = c->N[0] >> level;
     a.batch = c->batch;
+    a.generic = c->generic;
+    a.periodic = c->opt.periodic;
     a.tab_stride = c->tab_stride;
     a.halo = H;
     a.tile_out = c->TO(H);
@@ -574,6 +587,8 @@ struct CycleIO {
     int kind;      // kFirst / kEven / kOdd (solve); -1: a single warm-started cycle
 };
 
+// The initial value enters slab 0 of the forward initial-value problem only
+// (the drivers hand periodic problems no u0).
 const double *fold_of(const CycleIO &io) { return io.trans ? nullptr : io.u0; }
 
 // A solve's first level-0 down pass also yields the initial residual's norm
@@ -623,6 +638,8 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
     a.small = c->small_bottom();
+    a.generic = c->generic;
+    a.periodic = c->opt.periodic;
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, ninst, s));
     return TMG_OK;
 }
@@ -656,6 +673,8 @@ int enqueue_bottom_all(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     a.x_lv = reinterpret_cast<T *const *>(c->lvptr_d + Lm);
     a.soff_lv = reinterpret_cast<const int64_t *const *>(c->lvptr_d + 2 * Lm);
     a.small = c->small_bottom();
+    a.generic = c->generic;
+    a.periodic = c->opt.periodic;
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, n, s));
     return TMG_OK;
 }
@@ -1056,6 +1075,54 @@ int enqueue_first_down(tmg_ctx *c, const CycleIO &io, hipStream_t s, R0 *r0)
     return enqueue_down<double>(c, io, 0, true, s, kDeep, r0);
 }
 
+// Level 0 of a cycle on the generic kernels: a down leg from u (pre sweeps
+// stored in x0, residual restricted into level 1's right-hand side), the
+// coarse levels, and an up leg from x0 (correction, post sweeps) into u with
+// the residual norm of the result.  A solve's first cycle takes its down leg
+// from the solve's first level-0 down pass and recomputes the pre sweeps
+// from zero in the up leg instead of reading x0.
+int enqueue_generic_level0(tmg_ctx *c, const CycleIO &io, hipStream_t s)
+{
+    int rc;
+    TileList *tl;
+    const bool first = io.kind == kFirst, solve = io.kind >= 0;
+    if (!first) {
+        const int H = c->H_down();
+        if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+        LegArgs a = leg_args(c, 0, io.trans, tl, H);
+        a.f = io.f;
+        a.u0 = fold_of(io);
+        a.u_in = io.u;
+        a.u_out = c->x0;
+        a.rc = c->d.f[1];
+        a.st = io.use_state ? c->st : nullptr;
+        a.pre = c->opt.nu1;
+        HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
+    }
+    if ((rc = c->opt.gamma == 1 ? enqueue_vcycle_levels<double>(c, io, 1, 1, s)
+                                : enqueue_coarse_visits<double>(c, io, 1, s)))
+        return rc;
+    const int H = solve ? c->H_gup0() : c->H_up();
+    if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
+    LegArgs a = leg_args(c, 0, io.trans, tl, H);
+    a.f = io.f;
+    a.u0 = fold_of(io);
+    a.u_in = first ? nullptr : c->x0;
+    a.pre = first ? c->opt.nu1 : 0;
+    a.e = c->d.x(1, c->cur[1]);
+    a.post = c->opt.nu2;
+    a.u_out = io.u;
+    a.st = io.use_state ? c->st : nullptr;
+    if (solve) {
+        a.partial = c->partial;
+        a.norm_off = tl->d_off;
+    }
+    HIPCHK(c, launch_leg<double>(c->P, io.trans, a, tl->ntiles, s));
+    if (solve && io.use_state)
+        HIPCHK(c, launch_finalize(c->partial, tl->d_off, c->batch, c->st, c->ctl, c->mirror1(), 0, s));
+    return TMG_OK;
+}
+
 int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
 {
     int rc;
@@ -1073,7 +1140,9 @@ int enqueue_cycle(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     // instances that fit the bottom kernel entirely: the cycle is one launch
     // (FP64 in both precision modes)
     if ((rc = enqueue_bottom<double>(c, io, 0, first ? nullptr : io.u, io.u, s))) return rc;
-    if (c->deep_n[0] > 0 && c->mixed) {
+    if (c->deep_n[0] > 0 && c->generic) {
+        if ((rc = enqueue_generic_level0(c, io, s))) return rc;
+    } else if (c->deep_n[0] > 0 && c->mixed) {
         if ((rc = enqueue_mixed_level0(c, io, s))) return rc;
     } else if (c->deep_n[0] > 0) {
         TileList *tl;
@@ -1157,7 +1226,8 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
         if ((rc = get_tiles(c, l, kDeep, c->TO(c->H_down()), s, &tl))) return rc;
         if ((rc = get_tiles(c, l, kDeep, c->TO(c->H_up()), s, &tl))) return rc;
     }
-    const int H0[5] = {c->H_fused(), c->H_mixd(), c->H_mix(), c->H_mixv(), c->H_up()};
+    const int H0[6] = {c->H_fused(), c->H_mixd(), c->H_mix(), c->H_mixv(), c->H_up(),
+                       c->H_gup0()};
     for (int H : H0)
         if ((rc = get_tiles(c, 0, kDeep, c->TO(H), s, &tl))) return rc;
     if ((rc = get_tiles(c, 0, kDeepNext, c->TO(c->H_fused2()), s, &tl)) ||
@@ -1295,6 +1365,8 @@ bool read_run_bits(const HostHead *h, int words, long long ver, std::vector<unsi
 int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool trans, double rtol,
               int max_cycles, int *cycles, double *relres, hipStream_t s)
 {
+    // a periodic problem has no initial value
+    if (c->opt.periodic) u0 = nullptr;
     // active-set lists last for the cycles of this solve only
     struct ActiveOff {
         ActiveSet &A;
@@ -1556,6 +1628,12 @@ int plan_levels(const std::vector<int> &L, const int64_t *n_slabs, int64_t cap,
 // schedule and sizes the buffers that depend on it.
 int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hipStream_t s)
 {
+    if (c->generic) {
+        // one schedule: the bottom work-group solves the coarsest level only
+        cap = c->opt.n_coarse;
+        pairs = false;
+        span = 0;
+    }
     std::vector<int> lbv;
     int rc = plan_levels(c->L, c->N.data(), cap, &lbv);
     if (rc) return rc;
@@ -1649,6 +1727,7 @@ void tmg_default_options(tmg_options *o)
     o->omega = 0.5;
     o->precision = 0;
     o->schedule = -1;
+    o->periodic = 0;
 }
 
 const char *tmg_error_string(int code)
@@ -1676,6 +1755,15 @@ int tmg_last_hip_error(tmg_handle h) { return h ? h->last_hip : 0; }
 
 namespace {
 
+// The generic kernels serve degrees above the tuned kernels' and the
+// periodic problem; there the bottom work-group solves the coarsest level
+// only (exactly) and every other level streams.
+bool uses_generic(const tmg_options &o) { return o.p + 1 > kMaxTunedP || o.periodic != 0; }
+int64_t first_cap(const tmg_options &o)
+{
+    return uses_generic(o) ? o.n_coarse : schedule_cap(o.p + 1, o.schedule);
+}
+
 // Argument checks of a set-up (host only): options, lambda, T, and every
 // n_slabs[j] = n_coarse * 2^k; L[j] receives the level counts.
 int check_problem(int batch, const int64_t *n_slabs, const double *T, const double *lambda,
@@ -1687,6 +1775,9 @@ int check_problem(int batch, const int64_t *n_slabs, const double *T, const doub
         return TMG_ERR_INVALID;
     if (o.omega_mode == 1 && !(o.omega > 0.0 && o.omega <= 1.0)) return TMG_ERR_OMEGA;
     if (o.precision != 0 && o.precision != 1) return TMG_ERR_UNSUPPORTED;
+    if (o.periodic != 0 && o.periodic != 1) return TMG_ERR_INVALID;
+    // the FP32-inner cycle runs on the tuned kernels only
+    if (o.precision == 1 && uses_generic(o)) return TMG_ERR_UNSUPPORTED;
     std::vector<int> L(batch);
     for (int j = 0; j < batch; ++j) {
         if (!(std::isfinite(T[j]) && T[j] > 0.0 && std::isfinite(lambda[j]) && lambda[j] > 0.0))
@@ -1706,7 +1797,7 @@ int check_problem(int batch, const int64_t *n_slabs, const double *T, const doub
     // bottom kernel (schedule >= 0: bottom_cap = 2^schedule, capped); an
     // instance's coarsest level always does
     std::vector<int> lbv;
-    if (plan_levels(L, n_slabs, schedule_cap(o.p + 1, o.schedule), &lbv)) return TMG_ERR_SIZE;
+    if (plan_levels(L, n_slabs, first_cap(o), &lbv)) return TMG_ERR_SIZE;
     Lout->swap(L);
     return TMG_OK;
 }
@@ -1719,10 +1810,12 @@ int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
               hipStream_t s)
 {
     const int P = o.p + 1;
-    const int64_t bottom_cap = schedule_cap(P, o.schedule);
+    const int64_t bottom_cap = first_cap(o);
+    c->generic = uses_generic(o);
     c->batch = batch;
     c->P = P;
-    c->S = slabs_per_thread(P);
+    c->S = c->generic ? 1 : slabs_per_thread(P);
+    c->act.enabled = !c->generic;
     c->opt = o;
     c->N.assign(n_slabs, n_slabs + batch);
     c->T.assign(T, T + batch);
@@ -1786,7 +1879,8 @@ int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
             hipStreamSynchronize(s) != hipSuccess)
             return TMG_ERR_HIP;
     }
-    if ((rc = apply_plan(c, bottom_cap, true, 0, 2, s))) return rc;
+    if (c->generic && (rc = dalloc(c, &c->x0, c->level_size[0]))) return rc;
+    if ((rc = apply_plan(c, bottom_cap, !c->generic, 0, 2, s))) return rc;
     // tables, level-major: block (l, j) at (l * batch + j) * stride
     std::vector<double> tf((size_t)Lm * batch * c->tab_stride, 0.0),
         ta((size_t)Lm * batch * c->tab_stride, 0.0);
@@ -1817,7 +1911,7 @@ int build_ctx(tmg_ctx *c, int batch, const int64_t *n_slabs, const double *T,
         (rc = dalloc(c, &c->T_d, batch)) || (rc = dalloc(c, &c->N_d, batch)))
         return rc;
     // partial sums: one slot per level-0 tile at the smallest tile size in use
-    c->partial_cap = tiles_of(c, 0, kAll, tile_slabs(P) - c->rs(3 * kMaxSweeps + 4));
+    c->partial_cap = tiles_of(c, 0, kAll, std::min(c->ts(), tile_slabs(P)) - c->rs(3 * kMaxSweeps + 4));
     if ((rc = dalloc(c, &c->partial, c->partial_cap))) return rc;
     const size_t mirror_bytes =
         sizeof(HostHead) + sizeof(HostSum) + sizeof(unsigned) * run_words(batch);
@@ -1934,7 +2028,7 @@ int tmg_vcycle(tmg_handle c, const double *f, const double *u0, double *u, tmg_s
     hipStream_t s = (hipStream_t)stream;
     int rc = make_tiles(c, s);
     if (rc) return rc;
-    CycleIO io{f, u0, u, false, false, -1};
+    CycleIO io{f, c->opt.periodic ? nullptr : u0, u, false, false, -1};
     return enqueue_cycle(c, io, s);
 }
 
@@ -1985,7 +2079,8 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     // two-level launches), then how the streaming levels are launched at
     // that cap, then the launch mode
     std::vector<Cand> cands;
-    for (int k = 0; k <= 5; ++k) {
+    if (c->generic) cands.push_back({c->opt.n_coarse, false, 0, 2});   // only the launch mode
+    for (int k = 0; k <= 5 && !c->generic; ++k) {
         const int64_t cap = (int64_t)bottom_max(c->P) >> k;
         if (cap < c->opt.n_coarse) break;
         cands.push_back({cap, true, 0, 2});
@@ -2032,7 +2127,7 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
         }
     };
     run_stage();
-    if (rc >= 0 && c->opt.gamma == 1 && best >= 0.0f) {
+    if (rc >= 0 && c->opt.gamma == 1 && !c->generic && best >= 0.0f) {
         cands.clear();
         cands.push_back({pick.cap, false, 0, 2});
         for (int K = 3; K <= kMaxSpan; ++K)
@@ -2062,7 +2157,8 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
             best = ms;
             const Cand base = pick;
             for (int64_t cap : {base.cap * 2, base.cap / 2}) {
-                if (cap < c->opt.n_coarse || cap > (int64_t)bottom_max(c->P)) continue;
+                if (c->generic || cap < c->opt.n_coarse || cap > (int64_t)bottom_max(c->P))
+                    continue;
                 if (apply_plan(c, cap, base.pairs, base.span, base.after, s) != TMG_OK) continue;
                 c->direct = true;
                 const float m2 = timed();
@@ -2093,6 +2189,8 @@ int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int span, int 
 {
     if (!c || bottom_cap < c->opt.n_coarse || bottom_cap > (int64_t)bottom_max(c->P))
         return TMG_ERR_INVALID;
+    if (c->generic && (bottom_cap != c->opt.n_coarse || pairs || span))
+        return TMG_ERR_UNSUPPORTED;   // the generic kernels run one schedule
     if (span != 0 && (!pairs || c->opt.gamma != 1 || !c->span_fits(span) || span_after < 1))
         return TMG_ERR_INVALID;
     const int rc = apply_plan(c, bottom_cap, pairs != 0, span, span_after, (hipStream_t)stream);
@@ -2287,6 +2385,7 @@ int tmg_op_fused(tmg_handle c, int trans, const double *f, const double *fold_u0
 {
     if (!c || !f || !u_in || !e || !u_out || !rcout || c->Lmax < 2 || (fold_u0 && trans))
         return TMG_ERR_INVALID;
+    if (c->generic) return TMG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const int H = c->H_fused();
     TileList *tl;
@@ -2312,6 +2411,7 @@ int tmg_op_fused2(tmg_handle c, int trans, const double *f, const double *fold_u
 {
     if (!c || !f || !u_in || !f1 || !e2 || !u_out || !rcout || c->Lmax < 3 || (fold_u0 && trans))
         return TMG_ERR_INVALID;
+    if (c->generic) return TMG_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const int H = c->H_fused2();
     TileList *tl;
@@ -2361,6 +2461,8 @@ int tmg_op_coarse_solve(tmg_handle c, int level, int trans, const double *r, dou
     CoarseArgs a{};
     a.r = r;
     a.e = e;
+    a.generic = c->generic;
+    a.periodic = c->opt.periodic;
     a.tab = tab_of(c, level, trans != 0);
     a.slab_off = c->slab_off_d[level];
     a.inst = it->second.first;

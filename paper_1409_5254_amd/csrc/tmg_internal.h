@@ -7,7 +7,11 @@
 
 namespace tmg {
 
-constexpr int kMaxP = 6;        // P = p + 1 coefficients per slab
+constexpr int kMaxP = 21;       // P = p + 1 coefficients per slab (degrees up to 20)
+constexpr int kMaxTunedP = 6;   // the register-resident (tuned) kernels take P <= 6
+// Work-group (and tile, one slab per thread) of the generic kernels, which
+// take any P <= kMaxP and the time-periodic problem.
+constexpr int kGenThreads = 256;
 constexpr int kThreads = 256;   // work-group size of the scan and reduction kernels
 // Work-group size of the streaming (tile) kernels.  Four wavefronts: one
 // wavefront per work-group (barrier-free exchange) measured slower on the
@@ -146,6 +150,8 @@ struct LegArgsT {
     const int64_t *c2slab_off; // [batch+1] slab offsets of level l+2
     int64_t n0;              // slabs of instance 0 at this level (used when batch == 1)
     int batch;
+    int generic;             // 1: the generic kernel (P > kMaxTunedP, or periodic)
+    int periodic;            // 1: u(0) = u(T), slab -1 is slab N-1 (generic kernel only)
     int touch;               // 1: bring every table into the scalar cache at entry
     int tab_stride;
     int halo;                // left halo slabs per tile (even, a multiple of S)
@@ -219,10 +225,12 @@ struct CoarseArgs {
     const double *u0;        // fold values (level 0, forward) or null
     double *e;
     const double *tab;
+    const double *R;         // transfer matrices (generic kernel's table staging)
     const int64_t *slab_off;
     const int *inst;         // participating instance ids, one work-group each
     const InstState *st;     // may be null
     int tab_stride;
+    int generic, periodic;   // as in LegArgsT
 };
 
 // One multigrid visit of the levels `level` .. nlev[j]-1 of instance j per
@@ -254,6 +262,7 @@ struct BottomArgsT {
     // 1: every instance's first bottom level has at most 64 * bottom_slabs
     // slabs (one wavefront holds it): one-wavefront work-groups
     int small;
+    int generic, periodic;   // as in LegArgsT (the generic kernel solves its level exactly)
 };
 using BottomArgs = BottomArgsT<double>;
 
@@ -265,6 +274,12 @@ hipError_t launch_mix(int P, bool backward, const MixArgs &a, int64_t ntiles, hi
 template <typename T>
 hipError_t launch_span(int P, bool backward, const SpanArgsT<T> &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s);
+// The generic kernels (tmg_generic.h) for any P <= kMaxP; launch_leg,
+// launch_bottom and launch_coarse route to them when the arguments say so.
+hipError_t launch_gleg(int P, bool backward, const LegArgsT<double> &a, int64_t ntiles,
+                       hipStream_t s);
+hipError_t launch_gbottom(int P, bool backward, const BottomArgsT<double> &a, int ninst,
+                          hipStream_t s);
 template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s);
 // Level-0 halo slots of a tile list (tile_out output slabs and `halo` halo

@@ -2010,10 +2010,38 @@ __global__ __launch_bounds__(kThreads) void k_grad_finish(const double *__restri
     default: return hipErrorInvalidValue;             \
     }
 
+// Every P of the generic kernels (1 .. kMaxP).
+#define TMG_PCASE(n, ...) case n: { constexpr int PP = n; __VA_ARGS__; } break;
+#define TMG_DISPATCH_PALL(P, ...)                                                              \
+    switch (P) {                                                                               \
+    TMG_PCASE(1, __VA_ARGS__) TMG_PCASE(2, __VA_ARGS__) TMG_PCASE(3, __VA_ARGS__)              \
+    TMG_PCASE(4, __VA_ARGS__) TMG_PCASE(5, __VA_ARGS__) TMG_PCASE(6, __VA_ARGS__)              \
+    TMG_PCASE(7, __VA_ARGS__) TMG_PCASE(8, __VA_ARGS__) TMG_PCASE(9, __VA_ARGS__)              \
+    TMG_PCASE(10, __VA_ARGS__) TMG_PCASE(11, __VA_ARGS__) TMG_PCASE(12, __VA_ARGS__)           \
+    TMG_PCASE(13, __VA_ARGS__) TMG_PCASE(14, __VA_ARGS__) TMG_PCASE(15, __VA_ARGS__)           \
+    TMG_PCASE(16, __VA_ARGS__) TMG_PCASE(17, __VA_ARGS__) TMG_PCASE(18, __VA_ARGS__)           \
+    TMG_PCASE(19, __VA_ARGS__) TMG_PCASE(20, __VA_ARGS__) TMG_PCASE(21, __VA_ARGS__)           \
+    default: return hipErrorInvalidValue;                                                      \
+    }
+
+// The generic kernels' launchers for one P, instantiated in tmg_generic.hip
+// (compiled once per P).
+template <int P>
+hipError_t launch_gleg_p(bool backward, const LegArgsT<double> &a, int64_t ntiles, hipStream_t s);
+template <int P>
+hipError_t launch_gbottom_p(bool backward, const BottomArgsT<double> &a, int ninst, hipStream_t s);
+template <int P>
+hipError_t launch_gcoarse_p(bool backward, const CoarseArgs &a, int periodic, int ninst,
+                            hipStream_t s);
+
 template <typename T>
 hipError_t launch_leg(int P, bool backward, const LegArgsT<T> &a, int64_t ntiles, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
+    if (a.generic) {
+        if constexpr (std::is_same<T, double>::value) return launch_gleg(P, backward, a, ntiles, s);
+        else return hipErrorInvalidValue;   // the FP32-inner cycle has no generic form
+    }
     TMG_DISPATCH_P(P, {
         const dim3 grid((unsigned)ntiles), block(kLegThreads);
         // legs of a first visit from zero below level 0: the pruned forms

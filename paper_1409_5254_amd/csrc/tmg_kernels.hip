@@ -13,6 +13,10 @@ namespace tmg {
 hipError_t launch_coarse(int P, bool backward, const CoarseArgs &a, int ninst, hipStream_t s)
 {
     if (ninst <= 0) return hipSuccess;
+    if (a.generic) {
+        TMG_DISPATCH_PALL(P, { return launch_gcoarse_p<PP>(backward, a, a.periodic, ninst, s); })
+        return hipErrorInvalidValue;
+    }
     TMG_DISPATCH_P(P, {
         if (backward) hipLaunchKernelGGL((k_coarse<PP, true>), dim3(ninst), dim3(kThreads), 0, s, a);
         else hipLaunchKernelGGL((k_coarse<PP, false>), dim3(ninst), dim3(kThreads), 0, s, a);
@@ -24,7 +28,27 @@ template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s)
 {
     if (ninst <= 0) return hipSuccess;
+    if (a.generic) {
+        if constexpr (std::is_same<TIO, double>::value) return launch_gbottom(P, backward, a, ninst, s);
+        else return hipErrorInvalidValue;
+    }
     TMG_DISPATCH_P(P, { return launch_bottom_p<TIO, PP>(backward, a, ninst, s); })
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gleg(int P, bool backward, const LegArgsT<double> &a, int64_t ntiles,
+                       hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    TMG_DISPATCH_PALL(P, { return launch_gleg_p<PP>(backward, a, ntiles, s); })
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gbottom(int P, bool backward, const BottomArgsT<double> &a, int ninst,
+                          hipStream_t s)
+{
+    if (ninst <= 0) return hipSuccess;
+    TMG_DISPATCH_PALL(P, { return launch_gbottom_p<PP>(backward, a, ninst, s); })
     return hipErrorInvalidValue;
 }
 template hipError_t launch_bottom<double>(int, bool, const BottomArgsT<double> &, int, hipStream_t);
@@ -54,7 +78,7 @@ hipError_t launch_norm_f(int P, const double *f, const double *u0, const double 
                          hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    TMG_DISPATCH_P(P, {
+    TMG_DISPATCH_PALL(P, {
         hipLaunchKernelGGL((k_norm_f<PP>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s, f, u0, tab,
                            tab_stride, slab_off, tile_off, tile_inst, batch, partial);
     })
@@ -113,7 +137,7 @@ hipError_t launch_grad(int P, const double *u, const double *z, const double *ta
                        int64_t ntiles, int batch, double *partial, double *out, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    TMG_DISPATCH_P(P, {
+    TMG_DISPATCH_PALL(P, {
         hipLaunchKernelGGL((k_grad_partial<PP>), dim3((unsigned)ntiles), dim3(kLegThreads), 0, s,
                            u, z, slab_off, tile_off, tile_inst, batch, partial);
         hipLaunchKernelGGL((k_grad_finish<PP>), dim3(batch), dim3(kThreads), 0, s, partial,

@@ -49,8 +49,11 @@ def _setup(b, n, T, lam, **kw):
     ([1024], [0.0], [1.0], {}, -4),                       # T <= 0
     ([1024], [1.0], [-1.0], {}, -4),                      # lambda <= 0
     ([1024], [1.0], [float("nan")], {}, -4),
-    ([1024], [1.0], [1.0], dict(p=6), -1),                # degree not built (0..5)
-    ([1024], [1.0], [1.0], dict(p=7), -1),
+    ([1024], [1.0], [1.0], dict(p=21), -1),               # degree not built (0..20)
+    ([1024], [1.0], [1.0], dict(p=30), -1),
+    ([1024], [1.0], [1.0], dict(periodic=2), -1),
+    ([1024], [1.0], [1.0], dict(p=10, precision=1), -9),  # FP32-inner: tuned degrees only
+    ([1024], [1.0], [1.0], dict(periodic=1, precision=1), -9),
     ([1024], [1.0], [1.0], dict(p=-1), -1),
     ([1024], [1.0], [1.0], dict(gamma=3), -1),
     ([1024], [1.0], [1.0], dict(nu1=9), -1),

@@ -71,25 +71,35 @@ def fourier_load(p: int, N: int, T: float, a, phi) -> np.ndarray:
 
 
 def fourier_load_torch(p: int, N: int, T: float, a, phi, device="cuda", out=None):
-    """The same load vector as :func:`fourier_load`, evaluated with torch on
-    `device` (for large workloads); returns a flat float64 tensor, or fills
-    `out` (a flat view of N*(p+1) elements)."""
+    """The same load vector as :func:`fourier_load` (up to the order of the
+    sum over modes), evaluated with torch on `device` (for large workloads):
+    the sines and cosines of every mode in one pass each and the sum over
+    modes as two small matrix products.  Returns a flat float64 tensor, or
+    fills `out` (a flat view of N*(p+1) elements)."""
     import torch
     P = p + 1
     tau = T / N
+    K = len(a)
+    kk = torch.arange(1, K + 1, dtype=torch.float64, device=device)
     c = (torch.arange(N, dtype=torch.float64, device=device) + 0.5) * tau
-    f = out.view(N, P) if out is not None else torch.zeros((N, P), dtype=torch.float64,
-                                                            device=device)
-    if out is not None:
-        f.zero_()
-    for k, (ak, pk) in enumerate(zip(a, phi), start=1):
-        th = c * k + float(pk)
-        s, co = torch.sin(th), torch.cos(th)
+    th = torch.addcmul(torch.as_tensor(np.asarray(phi, dtype=np.float64), device=device)[:, None],
+                       kk[:, None], c[None, :])
+    S, C = torch.sin(th), torch.cos(th)
+    del th
+    # f_n[m] = tau sum_k a_k j_m(k tau/2) sin(k c_n + phi_k + m pi/2)
+    cs = np.zeros((P, K))
+    cc = np.zeros((P, K))
+    for k, ak in enumerate(a, start=1):
         for m in range(P):
-            jm = float(sph_jn(m, np.array([k * tau / 2.0]))[0])
-            trig = (s, co, -s, -co)[m % 4]
-            f[:, m] += (tau * float(ak) * jm) * trig
-    return f.reshape(-1)
+            w = tau * float(ak) * float(sph_jn(m, np.array([k * tau / 2.0]))[0])
+            (cs if m % 2 == 0 else cc)[m, k - 1] = w * (1.0 if m % 4 < 2 else -1.0)
+    f = torch.as_tensor(cs, device=device) @ S
+    f += torch.as_tensor(cc, device=device) @ C
+    del S, C
+    if out is not None:
+        out.view(N, P).copy_(f.t())
+        return out
+    return f.t().contiguous().reshape(-1)
 
 
 def quadrature_load(p: int, N: int, T: float, fn, q: int | None = None) -> np.ndarray:
