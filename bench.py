@@ -26,8 +26,8 @@ Other workloads (`--workload`):
               gradients (the backward pass of the autograd function);
   long        N = 2^24, p = 3, T = 1e4: FP64 cycle against FP32-inner defect
               correction, one instance and a batch of 64;
-  highdeg     the paper's own setting on one GPU at the highest degrees built:
-              p = 5 (and 4), tau = 1e-6, N = 2^20 steps, lambda = 1, to a
+  highdeg     the paper's own setting on one GPU (its Tables 1-2): p = 0, 1,
+              5, 10, 20, tau = 1e-6, N = 2^20 steps, lambda = 1, to a
               relative residual of 1e-8; a seeded random load from u = 0 in
               place of f = 0 from a random start (the same error iteration);
   convergence the section 4.2 study on the GPU: two-grid cycles (coarse level
@@ -37,7 +37,9 @@ Other workloads (`--workload`):
               the measured asymptotic contraction per case and the time per
               cycle;
   roofline    only the roofline measurement of the default run (for
-              profiler runs).
+              profiler runs);
+  batch       only the long-horizon batch solve (--precision 0 or 1), for
+              profiler runs (with --schedule to skip the tuning).
 """
 from __future__ import annotations
 
@@ -55,8 +57,17 @@ HBM_PEAK_GBS = 8000.0
 AUTOTUNE = True   # pick each handle's schedule with tmg_autotune before timing
 
 
+FIXED_SCHEDULE = None   # (bottom_cap, pairs, span, span_after, direct) from --schedule
+
+
 def tune(s, f, u0, u):
-    """Schedule chosen by the library's autotuner (not timed), or None."""
+    """Schedule chosen by the library's autotuner (not timed), a fixed one
+    from --schedule, or None (the library default)."""
+    if FIXED_SCHEDULE is not None:
+        cap, pairs, span, after, direct = FIXED_SCHEDULE
+        s.set_schedule(cap, pairs=bool(pairs), span=span, span_after=after, direct=bool(direct))
+        return dict(bottom_cap=cap, pairs=bool(pairs), span=span, span_after=after,
+                    direct=bool(direct))
     if not AUTOTUNE:
         return None
     return s.autotune(f, u0, u)
@@ -69,7 +80,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="default",
                     choices=["default", "scalar", "eigenmodes", "adjoint", "long", "highdeg",
-                             "convergence", "roofline"])
+                             "convergence", "roofline", "batch"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -81,6 +92,10 @@ def parse():
                     help="pick each handle's schedule with tmg_autotune before timing (1) or not")
     ap.add_argument("--cpu-log2n", type=int, default=20,
                     help="slabs (log2) of the oracle multigrid sample")
+    ap.add_argument("--precision", type=int, default=0, help="batch workload: 0 FP64, 1 FP32-inner")
+    ap.add_argument("--schedule", default="",
+                    help="bottom_cap,pairs,span,span_after,direct: install this schedule instead "
+                         "of tuning (scalar and batch workloads)")
     ap.add_argument("--roof-batch", type=int, default=16,
                     help="instances of the long-horizon batch in the roofline launch")
     ap.add_argument("--batch", type=int, default=0, help="instances of the batched workloads (0: default)")
@@ -349,8 +364,10 @@ def highdeg_run(p, steps, warmup):
     u = torch.empty_like(f)
     sched = tune(s, f, u0, u)
     dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-8, max_cycles=200), steps, warmup)
+    s.close()
     return dict(p=p, unknowns_per_s=N * P / dt, ms_per_solve=dt * 1e3, cycles=res.cycles[0],
                 relres=res.relres[0], status=res.status, schedule=sched,
+                kernels="tuned" if p <= 5 else "generic",
                 workload=f"u'+u=f, tau=1e-6, N=2^20 steps, p={p}, V(2,2) to 1e-8, "
                          "Gaussian Legendre load coefficients (torch generator, seed 6), u = 0")
 
@@ -448,6 +465,29 @@ def long_load(params, N, T, device="cuda"):
     for j, (lam, a, phi) in enumerate(params):
         gen.fourier_load_torch(3, N, T, a, phi, out=f[j * N * P:(j + 1) * N * P])
     return f
+
+
+def long_batch_run(B, log2n, precision, steps, warmup):
+    """The long-horizon batch in one precision mode (profiler runs)."""
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    N, P = 1 << log2n, 4
+    T = LONG_T * N / (1 << 24)
+    params = gen.long_horizon_params(B)
+    f = long_load(params, N, T)
+    u0 = torch.ones(B, dtype=torch.float64, device="cuda")
+    s = Solver([N] * B, [T] * B, [q[0] for q in params], p=3, precision=precision)
+    u = torch.empty_like(f)
+    sched = tune(s, f, u0, u)
+    log(f"batch of {B}, precision {precision}: schedule {sched}")
+    dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
+    log(f"  {dt * 1e3:.2f} ms per solve, {max(res.cycles)} cycles")
+    s.close()
+    return dict(unknowns_per_s=B * N * P / dt, ms_per_solve=dt * 1e3, cycles=max(res.cycles),
+                relres=max(res.relres), status=res.status, schedule=sched,
+                workload=f"{B} x (N=2^{log2n}, p=3, T={T:g}, lam ~ U(0.5,50)), precision "
+                         f"{precision}, V(2,2) to 1e-10")
 
 
 def batch_roofline(nb, log2n, reps):
@@ -565,6 +605,30 @@ def cpu_baseline_long(log2n_mg, ncores=0):
     return out
 
 
+def periodic_case(p, log2n, steps, warmup):
+    """The scalar workload as a time-periodic problem, u(0) = u(T) (the
+    generic kernels), V(2,2) to 1e-10."""
+    import torch
+    from paper_1409_5254_amd.binding import Solver
+    from workloads import gen
+    import numpy as np
+    N = 1 << log2n
+    T = 1000.0 * N / (1 << 22)
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal(16)
+    phi = rng.uniform(0.0, 2.0 * math.pi, 16)
+    f = gen.fourier_load_torch(p, N, T, a, phi, device="cuda")
+    u0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    u = torch.empty_like(f)
+    s = Solver([N], [T], [1.0], p=p, periodic=1)
+    sched = tune(s, f, u0, u)
+    dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=200), steps, warmup)
+    s.close()
+    return dict(p=p, N=N, periodic=True, unknowns_per_s=N * (p + 1) / dt, ms_per_solve=dt * 1e3,
+                cycles=res.cycles[0], relres=res.relres[0], status=res.status, schedule=sched,
+                kernels="generic")
+
+
 def w_cycle_case(p, log2n, steps, warmup):
     """The scalar workload with the W(2,2)-cycle, levels up to the bottom
     kernel's largest streaming, cycles after the first launched kernel by
@@ -594,8 +658,10 @@ def w_cycle_case(p, log2n, steps, warmup):
 
 def main():
     a = parse()
-    global AUTOTUNE
+    global AUTOTUNE, FIXED_SCHEDULE
     AUTOTUNE = bool(a.autotune)
+    if a.schedule:
+        FIXED_SCHEDULE = tuple(int(x) for x in a.schedule.split(","))
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the solve is not "
               "sharded across GPUs.", file=sys.stderr)
@@ -633,11 +699,11 @@ def main():
                           "config": {"workload": r["workload"]}, "result": r}))
         return
     if a.workload == "highdeg":
-        r5 = highdeg_run(5, a.steps, a.warmup)
-        r4 = highdeg_run(4, a.steps, a.warmup)
+        rs = [highdeg_run(p, a.steps, a.warmup) for p in (0, 1, 5, 10, 20)]
+        r20 = rs[-1]
         print(json.dumps({**base, "metric": "DG time-unknowns solved/s to rel. residual 1e-8",
-                          "value": r5["unknowns_per_s"], "ms_per_step": r5["ms_per_solve"],
-                          "config": {"workload": r5["workload"]}, "result": r5, "p4": r4}))
+                          "value": r20["unknowns_per_s"], "ms_per_step": r20["ms_per_solve"],
+                          "config": {"workload": r20["workload"]}, "results": rs}))
         return
     if a.workload == "long":
         r1 = long_horizon_compare(1, 24, a.steps, a.warmup)
@@ -645,6 +711,11 @@ def main():
         print(json.dumps({**base, "value": rb["fp32_inner"]["unknowns_per_s"],
                           "ms_per_step": rb["fp32_inner"]["ms_per_solve"],
                           "config": {"workload": rb["workload"]}, "scalar": r1, "batch": rb}))
+        return
+    if a.workload == "batch":
+        r = long_batch_run(a.batch or 64, 24, a.precision, a.steps, a.warmup)
+        print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
+                          "config": {"workload": r["workload"]}, "result": r}))
         return
     if a.workload == "roofline":
         print(json.dumps({"roofline": batch_roofline(a.roof_batch, 24, a.kernel_reps)}))
@@ -682,6 +753,12 @@ def main():
     wcyc = w_cycle_case(3, 22, 1, 0)
     torch.cuda.empty_cache()
     log(f"scalar N=2^22 p=3 W: {wcyc['ms_per_solve']:.3f} ms, {wcyc['cycles']} cycles")
+    per = periodic_case(3, 22, max(2, a.steps // 2), 1)
+    torch.cuda.empty_cache()
+    log(f"scalar N=2^22 p=3 periodic: {per['ms_per_solve']:.3f} ms, {per['cycles']} cycles")
+    hd = [highdeg_run(p, max(2, a.steps // 2), 1) for p in (10, 20)]
+    torch.cuda.empty_cache()
+    log("high degree: " + ", ".join(f"p={r['p']} {r['ms_per_solve']:.2f} ms" for r in hd))
     eig = eigenmode_run(4096, max(3, a.steps // 2), 1)
     torch.cuda.empty_cache()
     log(f"eigenmode batch: {eig['ms_per_solve']:.3f} ms")
@@ -710,6 +787,8 @@ def main():
         "scalar_2e22_V": [{k: r[k] for k in ("p", "unknowns_per_s", "ms_per_solve", "cycles",
                                              "relres", "schedule")} for r in sweep],
         "scalar_2e22_W": wcyc,
+        "scalar_2e22_periodic": per,
+        "highdeg": hd,
         "eigenmodes": eig,
         "adjoint": adj,
     }
