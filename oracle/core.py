@@ -64,6 +64,15 @@ def lib():
                                _pd, _pd, _pd],
             "or_cycle_mixed": [_i, _i64, _d, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _pd],
             "or_adjoint_rhs": [_i, _i64, _pd, _pd, _pd, _pd],
+            "or_heat_fold": [_i, _i, _i64, _pd, _pd, _pd],
+            "or_heat_apply": [_i, _i, _i64, _d, _pd, _pd],
+            "or_heat_residual": [_i, _i, _i64, _d, _pd, _pd, _pd],
+            "or_heat_sweeps": [_i, _i, _i64, _d, _d, _i, _pd, _pd],
+            "or_heat_direct": [_i, _i, _i64, _d, _pd, _pd],
+            "or_heat_levels": [_i, _i, _i64, _d, _i64, _i, _d, _pd],
+            "or_heat_cycles": [_i, _i, _i64, _d, _i, _i, _i, _i64, _i, _d, _i, _pd, _pd],
+            "or_heat_solve": [_i, _i, _i64, _d, _i, _i, _i, _i64, _i, _d, _pd, _d, _i, _pd, _pd,
+                              _pd],
             "or_gradients": [_i, _i64, _d, _d, _pd, _pd, _pd, _pd],
         }
         for name, args in sig.items():
@@ -258,3 +267,73 @@ def gradients(p: int, tau: float, lam: float, u, z):
     lib().or_gradients(p, u.size // (p + 1), tau, lam, _p(u), _p(z), ctypes.byref(dl),
                        ctypes.byref(du))
     return dl.value, du.value
+
+
+# --------------------------------------------------------------------------
+# space-time heat equation u_t - u_xx = f on (0,1), u = 0 at x = 0, 1
+# (arrays [point][slab][k], nx interior points of h = 1/(nx+1))
+# --------------------------------------------------------------------------
+
+def heat_fold(p: int, nx: int, u0, f) -> np.ndarray:
+    f, u0 = _c(f), _c(u0)
+    out = np.empty_like(f)
+    lib().or_heat_fold(p, nx, f.size // (nx * (p + 1)), _p(u0), _p(f), _p(out))
+    return out
+
+
+def heat_apply(p: int, nx: int, tau: float, u) -> np.ndarray:
+    u = _c(u)
+    out = np.empty_like(u)
+    lib().or_heat_apply(p, nx, u.size // (nx * (p + 1)), tau, _p(u), _p(out))
+    return out
+
+
+def heat_residual(p: int, nx: int, tau: float, f, u) -> np.ndarray:
+    f, u = _c(f), _c(u)
+    r = np.empty_like(f)
+    lib().or_heat_residual(p, nx, f.size // (nx * (p + 1)), tau, _p(f), _p(u), _p(r))
+    return r
+
+
+def heat_sweeps(p: int, nx: int, tau: float, f, u, nsweep: int, omega: float = 0.0) -> np.ndarray:
+    f = _c(f)
+    u = _c(u).copy()
+    lib().or_heat_sweeps(p, nx, f.size // (nx * (p + 1)), tau, omega, nsweep, _p(f), _p(u))
+    return u
+
+
+def heat_direct(p: int, nx: int, tau: float, f) -> np.ndarray:
+    f = _c(f)
+    u = np.empty_like(f)
+    lib().or_heat_direct(p, nx, f.size // (nx * (p + 1)), tau, _p(f), _p(u))
+    return u
+
+
+def heat_levels(p: int, nx: int, N: int, T: float, opts: Opts = Opts()) -> np.ndarray:
+    w = np.zeros(64)
+    n = lib().or_heat_levels(p, nx, N, T, opts.n_coarse, opts.omega_mode, opts.omega, _p(w))
+    assert n > 0
+    return w[:n].copy()
+
+
+def heat_cycles(p: int, nx: int, T: float, f, u, ncyc: int, opts: Opts = Opts()) -> np.ndarray:
+    f = _c(f)
+    u = _c(u).copy()
+    rc = lib().or_heat_cycles(p, nx, f.size // (nx * (p + 1)), T, opts.nu1, opts.nu2,
+                              opts.gamma, opts.n_coarse, opts.omega_mode, opts.omega, ncyc,
+                              _p(f), _p(u))
+    assert rc == 0
+    return u
+
+
+def heat_solve_folded(p: int, nx: int, T: float, f, rtol: float = 1e-10, max_cycles: int = 200,
+                      opts: Opts = Opts()):
+    f = _c(f)
+    u = np.empty_like(f)
+    hist = np.zeros(max_cycles + 1)
+    rr = _dref()
+    k = lib().or_heat_solve(p, nx, f.size // (nx * (p + 1)), T, opts.nu1, opts.nu2, opts.gamma,
+                            opts.n_coarse, opts.omega_mode, opts.omega, _p(f), rtol, max_cycles,
+                            _p(u), ctypes.byref(rr), _p(hist))
+    assert k >= 0
+    return u, k, rr.value, hist[:k + 1].copy()

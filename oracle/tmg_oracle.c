@@ -651,6 +651,378 @@ int or_solve(int p, int64_t N, double T, double lam, int nu1, int nu2, int gamma
 }
 
 /* ---------------------------------------------------------------------- */
+/* Space-time heat equation (section 6, Conclusions)                        */
+/* ---------------------------------------------------------------------- */
+/*
+ * u_t - u_xx = f on (0,1) x (0,T], u = 0 at x = 0, 1, u(x,0) = u0(x), with
+ * second-order finite differences on nx interior points x_i = i h,
+ * h = 1/(nx+1), L_h = tridiag(-1, 2, -1) / h^2, and the DG-in-time
+ * discretisation of the ODE part on every spatial point.  The slab system
+ * couples all points of a slab:
+ *     (I (x) K + L_h (x) M) U_n - (I (x) N) U_{n-1} = F_n,
+ * U_n ordered [point][k].  Arrays are [point][slab][k]: coefficient k of slab
+ * n at point i at (i*N + n)*P + k.  The time multigrid of section 3 applies
+ * with block Jacobi over whole slabs (every block solved exactly: the dense
+ * slab block is LU-factored once per level), time restriction and
+ * prolongation at every point, the coarse operator rediscretised at 2 tau on
+ * the same spatial grid, and forward substitution on the coarsest level.
+ */
+typedef struct {
+    int P, nx;
+    int64_t N;
+    double tau, h;
+    or_level t;   /* K, M (tau-scaled), N of the time slab */
+    double *LU;   /* (nx P)^2 LU factors of the slab block */
+    int *piv;
+    double omega;
+} or_heat_level;
+
+/* LU factorisation with partial pivoting of a dense n x n matrix (in place). */
+static void lu_factor(int n, double *a, int *piv)
+{
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int i = c + 1; i < n; ++i)
+            if (fabs(a[(int64_t)i * n + c]) > fabs(a[(int64_t)p * n + c])) p = i;
+        piv[c] = p;
+        if (p != c)
+            for (int j = 0; j < n; ++j) {
+                double t = a[(int64_t)c * n + j];
+                a[(int64_t)c * n + j] = a[(int64_t)p * n + j];
+                a[(int64_t)p * n + j] = t;
+            }
+        for (int i = c + 1; i < n; ++i) {
+            double m = a[(int64_t)i * n + c] / a[(int64_t)c * n + c];
+            a[(int64_t)i * n + c] = m;
+            for (int j = c + 1; j < n; ++j) a[(int64_t)i * n + j] -= m * a[(int64_t)c * n + j];
+        }
+    }
+}
+
+static void lu_solve(int n, const double *a, const int *piv, const double *b, double *x)
+{
+    for (int i = 0; i < n; ++i) x[i] = b[i];
+    for (int c = 0; c < n; ++c) {
+        if (piv[c] != c) {
+            double t = x[c];
+            x[c] = x[piv[c]];
+            x[piv[c]] = t;
+        }
+        for (int i = c + 1; i < n; ++i) x[i] -= a[(int64_t)i * n + c] * x[c];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int j = i + 1; j < n; ++j) s -= a[(int64_t)i * n + j] * x[j];
+        x[i] = s / a[(int64_t)i * n + i];
+    }
+}
+
+/* Smallest eigenvalue of L_h: (4/h^2) sin^2(pi h / 2). */
+static double heat_lambda1(int nx)
+{
+    const double h = 1.0 / (nx + 1), s = sin(M_PI * h / 2.0);
+    return 4.0 * s * s / (h * h);
+}
+
+/* alpha (the nonzero eigenvalue of A^{-1} N, Lemma chap4_theorem2) of the
+ * time slab at the smallest eigenvalue of L_h: the damping of Lemma
+ * chap4_lemma7 is taken there, for the slowest spatial mode. */
+static double heat_alpha(int P, double tau, int nx)
+{
+    or_level lv;
+    slab_matrices(P, tau, heat_lambda1(nx), &lv);
+    return lv.alpha;
+}
+
+static void heat_level_init(or_heat_level *hl, int P, int nx, int64_t N, double tau)
+{
+    hl->P = P;
+    hl->nx = nx;
+    hl->N = N;
+    hl->tau = tau;
+    hl->h = 1.0 / (nx + 1);
+    slab_matrices(P, tau, 1.0, &hl->t);
+    const int n = nx * P;
+    hl->LU = calloc((size_t)n * n, sizeof(double));
+    hl->piv = calloc((size_t)n, sizeof(int));
+    const double ih2 = 1.0 / (hl->h * hl->h);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < nx; ++j) {
+            double L = (i == j) ? 2.0 * ih2 : ((i - j == 1 || j - i == 1) ? -ih2 : 0.0);
+            for (int k = 0; k < P; ++k)
+                for (int l = 0; l < P; ++l) {
+                    double v = L * hl->t.M[k * P + l];
+                    if (i == j) v += hl->t.K[k * P + l];
+                    hl->LU[(int64_t)(i * P + k) * n + (j * P + l)] = v;
+                }
+        }
+    lu_factor(n, hl->LU, hl->piv);
+    hl->omega = omega_star(heat_alpha(P, tau, nx));
+}
+
+static void heat_level_free(or_heat_level *hl)
+{
+    free(hl->LU);
+    free(hl->piv);
+}
+
+/* (L U) at every point and slab: K u_{i,n} + M (L_h u)_{i,n} - N u_{i,n-1}. */
+static void heat_apply(const or_heat_level *hl, const double *u, double *out)
+{
+    const int P = hl->P, nx = hl->nx;
+    const int64_t N = hl->N;
+    const double ih2 = 1.0 / (hl->h * hl->h);
+    for (int i = 0; i < nx; ++i)
+        for (int64_t n = 0; n < N; ++n) {
+            const double *ui = u + ((int64_t)i * N + n) * P;
+            double lu[OR_MAXP];
+            for (int l = 0; l < P; ++l) {
+                double s = 2.0 * ui[l];
+                if (i > 0) s -= u[((int64_t)(i - 1) * N + n) * P + l];
+                if (i + 1 < nx) s -= u[((int64_t)(i + 1) * N + n) * P + l];
+                lu[l] = s * ih2;
+            }
+            for (int k = 0; k < P; ++k) {
+                double s = 0.0;
+                for (int l = 0; l < P; ++l) s += hl->t.K[k * P + l] * ui[l] + hl->t.M[k * P + l] * lu[l];
+                if (n > 0)
+                    for (int l = 0; l < P; ++l) s -= hl->t.Nm[k * P + l] * ui[l - P];
+                out[((int64_t)i * N + n) * P + k] = s;
+            }
+        }
+}
+
+static void heat_residual(const or_heat_level *hl, const double *f, const double *u, double *r)
+{
+    const int64_t n = (int64_t)hl->nx * hl->N * hl->P;
+    heat_apply(hl, u, r);
+    for (int64_t i = 0; i < n; ++i) r[i] = f[i] - r[i];
+}
+
+/* Gather slab n of every point into [point][k] (and scatter back). */
+static void heat_gather(const or_heat_level *hl, const double *a, int64_t n, double *s)
+{
+    for (int i = 0; i < hl->nx; ++i)
+        for (int k = 0; k < hl->P; ++k) s[i * hl->P + k] = a[((int64_t)i * hl->N + n) * hl->P + k];
+}
+static void heat_scatter(const or_heat_level *hl, const double *s, int64_t n, double *a)
+{
+    for (int i = 0; i < hl->nx; ++i)
+        for (int k = 0; k < hl->P; ++k) a[((int64_t)i * hl->N + n) * hl->P + k] = s[i * hl->P + k];
+}
+
+/* One damped block Jacobi step over whole slabs (eq. chap4_ODESmoother with
+ * the space-time slab block as D): u <- u + omega D^{-1} (f - L u). */
+static void heat_jacobi(const or_heat_level *hl, double omega, const double *f, double *u)
+{
+    const int P = hl->P, n = hl->nx * P;
+    const int64_t tot = (int64_t)hl->N * n;
+    double *r = malloc(sizeof(double) * tot);
+    double *rs = malloc(sizeof(double) * n), *d = malloc(sizeof(double) * n);
+    heat_residual(hl, f, u, r);
+    for (int64_t s = 0; s < hl->N; ++s) {
+        heat_gather(hl, r, s, rs);
+        lu_solve(n, hl->LU, hl->piv, rs, d);
+        for (int i = 0; i < hl->nx; ++i)
+            for (int k = 0; k < P; ++k) u[((int64_t)i * hl->N + s) * P + k] += omega * d[i * P + k];
+    }
+    free(r);
+    free(rs);
+    free(d);
+}
+
+/* Exact solve: forward substitution over the slabs, each slab block solved exactly. */
+static void heat_direct(const or_heat_level *hl, const double *f, double *u)
+{
+    const int P = hl->P, n = hl->nx * P;
+    double *rs = malloc(sizeof(double) * n), *d = malloc(sizeof(double) * n);
+    for (int64_t s = 0; s < hl->N; ++s) {
+        heat_gather(hl, f, s, rs);
+        if (s > 0)
+            for (int i = 0; i < hl->nx; ++i)
+                for (int k = 0; k < P; ++k) {
+                    double t = 0.0;
+                    for (int l = 0; l < P; ++l)
+                        t += hl->t.Nm[k * P + l] * u[((int64_t)i * hl->N + s - 1) * P + l];
+                    rs[i * P + k] += t;
+                }
+        lu_solve(n, hl->LU, hl->piv, rs, d);
+        heat_scatter(hl, d, s, u);
+    }
+    free(rs);
+    free(d);
+}
+
+typedef struct {
+    int P, nx, nlev, nu1, nu2, gamma;
+    or_heat_level *lv;
+    double R1T[OR_MAXP * OR_MAXP], R2T[OR_MAXP * OR_MAXP];
+} or_heat_hier;
+
+static int heat_build(or_heat_hier *H, int p, int nx, int64_t N, double T, int nu1, int nu2,
+                      int gamma, int64_t n_coarse, int omega_mode, double omega_fixed)
+{
+    if (p < 0 || p + 1 > OR_MAXP || nx < 1 || N < 1 || n_coarse < 1 || T <= 0.0) return -1;
+    int nlev = 1;
+    int64_t m = N;
+    while (m > n_coarse) {
+        if (m % 2) return -1;
+        m /= 2;
+        ++nlev;
+    }
+    if (m != n_coarse) return -1;
+    H->P = p + 1;
+    H->nx = nx;
+    H->nlev = nlev;
+    H->nu1 = nu1;
+    H->nu2 = nu2;
+    H->gamma = gamma;
+    H->lv = calloc((size_t)nlev, sizeof(or_heat_level));
+    for (int l = 0; l < nlev; ++l) {
+        heat_level_init(&H->lv[l], p + 1, nx, N >> l, T / (double)(N >> l));
+        if (omega_mode == 1) H->lv[l].omega = omega_fixed;
+    }
+    transfer_matrices(p + 1, H->R1T, H->R2T);
+    return 0;
+}
+
+static void heat_free(or_heat_hier *H)
+{
+    for (int l = 0; l < H->nlev; ++l) heat_level_free(&H->lv[l]);
+    free(H->lv);
+}
+
+/* One cycle on level l (eq. chap4_errorTwoGridCycle applied recursively, as
+ * in `cycle`), the transfers applied at every spatial point. */
+static void heat_cycle(const or_heat_hier *H, int l, const double *f, double *u)
+{
+    const or_heat_level *lv = &H->lv[l];
+    const int P = H->P, nx = H->nx;
+    if (l == H->nlev - 1) {
+        heat_direct(lv, f, u);
+        return;
+    }
+    for (int s = 0; s < H->nu1; ++s) heat_jacobi(lv, lv->omega, f, u);
+    const int64_t N = lv->N, Nc = N / 2;
+    double *r = malloc(sizeof(double) * nx * N * P);
+    double *rc = malloc(sizeof(double) * nx * Nc * P);
+    double *e = calloc((size_t)(nx * Nc * P), sizeof(double));
+    heat_residual(lv, f, u, r);
+    for (int i = 0; i < nx; ++i)
+        restrict_r(P, H->R1T, H->R2T, Nc, r + (int64_t)i * N * P, rc + (int64_t)i * Nc * P);
+    if (l + 1 == H->nlev - 1)
+        heat_direct(&H->lv[l + 1], rc, e);
+    else
+        for (int g = 0; g < H->gamma; ++g) heat_cycle(H, l + 1, rc, e);
+    for (int i = 0; i < nx; ++i)
+        prolong_add(P, H->R1T, H->R2T, Nc, e + (int64_t)i * Nc * P, u + (int64_t)i * N * P);
+    for (int s = 0; s < H->nu2; ++s) heat_jacobi(lv, lv->omega, f, u);
+    free(r);
+    free(rc);
+    free(e);
+}
+
+/* f_out = f with u0_i (-1)^k added to slab 0 of every point i. */
+int or_heat_fold(int p, int nx, int64_t N, const double *u0, const double *f, double *f_out)
+{
+    const int P = p + 1;
+    memcpy(f_out, f, sizeof(double) * nx * N * P);
+    for (int i = 0; i < nx; ++i) fold_u0(P, u0[i], f_out + (int64_t)i * N * P);
+    return 0;
+}
+
+int or_heat_apply(int p, int nx, int64_t N, double tau, const double *u, double *out)
+{
+    or_heat_level hl;
+    heat_level_init(&hl, p + 1, nx, N, tau);
+    heat_apply(&hl, u, out);
+    heat_level_free(&hl);
+    return 0;
+}
+
+int or_heat_residual(int p, int nx, int64_t N, double tau, const double *f, const double *u,
+                     double *r)
+{
+    or_heat_level hl;
+    heat_level_init(&hl, p + 1, nx, N, tau);
+    heat_residual(&hl, f, u, r);
+    heat_level_free(&hl);
+    return 0;
+}
+
+/* nsweep block Jacobi steps in place (omega <= 0: the level's damping). */
+int or_heat_sweeps(int p, int nx, int64_t N, double tau, double omega, int nsweep,
+                   const double *f, double *u)
+{
+    or_heat_level hl;
+    heat_level_init(&hl, p + 1, nx, N, tau);
+    if (omega <= 0.0) omega = hl.omega;
+    for (int s = 0; s < nsweep; ++s) heat_jacobi(&hl, omega, f, u);
+    heat_level_free(&hl);
+    return 0;
+}
+
+int or_heat_direct(int p, int nx, int64_t N, double tau, const double *f, double *u)
+{
+    or_heat_level hl;
+    heat_level_init(&hl, p + 1, nx, N, tau);
+    heat_direct(&hl, f, u);
+    heat_level_free(&hl);
+    return 0;
+}
+
+/* Per-level damping (array of length nlev); returns nlev. */
+int or_heat_levels(int p, int nx, int64_t N, double T, int64_t n_coarse, int omega_mode,
+                   double omega_fixed, double *omega)
+{
+    or_heat_hier H;
+    if (heat_build(&H, p, nx, N, T, 2, 2, 1, n_coarse, omega_mode, omega_fixed)) return -1;
+    for (int l = 0; l < H.nlev; ++l) omega[l] = H.lv[l].omega;
+    const int n = H.nlev;
+    heat_free(&H);
+    return n;
+}
+
+int or_heat_cycles(int p, int nx, int64_t N, double T, int nu1, int nu2, int gamma,
+                   int64_t n_coarse, int omega_mode, double omega_fixed, int ncyc,
+                   const double *f, double *u)
+{
+    or_heat_hier H;
+    if (heat_build(&H, p, nx, N, T, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+        return -1;
+    for (int c = 0; c < ncyc; ++c) heat_cycle(&H, 0, f, u);
+    heat_free(&H);
+    return 0;
+}
+
+/* Multigrid solve from u = 0 to ||f - L u||_2 <= rtol ||f||_2 (f folded). */
+int or_heat_solve(int p, int nx, int64_t N, double T, int nu1, int nu2, int gamma,
+                  int64_t n_coarse, int omega_mode, double omega_fixed, const double *f,
+                  double rtol, int max_cycles, double *u, double *relres, double *hist)
+{
+    or_heat_hier H;
+    if (heat_build(&H, p, nx, N, T, nu1, nu2, gamma, n_coarse, omega_mode, omega_fixed))
+        return -1;
+    const int64_t n = (int64_t)nx * N * (p + 1);
+    double *r = malloc(sizeof(double) * n);
+    memset(u, 0, sizeof(double) * n);
+    double r0 = norm2(n, f), rk = r0;
+    if (hist) hist[0] = r0;
+    int k = 0;
+    while (k < max_cycles && rk > rtol * r0) {
+        heat_cycle(&H, 0, f, u);
+        ++k;
+        heat_residual(&H.lv[0], f, u, r);
+        rk = norm2(n, r);
+        if (hist) hist[k] = rk;
+    }
+    *relres = r0 > 0.0 ? rk / r0 : 0.0;
+    free(r);
+    heat_free(&H);
+    return k;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Mixed precision reference (FP32 inner cycle, FP64 outer correction)    */
 /* ---------------------------------------------------------------------- */
 
