@@ -356,6 +356,46 @@ int tmg_op_coarse_solve(tmg_handle h, int level, int trans, const double *r, dou
 int tmg_op_residual_norm(tmg_handle h, int trans, const double *f, const double *fold_u0,
                          const double *u, double *norms, tmg_stream s);
 
+/* ------------------------------------------------------------------------
+ * Space-time heat equation (the paper's closing section: the time multigrid
+ * applied to u_t = u_xx + f, with the spatial problem solved inside every
+ * block Jacobi step).
+ *
+ *     u_t - u_xx = f  on (0,1) x (0,T],   u(0,t) = u(1,t) = 0,   u(x,0) = u0(x),
+ *
+ * second-order finite differences on nx interior points x_i = i h,
+ * h = 1/(nx+1), and at every point the DG-in-time discretisation of the
+ * header's first part (N slabs of degree p).  The slab block couples the
+ * points of a slab, I (x) K + L_h (x) M with L_h = tridiag(-1, 2, -1)/h^2;
+ * the cycle is that of section 3 (block Jacobi over whole slabs, each block
+ * solved exactly by block elimination over the points; factor-2 transfers
+ * in time at every point; the coarse operator rediscretised at 2 tau on the
+ * same spatial grid; forward substitution on the coarsest level).  Damping:
+ * omega_mode 0 takes Lemma chap4_lemma7's value at the smallest eigenvalue
+ * of L_h (the slowest spatial mode) per level, 1 the fixed opt->omega.
+ *
+ * LAYOUT.  f and u are device arrays [point][slab][k]: coefficient k of
+ * slab n at point i at (i*N + n)*P + k; f holds the load vectors at every
+ * point without the initial value; u0 is a device array of nx values.
+ * Options used: p (0 .. TMG_MAX_TUNED_DEGREE), nu1, nu2, gamma, n_coarse,
+ * omega_mode, omega; precision and periodic must be 0.  N must be
+ * n_coarse * 2^k with k >= 1.  Errors as above; calls are ordered on s and
+ * tmg_heat_solve blocks (it reads the residual norm after every cycle).
+ * --------------------------------------------------------------------- */
+typedef struct tmg_heat_ctx *tmg_heat_handle;
+#define TMG_HEAT_MAX_POINTS 4096
+
+int tmg_heat_setup(tmg_heat_handle *h, int64_t n_slabs, int nx, double T,
+                   const tmg_options *opt, tmg_stream s);
+/* One cycle in place on u (the initial guess). */
+int tmg_heat_vcycle(tmg_heat_handle h, const double *f, const double *u0, double *u,
+                    tmg_stream s);
+/* Solve from u = 0 to ||f - L u||_2 <= rtol ||f||_2 (u0 folded) or max_cycles. */
+int tmg_heat_solve(tmg_heat_handle h, const double *f, const double *u0, double *u, double rtol,
+                   int max_cycles, int *cycles, double *relres, tmg_stream s);
+int tmg_heat_destroy(tmg_heat_handle h);
+int tmg_heat_last_hip_error(tmg_heat_handle h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,8 @@ SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_a
            "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
            "tmg_op_coarse_solve",
            "tmg_op_residual_norm", "tmg_solve_noalloc", "tmg_op_down32", "tmg_op_up32",
-           "tmg_op_mix", "tmg_set_lambda"]
+           "tmg_op_mix", "tmg_set_lambda", "tmg_heat_setup", "tmg_heat_vcycle",
+           "tmg_heat_solve", "tmg_heat_destroy", "tmg_heat_last_hip_error"]
 
 
 class TmgError(RuntimeError):
@@ -101,6 +102,11 @@ def lib():
             "tmg_op_down32": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_up32": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
             "tmg_op_mix": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "tmg_heat_setup": (_i, [P(_vp), _i64, _i, _d, _vp, _vp]),
+            "tmg_heat_vcycle": (_i, [_vp, _vp, _vp, _vp, _vp]),
+            "tmg_heat_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d), _vp]),
+            "tmg_heat_destroy": (_i, [_vp]),
+            "tmg_heat_last_hip_error": (_i, [_vp]),
             "tmg_solve_noalloc": (_i, [_i64, _d, _d, _vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d),
                                        _vp]),
         }
@@ -329,3 +335,52 @@ class Solver:
                                         out, _stream())
         self._check(rc, "tmg_op_residual_norm")
         return list(out)
+
+
+class HeatSolver:
+    """The space-time heat equation u_t - u_xx = f on (0,1), u = 0 at both
+    ends, nx interior points, N slabs on (0, T]: arrays [point][slab][k]
+    (flat float64 device tensors); u0 has nx values."""
+
+    def __init__(self, n_slabs, nx, T, **opts):
+        self.N, self.nx, self.T = int(n_slabs), int(nx), float(T)
+        self.opts = Options.make(**opts)
+        self.P = self.opts.p + 1
+        self.size = self.N * self.nx * self.P
+        h = ctypes.c_void_p()
+        rc = lib().tmg_heat_setup(ctypes.byref(h), self.N, self.nx, self.T,
+                                  ctypes.byref(self.opts), _stream())
+        if rc != TMG_OK:
+            raise TmgError(rc, "tmg_heat_setup")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tmg_heat_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, where):
+        if rc < 0:
+            raise TmgError(rc, where, lib().tmg_heat_last_hip_error(self._h))
+        return rc
+
+    def vcycle(self, f, u0, u):
+        self._check(lib().tmg_heat_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),
+                    "tmg_heat_vcycle")
+        return u
+
+    def solve(self, f, u0, u=None, rtol=1e-10, max_cycles=100) -> SolveResult:
+        if u is None:
+            u = torch.empty_like(f)
+        cyc = (ctypes.c_int * 1)()
+        rr = (ctypes.c_double * 1)()
+        rc = lib().tmg_heat_solve(self._h, _ptr(f), _ptr(u0), _ptr(u), rtol, max_cycles, cyc, rr,
+                                  _stream())
+        self._check(rc, "tmg_heat_solve")
+        return SolveResult(u, list(cyc), list(rr), rc)

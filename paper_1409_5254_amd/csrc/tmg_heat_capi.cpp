@@ -1,0 +1,349 @@
+// Driver of the space-time heat equation (see include/tmg.h, tmg_heat_*):
+// the time multigrid of section 3 with every slab block, which couples all
+// spatial points of the slab, solved exactly inside the block Jacobi step.
+//
+// Each level l >= 1 keeps its right-hand side f_l, its result x_l and the
+// pre-smoothed iterate s_l of the visit in progress; level 0 keeps s_0.  A
+// visit is a down leg (pre sweeps into s_l, residual restricted into
+// f_{l+1}), gamma visits of the next level (or its exact solve), and an up
+// leg (correction from x_{l+1}, post sweeps) from s_l into x_l; level 0's up
+// leg writes the caller's u and the residual norm.  The host reads the norm
+// after every cycle.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/tmg.h"
+#include "tmg_heat.h"
+#include "tmg_internal.h"
+#include "tmg_tables.h"
+
+using namespace tmg;
+
+struct tmg_heat_ctx {
+    int P = 0, nx = 0, L = 0;
+    int64_t N = 0;
+    double T = 0.0, h = 0.0;
+    tmg_options opt{};
+    std::vector<int64_t> Nl;
+    std::vector<double> omega;
+    std::vector<double *> f, x, sx, Cinv, G, K, Md;   // per level (device)
+    double *R = nullptr, *ws = nullptr, *partial = nullptr, *sum = nullptr;
+    int64_t ws_tiles = 0;
+    std::vector<void *> allocs;
+    int last_hip = 0;
+};
+
+namespace {
+
+template <typename T>
+int halloc(tmg_heat_ctx *c, T **p, size_t n)
+{
+    *p = nullptr;
+    hipError_t e = hipMalloc((void **)p, (n ? n : 1) * sizeof(T));
+    if (e != hipSuccess) {
+        c->last_hip = (int)e;
+        return TMG_ERR_OOM;
+    }
+    c->allocs.push_back(*p);
+    return TMG_OK;
+}
+
+#define HCHK(c, expr)                                                      \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) {                                            \
+            (c)->last_hip = (int)e_;                                       \
+            return TMG_ERR_HIP;                                            \
+        }                                                                  \
+    } while (0)
+
+void heat_free(tmg_heat_ctx *c)
+{
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+int rs2(int x) { return (x + 1) & ~1; }   // even halos: restriction pairs stay in a tile
+int TO(int H) { return kHeatThreads - H; }
+int64_t tiles(int64_t N, int H) { return (N + TO(H) - 1) / TO(H); }
+// The largest halo of any launch (down legs nu1 + 1, up legs with the norm
+// nu2 + 1, the norm pass 2): the most tiles of a level, which sizes the
+// per-tile workspace and partials.
+int Hmax(const tmg_options &o) { return std::max(std::max(rs2(o.nu1 + 1), rs2(o.nu2 + 1)), 2); }
+
+// A leg's grid within the workspace it was sized for (else the launch would
+// write past the per-tile buffers).
+int launch_leg_checked(tmg_heat_ctx *c, const HeatArgs &a, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles > c->ws_tiles || a.halo < 2 || a.halo >= kHeatThreads) return TMG_ERR_INTERNAL;
+    HCHK(c, launch_hleg(c->P, a, ntiles, s));
+    return TMG_OK;
+}
+
+HeatArgs base_args(const tmg_heat_ctx *c, int l)
+{
+    HeatArgs a{};
+    a.Cinv = c->Cinv[l];
+    a.G = c->G[l];
+    a.K = c->K[l];
+    a.Md = c->Md[l];
+    a.R = c->R;
+    a.ws = c->ws;
+    a.N = c->Nl[l];
+    a.Nc = l + 1 < c->L ? c->Nl[l + 1] : 0;
+    a.ih2 = 1.0 / (c->h * c->h);
+    a.om = c->omega[l];
+    a.omc = 1.0 - c->omega[l];
+    a.nx = c->nx;
+    return a;
+}
+
+int visit(tmg_heat_ctx *c, int l, bool first, hipStream_t s);
+
+// The down leg at level l (from `in`, null: zero), the coarse visits, and
+// the up leg into `out`.
+int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const double *in,
+               double *out, double *partial, hipStream_t s)
+{
+    const int nu1 = c->opt.nu1, nu2 = c->opt.nu2;
+    int rc;
+    {
+        const int H = rs2(nu1 + 1);
+        HeatArgs a = base_args(c, l);
+        a.f = f;
+        a.u0 = u0;
+        a.u_in = in;
+        a.u_out = c->sx[l];
+        a.rc = c->f[l + 1];
+        a.halo = H;
+        a.tile_out = TO(H);
+        a.pre = nu1;
+        if ((rc = launch_leg_checked(c, a, tiles(c->Nl[l], H), s))) return rc;
+    }
+    for (int g = 0; g < c->opt.gamma; ++g)
+        if ((rc = visit(c, l + 1, g == 0, s))) return rc;
+    {
+        const int H = rs2(nu2 + (partial ? 1 : 0));
+        HeatArgs a = base_args(c, l);
+        a.f = f;
+        a.u0 = u0;
+        a.u_in = c->sx[l];
+        a.e = c->x[l + 1];
+        a.u_out = out;
+        a.partial = partial;
+        a.halo = H;
+        a.tile_out = TO(H);
+        a.post = nu2;
+        if ((rc = launch_leg_checked(c, a, tiles(c->Nl[l], H), s))) return rc;
+        if (partial) HCHK(c, launch_hsum(partial, tiles(c->Nl[l], H), c->sum, s));
+    }
+    return TMG_OK;
+}
+
+// One visit of level l >= 1 on L_l e = f_l (from zero on a first visit,
+// else from the current x_l); the coarsest level is solved exactly.
+int visit(tmg_heat_ctx *c, int l, bool first, hipStream_t s)
+{
+    if (l == c->L - 1) {
+        HeatArgs a = base_args(c, l);
+        a.f = c->f[l];
+        a.u_out = c->x[l];
+        HCHK(c, launch_hcoarse(c->P, a, s));
+        return TMG_OK;
+    }
+    return level_pass(c, l, c->f[l], nullptr, first ? nullptr : c->x[l], c->x[l], nullptr, s);
+}
+
+// Squared residual norm of u (or of the folded f when u is null) into c->sum.
+int norm2(tmg_heat_ctx *c, const double *f, const double *u0, const double *u, hipStream_t s)
+{
+    const int H = 2;
+    HeatArgs a = base_args(c, 0);
+    a.f = f;
+    a.u0 = u0;
+    a.u_in = u;
+    a.partial = c->partial;
+    a.norm_f = u ? 0 : 1;
+    a.halo = H;
+    a.tile_out = TO(H);
+    const int rc = launch_leg_checked(c, a, tiles(c->N, H), s);
+    if (rc) return rc;
+    HCHK(c, launch_hsum(c->partial, tiles(c->N, H), c->sum, s));
+    return TMG_OK;
+}
+
+int read_sum(tmg_heat_ctx *c, double *v, hipStream_t s)
+{
+    HCHK(c, hipMemcpyAsync(v, c->sum, sizeof(double), hipMemcpyDeviceToHost, s));
+    HCHK(c, hipStreamSynchronize(s));
+    return TMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
+                   const tmg_options *opt, tmg_stream stream)
+{
+    if (!hp || !opt) return TMG_ERR_INVALID;
+    *hp = nullptr;
+    const tmg_options &o = *opt;
+    if (o.p < 0 || o.p > TMG_MAX_TUNED_DEGREE || nx < 1 || nx > TMG_HEAT_MAX_POINTS ||
+        o.nu1 < 0 || o.nu1 > kMaxSweeps || o.nu2 < 0 || o.nu2 > kMaxSweeps ||
+        (o.gamma != 1 && o.gamma != 2) || o.n_coarse < 1 || o.n_coarse > kMaxCoarse ||
+        (o.omega_mode != 0 && o.omega_mode != 1))
+        return TMG_ERR_INVALID;
+    if (o.omega_mode == 1 && !(o.omega > 0.0 && o.omega <= 1.0)) return TMG_ERR_OMEGA;
+    if (o.precision != 0 || o.periodic != 0) return TMG_ERR_UNSUPPORTED;
+    if (!(std::isfinite(T) && T > 0.0)) return TMG_ERR_PARAM;
+    int L = 1;
+    int64_t n = n_slabs;
+    if (n < o.n_coarse || n > (int64_t(1) << 32)) return TMG_ERR_SIZE;
+    while (n > o.n_coarse) {
+        if (n & 1) return TMG_ERR_SIZE;
+        n >>= 1;
+        ++L;
+    }
+    if (n != o.n_coarse || L < 2) return TMG_ERR_SIZE;
+    tmg_heat_ctx *c = new (std::nothrow) tmg_heat_ctx;
+    if (!c) return TMG_ERR_OOM;
+    hipStream_t s = (hipStream_t)stream;
+    const int P = o.p + 1;
+    c->P = P;
+    c->nx = nx;
+    c->L = L;
+    c->N = n_slabs;
+    c->T = T;
+    c->h = 1.0 / (nx + 1);
+    c->opt = o;
+    auto fail = [&](int code) {
+        heat_free(c);
+        delete c;
+        return code;
+    };
+    const double ih2 = 1.0 / (c->h * c->h);
+    const double sh = std::sin(M_PI * c->h / 2.0);
+    const double lam1 = 4.0 * sh * sh * ih2;   // smallest eigenvalue of L_h
+    c->f.assign(L, nullptr);
+    c->x.assign(L, nullptr);
+    c->sx.assign(L, nullptr);
+    c->Cinv.assign(L, nullptr);
+    c->G.assign(L, nullptr);
+    c->K.assign(L, nullptr);
+    c->Md.assign(L, nullptr);
+    c->omega.assign(L, 0.0);
+    int rc;
+    int64_t maxtiles = 0;
+    for (int l = 0; l < L; ++l) {
+        const int64_t Nl = n_slabs >> l;
+        c->Nl.push_back(Nl);
+        const int64_t sz = Nl * nx * P;
+        if (l > 0 && ((rc = halloc(c, &c->f[l], sz)) || (rc = halloc(c, &c->x[l], sz))))
+            return fail(rc);
+        if (l + 1 < L && (rc = halloc(c, &c->sx[l], sz))) return fail(rc);
+        maxtiles = std::max(maxtiles, tiles(Nl, Hmax(o)));
+        // the slab matrices at tau_l: K, M = tau diag(1/(2k+1)); D = K + (2/h^2) M,
+        // E = -M/h^2; block elimination C_0 = D, C_i = D - E C_{i-1}^{-1} E
+        const double tau = T / (double)Nl;
+        std::vector<double> Km(P * P), Md(P), Ci((size_t)nx * P * P), Gi((size_t)nx * P * P);
+        for (int k = 0; k < P; ++k) {
+            Md[k] = tau / (2.0 * k + 1.0);
+            for (int j = 0; j < P; ++j) Km[k * P + j] = (j < k && ((k + j) & 1)) ? -1.0 : 1.0;
+        }
+        std::vector<double> C(P * P), Cprev_inv(P * P, 0.0);
+        for (int i = 0; i < nx; ++i) {
+            for (int k = 0; k < P; ++k)
+                for (int j = 0; j < P; ++j)
+                    C[k * P + j] = Km[k * P + j] + (k == j ? 2.0 * ih2 * Md[k] : 0.0);
+            if (i > 0)
+                // - E C_{i-1}^{-1} E with E = -diag(Md)/h^2
+                for (int k = 0; k < P; ++k)
+                    for (int j = 0; j < P; ++j)
+                        C[k * P + j] -= Md[k] * ih2 * Cprev_inv[k * P + j] * Md[j] * ih2;
+            double *inv = &Ci[(size_t)i * P * P];
+            table_invert(P, C.data(), inv);
+            for (int k = 0; k < P; ++k)
+                for (int j = 0; j < P; ++j) Gi[(size_t)i * P * P + k * P + j] = -inv[k * P + j] * Md[j] * ih2;
+            for (int q = 0; q < P * P; ++q) Cprev_inv[q] = inv[q];
+        }
+        std::vector<double> tab(TabLayout(P).stride());
+        const double alpha = level_table(P, lam1 * tau, 0, 0.0, false, tab.data());
+        c->omega[l] = o.omega_mode == 0 ? (alpha >= 0.0 ? 1.0 / (1.0 + alpha * alpha) : 1.0)
+                                        : o.omega;
+        if ((rc = halloc(c, &c->Cinv[l], Ci.size())) || (rc = halloc(c, &c->G[l], Gi.size())) ||
+            (rc = halloc(c, &c->K[l], Km.size())) || (rc = halloc(c, &c->Md[l], Md.size())))
+            return fail(rc);
+        if (hipMemcpyAsync(c->Cinv[l], Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->G[l], Gi.data(), Gi.size() * 8, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->K[l], Km.data(), Km.size() * 8, hipMemcpyHostToDevice, s) ||
+            hipMemcpyAsync(c->Md[l], Md.data(), Md.size() * 8, hipMemcpyHostToDevice, s) ||
+            hipStreamSynchronize(s))
+            return fail(TMG_ERR_HIP);
+    }
+    std::vector<double> R1T(P * P), R2T(P * P), R(2 * P * P);
+    build_transfer(P, R1T.data(), R2T.data());
+    for (int q = 0; q < P * P; ++q) {
+        R[q] = R1T[q];
+        R[P * P + q] = R2T[q];
+    }
+    c->ws_tiles = maxtiles;
+    if ((rc = halloc(c, &c->R, R.size())) ||
+        (rc = halloc(c, &c->ws, (size_t)maxtiles * 2 * nx * kHeatThreads * P)) ||
+        (rc = halloc(c, &c->partial, maxtiles)) || (rc = halloc(c, &c->sum, 1)))
+        return fail(rc);
+    if (hipMemcpyAsync(c->R, R.data(), R.size() * 8, hipMemcpyHostToDevice, s) ||
+        hipStreamSynchronize(s))
+        return fail(TMG_ERR_HIP);
+    *hp = c;
+    return TMG_OK;
+}
+
+int tmg_heat_vcycle(tmg_heat_handle c, const double *f, const double *u0, double *u,
+                    tmg_stream stream)
+{
+    if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    return level_pass(c, 0, f, u0, u, u, nullptr, s);
+}
+
+int tmg_heat_solve(tmg_heat_handle c, const double *f, const double *u0, double *u, double rtol,
+                   int max_cycles, int *cycles, double *relres, tmg_stream stream)
+{
+    if (!c || !f || !u0 || !u || !(rtol >= 0.0) || max_cycles < 0) return TMG_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    double r0 = 0.0, rk = 0.0;
+    if ((rc = norm2(c, f, u0, nullptr, s)) || (rc = read_sum(c, &r0, s))) return rc;
+    HCHK(c, hipMemsetAsync(u, 0, sizeof(double) * c->N * c->nx * c->P, s));
+    rk = r0;
+    int k = 0, status = TMG_OK;
+    if (!std::isfinite(r0)) status = TMG_ERR_NONFINITE;
+    while (status == TMG_OK && r0 > 0.0 && k < max_cycles && rk > rtol * rtol * r0) {
+        if ((rc = level_pass(c, 0, f, u0, k == 0 ? nullptr : u, u, c->partial, s))) return rc;
+        ++k;
+        if ((rc = read_sum(c, &rk, s))) return rc;
+        if (!std::isfinite(rk)) status = TMG_ERR_NONFINITE;
+        else if (rk > 1e6 * r0) status = TMG_ERR_DIVERGED;
+    }
+    if (status == TMG_OK && r0 > 0.0 && rk > rtol * rtol * r0) status = TMG_NOT_CONVERGED;
+    if (cycles) *cycles = k;
+    if (relres) *relres = r0 > 0.0 ? std::sqrt(rk / r0) : 0.0;
+    return status;
+}
+
+int tmg_heat_destroy(tmg_heat_handle c)
+{
+    if (!c) return TMG_ERR_INVALID;
+    (void)hipDeviceSynchronize();
+    heat_free(c);
+    delete c;
+    return TMG_OK;
+}
+
+int tmg_heat_last_hip_error(tmg_heat_handle c) { return c ? c->last_hip : 0; }
+
+}  // extern "C"

@@ -112,3 +112,22 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+@pytest.mark.parametrize("n,nx,T,kw,code", [
+    (1024, 0, 1.0, {}, -1),
+    (1024, 5000, 1.0, {}, -1),            # above TMG_HEAT_MAX_POINTS
+    (1024, 15, 1.0, dict(p=6), -1),       # the heat solver takes the tuned degrees
+    (1024, 15, 1.0, dict(precision=1), -9),
+    (1024, 15, 1.0, dict(periodic=1), -9),
+    (1000, 15, 1.0, {}, -2),              # not n_coarse * 2^k
+    (2, 15, 1.0, {}, -2),                 # one level only
+    (1024, 15, 0.0, {}, -4),
+    (1024, 15, 1.0, dict(omega_mode=1, omega=1.5), -3),
+])
+def test_heat_setup_rejects(n, nx, T, kw, code):
+    """tmg_heat_setup checks its arguments before any device work."""
+    b = _lib()
+    o = b.Options.make(**kw)
+    h = ctypes.c_void_p()
+    assert b.lib().tmg_heat_setup(ctypes.byref(h), n, nx, T, ctypes.byref(o), None) == code
