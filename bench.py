@@ -39,7 +39,9 @@ Other workloads (`--workload`):
   roofline    only the roofline measurement of the default run (for
               profiler runs);
   batch       only the long-horizon batch solve (--precision 0 or 1), for
-              profiler runs (with --schedule to skip the tuning).
+              profiler runs (with --schedule to skip the tuning);
+  heat        the space-time heat equation u_t - u_xx = f (nx = 255 points,
+              N = 2^17 slabs on (0, 0.8], p = 1: 6.7e7 unknowns).
 """
 from __future__ import annotations
 
@@ -80,7 +82,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="default",
                     choices=["default", "scalar", "eigenmodes", "adjoint", "long", "highdeg",
-                             "convergence", "roofline", "batch"])
+                             "convergence", "roofline", "batch", "heat"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -629,6 +631,29 @@ def periodic_case(p, log2n, steps, warmup):
                 kernels="generic")
 
 
+def heat_run(steps, warmup, p=1, nx=255, log2n=17, T=0.8):
+    """The space-time heat equation u_t - u_xx = f on (0,1) (finite
+    differences on nx interior points, DG in time, slab blocks solved
+    exactly inside the block Jacobi step), V(2,2) to 1e-10."""
+    import torch
+    from paper_1409_5254_amd.binding import HeatSolver
+    from workloads import gen
+    N = 1 << log2n
+    u0n, fn = gen.heat_problem(p, nx, N, T)
+    f = torch.as_tensor(fn, device="cuda")
+    u0 = torch.as_tensor(u0n, device="cuda")
+    u = torch.empty_like(f)
+    s = HeatSolver(N, nx, T, p=p)
+    dt, res = time_solves(lambda: s.solve(f, u0, u=u, rtol=1e-10, max_cycles=100), steps, warmup)
+    s.close()
+    n = N * nx * (p + 1)
+    return dict(unknowns_per_s=n / dt, ms_per_solve=dt * 1e3, cycles=res.cycles[0],
+                relres=res.relres[0], status=res.status, unknowns=n,
+                workload=f"u_t - u_xx = f on (0,1), nx={nx} interior points, N=2^{log2n} slabs on "
+                         f"(0,{T:g}], p={p}, V(2,2) to 1e-10, u0 = sin(pi x), Gaussian Legendre "
+                         "load (seed 7)")
+
+
 def w_cycle_case(p, log2n, steps, warmup):
     """The scalar workload with the W(2,2)-cycle, levels up to the bottom
     kernel's largest streaming, cycles after the first launched kernel by
@@ -717,6 +742,11 @@ def main():
         print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
                           "config": {"workload": r["workload"]}, "result": r}))
         return
+    if a.workload == "heat":
+        r = heat_run(a.steps, a.warmup)
+        print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
+                          "config": {"workload": r["workload"]}, "result": r}))
+        return
     if a.workload == "roofline":
         print(json.dumps({"roofline": batch_roofline(a.roof_batch, 24, a.kernel_reps)}))
         return
@@ -759,6 +789,9 @@ def main():
     hd = [highdeg_run(p, max(2, a.steps // 2), 1) for p in (10, 20)]
     torch.cuda.empty_cache()
     log("high degree: " + ", ".join(f"p={r['p']} {r['ms_per_solve']:.2f} ms" for r in hd))
+    heat = heat_run(max(2, a.steps // 3), 1)
+    torch.cuda.empty_cache()
+    log(f"heat equation: {heat['ms_per_solve']:.2f} ms, {heat['cycles']} cycles")
     eig = eigenmode_run(4096, max(3, a.steps // 2), 1)
     torch.cuda.empty_cache()
     log(f"eigenmode batch: {eig['ms_per_solve']:.3f} ms")
@@ -789,6 +822,7 @@ def main():
         "scalar_2e22_W": wcyc,
         "scalar_2e22_periodic": per,
         "highdeg": hd,
+        "heat": heat,
         "eigenmodes": eig,
         "adjoint": adj,
     }

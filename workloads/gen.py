@@ -231,3 +231,17 @@ def long_horizon(B: int = 1, N: int = 1 << 24, T: float = 1e4, seed: int = 5) ->
     rng = np.random.default_rng(seed)
     lam = rng.uniform(0.5, 50.0, B)
     return fourier_batch(f"long_horizon_b{B}", 3, N, T, lam, rng)
+
+
+def heat_problem(p: int = 1, nx: int = 255, N: int = 1 << 14, T: float = 0.1, seed: int = 7):
+    """Space-time heat equation u_t - u_xx = f on (0,1), u = 0 at both ends,
+    nx interior points: u0 = sin(pi x) and a load M_tau c with Gaussian
+    Legendre coefficients c ~ N(0, 1) at every point (layout
+    [point][slab][k]).  Returns (u0, f)."""
+    rng = np.random.default_rng(seed)
+    P = p + 1
+    tau = T / N
+    x = np.arange(1, nx + 1) / (nx + 1.0)
+    c = rng.standard_normal((nx, N, P))
+    f = (c * (tau / (2.0 * np.arange(P) + 1.0))[None, None, :]).reshape(-1)
+    return np.sin(np.pi * x), f
