@@ -28,7 +28,7 @@ struct HeatArgs {
     int64_t N, Nc;          // slabs of this level and of the next
     double ih2;             // 1 / h^2
     double omc, om;         // 1 - omega, omega
-    int nx, halo, tile_out, pre, post, next, norm_f;
+    int nx, halo, tile_out, sweeps, norm_f;
 };
 
 hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, hipStream_t s);

@@ -15,6 +15,13 @@
 // A tile keeps its slabs' iterate and the forward-elimination values in a
 // workspace of its own ([point][lane][k], coalesced); its first `halo`
 // slabs are recomputed copies of the left neighbour's and never stored.
+//
+// The walks over the points are sequential (the elimination carries a value
+// from point to point), so they are pipelined: points are loaded in blocks,
+// a block's loads issued before the previous block's arithmetic runs.  The
+// first sweep of a leg reads the caller's iterate (and adds the prolongated
+// correction) on its way, and the last back substitution writes the result
+// and the residual, so a leg makes 2 walks per sweep and no other pass.
 #include <hip/hip_runtime.h>
 
 #include "tmg_heat.h"
@@ -23,6 +30,13 @@ namespace tmg {
 namespace {
 
 constexpr int kHT = kHeatThreads;   // one wavefront
+
+// The tables of a launch (elimination factors, K, M, transfer, u0) are not
+// written while it runs: they are read through the constant address space,
+// as scalar loads of uniform addresses, whose waits do not hold up the
+// vector loads in flight.
+typedef __attribute__((address_space(4))) const double cdouble;
+__device__ __forceinline__ const cdouble *ro(const double *p) { return (const cdouble *)p; }
 
 __device__ __forceinline__ double shr1(double x)
 {
@@ -37,270 +51,504 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
+// Points per block of the pipelined walks: about kHeatBlockValues
+// coefficients per array (two register buffers of up to three B x P arrays).
+#ifndef TMG_HEAT_BLOCK_VALUES
+#define TMG_HEAT_BLOCK_VALUES 8
+#endif
+template <int P>
+constexpr int kHB = (TMG_HEAT_BLOCK_VALUES / P) < 2 ? 2 : TMG_HEAT_BLOCK_VALUES / P;
+
+// Walks blocks 0 .. nb-1 (or nb-1 .. 0 when rev): load(b, buf) issues the
+// loads of block b into a register buffer, run(b, buf) consumes it.  The
+// next block's loads are issued before a block runs (past the last block
+// they fetch the last block again), and an empty asm with a memory clobber
+// keeps the compiler from moving them down to their uses.
+template <class Buf, class Load, class Run>
+__device__ __forceinline__ void pipe2(int nb, bool rev, Load &&load, Run &&run)
+{
+    if (nb <= 0) return;
+    Buf A, Q;
+    const int st = rev ? -1 : 1;
+    auto clampb = [&](int x) { return x < 0 ? 0 : (x >= nb ? nb - 1 : x); };
+    int b = rev ? nb - 1 : 0;
+    load(b, A);
+    for (int t = 0; t < nb; t += 2, b += 2 * st) {
+        load(clampb(b + st), Q);
+        __asm__ volatile("" ::: "memory");
+        run(b, A);
+        if (t + 1 >= nb) break;
+        load(clampb(b + 2 * st), A);
+        __asm__ volatile("" ::: "memory");
+        run(b + st, Q);
+    }
+}
+
+// Where a walk takes the iterate from: the tile's workspace, the caller's
+// u_in, or zero (u_in null).
+enum HSrc { kFromWs = 0, kFromIn = 1, kFromZero = 2 };
+
 template <int P>
 struct HLeg {
+    static constexpr int B = kHB<P>;
     const HeatArgs &a;
-    int li;
-    int64_t m;
-    bool valid, out;
+    int li, nb;
+    int64_t m, mc;   // the lane's slab, and that slab clamped into the level
+    bool valid, out, resid, norm;
     double *wu, *wy;
-    __device__ HLeg(const HeatArgs &a_) : a(a_)
+    __device__ __forceinline__ HLeg(const HeatArgs &a_) : a(a_)
     {
         li = threadIdx.x;
         m = (int64_t)blockIdx.x * a.tile_out - a.halo + li;
         valid = m >= 0 && m < a.N;
+        mc = m < 0 ? 0 : (m >= a.N ? a.N - 1 : m);
         out = li >= a.halo && valid;
+        nb = (a.nx + B - 1) / B;
+        norm = a.partial && !a.norm_f;
+        resid = norm || a.rc;
         wu = a.ws + (int64_t)blockIdx.x * 2 * a.nx * kHT * P;
         wy = wu + (int64_t)a.nx * kHT * P;
     }
-    __device__ double *U(int i) const { return wu + ((int64_t)i * kHT + li) * P; }
-    __device__ double *Y(int i) const { return wy + ((int64_t)i * kHT + li) * P; }
-    // right-hand side at point i (u0 folded into slab 0 at level 0)
-    __device__ void rhs(int i, double (&x)[P]) const
-    {
-#pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = valid ? a.f[((int64_t)i * a.N + m) * P + k] : 0.0;
-        if (a.u0 && m == 0)
-#pragma unroll
-            for (int k = 0; k < P; ++k) x[k] += a.u0[i] * ((k & 1) ? -1.0 : 1.0);
-    }
-    __device__ void ld(const double *p, double (&x)[P]) const
+    // Loads are issued without branches (a lane outside the level loads its
+    // clamped slab, a point past the last loads the last point); what they
+    // bring is masked where it is used.
+    __device__ __forceinline__ int row(int i) const { return i < a.nx ? i : a.nx - 1; }
+    __device__ __forceinline__ double *U(int i) const { return wu + ((int64_t)i * kHT + li) * P; }
+    __device__ __forceinline__ double *Y(int i) const { return wy + ((int64_t)i * kHT + li) * P; }
+    __device__ __forceinline__ void ld(const double *p, double (&x)[P]) const
     {
 #pragma unroll
         for (int k = 0; k < P; ++k) x[k] = p[k];
     }
-    __device__ void st(double *p, const double (&x)[P]) const
+    __device__ __forceinline__ void st(double *p, const double (&x)[P]) const
     {
 #pragma unroll
         for (int k = 0; k < P; ++k) p[k] = x[k];
     }
-    // end value c^T u of the left slab (c = 1): lane 0 sees zero
-    __device__ double wl(const double (&u)[P]) const
+    __device__ __forceinline__ void mask(double (&x)[P]) const
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = valid ? x[k] : 0.0;
+    }
+    // the lane's slab of a [point][slab][k] array at point i
+    __device__ __forceinline__ const double *at(const double *v, int i) const
+    {
+        return v + ((int64_t)row(i) * a.N + mc) * P;
+    }
+    // right-hand side f at point i (u0 enters slab 0 as its left end value,
+    // see wl); masked by the caller
+    __device__ __forceinline__ void ld_rhs(int i, double (&x)[P]) const { ld(at(a.f, i), x); }
+    // the iterate at point i (masked by the caller when from u_in)
+    template <int SRC>
+    __device__ __forceinline__ void ld_iter(int i, double (&u)[P]) const
+    {
+        if constexpr (SRC == kFromWs) ld(U(row(i)), u);
+        else if constexpr (SRC == kFromIn) ld(at(a.u_in, i), u);
+        else
+#pragma unroll
+            for (int k = 0; k < P; ++k) u[k] = 0.0;
+    }
+    __device__ __forceinline__ void ld_e(int i, double (&e)[P]) const
+    {
+        ld(a.e + ((int64_t)row(i) * a.Nc + mc / 2) * P, e);
+    }
+    // u_m += R_i^T e_{m/2} (i the parity of m); e masked here
+    __device__ __forceinline__ void add_e(double (&e)[P], double (&u)[P]) const
+    {
+        mask(e);
+        const cdouble *R = ro(a.R);
+        const bool odd = m & 1;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = 0; l < P; ++l) t += (odd ? R[P * P + k * P + l] : R[k * P + l]) * e[l];
+            u[k] += t;
+        }
+    }
+    // end value c^T u of the left slab (c = 1) at point i: lane 0 sees zero,
+    // slab 0 at level 0 the initial value u0 (its left lane, outside the
+    // time interval, holds zero)
+    __device__ __forceinline__ double wl(int i, const double (&u)[P]) const
     {
         double w = 0.0;
 #pragma unroll
         for (int k = 0; k < P; ++k) w += u[k];
-        return shr1(w);
+        w = shr1(w);
+        const double g = a.u0 ? ro(a.u0)[i] : 0.0;
+        return m == 0 ? w + g : w;
     }
-    // u <- (1 - omega) u + omega A_h^{-1} (f + v w_left), nsweep times
-    __device__ void sweeps(int nsweep) const
+    // residual at point i: f + v w_left - (K u_i + M (L_h u)_i), with um, up
+    // the neighbouring points' iterates (zero beyond the ends) and fi the
+    // masked f; its square into acc, its restriction into rc
+    __device__ __forceinline__ void resid_point(int i, const double (&um)[P], const double (&u)[P],
+                                                const double (&up)[P], const double (&fi)[P],
+                                                double &acc) const
     {
-        for (int s = 0; s < nsweep; ++s) {
-            double y[P];
-#pragma unroll
-            for (int k = 0; k < P; ++k) y[k] = 0.0;
-            for (int i = 0; i < a.nx; ++i) {
-                double u[P], z[P];
-                ld(U(i), u);
-                const double w = wl(u);
-                rhs(i, z);
-#pragma unroll
-                for (int k = 0; k < P; ++k)
-                    z[k] += ((k & 1) ? -w : w) + a.Md[k] * a.ih2 * y[k];   // - E y_{i-1}
-                const double *Ci = a.Cinv + (int64_t)i * P * P;
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int l = 0; l < P; ++l) t += Ci[k * P + l] * z[l];
-                    y[k] = t;
-                }
-                st(Y(i), y);
-            }
-            double x[P];
-#pragma unroll
-            for (int k = 0; k < P; ++k) x[k] = 0.0;
-            for (int i = a.nx - 1; i >= 0; --i) {
-                double yi[P], u[P];
-                ld(Y(i), yi);
-                const double *Gi = a.G + (int64_t)i * P * P;
-                double xn[P];
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    double t = yi[k];
-#pragma unroll
-                    for (int l = 0; l < P; ++l) t -= Gi[k * P + l] * x[l];
-                    xn[k] = t;
-                }
-#pragma unroll
-                for (int k = 0; k < P; ++k) x[k] = xn[k];
-                ld(U(i), u);
-#pragma unroll
-                for (int k = 0; k < P; ++k) u[k] = a.omc * u[k] + a.om * x[k];
-                st(U(i), u);
-            }
-        }
-    }
-    // residual at point i: f + v w_left - (K u_i + M (L_h u)_i); um, up the
-    // neighbouring points' iterates (zero beyond the ends)
-    __device__ void residual(int i, const double (&um)[P], const double (&u)[P],
-                             const double (&up)[P], double (&r)[P]) const
-    {
-        const double w = wl(u);
-        rhs(i, r);
+        const double w = wl(i, u);
+        double r[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            double s = r[k] + ((k & 1) ? -w : w);
+            double s = fi[k] + ((k & 1) ? -w : w);
 #pragma unroll
-            for (int l = 0; l < P; ++l) s -= a.K[k * P + l] * u[l];
-            s -= a.Md[k] * (2.0 * u[k] - um[k] - up[k]) * a.ih2;
+            for (int l = 0; l < P; ++l) s -= ro(a.K)[k * P + l] * u[l];
+            s -= ro(a.Md)[k] * (2.0 * u[k] - um[k] - up[k]) * a.ih2;
             r[k] = s;
         }
-    }
-};
-
-template <int P>
-__global__ __launch_bounds__(kHT) void k_hleg(HeatArgs a)
-{
-    const HLeg<P> g(a);
-    // the initial iterate of the tile's slabs into the workspace
-    for (int i = 0; i < a.nx; ++i) {
-        double u[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k)
-            u[k] = (a.u_in && g.valid) ? a.u_in[((int64_t)i * a.N + g.m) * P + k] : 0.0;
-        g.st(g.U(i), u);
-    }
-    if (a.norm_f) {
-        double acc = 0.0;
-        for (int i = 0; i < a.nx; ++i) {
-            double x[P];
-            g.rhs(i, x);
-#pragma unroll
-            for (int k = 0; k < P; ++k) acc += g.out ? x[k] * x[k] : 0.0;
-        }
-        acc = wave_sum(acc);
-        if (g.li == 0) a.partial[blockIdx.x] = acc;
-    }
-    g.sweeps(a.pre);
-    if (a.e) {
-        // u_m += R_i^T e_{m/2} at every point (i the parity of m)
-        const int par = (int)(g.m & 1);
-        const double *R = a.R + par * P * P;
-        for (int i = 0; i < a.nx; ++i) {
-            double u[P], e[P];
-            g.ld(g.U(i), u);
-#pragma unroll
-            for (int k = 0; k < P; ++k)
-                e[k] = g.valid ? a.e[((int64_t)i * a.Nc + g.m / 2) * P + k] : 0.0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double t = 0.0;
-#pragma unroll
-                for (int l = 0; l < P; ++l) t += R[k * P + l] * e[l];
-                u[k] += t;
-            }
-            g.st(g.U(i), u);
-        }
-    }
-    g.sweeps(a.post);
-    if (a.u_out && g.out)
-        for (int i = 0; i < a.nx; ++i) {
-            double u[P];
-            g.ld(g.U(i), u);
-            g.st(a.u_out + ((int64_t)i * a.N + g.m) * P, u);
-        }
-    const bool norm = a.partial && !a.norm_f;
-    if (!norm && !a.rc) return;
-    g.sweeps(a.next);
-    double acc = 0.0;
-    double um[P], u[P], up[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) um[k] = 0.0;
-    g.ld(g.U(0), u);
-    for (int i = 0; i < a.nx; ++i) {
-        if (i + 1 < a.nx) g.ld(g.U(i + 1), up);
-        else
-#pragma unroll
-            for (int k = 0; k < P; ++k) up[k] = 0.0;
-        double r[P];
-        g.residual(i, um, u, up, r);
         if (norm)
 #pragma unroll
-            for (int k = 0; k < P; ++k) acc += g.out ? r[k] * r[k] : 0.0;
+            for (int k = 0; k < P; ++k) acc += out ? r[k] * r[k] : 0.0;
         if (a.rc) {
             // rc_{m/2} = R_1 r_m + R_2 r_{m+1}: the even slab's lane takes
             // its partner's residual from the next lane
             double rn[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[k], 1, 64);
-            if (g.out && !(g.m & 1)) {
+            if (out && !(m & 1)) {
                 double rc[P];
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     double t = 0.0;
 #pragma unroll
                     for (int l = 0; l < P; ++l)
-                        t += a.R[l * P + k] * r[l] + a.R[P * P + l * P + k] * rn[l];
+                        t += ro(a.R)[l * P + k] * r[l] + ro(a.R)[P * P + l * P + k] * rn[l];
                     rc[k] = t;
                 }
-                g.st(a.rc + ((int64_t)i * a.Nc + g.m / 2) * P, rc);
+                st(a.rc + ((int64_t)i * a.Nc + m / 2) * P, rc);
             }
         }
+    }
+    // Forward elimination of one damped block Jacobi sweep: y_i = C_i^{-1}
+    // (f_i + v w_left,i - E y_{i-1}) into the workspace.  The iterate from
+    // SRC; ADDE: the prolongated correction is added first; unless it came
+    // unchanged from the workspace, the iterate is stored there on the way.
+    template <int SRC, bool ADDE>
+    __device__ __forceinline__ void forward() const
+    {
+        struct Buf {
+            double u[B][P], z[B][P], e[ADDE ? B : 1][P];
+        };
+        double y[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            um[k] = u[k];
-            u[k] = up[k];
+        for (int k = 0; k < P; ++k) y[k] = 0.0;
+        pipe2<Buf>(
+            nb, false,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    ld_iter<SRC>(b * B + j, q.u[j]);
+                    if constexpr (ADDE) ld_e(b * B + j, q.e[j]);
+                    ld_rhs(b * B + j, q.z[j]);
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const int i = b * B + j;
+                    if (i < a.nx) {
+                        if constexpr (SRC == kFromIn) mask(q.u[j]);
+                        if constexpr (ADDE) add_e(q.e[j], q.u[j]);
+                        if constexpr (SRC != kFromWs || ADDE) st(U(i), q.u[j]);
+                        mask(q.z[j]);
+                        const double w = wl(i, q.u[j]);
+                        double z[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k)   // - E y_{i-1} = + M y_{i-1} / h^2
+                            z[k] = q.z[j][k] + ((k & 1) ? -w : w) + ro(a.Md)[k] * a.ih2 * y[k];
+                        const cdouble *Ci = ro(a.Cinv) + (int64_t)i * P * P;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = 0.0;
+#pragma unroll
+                            for (int l = 0; l < P; ++l) t += Ci[k * P + l] * z[l];
+                            y[k] = t;
+                        }
+                        st(Y(i), y);
+                    }
+                }
+            });
+    }
+    // Back substitution x_i = y_i - C_i^{-1} E x_{i+1} and the damped update
+    // u_i <- (1 - omega) u_i + omega x_i.  FIN (the leg's last sweep): the
+    // result goes to u_out and, one point behind, into the residual, and the
+    // workspace is not written.
+    template <bool FIN>
+    __device__ __forceinline__ void backward(double &acc) const
+    {
+        struct Buf {
+            double y[B][P], u[B][P], f[FIN ? B : 1][P];
+        };
+        double x[P], u1[P], u2[P], f1[P];   // FIN: result at points i+1, i+2, f at i+1
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = u1[k] = u2[k] = f1[k] = 0.0;
+        pipe2<Buf>(
+            nb, true,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    ld(Y(row(b * B + j)), q.y[j]);
+                    ld(U(row(b * B + j)), q.u[j]);
+                    if constexpr (FIN) ld_rhs(b * B + j, q.f[j]);
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = B - 1; j >= 0; --j) {
+                    const int i = b * B + j;
+                    if (i < a.nx) {
+                        const cdouble *Gi = ro(a.G) + (int64_t)i * P * P;
+                        double xn[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = q.y[j][k];
+#pragma unroll
+                            for (int l = 0; l < P; ++l) t -= Gi[k * P + l] * x[l];
+                            xn[k] = t;
+                        }
+                        double u[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            x[k] = xn[k];
+                            u[k] = a.omc * q.u[j][k] + a.om * xn[k];
+                        }
+                        if constexpr (!FIN) {
+                            st(U(i), u);
+                        } else {
+                            if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, u);
+                            if (resid && i + 1 < a.nx) resid_point(i + 1, u, u1, u2, f1, acc);
+                            mask(q.f[j]);
+#pragma unroll
+                            for (int k = 0; k < P; ++k) {
+                                u2[k] = u1[k];
+                                u1[k] = u[k];
+                                f1[k] = q.f[j][k];
+                            }
+                        }
+                    }
+                }
+            });
+        if constexpr (FIN)
+            if (resid) {
+                double z0[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) z0[k] = 0.0;
+                resid_point(0, z0, u1, u2, f1, acc);
+            }
+    }
+    // The leg's outputs from an iterate no sweep follows (from SRC), after
+    // adding the correction when ADDE: u_out and, one point behind, the
+    // residual.
+    template <int SRC, bool ADDE>
+    __device__ __forceinline__ void final_pass(double &acc) const
+    {
+        struct Buf {
+            double u[B][P], f[B][P], e[ADDE ? B : 1][P];
+        };
+        double um[P], uc[P], fc[P];   // iterate at points i-2, i-1, f at i-1
+#pragma unroll
+        for (int k = 0; k < P; ++k) um[k] = uc[k] = fc[k] = 0.0;
+        pipe2<Buf>(
+            nb, false,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    ld_iter<SRC>(b * B + j, q.u[j]);
+                    if constexpr (ADDE) ld_e(b * B + j, q.e[j]);
+                    ld_rhs(b * B + j, q.f[j]);
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const int i = b * B + j;
+                    if (i < a.nx) {
+                        if constexpr (SRC == kFromIn) mask(q.u[j]);
+                        if constexpr (ADDE) add_e(q.e[j], q.u[j]);
+                        if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, q.u[j]);
+                        if (resid && i > 0) resid_point(i - 1, um, uc, q.u[j], fc, acc);
+                        mask(q.f[j]);
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            um[k] = uc[k];
+                            uc[k] = q.u[j][k];
+                            fc[k] = q.f[j][k];
+                        }
+                    }
+                }
+            });
+        if (resid) {
+            double z0[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) z0[k] = 0.0;
+            resid_point(a.nx - 1, um, uc, z0, fc, acc);
         }
     }
-    if (norm) {
+    // squared norm of the right-hand side (the tile's own slabs)
+    __device__ __forceinline__ void norm_rhs(double &acc) const
+    {
+        struct Buf {
+            double f[B][P];
+        };
+        pipe2<Buf>(
+            nb, false,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) ld_rhs(b * B + j, q.f[j]);
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+                    if (b * B + j < a.nx) {
+                        // the folded f + v u0 of slab 0
+                        const double g0 = a.u0 ? ro(a.u0)[b * B + j] : 0.0, g = m == 0 ? g0 : 0.0;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            const double x = q.f[j][k] + ((k & 1) ? -g : g);
+                            acc += out ? x * x : 0.0;
+                        }
+                    }
+            });
+    }
+};
+
+// One leg on one level: the iterate u_in (zero when null) plus the
+// prolongated correction e (when given), `sweeps` damped block Jacobi
+// sweeps, then the result into u_out, and its residual restricted into rc
+// and/or squared into the tile's partial.  With norm_f, only the squared
+// norm of the right-hand side.  Each walk variant appears once, so that no
+// loop holds the state of several.
+template <int P>
+__global__ __launch_bounds__(kHT) void k_hleg(HeatArgs a)
+{
+    const HLeg<P> g(a);
+    double acc = 0.0;
+    if (a.norm_f) {
+        g.norm_rhs(acc);
+    } else if (a.sweeps == 0) {
+        if (a.u_in) {
+            if (a.e) g.template final_pass<kFromIn, true>(acc);
+            else g.template final_pass<kFromIn, false>(acc);
+        } else {
+            if (a.e) g.template final_pass<kFromZero, true>(acc);
+            else g.template final_pass<kFromZero, false>(acc);
+        }
+    } else {
+        if (a.u_in) {
+            if (a.e) g.template forward<kFromIn, true>();
+            else g.template forward<kFromIn, false>();
+        } else {
+            if (a.e) g.template forward<kFromZero, true>();
+            else g.template forward<kFromZero, false>();
+        }
+        for (int s = 1; s < a.sweeps; ++s) {
+            g.template backward<false>(acc);
+            g.template forward<kFromWs, false>();
+        }
+        g.template backward<true>(acc);
+    }
+    if (a.partial) {
         acc = wave_sum(acc);
         if (g.li == 0) a.partial[blockIdx.x] = acc;
     }
 }
 
 // Exact solve on the coarsest level: forward substitution over its slabs,
-// each slab block solved by the elimination over the points (one lane).
+// each slab block solved by the elimination over the points (one lane, the
+// walks pipelined as in the legs).
 template <int P>
 __global__ __launch_bounds__(kHT) void k_hcoarse(HeatArgs a)
 {
     if (threadIdx.x != 0) return;
+    constexpr int B = kHB<P>;
+    const int nb = (a.nx + B - 1) / B;
     double *y = a.ws;
     for (int64_t n = 0; n < a.N; ++n) {
+        struct FB {
+            double z[B][P], up[B][P], g[B];
+        };
         double yp[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) yp[k] = 0.0;
-        for (int i = 0; i < a.nx; ++i) {
-            double z[P];
-            double w = 0.0;
-            if (n > 0)
+        pipe2<FB>(
+            nb, false,
+            [&](int b, FB &q) {
 #pragma unroll
-                for (int k = 0; k < P; ++k) w += a.u_out[((int64_t)i * a.N + n - 1) * P + k];
+                for (int j = 0; j < B; ++j) {
+                    const int i = b * B + j;
+                    if (i < a.nx) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                z[k] = a.f[((int64_t)i * a.N + n) * P + k] + ((k & 1) ? -w : w) +
-                       a.Md[k] * a.ih2 * yp[k];
-                if (a.u0 && n == 0) z[k] += a.u0[i] * ((k & 1) ? -1.0 : 1.0);
-            }
-            const double *Ci = a.Cinv + (int64_t)i * P * P;
+                        for (int k = 0; k < P; ++k) {
+                            q.z[j][k] = a.f[((int64_t)i * a.N + n) * P + k];
+                            q.up[j][k] = n > 0 ? a.u_out[((int64_t)i * a.N + n - 1) * P + k] : 0.0;
+                        }
+                        q.g[j] = (a.u0 && n == 0) ? ro(a.u0)[i] : 0.0;
+                    }
+                }
+            },
+            [&](int b, FB &q) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double t = 0.0;
+                for (int j = 0; j < B; ++j) {
+                    const int i = b * B + j;
+                    if (i < a.nx) {
+                        double w = q.g[j];   // u0 enters slab 0 as the left end value
 #pragma unroll
-                for (int l = 0; l < P; ++l) t += Ci[k * P + l] * z[l];
-                yp[k] = t;
-                y[i * P + k] = t;
-            }
-        }
+                        for (int k = 0; k < P; ++k) w += q.up[j][k];
+                        double z[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k)
+                            z[k] = q.z[j][k] + ((k & 1) ? -w : w) + ro(a.Md)[k] * a.ih2 * yp[k];
+                        const cdouble *Ci = ro(a.Cinv) + (int64_t)i * P * P;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = 0.0;
+#pragma unroll
+                            for (int l = 0; l < P; ++l) t += Ci[k * P + l] * z[l];
+                            yp[k] = t;
+                        }
+#pragma unroll
+                        for (int k = 0; k < P; ++k) y[i * P + k] = yp[k];
+                    }
+                }
+            });
+        struct BB {
+            double y[B][P];
+        };
         double x[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) x[k] = 0.0;
-        for (int i = a.nx - 1; i >= 0; --i) {
-            const double *Gi = a.G + (int64_t)i * P * P;
-            double xn[P];
+        pipe2<BB>(
+            nb, true,
+            [&](int b, BB &q) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                double t = y[i * P + k];
+                for (int j = 0; j < B; ++j) {
+                    const int i = b * B + j;
+                    if (i < a.nx)
 #pragma unroll
-                for (int l = 0; l < P; ++l) t -= Gi[k * P + l] * x[l];
-                xn[k] = t;
-            }
+                        for (int k = 0; k < P; ++k) q.y[j][k] = y[i * P + k];
+                }
+            },
+            [&](int b, BB &q) {
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                x[k] = xn[k];
-                a.u_out[((int64_t)i * a.N + n) * P + k] = xn[k];
-            }
-        }
+                for (int j = B - 1; j >= 0; --j) {
+                    const int i = b * B + j;
+                    if (i < a.nx) {
+                        const cdouble *Gi = ro(a.G) + (int64_t)i * P * P;
+                        double xn[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = q.y[j][k];
+#pragma unroll
+                            for (int l = 0; l < P; ++l) t -= Gi[k * P + l] * x[l];
+                            xn[k] = t;
+                        }
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            x[k] = xn[k];
+                            a.u_out[((int64_t)i * a.N + n) * P + k] = xn[k];
+                        }
+                    }
+                }
+            });
     }
 }
 

@@ -11,6 +11,7 @@
 // after every cycle.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -66,7 +67,8 @@ void heat_free(tmg_heat_ctx *c)
     c->allocs.clear();
 }
 
-int rs2(int x) { return (x + 1) & ~1; }   // even halos: restriction pairs stay in a tile
+// even halos of at least 2 slabs: restriction pairs stay in a tile
+int rs2(int x) { return (x + 1) & ~1; }
 int TO(int H) { return kHeatThreads - H; }
 int64_t tiles(int64_t N, int H) { return (N + TO(H) - 1) / TO(H); }
 // The largest halo of any launch (down legs nu1 + 1, up legs with the norm
@@ -120,13 +122,13 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
         a.rc = c->f[l + 1];
         a.halo = H;
         a.tile_out = TO(H);
-        a.pre = nu1;
+        a.sweeps = nu1;
         if ((rc = launch_leg_checked(c, a, tiles(c->Nl[l], H), s))) return rc;
     }
     for (int g = 0; g < c->opt.gamma; ++g)
         if ((rc = visit(c, l + 1, g == 0, s))) return rc;
     {
-        const int H = rs2(nu2 + (partial ? 1 : 0));
+        const int H = std::max(2, rs2(nu2 + (partial ? 1 : 0)));
         HeatArgs a = base_args(c, l);
         a.f = f;
         a.u0 = u0;
@@ -136,7 +138,7 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
         a.partial = partial;
         a.halo = H;
         a.tile_out = TO(H);
-        a.post = nu2;
+        a.sweeps = nu2;
         if ((rc = launch_leg_checked(c, a, tiles(c->Nl[l], H), s))) return rc;
         if (partial) HCHK(c, launch_hsum(partial, tiles(c->Nl[l], H), c->sum, s));
     }

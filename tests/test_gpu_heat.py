@@ -59,6 +59,29 @@ def test_heat_cycles(p, gamma, nx, N, T, omega):
     s.close()
 
 
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("nu1,nu2", [(0, 2), (2, 0), (0, 0), (1, 3), (3, 1)])
+@pytest.mark.parametrize("nx,n_coarse", [(1, 2), (13, 1), (40, 4)])
+def test_heat_cycles_sweeps(p, nu1, nu2, nx, n_coarse):
+    """Every leg shape: no pre-sweeps (the first post-sweep reads the
+    caller's iterate and adds the correction), no post-sweeps (the
+    correction and the outputs in a pass of their own), none at all; point
+    counts that leave a ragged last block; several coarsest slabs."""
+    rng = np.random.default_rng(1300 + 10 * nu1 + nu2 + nx)
+    N, T = 128, 0.3
+    P = p + 1
+    kw = dict(nu1=nu1, nu2=nu2, n_coarse=n_coarse)
+    s = B().HeatSolver(N, nx, T, p=p, **kw)
+    f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
+    u0 = rng.standard_normal(nx)
+    du = dev(u)
+    for _ in range(2):
+        s.vcycle(dev(f), dev(u0), du)
+    ref = core.heat_cycles(p, nx, T, core.heat_fold(p, nx, u0, f), u, 2, core.Opts(**kw))
+    assert relerr(host(du), ref) <= TOL
+    s.close()
+
+
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
 @pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("nx", [1, 31, 127])
