@@ -13,7 +13,7 @@ constexpr int kHeatThreads = 64;   // one wavefront per tile of as many slabs
 // level's exact solve (k_hcoarse: f, u0, u_out, Cinv, G, Md, ih2, ws, N, nx).
 struct HeatArgs {
     const double *f;        // right-hand side of the level, [point][slab][k]
-    const double *u0;       // [nx] initial values folded into slab 0 (level 0), or null
+    const double *u0;       // [nx] initial values entering slab 0 (zeros above level 0)
     const double *u_in;     // iterate (null: zero)
     const double *e;        // next level's correction to prolongate (null: none)
     double *u_out;          // result (null: none)

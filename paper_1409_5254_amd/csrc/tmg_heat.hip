@@ -91,23 +91,49 @@ enum HSrc { kFromWs = 0, kFromIn = 1, kFromZero = 2 };
 template <int P>
 struct HLeg {
     static constexpr int B = kHB<P>;
+    // up to P = 3 the per-point factors travel with the prefetched data and
+    // the small slab tables stay in registers; above, both are read per
+    // point through the constant address space
+    static constexpr bool kRegTab = P <= 3;
     const HeatArgs &a;
     int li, nb;
     int64_t m, mc;   // the lane's slab, and that slab clamped into the level
-    bool valid, out, resid, norm;
+    bool valid, out, resid, norm, odd;
     double *wu, *wy;
+    double mdh[P];                          // diag(M) / h^2
+    double Kt[kRegTab ? P * P : 1];         // K
+    double Rt[kRegTab ? 2 * P * P : 1];     // R_1^T, R_2^T
     __device__ __forceinline__ HLeg(const HeatArgs &a_) : a(a_)
     {
         li = threadIdx.x;
         m = (int64_t)blockIdx.x * a.tile_out - a.halo + li;
         valid = m >= 0 && m < a.N;
         mc = m < 0 ? 0 : (m >= a.N ? a.N - 1 : m);
+        odd = m & 1;
         out = li >= a.halo && valid;
         nb = (a.nx + B - 1) / B;
         norm = a.partial && !a.norm_f;
         resid = norm || a.rc;
         wu = a.ws + (int64_t)blockIdx.x * 2 * a.nx * kHT * P;
         wy = wu + (int64_t)a.nx * kHT * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) mdh[k] = ro(a.Md)[k] * a.ih2;
+        if constexpr (kRegTab) {
+#pragma unroll
+            for (int q = 0; q < P * P; ++q) Kt[q] = ro(a.K)[q];
+#pragma unroll
+            for (int q = 0; q < 2 * P * P; ++q) Rt[q] = ro(a.R)[q];
+        }
+    }
+    __device__ __forceinline__ double Kc(int q) const
+    {
+        if constexpr (kRegTab) return Kt[q];
+        else return ro(a.K)[q];
+    }
+    __device__ __forceinline__ double Rc(int q) const
+    {
+        if constexpr (kRegTab) return Rt[q];
+        else return ro(a.R)[q];
     }
     // Loads are issued without branches (a lane outside the level loads its
     // clamped slab, a point past the last loads the last point); what they
@@ -115,11 +141,13 @@ struct HLeg {
     __device__ __forceinline__ int row(int i) const { return i < a.nx ? i : a.nx - 1; }
     __device__ __forceinline__ double *U(int i) const { return wu + ((int64_t)i * kHT + li) * P; }
     __device__ __forceinline__ double *Y(int i) const { return wy + ((int64_t)i * kHT + li) * P; }
-    __device__ __forceinline__ void ld(const double *p, double (&x)[P]) const
+    template <int n>
+    __device__ __forceinline__ void ldn(const double *p, double (&x)[n]) const
     {
 #pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = p[k];
+        for (int k = 0; k < n; ++k) x[k] = p[k];
     }
+    __device__ __forceinline__ void ld(const double *p, double (&x)[P]) const { ldn<P>(p, x); }
     __device__ __forceinline__ void st(double *p, const double (&x)[P]) const
     {
 #pragma unroll
@@ -135,9 +163,13 @@ struct HLeg {
     {
         return v + ((int64_t)row(i) * a.N + mc) * P;
     }
-    // right-hand side f at point i (u0 enters slab 0 as its left end value,
-    // see wl); masked by the caller
-    __device__ __forceinline__ void ld_rhs(int i, double (&x)[P]) const { ld(at(a.f, i), x); }
+    // right-hand side f at point i (masked by the caller) and u0 at the
+    // point (zero above level 0), which enters slab 0 as its left end value
+    __device__ __forceinline__ void ld_rhs(int i, double (&x)[P], double &g) const
+    {
+        ld(at(a.f, i), x);
+        g = a.u0[row(i)];
+    }
     // the iterate at point i (masked by the caller when from u_in)
     template <int SRC>
     __device__ __forceinline__ void ld_iter(int i, double (&u)[P]) const
@@ -152,46 +184,49 @@ struct HLeg {
     {
         ld(a.e + ((int64_t)row(i) * a.Nc + mc / 2) * P, e);
     }
+    // the per-point factor table T (C_i^{-1} or C_i^{-1} E) at point i
+    __device__ __forceinline__ void ld_tab(const double *T, int i, double (&c)[P * P]) const
+    {
+        ldn<P * P>(T + (int64_t)row(i) * P * P, c);
+    }
     // u_m += R_i^T e_{m/2} (i the parity of m); e masked here
     __device__ __forceinline__ void add_e(double (&e)[P], double (&u)[P]) const
     {
         mask(e);
-        const cdouble *R = ro(a.R);
-        const bool odd = m & 1;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double t = 0.0;
 #pragma unroll
-            for (int l = 0; l < P; ++l) t += (odd ? R[P * P + k * P + l] : R[k * P + l]) * e[l];
+            for (int l = 0; l < P; ++l) t += (odd ? Rc(P * P + k * P + l) : Rc(k * P + l)) * e[l];
             u[k] += t;
         }
     }
-    // end value c^T u of the left slab (c = 1) at point i: lane 0 sees zero,
-    // slab 0 at level 0 the initial value u0 (its left lane, outside the
-    // time interval, holds zero)
-    __device__ __forceinline__ double wl(int i, const double (&u)[P]) const
+    // end value c^T u of the left slab (c = 1): lane 0 sees zero, slab 0
+    // the initial value g (its left lane, outside the time interval, holds
+    // zero)
+    __device__ __forceinline__ double wl(const double (&u)[P], double g) const
     {
         double w = 0.0;
 #pragma unroll
         for (int k = 0; k < P; ++k) w += u[k];
         w = shr1(w);
-        const double g = a.u0 ? ro(a.u0)[i] : 0.0;
         return m == 0 ? w + g : w;
     }
     // residual at point i: f + v w_left - (K u_i + M (L_h u)_i), with um, up
-    // the neighbouring points' iterates (zero beyond the ends) and fi the
-    // masked f; its square into acc, its restriction into rc
+    // the neighbouring points' iterates (zero beyond the ends), fi the
+    // masked f and g the point's u0; its square into acc, its restriction
+    // into rc
     __device__ __forceinline__ void resid_point(int i, const double (&um)[P], const double (&u)[P],
                                                 const double (&up)[P], const double (&fi)[P],
-                                                double &acc) const
+                                                double g, double &acc) const
     {
-        const double w = wl(i, u);
+        const double w = wl(u, g);
         double r[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double s = fi[k] + ((k & 1) ? -w : w);
 #pragma unroll
-            for (int l = 0; l < P; ++l) s -= ro(a.K)[k * P + l] * u[l];
+            for (int l = 0; l < P; ++l) s -= Kc(k * P + l) * u[l];
             s -= ro(a.Md)[k] * (2.0 * u[k] - um[k] - up[k]) * a.ih2;
             r[k] = s;
         }
@@ -204,14 +239,13 @@ struct HLeg {
             double rn[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[k], 1, 64);
-            if (out && !(m & 1)) {
+            if (out && !odd) {
                 double rc[P];
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     double t = 0.0;
 #pragma unroll
-                    for (int l = 0; l < P; ++l)
-                        t += ro(a.R)[l * P + k] * r[l] + ro(a.R)[P * P + l * P + k] * rn[l];
+                    for (int l = 0; l < P; ++l) t += Rc(l * P + k) * r[l] + Rc(P * P + l * P + k) * rn[l];
                     rc[k] = t;
                 }
                 st(a.rc + ((int64_t)i * a.Nc + m / 2) * P, rc);
@@ -226,7 +260,7 @@ struct HLeg {
     __device__ __forceinline__ void forward() const
     {
         struct Buf {
-            double u[B][P], z[B][P], e[ADDE ? B : 1][P];
+            double u[B][P], z[B][P], e[ADDE ? B : 1][P], c[kRegTab ? B : 1][P * P], g[B];
         };
         double y[P];
 #pragma unroll
@@ -238,7 +272,8 @@ struct HLeg {
                 for (int j = 0; j < B; ++j) {
                     ld_iter<SRC>(b * B + j, q.u[j]);
                     if constexpr (ADDE) ld_e(b * B + j, q.e[j]);
-                    ld_rhs(b * B + j, q.z[j]);
+                    ld_rhs(b * B + j, q.z[j], q.g[j]);
+                    if constexpr (kRegTab) ld_tab(a.Cinv, b * B + j, q.c[j]);
                 }
             },
             [&](int b, Buf &q) {
@@ -250,17 +285,21 @@ struct HLeg {
                         if constexpr (ADDE) add_e(q.e[j], q.u[j]);
                         if constexpr (SRC != kFromWs || ADDE) st(U(i), q.u[j]);
                         mask(q.z[j]);
-                        const double w = wl(i, q.u[j]);
+                        const double w = wl(q.u[j], q.g[j]);
                         double z[P];
 #pragma unroll
                         for (int k = 0; k < P; ++k)   // - E y_{i-1} = + M y_{i-1} / h^2
-                            z[k] = q.z[j][k] + ((k & 1) ? -w : w) + ro(a.Md)[k] * a.ih2 * y[k];
-                        const cdouble *Ci = ro(a.Cinv) + (int64_t)i * P * P;
+                            z[k] = q.z[j][k] + ((k & 1) ? -w : w) + mdh[k] * y[k];
 #pragma unroll
                         for (int k = 0; k < P; ++k) {
                             double t = 0.0;
 #pragma unroll
-                            for (int l = 0; l < P; ++l) t += Ci[k * P + l] * z[l];
+                            for (int l = 0; l < P; ++l) {
+                                double c;
+                                if constexpr (kRegTab) c = q.c[j][k * P + l];
+                                else c = ro(a.Cinv)[(int64_t)i * P * P + k * P + l];
+                                t += c * z[l];
+                            }
                             y[k] = t;
                         }
                         st(Y(i), y);
@@ -276,9 +315,9 @@ struct HLeg {
     __device__ __forceinline__ void backward(double &acc) const
     {
         struct Buf {
-            double y[B][P], u[B][P], f[FIN ? B : 1][P];
+            double y[B][P], u[B][P], f[FIN ? B : 1][P], c[kRegTab ? B : 1][P * P], g[FIN ? B : 1];
         };
-        double x[P], u1[P], u2[P], f1[P];   // FIN: result at points i+1, i+2, f at i+1
+        double x[P], u1[P], u2[P], f1[P], g1 = 0.0;   // FIN: result at i+1, i+2; f, u0 at i+1
 #pragma unroll
         for (int k = 0; k < P; ++k) x[k] = u1[k] = u2[k] = f1[k] = 0.0;
         pipe2<Buf>(
@@ -288,7 +327,8 @@ struct HLeg {
                 for (int j = 0; j < B; ++j) {
                     ld(Y(row(b * B + j)), q.y[j]);
                     ld(U(row(b * B + j)), q.u[j]);
-                    if constexpr (FIN) ld_rhs(b * B + j, q.f[j]);
+                    if constexpr (FIN) ld_rhs(b * B + j, q.f[j], q.g[j]);
+                    if constexpr (kRegTab) ld_tab(a.G, b * B + j, q.c[j]);
                 }
             },
             [&](int b, Buf &q) {
@@ -296,13 +336,17 @@ struct HLeg {
                 for (int j = B - 1; j >= 0; --j) {
                     const int i = b * B + j;
                     if (i < a.nx) {
-                        const cdouble *Gi = ro(a.G) + (int64_t)i * P * P;
                         double xn[P];
 #pragma unroll
                         for (int k = 0; k < P; ++k) {
                             double t = q.y[j][k];
 #pragma unroll
-                            for (int l = 0; l < P; ++l) t -= Gi[k * P + l] * x[l];
+                            for (int l = 0; l < P; ++l) {
+                                double c;
+                                if constexpr (kRegTab) c = q.c[j][k * P + l];
+                                else c = ro(a.G)[(int64_t)i * P * P + k * P + l];
+                                t -= c * x[l];
+                            }
                             xn[k] = t;
                         }
                         double u[P];
@@ -315,7 +359,7 @@ struct HLeg {
                             st(U(i), u);
                         } else {
                             if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, u);
-                            if (resid && i + 1 < a.nx) resid_point(i + 1, u, u1, u2, f1, acc);
+                            if (resid && i + 1 < a.nx) resid_point(i + 1, u, u1, u2, f1, g1, acc);
                             mask(q.f[j]);
 #pragma unroll
                             for (int k = 0; k < P; ++k) {
@@ -323,6 +367,7 @@ struct HLeg {
                                 u1[k] = u[k];
                                 f1[k] = q.f[j][k];
                             }
+                            g1 = q.g[j];
                         }
                     }
                 }
@@ -332,7 +377,7 @@ struct HLeg {
                 double z0[P];
 #pragma unroll
                 for (int k = 0; k < P; ++k) z0[k] = 0.0;
-                resid_point(0, z0, u1, u2, f1, acc);
+                resid_point(0, z0, u1, u2, f1, g1, acc);
             }
     }
     // The leg's outputs from an iterate no sweep follows (from SRC), after
@@ -342,9 +387,9 @@ struct HLeg {
     __device__ __forceinline__ void final_pass(double &acc) const
     {
         struct Buf {
-            double u[B][P], f[B][P], e[ADDE ? B : 1][P];
+            double u[B][P], f[B][P], e[ADDE ? B : 1][P], g[B];
         };
-        double um[P], uc[P], fc[P];   // iterate at points i-2, i-1, f at i-1
+        double um[P], uc[P], fc[P], gc = 0.0;   // iterate at i-2, i-1; f, u0 at i-1
 #pragma unroll
         for (int k = 0; k < P; ++k) um[k] = uc[k] = fc[k] = 0.0;
         pipe2<Buf>(
@@ -354,7 +399,7 @@ struct HLeg {
                 for (int j = 0; j < B; ++j) {
                     ld_iter<SRC>(b * B + j, q.u[j]);
                     if constexpr (ADDE) ld_e(b * B + j, q.e[j]);
-                    ld_rhs(b * B + j, q.f[j]);
+                    ld_rhs(b * B + j, q.f[j], q.g[j]);
                 }
             },
             [&](int b, Buf &q) {
@@ -365,7 +410,7 @@ struct HLeg {
                         if constexpr (SRC == kFromIn) mask(q.u[j]);
                         if constexpr (ADDE) add_e(q.e[j], q.u[j]);
                         if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, q.u[j]);
-                        if (resid && i > 0) resid_point(i - 1, um, uc, q.u[j], fc, acc);
+                        if (resid && i > 0) resid_point(i - 1, um, uc, q.u[j], fc, gc, acc);
                         mask(q.f[j]);
 #pragma unroll
                         for (int k = 0; k < P; ++k) {
@@ -373,6 +418,7 @@ struct HLeg {
                             uc[k] = q.u[j][k];
                             fc[k] = q.f[j][k];
                         }
+                        gc = q.g[j];
                     }
                 }
             });
@@ -380,27 +426,27 @@ struct HLeg {
             double z0[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) z0[k] = 0.0;
-            resid_point(a.nx - 1, um, uc, z0, fc, acc);
+            resid_point(a.nx - 1, um, uc, z0, fc, gc, acc);
         }
     }
     // squared norm of the right-hand side (the tile's own slabs)
     __device__ __forceinline__ void norm_rhs(double &acc) const
     {
         struct Buf {
-            double f[B][P];
+            double f[B][P], g[B];
         };
         pipe2<Buf>(
             nb, false,
             [&](int b, Buf &q) {
 #pragma unroll
-                for (int j = 0; j < B; ++j) ld_rhs(b * B + j, q.f[j]);
+                for (int j = 0; j < B; ++j) ld_rhs(b * B + j, q.f[j], q.g[j]);
             },
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j)
                     if (b * B + j < a.nx) {
                         // the folded f + v u0 of slab 0
-                        const double g0 = a.u0 ? ro(a.u0)[b * B + j] : 0.0, g = m == 0 ? g0 : 0.0;
+                        const double g = m == 0 ? q.g[j] : 0.0;
 #pragma unroll
                         for (int k = 0; k < P; ++k) {
                             const double x = q.f[j][k] + ((k & 1) ? -g : g);
@@ -481,7 +527,7 @@ __global__ __launch_bounds__(kHT) void k_hcoarse(HeatArgs a)
                             q.z[j][k] = a.f[((int64_t)i * a.N + n) * P + k];
                             q.up[j][k] = n > 0 ? a.u_out[((int64_t)i * a.N + n - 1) * P + k] : 0.0;
                         }
-                        q.g[j] = (a.u0 && n == 0) ? ro(a.u0)[i] : 0.0;
+                        q.g[j] = n == 0 ? a.u0[i] : 0.0;
                     }
                 }
             },

@@ -32,6 +32,7 @@ struct tmg_heat_ctx {
     std::vector<double> omega;
     std::vector<double *> f, x, sx, Cinv, G, K, Md;   // per level (device)
     double *R = nullptr, *ws = nullptr, *partial = nullptr, *sum = nullptr;
+    double *zeros = nullptr;   // nx zeros: the u0 of the levels above 0
     int64_t ws_tiles = 0;
     std::vector<void *> allocs;
     int last_hip = 0;
@@ -93,6 +94,7 @@ HeatArgs base_args(const tmg_heat_ctx *c, int l)
     a.K = c->K[l];
     a.Md = c->Md[l];
     a.R = c->R;
+    a.u0 = c->zeros;
     a.ws = c->ws;
     a.N = c->Nl[l];
     a.Nc = l + 1 < c->L ? c->Nl[l + 1] : 0;
@@ -116,7 +118,7 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
         const int H = rs2(nu1 + 1);
         HeatArgs a = base_args(c, l);
         a.f = f;
-        a.u0 = u0;
+        if (u0) a.u0 = u0;
         a.u_in = in;
         a.u_out = c->sx[l];
         a.rc = c->f[l + 1];
@@ -131,7 +133,7 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
         const int H = std::max(2, rs2(nu2 + (partial ? 1 : 0)));
         HeatArgs a = base_args(c, l);
         a.f = f;
-        a.u0 = u0;
+        if (u0) a.u0 = u0;
         a.u_in = c->sx[l];
         a.e = c->x[l + 1];
         a.u_out = out;
@@ -293,12 +295,12 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
         R[P * P + q] = R2T[q];
     }
     c->ws_tiles = maxtiles;
-    if ((rc = halloc(c, &c->R, R.size())) ||
+    if ((rc = halloc(c, &c->R, R.size())) || (rc = halloc(c, &c->zeros, nx)) ||
         (rc = halloc(c, &c->ws, (size_t)maxtiles * 2 * nx * kHeatThreads * P)) ||
         (rc = halloc(c, &c->partial, maxtiles)) || (rc = halloc(c, &c->sum, 1)))
         return fail(rc);
     if (hipMemcpyAsync(c->R, R.data(), R.size() * 8, hipMemcpyHostToDevice, s) ||
-        hipStreamSynchronize(s))
+        hipMemsetAsync(c->zeros, 0, sizeof(double) * nx, s) || hipStreamSynchronize(s))
         return fail(TMG_ERR_HIP);
     *hp = c;
     return TMG_OK;
