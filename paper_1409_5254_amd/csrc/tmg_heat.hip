@@ -135,9 +135,13 @@ struct HLeg {
         if constexpr (kRegTab) return Rt[q];
         else return ro(a.R)[q];
     }
-    // Loads are issued without branches (a lane outside the level loads its
-    // clamped slab, a point past the last loads the last point); what they
-    // bring is masked where it is used.
+    // Loads are issued without branches: a lane outside the level loads its
+    // clamped slab, a point past the last loads the last point.  A lane
+    // outside the level computes on that copy, and no slab of the level
+    // reads it: a lane takes the end value of the lane on its left, and
+    // slab 0 takes u0 instead (lanes past the last slab are on the right);
+    // outputs are written, and residuals summed, for the tile's own slabs
+    // only.
     __device__ __forceinline__ int row(int i) const { return i < a.nx ? i : a.nx - 1; }
     __device__ __forceinline__ double *U(int i) const { return wu + ((int64_t)i * kHT + li) * P; }
     __device__ __forceinline__ double *Y(int i) const { return wy + ((int64_t)i * kHT + li) * P; }
@@ -153,24 +157,19 @@ struct HLeg {
 #pragma unroll
         for (int k = 0; k < P; ++k) p[k] = x[k];
     }
-    __device__ __forceinline__ void mask(double (&x)[P]) const
-    {
-#pragma unroll
-        for (int k = 0; k < P; ++k) x[k] = valid ? x[k] : 0.0;
-    }
     // the lane's slab of a [point][slab][k] array at point i
     __device__ __forceinline__ const double *at(const double *v, int i) const
     {
         return v + ((int64_t)row(i) * a.N + mc) * P;
     }
-    // right-hand side f at point i (masked by the caller) and u0 at the
-    // point (zero above level 0), which enters slab 0 as its left end value
+    // right-hand side f at point i and u0 at the point (zero above level
+    // 0), which enters slab 0 as its left end value
     __device__ __forceinline__ void ld_rhs(int i, double (&x)[P], double &g) const
     {
         ld(at(a.f, i), x);
         g = a.u0[row(i)];
     }
-    // the iterate at point i (masked by the caller when from u_in)
+    // the iterate at point i
     template <int SRC>
     __device__ __forceinline__ void ld_iter(int i, double (&u)[P]) const
     {
@@ -189,10 +188,9 @@ struct HLeg {
     {
         ldn<P * P>(T + (int64_t)row(i) * P * P, c);
     }
-    // u_m += R_i^T e_{m/2} (i the parity of m); e masked here
-    __device__ __forceinline__ void add_e(double (&e)[P], double (&u)[P]) const
+    // u_m += R_i^T e_{m/2} (i the parity of m)
+    __device__ __forceinline__ void add_e(const double (&e)[P], double (&u)[P]) const
     {
-        mask(e);
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double t = 0.0;
@@ -202,20 +200,18 @@ struct HLeg {
         }
     }
     // end value c^T u of the left slab (c = 1): lane 0 sees zero, slab 0
-    // the initial value g (its left lane, outside the time interval, holds
-    // zero)
+    // the initial value g
     __device__ __forceinline__ double wl(const double (&u)[P], double g) const
     {
-        double w = 0.0;
+        double w = u[0];
 #pragma unroll
-        for (int k = 0; k < P; ++k) w += u[k];
+        for (int k = 1; k < P; ++k) w += u[k];
         w = shr1(w);
-        return m == 0 ? w + g : w;
+        return m == 0 ? g : w;
     }
     // residual at point i: f + v w_left - (K u_i + M (L_h u)_i), with um, up
-    // the neighbouring points' iterates (zero beyond the ends), fi the
-    // masked f and g the point's u0; its square into acc, its restriction
-    // into rc
+    // the neighbouring points' iterates (zero beyond the ends), fi the f and
+    // g the u0 of the point; its square into acc, its restriction into rc
     __device__ __forceinline__ void resid_point(int i, const double (&um)[P], const double (&u)[P],
                                                 const double (&up)[P], const double (&fi)[P],
                                                 double g, double &acc) const
@@ -281,10 +277,8 @@ struct HLeg {
                 for (int j = 0; j < B; ++j) {
                     const int i = b * B + j;
                     if (i < a.nx) {
-                        if constexpr (SRC == kFromIn) mask(q.u[j]);
                         if constexpr (ADDE) add_e(q.e[j], q.u[j]);
                         if constexpr (SRC != kFromWs || ADDE) st(U(i), q.u[j]);
-                        mask(q.z[j]);
                         const double w = wl(q.u[j], q.g[j]);
                         double z[P];
 #pragma unroll
@@ -360,7 +354,6 @@ struct HLeg {
                         } else {
                             if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, u);
                             if (resid && i + 1 < a.nx) resid_point(i + 1, u, u1, u2, f1, g1, acc);
-                            mask(q.f[j]);
 #pragma unroll
                             for (int k = 0; k < P; ++k) {
                                 u2[k] = u1[k];
@@ -407,11 +400,9 @@ struct HLeg {
                 for (int j = 0; j < B; ++j) {
                     const int i = b * B + j;
                     if (i < a.nx) {
-                        if constexpr (SRC == kFromIn) mask(q.u[j]);
                         if constexpr (ADDE) add_e(q.e[j], q.u[j]);
                         if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, q.u[j]);
                         if (resid && i > 0) resid_point(i - 1, um, uc, q.u[j], fc, gc, acc);
-                        mask(q.f[j]);
 #pragma unroll
                         for (int k = 0; k < P; ++k) {
                             um[k] = uc[k];
