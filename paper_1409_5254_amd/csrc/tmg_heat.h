@@ -31,7 +31,9 @@ struct HeatArgs {
     int nx, halo, tile_out, sweeps, norm_f;
 };
 
-hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, hipStream_t s);
+// lean: the variant with fewer registers per wavefront (more resident), for
+// launches with more tiles than two wavefronts per SIMD
+hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, bool lean, hipStream_t s);
 hipError_t launch_hcoarse(int P, const HeatArgs &a, hipStream_t s);
 hipError_t launch_hsum(const double *partial, int64_t n, double *out, hipStream_t s);
 

@@ -51,13 +51,14 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// Points per block of the pipelined walks: about kHeatBlockValues
-// coefficients per array (two register buffers of up to three B x P arrays).
-#ifndef TMG_HEAT_BLOCK_VALUES
-#define TMG_HEAT_BLOCK_VALUES 8
-#endif
+// Points per block of the pipelined walks (two register buffers of up to
+// four B x P arrays): about 8 coefficients per array, or 4 in the lean
+// variant, whose fewer registers fit 3 wavefronts per SIMD (launches with
+// more tiles than 2 wavefronts per SIMD would run in two rounds).
 template <int P>
-constexpr int kHB = (TMG_HEAT_BLOCK_VALUES / P) < 2 ? 2 : TMG_HEAT_BLOCK_VALUES / P;
+constexpr int kHB = P > 3 ? 1 : ((8 / P) < 2 ? 2 : 8 / P);
+template <int P>
+constexpr int kHBLean = (4 / P) < 1 ? 1 : 4 / P;
 
 // Walks blocks 0 .. nb-1 (or nb-1 .. 0 when rev): load(b, buf) issues the
 // loads of block b into a register buffer, run(b, buf) consumes it.  The
@@ -88,9 +89,8 @@ __device__ __forceinline__ void pipe2(int nb, bool rev, Load &&load, Run &&run)
 // u_in, or zero (u_in null).
 enum HSrc { kFromWs = 0, kFromIn = 1, kFromZero = 2 };
 
-template <int P>
+template <int P, int B>
 struct HLeg {
-    static constexpr int B = kHB<P>;
     // up to P = 3 the per-point factors travel with the prefetched data and
     // the small slab tables stay in registers; above, both are read per
     // point through the constant address space
@@ -454,10 +454,10 @@ struct HLeg {
 // and/or squared into the tile's partial.  With norm_f, only the squared
 // norm of the right-hand side.  Each walk variant appears once, so that no
 // loop holds the state of several.
-template <int P>
+template <int P, int B>
 __global__ __launch_bounds__(kHT) void k_hleg(HeatArgs a)
 {
-    const HLeg<P> g(a);
+    const HLeg<P, B> g(a);
     double acc = 0.0;
     if (a.norm_f) {
         g.norm_rhs(acc);
@@ -614,10 +614,13 @@ __global__ __launch_bounds__(256) void k_hsum(const double *partial, int64_t n, 
     default: return hipErrorInvalidValue;                     \
     }
 
-hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, hipStream_t s)
+hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, bool lean, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
-    TMG_HEAT_P(P, { hipLaunchKernelGGL((k_hleg<PP>), dim3((unsigned)ntiles), dim3(kHT), 0, s, a); })
+    if (lean)
+        TMG_HEAT_P(P, { hipLaunchKernelGGL((k_hleg<PP, kHBLean<PP>>), dim3((unsigned)ntiles), dim3(kHT), 0, s, a); })
+    else
+        TMG_HEAT_P(P, { hipLaunchKernelGGL((k_hleg<PP, kHB<PP>>), dim3((unsigned)ntiles), dim3(kHT), 0, s, a); })
     return hipGetLastError();
 }
 

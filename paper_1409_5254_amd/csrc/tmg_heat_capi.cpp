@@ -34,6 +34,7 @@ struct tmg_heat_ctx {
     double *R = nullptr, *ws = nullptr, *partial = nullptr, *sum = nullptr;
     double *zeros = nullptr;   // nx zeros: the u0 of the levels above 0
     int64_t ws_tiles = 0;
+    int64_t wide_tiles = 0;   // two wavefronts per SIMD of the device
     std::vector<void *> allocs;
     int last_hip = 0;
 };
@@ -82,7 +83,7 @@ int Hmax(const tmg_options &o) { return std::max(std::max(rs2(o.nu1 + 1), rs2(o.
 int launch_leg_checked(tmg_heat_ctx *c, const HeatArgs &a, int64_t ntiles, hipStream_t s)
 {
     if (ntiles > c->ws_tiles || a.halo < 2 || a.halo >= kHeatThreads) return TMG_ERR_INTERNAL;
-    HCHK(c, launch_hleg(c->P, a, ntiles, s));
+    HCHK(c, launch_hleg(c->P, a, ntiles, ntiles > c->wide_tiles, s));
     return TMG_OK;
 }
 
@@ -295,6 +296,13 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
         R[P * P + q] = R2T[q];
     }
     c->ws_tiles = maxtiles;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return fail(TMG_ERR_HIP);
+        c->wide_tiles = 2 * 4 * (int64_t)ncu;
+    }
     if ((rc = halloc(c, &c->R, R.size())) || (rc = halloc(c, &c->zeros, nx)) ||
         (rc = halloc(c, &c->ws, (size_t)maxtiles * 2 * nx * kHeatThreads * P)) ||
         (rc = halloc(c, &c->partial, maxtiles)) || (rc = halloc(c, &c->sum, 1)))
