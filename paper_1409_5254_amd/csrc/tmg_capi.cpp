@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <thread>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -1499,9 +1500,12 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
         if ((rc = launch(want - launched))) return rc;
     }
     long long last_ver = -1;
-    long polls = 0;
     constexpr std::chrono::microseconds kQuiet(2000);
-    auto since = std::chrono::steady_clock::now();
+    // Between summaries the host spins for a short while, then yields its
+    // core, then sleeps in short steps: the device runs cycles already
+    // queued meanwhile, so the host need not answer within microseconds.
+    constexpr std::chrono::microseconds kSpin(50), kYield(1000), kNap(20);
+    auto since = std::chrono::steady_clock::now(), queried = since;
     while (!c->fixed()) {
         long long ver = 0;
         HostSum q;
@@ -1541,11 +1545,14 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
             since = std::chrono::steady_clock::now();
             continue;
         }
+        const auto now = std::chrono::steady_clock::now();
+        if (now - since > kYield) std::this_thread::sleep_for(kNap);
+        else if (now - since > kSpin) std::this_thread::yield();
         // nothing new for a while: if the stream has drained, every summary
         // it will write is there, so one more read decides (queried rarely:
         // a query is not free for the stream)
-        if (++polls % 4096 == 0 && std::chrono::steady_clock::now() - since > kQuiet) {
-            since = std::chrono::steady_clock::now();
+        if (now - since > kQuiet && now - queried > kQuiet) {
+            queried = now;
             const hipError_t qs = hipStreamQuery(s);
             if (qs == hipSuccess) {
                 long long v = 0;
