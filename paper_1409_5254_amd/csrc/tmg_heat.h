@@ -8,6 +8,14 @@
 namespace tmg {
 
 constexpr int kHeatThreads = 64;   // one wavefront per tile of as many slabs
+constexpr int kHeatMaxChunks = 8;  // wavefronts sharing a tile in a partitioned leg
+// LDS of a partitioned leg: the chunk end exchange and the level's four
+// per-point tables (read from global memory when they do not fit)
+constexpr size_t kHeatPartLdsBytes = 64 * 1024;
+inline size_t heat_part_lds_bytes(int P, int nx, int chunks)
+{
+    return sizeof(double) * ((size_t)2 * chunks * kHeatThreads * P + (size_t)4 * nx * P * P);
+}
 
 // One leg of the heat cycle on one level (see k_hleg), or the coarsest
 // level's exact solve (k_hcoarse: f, u0, u_out, Cinv, G, Md, ih2, ws, N, nx).
@@ -29,11 +37,18 @@ struct HeatArgs {
     double ih2;             // 1 / h^2
     double omc, om;         // 1 - omega, omega
     int nx, halo, tile_out, sweeps, norm_f;
+    // partitioned legs (k_hlegp): `chunks` chunks of the points, the
+    // elimination factors restarted at each chunk's first point, the spikes
+    // and the reduced system's inverse ((2 chunks P)^2)
+    int chunks;
+    const double *Cl, *Gl, *SL, *SR, *Minv;
 };
 
 // lean: the variant with fewer registers per wavefront (more resident), for
 // launches with more tiles than two wavefronts per SIMD
 hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, bool lean, hipStream_t s);
+// a leg whose spatial solves are partitioned over a.chunks wavefronts (sweeps >= 1)
+hipError_t launch_hlegp(int P, const HeatArgs &a, int64_t ntiles, hipStream_t s);
 hipError_t launch_hcoarse(int P, const HeatArgs &a, hipStream_t s);
 hipError_t launch_hsum(const double *partial, int64_t n, double *out, hipStream_t s);
 

@@ -59,6 +59,10 @@ template <int P>
 constexpr int kHB = P > 3 ? 1 : ((8 / P) < 2 ? 2 : 8 / P);
 template <int P>
 constexpr int kHBLean = (4 / P) < 1 ? 1 : 4 / P;
+// partitioned legs with their tables in LDS (wider work-groups, at most 256
+// registers); with the tables in global memory, kHBLean
+template <int P>
+constexpr int kHBPart = P == 1 ? 4 : kHB<P>;
 
 // Walks blocks 0 .. nb-1 (or nb-1 .. 0 when rev): load(b, buf) issues the
 // loads of block b into a register buffer, run(b, buf) consumes it.  The
@@ -89,29 +93,37 @@ __device__ __forceinline__ void pipe2(int nb, bool rev, Load &&load, Run &&run)
 // u_in, or zero (u_in null).
 enum HSrc { kFromWs = 0, kFromIn = 1, kFromZero = 2 };
 
-template <int P, int B>
+template <int P, int B, bool TL = false>
 struct HLeg {
     // up to P = 3 the per-point factors travel with the prefetched data and
     // the small slab tables stay in registers; above, both are read per
-    // point through the constant address space
+    // point through the constant address space.  TL: the per-point tables
+    // are in LDS (copied there by the kernel) and read where they are used.
     static constexpr bool kRegTab = P <= 3;
+    static constexpr bool kPre = kRegTab && !TL;
     const HeatArgs &a;
     int li, nb;
+    int i0, i1;                 // the points this wavefront walks
+    const double *tC, *tG;      // its elimination factors C_i^{-1}, C_i^{-1} E
+    const double *tSL, *tSR;    // partitioned sweeps: the spikes
     int64_t m, mc;   // the lane's slab, and that slab clamped into the level
     bool valid, out, resid, norm, odd;
     double *wu, *wy;
     double mdh[P];                          // diag(M) / h^2
     double Kt[kRegTab ? P * P : 1];         // K
     double Rt[kRegTab ? 2 * P * P : 1];     // R_1^T, R_2^T
-    __device__ __forceinline__ HLeg(const HeatArgs &a_) : a(a_)
+    __device__ __forceinline__ HLeg(const HeatArgs &a_, int i0_, int i1_, const double *tC_,
+                                    const double *tG_, const double *tSL_ = nullptr,
+                                    const double *tSR_ = nullptr)
+        : a(a_), i0(i0_), i1(i1_), tC(tC_), tG(tG_), tSL(tSL_), tSR(tSR_)
     {
-        li = threadIdx.x;
+        li = threadIdx.x & (kHT - 1);
         m = (int64_t)blockIdx.x * a.tile_out - a.halo + li;
         valid = m >= 0 && m < a.N;
         mc = m < 0 ? 0 : (m >= a.N ? a.N - 1 : m);
         odd = m & 1;
         out = li >= a.halo && valid;
-        nb = (a.nx + B - 1) / B;
+        nb = (i1 - i0 + B - 1) / B;
         norm = a.partial && !a.norm_f;
         resid = norm || a.rc;
         wu = a.ws + (int64_t)blockIdx.x * 2 * a.nx * kHT * P;
@@ -125,6 +137,12 @@ struct HLeg {
             for (int q = 0; q < 2 * P * P; ++q) Rt[q] = ro(a.R)[q];
         }
     }
+    // entry idx of a per-point table
+    __device__ __forceinline__ double tab(const double *T, int64_t idx) const
+    {
+        if constexpr (TL) return T[idx];
+        else return ro(T)[idx];
+    }
     __device__ __forceinline__ double Kc(int q) const
     {
         if constexpr (kRegTab) return Kt[q];
@@ -136,13 +154,13 @@ struct HLeg {
         else return ro(a.R)[q];
     }
     // Loads are issued without branches: a lane outside the level loads its
-    // clamped slab, a point past the last loads the last point.  A lane
+    // clamped slab, a point past the walk's last loads the last point.  A lane
     // outside the level computes on that copy, and no slab of the level
     // reads it: a lane takes the end value of the lane on its left, and
     // slab 0 takes u0 instead (lanes past the last slab are on the right);
     // outputs are written, and residuals summed, for the tile's own slabs
     // only.
-    __device__ __forceinline__ int row(int i) const { return i < a.nx ? i : a.nx - 1; }
+    __device__ __forceinline__ int row(int i) const { return i < i1 ? i : i1 - 1; }
     __device__ __forceinline__ double *U(int i) const { return wu + ((int64_t)i * kHT + li) * P; }
     __device__ __forceinline__ double *Y(int i) const { return wy + ((int64_t)i * kHT + li) * P; }
     template <int n>
@@ -256,7 +274,7 @@ struct HLeg {
     __device__ __forceinline__ void forward() const
     {
         struct Buf {
-            double u[B][P], z[B][P], e[ADDE ? B : 1][P], c[kRegTab ? B : 1][P * P], g[B];
+            double u[B][P], z[B][P], e[ADDE ? B : 1][P], c[kPre ? B : 1][P * P], g[B];
         };
         double y[P];
 #pragma unroll
@@ -266,17 +284,17 @@ struct HLeg {
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
-                    ld_iter<SRC>(b * B + j, q.u[j]);
-                    if constexpr (ADDE) ld_e(b * B + j, q.e[j]);
-                    ld_rhs(b * B + j, q.z[j], q.g[j]);
-                    if constexpr (kRegTab) ld_tab(a.Cinv, b * B + j, q.c[j]);
+                    ld_iter<SRC>(i0 + b * B + j, q.u[j]);
+                    if constexpr (ADDE) ld_e(i0 + b * B + j, q.e[j]);
+                    ld_rhs(i0 + b * B + j, q.z[j], q.g[j]);
+                    if constexpr (kPre) ld_tab(tC, i0 + b * B + j, q.c[j]);
                 }
             },
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
-                    const int i = b * B + j;
-                    if (i < a.nx) {
+                    const int i = i0 + b * B + j;
+                    if (i < i1) {
                         if constexpr (ADDE) add_e(q.e[j], q.u[j]);
                         if constexpr (SRC != kFromWs || ADDE) st(U(i), q.u[j]);
                         const double w = wl(q.u[j], q.g[j]);
@@ -290,8 +308,8 @@ struct HLeg {
 #pragma unroll
                             for (int l = 0; l < P; ++l) {
                                 double c;
-                                if constexpr (kRegTab) c = q.c[j][k * P + l];
-                                else c = ro(a.Cinv)[(int64_t)i * P * P + k * P + l];
+                                if constexpr (kPre) c = q.c[j][k * P + l];
+                                else c = tab(tC, (int64_t)i * P * P + k * P + l);
                                 t += c * z[l];
                             }
                             y[k] = t;
@@ -309,7 +327,7 @@ struct HLeg {
     __device__ __forceinline__ void backward(double &acc) const
     {
         struct Buf {
-            double y[B][P], u[B][P], f[FIN ? B : 1][P], c[kRegTab ? B : 1][P * P], g[FIN ? B : 1];
+            double y[B][P], u[B][P], f[FIN ? B : 1][P], c[kPre ? B : 1][P * P], g[FIN ? B : 1];
         };
         double x[P], u1[P], u2[P], f1[P], g1 = 0.0;   // FIN: result at i+1, i+2; f, u0 at i+1
 #pragma unroll
@@ -319,17 +337,17 @@ struct HLeg {
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
-                    ld(Y(row(b * B + j)), q.y[j]);
-                    ld(U(row(b * B + j)), q.u[j]);
-                    if constexpr (FIN) ld_rhs(b * B + j, q.f[j], q.g[j]);
-                    if constexpr (kRegTab) ld_tab(a.G, b * B + j, q.c[j]);
+                    ld(Y(row(i0 + b * B + j)), q.y[j]);
+                    ld(U(row(i0 + b * B + j)), q.u[j]);
+                    if constexpr (FIN) ld_rhs(i0 + b * B + j, q.f[j], q.g[j]);
+                    if constexpr (kPre) ld_tab(tG, i0 + b * B + j, q.c[j]);
                 }
             },
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = B - 1; j >= 0; --j) {
-                    const int i = b * B + j;
-                    if (i < a.nx) {
+                    const int i = i0 + b * B + j;
+                    if (i < i1) {
                         double xn[P];
 #pragma unroll
                         for (int k = 0; k < P; ++k) {
@@ -337,8 +355,8 @@ struct HLeg {
 #pragma unroll
                             for (int l = 0; l < P; ++l) {
                                 double c;
-                                if constexpr (kRegTab) c = q.c[j][k * P + l];
-                                else c = ro(a.G)[(int64_t)i * P * P + k * P + l];
+                                if constexpr (kPre) c = q.c[j][k * P + l];
+                                else c = tab(tG, (int64_t)i * P * P + k * P + l);
                                 t -= c * x[l];
                             }
                             xn[k] = t;
@@ -353,7 +371,7 @@ struct HLeg {
                             st(U(i), u);
                         } else {
                             if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, u);
-                            if (resid && i + 1 < a.nx) resid_point(i + 1, u, u1, u2, f1, g1, acc);
+                            if (resid && i + 1 < i1) resid_point(i + 1, u, u1, u2, f1, g1, acc);
 #pragma unroll
                             for (int k = 0; k < P; ++k) {
                                 u2[k] = u1[k];
@@ -370,7 +388,7 @@ struct HLeg {
                 double z0[P];
 #pragma unroll
                 for (int k = 0; k < P; ++k) z0[k] = 0.0;
-                resid_point(0, z0, u1, u2, f1, g1, acc);
+                resid_point(i0, z0, u1, u2, f1, g1, acc);
             }
     }
     // The leg's outputs from an iterate no sweep follows (from SRC), after
@@ -390,16 +408,16 @@ struct HLeg {
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
-                    ld_iter<SRC>(b * B + j, q.u[j]);
-                    if constexpr (ADDE) ld_e(b * B + j, q.e[j]);
-                    ld_rhs(b * B + j, q.f[j], q.g[j]);
+                    ld_iter<SRC>(i0 + b * B + j, q.u[j]);
+                    if constexpr (ADDE) ld_e(i0 + b * B + j, q.e[j]);
+                    ld_rhs(i0 + b * B + j, q.f[j], q.g[j]);
                 }
             },
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j) {
-                    const int i = b * B + j;
-                    if (i < a.nx) {
+                    const int i = i0 + b * B + j;
+                    if (i < i1) {
                         if constexpr (ADDE) add_e(q.e[j], q.u[j]);
                         if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, q.u[j]);
                         if (resid && i > 0) resid_point(i - 1, um, uc, q.u[j], fc, gc, acc);
@@ -417,7 +435,7 @@ struct HLeg {
             double z0[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) z0[k] = 0.0;
-            resid_point(a.nx - 1, um, uc, z0, fc, gc, acc);
+            resid_point(i1 - 1, um, uc, z0, fc, gc, acc);
         }
     }
     // squared norm of the right-hand side (the tile's own slabs)
@@ -430,12 +448,12 @@ struct HLeg {
             nb, false,
             [&](int b, Buf &q) {
 #pragma unroll
-                for (int j = 0; j < B; ++j) ld_rhs(b * B + j, q.f[j], q.g[j]);
+                for (int j = 0; j < B; ++j) ld_rhs(i0 + b * B + j, q.f[j], q.g[j]);
             },
             [&](int b, Buf &q) {
 #pragma unroll
                 for (int j = 0; j < B; ++j)
-                    if (b * B + j < a.nx) {
+                    if (i0 + b * B + j < i1) {
                         // the folded f + v u0 of slab 0
                         const double g = m == 0 ? q.g[j] : 0.0;
 #pragma unroll
@@ -445,6 +463,234 @@ struct HLeg {
                         }
                     }
             });
+    }
+
+    // ---- Partitioned sweeps.  K wavefronts share the tile, wavefront c
+    // walking the chunk [i0, i1) of the points with the factors of the
+    // chunk's own system (the elimination restarted at i0).  With v the
+    // solution of that system (zero beyond the chunk) and the spikes
+    // S^L = A_c^{-1} (e_first (x) E), S^R = A_c^{-1} (e_last (x) E), the
+    // block row's solution is x = v - S^L x_{i0-1} - S^R x_{i1}; the values
+    // at the chunk ends solve a reduced system of 2K blocks, whose inverse
+    // is a table of the level.
+
+    // Back substitution of the chunk's system, v_i = y_i - C_i^{-1} E v_{i+1},
+    // into Y; v at the chunk's first and last points into vF, vL.
+    __device__ __forceinline__ void backward_local(double (&vF)[P], double (&vL)[P]) const
+    {
+        struct Buf {
+            double y[B][P], c[kPre ? B : 1][P * P];
+        };
+        double x[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = vF[k] = vL[k] = 0.0;
+        pipe2<Buf>(
+            nb, true,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    ld(Y(row(i0 + b * B + j)), q.y[j]);
+                    if constexpr (kPre) ld_tab(tG, i0 + b * B + j, q.c[j]);
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = B - 1; j >= 0; --j) {
+                    const int i = i0 + b * B + j;
+                    if (i < i1) {
+                        double xn[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = q.y[j][k];
+#pragma unroll
+                            for (int l = 0; l < P; ++l) {
+                                double c;
+                                if constexpr (kPre) c = q.c[j][k * P + l];
+                                else c = tab(tG, (int64_t)i * P * P + k * P + l);
+                                t -= c * x[l];
+                            }
+                            xn[k] = t;
+                        }
+#pragma unroll
+                        for (int k = 0; k < P; ++k) x[k] = xn[k];
+                        st(Y(i), xn);
+                        if (i == i1 - 1)
+#pragma unroll
+                            for (int k = 0; k < P; ++k) vL[k] = xn[k];
+                        if (i == i0)
+#pragma unroll
+                            for (int k = 0; k < P; ++k) vF[k] = xn[k];
+                    }
+                }
+            });
+    }
+    // The neighbour chunks' end values bL = x_{i0-1}, bR = x_{i1} (zero
+    // beyond the ends): every chunk's v at its ends through LDS ([2K][64][P],
+    // F then L per chunk), then the two block rows of the reduced system's
+    // inverse that give them.
+    template <int K>
+    __device__ __forceinline__ void reduce(double *lds, int c, const double (&vF)[P],
+                                           const double (&vL)[P], double (&bL)[P],
+                                           double (&bR)[P]) const
+    {
+        st(lds + ((2 * c) * kHT + li) * P, vF);
+        st(lds + ((2 * c + 1) * kHT + li) * P, vL);
+        __syncthreads();
+        constexpr int n = 2 * K * P;
+        const cdouble *Mi = ro(a.Minv);
+#pragma unroll
+        for (int k = 0; k < P; ++k) bL[k] = bR[k] = 0.0;
+        if (c > 0) {
+            const int r = (2 * (c - 1) + 1) * P;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double t = 0.0;
+#pragma unroll
+                for (int j = 0; j < n; ++j)
+                    t += Mi[(int64_t)(r + k) * n + j] * lds[((j / P) * kHT + li) * P + j % P];
+                bL[k] = t;
+            }
+        }
+        if (c + 1 < K) {
+            const int r = 2 * (c + 1) * P;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double t = 0.0;
+#pragma unroll
+                for (int j = 0; j < n; ++j)
+                    t += Mi[(int64_t)(r + k) * n + j] * lds[((j / P) * kHT + li) * P + j % P];
+                bR[k] = t;
+            }
+        }
+        __syncthreads();
+    }
+    // x_i = v_i - S^L_i bL - S^R_i bR and the damped update u_i <- (1 - omega)
+    // u_i + omega x_i.  FIN (the leg's last sweep): the result to u_out and,
+    // one point behind, into the residual; the residual at the chunk's ends
+    // takes the neighbours' results through LDS.  Otherwise the result goes
+    // to the workspace, and the next sweep's forward elimination runs in the
+    // same walk (it needs the point's new iterate and the chain below it).
+    template <bool FIN, int K>
+    __device__ __forceinline__ void correct(const double (&bL)[P], const double (&bR)[P],
+                                            double *lds, int c, double &acc) const
+    {
+        constexpr bool FWD = !FIN;
+        struct Buf {
+            double v[B][P], u[B][P], sl[kPre ? B : 1][P * P], sr[kPre ? B : 1][P * P],
+                f[B][P], g[B], cf[(FWD && kPre) ? B : 1][P * P];
+        };
+        double y[P];   // FWD: the forward elimination's chain
+#pragma unroll
+        for (int k = 0; k < P; ++k) y[k] = 0.0;
+        // FIN: the iterate at i-2, i-1 with f, u0 at i-1; the first two
+        // points' iterate with the first's f, u0
+        double um[P], uc[P], fc[P], uS[P], uS1[P], fS[P], gc = 0.0, gS = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) um[k] = uc[k] = fc[k] = uS[k] = uS1[k] = fS[k] = 0.0;
+        pipe2<Buf>(
+            nb, false,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const int i = i0 + b * B + j;
+                    ld(Y(row(i)), q.v[j]);
+                    ld(U(row(i)), q.u[j]);
+                    if constexpr (kPre) {
+                        ld_tab(tSL, i, q.sl[j]);
+                        ld_tab(tSR, i, q.sr[j]);
+                        if constexpr (FWD) ld_tab(tC, i, q.cf[j]);
+                    }
+                    ld_rhs(i, q.f[j], q.g[j]);
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const int i = i0 + b * B + j;
+                    if (i < i1) {
+                        double un[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = q.v[j][k];
+#pragma unroll
+                            for (int l = 0; l < P; ++l) {
+                                double cl, cr;
+                                if constexpr (kPre) {
+                                    cl = q.sl[j][k * P + l];
+                                    cr = q.sr[j][k * P + l];
+                                } else {
+                                    cl = tab(tSL, (int64_t)i * P * P + k * P + l);
+                                    cr = tab(tSR, (int64_t)i * P * P + k * P + l);
+                                }
+                                t -= cl * bL[l];
+                                t -= cr * bR[l];
+                            }
+                            un[k] = a.omc * q.u[j][k] + a.om * t;
+                        }
+                        if constexpr (FWD) {
+                            st(U(i), un);
+                            const double w = wl(un, q.g[j]);
+                            double z[P];
+#pragma unroll
+                            for (int k = 0; k < P; ++k)
+                                z[k] = q.f[j][k] + ((k & 1) ? -w : w) + mdh[k] * y[k];
+#pragma unroll
+                            for (int k = 0; k < P; ++k) {
+                                double t = 0.0;
+#pragma unroll
+                                for (int l = 0; l < P; ++l) {
+                                    double cc;
+                                    if constexpr (kPre) cc = q.cf[j][k * P + l];
+                                    else cc = tab(tC, (int64_t)i * P * P + k * P + l);
+                                    t += cc * z[l];
+                                }
+                                y[k] = t;
+                            }
+                            st(Y(i), y);
+                        } else {
+                            if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, un);
+                            if (resid && i >= i0 + 2) resid_point(i - 1, um, uc, un, fc, gc, acc);
+                            if (i == i0) {
+#pragma unroll
+                                for (int k = 0; k < P; ++k) {
+                                    uS[k] = un[k];
+                                    fS[k] = q.f[j][k];
+                                }
+                                gS = q.g[j];
+                            }
+                            if (i == i0 + 1)
+#pragma unroll
+                                for (int k = 0; k < P; ++k) uS1[k] = un[k];
+#pragma unroll
+                            for (int k = 0; k < P; ++k) {
+                                um[k] = uc[k];
+                                uc[k] = un[k];
+                                fc[k] = q.f[j][k];
+                            }
+                            gc = q.g[j];
+                        }
+                    }
+                }
+            });
+        if constexpr (FIN) {
+            st(lds + ((2 * c) * kHT + li) * P, uS);
+            st(lds + ((2 * c + 1) * kHT + li) * P, uc);
+            __syncthreads();
+            const int cl = c > 0 ? c - 1 : 0, cr = c + 1 < K ? c + 1 : c;
+            double left[P], right[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double l = lds[((2 * cl + 1) * kHT + li) * P + k];
+                const double r = lds[((2 * cr) * kHT + li) * P + k];
+                left[k] = c > 0 ? l : 0.0;
+                right[k] = c + 1 < K ? r : 0.0;
+            }
+            __syncthreads();
+            if (resid) {
+                resid_point(i0, left, uS, uS1, fS, gS, acc);
+                resid_point(i1 - 1, um, uc, right, fc, gc, acc);
+            }
+        }
     }
 };
 
@@ -457,7 +703,7 @@ struct HLeg {
 template <int P, int B>
 __global__ __launch_bounds__(kHT) void k_hleg(HeatArgs a)
 {
-    const HLeg<P, B> g(a);
+    const HLeg<P, B> g(a, 0, a.nx, a.Cinv, a.G);
     double acc = 0.0;
     if (a.norm_f) {
         g.norm_rhs(acc);
@@ -486,6 +732,64 @@ __global__ __launch_bounds__(kHT) void k_hleg(HeatArgs a)
     if (a.partial) {
         acc = wave_sum(acc);
         if (g.li == 0) a.partial[blockIdx.x] = acc;
+    }
+}
+
+// One leg with its spatial solves partitioned over a.chunks wavefronts (see the
+// partitioned sweeps above): sweeps >= 1, otherwise as k_hleg.
+template <int P, int B, int K, bool TL>
+__global__ __launch_bounds__(kHT * K) void k_hlegp(HeatArgs a)
+{
+    // LDS: the chunk end exchange [2K][64][P], then (TL) the level's
+    // per-point tables C_i^{-1}, C_i^{-1} E, S^L, S^R (nx P^2 each), copied
+    // at start; without TL they are read from global memory
+    extern __shared__ double lds[];
+    __shared__ double red[K];
+    const int c = threadIdx.x / kHT;
+    const int i0 = (int)((int64_t)c * a.nx / K), i1 = (int)((int64_t)(c + 1) * a.nx / K);
+    const double *tC = a.Cl, *tG = a.Gl, *tSL = a.SL, *tSR = a.SR;
+    if constexpr (TL) {
+        const int nt = a.nx * P * P;
+        double *tl = lds + 2 * K * kHT * P;
+        for (int q = threadIdx.x; q < nt; q += kHT * K) {
+            tl[q] = a.Cl[q];
+            tl[nt + q] = a.Gl[q];
+            tl[2 * nt + q] = a.SL[q];
+            tl[3 * nt + q] = a.SR[q];
+        }
+        __syncthreads();
+        tC = tl;
+        tG = tl + nt;
+        tSL = tl + 2 * nt;
+        tSR = tl + 3 * nt;
+    }
+    const HLeg<P, B, TL> g(a, i0, i1, tC, tG, tSL, tSR);
+    double acc = 0.0;
+    if (a.u_in) {
+        if (a.e) g.template forward<kFromIn, true>();
+        else g.template forward<kFromIn, false>();
+    } else {
+        if (a.e) g.template forward<kFromZero, true>();
+        else g.template forward<kFromZero, false>();
+    }
+    double vF[P], vL[P], bL[P], bR[P];
+    for (int s = 1; s < a.sweeps; ++s) {
+        g.backward_local(vF, vL);
+        g.template reduce<K>(lds, c, vF, vL, bL, bR);
+        g.template correct<false, K>(bL, bR, lds, c, acc);   // with the next forward
+    }
+    g.backward_local(vF, vL);
+    g.template reduce<K>(lds, c, vF, vL, bL, bR);
+    g.template correct<true, K>(bL, bR, lds, c, acc);
+    if (a.partial) {
+        acc = wave_sum(acc);
+        if (g.li == 0) red[c] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < K; ++q) t += red[q];
+            a.partial[blockIdx.x] = t;
+        }
     }
 }
 
@@ -621,6 +925,31 @@ hipError_t launch_hleg(int P, const HeatArgs &a, int64_t ntiles, bool lean, hipS
         TMG_HEAT_P(P, { hipLaunchKernelGGL((k_hleg<PP, kHBLean<PP>>), dim3((unsigned)ntiles), dim3(kHT), 0, s, a); })
     else
         TMG_HEAT_P(P, { hipLaunchKernelGGL((k_hleg<PP, kHB<PP>>), dim3((unsigned)ntiles), dim3(kHT), 0, s, a); })
+    return hipGetLastError();
+}
+
+hipError_t launch_hlegp(int P, const HeatArgs &a, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (a.chunks < 2 || a.chunks > kHeatMaxChunks || a.sweeps < 1 || a.nx < 2 * a.chunks)
+        return hipErrorInvalidValue;
+    // the tables in LDS when they fit
+    const size_t full = heat_part_lds_bytes(P, a.nx, a.chunks);
+    const bool tl = full <= kHeatPartLdsBytes;
+    const size_t lds = tl ? full : sizeof(double) * 2 * a.chunks * kHT * P;
+    const dim3 grid((unsigned)ntiles), block(kHT * a.chunks);
+#define TMG_HLEGP(KK)                                                                          \
+    TMG_HEAT_P(P, {                                                                            \
+        if (tl) hipLaunchKernelGGL((k_hlegp<PP, kHBPart<PP>, KK, true>), grid, block, lds, s, a); \
+        else hipLaunchKernelGGL((k_hlegp<PP, kHBLean<PP>, KK, false>), grid, block, lds, s, a);   \
+    })
+    switch (a.chunks) {
+    case 2: TMG_HLEGP(2) break;
+    case 4: TMG_HLEGP(4) break;
+    case 8: TMG_HLEGP(8) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef TMG_HLEGP
     return hipGetLastError();
 }
 

@@ -31,6 +31,10 @@ struct tmg_heat_ctx {
     std::vector<int64_t> Nl;
     std::vector<double> omega;
     std::vector<double *> f, x, sx, Cinv, G, K, Md;   // per level (device)
+    // per level: wavefronts sharing a tile (1: none) and the partitioned
+    // solve's tables (device, null when unpartitioned)
+    std::vector<int> chunks;
+    std::vector<double *> Cl, Gl, SL, SR, Minv;
     double *R = nullptr, *ws = nullptr, *partial = nullptr, *sum = nullptr;
     double *zeros = nullptr;   // nx zeros: the u0 of the levels above 0
     int64_t ws_tiles = 0;
@@ -83,8 +87,136 @@ int Hmax(const tmg_options &o) { return std::max(std::max(rs2(o.nu1 + 1), rs2(o.
 int launch_leg_checked(tmg_heat_ctx *c, const HeatArgs &a, int64_t ntiles, hipStream_t s)
 {
     if (ntiles > c->ws_tiles || a.halo < 2 || a.halo >= kHeatThreads) return TMG_ERR_INTERNAL;
-    HCHK(c, launch_hleg(c->P, a, ntiles, ntiles > c->wide_tiles, s));
+    if (a.chunks > 1 && a.sweeps > 0) HCHK(c, launch_hlegp(c->P, a, ntiles, s));
+    else HCHK(c, launch_hleg(c->P, a, ntiles, ntiles > c->wide_tiles, s));
     return TMG_OK;
+}
+
+// Gauss-Jordan inverse with partial pivoting of an n x n matrix (row-major);
+// false when singular.
+bool invert_dense(int n, std::vector<double> A, std::vector<double> &Ai)
+{
+    Ai.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Ai[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
+        if (!(std::fabs(A[(size_t)piv * n + col]) > 0.0)) return false;
+        if (piv != col)
+            for (int j = 0; j < n; ++j) {
+                std::swap(A[(size_t)piv * n + j], A[(size_t)col * n + j]);
+                std::swap(Ai[(size_t)piv * n + j], Ai[(size_t)col * n + j]);
+            }
+        const double d = 1.0 / A[(size_t)col * n + col];
+        for (int j = 0; j < n; ++j) {
+            A[(size_t)col * n + j] *= d;
+            Ai[(size_t)col * n + j] *= d;
+        }
+        for (int r = 0; r < n; ++r)
+            if (r != col) {
+                const double fct = A[(size_t)r * n + col];
+                if (fct == 0.0) continue;
+                for (int j = 0; j < n; ++j) {
+                    A[(size_t)r * n + j] -= fct * A[(size_t)col * n + j];
+                    Ai[(size_t)r * n + j] -= fct * Ai[(size_t)col * n + j];
+                }
+            }
+    }
+    return true;
+}
+
+// Wavefronts sharing a tile at a level of `ntiles` tiles: none unless the
+// level has at most a quarter wavefront per SIMD (`waves` of them; with
+// more, the extra walk of the partitioned sweep costs more than the shorter
+// chains save), else the largest power of two that keeps the level within
+// one wavefront per SIMD, at least 2 points per chunk, and the register
+// budget (P <= 4).
+int pick_chunks(int P, int nx, int64_t ntiles, int64_t waves)
+{
+    if (P > 4 || 4 * ntiles > waves) return 1;
+    const int kmax = std::min(kHeatMaxChunks, 16 / P);
+    int K = 1;
+    while (2 * K <= kmax && nx >= 4 * K && ntiles * 2 * K <= waves) K *= 2;
+    return K;
+}
+
+// The partitioned solve's tables of one level (slab block D = K + 2 M/h^2
+// on the diagonal, E = -M/h^2 beside it): per point the elimination factors
+// C_i^{-1} and C_i^{-1} E restarted at every chunk's first point, the spikes
+// S^L = A_c^{-1} (e_first (x) E) and S^R = A_c^{-1} (e_last (x) E) of the
+// point's chunk, and the inverse of the reduced system of the chunk end
+// values (block order: first, last point of chunk 0, of chunk 1, ...).
+bool part_tables(int P, int nx, int K, const double *Km, const double *Md, double ih2,
+                 std::vector<double> &Cl, std::vector<double> &Gl, std::vector<double> &SL,
+                 std::vector<double> &SR, std::vector<double> &Minv)
+{
+    const int PP = P * P;
+    Cl.assign((size_t)nx * PP, 0.0);
+    Gl.assign((size_t)nx * PP, 0.0);
+    SL.assign((size_t)nx * PP, 0.0);
+    SR.assign((size_t)nx * PP, 0.0);
+    std::vector<double> E(P), D(PP), C(PP), Y((size_t)nx * PP);
+    for (int k = 0; k < P; ++k) E[k] = -Md[k] * ih2;
+    for (int k = 0; k < P; ++k)
+        for (int j = 0; j < P; ++j) D[k * P + j] = Km[k * P + j] + (k == j ? 2.0 * ih2 * Md[k] : 0.0);
+    auto at = [&](std::vector<double> &v, int i) { return &v[(size_t)i * PP]; };
+    for (int c = 0; c < K; ++c) {
+        const int s = (int)((int64_t)c * nx / K), e = (int)((int64_t)(c + 1) * nx / K);
+        for (int i = s; i < e; ++i) {
+            for (int q = 0; q < PP; ++q) C[q] = D[q];
+            if (i > s)
+                for (int k = 0; k < P; ++k)
+                    for (int j = 0; j < P; ++j) C[k * P + j] -= E[k] * at(Cl, i - 1)[k * P + j] * E[j];
+            table_invert(P, C.data(), at(Cl, i));
+            for (int k = 0; k < P; ++k)
+                for (int j = 0; j < P; ++j) at(Gl, i)[k * P + j] = at(Cl, i)[k * P + j] * E[j];
+        }
+        // left spike: right-hand side E at the first point; right spike: at
+        // the last point (forward elimination, then back substitution)
+        for (int side = 0; side < 2; ++side) {
+            std::vector<double> &S = side ? SR : SL;
+            for (int i = s; i < e; ++i) {
+                double *y = at(Y, i);
+                const bool src = side ? i == e - 1 : i == s;
+                for (int k = 0; k < P; ++k)
+                    for (int j = 0; j < P; ++j) {
+                        // C_i^{-1} (b_i - E y_{i-1}), b_i = E at the source point
+                        double t = 0.0;
+                        for (int l = 0; l < P; ++l) {
+                            double r = (src && l == j) ? E[l] : 0.0;
+                            if (i > s) r -= E[l] * at(Y, i - 1)[l * P + j];
+                            t += at(Cl, i)[k * P + l] * r;
+                        }
+                        y[k * P + j] = t;
+                    }
+            }
+            for (int i = e - 1; i >= s; --i)
+                for (int k = 0; k < P; ++k)
+                    for (int j = 0; j < P; ++j) {
+                        double t = at(Y, i)[k * P + j];
+                        if (i < e - 1)
+                            for (int l = 0; l < P; ++l) t -= at(Gl, i)[k * P + l] * at(S, i + 1)[l * P + j];
+                        at(S, i)[k * P + j] = t;
+                    }
+        }
+    }
+    const int n = 2 * K * P;
+    std::vector<double> M((size_t)n * n, 0.0);
+    for (int q = 0; q < n; ++q) M[(size_t)q * n + q] = 1.0;
+    for (int c = 0; c < K; ++c) {
+        const int s = (int)((int64_t)c * nx / K), e = (int)((int64_t)(c + 1) * nx / K);
+        const int rows[2] = {s, e - 1};
+        for (int side = 0; side < 2; ++side) {
+            const int r0 = (2 * c + side) * P, i = rows[side];
+            for (int k = 0; k < P; ++k)
+                for (int j = 0; j < P; ++j) {
+                    if (c > 0) M[(size_t)(r0 + k) * n + (2 * (c - 1) + 1) * P + j] += at(SL, i)[k * P + j];
+                    if (c + 1 < K) M[(size_t)(r0 + k) * n + 2 * (c + 1) * P + j] += at(SR, i)[k * P + j];
+                }
+        }
+    }
+    return invert_dense(n, M, Minv);
 }
 
 HeatArgs base_args(const tmg_heat_ctx *c, int l)
@@ -100,6 +232,12 @@ HeatArgs base_args(const tmg_heat_ctx *c, int l)
     a.N = c->Nl[l];
     a.Nc = l + 1 < c->L ? c->Nl[l + 1] : 0;
     a.ih2 = 1.0 / (c->h * c->h);
+    a.chunks = c->chunks[l];
+    a.Cl = c->Cl[l];
+    a.Gl = c->Gl[l];
+    a.SL = c->SL[l];
+    a.SR = c->SR[l];
+    a.Minv = c->Minv[l];
     a.om = c->omega[l];
     a.omc = 1.0 - c->omega[l];
     a.nx = c->nx;
@@ -241,6 +379,20 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
     c->K.assign(L, nullptr);
     c->Md.assign(L, nullptr);
     c->omega.assign(L, 0.0);
+    c->chunks.assign(L, 1);
+    c->Cl.assign(L, nullptr);
+    c->Gl.assign(L, nullptr);
+    c->SL.assign(L, nullptr);
+    c->SR.assign(L, nullptr);
+    c->Minv.assign(L, nullptr);
+    int64_t simds = 0;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return fail(TMG_ERR_HIP);
+        simds = 4 * (int64_t)ncu;
+    }
     int rc;
     int64_t maxtiles = 0;
     for (int l = 0; l < L; ++l) {
@@ -288,6 +440,26 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
             hipMemcpyAsync(c->Md[l], Md.data(), Md.size() * 8, hipMemcpyHostToDevice, s) ||
             hipStreamSynchronize(s))
             return fail(TMG_ERR_HIP);
+        // levels with few tiles: the spatial solves partitioned over
+        // several wavefronts per tile (the coarsest level is solved apart)
+        const int K = l + 1 < L ? pick_chunks(P, nx, tiles(Nl, Hmax(o)), simds) : 1;
+        if (K > 1) {
+            std::vector<double> Cl, Gl, SL, SR, Mi;
+            if (!part_tables(P, nx, K, Km.data(), Md.data(), ih2, Cl, Gl, SL, SR, Mi))
+                return fail(TMG_ERR_PARAM);
+            if ((rc = halloc(c, &c->Cl[l], Cl.size())) || (rc = halloc(c, &c->Gl[l], Gl.size())) ||
+                (rc = halloc(c, &c->SL[l], SL.size())) || (rc = halloc(c, &c->SR[l], SR.size())) ||
+                (rc = halloc(c, &c->Minv[l], Mi.size())))
+                return fail(rc);
+            if (hipMemcpyAsync(c->Cl[l], Cl.data(), Cl.size() * 8, hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(c->Gl[l], Gl.data(), Gl.size() * 8, hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(c->SL[l], SL.data(), SL.size() * 8, hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(c->SR[l], SR.data(), SR.size() * 8, hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(c->Minv[l], Mi.data(), Mi.size() * 8, hipMemcpyHostToDevice, s) ||
+                hipStreamSynchronize(s))
+                return fail(TMG_ERR_HIP);
+            c->chunks[l] = K;
+        }
     }
     std::vector<double> R1T(P * P), R2T(P * P), R(2 * P * P);
     build_transfer(P, R1T.data(), R2T.data());
@@ -296,13 +468,7 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
         R[P * P + q] = R2T[q];
     }
     c->ws_tiles = maxtiles;
-    {
-        int dev = 0, ncu = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return fail(TMG_ERR_HIP);
-        c->wide_tiles = 2 * 4 * (int64_t)ncu;
-    }
+    c->wide_tiles = 2 * simds;
     if ((rc = halloc(c, &c->R, R.size())) || (rc = halloc(c, &c->zeros, nx)) ||
         (rc = halloc(c, &c->ws, (size_t)maxtiles * 2 * nx * kHeatThreads * P)) ||
         (rc = halloc(c, &c->partial, maxtiles)) || (rc = halloc(c, &c->sum, 1)))
