@@ -75,6 +75,7 @@ void heat_free(tmg_heat_ctx *c)
 
 // even halos of at least 2 slabs: restriction pairs stay in a tile
 int rs2(int x) { return (x + 1) & ~1; }
+constexpr int64_t kLegCoarse = 32;   // coarsest levels solved by a leg (one tile)
 int TO(int H) { return kHeatThreads - H; }
 int64_t tiles(int64_t N, int H) { return (N + TO(H) - 1) / TO(H); }
 // The largest halo of any launch (down legs nu1 + 1, up legs with the norm
@@ -287,13 +288,25 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
 }
 
 // One visit of level l >= 1 on L_l e = f_l (from zero on a first visit,
-// else from the current x_l); the coarsest level is solved exactly.
+// else from the current x_l); the coarsest level is solved exactly.  With
+// at most kLegCoarse slabs it is one tile's leg of as many undamped sweeps
+// from zero: the system is block lower bidiagonal in time, so after k
+// sweeps the first k slabs are exact.  Otherwise slab after slab on one
+// lane (k_hcoarse).
 int visit(tmg_heat_ctx *c, int l, bool first, hipStream_t s)
 {
     if (l == c->L - 1) {
         HeatArgs a = base_args(c, l);
         a.f = c->f[l];
         a.u_out = c->x[l];
+        if (c->Nl[l] <= kLegCoarse) {
+            a.halo = 2;
+            a.tile_out = TO(2);
+            a.sweeps = (int)c->Nl[l];
+            a.om = 1.0;
+            a.omc = 0.0;
+            return launch_leg_checked(c, a, 1, s);
+        }
         HCHK(c, launch_hcoarse(c->P, a, s));
         return TMG_OK;
     }
@@ -440,9 +453,9 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
             hipMemcpyAsync(c->Md[l], Md.data(), Md.size() * 8, hipMemcpyHostToDevice, s) ||
             hipStreamSynchronize(s))
             return fail(TMG_ERR_HIP);
-        // levels with few tiles: the spatial solves partitioned over
-        // several wavefronts per tile (the coarsest level is solved apart)
-        const int K = l + 1 < L ? pick_chunks(P, nx, tiles(Nl, Hmax(o)), simds) : 1;
+        // levels with few tiles (the coarsest too, when a leg solves it):
+        // the spatial solves partitioned over several wavefronts per tile
+        const int K = pick_chunks(P, nx, tiles(Nl, Hmax(o)), simds);
         if (K > 1) {
             std::vector<double> Cl, Gl, SL, SR, Mi;
             if (!part_tables(P, nx, K, Km.data(), Md.data(), ih2, Cl, Gl, SL, SR, Mi))
