@@ -82,6 +82,47 @@ def test_heat_cycles_sweeps(p, nu1, nu2, nx, n_coarse):
     s.close()
 
 
+@pytest.mark.parametrize("p", [0, 1, 3])
+@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("nx", [4, 8, 16, 17, 33])
+def test_heat_cycles_partitioned(p, gamma, nx):
+    """Levels with few tiles split the points into chunks solved by
+    several wavefronts (2 to 8 chunks, down to 2 points each: nx = 4, 8,
+    16; ragged chunks: 17, 33); the coarsest level (2 slabs) is solved by
+    undamped sweeps.  Two cycles against the oracle."""
+    rng = np.random.default_rng(1400 + 10 * p + nx)
+    N, T = 256, 0.2
+    P = p + 1
+    s = B().HeatSolver(N, nx, T, p=p, gamma=gamma, nu1=1, nu2=3)
+    f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
+    u0 = rng.standard_normal(nx)
+    du = dev(u)
+    for _ in range(2):
+        s.vcycle(dev(f), dev(u0), du)
+    ref = core.heat_cycles(p, nx, T, core.heat_fold(p, nx, u0, f), u, 2,
+                           core.Opts(gamma=gamma, nu1=1, nu2=3))
+    assert relerr(host(du), ref) <= TOL
+    s.close()
+
+
+@pytest.mark.parametrize("p,nx,N", [(1, 500, 128), (0, 1800, 64)])
+def test_heat_partitioned_global_tables(p, nx, N):
+    """Partitioned levels whose point tables exceed the LDS budget read
+    them from global memory: two cycles against the oracle."""
+    rng = np.random.default_rng(1500 + nx)
+    T = 0.05
+    P = p + 1
+    f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
+    u0 = rng.standard_normal(nx)
+    s = B().HeatSolver(N, nx, T, p=p)
+    du = dev(u)
+    for _ in range(2):
+        s.vcycle(dev(f), dev(u0), du)
+    ref = core.heat_cycles(p, nx, T, core.heat_fold(p, nx, u0, f), u, 2, core.Opts())
+    assert relerr(host(du), ref) <= TOL
+    s.close()
+
+
 @pytest.mark.parametrize("p", [0, 1, 2, 3])
 @pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("nx", [1, 31, 127])
