@@ -30,6 +30,8 @@ Other workloads (`--workload`):
               5, 10, 20, tau = 1e-6, N = 2^20 steps, lambda = 1, to a
               relative residual of 1e-8; a seeded random load from u = 0 in
               place of f = 0 from a random start (the same error iteration);
+              --degrees picks the degrees;
+  periodic    the scalar workload as a time-periodic problem (--p, --log2n);
   convergence the section 4.2 study on the GPU: two-grid cycles (coarse level
               N/2 solved exactly) on u' + u = 0 from a seeded random start,
               N = 1024 as in the paper, tau = z in 10^-6 .. 10^6, p = 0..5,
@@ -82,7 +84,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="default",
                     choices=["default", "scalar", "eigenmodes", "adjoint", "long", "highdeg",
-                             "convergence", "roofline", "batch", "heat"])
+                             "convergence", "roofline", "batch", "heat", "periodic"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -101,6 +103,8 @@ def parse():
     ap.add_argument("--roof-batch", type=int, default=16,
                     help="instances of the long-horizon batch in the roofline launch")
     ap.add_argument("--batch", type=int, default=0, help="instances of the batched workloads (0: default)")
+    ap.add_argument("--degrees", default="0,1,5,10,20",
+                    help="highdeg workload: the degrees p to time")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -724,7 +728,7 @@ def main():
                           "config": {"workload": r["workload"]}, "result": r}))
         return
     if a.workload == "highdeg":
-        rs = [highdeg_run(p, a.steps, a.warmup) for p in (0, 1, 5, 10, 20)]
+        rs = [highdeg_run(int(p), a.steps, a.warmup) for p in a.degrees.split(",")]
         r20 = rs[-1]
         print(json.dumps({**base, "metric": "DG time-unknowns solved/s to rel. residual 1e-8",
                           "value": r20["unknowns_per_s"], "ms_per_step": r20["ms_per_solve"],
@@ -741,6 +745,13 @@ def main():
         r = long_batch_run(a.batch or 64, 24, a.precision, a.steps, a.warmup)
         print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
                           "config": {"workload": r["workload"]}, "result": r}))
+        return
+    if a.workload == "periodic":
+        r = periodic_case(a.p, a.log2n, a.steps, a.warmup)
+        print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
+                          "config": {"workload": f"u'+u=f time-periodic (u(0) = u(T)), T=1000, "
+                                                 f"N=2^{a.log2n} slabs, p={a.p}, V(2,2) to 1e-10"},
+                          "result": r}))
         return
     if a.workload == "heat":
         r = heat_run(a.steps, a.warmup)
