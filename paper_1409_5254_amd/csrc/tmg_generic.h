@@ -137,8 +137,11 @@ __device__ __forceinline__ void g_store(double *base, const double (&x)[P], int6
     for (int k = 0; k < P; ++k) p[k] = x[k];
 }
 
+// P >= 16: held to 256 registers so that two wavefronts share a SIMD (the
+// legs are bound by the products with the P x P blocks, whose LDS reads one
+// wavefront alone cannot hide)
 template <int P, bool BW>
-__global__ __launch_bounds__(kGenThreads) void k_gleg(LegArgsT<double> a)
+__global__ __launch_bounds__(kGenThreads, P >= 16 ? 2 : 1) void k_gleg(LegArgsT<double> a)
 {
     __shared__ GOps<P> op;
     __shared__ double xw[2][kGWaves];
