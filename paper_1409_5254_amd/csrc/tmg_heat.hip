@@ -206,6 +206,13 @@ struct HLeg {
     {
         ldn<P * P>(T + (int64_t)row(i) * P * P, c);
     }
+    // ... and at the mirrored point nx-1-i: the factors of the elimination
+    // down the points (the spatial operator has the same blocks E on both
+    // sides of D, so eliminating from the last point gives C'_i = C_{nx-1-i})
+    __device__ __forceinline__ void ld_tab_m(const double *T, int i, double (&c)[P * P]) const
+    {
+        ldn<P * P>(T + (int64_t)(a.nx - 1 - row(i)) * P * P, c);
+    }
     // u_m += R_i^T e_{m/2} (i the parity of m)
     __device__ __forceinline__ void add_e(const double (&e)[P], double (&u)[P]) const
     {
@@ -463,6 +470,154 @@ struct HLeg {
                         }
                     }
             });
+    }
+
+    // ---- Legs of two sweeps (whole point range).  The first sweep's back
+    // substitution and the second sweep's elimination run in one walk down
+    // the points (the second eliminates from the last point: C'_i =
+    // C_{nx-1-i}, C'^{-1}_i E = C_{nx-1-i}^{-1} E), whose back substitution
+    // then runs up the points with the leg's outputs: three walks instead of
+    // four.
+
+    // x_i = y_i - C_i^{-1} E x_{i+1} and u_i <- (1 - omega) u_i + omega x_i
+    // into the workspace; then y'_i = C'^{-1}_i (f_i + v w_i - E y'_{i+1}) with
+    // w_i the left slab's new end value, into Y (whose y_i is consumed).
+    __device__ __forceinline__ void bsub_elim_down() const
+    {
+        constexpr int B2 = B > 1 ? B / 2 : 1;
+        const int nb2 = (i1 - i0 + B2 - 1) / B2;
+        struct Buf {
+            double y[B2][P], u[B2][P], f[B2][P], g[B2], cg[kPre ? B2 : 1][P * P],
+                cc[kPre ? B2 : 1][P * P];
+        };
+        double x[P], yp[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = yp[k] = 0.0;
+        pipe2<Buf>(
+            nb2, true,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B2; ++j) {
+                    const int i = i0 + b * B2 + j;
+                    ld(Y(row(i)), q.y[j]);
+                    ld(U(row(i)), q.u[j]);
+                    ld_rhs(i, q.f[j], q.g[j]);
+                    if constexpr (kPre) {
+                        ld_tab(tG, i, q.cg[j]);
+                        ld_tab_m(tC, i, q.cc[j]);
+                    }
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = B2 - 1; j >= 0; --j) {
+                    const int i = i0 + b * B2 + j;
+                    if (i < i1) {
+                        double un[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = q.y[j][k];
+#pragma unroll
+                            for (int l = 0; l < P; ++l) {
+                                double c;
+                                if constexpr (kPre) c = q.cg[j][k * P + l];
+                                else c = tab(tG, (int64_t)i * P * P + k * P + l);
+                                t -= c * x[l];
+                            }
+                            un[k] = t;
+                        }
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            x[k] = un[k];
+                            un[k] = a.omc * q.u[j][k] + a.om * un[k];
+                        }
+                        st(U(i), un);
+                        const double w = wl(un, q.g[j]);
+                        double z[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k)   // - E y'_{i+1} = + M y'_{i+1} / h^2
+                            z[k] = q.f[j][k] + ((k & 1) ? -w : w) + mdh[k] * yp[k];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = 0.0;
+#pragma unroll
+                            for (int l = 0; l < P; ++l) {
+                                double c;
+                                if constexpr (kPre) c = q.cc[j][k * P + l];
+                                else c = tab(tC, (int64_t)(a.nx - 1 - i) * P * P + k * P + l);
+                                t += c * z[l];
+                            }
+                            yp[k] = t;
+                        }
+                        st(Y(i), yp);
+                    }
+                }
+            });
+    }
+    // The back substitution of the elimination down the points, up the
+    // points: x_i = y'_i - C'^{-1}_i E x_{i-1}, the damped update, the result
+    // to u_out and, one point behind, into the residual.
+    __device__ __forceinline__ void bsub_up_fin(double &acc) const
+    {
+        struct Buf {
+            double y[B][P], u[B][P], f[B][P], g[B], cg[kPre ? B : 1][P * P];
+        };
+        double x[P], um[P], uc[P], fc[P], gc = 0.0;   // chain; iterate at i-2, i-1; f, u0 at i-1
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = um[k] = uc[k] = fc[k] = 0.0;
+        pipe2<Buf>(
+            nb, false,
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const int i = i0 + b * B + j;
+                    ld(Y(row(i)), q.y[j]);
+                    ld(U(row(i)), q.u[j]);
+                    ld_rhs(i, q.f[j], q.g[j]);
+                    if constexpr (kPre) ld_tab_m(tG, i, q.cg[j]);
+                }
+            },
+            [&](int b, Buf &q) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    const int i = i0 + b * B + j;
+                    if (i < i1) {
+                        double un[P];
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            double t = q.y[j][k];
+#pragma unroll
+                            for (int l = 0; l < P; ++l) {
+                                double c;
+                                if constexpr (kPre) c = q.cg[j][k * P + l];
+                                else c = tab(tG, (int64_t)(a.nx - 1 - i) * P * P + k * P + l);
+                                t -= c * x[l];
+                            }
+                            un[k] = t;
+                        }
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            x[k] = un[k];
+                            un[k] = a.omc * q.u[j][k] + a.om * un[k];
+                        }
+                        if (a.u_out && out) st(a.u_out + ((int64_t)i * a.N + m) * P, un);
+                        if (resid && i > i0) resid_point(i - 1, um, uc, un, fc, gc, acc);
+#pragma unroll
+                        for (int k = 0; k < P; ++k) {
+                            um[k] = uc[k];
+                            uc[k] = un[k];
+                            fc[k] = q.f[j][k];
+                        }
+                        gc = q.g[j];
+                    }
+                }
+            });
+        if (resid) {
+            double z0[P];
+#pragma unroll
+            for (int k = 0; k < P; ++k) z0[k] = 0.0;
+            resid_point(i1 - 1, um, uc, z0, fc, gc, acc);
+        }
     }
 
     // ---- Partitioned sweeps.  K wavefronts share the tile, wavefront c
@@ -723,11 +878,16 @@ __global__ __launch_bounds__(kHT) void k_hleg(HeatArgs a)
             if (a.e) g.template forward<kFromZero, true>();
             else g.template forward<kFromZero, false>();
         }
-        for (int s = 1; s < a.sweeps; ++s) {
-            g.template backward<false>(acc);
-            g.template forward<kFromWs, false>();
+        if (a.sweeps == 2) {
+            g.bsub_elim_down();
+            g.bsub_up_fin(acc);
+        } else {
+            for (int s = 1; s < a.sweeps; ++s) {
+                g.template backward<false>(acc);
+                g.template forward<kFromWs, false>();
+            }
+            g.template backward<true>(acc);
         }
-        g.template backward<true>(acc);
     }
     if (a.partial) {
         acc = wave_sum(acc);
