@@ -200,7 +200,9 @@ int tmg_set_schedule(tmg_handle h, int64_t bottom_cap, int pairs, int span, int 
  * matrices with z = lambda tau, alpha and the damping of Lemma
  * chap4_lemma7, as tmg_setup builds them, to the same bits) are rebuilt by a
  * kernel on stream s, so nothing is read back to the host and no buffer,
- * schedule or graph is rebuilt.  Later calls on h see the new tables in
+ * schedule or graph is rebuilt (a W-cycle's dense bottom operator, see
+ * tmg_set_dense_bottom, is recomputed from the new tables by kernels before
+ * the next cycle, in place).  Later calls on h see the new tables in
  * stream order (work on another stream must be ordered after s by the
  * caller).  A lambda that is not finite and positive leaves non-finite
  * tables: the next solve then returns TMG_ERR_NONFINITE.  Returns
@@ -221,6 +223,25 @@ int tmg_set_lambda(tmg_handle h, const double *lambda, tmg_stream s);
  * Returns TMG_ERR_INVALID for a null handle.
  */
 int tmg_set_active_set(tmg_handle h, int on);
+
+/*
+ * The W-cycle's bottom visits as one dense operator (on by default).  The
+ * gamma visits of a level that the cycle's recursion makes from a zero
+ * iterate (the recursion of eq. chap4_errorTwoGridCycle, section 3, applied
+ * below that level, with the exact solve on the coarsest) form one fixed
+ * linear map of that level's right-hand side.  Where it applies (one
+ * instance, FP64, gamma = 2, forward solves and cycles, a bottom level
+ * strictly between level 0 and the coarsest with at most 4096 unknowns) the
+ * library builds the map's matrix once per schedule and set of tables
+ * (n x n doubles, n = slabs x (p + 1), at most 128 MiB of device memory;
+ * one bottom-kernel visit per unit load, before the first cycle that uses
+ * it) and applies it at each visit instead of the recursion.  The result is
+ * the same cycle up to rounding (the matrix-vector product sums in another
+ * order).  on = 0 runs the recursion at every visit.  Drops the graphs
+ * captured so far (waits for the handle's queued work and for stream s).
+ * Returns TMG_ERR_INVALID for a null handle.
+ */
+int tmg_set_dense_bottom(tmg_handle h, int on, tmg_stream s);
 
 /*
  * For callers that cannot allocate device memory (code that must not call

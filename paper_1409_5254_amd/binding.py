@@ -28,7 +28,7 @@ MAX_TUNED_DEGREE = 5
 # every symbol the header declares
 SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_adjoint_solve",
            "tmg_autotune", "tmg_set_schedule", "tmg_set_active_set",
-           "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
+           "tmg_set_dense_bottom", "tmg_destroy", "tmg_error_string", "tmg_last_hip_error", "tmg_level_info",
            "tmg_level_size", "tmg_op_down", "tmg_op_up", "tmg_op_fused", "tmg_op_fused2",
            "tmg_op_coarse_solve",
            "tmg_op_residual_norm", "tmg_solve_noalloc", "tmg_op_down32", "tmg_op_up32",
@@ -87,6 +87,7 @@ def lib():
             "tmg_autotune": (_i, [_vp, _vp, _vp, _vp, P(_i64), P(_i), P(_i), P(_i), P(_i), _vp]),
             "tmg_set_schedule": (_i, [_vp, _i64, _i, _i, _i, _i, _vp]),
             "tmg_set_active_set": (_i, [_vp, _i]),
+            "tmg_set_dense_bottom": (_i, [_vp, _i, _vp]),
             "tmg_set_lambda": (_i, [_vp, _vp, _vp]),
             "tmg_destroy": (_i, [_vp]),
             "tmg_error_string": (ctypes.c_char_p, [_i]),
@@ -253,6 +254,13 @@ class Solver:
         """Later cycles of a batch on the running instances' tiles only
         (on by default; the results are bitwise the same either way)."""
         self._check(lib().tmg_set_active_set(self._h, int(bool(on))), "tmg_set_active_set")
+
+    def set_dense_bottom(self, on):
+        """A W-cycle's bottom visits as one precomputed dense operator (on by
+        default; the same cycle up to rounding); off: the recursion at every
+        visit."""
+        self._check(lib().tmg_set_dense_bottom(self._h, int(bool(on)), _stream()),
+                    "tmg_set_dense_bottom")
 
     def vcycle(self, f, u0, u):
         self._check(lib().tmg_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),

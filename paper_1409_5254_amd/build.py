@@ -23,7 +23,7 @@ SOURCES = ([("tmg_bottom.hip", [f"-DTMG_BOTTOM_P={p}"], f"tmg_bottom_p{p}") for 
            + [("tmg_generic.hip", [f"-DTMG_GEN_P={p}"], f"tmg_generic_p{p}") for p in range(21, 0, -1)]
            + [(s, [], os.path.splitext(s)[0]) for s in
               ("tmg_leg64.hip", "tmg_leg32.hip", "tmg_span.hip", "tmg_mix.hip", "tmg_capi.cpp",
-               "tmg_heat.hip", "tmg_heat_capi.cpp", "tmg_kernels.hip", "tmg_tables.cpp")])
+               "tmg_heat.hip", "tmg_heat_capi.cpp", "tmg_kernels.hip", "tmg_dense.hip", "tmg_tables.cpp")])
 ARCH = "gfx950"
 
 

@@ -35,6 +35,7 @@
 #include <set>
 #include <new>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tmg.h"
@@ -192,6 +193,15 @@ struct tmg_ctx {
     double *T_d = nullptr;                        // [batch] T_j and N_j: tables built on the
     int64_t *N_d = nullptr;                       // device (tmg_set_lambda)
     bool lam_device = false;                      // lambda last set from a device array
+    // A W-cycle's bottom visits as one dense operator (one FP64 instance,
+    // forward solves): D of the bottom level (dense_n unknowns), its rows'
+    // lengths, valid for the current schedule and tables while dense_ok.
+    bool dense_on = true;
+    bool dense_ok = false;
+    int dense_level = -1;
+    int64_t dense_n = 0, dense_cap = 0;
+    double *dense = nullptr;
+    int *dense_len = nullptr;
     std::map<std::tuple<int, int, int>, TileList> tiles;
     std::map<int, std::pair<int *, int>> op_coarse;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -261,6 +271,16 @@ struct tmg_ctx {
     int H_gup0() const { return rs(opt.nu1 + opt.nu2 + 1); }
     // every bottom-kernel level fits one wavefront (one-wavefront work-groups)
     bool small_bottom() const { return bottom_cap <= 64 * bottom_slabs(P); }
+    // the dense bottom operator applies: a W-cycle on one instance in FP64
+    // whose bottom level lies strictly between level 0 and the coarsest
+    bool want_dense() const
+    {
+        if (!dense_on || opt.gamma < 2 || batch != 1 || generic || mixed || fixed() ||
+            opt.periodic || lb.empty())
+            return false;
+        const int l = lb[0];
+        return l >= 1 && l < L[0] - 1 && (N[0] >> l) * P <= kDenseMaxN;
+    }
     // spans of K levels (k_span, one top-level slab per thread): the down
     // legs lose nu1 + 1 slabs at the top level and, at each level below,
     // half the wrong slabs restricted from above plus nu1 + 1 (the last
@@ -760,6 +780,14 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
     int rc;
     LevelStore<T> &L = store<T>(c);
     c->cur[l] = 0;
+    if constexpr (std::is_same<T, double>::value) {
+        // the instance's gamma bottom visits from zero in one product
+        if (c->dense_ok && !io.trans && l == c->dense_level) {
+            HIPCHK(c, launch_dense_apply(c->dense, c->dense_len, L.f[l], L.x(l, 0), c->dense_n,
+                                         io.use_state ? c->st : nullptr, s));
+            return TMG_OK;
+        }
+    }
     for (int g = 0; g < c->opt.gamma; ++g) {
         const int cur = c->cur[l];
         // bottom instances: a first visit starts from zero in place, a repeated
@@ -1310,6 +1338,50 @@ int drain(tmg_ctx *c)
     return TMG_OK;
 }
 
+// Builds the dense bottom operator where it applies and is not current:
+// one work-group per unit load runs the bottom visits (columns of D), then
+// the rows' lengths.  Launched on s before any cycle that applies it; the
+// buffers grow only after a schedule change, which drops every graph.
+int ensure_dense(tmg_ctx *c, hipStream_t s)
+{
+    if (c->dense_ok || !c->want_dense()) return TMG_OK;
+    const int l = c->lb[0];
+    const int64_t N = c->N[0] >> l, n = N * c->P;
+    int rc;
+    if (n * n > c->dense_cap) {
+        if ((rc = drain(c))) return rc;
+        HIPCHK(c, hipStreamSynchronize(s));
+        dfree(c, c->dense);
+        dfree(c, c->dense_len);
+        c->dense = nullptr;
+        c->dense_len = nullptr;
+        c->dense_cap = 0;
+        if ((rc = dalloc(c, &c->dense, (size_t)(n * n))) ||
+            (rc = dalloc(c, &c->dense_len, (size_t)kDenseMaxN)))
+            return rc;
+        c->dense_cap = n * n;
+    }
+    // cycles a solve left queued past convergence may still read D
+    if (c->drain_pending) HIPCHK(c, hipStreamWaitEvent(s, c->drain_ev, 0));
+    DenseColArgs a{};
+    a.tab = c->tab_fwd;   // instance 0
+    a.tab_level = (int64_t)c->batch * c->tab_stride;
+    a.R = c->R_fwd;
+    a.D = c->dense;
+    a.N = N;
+    a.level = l;
+    a.Lc = c->L[0] - 1;
+    a.nu1 = c->opt.nu1;
+    a.nu2 = c->opt.nu2;
+    a.gamma = c->opt.gamma;
+    HIPCHK(c, launch_dense_cols(c->P, a, s));
+    HIPCHK(c, launch_dense_len(c->dense, n, c->dense_len, s));
+    c->dense_level = l;
+    c->dense_n = n;
+    c->dense_ok = true;
+    return TMG_OK;
+}
+
 void free_all(tmg_ctx *c)
 {
     (void)drain(c);
@@ -1384,6 +1456,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // while the state they read says finished: this solve resets that state,
     // so its stream waits for them first (nothing to wait for on one stream)
     if (c->drain_pending) HIPCHK(c, hipStreamWaitEvent(s, c->drain_ev, 0));
+    if (!trans && (rc = ensure_dense(c, s))) return rc;
     c->epoch = c->epoch % (1 << 20) + 1;
     const long long epoch = c->epoch;
     c->ctl_host->rtol2 = rtol * rtol;
@@ -1659,6 +1732,7 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
     c->bot_all_d = nullptr;
     const int Lm = c->Lmax, batch = c->batch, P = c->P;
     c->lb = lbv;
+    c->dense_ok = false;
     c->bottom_cap = cap;
     c->pairs = pairs;
     c->span = c->span_fits(span) ? span : 0;
@@ -2034,7 +2108,7 @@ int tmg_vcycle(tmg_handle c, const double *f, const double *u0, double *u, tmg_s
     if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     int rc = make_tiles(c, s);
-    if (rc) return rc;
+    if (rc || (rc = ensure_dense(c, s))) return rc;
     CycleIO io{f, c->opt.periodic ? nullptr : u0, u, false, false, -1};
     return enqueue_cycle(c, io, s);
 }
@@ -2216,6 +2290,21 @@ int tmg_set_lambda(tmg_handle c, const double *lambda, tmg_stream stream)
                                 c->opt.omega_mode, c->opt.omega, c->tab_stride, c->tab_fwd,
                                 c->tab_adj, c->tab32_fwd, c->tab32_adj, s));
     c->lam_device = true;
+    c->dense_ok = false;   // rebuilt from the new tables before the next cycle
+    return TMG_OK;
+}
+
+int tmg_set_dense_bottom(tmg_handle c, int on, tmg_stream stream)
+{
+    if (!c) return TMG_ERR_INVALID;
+    // graphs captured with the other form are dropped
+    const int rc = drain(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    c->dense_on = on != 0;
+    c->dense_ok = false;
     return TMG_OK;
 }
 

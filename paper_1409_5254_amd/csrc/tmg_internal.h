@@ -282,6 +282,33 @@ hipError_t launch_gbottom(int P, bool backward, const BottomArgsT<double> &a, in
                           hipStream_t s);
 template <typename TIO>
 hipError_t launch_bottom(int P, bool backward, const BottomArgsT<TIO> &a, int ninst, hipStream_t s);
+
+// The gamma visits of a W-cycle's bottom level (one instance, forward, from
+// zero) are one linear map of that level's right-hand side: D, n x n with
+// n = N P, row-major over the level's unknowns (slab-major).  Its columns
+// are the bottom kernel's visits of the unit loads (tmg_bottom.hip); the
+// cycle then applies D instead of repeating the recursion below the level.
+constexpr int64_t kDenseMaxN = 4096;   // unknowns of the level (D: 128 MiB)
+struct DenseColArgs {
+    const double *tab;   // the instance's tables: level l at tab + l * tab_level
+    const double *R;     // R_1^T, R_2^T
+    double *D;           // [n][n]
+    int64_t N;           // slabs of level `level` (at most the bottom kernel's)
+    int64_t tab_level;
+    int level, Lc, nu1, nu2, gamma;   // Lc: the coarsest level
+};
+template <int PP>
+hipError_t launch_dense_cols_p(const DenseColArgs &a, hipStream_t s);
+hipError_t launch_dense_cols(int P, const DenseColArgs &a, hipStream_t s);
+// len[i] = 1 + the column of row i's last nonzero entry (0: none).  Every
+// entry past it is an exact zero (a later unit load cannot reach the row's
+// slab before the coarsest level's block ends), so leaving them out of the
+// product changes no bit.
+hipError_t launch_dense_len(const double *D, int64_t n, int *len, hipStream_t s);
+// x = D r over the rows' lengths (nothing when *st says finished).
+hipError_t launch_dense_apply(const double *D, const int *len, const double *r, double *x,
+                              int64_t n, const InstState *st, hipStream_t s);
+
 // Level-0 halo slots of a tile list (tile_out output slabs and `halo` halo
 // slabs per tile) from the iterate u, as the level-0 pass stores them.
 hipError_t launch_seed(int P, bool backward, const double *u, double *hb, const int64_t *tile_off,

@@ -1,0 +1,153 @@
+"""GPU parity of the W-cycle's dense bottom operator (tmg_set_dense_bottom).
+
+The gamma visits that the W-cycle (eq. chap4_errorTwoGridCycle of section 3,
+applied recursively with the exact solve on the coarsest level) makes of a
+level from a zero iterate are one linear map of that level's right-hand
+side; the library tabulates it once per schedule and tables and applies it
+as a matrix.  The cycles are then the oracle's W-cycles up to the rounding of
+the matrix-vector product (its sums run in another order than the
+recursion's), so the bars are those of the other FP64 cycle tests: 1e-12
+against the oracle, for cycles from identical inputs and for converged
+solves with the same number of cycles.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import core  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+TOL = 1e-12
+
+
+def B():
+    from paper_1409_5254_amd import binding
+    return binding
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def bottom_max(P):
+    """Largest level of the bottom kernel (its work-group's slabs)."""
+    return (256 if P >= 5 else 512) * {1: 8, 2: 4}.get(P, 2)
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("log2cap", [3, 5, 7, 9])
+def test_dense_cycles_match_oracle(p, log2cap):
+    """Three W-cycles from a random start (tmg_vcycle) with the dense bottom
+    operator at a bottom level of 2^log2cap slabs, and with the recursion at
+    every visit, both against the oracle's cycles."""
+    P = p + 1
+    cap = 1 << log2cap
+    if cap > bottom_max(P) or cap * P > 4096:
+        pytest.skip("bottom level larger than the bottom kernel's or the dense operator's")
+    rng = np.random.default_rng(300 + 10 * p + log2cap)
+    N, T, lam, u0 = 4096, 10.0, 1.3, 0.5
+    f, u = rng.standard_normal(N * P), rng.standard_normal(N * P)
+    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, core.Opts(gamma=2))
+    out = {}
+    for on in (True, False):
+        s = B().Solver([N], [T], [lam], p=p, gamma=2)
+        s.set_schedule(cap, pairs=True)
+        s.set_dense_bottom(on)
+        du = dev(u)
+        for _ in range(3):
+            s.vcycle(dev(f), dev([u0]), du)
+        out[on] = host(du)
+        s.close()
+        assert relerr(out[on], ref) <= TOL, (on, relerr(out[on], ref))
+    assert relerr(out[True], out[False]) <= TOL
+
+
+@pytest.mark.parametrize("p,log2n,cap", [(0, 16, 4096), (1, 16, 2048), (3, 15, 1024),
+                                         (3, 14, 1024), (5, 14, 512), (2, 13, 64)])
+def test_dense_solve_matches_oracle(p, log2n, cap):
+    """W(2,2) solves to 1e-10 with the dense bottom operator at its largest
+    sizes (4096 unknowns) and a small one: the oracle's cycle count and its
+    solution at 1e-12."""
+    P = p + 1
+    rng = np.random.default_rng(500 + p + log2n)
+    N = 1 << log2n
+    T, lam, u0 = 1000.0 * N / (1 << 22), 1.0, 1.0
+    f = rng.standard_normal(N * P)
+    s = B().Solver([N], [T], [lam], p=p, gamma=2)
+    s.set_schedule(cap, pairs=True, direct=True)
+    res = s.solve(dev(f), dev([u0]), rtol=1e-10, max_cycles=60)
+    u = host(res.u)
+    s.close()
+    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=2))
+    assert res.status == 0 and res.cycles[0] == k, (res.status, res.cycles, k)
+    assert relerr(u, uo) <= TOL
+
+
+def test_dense_rebuilt_after_lambda_and_schedule():
+    """The operator follows the tables and the schedule: a new lambda (set
+    on the device) and then a new bottom level, each followed by W-cycles
+    against the oracle's for the same problem; graphs captured before each
+    change are replayed after it."""
+    p, N, T, u0 = 2, 4096, 10.0, 0.5
+    P = p + 1
+    rng = np.random.default_rng(77)
+    f, u = rng.standard_normal(N * P), rng.standard_normal(N * P)
+    s = B().Solver([N], [T], [1.3], p=p, gamma=2)
+    s.set_schedule(256, pairs=True)
+    for lam, cap in ((1.3, 256), (40.0, 256), (40.0, 64), (0.01, 64)):
+        if cap != 256:
+            s.set_schedule(cap, pairs=True)
+        s.set_lambda(dev([lam]))
+        res = s.solve(dev(f), dev([u0]), rtol=1e-10, max_cycles=60)
+        uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=2))
+        assert res.status == 0 and res.cycles[0] == k, (lam, cap, res.cycles, k)
+        assert relerr(host(res.u), uo) <= TOL, (lam, cap)
+        du = dev(u)
+        s.vcycle(dev(f), dev([u0]), du)
+        ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 1, core.Opts(gamma=2))
+        assert relerr(host(du), ref) <= TOL, (lam, cap)
+    s.close()
+
+
+def test_dense_off_for_batches_and_adjoint():
+    """Where the operator does not apply (a batch; the adjoint solve) the
+    W-cycle runs the recursion: a two-instance batch and the adjoint solve
+    of one instance against the oracle."""
+    p, N, T = 1, 2048, 10.0
+    P = p + 1
+    rng = np.random.default_rng(78)
+    fs = [rng.standard_normal(N * P) for _ in range(2)]
+    lams = [1.0, 7.0]
+    s = B().Solver([N, N], [T, T], lams, p=p, gamma=2)
+    s.set_schedule(128, pairs=True)
+    res = s.solve(dev(np.concatenate(fs)), dev([0.5, 0.25]), rtol=1e-10, max_cycles=60)
+    u = host(res.u)
+    s.close()
+    for j in range(2):
+        uo, k, _, _ = core.solve(p, T, lams[j], [0.5, 0.25][j], fs[j], opts=core.Opts(gamma=2))
+        assert res.cycles[j] == k
+        assert relerr(u[j * N * P:(j + 1) * N * P], uo) <= TOL
+    s = B().Solver([N], [T], [1.0], p=p, gamma=2)
+    s.set_schedule(128, pairs=True)
+    fw = s.solve(dev(fs[0]), dev([0.5]), rtol=1e-10, max_cycles=60)
+    z, _, _, cyc, _, st = s.adjoint_solve(dev(fs[1]), u=fw.u, rtol=1e-10, max_cycles=60)
+    z = host(z)
+    s.close()
+    zo, kz, _, _ = core.solve_folded(p, T, 1.0, fs[1], rtol=1e-10, trans=True,
+                                     opts=core.Opts(gamma=2))
+    assert st == 0 and cyc[0] == kz
+    assert relerr(z, zo) <= TOL
