@@ -195,13 +195,13 @@ struct tmg_ctx {
     bool lam_device = false;                      // lambda last set from a device array
     // A W-cycle's bottom visits as one dense operator (one FP64 instance,
     // forward solves): D of the bottom level (dense_n unknowns), its rows'
-    // lengths, valid for the current schedule and tables while dense_ok.
+    // windows, valid for the current schedule and tables while dense_ok.
     bool dense_on = true;
     bool dense_ok = false;
     int dense_level = -1;
     int64_t dense_n = 0, dense_cap = 0;
     double *dense = nullptr;
-    int *dense_len = nullptr;
+    int *dense_win = nullptr;
     std::map<std::tuple<int, int, int>, TileList> tiles;
     std::map<int, std::pair<int *, int>> op_coarse;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -247,6 +247,18 @@ struct tmg_ctx {
     {
         const int q = S < 4 ? 4 : S;
         return ((3 * (opt.nu1 + opt.nu2) + 1 + 2 * opt.nu1 + q - 1) / q) * q;
+    }
+    // The W-cycle's fused launch at a level l >= 1: the up leg of a first
+    // visit (nu1 + nu2 sweeps), the down leg of the next visit (nu1 sweeps,
+    // the residual) and, with next2, level l+1's first down leg from zero
+    // on the restricted residual (nu1 sweeps, the residual, restricted once
+    // more).  Wrong slabs counted without the saving of a zero start; with
+    // next2 in fine slabs, a multiple of 4 so that level-(l+2) pairs stay
+    // inside a tile.
+    int H_wfused(bool next2) const
+    {
+        const int w = 2 * opt.nu1 + opt.nu2 + 1;
+        return next2 ? r4(2 * ((w + 1) / 2 + opt.nu1 + 1)) : rs(w);
     }
     // V-cycle solves in FP64 fuse level 1's legs into the level-0 pass
     bool fuse_up1() const { return opt.gamma == 1 && !mixed && pairs; }
@@ -760,6 +772,10 @@ int enqueue_up(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t 
 template <typename T>
 int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, bool skip_up = false);
 
+// A W-cycle's two visits of a level that one instance streams (below).
+template <typename T>
+int enqueue_w_visits(tmg_ctx *c, const CycleIO &io, int l, bool ready, hipStream_t s);
+
 // skip_up: the up leg of this level runs inside the level-0 pass instead
 template <typename T>
 int enqueue_visit(tmg_ctx *c, const CycleIO &io, int level, bool zero, hipStream_t s,
@@ -783,10 +799,14 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
     if constexpr (std::is_same<T, double>::value) {
         // the instance's gamma bottom visits from zero in one product
         if (c->dense_ok && !io.trans && l == c->dense_level) {
-            HIPCHK(c, launch_dense_apply(c->dense, c->dense_len, L.f[l], L.x(l, 0), c->dense_n,
+            HIPCHK(c, launch_dense_apply(c->dense, c->dense_win, L.f[l], L.x(l, 0), c->dense_n,
                                          io.use_state ? c->st : nullptr, s));
             return TMG_OK;
         }
+        // one instance's streaming levels of a W-cycle in fused launches
+        if (c->opt.gamma == 2 && c->batch == 1 && c->pairs && !c->generic && !skip_up &&
+            l < c->lb[0])
+            return enqueue_w_visits<T>(c, io, l, false, s);
     }
     for (int g = 0; g < c->opt.gamma; ++g) {
         const int cur = c->cur[l];
@@ -880,6 +900,69 @@ int enqueue_pair(tmg_ctx *c, const CycleIO &io, int level, bool down, int kind, 
     HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
     return r0 ? finalize_r0(c, r0, tl, s) : TMG_OK;
 }
+
+// The W-cycle's launch between a level's two visits (one instance, l >= 1):
+// the up leg of the first visit (from zero) and the down leg of the second
+// from its result, restricted into level l+1, and with next2 level l+1's
+// first down leg from zero on it, restricted into level l+2.
+template <typename T>
+int enqueue_w_fused(tmg_ctx *c, const CycleIO &io, int l, bool next2, hipStream_t s)
+{
+    TileList *tl;
+    const int H = c->H_wfused(next2);
+    int rc = get_tiles(c, l, next2 ? kDeepNext : kDeep, c->TO(H), s, &tl);
+    if (rc) return rc;
+    if (tl->ntiles == 0) return TMG_OK;
+    LevelStore<T> &L = store<T>(c);
+    LegArgsT<T> a = leg_args<T>(c, l, io.trans, tl, H);
+    a.f = L.f[l];
+    a.e = L.x(l + 1, c->cur[l + 1]);
+    a.u_out = L.x(l, c->cur[l]);
+    a.rc = L.f[l + 1];
+    a.st = io.use_state ? c->st : nullptr;
+    a.pre = c->opt.nu1;
+    a.post = c->opt.nu2;
+    a.next = c->opt.nu1;
+    if (next2) {
+        a.tab1 = tab_of(c, l + 1, io.trans);
+        a.tab1T = tabT_of<T>(c, l + 1, io.trans);
+        a.c2slab_off = c->slab_off_d[l + 2];
+        a.f2 = L.f[l + 2];
+    }
+    HIPCHK(c, launch_leg<T>(c->P, io.trans, a, tl->ntiles, s));
+    return TMG_OK;
+}
+
+// A W-cycle's two visits of a level l >= 1 that one instance streams: each
+// visit is down(l), the visits of l+1, up(l), launched as
+//   [down(l) + first down(l+1)] ... [up(l) + down(l) + first down(l+1)] ... [up(l)]
+// where the first down leg of l+1 (from zero) joins the launch before it
+// when l+1 streams too.  `ready`: this level's first down leg ran in the
+// caller's launch (which then did not run level l+1's, so the first visit
+// of l+1 starts with its own launch).  Every kernel computes what the
+// one-level legs compute, in the same order, so the iterates are the same
+// to the last bit.
+template <typename T>
+int enqueue_w_visits(tmg_ctx *c, const CycleIO &io, int l, bool ready, hipStream_t s)
+{
+    const bool next2 = l + 1 < c->lb[0];
+    int rc;
+    c->cur[l] = 0;
+    if (!ready && (rc = next2 ? enqueue_pair<T>(c, io, l, true, kDeepNext, s)
+                              : enqueue_down<T>(c, io, l, true, s)))
+        return rc;
+    for (int g = 0; g < 2; ++g) {
+        // level l+1's first down leg ran in this call's last launch unless
+        // that launch was the caller's
+        const bool next_ready = g == 1 || !ready;
+        if ((rc = next2 ? enqueue_w_visits<T>(c, io, l + 1, next_ready, s)
+                        : enqueue_coarse_visits<T>(c, io, l + 1, s, false)))
+            return rc;
+        if (g == 0 && (rc = enqueue_w_fused<T>(c, io, l, next2, s))) return rc;
+    }
+    return enqueue_up<T>(c, io, l, false, s);
+}
+
 
 // First level run in spans: after the first span_after streaming levels
 // (spans pay only where a launch is latency-bound; the larger levels stay
@@ -1279,6 +1362,13 @@ int make_tiles(tmg_ctx *c, hipStream_t s)
             (rc = get_tiles(c, l, kPair2, c->TO(c->H_upair()), s, &tl)) ||
             (rc = get_tiles(c, l, kSingle2, c->TO(c->H_up()), s, &tl)))
             return rc;
+    // one instance's W-cycle: first-visit down pairs and fused launches
+    if (c->opt.gamma == 2 && c->batch == 1 && !c->generic)
+        for (int l = 1; l < c->Lmax; ++l)
+            if ((rc = get_tiles(c, l, kDeepNext, c->TO(c->H_dpair()), s, &tl)) ||
+                (rc = get_tiles(c, l, kDeepNext, c->TO(c->H_wfused(true)), s, &tl)) ||
+                (rc = get_tiles(c, l, kDeep, c->TO(c->H_wfused(false)), s, &tl)))
+                return rc;
     if (c->span_fits(c->span))
         for (int l = 1; l < c->Lmax; ++l)
             if ((rc = get_tiles(c, l, kDeep, kSpanThreads - c->H_sdown(c->span), s, &tl)) ||
@@ -1340,7 +1430,7 @@ int drain(tmg_ctx *c)
 
 // Builds the dense bottom operator where it applies and is not current:
 // one work-group per unit load runs the bottom visits (columns of D), then
-// the rows' lengths.  Launched on s before any cycle that applies it; the
+// the rows' windows.  Launched on s before any cycle that applies it; the
 // buffers grow only after a schedule change, which drops every graph.
 int ensure_dense(tmg_ctx *c, hipStream_t s)
 {
@@ -1352,12 +1442,12 @@ int ensure_dense(tmg_ctx *c, hipStream_t s)
         if ((rc = drain(c))) return rc;
         HIPCHK(c, hipStreamSynchronize(s));
         dfree(c, c->dense);
-        dfree(c, c->dense_len);
+        dfree(c, c->dense_win);
         c->dense = nullptr;
-        c->dense_len = nullptr;
+        c->dense_win = nullptr;
         c->dense_cap = 0;
         if ((rc = dalloc(c, &c->dense, (size_t)(n * n))) ||
-            (rc = dalloc(c, &c->dense_len, (size_t)kDenseMaxN)))
+            (rc = dalloc(c, &c->dense_win, (size_t)(2 * kDenseMaxN))))
             return rc;
         c->dense_cap = n * n;
     }
@@ -1375,7 +1465,7 @@ int ensure_dense(tmg_ctx *c, hipStream_t s)
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
     HIPCHK(c, launch_dense_cols(c->P, a, s));
-    HIPCHK(c, launch_dense_len(c->dense, n, c->dense_len, s));
+    HIPCHK(c, launch_dense_window(c->dense, n, c->dense_win, s));
     c->dense_level = l;
     c->dense_n = n;
     c->dense_ok = true;

@@ -1,4 +1,4 @@
-// The dense operator of a W-cycle's bottom visits: its rows' lengths and
+// The dense operator of a W-cycle's bottom visits: its rows' windows and
 // its application (the columns are built in tmg_bottom.hip).
 #include <hip/hip_runtime.h>
 
@@ -14,70 +14,124 @@ constexpr int kDenseRows = 4;               // rows per work-group (one load of 
 // column pairs per thread that cover the largest operator's rows
 constexpr int kDensePasses = (int)(kDenseMaxN / (2 * kDenseThreads));
 
-// len[row] = 1 + the last column with a nonzero entry: one wavefront per row.
-__global__ __launch_bounds__(kDenseThreads) void k_dense_len(const double *__restrict__ D, int64_t n,
-                                                          int *__restrict__ len)
+// Stands in for a missing state (never finished), so that the flag's load
+// needs no branch.
+__device__ InstState g_no_state{};
+
+// Row windows (see launch_dense_window): one wavefront per row, a pass for
+// the row's largest magnitude, a pass for the first and last column above
+// the drop threshold.
+__global__ __launch_bounds__(kDenseThreads) void k_dense_window(const double *__restrict__ D,
+                                                             int64_t n, int *__restrict__ win)
 {
     const int64_t row = (int64_t)blockIdx.x * kDenseWaves + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
     const double *d = D + row * n;
-    int last = -1;
+    double M = 0.0;
+    int bad = 0;
+    for (int64_t c = lane; c < n; c += 64) {
+        if (!isfinite(d[c])) bad = 1;
+        else M = fmax(M, fabs(d[c]));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        M = fmax(M, __shfl_xor(M, o));
+        bad |= __shfl_xor(bad, o);
+    }
+    const double thr = ldexp(M, kDenseDropExp);
+    int first = (int)n, last = -1;
     for (int64_t c = lane; c < n; c += 64)
-        if (d[c] != 0.0) last = (int)c;
-    for (int o = 32; o > 0; o >>= 1) last = max(last, __shfl_xor(last, o));
-    if (lane == 0) len[row] = last + 1;
+        if (fabs(d[c]) > thr) {
+            first = min(first, (int)c);
+            last = (int)c;
+        }
+    for (int o = 32; o > 0; o >>= 1) {
+        first = min(first, __shfl_xor(first, o));
+        last = max(last, __shfl_xor(last, o));
+    }
+    if (lane == 0) {
+        int s = 0, e = 0;
+        if (bad) {
+            e = (int)n;
+        } else if (last >= 0) {
+            s = first & ~1;
+            e = last + 1;
+        }
+        win[2 * row] = s;
+        win[2 * row + 1] = e;
+    }
 }
 
 // x = D r: kDenseRows rows per work-group.  Thread t takes the column pairs
-// (c, c + 1), c = 2 t + 2 kDenseThreads i, of every row: every load is
-// issued first (16-byte loads; VEC = false: one column at a time, for an odd
-// n or unaligned arrays), then the thread sums its products in column
-// order, and the threads' sums of a row are combined in a fixed order
-// (butterfly within each wavefront, the wavefronts in turn), so every run
-// gives the same bits.  Pairs at or past a row's length are not read (the
-// entries there are zero; a pair that straddles the length adds 0 r_c).
+// (c, c + 1), c = c0 + 2 t + 2 kDenseThreads i, from the smallest window
+// start c0 of the group's rows, and of each row the pairs inside its window:
+// every load is issued first (16-byte loads; VEC = false: one column at a
+// time, for an odd n or unaligned arrays), then the thread sums its
+// products in column order, and the threads' sums of a row are combined in
+// a fixed order (butterfly within each wavefront, the wavefronts in turn),
+// so every run gives the same bits.  (A pair that ends one past a window
+// adds one more small product.)
 template <bool VEC>
 __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__restrict__ D,
-                                                            const int *__restrict__ len,
+                                                            const int *__restrict__ win,
                                                             const double *__restrict__ r,
                                                             double *__restrict__ x, int64_t n,
                                                             const InstState *__restrict__ st)
 {
-    if (st && st->done) return;
     __shared__ double red[kDenseRows][kDenseWaves];
     const int64_t row0 = (int64_t)blockIdx.x * kDenseRows;
     const int t = threadIdx.x;
-    int m[kDenseRows];
-    int mm = 0;
+    // the windows and the state flag in one round trip
+    const InstState *sp = st ? st : &g_no_state;
+    int ws[kDenseRows], we[kDenseRows];
 #pragma unroll
     for (int q = 0; q < kDenseRows; ++q) {
-        m[q] = row0 + q < n ? len[row0 + q] : 0;
-        mm = max(mm, m[q]);
+        const int64_t rq = min(row0 + q, n - 1);   // clamped: loads without branches
+        ws[q] = win[2 * rq];
+        we[q] = win[2 * rq + 1];
+    }
+    const int done = sp->done;
+    // the windows are inputs of this (empty) statement, so their loads are
+    // issued with the flag's, ahead of the exit test, and one wait covers all
+    __asm__ volatile("" ::"s"(ws[0]), "s"(ws[1]), "s"(ws[2]), "s"(ws[3]), "s"(we[0]), "s"(we[1]),
+                     "s"(we[2]), "s"(we[3]), "s"(done));
+    if (done) return;
+#pragma unroll
+    for (int q = 0; q < kDenseRows; ++q)
+        if (row0 + q >= n) we[q] = ws[q];   // a row past the end: an empty window
+    int c0 = (int)n, c1 = 0;
+#pragma unroll
+    for (int q = 0; q < kDenseRows; ++q) {
+        if (we[q] > ws[q]) {
+            c0 = min(c0, ws[q]);
+            c1 = max(c1, we[q]);
+        }
     }
     double rv[kDensePasses][2], dv[kDenseRows][kDensePasses][2];
 #pragma unroll
     for (int i = 0; i < kDensePasses; ++i) {
-        const int64_t c = 2 * t + 2 * kDenseThreads * i;
+        const int64_t c = c0 + 2 * t + 2 * kDenseThreads * i;
         if (VEC) {
             double2 a = make_double2(0.0, 0.0);
-            if (c < mm) a = *reinterpret_cast<const double2 *>(r + c);
+            if (c < c1) a = *reinterpret_cast<const double2 *>(r + c);
             rv[i][0] = a.x;
             rv[i][1] = a.y;
 #pragma unroll
             for (int q = 0; q < kDenseRows; ++q) {
                 double2 d = make_double2(0.0, 0.0);
-                if (c < m[q]) d = *reinterpret_cast<const double2 *>(D + (row0 + q) * n + c);
+                if (c >= ws[q] && c < we[q])
+                    d = *reinterpret_cast<const double2 *>(D + (row0 + q) * n + c);
                 dv[q][i][0] = d.x;
                 dv[q][i][1] = d.y;
             }
         } else {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                rv[i][h] = c + h < mm ? r[c + h] : 0.0;
+                const int64_t cc = c + h;
+                rv[i][h] = cc < c1 ? r[cc] : 0.0;
 #pragma unroll
                 for (int q = 0; q < kDenseRows; ++q)
-                    dv[q][i][h] = c + h < m[q] ? D[(row0 + q) * n + c + h] : 0.0;
+                    dv[q][i][h] = cc >= ws[q] && cc < we[q] ? D[(row0 + q) * n + cc] : 0.0;
             }
         }
     }
@@ -115,22 +169,22 @@ hipError_t launch_dense_cols(int P, const DenseColArgs &a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_dense_len(const double *D, int64_t n, int *len, hipStream_t s)
+hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t s)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dense_len, dim3((unsigned)((n + kDenseWaves - 1) / kDenseWaves)),
-                       dim3(kDenseThreads), 0, s, D, n, len);
+    hipLaunchKernelGGL(k_dense_window, dim3((unsigned)((n + kDenseWaves - 1) / kDenseWaves)),
+                       dim3(kDenseThreads), 0, s, D, n, win);
     return hipGetLastError();
 }
 
-hipError_t launch_dense_apply(const double *D, const int *len, const double *r, double *x,
+hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
                               int64_t n, const InstState *st, hipStream_t s)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows)), block(kDenseThreads);
     const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
-    if (vec) hipLaunchKernelGGL(k_dense_apply<true>, grid, block, 0, s, D, len, r, x, n, st);
-    else hipLaunchKernelGGL(k_dense_apply<false>, grid, block, 0, s, D, len, r, x, n, st);
+    if (vec) hipLaunchKernelGGL(k_dense_apply<true>, grid, block, 0, s, D, win, r, x, n, st);
+    else hipLaunchKernelGGL(k_dense_apply<false>, grid, block, 0, s, D, win, r, x, n, st);
     return hipGetLastError();
 }
 

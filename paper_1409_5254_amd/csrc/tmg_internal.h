@@ -300,13 +300,17 @@ struct DenseColArgs {
 template <int PP>
 hipError_t launch_dense_cols_p(const DenseColArgs &a, hipStream_t s);
 hipError_t launch_dense_cols(int P, const DenseColArgs &a, hipStream_t s);
-// len[i] = 1 + the column of row i's last nonzero entry (0: none).  Every
-// entry past it is an exact zero (a later unit load cannot reach the row's
-// slab before the coarsest level's block ends), so leaving them out of the
-// product changes no bit.
-hipError_t launch_dense_len(const double *D, int64_t n, int *len, hipStream_t s);
-// x = D r over the rows' lengths (nothing when *st says finished).
-hipError_t launch_dense_apply(const double *D, const int *len, const double *r, double *x,
+// Row i's window [win[2i], win[2i+1]): the columns from its first to its
+// last entry of magnitude above 2^-64 times the row's largest (the start
+// rounded down to even; every column if the row holds a non-finite entry).
+// The entries outside sum to at most n 2^-64 max_j |D_ij| ||r||_inf, at most
+// two units of FP64 rounding of the row's largest product for n <= 4096,
+// so the product leaves them out (the operator decays away from its
+// diagonal: slabs many decay lengths apart barely couple).
+constexpr int kDenseDropExp = -64;
+hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t s);
+// x = D r over the rows' windows (nothing when *st says finished).
+hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
                               int64_t n, const InstState *st, hipStream_t s);
 
 // Level-0 halo slots of a tile list (tile_out output slabs and `halo` halo

@@ -1,4 +1,5 @@
-"""GPU parity of the W-cycle's dense bottom operator (tmg_set_dense_bottom).
+"""GPU parity of the W-cycle's launches: the dense bottom operator
+(tmg_set_dense_bottom) and the fused streaming legs.
 
 The gamma visits that the W-cycle (eq. chap4_errorTwoGridCycle of section 3,
 applied recursively with the exact solve on the coarsest level) makes of a
@@ -9,6 +10,13 @@ the matrix-vector product (its sums run in another order than the
 recursion's), so the bars are those of the other FP64 cycle tests: 1e-12
 against the oracle, for cycles from identical inputs and for converged
 solves with the same number of cycles.
+
+The streaming levels of one instance's W-cycle run in fused launches (the
+first visit's up leg with the second visit's down leg, and each first
+visit's down leg with the level above's launch) when the schedule has
+two-level launches on; every kernel computes what the one-level legs
+compute, in the same order, so with them off the iterates must be equal to
+the last bit.
 """
 import numpy as np
 import pytest
@@ -149,5 +157,56 @@ def test_dense_off_for_batches_and_adjoint():
     s.close()
     zo, kz, _, _ = core.solve_folded(p, T, 1.0, fs[1], rtol=1e-10, trans=True,
                                      opts=core.Opts(gamma=2))
+    assert st == 0 and cyc[0] == kz
+    assert relerr(z, zo) <= TOL
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("nu", [(2, 2), (1, 0), (0, 3), (3, 1)])
+@pytest.mark.parametrize("dense", [True, False])
+def test_fused_w_legs_bitwise(p, nu, dense):
+    """Three W-cycles of one instance with the fused streaming launches and
+    with one-level legs, bitwise equal, and both equal to the oracle's
+    cycles at 1e-12 (N = 2^13: eight streaming levels above a bottom level
+    of 32 slabs, ragged tiles at every level)."""
+    P = p + 1
+    nu1, nu2 = nu
+    rng = np.random.default_rng(900 + 10 * p + nu1 * 4 + nu2)
+    N, T, lam, u0 = 8192, 20.0, 0.7, 0.5
+    f, u = rng.standard_normal(N * P), rng.standard_normal(N * P)
+    out = {}
+    for pairs in (True, False):
+        s = B().Solver([N], [T], [lam], p=p, gamma=2, nu1=nu1, nu2=nu2)
+        s.set_schedule(32, pairs=pairs)
+        s.set_dense_bottom(dense)
+        du = dev(u)
+        for _ in range(3):
+            s.vcycle(dev(f), dev([u0]), du)
+        out[pairs] = host(du)
+        s.close()
+    assert np.array_equal(out[True], out[False])
+    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, core.Opts(gamma=2, nu1=nu1, nu2=nu2))
+    assert relerr(out[True], ref) <= TOL
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_fused_w_solve_and_adjoint(p):
+    """A W(2,2) solve and the adjoint solve of one instance with the fused
+    launches (N = 2^14, bottom level 64 slabs) against the oracle: the same
+    cycle counts, solutions at 1e-12."""
+    P = p + 1
+    rng = np.random.default_rng(950 + p)
+    N, T, lam, u0 = 16384, 40.0, 1.1, 0.3
+    f, g = rng.standard_normal(N * P), rng.standard_normal(N * P)
+    s = B().Solver([N], [T], [lam], p=p, gamma=2)
+    s.set_schedule(64, pairs=True)
+    res = s.solve(dev(f), dev([u0]), rtol=1e-10, max_cycles=60)
+    z, _, _, cyc, _, st = s.adjoint_solve(dev(g), u=res.u, rtol=1e-10, max_cycles=60)
+    u, z = host(res.u), host(z)
+    s.close()
+    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=2))
+    assert res.status == 0 and res.cycles[0] == k
+    assert relerr(u, uo) <= TOL
+    zo, kz, _, _ = core.solve_folded(p, T, lam, g, rtol=1e-10, trans=True, opts=core.Opts(gamma=2))
     assert st == 0 and cyc[0] == kz
     assert relerr(z, zo) <= TOL
