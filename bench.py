@@ -43,7 +43,9 @@ Other workloads (`--workload`):
   batch       only the long-horizon batch solve (--precision 0 or 1), for
               profiler runs (with --schedule to skip the tuning);
   heat        the space-time heat equation u_t - u_xx = f (nx = 255 points,
-              N = 2^17 slabs on (0, 0.8], p = 1: 6.7e7 unknowns).
+              N = 2^17 slabs on (0, 0.8], p = 1: 6.7e7 unknowns);
+  wcycle      the scalar workload with the W(2,2)-cycle (--p, --log2n): the
+              bottom level's dense operator built once, then timed solves.
 """
 from __future__ import annotations
 
@@ -84,7 +86,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="default",
                     choices=["default", "scalar", "eigenmodes", "adjoint", "long", "highdeg",
-                             "convergence", "roofline", "batch", "heat", "periodic"])
+                             "convergence", "roofline", "batch", "heat", "periodic", "wcycle"])
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--cycle", choices=["V", "W"], default="V")
@@ -756,6 +758,13 @@ def main():
         print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
                           "config": {"workload": f"u'+u=f time-periodic (u(0) = u(T)), T=1000, "
                                                  f"N=2^{a.log2n} slabs, p={a.p}, V(2,2) to 1e-10"},
+                          "result": r}))
+        return
+    if a.workload == "wcycle":
+        r = w_cycle_case(a.p, a.log2n, a.steps, a.warmup)
+        print(json.dumps({**base, "value": r["unknowns_per_s"], "ms_per_step": r["ms_per_solve"],
+                          "config": {"workload": f"u'+u=f, T={1000.0 * (1 << a.log2n) / (1 << 22):g}, "
+                                                 f"N=2^{a.log2n} slabs, p={a.p}, W(2,2) to 1e-10"},
                           "result": r}))
         return
     if a.workload == "heat":

@@ -163,8 +163,11 @@ int tmg_adjoint_solve(tmg_handle h, const double *g, const double *u, double *z,
  * three runs timed with HIP events.  A schedule is the size up to which an
  * instance's levels run inside the single-work-group bottom kernel
  * (bottom_cap, the largest the bottom kernel holds divided by 1, 2, ...,
- * 32) and, for V-cycles, whether
- * consecutive levels share two-level launches, and whether the levels
+ * 32) and whether consecutive levels share two-level launches (V-cycles;
+ * for the W-cycle of one instance in FP64, pairs also fuses each level's
+ * up leg between its two visits with the next visit's down leg, and each
+ * first visit's down leg with the launch before it: the same iterates to
+ * the last bit, half the launches), and whether the levels
  * after the first `span_after` streaming levels below level 1 (in pairs, an
  * odd one out alone) run in spans of `span` levels per launch (3 or 4; 0:
  * no spans; V-cycles only), chosen in that order, then the caps next to
@@ -235,9 +238,14 @@ int tmg_set_active_set(tmg_handle h, int on);
  * library builds the map's matrix once per schedule and set of tables
  * (n x n doubles, n = slabs x (p + 1), at most 128 MiB of device memory;
  * one bottom-kernel visit per unit load, before the first cycle that uses
- * it) and applies it at each visit instead of the recursion.  The result is
- * the same cycle up to rounding (the matrix-vector product sums in another
- * order).  on = 0 runs the recursion at every visit.  Drops the graphs
+ * it) and applies it at each visit instead of the recursion.  The map
+ * decays away from its diagonal (slabs many decay lengths apart barely
+ * couple), so each row's product covers only the columns from its first to
+ * its last entry above 2^-64 times the row's largest magnitude: the entries
+ * left out contribute at most n 2^-64 max_j |D_ij| max_j |r_j|, two units
+ * of FP64 rounding of the row's largest product.  The result is the same
+ * cycle up to rounding (the product also sums in another order than the
+ * recursion).  on = 0 runs the recursion at every visit.  Drops the graphs
  * captured so far (waits for the handle's queued work and for stream s).
  * Returns TMG_ERR_INVALID for a null handle.
  */
@@ -253,8 +261,10 @@ int tmg_set_dense_bottom(tmg_handle h, int on, tmg_stream s);
  * library (TMG_NOALLOC_SCRATCH_BYTES per device, held from the library's
  * load to the end of the process).  The call allocates no device or pinned
  * host memory and creates no streams, events or graphs; it rebuilds the
- * tables and schedule (default schedule, cycles launched kernel by kernel)
- * on every call, and it blocks until the solve is done.
+ * tables and schedule (default schedule, cycles launched kernel by kernel;
+ * a W-cycle's bottom visits run the recursion, without the dense operator
+ * of tmg_set_dense_bottom) on every call, and it blocks until the solve is
+ * done.
  * f, u0 (length 1) and u are device arrays as for tmg_solve; cycles and
  * relres (host, may be NULL) receive one value each.  Returns as tmg_solve,
  * or TMG_ERR_SIZE when n_slabs * (p + 1) exceeds TMG_NOALLOC_MAX_UNKNOWNS.
