@@ -228,13 +228,14 @@ int tmg_set_lambda(tmg_handle h, const double *lambda, tmg_stream s);
 int tmg_set_active_set(tmg_handle h, int on);
 
 /*
- * The W-cycle's bottom visits as one dense operator (on by default).  The
+ * The bottom level's visits as one dense operator (on by default).  The
  * gamma visits of a level that the cycle's recursion makes from a zero
  * iterate (the recursion of eq. chap4_errorTwoGridCycle, section 3, applied
- * below that level, with the exact solve on the coarsest) form one fixed
- * linear map of that level's right-hand side.  Where it applies (one
- * instance, FP64, gamma = 2, forward solves and cycles, a bottom level
- * strictly between level 0 and the coarsest with at most 4096 unknowns) the
+ * below that level, with the exact solve on the coarsest; one visit for a
+ * V-cycle, two for a W-cycle) form one fixed linear map of that level's
+ * right-hand side.  Where it applies (one instance, FP64, forward solves
+ * and cycles, a bottom level strictly between level 0 and the coarsest with
+ * at most 4096 unknowns, which every bottom_cap of tmg_set_schedule gives) the
  * library builds the map's matrix once per schedule and set of tables
  * (n x n doubles, n = slabs x (p + 1), at most 128 MiB of device memory;
  * one bottom-kernel visit per unit load, before the first cycle that uses

@@ -256,9 +256,9 @@ class Solver:
         self._check(lib().tmg_set_active_set(self._h, int(bool(on))), "tmg_set_active_set")
 
     def set_dense_bottom(self, on):
-        """A W-cycle's bottom visits as one precomputed dense operator (on by
-        default; the same cycle up to rounding); off: the recursion at every
-        visit."""
+        """The bottom level's visits (V or W) as one precomputed dense
+        operator (on by default; the same cycle up to rounding); off: the
+        bottom kernel's recursion at every visit."""
         self._check(lib().tmg_set_dense_bottom(self._h, int(bool(on)), _stream()),
                     "tmg_set_dense_bottom")
 

@@ -193,9 +193,10 @@ struct tmg_ctx {
     double *T_d = nullptr;                        // [batch] T_j and N_j: tables built on the
     int64_t *N_d = nullptr;                       // device (tmg_set_lambda)
     bool lam_device = false;                      // lambda last set from a device array
-    // A W-cycle's bottom visits as one dense operator (one FP64 instance,
-    // forward solves): D of the bottom level (dense_n unknowns), its rows'
-    // windows, valid for the current schedule and tables while dense_ok.
+    // The bottom level's visits as one dense operator (one FP64 instance,
+    // forward solves; the gamma visits of a cycle's recursion): D of the
+    // bottom level (dense_n unknowns), its rows' windows, valid for the
+    // current schedule and tables while dense_ok.
     bool dense_on = true;
     bool dense_ok = false;
     int dense_level = -1;
@@ -283,12 +284,11 @@ struct tmg_ctx {
     int H_gup0() const { return rs(opt.nu1 + opt.nu2 + 1); }
     // every bottom-kernel level fits one wavefront (one-wavefront work-groups)
     bool small_bottom() const { return bottom_cap <= 64 * bottom_slabs(P); }
-    // the dense bottom operator applies: a W-cycle on one instance in FP64
-    // whose bottom level lies strictly between level 0 and the coarsest
+    // the dense bottom operator applies: one instance in FP64 whose bottom
+    // level lies strictly between level 0 and the coarsest (V or W)
     bool want_dense() const
     {
-        if (!dense_on || opt.gamma < 2 || batch != 1 || generic || mixed || fixed() ||
-            opt.periodic || lb.empty())
+        if (!dense_on || batch != 1 || generic || mixed || fixed() || opt.periodic || lb.empty())
             return false;
         const int l = lb[0];
         return l >= 1 && l < L[0] - 1 && (N[0] >> l) * P <= kDenseMaxN;
@@ -651,6 +651,14 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     int ninst;
     bottom_list(c, level, &inst, &ninst);
     if (ninst == 0) return TMG_OK;
+    if constexpr (std::is_same<T, double>::value) {
+        // a V-cycle's visit from zero: one product with the dense operator
+        if (c->dense_ok && c->opt.gamma == 1 && !io.trans && !x_in && level == c->dense_level) {
+            HIPCHK(c, launch_dense_apply(c->dense, c->dense_win, store<T>(c).f[level], x_out,
+                                         c->dense_n, io.use_state ? c->st : nullptr, s));
+            return TMG_OK;
+        }
+    }
     BottomArgsT<T> a{};
     a.f = level == 0 ? reinterpret_cast<const T *>(io.f) : store<T>(c).f[level];
     a.u0 = level == 0 ? fold_of(io) : nullptr;

@@ -1,7 +1,7 @@
-"""GPU parity of the W-cycle's launches: the dense bottom operator
-(tmg_set_dense_bottom) and the fused streaming legs.
+"""GPU parity of the cycles' launch forms: the dense bottom operator
+(tmg_set_dense_bottom, V and W) and the W-cycle's fused streaming legs.
 
-The gamma visits that the W-cycle (eq. chap4_errorTwoGridCycle of section 3,
+The gamma visits that a cycle (eq. chap4_errorTwoGridCycle of section 3,
 applied recursively with the exact solve on the coarsest level) makes of a
 level from a zero iterate are one linear map of that level's right-hand
 side; the library tabulates it once per schedule and tables and applies it
@@ -56,12 +56,13 @@ def bottom_max(P):
     return (256 if P >= 5 else 512) * {1: 8, 2: 4}.get(P, 2)
 
 
+@pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("log2cap", [3, 5, 7, 9])
-def test_dense_cycles_match_oracle(p, log2cap):
-    """Three W-cycles from a random start (tmg_vcycle) with the dense bottom
-    operator at a bottom level of 2^log2cap slabs, and with the recursion at
-    every visit, both against the oracle's cycles."""
+def test_dense_cycles_match_oracle(p, log2cap, gamma):
+    """Three V- or W-cycles from a random start (tmg_vcycle) with the dense
+    bottom operator at a bottom level of 2^log2cap slabs, and with the
+    recursion at every visit, both against the oracle's cycles."""
     P = p + 1
     cap = 1 << log2cap
     if cap > bottom_max(P) or cap * P > 4096:
@@ -69,10 +70,10 @@ def test_dense_cycles_match_oracle(p, log2cap):
     rng = np.random.default_rng(300 + 10 * p + log2cap)
     N, T, lam, u0 = 4096, 10.0, 1.3, 0.5
     f, u = rng.standard_normal(N * P), rng.standard_normal(N * P)
-    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, core.Opts(gamma=2))
+    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, core.Opts(gamma=gamma))
     out = {}
     for on in (True, False):
-        s = B().Solver([N], [T], [lam], p=p, gamma=2)
+        s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
         s.set_schedule(cap, pairs=True)
         s.set_dense_bottom(on)
         du = dev(u)
@@ -84,23 +85,24 @@ def test_dense_cycles_match_oracle(p, log2cap):
     assert relerr(out[True], out[False]) <= TOL
 
 
+@pytest.mark.parametrize("gamma", [1, 2])
 @pytest.mark.parametrize("p,log2n,cap", [(0, 16, 4096), (1, 16, 2048), (3, 15, 1024),
                                          (3, 14, 1024), (5, 14, 512), (2, 13, 64)])
-def test_dense_solve_matches_oracle(p, log2n, cap):
-    """W(2,2) solves to 1e-10 with the dense bottom operator at its largest
-    sizes (4096 unknowns) and a small one: the oracle's cycle count and its
-    solution at 1e-12."""
+def test_dense_solve_matches_oracle(p, log2n, cap, gamma):
+    """V(2,2) and W(2,2) solves to 1e-10 with the dense bottom operator at its
+    largest sizes (4096 unknowns) and a small one: the oracle's cycle count
+    and its solution at 1e-12."""
     P = p + 1
     rng = np.random.default_rng(500 + p + log2n)
     N = 1 << log2n
     T, lam, u0 = 1000.0 * N / (1 << 22), 1.0, 1.0
     f = rng.standard_normal(N * P)
-    s = B().Solver([N], [T], [lam], p=p, gamma=2)
+    s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
     s.set_schedule(cap, pairs=True, direct=True)
     res = s.solve(dev(f), dev([u0]), rtol=1e-10, max_cycles=60)
     u = host(res.u)
     s.close()
-    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=2))
+    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=gamma))
     assert res.status == 0 and res.cycles[0] == k, (res.status, res.cycles, k)
     assert relerr(u, uo) <= TOL
 
