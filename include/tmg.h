@@ -100,7 +100,10 @@ typedef struct {
 
 /* Degrees 0 .. 5 run on register-resident tuned kernels; degrees 6 .. 20, and
  * every periodic problem, on generic kernels (one slab per thread, operators
- * in LDS; every level except the coarsest streams, FP64 only). */
+ * in LDS, FP64 only; the levels above the bottom stream in one-level legs,
+ * and one work-group visits the levels of at most 256 slabs for p <= 9, 128
+ * above, as the bottom cap allows; the periodic problem's bottom is its
+ * coarsest level alone). */
 #define TMG_MAX_DEGREE 20
 #define TMG_MAX_TUNED_DEGREE 5
 

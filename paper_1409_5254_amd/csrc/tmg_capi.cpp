@@ -284,11 +284,21 @@ struct tmg_ctx {
     int H_gup0() const { return rs(opt.nu1 + opt.nu2 + 1); }
     // every bottom-kernel level fits one wavefront (one-wavefront work-groups)
     bool small_bottom() const { return bottom_cap <= 64 * bottom_slabs(P); }
+    // largest bottom cap: the bottom kernel's level, or the generic kernels'
+    // bottom visit (the periodic problem: its coarsest level only)
+    int64_t max_cap() const
+    {
+        if (!generic) return bottom_max(P);
+        return std::max<int64_t>(opt.n_coarse, opt.periodic ? 0 : gbottom_max(P));
+    }
+    // generic: the bottom spans several levels (k_gvisit)
+    bool gvisit() const { return generic && bottom_cap > opt.n_coarse; }
     // the dense bottom operator applies: one instance in FP64 whose bottom
-    // level lies strictly between level 0 and the coarsest (V or W)
+    // level lies strictly between level 0 and the coarsest (V or W; the
+    // generic kernels' bottom visit too, not the periodic problem's)
     bool want_dense() const
     {
-        if (!dense_on || batch != 1 || generic || mixed || fixed() || opt.periodic || lb.empty())
+        if (!dense_on || batch != 1 || mixed || fixed() || opt.periodic || lb.empty())
             return false;
         const int l = lb[0];
         return l >= 1 && l < L[0] - 1 && (N[0] >> l) * P <= kDenseMaxN;
@@ -681,6 +691,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     a.small = c->small_bottom();
     a.generic = c->generic;
     a.periodic = c->opt.periodic;
+    a.visit = c->gvisit();
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, ninst, s));
     return TMG_OK;
 }
@@ -716,6 +727,7 @@ int enqueue_bottom_all(tmg_ctx *c, const CycleIO &io, hipStream_t s)
     a.small = c->small_bottom();
     a.generic = c->generic;
     a.periodic = c->opt.periodic;
+    a.visit = c->gvisit();
     HIPCHK(c, launch_bottom<T>(c->P, io.trans, a, n, s));
     return TMG_OK;
 }
@@ -1472,7 +1484,7 @@ int ensure_dense(tmg_ctx *c, hipStream_t s)
     a.nu1 = c->opt.nu1;
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
-    HIPCHK(c, launch_dense_cols(c->P, a, s));
+    HIPCHK(c, c->generic ? launch_gdense_cols(c->P, a, s) : launch_dense_cols(c->P, a, s));
     HIPCHK(c, launch_dense_window(c->dense, n, c->dense_win, s));
     c->dense_level = l;
     c->dense_n = n;
@@ -1807,8 +1819,10 @@ int plan_levels(const std::vector<int> &L, const int64_t *n_slabs, int64_t cap,
 int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hipStream_t s)
 {
     if (c->generic) {
-        // one schedule: the bottom work-group solves the coarsest level only
-        cap = c->opt.n_coarse;
+        // the bottom work-group solves the coarsest level, or visits the
+        // levels up to gbottom_max(P) slabs (k_gvisit); every level above
+        // streams in one-level legs
+        cap = std::max<int64_t>(c->opt.n_coarse, std::min(cap, c->max_cap()));
         pairs = false;
         span = 0;
     }
@@ -1935,12 +1949,19 @@ int tmg_last_hip_error(tmg_handle h) { return h ? h->last_hip : 0; }
 namespace {
 
 // The generic kernels serve degrees above the tuned kernels' and the
-// periodic problem; there the bottom work-group solves the coarsest level
-// only (exactly) and every other level streams.
+// periodic problem; there every level above the bottom streams in one-level
+// legs, and the bottom work-group visits the levels up to gbottom_max(P)
+// slabs (the periodic problem: solves its coarsest level exactly).
 bool uses_generic(const tmg_options &o) { return o.p + 1 > kMaxTunedP || o.periodic != 0; }
 int64_t first_cap(const tmg_options &o)
 {
-    return uses_generic(o) ? o.n_coarse : schedule_cap(o.p + 1, o.schedule);
+    if (!uses_generic(o)) return schedule_cap(o.p + 1, o.schedule);
+    // the generic bottom visit up to gbottom_max(P) slabs (periodic: the
+    // coarsest level only)
+    const int64_t gmax = o.periodic ? o.n_coarse : gbottom_max(o.p + 1);
+    const int64_t cap = o.schedule < 0 ? gmax
+                                       : std::min<int64_t>(gmax, int64_t(1) << std::min(o.schedule, 40));
+    return std::max<int64_t>(o.n_coarse, cap);
 }
 
 // Argument checks of a set-up (host only): options, lambda, T, and every
@@ -2258,11 +2279,10 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
     // two-level launches), then how the streaming levels are launched at
     // that cap, then the launch mode
     std::vector<Cand> cands;
-    if (c->generic) cands.push_back({c->opt.n_coarse, false, 0, 2});   // only the launch mode
-    for (int k = 0; k <= 5 && !c->generic; ++k) {
-        const int64_t cap = (int64_t)bottom_max(c->P) >> k;
+    for (int k = 0; k <= 5; ++k) {
+        const int64_t cap = c->max_cap() >> k;
         if (cap < c->opt.n_coarse) break;
-        cands.push_back({cap, true, 0, 2});
+        cands.push_back({cap, !c->generic, 0, 2});
     }
     const Cand old{c->bottom_cap, c->pairs, c->span, c->span_after};
     c->direct = false;
@@ -2317,7 +2337,7 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
         // the second stage chose for it
         cands.clear();
         for (int64_t cap : {pick.cap * 2, pick.cap / 2})
-            if (cap >= c->opt.n_coarse && cap <= (int64_t)bottom_max(c->P))
+            if (cap >= c->opt.n_coarse && cap <= c->max_cap())
                 cands.push_back({cap, pick.pairs, pick.span, pick.after});
         if (rc >= 0) run_stage();
     }
@@ -2336,8 +2356,7 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
             best = ms;
             const Cand base = pick;
             for (int64_t cap : {base.cap * 2, base.cap / 2}) {
-                if (c->generic || cap < c->opt.n_coarse || cap > (int64_t)bottom_max(c->P))
-                    continue;
+                if (cap < c->opt.n_coarse || cap > c->max_cap()) continue;
                 if (apply_plan(c, cap, base.pairs, base.span, base.after, s) != TMG_OK) continue;
                 c->direct = true;
                 const float m2 = timed();
@@ -2366,10 +2385,9 @@ int tmg_autotune(tmg_handle c, const double *f, const double *u0, double *u, int
 int tmg_set_schedule(tmg_handle c, int64_t bottom_cap, int pairs, int span, int span_after,
                      int direct, tmg_stream stream)
 {
-    if (!c || bottom_cap < c->opt.n_coarse || bottom_cap > (int64_t)bottom_max(c->P))
-        return TMG_ERR_INVALID;
-    if (c->generic && (bottom_cap != c->opt.n_coarse || pairs || span))
-        return TMG_ERR_UNSUPPORTED;   // the generic kernels run one schedule
+    if (!c || bottom_cap < c->opt.n_coarse || bottom_cap > c->max_cap()) return TMG_ERR_INVALID;
+    if (c->generic && (pairs || span))
+        return TMG_ERR_UNSUPPORTED;   // the generic kernels stream in one-level legs
     if (span != 0 && (!pairs || c->opt.gamma != 1 || !c->span_fits(span) || span_after < 1))
         return TMG_ERR_INVALID;
     const int rc = apply_plan(c, bottom_cap, pairs != 0, span, span_after, (hipStream_t)stream);

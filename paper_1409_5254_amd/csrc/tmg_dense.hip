@@ -169,6 +169,12 @@ hipError_t launch_dense_cols(int P, const DenseColArgs &a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_gdense_cols(int P, const DenseColArgs &a, hipStream_t s)
+{
+    TMG_DISPATCH_PALL(P, { return launch_gdense_cols_p<PP>(a, s); })
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t s)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;

@@ -343,6 +343,239 @@ __global__ __launch_bounds__(kGenThreads) void k_gbottom(BottomArgsT<double> a)
     if (fin && threadIdx.x == 0) finish_cycle(a.st, j, a.st[j], acc, a.ctl, a.mirror);
 }
 
+// A whole V/W visit of an instance's bottom levels (its first bottom level
+// lb up to the coarsest, at most gbottom_max(P) slabs) by one work-group,
+// one slab per thread, in place of the streaming legs and k_gbottom.  The
+// levels' right-hand sides and iterates stay in LDS in logical slab order;
+// the level's table block is reloaded as the visit moves between levels.
+// Each step is the streaming leg's (g_sweeps, g_residual, the transfers
+// in the same order of operations) on the whole level, whose slab 0 has the
+// zero left neighbour, and the coarsest level's exact solve is g_exact: the
+// same arithmetic as the streaming kernels.  Down legs store the restricted
+// residual; up legs recompute the pre-smoothing from the visit's initial
+// iterate (as the streaming legs do) and store the result.  A first bottom
+// level of 0 folds u0 and finishes the instance's cycle (k_bottom's way).
+template <int P>
+struct GVisitLds {
+    static constexpr int BMAX = gbottom_max(P);
+    double f[2 * BMAX * P];
+    double x[2 * BMAX * P];
+};
+
+// The visit of level lb (its right-hand side and initial iterate in sm, in
+// logical slab order; op holds the table block of level `cur`).
+template <int P>
+__device__ __forceinline__ void gvisit_levels(GOps<P> &op, GVisitLds<P> &sm, double *bw, double *sa,
+                                              double *sb, double (*xw)[kGWaves], double *red,
+                                              const double *tab0, int64_t tstep, int N, int lb,
+                                              int Lc, int nu1, int nu2, int gamma, bool zero,
+                                              int &cur, int &phase)
+{
+    const int t = threadIdx.x;
+    auto use = [&](int l) {
+        // the table block of level l in LDS (every thread done with the last)
+        __syncthreads();
+        if (l != cur) {
+            op.load(tab0 + (int64_t)l * tstep, nullptr);
+            __syncthreads();
+            cur = l;
+        }
+    };
+    auto nsl = [&](int l) { return N >> (l - lb); };
+    auto loff = [&](int l) { return (2 * N - 2 * nsl(l)) * P; };
+    auto load = [&](double (&x)[P], const double *base, int l, bool zr) {
+        const bool in = !zr && t < nsl(l);
+#pragma unroll
+        for (int k = 0; k < P; ++k) x[k] = in ? base[loff(l) + t * P + k] : 0.0;
+    };
+    auto gf = [&](double (&g)[P], const double (&f)[P]) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double s = 0.0;
+            for (int l = 0; l < P; ++l) s += op.G(k, l) * f[l];
+            g[k] = s;
+        }
+    };
+    // pre-smoothing from the visit's iterate (zr: from zero), residual,
+    // restriction into level l+1
+    auto down = [&](int l, bool zr) {
+        use(l);
+        double f[P], u[P], g[P], r[P], rn[P];
+        load(f, sm.f, l, false);
+        load(u, sm.x, l, zr);
+        gf(g, f);
+        g_sweeps<P>(u, g, op, nu1, xw, phase);
+        g_residual<P>(r, u, f, op, xw, phase);
+#pragma unroll
+        for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[k], 1, 64);
+        if (t < nsl(l) && !(t & 1)) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                double s = 0.0;
+                for (int q = 0; q < P; ++q) s += op.RT(0, q, k) * r[q] + op.RT(1, q, k) * rn[q];
+                sm.f[loff(l + 1) + (t / 2) * P + k] = s;
+            }
+        }
+    };
+    // the pre-smoothing recomputed, the correction of level l+1 prolongated,
+    // post-smoothing, stored
+    auto up = [&](int l, bool zr) {
+        use(l);
+        double f[P], u[P], g[P], e[P];
+        load(f, sm.f, l, false);
+        load(u, sm.x, l, zr);
+        gf(g, f);
+        g_sweeps<P>(u, g, op, nu1, xw, phase);
+        const bool in = t < nsl(l);
+#pragma unroll
+        for (int k = 0; k < P; ++k) e[k] = in ? sm.x[loff(l + 1) + (t / 2) * P + k] : 0.0;
+        const int par = t & 1;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < P; ++q) s += op.RT(par, k, q) * e[q];
+            u[k] += s;
+        }
+        g_sweeps<P>(u, g, op, nu2, xw, phase);
+        __syncthreads();   // every thread has read its iterate and correction
+        if (in)
+#pragma unroll
+            for (int k = 0; k < P; ++k) sm.x[loff(l) + t * P + k] = u[k];
+    };
+    auto coarse = [&](int l) {
+        use(l);
+        (void)g_exact<P, false>(sm.f + loff(l), sm.x + loff(l), nsl(l), 0, op, bw, sa, sb, xw, red,
+                                false, nullptr);
+    };
+    // bit l of `again` marks the second visit of level l
+    uint64_t again = 0;
+    int l = lb;
+    down(l, zero);
+    while (true) {
+        if (l + 1 == Lc) {
+            coarse(l + 1);
+        } else {
+            ++l;
+            down(l, true);
+            continue;
+        }
+        bool finished = false;
+        while (true) {
+            up(l, l == lb ? zero : !((again >> l) & 1));
+            if (l == lb) {
+                finished = true;
+                break;
+            }
+            if (gamma > 1 && !((again >> l) & 1)) {
+                again |= (uint64_t)1 << l;
+                down(l, false);
+                break;
+            }
+            again &= ~((uint64_t)1 << l);
+            --l;
+        }
+        if (finished) break;
+    }
+    __syncthreads();
+}
+
+template <int P, bool BW>
+__global__ __launch_bounds__(kGenThreads) void k_gvisit(BottomArgsT<double> a)
+{
+    __shared__ GOps<P> op;
+    __shared__ GVisitLds<P> sm;
+    __shared__ double bw[kMaxCoarse];
+    __shared__ double sa[kGenThreads], sb[kGenThreads];
+    __shared__ double xw[2][kGWaves];
+    __shared__ double red[kGWaves];
+    const int j = a.inst[blockIdx.x];
+    if (a.st && a.st[j].done) return;
+    const int lb = a.lbs ? a.lbs[j] : a.level, Lc = a.nlev[j] - 1;
+    const double *fg = a.lbs ? a.f_lv[lb] : a.f;
+    double *xg = a.lbs ? a.x_lv[lb] : a.x_out;
+    const int64_t *soff = a.lbs ? a.soff_lv[lb] : a.slab_off;
+    const int64_t off = soff[j];
+    const int N = (int)(soff[j + 1] - off);
+    const int t = threadIdx.x;
+    const double *tab0 = a.tab + (int64_t)j * a.tab_stride;
+    const int64_t tstep = (int64_t)a.batch * a.tab_stride;
+    op.load(tab0 + (int64_t)lb * tstep, a.R);
+    __syncthreads();
+    if (lb == Lc) {
+        // one level: its exact solve (k_gbottom)
+        const bool fin = lb == 0 && a.st;
+        const double acc = g_exact<P, BW>(fg + off * P, xg + off * P, N, a.periodic, op, bw, sa, sb,
+                                          xw, red, fin, (lb == 0 && a.u0) ? a.u0 + j : nullptr);
+        if (fin && t == 0) finish_cycle(a.st, j, a.st[j], acc, a.ctl, a.mirror);
+        return;
+    }
+    if (N > GVisitLds<P>::BMAX) return;   // the host never plans such a bottom
+    for (int i = t; i < N * P; i += kGenThreads) {
+        const int m = i / P, k = i - m * P;
+        const int64_t pm = off + (BW ? N - 1 - m : m);
+        sm.f[i] = fg[pm * P + k];
+        sm.x[i] = a.x_in ? a.x_in[pm * P + k] : 0.0;
+    }
+    __syncthreads();
+    if (lb == 0 && a.u0 && t < P) sm.f[t] += a.u0[j] * op.v(t);   // u0 enters slab 0
+    int phase = 0, cur = lb;
+    gvisit_levels<P>(op, sm, bw, sa, sb, xw, red, tab0, tstep, N, lb, Lc, a.nu1, a.nu2, a.gamma,
+                     a.x_in == nullptr, cur, phase);
+    for (int i = t; i < N * P; i += kGenThreads) {
+        const int m = i / P, k = i - m * P;
+        xg[(off + (BW ? N - 1 - m : m)) * P + k] = sm.x[i];
+    }
+    if (lb == 0 && a.st) {
+        // squared residual of the result (level 0): the work-group finishes
+        // the instance's cycle
+        __syncthreads();
+        if (cur != 0) {
+            op.load(tab0, nullptr);
+            __syncthreads();
+        }
+        double f[P], u[P], r[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            f[k] = t < N ? sm.f[t * P + k] : 0.0;
+            u[k] = t < N ? sm.x[t * P + k] : 0.0;
+        }
+        g_residual<P>(r, u, f, op, xw, phase);
+        double acc = 0.0;
+        if (t < N)
+#pragma unroll
+            for (int k = 0; k < P; ++k) acc += r[k] * r[k];
+        acc = block_sum<kGWaves>(acc, red);
+        if (t == 0) finish_cycle(a.st, j, a.st[j], acc, a.ctl, a.mirror);
+    }
+}
+
+// Column `col` of the dense bottom operator on the generic kernels (one
+// work-group per column; see k_dense_cols): gamma visits of level a.level
+// from zero on the unit load e_col, as k_gvisit runs them.
+template <int P>
+__global__ __launch_bounds__(kGenThreads) void k_gdense_cols(DenseColArgs a)
+{
+    __shared__ GOps<P> op;
+    __shared__ GVisitLds<P> sm;
+    __shared__ double bw[kMaxCoarse];
+    __shared__ double sa[kGenThreads], sb[kGenThreads];
+    __shared__ double xw[2][kGWaves];
+    __shared__ double red[kGWaves];
+    const int64_t col = blockIdx.x;
+    const int N = (int)a.N, n = N * P, lb = a.level;
+    op.load(a.tab + (int64_t)lb * a.tab_level, a.R);
+    for (int i = threadIdx.x; i < n; i += kGenThreads) {
+        sm.f[i] = i == col ? 1.0 : 0.0;
+        sm.x[i] = 0.0;
+    }
+    __syncthreads();
+    int phase = 0, cur = lb;
+    for (int g = 0; g < a.gamma; ++g)
+        gvisit_levels<P>(op, sm, bw, sa, sb, xw, red, a.tab, a.tab_level, N, lb, a.Lc, a.nu1, a.nu2,
+                         a.gamma, g == 0, cur, phase);
+    for (int64_t i = threadIdx.x; i < n; i += kGenThreads) a.D[i * n + col] = sm.x[i];
+}
+
 // tmg_op_coarse_solve on the generic path
 template <int P, bool BW>
 __global__ __launch_bounds__(kGenThreads) void k_gcoarse(CoarseArgs a, int periodic)

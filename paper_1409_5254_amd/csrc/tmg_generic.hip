@@ -24,8 +24,22 @@ template <int PP>
 hipError_t launch_gbottom_p(bool backward, const BottomArgsT<double> &a, int ninst, hipStream_t s)
 {
     const dim3 grid(ninst), block(kGenThreads);
-    if (backward) hipLaunchKernelGGL((k_gbottom<PP, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_gbottom<PP, false>), grid, block, 0, s, a);
+    if (a.visit && !a.periodic) {
+        if (backward) hipLaunchKernelGGL((k_gvisit<PP, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_gvisit<PP, false>), grid, block, 0, s, a);
+    } else {
+        if (backward) hipLaunchKernelGGL((k_gbottom<PP, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_gbottom<PP, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int PP>
+hipError_t launch_gdense_cols_p(const DenseColArgs &a, hipStream_t s)
+{
+    if (a.N < 1 || a.N > gbottom_max(PP) || a.Lc <= a.level || a.N * PP > kDenseMaxN)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gdense_cols<PP>), dim3((unsigned)(a.N * PP)), dim3(kGenThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -43,5 +57,6 @@ template hipError_t launch_gleg_p<TMG_GEN_P>(bool, const LegArgsT<double> &, int
 template hipError_t launch_gbottom_p<TMG_GEN_P>(bool, const BottomArgsT<double> &, int,
                                                 hipStream_t);
 template hipError_t launch_gcoarse_p<TMG_GEN_P>(bool, const CoarseArgs &, int, int, hipStream_t);
+template hipError_t launch_gdense_cols_p<TMG_GEN_P>(const DenseColArgs &, hipStream_t);
 
 }  // namespace tmg

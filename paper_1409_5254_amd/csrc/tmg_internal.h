@@ -35,6 +35,10 @@ constexpr int bottom_slabs(int P) { return P == 1 ? 8 : (P == 2 ? 4 : 2); }
 // P >= 5, whose levels would not fit the LDS otherwise
 constexpr int bottom_threads(int P) { return P >= 5 ? kBottomThreads / 2 : kBottomThreads; }
 constexpr int bottom_max(int P) { return bottom_threads(P) * bottom_slabs(P); }
+// Largest level (slabs) of the generic kernels' bottom visit (k_gvisit):
+// one slab per thread of kGenThreads, every level's right-hand side and
+// iterate in LDS next to one level's table block and the transfer matrices.
+constexpr int gbottom_max(int P) { return P <= 10 ? 256 : 128; }
 constexpr int kBottomMaxLevels = 13;
 
 // The entry point that allocates nothing (tmg_solve_noalloc) carves every
@@ -263,6 +267,7 @@ struct BottomArgsT {
     // slabs (one wavefront holds it): one-wavefront work-groups
     int small;
     int generic, periodic;   // as in LegArgsT (the generic kernel solves its level exactly)
+    int visit;               // generic: the bottom spans several levels (k_gvisit)
 };
 using BottomArgs = BottomArgsT<double>;
 
@@ -300,6 +305,10 @@ struct DenseColArgs {
 template <int PP>
 hipError_t launch_dense_cols_p(const DenseColArgs &a, hipStream_t s);
 hipError_t launch_dense_cols(int P, const DenseColArgs &a, hipStream_t s);
+// the same on the generic kernels (k_gvisit's visits; any P <= kMaxP)
+template <int PP>
+hipError_t launch_gdense_cols_p(const DenseColArgs &a, hipStream_t s);
+hipError_t launch_gdense_cols(int P, const DenseColArgs &a, hipStream_t s);
 // Row i's window [win[2i], win[2i+1]): the columns from its first to its
 // last entry of magnitude above 2^-64 times the row's largest (the start
 // rounded down to even; every column if the row holds a non-finite entry).

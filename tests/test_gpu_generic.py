@@ -236,3 +236,85 @@ def test_periodic_two_grid_contraction(p, z, nu):
     else:
         assert est < 1e-4
     s.close()
+
+
+@pytest.mark.parametrize("p", [6, 9, 10, 15, 20])
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_generic_bottom_visit_bitwise(p, gamma):
+    """The generic bottom visit (one work-group runs the levels up to the
+    bottom cap, k_gvisit) computes each slab's steps as the one-level legs
+    and the coarsest level's exact solve do: a solve and an adjoint solve
+    give the same bits with the bottom cap at the coarsest level (every
+    other level streams), at 8 and 32 slabs, and at the largest (256 slabs
+    up to p = 9, 128 above); and they equal the oracle's at 1e-12."""
+    rng = np.random.default_rng(1000 + p + 10 * gamma)
+    N, T, lam, u0 = 8192, 30.0, 0.9, 0.6
+    P = p + 1
+    f = rng.standard_normal(N * P) * 0.1
+    g = rng.standard_normal(N * P) * 0.1
+    s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
+    s.set_dense_bottom(False)   # the recursion at every visit (compared bit for bit)
+    out = []
+    largest = 256 if P <= 10 else 128
+    for cap in (2, 8, 32, largest):
+        s.set_schedule(cap, pairs=False)
+        r = s.solve(dev(f), dev([u0]), rtol=1e-10)
+        z, _, _, cz, _, st = s.adjoint_solve(dev(g), rtol=1e-10)
+        assert r.status == 0 and st == 0
+        out.append((host(r.u).copy(), list(r.cycles), host(z).copy(), list(cz)))
+    s.close()
+    for o in out[1:]:
+        assert o[1] == out[0][1] and o[3] == out[0][3]
+        assert np.array_equal(o[0], out[0][0]) and np.array_equal(o[2], out[0][2])
+    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=gamma))
+    assert out[0][1][0] == k
+    assert relerr(out[0][0], uo) <= TOL
+    zo, kz, _, _ = core.solve_folded(p, T, lam, g, rtol=1e-10, trans=True,
+                                     opts=core.Opts(gamma=gamma))
+    assert out[0][3][0] == kz
+    assert relerr(out[0][2], zo) <= TOL
+
+
+def test_generic_schedule_caps():
+    """A generic handle takes bottom caps from the coarsest level up to its
+    bottom visit's largest level, without two-level launches or spans; the
+    periodic problem takes only the coarsest level."""
+    s = B().Solver([1024], [1.0], [1.0], p=10)
+    s.set_schedule(128, pairs=False)
+    s.set_schedule(2, pairs=False)
+    with pytest.raises(B().TmgError):
+        s.set_schedule(256, pairs=False)
+    with pytest.raises(B().TmgError):
+        s.set_schedule(64, pairs=True)
+    s.close()
+    s = B().Solver([1024], [1.0], [1.0], p=3, periodic=1)
+    s.set_schedule(2, pairs=False)
+    with pytest.raises(B().TmgError):
+        s.set_schedule(8, pairs=False)
+    s.close()
+
+
+@pytest.mark.parametrize("p", [6, 10, 15, 20])
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_generic_dense_bottom(p, gamma):
+    """One instance's bottom visits as the tabulated dense operator on the
+    generic kernels (its columns are k_gvisit's visits of the unit loads):
+    three cycles from a random start and a solve, at the largest bottom
+    level (256 slabs up to p = 9, 128 above: 1408 to 2688 unknowns), against
+    the oracle at 1e-12 with the same cycle count."""
+    rng = np.random.default_rng(1100 + p + 10 * gamma)
+    N, T, lam, u0 = 4096, 8.0, 1.1, 0.4
+    P = p + 1
+    f, u = rng.standard_normal(N * P) * 0.1, rng.standard_normal(N * P)
+    s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
+    s.set_schedule(256 if P <= 10 else 128, pairs=False)
+    du = dev(u)
+    for _ in range(3):
+        s.vcycle(dev(f), dev([u0]), du)
+    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, core.Opts(gamma=gamma))
+    assert relerr(host(du), ref) <= TOL
+    res = s.solve(dev(f), dev([u0]), rtol=1e-10)
+    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=core.Opts(gamma=gamma))
+    assert res.status == 0 and res.cycles[0] == k
+    assert relerr(host(res.u), uo) <= TOL
+    s.close()
