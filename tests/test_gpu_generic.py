@@ -248,7 +248,7 @@ def test_generic_bottom_visit_bitwise(p, gamma):
     other level streams), at 8 and 32 slabs, and at the largest (256 slabs
     up to p = 9, 128 above); and they equal the oracle's at 1e-12."""
     rng = np.random.default_rng(1000 + p + 10 * gamma)
-    N, T, lam, u0 = 8192, 30.0, 0.9, 0.6
+    N, T, lam, u0 = 2048, 8.0, 0.9, 0.6
     P = p + 1
     f = rng.standard_normal(N * P) * 0.1
     g = rng.standard_normal(N * P) * 0.1
