@@ -212,3 +212,38 @@ def test_fused_w_solve_and_adjoint(p):
     zo, kz, _, _ = core.solve_folded(p, T, lam, g, rtol=1e-10, trans=True, opts=core.Opts(gamma=2))
     assert st == 0 and cyc[0] == kz
     assert relerr(z, zo) <= TOL
+
+
+@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("opts", [dict(n_coarse=1), dict(n_coarse=4), dict(nu1=1, nu2=3),
+                                  dict(nu1=3, nu2=0), dict(omega_mode=1, omega=0.5)])
+@pytest.mark.parametrize("p", [0, 2, 5])
+def test_dense_bottom_options(p, opts, gamma):
+    """The dense bottom operator under the other options: coarsest levels
+    of 1 and 4 slabs, uneven sweep counts, the fixed damping 1/2.  Three
+    cycles (tmg_vcycle) and a solve against the oracle at 1e-12; the
+    operator on and off give the same cycle count."""
+    P = p + 1
+    nc = opts.get("n_coarse", 2)
+    N = 1024 * nc
+    rng = np.random.default_rng(1300 + p + 7 * gamma + len(str(opts)))
+    T, lam, u0 = 6.0, 1.7, 0.3
+    f, u = rng.standard_normal(N * P), rng.standard_normal(N * P)
+    oo = core.Opts(gamma=gamma, **opts)
+    ref = core.cycles(p, T, lam, core.fold(p, u0, f), u, 3, oo)
+    uo, k, _, _ = core.solve(p, T, lam, u0, f, opts=oo)
+    cyc = {}
+    for on in (True, False):
+        s = B().Solver([N], [T], [lam], p=p, gamma=gamma, **opts)
+        s.set_schedule(min(64 * nc, 512), pairs=True)
+        s.set_dense_bottom(on)
+        du = dev(u)
+        for _ in range(3):
+            s.vcycle(dev(f), dev([u0]), du)
+        assert relerr(host(du), ref) <= TOL, (on, relerr(host(du), ref))
+        res = s.solve(dev(f), dev([u0]), rtol=1e-10, max_cycles=80)
+        assert res.status == 0 and res.cycles[0] == k, (on, res.cycles, k)
+        assert relerr(host(res.u), uo) <= TOL
+        cyc[on] = res.cycles[0]
+        s.close()
+    assert cyc[True] == cyc[False]
