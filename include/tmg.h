@@ -236,8 +236,9 @@ int tmg_set_active_set(tmg_handle h, int on);
  * iterate (the recursion of eq. chap4_errorTwoGridCycle, section 3, applied
  * below that level, with the exact solve on the coarsest; one visit for a
  * V-cycle, two for a W-cycle) form one fixed linear map of that level's
- * right-hand side.  Where it applies (one instance, FP64, forward solves
- * and cycles, a bottom level strictly between level 0 and the coarsest with
+ * right-hand side.  Where it applies (one instance, FP64, solves, adjoint
+ * solves (the transposed system's own operator) and cycles, a bottom level
+ * strictly between level 0 and the coarsest with
  * at most 4096 unknowns, which every bottom_cap of tmg_set_schedule gives) the
  * library builds the map's matrix once per schedule and set of tables
  * (n x n doubles, n = slabs x (p + 1), at most 128 MiB of device memory;

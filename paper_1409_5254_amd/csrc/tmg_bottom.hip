@@ -39,10 +39,12 @@ hipError_t launch_bottom_p(bool backward, const BottomArgsT<TIO> &a, int ninst, 
 // level run from zero in LDS exactly as k_bottom's launches run them (the
 // iterate kept between visits, the right-hand side of the level untouched
 // by them).  The column goes to row-major D.
-template <int P, int NT>
+template <int P, int NT, bool BW>
 __global__ __launch_bounds__(NT) void k_dense_cols(DenseColArgs a)
 {
-    using B = Bottom<P, false, NT>;
+    // the levels sit in LDS in physical slab order (BW: Bottom's steps map
+    // logical slabs onto it), so the unit load and the column are physical
+    using B = Bottom<P, BW, NT>;
     constexpr int STRIDE = B::STRIDE;
     __shared__ BottomLds<P, NT> sm;
     const int64_t col = blockIdx.x;
@@ -79,7 +81,10 @@ hipError_t launch_dense_cols_p(const DenseColArgs &a, hipStream_t s)
     if (a.N < 1 || a.N > NT * bottom_slabs(PP) || a.Lc <= a.level ||
         a.Lc - a.level + 1 > kBottomMaxLevels)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_dense_cols<PP, NT>), dim3((unsigned)(a.N * PP)), dim3(NT), 0, s, a);
+    if (a.backward)
+        hipLaunchKernelGGL((k_dense_cols<PP, NT, true>), dim3((unsigned)(a.N * PP)), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_dense_cols<PP, NT, false>), dim3((unsigned)(a.N * PP)), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 

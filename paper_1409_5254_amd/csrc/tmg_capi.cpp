@@ -193,16 +193,18 @@ struct tmg_ctx {
     double *T_d = nullptr;                        // [batch] T_j and N_j: tables built on the
     int64_t *N_d = nullptr;                       // device (tmg_set_lambda)
     bool lam_device = false;                      // lambda last set from a device array
-    // The bottom level's visits as one dense operator (one FP64 instance,
-    // forward solves; the gamma visits of a cycle's recursion): D of the
-    // bottom level (dense_n unknowns), its rows' windows, valid for the
-    // current schedule and tables while dense_ok.
+    // The bottom level's visits as one dense operator (one FP64 instance;
+    // the gamma visits of a cycle's recursion): D of the bottom level
+    // (dense_n unknowns) and its rows' windows, [0] forward and [1] the
+    // transposed system's, each valid for the current schedule and tables
+    // while dense_ok[.].
     bool dense_on = true;
-    bool dense_ok = false;
+    bool dense_ok[2] = {false, false};
     int dense_level = -1;
-    int64_t dense_n = 0, dense_cap = 0;
-    double *dense = nullptr;
-    int *dense_win = nullptr;
+    int64_t dense_n = 0, dense_cap[2] = {0, 0};
+    double *dense[2] = {nullptr, nullptr};
+    int *dense_win[2] = {nullptr, nullptr};
+    void dense_stale() { dense_ok[0] = dense_ok[1] = false; }
     std::map<std::tuple<int, int, int>, TileList> tiles;
     std::map<int, std::pair<int *, int>> op_coarse;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -663,8 +665,9 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
     if (ninst == 0) return TMG_OK;
     if constexpr (std::is_same<T, double>::value) {
         // a V-cycle's visit from zero: one product with the dense operator
-        if (c->dense_ok && c->opt.gamma == 1 && !io.trans && !x_in && level == c->dense_level) {
-            HIPCHK(c, launch_dense_apply(c->dense, c->dense_win, store<T>(c).f[level], x_out,
+        const int d = io.trans ? 1 : 0;
+        if (c->dense_ok[d] && c->opt.gamma == 1 && !x_in && level == c->dense_level) {
+            HIPCHK(c, launch_dense_apply(c->dense[d], c->dense_win[d], store<T>(c).f[level], x_out,
                                          c->dense_n, io.use_state ? c->st : nullptr, s));
             return TMG_OK;
         }
@@ -818,8 +821,9 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
     c->cur[l] = 0;
     if constexpr (std::is_same<T, double>::value) {
         // the instance's gamma bottom visits from zero in one product
-        if (c->dense_ok && !io.trans && l == c->dense_level) {
-            HIPCHK(c, launch_dense_apply(c->dense, c->dense_win, L.f[l], L.x(l, 0), c->dense_n,
+        const int d = io.trans ? 1 : 0;
+        if (c->dense_ok[d] && l == c->dense_level) {
+            HIPCHK(c, launch_dense_apply(c->dense[d], c->dense_win[d], L.f[l], L.x(l, 0), c->dense_n,
                                          io.use_state ? c->st : nullptr, s));
             return TMG_OK;
         }
@@ -1452,32 +1456,34 @@ int drain(tmg_ctx *c)
 // one work-group per unit load runs the bottom visits (columns of D), then
 // the rows' windows.  Launched on s before any cycle that applies it; the
 // buffers grow only after a schedule change, which drops every graph.
-int ensure_dense(tmg_ctx *c, hipStream_t s)
+int ensure_dense(tmg_ctx *c, hipStream_t s, bool trans)
 {
-    if (c->dense_ok || !c->want_dense()) return TMG_OK;
+    const int d = trans ? 1 : 0;
+    if (c->dense_ok[d] || !c->want_dense()) return TMG_OK;
     const int l = c->lb[0];
     const int64_t N = c->N[0] >> l, n = N * c->P;
     int rc;
-    if (n * n > c->dense_cap) {
+    if (n * n > c->dense_cap[d]) {
         if ((rc = drain(c))) return rc;
         HIPCHK(c, hipStreamSynchronize(s));
-        dfree(c, c->dense);
-        dfree(c, c->dense_win);
-        c->dense = nullptr;
-        c->dense_win = nullptr;
-        c->dense_cap = 0;
-        if ((rc = dalloc(c, &c->dense, (size_t)(n * n))) ||
-            (rc = dalloc(c, &c->dense_win, (size_t)(2 * kDenseMaxN))))
+        dfree(c, c->dense[d]);
+        dfree(c, c->dense_win[d]);
+        c->dense[d] = nullptr;
+        c->dense_win[d] = nullptr;
+        c->dense_cap[d] = 0;
+        if ((rc = dalloc(c, &c->dense[d], (size_t)(n * n))) ||
+            (rc = dalloc(c, &c->dense_win[d], (size_t)(2 * kDenseMaxN))))
             return rc;
-        c->dense_cap = n * n;
+        c->dense_cap[d] = n * n;
     }
     // cycles a solve left queued past convergence may still read D
     if (c->drain_pending) HIPCHK(c, hipStreamWaitEvent(s, c->drain_ev, 0));
     DenseColArgs a{};
-    a.tab = c->tab_fwd;   // instance 0
+    a.tab = trans ? c->tab_adj : c->tab_fwd;   // instance 0
     a.tab_level = (int64_t)c->batch * c->tab_stride;
-    a.R = c->R_fwd;
-    a.D = c->dense;
+    a.R = trans ? c->R_adj : c->R_fwd;
+    a.D = c->dense[d];
+    a.backward = trans ? 1 : 0;
     a.N = N;
     a.level = l;
     a.Lc = c->L[0] - 1;
@@ -1485,10 +1491,11 @@ int ensure_dense(tmg_ctx *c, hipStream_t s)
     a.nu2 = c->opt.nu2;
     a.gamma = c->opt.gamma;
     HIPCHK(c, c->generic ? launch_gdense_cols(c->P, a, s) : launch_dense_cols(c->P, a, s));
-    HIPCHK(c, launch_dense_window(c->dense, n, c->dense_win, s));
+    HIPCHK(c, launch_dense_window(c->dense[d], n, c->dense_win[d], s));
+    if (c->dense_level != l || c->dense_n != n) c->dense_ok[1 - d] = false;
     c->dense_level = l;
     c->dense_n = n;
-    c->dense_ok = true;
+    c->dense_ok[d] = true;
     return TMG_OK;
 }
 
@@ -1566,7 +1573,7 @@ int run_solve(tmg_ctx *c, const double *f, const double *u0, double *u, bool tra
     // while the state they read says finished: this solve resets that state,
     // so its stream waits for them first (nothing to wait for on one stream)
     if (c->drain_pending) HIPCHK(c, hipStreamWaitEvent(s, c->drain_ev, 0));
-    if (!trans && (rc = ensure_dense(c, s))) return rc;
+    if ((rc = ensure_dense(c, s, trans))) return rc;
     c->epoch = c->epoch % (1 << 20) + 1;
     const long long epoch = c->epoch;
     c->ctl_host->rtol2 = rtol * rtol;
@@ -1844,7 +1851,7 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
     c->bot_all_d = nullptr;
     const int Lm = c->Lmax, batch = c->batch, P = c->P;
     c->lb = lbv;
-    c->dense_ok = false;
+    c->dense_stale();
     c->bottom_cap = cap;
     c->pairs = pairs;
     c->span = c->span_fits(span) ? span : 0;
@@ -2227,7 +2234,7 @@ int tmg_vcycle(tmg_handle c, const double *f, const double *u0, double *u, tmg_s
     if (!c || !f || !u0 || !u) return TMG_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     int rc = make_tiles(c, s);
-    if (rc || (rc = ensure_dense(c, s))) return rc;
+    if (rc || (rc = ensure_dense(c, s, false))) return rc;
     CycleIO io{f, c->opt.periodic ? nullptr : u0, u, false, false, -1};
     return enqueue_cycle(c, io, s);
 }
@@ -2406,7 +2413,7 @@ int tmg_set_lambda(tmg_handle c, const double *lambda, tmg_stream stream)
                                 c->opt.omega_mode, c->opt.omega, c->tab_stride, c->tab_fwd,
                                 c->tab_adj, c->tab32_fwd, c->tab32_adj, s));
     c->lam_device = true;
-    c->dense_ok = false;   // rebuilt from the new tables before the next cycle
+    c->dense_stale();   // rebuilt from the new tables before the next cycle
     return TMG_OK;
 }
 
@@ -2420,7 +2427,7 @@ int tmg_set_dense_bottom(tmg_handle c, int on, tmg_stream stream)
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     c->dense_on = on != 0;
-    c->dense_ok = false;
+    c->dense_stale();
     return TMG_OK;
 }
 

@@ -551,8 +551,10 @@ __global__ __launch_bounds__(kGenThreads) void k_gvisit(BottomArgsT<double> a)
 
 // Column `col` of the dense bottom operator on the generic kernels (one
 // work-group per column; see k_dense_cols): gamma visits of level a.level
-// from zero on the unit load e_col, as k_gvisit runs them.
-template <int P>
+// from zero on the unit load e_col, as k_gvisit runs them.  The visit
+// works in logical slab order; the column and the unit load are physical
+// (BW: logical slab m is physical N-1-m).
+template <int P, bool BW>
 __global__ __launch_bounds__(kGenThreads) void k_gdense_cols(DenseColArgs a)
 {
     __shared__ GOps<P> op;
@@ -563,9 +565,12 @@ __global__ __launch_bounds__(kGenThreads) void k_gdense_cols(DenseColArgs a)
     __shared__ double red[kGWaves];
     const int64_t col = blockIdx.x;
     const int N = (int)a.N, n = N * P, lb = a.level;
+    // physical index <-> logical index (an involution)
+    auto phys = [&](int i) { return BW ? (N - 1 - i / P) * P + i % P : i; };
+    const int lcol = phys((int)col);
     op.load(a.tab + (int64_t)lb * a.tab_level, a.R);
     for (int i = threadIdx.x; i < n; i += kGenThreads) {
-        sm.f[i] = i == col ? 1.0 : 0.0;
+        sm.f[i] = i == lcol ? 1.0 : 0.0;
         sm.x[i] = 0.0;
     }
     __syncthreads();
@@ -573,7 +578,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gdense_cols(DenseColArgs a)
     for (int g = 0; g < a.gamma; ++g)
         gvisit_levels<P>(op, sm, bw, sa, sb, xw, red, a.tab, a.tab_level, N, lb, a.Lc, a.nu1, a.nu2,
                          a.gamma, g == 0, cur, phase);
-    for (int64_t i = threadIdx.x; i < n; i += kGenThreads) a.D[i * n + col] = sm.x[i];
+    for (int i = threadIdx.x; i < n; i += kGenThreads) a.D[(int64_t)phys(i) * n + col] = sm.x[i];
 }
 
 // tmg_op_coarse_solve on the generic path

@@ -39,7 +39,10 @@ hipError_t launch_gdense_cols_p(const DenseColArgs &a, hipStream_t s)
 {
     if (a.N < 1 || a.N > gbottom_max(PP) || a.Lc <= a.level || a.N * PP > kDenseMaxN)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gdense_cols<PP>), dim3((unsigned)(a.N * PP)), dim3(kGenThreads), 0, s, a);
+    if (a.backward)
+        hipLaunchKernelGGL((k_gdense_cols<PP, true>), dim3((unsigned)(a.N * PP)), dim3(kGenThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gdense_cols<PP, false>), dim3((unsigned)(a.N * PP)), dim3(kGenThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -301,6 +301,8 @@ struct DenseColArgs {
     int64_t N;           // slabs of level `level` (at most the bottom kernel's)
     int64_t tab_level;
     int level, Lc, nu1, nu2, gamma;   // Lc: the coarsest level
+    int backward;   // the transposed system (backward in time; tables and
+                    // transfers of the adjoint), D over physical slab order
 };
 template <int PP>
 hipError_t launch_dense_cols_p(const DenseColArgs &a, hipStream_t s);

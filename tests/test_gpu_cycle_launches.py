@@ -133,10 +133,11 @@ def test_dense_rebuilt_after_lambda_and_schedule():
     s.close()
 
 
-def test_dense_off_for_batches_and_adjoint():
-    """Where the operator does not apply (a batch; the adjoint solve) the
-    W-cycle runs the recursion: a two-instance batch and the adjoint solve
-    of one instance against the oracle."""
+def test_dense_batches_and_adjoint():
+    """A batch runs the recursion (the operator is one instance's); one
+    instance's adjoint solve applies the transposed system's operator (its
+    columns are the backward-in-time visits): a two-instance batch and the
+    adjoint W solve of one instance against the oracle."""
     p, N, T = 1, 2048, 10.0
     P = p + 1
     rng = np.random.default_rng(78)
@@ -247,3 +248,27 @@ def test_dense_bottom_options(p, opts, gamma):
         cyc[on] = res.cycles[0]
         s.close()
     assert cyc[True] == cyc[False]
+
+
+@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("p", [0, 1, 3, 5, 6, 10])
+def test_dense_adjoint_on_off(p, gamma):
+    """The adjoint solve of one instance with the transposed operator and
+    with the recursion: the same cycle count, both at 1e-12 of the oracle's
+    backward-in-time solve (tuned and generic kernels)."""
+    P = p + 1
+    rng = np.random.default_rng(1400 + p + 3 * gamma)
+    N, T, lam = 4096, 12.0, 0.8
+    g = rng.standard_normal(N * P)
+    zo, k, _, _ = core.solve_folded(p, T, lam, g, rtol=1e-10, trans=True,
+                                    opts=core.Opts(gamma=gamma))
+    out = {}
+    for on in (True, False):
+        s = B().Solver([N], [T], [lam], p=p, gamma=gamma)
+        s.set_schedule(128, pairs=P <= 6)
+        s.set_dense_bottom(on)
+        z, _, _, cyc, _, st = s.adjoint_solve(dev(g), rtol=1e-10, max_cycles=80)
+        out[on] = host(z)
+        s.close()
+        assert st == 0 and cyc[0] == k, (on, cyc, k)
+        assert relerr(out[on], zo) <= TOL, (on, relerr(out[on], zo))
