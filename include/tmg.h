@@ -431,6 +431,21 @@ int tmg_heat_solve(tmg_heat_handle h, const double *f, const double *u0, double 
                    int max_cycles, int *cycles, double *relres, tmg_stream s);
 int tmg_heat_destroy(tmg_heat_handle h);
 int tmg_heat_last_hip_error(tmg_heat_handle h);
+/*
+ * The coarse levels by sine modes (on by default).  The cycle acts on each
+ * eigenvector of L_h separately: the slab block I (x) K + L_h (x) M, the
+ * residual and the transfers in time are all diagonal in them.  Mode k
+ * (eigenvalue 4 sin^2(pi k h/2)/h^2) follows the scalar problem of the
+ * header's first part with that lambda and this cycle's damping.  So the
+ * visits of the first level of at most 64 slabs above the coarsest (the
+ * per-mode operators within 1 GiB of device memory) are: the orthonormal
+ * sine transform over the points, for each mode the scalar problem's
+ * visit operator (tabulated at setup, as by tmg_set_dense_bottom), and the
+ * inverse transform.  That is the same cycle up to rounding, and replaces
+ * every level below with three launches.  on = 0 runs those levels' legs.
+ * Returns TMG_ERR_INVALID for a null handle.
+ */
+int tmg_heat_set_mode_solve(tmg_heat_handle h, int on);
 
 #ifdef __cplusplus
 }

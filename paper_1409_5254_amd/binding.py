@@ -33,7 +33,8 @@ SYMBOLS = ["tmg_default_options", "tmg_setup", "tmg_vcycle", "tmg_solve", "tmg_a
            "tmg_op_coarse_solve",
            "tmg_op_residual_norm", "tmg_solve_noalloc", "tmg_op_down32", "tmg_op_up32",
            "tmg_op_mix", "tmg_set_lambda", "tmg_heat_setup", "tmg_heat_vcycle",
-           "tmg_heat_solve", "tmg_heat_destroy", "tmg_heat_last_hip_error"]
+           "tmg_heat_solve", "tmg_heat_destroy", "tmg_heat_last_hip_error",
+           "tmg_heat_set_mode_solve"]
 
 
 class TmgError(RuntimeError):
@@ -108,6 +109,7 @@ def lib():
             "tmg_heat_solve": (_i, [_vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d), _vp]),
             "tmg_heat_destroy": (_i, [_vp]),
             "tmg_heat_last_hip_error": (_i, [_vp]),
+            "tmg_heat_set_mode_solve": (_i, [_vp, _i]),
             "tmg_solve_noalloc": (_i, [_i64, _d, _d, _vp, _vp, _vp, _vp, _d, _i, P(_i), P(_d),
                                        _vp]),
         }
@@ -377,6 +379,12 @@ class HeatSolver:
         if rc < 0:
             raise TmgError(rc, where, lib().tmg_heat_last_hip_error(self._h))
         return rc
+
+    def set_mode_solve(self, on):
+        """The coarse levels by sine modes (on by default; the same cycle up
+        to rounding); off: their legs."""
+        self._check(lib().tmg_heat_set_mode_solve(self._h, int(bool(on))),
+                    "tmg_heat_set_mode_solve")
 
     def vcycle(self, f, u0, u):
         self._check(lib().tmg_heat_vcycle(self._h, _ptr(f), _ptr(u0), _ptr(u), _stream()),

@@ -81,6 +81,14 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     __shared__ double red[kDenseRows][kDenseWaves];
     const int64_t row0 = (int64_t)blockIdx.x * kDenseRows;
     const int t = threadIdx.x;
+    // a batch of operators (the heat equation's sine modes): operator y
+    {
+        const int64_t y = blockIdx.y;
+        D += y * n * n;
+        win += y * 2 * n;
+        r += y * n;
+        x += y * n;
+    }
     // the windows and the state flag in one round trip
     const InstState *sp = st ? st : &g_no_state;
     int ws[kDenseRows], we[kDenseRows];
@@ -161,7 +169,45 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     }
 }
 
+// out[a][j] = sum_b Q[a][b] in[b][j] over a, b < nx, j < n: one thread per
+// output, the b in order.
+__global__ __launch_bounds__(kDenseThreads) void k_mode_transform(const double *__restrict__ Q,
+                                                               const double *__restrict__ in,
+                                                               double *__restrict__ out, int nx,
+                                                               int64_t n)
+{
+    const int64_t j = (int64_t)blockIdx.x * kDenseThreads + threadIdx.x;
+    const int a = blockIdx.y;
+    if (j >= n) return;
+    const double *q = Q + (int64_t)a * nx;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < nx; ++b) acc = fma(q[b], in[(int64_t)b * n + j], acc);
+    out[(int64_t)a * n + j] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_mode_transform(const double *Q, const double *in, double *out, int nx,
+                                 int64_t n, hipStream_t s)
+{
+    if (nx < 1 || nx > 65535 || n < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + kDenseThreads - 1) / kDenseThreads), (unsigned)nx);
+    hipLaunchKernelGGL(k_mode_transform, grid, dim3(kDenseThreads), 0, s, Q, in, out, nx, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_apply_batch(const double *D, const int *win, const double *r, double *x,
+                                    int64_t n, int nop, hipStream_t s)
+{
+    if (n < 1 || n > kDenseMaxN || nop < 1 || nop > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows), (unsigned)nop),
+        block(kDenseThreads);
+    const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
+    if (vec) hipLaunchKernelGGL(k_dense_apply<true>, grid, block, 0, s, D, win, r, x, n, nullptr);
+    else hipLaunchKernelGGL(k_dense_apply<false>, grid, block, 0, s, D, win, r, x, n, nullptr);
+    return hipGetLastError();
+}
 
 hipError_t launch_dense_cols(int P, const DenseColArgs &a, hipStream_t s)
 {

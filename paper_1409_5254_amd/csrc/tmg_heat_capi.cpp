@@ -39,6 +39,20 @@ struct tmg_heat_ctx {
     double *zeros = nullptr;   // nx zeros: the u0 of the levels above 0
     int64_t ws_tiles = 0;
     int64_t wide_tiles = 0;   // two wavefronts per SIMD of the device
+    // The coarse levels by sine modes.  The slab block, the residual and the
+    // transfers in time all act on each eigenvector of L_h separately, so a
+    // visit of level mode_level (its gamma visits from zero, with every
+    // level below) is: the orthonormal sine transform over the points, for
+    // each mode the scalar problem's visit operator (lambda = the mode's
+    // eigenvalue, this cycle's damping per level; tabulated as the dense
+    // bottom operator), and the inverse transform (the same matrix).
+    int mode_level = -1;                  // -1: none
+    bool mode_on = true;
+    int64_t mode_n = 0;                   // unknowns per point of that level
+    double *Q = nullptr;                  // [nx][nx], symmetric
+    double *mD = nullptr;                 // [nx][n][n] per-mode operators
+    int *mwin = nullptr;                  // [nx][2n] their rows' windows
+    double *mt[2] = {nullptr, nullptr};   // [nx][n] the transformed f, result
     std::vector<void *> allocs;
     int last_hip = 0;
 };
@@ -76,6 +90,10 @@ void heat_free(tmg_heat_ctx *c)
 // even halos of at least 2 slabs: restriction pairs stay in a tile
 int rs2(int x) { return (x + 1) & ~1; }
 constexpr int64_t kLegCoarse = 32;   // coarsest levels solved by a leg (one tile)
+// the sine-mode visits: a level of at most kModeSlabs slabs (and the
+// per-mode operators within kModeBytes), above the coarsest
+constexpr int64_t kModeSlabs = 64;
+constexpr double kModeBytes = double(1u << 30);
 int TO(int H) { return kHeatThreads - H; }
 int64_t tiles(int64_t N, int H) { return (N + TO(H) - 1) / TO(H); }
 // The largest halo of any launch (down legs nu1 + 1, up legs with the norm
@@ -267,8 +285,17 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
         a.sweeps = nu1;
         if ((rc = launch_leg_checked(c, a, tiles(c->Nl[l], H), s))) return rc;
     }
-    for (int g = 0; g < c->opt.gamma; ++g)
-        if ((rc = visit(c, l + 1, g == 0, s))) return rc;
+    if (c->mode_on && c->mode_level == l + 1) {
+        // the gamma visits of level l+1 by sine modes
+        const int d = l + 1, nx = c->nx;
+        const int64_t n = c->mode_n;
+        HCHK(c, launch_mode_transform(c->Q, c->f[d], c->mt[0], nx, n, s));
+        HCHK(c, launch_dense_apply_batch(c->mD, c->mwin, c->mt[0], c->mt[1], n, nx, s));
+        HCHK(c, launch_mode_transform(c->Q, c->mt[1], c->x[d], nx, n, s));
+    } else {
+        for (int g = 0; g < c->opt.gamma; ++g)
+            if ((rc = visit(c, l + 1, g == 0, s))) return rc;
+    }
     {
         const int H = std::max(2, rs2(nu2 + (partial ? 1 : 0)));
         HeatArgs a = base_args(c, l);
@@ -311,6 +338,65 @@ int visit(tmg_heat_ctx *c, int l, bool first, hipStream_t s)
         return TMG_OK;
     }
     return level_pass(c, l, c->f[l], nullptr, first ? nullptr : c->x[l], c->x[l], nullptr, s);
+}
+
+// The sine-mode visits (see tmg_heat_ctx): the first level l >= 1 above the
+// coarsest with at most kModeSlabs slabs whose per-mode operators fit
+// kModeBytes; mode k (1..nx) has eigenvalue 4 sin^2(pi k h / 2) / h^2 and
+// eigenvector sqrt(2h) sin(pi k i h) (i = 1..nx).  The operators' columns
+// are the bottom kernel's visits of the unit loads (one launch per mode).
+int build_modes(tmg_heat_ctx *c, hipStream_t s)
+{
+    const int P = c->P, nx = c->nx, L = c->L;
+    int d = -1;
+    for (int l = 1; l + 1 < L; ++l) {
+        const double n = double(c->Nl[l] * P);
+        if (c->Nl[l] <= kModeSlabs && nx * n * n * 8.0 <= kModeBytes) {
+            d = l;
+            break;
+        }
+    }
+    if (d < 0 || L - d > kBottomMaxLevels) return TMG_OK;
+    const int64_t N = c->Nl[d], n = N * P;
+    const int nlv = L - d, stride = TabLayout(P).stride();
+    const double h = c->h;
+    std::vector<double> Q((size_t)nx * nx), tab((size_t)nx * nlv * stride);
+    for (int k = 1; k <= nx; ++k) {
+        const double sk = std::sin(M_PI * k * h / 2.0);
+        const double mu = 4.0 * sk * sk / (h * h);
+        for (int j = 0; j < nlv; ++j)
+            (void)level_table(P, mu * (c->T / (double)c->Nl[d + j]), 1, c->omega[d + j], false,
+                              &tab[((size_t)(k - 1) * nlv + j) * stride]);
+        for (int i = 1; i <= nx; ++i)
+            Q[(size_t)(k - 1) * nx + (i - 1)] = std::sqrt(2.0 * h) * std::sin(M_PI * k * i * h);
+    }
+    double *dtab = nullptr;
+    int rc;
+    if ((rc = halloc(c, &c->Q, Q.size())) || (rc = halloc(c, &dtab, tab.size())) ||
+        (rc = halloc(c, &c->mD, (size_t)nx * n * n)) || (rc = halloc(c, &c->mwin, (size_t)nx * 2 * n)) ||
+        (rc = halloc(c, &c->mt[0], (size_t)nx * n)) || (rc = halloc(c, &c->mt[1], (size_t)nx * n)))
+        return rc;
+    HCHK(c, hipMemcpyAsync(c->Q, Q.data(), Q.size() * 8, hipMemcpyHostToDevice, s));
+    HCHK(c, hipMemcpyAsync(dtab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < nx; ++k) {
+        DenseColArgs a{};
+        a.tab = dtab + (size_t)k * nlv * stride;
+        a.tab_level = stride;
+        a.R = c->R;
+        a.D = c->mD + (size_t)k * n * n;
+        a.N = N;
+        a.level = 0;
+        a.Lc = nlv - 1;
+        a.nu1 = c->opt.nu1;
+        a.nu2 = c->opt.nu2;
+        a.gamma = c->opt.gamma;
+        HCHK(c, launch_dense_cols(P, a, s));
+        HCHK(c, launch_dense_window(a.D, n, c->mwin + (size_t)k * 2 * n, s));
+    }
+    HCHK(c, hipStreamSynchronize(s));
+    c->mode_level = d;
+    c->mode_n = n;
+    return TMG_OK;
 }
 
 // Squared residual norm of u (or of the folded f when u is null) into c->sum.
@@ -489,6 +575,7 @@ int tmg_heat_setup(tmg_heat_handle *hp, int64_t n_slabs, int nx, double T,
     if (hipMemcpyAsync(c->R, R.data(), R.size() * 8, hipMemcpyHostToDevice, s) ||
         hipMemsetAsync(c->zeros, 0, sizeof(double) * nx, s) || hipStreamSynchronize(s))
         return fail(TMG_ERR_HIP);
+    if ((rc = build_modes(c, s))) return fail(rc);
     *hp = c;
     return TMG_OK;
 }
@@ -536,5 +623,12 @@ int tmg_heat_destroy(tmg_heat_handle c)
 }
 
 int tmg_heat_last_hip_error(tmg_heat_handle c) { return c ? c->last_hip : 0; }
+
+int tmg_heat_set_mode_solve(tmg_heat_handle c, int on)
+{
+    if (!c) return TMG_ERR_INVALID;
+    c->mode_on = on != 0;
+    return TMG_OK;
+}
 
 }  // extern "C"

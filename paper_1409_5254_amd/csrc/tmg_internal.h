@@ -323,6 +323,13 @@ hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t
 // x = D r over the rows' windows (nothing when *st says finished).
 hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
                               int64_t n, const InstState *st, hipStream_t s);
+// nop such products at once: operator y (D + y n^2, win + 2 y n) on
+// r + y n into x + y n.
+hipError_t launch_dense_apply_batch(const double *D, const int *win, const double *r, double *x,
+                                    int64_t n, int nop, hipStream_t s);
+// out = Q in for Q [nx][nx] and in, out [nx][n] (row-major).
+hipError_t launch_mode_transform(const double *Q, const double *in, double *out, int nx,
+                                 int64_t n, hipStream_t s);
 
 // Level-0 halo slots of a tile list (tile_out output slabs and `halo` halo
 // slabs per tile) from the iterate u, as the level-0 pass stores them.

@@ -77,6 +77,7 @@ def test_null_arguments():
     assert L.tmg_level_size(None, 0) == -1
     assert L.tmg_set_active_set(None, 1) == -1
     assert L.tmg_set_dense_bottom(None, 1, None) == -1
+    assert L.tmg_heat_set_mode_solve(None, 1) == -1
     o = b.Options.make(p=1)
     assert L.tmg_solve_noalloc(1024, 1.0, 1.0, None, None, None, None, 1e-10, 10, None, None,
                                None) == -1

@@ -72,6 +72,7 @@ def test_heat_cycles_sweeps(p, nu1, nu2, nx, n_coarse):
     P = p + 1
     kw = dict(nu1=nu1, nu2=nu2, n_coarse=n_coarse)
     s = B().HeatSolver(N, nx, T, p=p, **kw)
+    s.set_mode_solve(False)   # every level's legs
     f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
     u0 = rng.standard_normal(nx)
     du = dev(u)
@@ -94,6 +95,7 @@ def test_heat_cycles_partitioned(p, gamma, nx):
     N, T = 256, 0.2
     P = p + 1
     s = B().HeatSolver(N, nx, T, p=p, gamma=gamma, nu1=1, nu2=3)
+    s.set_mode_solve(False)   # every level's legs
     f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
     u0 = rng.standard_normal(nx)
     du = dev(u)
@@ -115,6 +117,7 @@ def test_heat_partitioned_global_tables(p, nx, N):
     f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
     u0 = rng.standard_normal(nx)
     s = B().HeatSolver(N, nx, T, p=p)
+    s.set_mode_solve(False)   # every level's legs
     du = dev(u)
     for _ in range(2):
         s.vcycle(dev(f), dev(u0), du)
@@ -178,3 +181,34 @@ def test_heat_sine_mode(p):
     ref = np.outer(np.sin(np.pi * x), an.alpha_of(p, lam1 * T / N) ** np.arange(1, N + 1))
     assert np.max(np.abs(w - ref)) <= 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("p,gamma,nx,N",
+                         [(p, g, nx, N) for p in (0, 1, 2, 3, 5) for g in (1, 2)
+                          for nx, N in ((1, 256), (15, 512), (31, 256), (127, 64))]
+                         + [(p, g, 255, 128) for p in (0, 1) for g in (1, 2)])
+def test_heat_mode_solve(p, gamma, nx, N):
+    """The coarse levels by sine modes (tmg_heat_set_mode_solve): two cycles
+    from a random start with it on and off, both at 1e-12 of the heat
+    oracle's; a solve with it on, the oracle's cycle count and iterate."""
+    rng = np.random.default_rng(1500 + 7 * p + gamma + nx)
+    T = 0.4
+    P = p + 1
+    f, u = rng.standard_normal(nx * N * P), rng.standard_normal(nx * N * P)
+    u0 = rng.standard_normal(nx)
+    ff = core.heat_fold(p, nx, u0, f)
+    ref = core.heat_cycles(p, nx, T, ff, u, 2, core.Opts(gamma=gamma))
+    for on in (True, False):
+        s = B().HeatSolver(N, nx, T, p=p, gamma=gamma)
+        s.set_mode_solve(on)
+        du = dev(u)
+        for _ in range(2):
+            s.vcycle(dev(f), dev(u0), du)
+        assert relerr(host(du), ref) <= TOL, (on, relerr(host(du), ref))
+        if on:
+            res = s.solve(dev(f * 0.01), dev(u0), rtol=1e-10)
+            uo, k, _, _ = core.heat_solve_folded(p, nx, T, core.heat_fold(p, nx, u0, f * 0.01),
+                                                 opts=core.Opts(gamma=gamma))
+            assert res.status == 0 and res.cycles[0] == k, (res.cycles, k)
+            assert relerr(host(res.u), uo) <= TOL
+        s.close()
