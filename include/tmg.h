@@ -437,7 +437,7 @@ int tmg_heat_last_hip_error(tmg_heat_handle h);
  * residual and the transfers in time are all diagonal in them.  Mode k
  * (eigenvalue 4 sin^2(pi k h/2)/h^2) follows the scalar problem of the
  * header's first part with that lambda and this cycle's damping.  So the
- * visits of the first level of at most 64 slabs above the coarsest (the
+ * visits of the first level of at most 256 slabs above the coarsest (the
  * per-mode operators within 1 GiB of device memory) are: the orthonormal
  * sine transform over the points, for each mode the scalar problem's
  * visit operator (tabulated at setup, as by tmg_set_dense_bottom), and the

@@ -13,6 +13,13 @@ constexpr int kDenseWaves = kDenseThreads / 64;
 constexpr int kDenseRows = 4;               // rows per work-group (one load of r feeds them)
 // column pairs per thread that cover the largest operator's rows
 constexpr int kDensePasses = (int)(kDenseMaxN / (2 * kDenseThreads));
+// passes that cover n columns (1, 2, 4 or 8: fewer registers, more
+// work-groups resident for the short operators)
+inline int dense_passes(int64_t n)
+{
+    const int64_t q = (n + 2 * kDenseThreads - 1) / (2 * kDenseThreads);
+    return q <= 1 ? 1 : q <= 2 ? 2 : q <= 4 ? 4 : kDensePasses;
+}
 
 // Stands in for a missing state (never finished), so that the flag's load
 // needs no branch.
@@ -71,7 +78,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_window(const double *__
 // a fixed order (butterfly within each wavefront, the wavefronts in turn),
 // so every run gives the same bits.  (A pair that ends one past a window
 // adds one more small product.)
-template <bool VEC>
+template <bool VEC, int PASSES>
 __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__restrict__ D,
                                                             const int *__restrict__ win,
                                                             const double *__restrict__ r,
@@ -115,9 +122,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
             c1 = max(c1, we[q]);
         }
     }
-    double rv[kDensePasses][2], dv[kDenseRows][kDensePasses][2];
+    double rv[PASSES][2], dv[kDenseRows][PASSES][2];
 #pragma unroll
-    for (int i = 0; i < kDensePasses; ++i) {
+    for (int i = 0; i < PASSES; ++i) {
         const int64_t c = c0 + 2 * t + 2 * kDenseThreads * i;
         if (VEC) {
             double2 a = make_double2(0.0, 0.0);
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     for (int q = 0; q < kDenseRows; ++q) {
         acc[q] = 0.0;
 #pragma unroll
-        for (int i = 0; i < kDensePasses; ++i) {
+        for (int i = 0; i < PASSES; ++i) {
             acc[q] = fma(dv[q][i][0], rv[i][0], acc[q]);
             acc[q] = fma(dv[q][i][1], rv[i][1], acc[q]);
         }
@@ -186,6 +193,28 @@ __global__ __launch_bounds__(kDenseThreads) void k_mode_transform(const double *
     out[(int64_t)a * n + j] = acc;
 }
 
+// k_dense_apply with the passes that cover n and 16-byte loads where n is
+// even and D, r are 16-byte aligned.
+template <int PASSES>
+void launch_apply_p(const double *D, const int *win, const double *r, double *x, int64_t n,
+                    const InstState *st, dim3 grid, hipStream_t s)
+{
+    const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
+    if (vec) hipLaunchKernelGGL((k_dense_apply<true, PASSES>), grid, dim3(kDenseThreads), 0, s, D, win, r, x, n, st);
+    else hipLaunchKernelGGL((k_dense_apply<false, PASSES>), grid, dim3(kDenseThreads), 0, s, D, win, r, x, n, st);
+}
+
+void launch_apply(const double *D, const int *win, const double *r, double *x, int64_t n,
+                  const InstState *st, dim3 grid, hipStream_t s)
+{
+    switch (dense_passes(n)) {
+    case 1: launch_apply_p<1>(D, win, r, x, n, st, grid, s); break;
+    case 2: launch_apply_p<2>(D, win, r, x, n, st, grid, s); break;
+    case 4: launch_apply_p<4>(D, win, r, x, n, st, grid, s); break;
+    default: launch_apply_p<kDensePasses>(D, win, r, x, n, st, grid, s); break;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_mode_transform(const double *Q, const double *in, double *out, int nx,
@@ -201,11 +230,8 @@ hipError_t launch_dense_apply_batch(const double *D, const int *win, const doubl
                                     int64_t n, int nop, hipStream_t s)
 {
     if (n < 1 || n > kDenseMaxN || nop < 1 || nop > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows), (unsigned)nop),
-        block(kDenseThreads);
-    const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
-    if (vec) hipLaunchKernelGGL(k_dense_apply<true>, grid, block, 0, s, D, win, r, x, n, nullptr);
-    else hipLaunchKernelGGL(k_dense_apply<false>, grid, block, 0, s, D, win, r, x, n, nullptr);
+    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows), (unsigned)nop);
+    launch_apply(D, win, r, x, n, nullptr, grid, s);
     return hipGetLastError();
 }
 
@@ -233,10 +259,8 @@ hipError_t launch_dense_apply(const double *D, const int *win, const double *r, 
                               int64_t n, const InstState *st, hipStream_t s)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows)), block(kDenseThreads);
-    const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
-    if (vec) hipLaunchKernelGGL(k_dense_apply<true>, grid, block, 0, s, D, win, r, x, n, st);
-    else hipLaunchKernelGGL(k_dense_apply<false>, grid, block, 0, s, D, win, r, x, n, st);
+    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows));
+    launch_apply(D, win, r, x, n, st, grid, s);
     return hipGetLastError();
 }
 

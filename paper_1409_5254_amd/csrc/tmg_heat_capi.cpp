@@ -92,7 +92,7 @@ int rs2(int x) { return (x + 1) & ~1; }
 constexpr int64_t kLegCoarse = 32;   // coarsest levels solved by a leg (one tile)
 // the sine-mode visits: a level of at most kModeSlabs slabs (and the
 // per-mode operators within kModeBytes), above the coarsest
-constexpr int64_t kModeSlabs = 64;
+constexpr int64_t kModeSlabs = 256;
 constexpr double kModeBytes = double(1u << 30);
 int TO(int H) { return kHeatThreads - H; }
 int64_t tiles(int64_t N, int H) { return (N + TO(H) - 1) / TO(H); }
