@@ -204,6 +204,7 @@ struct tmg_ctx {
     int64_t dense_n = 0, dense_cap[2] = {0, 0};
     double *dense[2] = {nullptr, nullptr};
     int *dense_win[2] = {nullptr, nullptr};
+    bool dense_nomem = false;   // an operator's allocation failed (until the next plan)
     void dense_stale() { dense_ok[0] = dense_ok[1] = false; }
     std::map<std::tuple<int, int, int>, TileList> tiles;
     std::map<int, std::pair<int *, int>> op_coarse;
@@ -1459,7 +1460,7 @@ int drain(tmg_ctx *c)
 int ensure_dense(tmg_ctx *c, hipStream_t s, bool trans)
 {
     const int d = trans ? 1 : 0;
-    if (c->dense_ok[d] || !c->want_dense()) return TMG_OK;
+    if (c->dense_ok[d] || c->dense_nomem || !c->want_dense()) return TMG_OK;
     const int l = c->lb[0];
     const int64_t N = c->N[0] >> l, n = N * c->P;
     int rc;
@@ -1471,9 +1472,18 @@ int ensure_dense(tmg_ctx *c, hipStream_t s, bool trans)
         c->dense[d] = nullptr;
         c->dense_win[d] = nullptr;
         c->dense_cap[d] = 0;
-        if ((rc = dalloc(c, &c->dense[d], (size_t)(n * n))) ||
-            (rc = dalloc(c, &c->dense_win[d], (size_t)(2 * kDenseMaxN))))
-            return rc;
+        if (dalloc(c, &c->dense[d], (size_t)(n * n)) ||
+            dalloc(c, &c->dense_win[d], (size_t)(2 * kDenseMaxN))) {
+            // no room for the operator: the cycles run the recursion
+            dfree(c, c->dense[d]);
+            dfree(c, c->dense_win[d]);
+            c->dense[d] = nullptr;
+            c->dense_win[d] = nullptr;
+            c->dense_nomem = true;
+            c->last_hip = 0;
+            (void)hipGetLastError();   // the failed allocation is no error of this call
+            return TMG_OK;
+        }
         c->dense_cap[d] = n * n;
     }
     // cycles a solve left queued past convergence may still read D
@@ -1852,6 +1862,7 @@ int apply_plan(tmg_ctx *c, int64_t cap, bool pairs, int span, int span_after, hi
     const int Lm = c->Lmax, batch = c->batch, P = c->P;
     c->lb = lbv;
     c->dense_stale();
+    c->dense_nomem = false;
     c->bottom_cap = cap;
     c->pairs = pairs;
     c->span = c->span_fits(span) ? span : 0;

@@ -371,11 +371,15 @@ int build_modes(tmg_heat_ctx *c, hipStream_t s)
             Q[(size_t)(k - 1) * nx + (i - 1)] = std::sqrt(2.0 * h) * std::sin(M_PI * k * i * h);
     }
     double *dtab = nullptr;
-    int rc;
-    if ((rc = halloc(c, &c->Q, Q.size())) || (rc = halloc(c, &dtab, tab.size())) ||
-        (rc = halloc(c, &c->mD, (size_t)nx * n * n)) || (rc = halloc(c, &c->mwin, (size_t)nx * 2 * n)) ||
-        (rc = halloc(c, &c->mt[0], (size_t)nx * n)) || (rc = halloc(c, &c->mt[1], (size_t)nx * n)))
-        return rc;
+    if (halloc(c, &c->Q, Q.size()) || halloc(c, &dtab, tab.size()) ||
+        halloc(c, &c->mD, (size_t)nx * n * n) || halloc(c, &c->mwin, (size_t)nx * 2 * n) ||
+        halloc(c, &c->mt[0], (size_t)nx * n) || halloc(c, &c->mt[1], (size_t)nx * n)) {
+        // no room for the modes' operators: every level runs its legs (the
+        // buffers made so far are freed with the handle)
+        c->last_hip = 0;
+        (void)hipGetLastError();   // the failed allocation is no error of this call
+        return TMG_OK;
+    }
     HCHK(c, hipMemcpyAsync(c->Q, Q.data(), Q.size() * 8, hipMemcpyHostToDevice, s));
     HCHK(c, hipMemcpyAsync(dtab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, s));
     for (int k = 0; k < nx; ++k) {
