@@ -102,8 +102,7 @@ typedef struct {
  * every periodic problem, on generic kernels (one slab per thread, operators
  * in LDS, FP64 only; the levels above the bottom stream in one-level legs,
  * and one work-group visits the levels of at most 256 slabs for p <= 9, 128
- * above, as the bottom cap allows; the periodic problem's bottom is its
- * coarsest level alone). */
+ * above, as the bottom cap allows). */
 #define TMG_MAX_DEGREE 20
 #define TMG_MAX_TUNED_DEGREE 5
 

@@ -288,21 +288,20 @@ struct tmg_ctx {
     // every bottom-kernel level fits one wavefront (one-wavefront work-groups)
     bool small_bottom() const { return bottom_cap <= 64 * bottom_slabs(P); }
     // largest bottom cap: the bottom kernel's level, or the generic kernels'
-    // bottom visit (the periodic problem: its coarsest level only)
+    // bottom visit
     int64_t max_cap() const
     {
         if (!generic) return bottom_max(P);
-        return std::max<int64_t>(opt.n_coarse, opt.periodic ? 0 : gbottom_max(P));
+        return std::max<int64_t>(opt.n_coarse, gbottom_max(P));
     }
     // generic: the bottom spans several levels (k_gvisit)
     bool gvisit() const { return generic && bottom_cap > opt.n_coarse; }
     // the dense bottom operator applies: one instance in FP64 whose bottom
     // level lies strictly between level 0 and the coarsest (V or W; the
-    // generic kernels' bottom visit too, not the periodic problem's)
+    // generic kernels' bottom visit too, the periodic problem's included)
     bool want_dense() const
     {
-        if (!dense_on || batch != 1 || mixed || fixed() || opt.periodic || lb.empty())
-            return false;
+        if (!dense_on || batch != 1 || mixed || fixed() || lb.empty()) return false;
         const int l = lb[0];
         return l >= 1 && l < L[0] - 1 && (N[0] >> l) * P <= kDenseMaxN;
     }
@@ -1494,6 +1493,7 @@ int ensure_dense(tmg_ctx *c, hipStream_t s, bool trans)
     a.R = trans ? c->R_adj : c->R_fwd;
     a.D = c->dense[d];
     a.backward = trans ? 1 : 0;
+    a.periodic = c->opt.periodic;
     a.N = N;
     a.level = l;
     a.Lc = c->L[0] - 1;
@@ -1969,14 +1969,13 @@ namespace {
 // The generic kernels serve degrees above the tuned kernels' and the
 // periodic problem; there every level above the bottom streams in one-level
 // legs, and the bottom work-group visits the levels up to gbottom_max(P)
-// slabs (the periodic problem: solves its coarsest level exactly).
+// slabs.
 bool uses_generic(const tmg_options &o) { return o.p + 1 > kMaxTunedP || o.periodic != 0; }
 int64_t first_cap(const tmg_options &o)
 {
     if (!uses_generic(o)) return schedule_cap(o.p + 1, o.schedule);
-    // the generic bottom visit up to gbottom_max(P) slabs (periodic: the
-    // coarsest level only)
-    const int64_t gmax = o.periodic ? o.n_coarse : gbottom_max(o.p + 1);
+    // the generic bottom visit up to gbottom_max(P) slabs
+    const int64_t gmax = gbottom_max(o.p + 1);
     const int64_t cap = o.schedule < 0 ? gmax
                                        : std::min<int64_t>(gmax, int64_t(1) << std::min(o.schedule, 40));
     return std::max<int64_t>(o.n_coarse, cap);

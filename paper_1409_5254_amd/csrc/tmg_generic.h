@@ -362,14 +362,59 @@ struct GVisitLds {
     double x[2 * BMAX * P];
 };
 
+// g_left over a whole level of nl slabs held one per thread; periodic:
+// slab 0's left neighbour is slab nl-1 (through wrap[], alternating as xw).
+__device__ __forceinline__ double gv_left(double mine, double (*xw)[kGWaves], double *wrap,
+                                          int &phase, int nl, int periodic)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v = lane_shr1(mine);
+    if (lane == 63) xw[phase][wave] = mine;
+    if (periodic && (int)threadIdx.x == nl - 1) wrap[phase] = mine;
+    __syncthreads();
+    if (lane == 0) v = wave ? xw[phase][wave - 1] : (periodic ? wrap[phase] : 0.0);
+    phase ^= 1;
+    return v;
+}
+
+// g_sweeps and g_residual on a whole level (gv_left; the same arithmetic)
+template <int P>
+__device__ __forceinline__ void gv_sweeps(double (&u)[P], const double (&g)[P], const GOps<P> &op,
+                                          int nsweep, double (*xw)[kGWaves], double *wrap,
+                                          int &phase, int nl, int periodic)
+{
+    for (int s = 0; s < nsweep; ++s) {
+        const double wl = gv_left(g_end<P>(u, op), xw, wrap, phase, nl, periodic);
+        const double om = op.omc();
+#pragma unroll
+        for (int k = 0; k < P; ++k) u[k] = om * u[k] + g[k] + op.h(k) * wl;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void gv_residual(double (&r)[P], const double (&u)[P], const double (&f)[P],
+                                            const GOps<P> &op, double (*xw)[kGWaves], double *wrap,
+                                            int &phase, int nl, int periodic)
+{
+    const double wl = gv_left(g_end<P>(u, op), xw, wrap, phase, nl, periodic);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double s = f[k] + op.v(k) * wl;
+        for (int l = 0; l < P; ++l) s -= op.A(k, l) * u[l];
+        r[k] = s;
+    }
+}
+
 // The visit of level lb (its right-hand side and initial iterate in sm, in
-// logical slab order; op holds the table block of level `cur`).
+// logical slab order; op holds the table block of level `cur`); periodic:
+// every level wraps around (slab -1 is slab N_l - 1) and the coarsest
+// level's solve closes cyclically.
 template <int P>
 __device__ __forceinline__ void gvisit_levels(GOps<P> &op, GVisitLds<P> &sm, double *bw, double *sa,
-                                              double *sb, double (*xw)[kGWaves], double *red,
-                                              const double *tab0, int64_t tstep, int N, int lb,
-                                              int Lc, int nu1, int nu2, int gamma, bool zero,
-                                              int &cur, int &phase)
+                                              double *sb, double (*xw)[kGWaves], double *wrap,
+                                              double *red, const double *tab0, int64_t tstep, int N,
+                                              int lb, int Lc, int nu1, int nu2, int gamma,
+                                              int periodic, bool zero, int &cur, int &phase)
 {
     const int t = threadIdx.x;
     auto use = [&](int l) {
@@ -404,8 +449,8 @@ __device__ __forceinline__ void gvisit_levels(GOps<P> &op, GVisitLds<P> &sm, dou
         load(f, sm.f, l, false);
         load(u, sm.x, l, zr);
         gf(g, f);
-        g_sweeps<P>(u, g, op, nu1, xw, phase);
-        g_residual<P>(r, u, f, op, xw, phase);
+        gv_sweeps<P>(u, g, op, nu1, xw, wrap, phase, nsl(l), periodic);
+        gv_residual<P>(r, u, f, op, xw, wrap, phase, nsl(l), periodic);
 #pragma unroll
         for (int k = 0; k < P; ++k) rn[k] = __shfl_down(r[k], 1, 64);
         if (t < nsl(l) && !(t & 1)) {
@@ -425,7 +470,7 @@ __device__ __forceinline__ void gvisit_levels(GOps<P> &op, GVisitLds<P> &sm, dou
         load(f, sm.f, l, false);
         load(u, sm.x, l, zr);
         gf(g, f);
-        g_sweeps<P>(u, g, op, nu1, xw, phase);
+        gv_sweeps<P>(u, g, op, nu1, xw, wrap, phase, nsl(l), periodic);
         const bool in = t < nsl(l);
 #pragma unroll
         for (int k = 0; k < P; ++k) e[k] = in ? sm.x[loff(l + 1) + (t / 2) * P + k] : 0.0;
@@ -436,7 +481,7 @@ __device__ __forceinline__ void gvisit_levels(GOps<P> &op, GVisitLds<P> &sm, dou
             for (int q = 0; q < P; ++q) s += op.RT(par, k, q) * e[q];
             u[k] += s;
         }
-        g_sweeps<P>(u, g, op, nu2, xw, phase);
+        gv_sweeps<P>(u, g, op, nu2, xw, wrap, phase, nsl(l), periodic);
         __syncthreads();   // every thread has read its iterate and correction
         if (in)
 #pragma unroll
@@ -444,8 +489,8 @@ __device__ __forceinline__ void gvisit_levels(GOps<P> &op, GVisitLds<P> &sm, dou
     };
     auto coarse = [&](int l) {
         use(l);
-        (void)g_exact<P, false>(sm.f + loff(l), sm.x + loff(l), nsl(l), 0, op, bw, sa, sb, xw, red,
-                                false, nullptr);
+        (void)g_exact<P, false>(sm.f + loff(l), sm.x + loff(l), nsl(l), periodic, op, bw, sa, sb, xw,
+                                red, false, nullptr);
     };
     // bit l of `again` marks the second visit of level l
     uint64_t again = 0;
@@ -487,6 +532,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gvisit(BottomArgsT<double> a)
     __shared__ double bw[kMaxCoarse];
     __shared__ double sa[kGenThreads], sb[kGenThreads];
     __shared__ double xw[2][kGWaves];
+    __shared__ double wrap[2];
     __shared__ double red[kGWaves];
     const int j = a.inst[blockIdx.x];
     if (a.st && a.st[j].done) return;
@@ -519,8 +565,8 @@ __global__ __launch_bounds__(kGenThreads) void k_gvisit(BottomArgsT<double> a)
     __syncthreads();
     if (lb == 0 && a.u0 && t < P) sm.f[t] += a.u0[j] * op.v(t);   // u0 enters slab 0
     int phase = 0, cur = lb;
-    gvisit_levels<P>(op, sm, bw, sa, sb, xw, red, tab0, tstep, N, lb, Lc, a.nu1, a.nu2, a.gamma,
-                     a.x_in == nullptr, cur, phase);
+    gvisit_levels<P>(op, sm, bw, sa, sb, xw, wrap, red, tab0, tstep, N, lb, Lc, a.nu1, a.nu2, a.gamma,
+                     a.periodic, a.x_in == nullptr, cur, phase);
     for (int i = t; i < N * P; i += kGenThreads) {
         const int m = i / P, k = i - m * P;
         xg[(off + (BW ? N - 1 - m : m)) * P + k] = sm.x[i];
@@ -539,7 +585,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gvisit(BottomArgsT<double> a)
             f[k] = t < N ? sm.f[t * P + k] : 0.0;
             u[k] = t < N ? sm.x[t * P + k] : 0.0;
         }
-        g_residual<P>(r, u, f, op, xw, phase);
+        gv_residual<P>(r, u, f, op, xw, wrap, phase, N, a.periodic);
         double acc = 0.0;
         if (t < N)
 #pragma unroll
@@ -562,6 +608,7 @@ __global__ __launch_bounds__(kGenThreads) void k_gdense_cols(DenseColArgs a)
     __shared__ double bw[kMaxCoarse];
     __shared__ double sa[kGenThreads], sb[kGenThreads];
     __shared__ double xw[2][kGWaves];
+    __shared__ double wrap[2];
     __shared__ double red[kGWaves];
     const int64_t col = blockIdx.x;
     const int N = (int)a.N, n = N * P, lb = a.level;
@@ -576,8 +623,8 @@ __global__ __launch_bounds__(kGenThreads) void k_gdense_cols(DenseColArgs a)
     __syncthreads();
     int phase = 0, cur = lb;
     for (int g = 0; g < a.gamma; ++g)
-        gvisit_levels<P>(op, sm, bw, sa, sb, xw, red, a.tab, a.tab_level, N, lb, a.Lc, a.nu1, a.nu2,
-                         a.gamma, g == 0, cur, phase);
+        gvisit_levels<P>(op, sm, bw, sa, sb, xw, wrap, red, a.tab, a.tab_level, N, lb, a.Lc, a.nu1,
+                         a.nu2, a.gamma, a.periodic, g == 0, cur, phase);
     for (int i = threadIdx.x; i < n; i += kGenThreads) a.D[(int64_t)phys(i) * n + col] = sm.x[i];
 }
 

@@ -24,7 +24,7 @@ template <int PP>
 hipError_t launch_gbottom_p(bool backward, const BottomArgsT<double> &a, int ninst, hipStream_t s)
 {
     const dim3 grid(ninst), block(kGenThreads);
-    if (a.visit && !a.periodic) {
+    if (a.visit) {
         if (backward) hipLaunchKernelGGL((k_gvisit<PP, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_gvisit<PP, false>), grid, block, 0, s, a);
     } else {

@@ -303,6 +303,7 @@ struct DenseColArgs {
     int level, Lc, nu1, nu2, gamma;   // Lc: the coarsest level
     int backward;   // the transposed system (backward in time; tables and
                     // transfers of the adjoint), D over physical slab order
+    int periodic;   // the time-periodic problem (generic kernels only)
 };
 template <int PP>
 hipError_t launch_dense_cols_p(const DenseColArgs &a, hipStream_t s);

@@ -277,8 +277,8 @@ def test_generic_bottom_visit_bitwise(p, gamma):
 
 def test_generic_schedule_caps():
     """A generic handle takes bottom caps from the coarsest level up to its
-    bottom visit's largest level, without two-level launches or spans; the
-    periodic problem takes only the coarsest level."""
+    bottom visit's largest level (the periodic problem's too), without
+    two-level launches or spans."""
     s = B().Solver([1024], [1.0], [1.0], p=10)
     s.set_schedule(128, pairs=False)
     s.set_schedule(2, pairs=False)
@@ -289,8 +289,9 @@ def test_generic_schedule_caps():
     s.close()
     s = B().Solver([1024], [1.0], [1.0], p=3, periodic=1)
     s.set_schedule(2, pairs=False)
+    s.set_schedule(256, pairs=False)
     with pytest.raises(B().TmgError):
-        s.set_schedule(8, pairs=False)
+        s.set_schedule(512, pairs=False)
     s.close()
 
 
@@ -318,3 +319,40 @@ def test_generic_dense_bottom(p, gamma):
     assert res.status == 0 and res.cycles[0] == k
     assert relerr(host(res.u), uo) <= TOL
     s.close()
+
+
+@pytest.mark.parametrize("p", [0, 3, 10])
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_periodic_bottom_visit(p, gamma):
+    """The periodic problem's bottom visit (every level wraps around: slab
+    -1 is slab N_l - 1; the coarsest level closes cyclically): solves and
+    adjoint solves with bottom caps 2, 8, 32 and the largest give the same
+    bits with the dense operator off, and equal the oracle's periodic
+    solves at 1e-12; with the operator on (one instance), the same cycle
+    count and 1e-12."""
+    rng = np.random.default_rng(1600 + p + 10 * gamma)
+    N, T, lam = 2048, 8.0, 0.9
+    P = p + 1
+    f = rng.standard_normal(N * P) * 0.1
+    g = rng.standard_normal(N * P) * 0.1
+    largest = 256 if P <= 10 else 128
+    uo, k, _, _ = core.solve_folded(p, T, lam, f, opts=core.Opts(gamma=gamma), periodic=True)
+    zo, kz, _, _ = core.solve_folded(p, T, lam, g, rtol=1e-10, trans=True,
+                                     opts=core.Opts(gamma=gamma), periodic=True)
+    for dense in (False, True):
+        s = B().Solver([N], [T], [lam], p=p, gamma=gamma, periodic=1)
+        s.set_dense_bottom(dense)
+        out = []
+        for cap in ((2, 8, 32, largest) if not dense else (largest,)):
+            s.set_schedule(cap, pairs=False)
+            r = s.solve(dev(f), dev([0.0]), rtol=1e-10)
+            z, _, _, cz, _, st = s.adjoint_solve(dev(g), rtol=1e-10)
+            assert r.status == 0 and st == 0
+            out.append((host(r.u).copy(), list(r.cycles), host(z).copy(), list(cz)))
+        s.close()
+        for o in out:
+            assert o[1][0] == k and o[3][0] == kz, (dense, o[1], k, o[3], kz)
+            assert relerr(o[0], uo) <= TOL and relerr(o[2], zo) <= TOL
+        if not dense:
+            for o in out[1:]:
+                assert np.array_equal(o[0], out[0][0]) and np.array_equal(o[2], out[0][2])
