@@ -205,6 +205,8 @@ struct tmg_ctx {
     double *dense[2] = {nullptr, nullptr};
     int *dense_win[2] = {nullptr, nullptr};
     bool dense_nomem = false;   // an operator's allocation failed (until the next plan)
+    int64_t dense_w[2] = {0, 0};   // the widest span a product's work-group loads
+    int *dense_wd = nullptr;       // device copy of the last one measured
     void dense_stale() { dense_ok[0] = dense_ok[1] = false; }
     std::map<std::tuple<int, int, int>, TileList> tiles;
     std::map<int, std::pair<int *, int>> op_coarse;
@@ -668,7 +670,8 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
         const int d = io.trans ? 1 : 0;
         if (c->dense_ok[d] && c->opt.gamma == 1 && !x_in && level == c->dense_level) {
             HIPCHK(c, launch_dense_apply(c->dense[d], c->dense_win[d], store<T>(c).f[level], x_out,
-                                         c->dense_n, io.use_state ? c->st : nullptr, s));
+                                         c->dense_n, io.use_state ? c->st : nullptr, s,
+                                         c->dense_w[d]));
             return TMG_OK;
         }
     }
@@ -824,7 +827,7 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
         const int d = io.trans ? 1 : 0;
         if (c->dense_ok[d] && l == c->dense_level) {
             HIPCHK(c, launch_dense_apply(c->dense[d], c->dense_win[d], L.f[l], L.x(l, 0), c->dense_n,
-                                         io.use_state ? c->st : nullptr, s));
+                                         io.use_state ? c->st : nullptr, s, c->dense_w[d]));
             return TMG_OK;
         }
         // one instance's streaming levels of a W-cycle in fused launches
@@ -1502,6 +1505,18 @@ int ensure_dense(tmg_ctx *c, hipStream_t s, bool trans)
     a.gamma = c->opt.gamma;
     HIPCHK(c, c->generic ? launch_gdense_cols(c->P, a, s) : launch_dense_cols(c->P, a, s));
     HIPCHK(c, launch_dense_window(c->dense[d], n, c->dense_win[d], s));
+    // the widest span a product's work-group loads (sets its passes)
+    c->dense_w[d] = n;
+    if (c->dense_wd || dalloc(c, &c->dense_wd, 1) == TMG_OK) {
+        int w = (int)n;
+        HIPCHK(c, launch_dense_window_max(c->dense_win[d], n, 1, c->dense_wd, s));
+        HIPCHK(c, hipMemcpyAsync(&w, c->dense_wd, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        c->dense_w[d] = w;
+    } else {
+        c->last_hip = 0;
+        (void)hipGetLastError();
+    }
     if (c->dense_level != l || c->dense_n != n) c->dense_ok[1 - d] = false;
     c->dense_level = l;
     c->dense_n = n;

@@ -2,6 +2,9 @@
 // its application (the columns are built in tmg_bottom.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
+
 #include "tmg_kernels.h"
 
 namespace tmg {
@@ -176,6 +179,37 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     }
 }
 
+// *wmax = the widest span a work-group of k_dense_apply loads: over the
+// groups of kDenseRows consecutive rows of each of nop operators of n rows
+// (win: 2 ints per row), the largest end minus the smallest start of the
+// group's nonempty windows.  One work-group, a fixed reduction.
+__global__ __launch_bounds__(kDenseThreads) void k_dense_wmax(const int *__restrict__ win, int64_t n,
+                                                           int nop, int *__restrict__ wmax)
+{
+    __shared__ int red[kDenseWaves];
+    const int64_t groups = (n + kDenseRows - 1) / kDenseRows;
+    int w = 0;
+    for (int64_t i = threadIdx.x; i < groups * nop; i += kDenseThreads) {
+        const int64_t y = i / groups, r0 = (i - y * groups) * kDenseRows;
+        int c0 = INT_MAX, c1 = 0;
+        for (int q = 0; q < kDenseRows && r0 + q < n; ++q) {
+            const int *p = win + 2 * (y * n + r0 + q);
+            if (p[1] > p[0]) {
+                c0 = min(c0, p[0]);
+                c1 = max(c1, p[1]);
+            }
+        }
+        if (c1 > c0) w = max(w, c1 - c0);
+    }
+    for (int o = 32; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kDenseWaves; ++k) w = max(w, red[k]);
+        *wmax = w;
+    }
+}
+
 // out[a][j] = sum_b Q[a][b] in[b][j] over a, b < nx, j < n: one thread per
 // output, the b in order.
 __global__ __launch_bounds__(kDenseThreads) void k_mode_transform(const double *__restrict__ Q,
@@ -205,9 +239,10 @@ void launch_apply_p(const double *D, const int *win, const double *r, double *x,
 }
 
 void launch_apply(const double *D, const int *win, const double *r, double *x, int64_t n,
-                  const InstState *st, dim3 grid, hipStream_t s)
+                  const InstState *st, dim3 grid, hipStream_t s, int64_t width)
 {
-    switch (dense_passes(n)) {
+    // the passes cover the widest span a work-group loads (at most n)
+    switch (dense_passes(std::min<int64_t>(n, width))) {
     case 1: launch_apply_p<1>(D, win, r, x, n, st, grid, s); break;
     case 2: launch_apply_p<2>(D, win, r, x, n, st, grid, s); break;
     case 4: launch_apply_p<4>(D, win, r, x, n, st, grid, s); break;
@@ -226,12 +261,19 @@ hipError_t launch_mode_transform(const double *Q, const double *in, double *out,
     return hipGetLastError();
 }
 
+hipError_t launch_dense_window_max(const int *win, int64_t n, int nop, int *wmax, hipStream_t s)
+{
+    if (n < 1 || nop < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dense_wmax, dim3(1), dim3(kDenseThreads), 0, s, win, n, nop, wmax);
+    return hipGetLastError();
+}
+
 hipError_t launch_dense_apply_batch(const double *D, const int *win, const double *r, double *x,
-                                    int64_t n, int nop, hipStream_t s)
+                                    int64_t n, int nop, hipStream_t s, int64_t width)
 {
     if (n < 1 || n > kDenseMaxN || nop < 1 || nop > 65535) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows), (unsigned)nop);
-    launch_apply(D, win, r, x, n, nullptr, grid, s);
+    launch_apply(D, win, r, x, n, nullptr, grid, s, width);
     return hipGetLastError();
 }
 
@@ -256,11 +298,11 @@ hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t
 }
 
 hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
-                              int64_t n, const InstState *st, hipStream_t s)
+                              int64_t n, const InstState *st, hipStream_t s, int64_t width)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows));
-    launch_apply(D, win, r, x, n, st, grid, s);
+    launch_apply(D, win, r, x, n, st, grid, s, width);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct tmg_heat_ctx {
     double *mD = nullptr;                 // [nx][n][n] per-mode operators
     int *mwin = nullptr;                  // [nx][2n] their rows' windows
     double *mt[2] = {nullptr, nullptr};   // [nx][n] the transformed f, result
+    int64_t mode_w = 0;                   // the widest span a product's work-group loads
     std::vector<void *> allocs;
     int last_hip = 0;
 };
@@ -290,7 +291,7 @@ int level_pass(tmg_heat_ctx *c, int l, const double *f, const double *u0, const 
         const int d = l + 1, nx = c->nx;
         const int64_t n = c->mode_n;
         HCHK(c, launch_mode_transform(c->Q, c->f[d], c->mt[0], nx, n, s));
-        HCHK(c, launch_dense_apply_batch(c->mD, c->mwin, c->mt[0], c->mt[1], n, nx, s));
+        HCHK(c, launch_dense_apply_batch(c->mD, c->mwin, c->mt[0], c->mt[1], n, nx, s, c->mode_w));
         HCHK(c, launch_mode_transform(c->Q, c->mt[1], c->x[d], nx, n, s));
     } else {
         for (int g = 0; g < c->opt.gamma; ++g)
@@ -397,7 +398,18 @@ int build_modes(tmg_heat_ctx *c, hipStream_t s)
         HCHK(c, launch_dense_cols(P, a, s));
         HCHK(c, launch_dense_window(a.D, n, c->mwin + (size_t)k * 2 * n, s));
     }
+    // the widest span a product's work-group loads, over every mode
+    int w = (int)n;
+    int *wd = nullptr;
+    if (halloc(c, &wd, 1) == TMG_OK) {
+        HCHK(c, launch_dense_window_max(c->mwin, n, nx, wd, s));
+        HCHK(c, hipMemcpyAsync(&w, wd, sizeof(int), hipMemcpyDeviceToHost, s));
+    } else {
+        c->last_hip = 0;
+        (void)hipGetLastError();
+    }
     HCHK(c, hipStreamSynchronize(s));
+    c->mode_w = w;
     c->mode_level = d;
     c->mode_n = n;
     return TMG_OK;

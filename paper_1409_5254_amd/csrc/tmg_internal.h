@@ -321,13 +321,17 @@ hipError_t launch_gdense_cols(int P, const DenseColArgs &a, hipStream_t s);
 // diagonal: slabs many decay lengths apart barely couple).
 constexpr int kDenseDropExp = -64;
 hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t s);
-// x = D r over the rows' windows (nothing when *st says finished).
+// *wmax (device) = the widest span of columns a work-group of the product
+// loads, over nop operators of n rows (their windows in win, in turn).
+hipError_t launch_dense_window_max(const int *win, int64_t n, int nop, int *wmax, hipStream_t s);
+// x = D r over the rows' windows (nothing when *st says finished); width:
+// launch_dense_window_max's span (n when unknown), which sets the passes.
 hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
-                              int64_t n, const InstState *st, hipStream_t s);
+                              int64_t n, const InstState *st, hipStream_t s, int64_t width);
 // nop such products at once: operator y (D + y n^2, win + 2 y n) on
 // r + y n into x + y n.
 hipError_t launch_dense_apply_batch(const double *D, const int *win, const double *r, double *x,
-                                    int64_t n, int nop, hipStream_t s);
+                                    int64_t n, int nop, hipStream_t s, int64_t width);
 // out = Q in for Q [nx][nx] and in, out [nx][n] (row-major).
 hipError_t launch_mode_transform(const double *Q, const double *in, double *out, int nx,
                                  int64_t n, hipStream_t s);
