@@ -13,7 +13,10 @@ namespace {
 
 constexpr int kDenseThreads = 256;          // four wavefronts
 constexpr int kDenseWaves = kDenseThreads / 64;
-constexpr int kDenseRows = 4;               // rows per work-group (one load of r feeds them)
+// rows per work-group: one, so that a work-group's chain after its loads
+// is a single row's reduction (groups of 2 rows measured the same, of 4
+// and 8 rows slower: their reductions run one after another)
+constexpr int kDenseRows = 1;
 // column pairs per thread that cover the largest operator's rows
 constexpr int kDensePasses = (int)(kDenseMaxN / (2 * kDenseThreads));
 // passes that cover n columns (1, 2, 4 or 8: fewer registers, more
@@ -109,10 +112,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
         we[q] = win[2 * rq + 1];
     }
     const int done = sp->done;
-    // the windows are inputs of this (empty) statement, so their loads are
+    // the windows are inputs of these (empty) statements, so their loads are
     // issued with the flag's, ahead of the exit test, and one wait covers all
-    __asm__ volatile("" ::"s"(ws[0]), "s"(ws[1]), "s"(ws[2]), "s"(ws[3]), "s"(we[0]), "s"(we[1]),
-                     "s"(we[2]), "s"(we[3]), "s"(done));
+#pragma unroll
+    for (int q = 0; q < kDenseRows; ++q) __asm__ volatile("" ::"s"(ws[q]), "s"(we[q]));
+    __asm__ volatile("" ::"s"(done));
     if (done) return;
 #pragma unroll
     for (int q = 0; q < kDenseRows; ++q)
