@@ -13,10 +13,10 @@ namespace {
 
 constexpr int kDenseThreads = 256;          // four wavefronts
 constexpr int kDenseWaves = kDenseThreads / 64;
-// rows per work-group: one, so that a work-group's chain after its loads
-// is a single row's reduction (groups of 2 rows measured the same, of 4
-// and 8 rows slower: their reductions run one after another)
-constexpr int kDenseRows = 1;
+// rows per work-group of the product: kDenseRows (one load of r feeds
+// them), or one, whose chain after the loads is a single row's reduction
+// (for products that follow each other with the operator in the L2 caches)
+constexpr int kDenseRows = 4;
 // column pairs per thread that cover the largest operator's rows
 constexpr int kDensePasses = (int)(kDenseMaxN / (2 * kDenseThreads));
 // passes that cover n columns (1, 2, 4 or 8: fewer registers, more
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_window(const double *__
     }
 }
 
-// x = D r: kDenseRows rows per work-group.  Thread t takes the column pairs
+// x = D r: ROWS rows per work-group.  Thread t takes the column pairs
 // (c, c + 1), c = c0 + 2 t + 2 kDenseThreads i, from the smallest window
 // start c0 of the group's rows, and of each row the pairs inside its window:
 // every load is issued first (16-byte loads; VEC = false: one column at a
@@ -84,15 +84,15 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_window(const double *__
 // a fixed order (butterfly within each wavefront, the wavefronts in turn),
 // so every run gives the same bits.  (A pair that ends one past a window
 // adds one more small product.)
-template <bool VEC, int PASSES>
+template <bool VEC, int PASSES, int ROWS>
 __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__restrict__ D,
                                                             const int *__restrict__ win,
                                                             const double *__restrict__ r,
                                                             double *__restrict__ x, int64_t n,
                                                             const InstState *__restrict__ st)
 {
-    __shared__ double red[kDenseRows][kDenseWaves];
-    const int64_t row0 = (int64_t)blockIdx.x * kDenseRows;
+    __shared__ double red[ROWS][kDenseWaves];
+    const int64_t row0 = (int64_t)blockIdx.x * ROWS;
     const int t = threadIdx.x;
     // a batch of operators (the heat equation's sine modes): operator y
     {
@@ -104,9 +104,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     }
     // the windows and the state flag in one round trip
     const InstState *sp = st ? st : &g_no_state;
-    int ws[kDenseRows], we[kDenseRows];
+    int ws[ROWS], we[ROWS];
 #pragma unroll
-    for (int q = 0; q < kDenseRows; ++q) {
+    for (int q = 0; q < ROWS; ++q) {
         const int64_t rq = min(row0 + q, n - 1);   // clamped: loads without branches
         ws[q] = win[2 * rq];
         we[q] = win[2 * rq + 1];
@@ -115,21 +115,21 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     // the windows are inputs of these (empty) statements, so their loads are
     // issued with the flag's, ahead of the exit test, and one wait covers all
 #pragma unroll
-    for (int q = 0; q < kDenseRows; ++q) __asm__ volatile("" ::"s"(ws[q]), "s"(we[q]));
+    for (int q = 0; q < ROWS; ++q) __asm__ volatile("" ::"s"(ws[q]), "s"(we[q]));
     __asm__ volatile("" ::"s"(done));
     if (done) return;
 #pragma unroll
-    for (int q = 0; q < kDenseRows; ++q)
+    for (int q = 0; q < ROWS; ++q)
         if (row0 + q >= n) we[q] = ws[q];   // a row past the end: an empty window
     int c0 = (int)n, c1 = 0;
 #pragma unroll
-    for (int q = 0; q < kDenseRows; ++q) {
+    for (int q = 0; q < ROWS; ++q) {
         if (we[q] > ws[q]) {
             c0 = min(c0, ws[q]);
             c1 = max(c1, we[q]);
         }
     }
-    double rv[PASSES][2], dv[kDenseRows][PASSES][2];
+    double rv[PASSES][2], dv[ROWS][PASSES][2];
 #pragma unroll
     for (int i = 0; i < PASSES; ++i) {
         const int64_t c = c0 + 2 * t + 2 * kDenseThreads * i;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
             rv[i][0] = a.x;
             rv[i][1] = a.y;
 #pragma unroll
-            for (int q = 0; q < kDenseRows; ++q) {
+            for (int q = 0; q < ROWS; ++q) {
                 double2 d = make_double2(0.0, 0.0);
                 if (c >= ws[q] && c < we[q])
                     d = *reinterpret_cast<const double2 *>(D + (row0 + q) * n + c);
@@ -152,14 +152,14 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
                 const int64_t cc = c + h;
                 rv[i][h] = cc < c1 ? r[cc] : 0.0;
 #pragma unroll
-                for (int q = 0; q < kDenseRows; ++q)
+                for (int q = 0; q < ROWS; ++q)
                     dv[q][i][h] = cc >= ws[q] && cc < we[q] ? D[(row0 + q) * n + cc] : 0.0;
             }
         }
     }
-    double acc[kDenseRows];
+    double acc[ROWS];
 #pragma unroll
-    for (int q = 0; q < kDenseRows; ++q) {
+    for (int q = 0; q < ROWS; ++q) {
         acc[q] = 0.0;
 #pragma unroll
         for (int i = 0; i < PASSES; ++i) {
@@ -169,13 +169,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     }
     const int lane = t & 63, w = t >> 6;
 #pragma unroll
-    for (int q = 0; q < kDenseRows; ++q) {
+    for (int q = 0; q < ROWS; ++q) {
         double v = acc[q];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
         if (lane == 0) red[q][w] = v;
     }
     __syncthreads();
-    if (t < kDenseRows && row0 + t < n) {
+    if (t < ROWS && row0 + t < n) {
         double v = red[t][0];
 #pragma unroll
         for (int k = 1; k < kDenseWaves; ++k) v += red[t][k];
@@ -233,24 +233,31 @@ __global__ __launch_bounds__(kDenseThreads) void k_mode_transform(const double *
 
 // k_dense_apply with the passes that cover n and 16-byte loads where n is
 // even and D, r are 16-byte aligned.
-template <int PASSES>
+template <int PASSES, int ROWS>
 void launch_apply_p(const double *D, const int *win, const double *r, double *x, int64_t n,
                     const InstState *st, dim3 grid, hipStream_t s)
 {
     const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
-    if (vec) hipLaunchKernelGGL((k_dense_apply<true, PASSES>), grid, dim3(kDenseThreads), 0, s, D, win, r, x, n, st);
-    else hipLaunchKernelGGL((k_dense_apply<false, PASSES>), grid, dim3(kDenseThreads), 0, s, D, win, r, x, n, st);
+    if (vec)
+        hipLaunchKernelGGL((k_dense_apply<true, PASSES, ROWS>), grid, dim3(kDenseThreads), 0, s, D,
+                           win, r, x, n, st);
+    else
+        hipLaunchKernelGGL((k_dense_apply<false, PASSES, ROWS>), grid, dim3(kDenseThreads), 0, s,
+                           D, win, r, x, n, st);
 }
 
+template <int ROWS>
 void launch_apply(const double *D, const int *win, const double *r, double *x, int64_t n,
-                  const InstState *st, dim3 grid, hipStream_t s, int64_t width)
+                  const InstState *st, unsigned nop, hipStream_t s, int64_t width)
 {
-    // the passes cover the widest span a work-group loads (at most n)
+    const dim3 grid((unsigned)((n + ROWS - 1) / ROWS), nop);
+    // the passes cover the widest span a group of kDenseRows rows loads (at
+    // most n), which bounds a single row's
     switch (dense_passes(std::min<int64_t>(n, width))) {
-    case 1: launch_apply_p<1>(D, win, r, x, n, st, grid, s); break;
-    case 2: launch_apply_p<2>(D, win, r, x, n, st, grid, s); break;
-    case 4: launch_apply_p<4>(D, win, r, x, n, st, grid, s); break;
-    default: launch_apply_p<kDensePasses>(D, win, r, x, n, st, grid, s); break;
+    case 1: launch_apply_p<1, ROWS>(D, win, r, x, n, st, grid, s); break;
+    case 2: launch_apply_p<2, ROWS>(D, win, r, x, n, st, grid, s); break;
+    case 4: launch_apply_p<4, ROWS>(D, win, r, x, n, st, grid, s); break;
+    default: launch_apply_p<kDensePasses, ROWS>(D, win, r, x, n, st, grid, s); break;
     }
 }
 
@@ -276,8 +283,7 @@ hipError_t launch_dense_apply_batch(const double *D, const int *win, const doubl
                                     int64_t n, int nop, hipStream_t s, int64_t width)
 {
     if (n < 1 || n > kDenseMaxN || nop < 1 || nop > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows), (unsigned)nop);
-    launch_apply(D, win, r, x, n, nullptr, grid, s, width);
+    launch_apply<kDenseRows>(D, win, r, x, n, nullptr, (unsigned)nop, s, width);
     return hipGetLastError();
 }
 
@@ -302,11 +308,12 @@ hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t
 }
 
 hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
-                              int64_t n, const InstState *st, hipStream_t s, int64_t width)
+                              int64_t n, const InstState *st, hipStream_t s, int64_t width,
+                              bool row_groups)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows));
-    launch_apply(D, win, r, x, n, st, grid, s, width);
+    if (row_groups) launch_apply<kDenseRows>(D, win, r, x, n, st, 1u, s, width);
+    else launch_apply<1>(D, win, r, x, n, st, 1u, s, width);
     return hipGetLastError();
 }
 
