@@ -75,23 +75,26 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_window(const double *__
     }
 }
 
-// x = D r: ROWS rows per work-group.  Thread t takes the column pairs
-// (c, c + 1), c = c0 + 2 t + 2 kDenseThreads i, from the smallest window
+// x = D r: ROWS rows per work-group of THREADS threads.  Thread t takes
+// the column pairs (c, c + 1), c = c0 + 2 t + 2 THREADS i, from the smallest window
 // start c0 of the group's rows, and of each row the pairs inside its window:
 // every load is issued first (16-byte loads; VEC = false: one column at a
 // time, for an odd n or unaligned arrays), then the thread sums its
 // products in column order, and the threads' sums of a row are combined in
 // a fixed order (butterfly within each wavefront, the wavefronts in turn),
 // so every run gives the same bits.  (A pair that ends one past a window
-// adds one more small product.)
-template <bool VEC, int PASSES, int ROWS>
-__global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__restrict__ D,
+// adds one more small product.)  A single wavefront (THREADS = 64) needs
+// no exchange between wavefronts: its butterfly leaves the row's sum in
+// every lane.
+template <bool VEC, int PASSES, int ROWS, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_dense_apply(const double *__restrict__ D,
                                                             const int *__restrict__ win,
                                                             const double *__restrict__ r,
                                                             double *__restrict__ x, int64_t n,
                                                             const InstState *__restrict__ st)
 {
-    __shared__ double red[ROWS][kDenseWaves];
+    constexpr int WAVES = THREADS / 64;
+    __shared__ double red[ROWS][WAVES];
     const int64_t row0 = (int64_t)blockIdx.x * ROWS;
     const int t = threadIdx.x;
     // a batch of operators (the heat equation's sine modes): operator y
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     double rv[PASSES][2], dv[ROWS][PASSES][2];
 #pragma unroll
     for (int i = 0; i < PASSES; ++i) {
-        const int64_t c = c0 + 2 * t + 2 * kDenseThreads * i;
+        const int64_t c = c0 + 2 * t + 2 * THREADS * i;
         if (VEC) {
             double2 a = make_double2(0.0, 0.0);
             if (c < c1) a = *reinterpret_cast<const double2 *>(r + c);
@@ -172,13 +175,18 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_apply(const double *__r
     for (int q = 0; q < ROWS; ++q) {
         double v = acc[q];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) red[q][w] = v;
+        if (WAVES == 1) {
+            if (lane == 0 && row0 + q < n) x[row0 + q] = v;
+        } else if (lane == 0) {
+            red[q][w] = v;
+        }
     }
+    if (WAVES == 1) return;
     __syncthreads();
     if (t < ROWS && row0 + t < n) {
         double v = red[t][0];
 #pragma unroll
-        for (int k = 1; k < kDenseWaves; ++k) v += red[t][k];
+        for (int k = 1; k < WAVES; ++k) v += red[t][k];
         x[row0 + t] = v;
     }
 }
@@ -231,33 +239,42 @@ __global__ __launch_bounds__(kDenseThreads) void k_mode_transform(const double *
     out[(int64_t)a * n + j] = acc;
 }
 
-// k_dense_apply with the passes that cover n and 16-byte loads where n is
-// even and D, r are 16-byte aligned.
-template <int PASSES, int ROWS>
+// k_dense_apply with 16-byte loads where n is even and D, r are 16-byte
+// aligned.
+template <int PASSES, int ROWS, int THREADS>
 void launch_apply_p(const double *D, const int *win, const double *r, double *x, int64_t n,
                     const InstState *st, dim3 grid, hipStream_t s)
 {
     const bool vec = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
     if (vec)
-        hipLaunchKernelGGL((k_dense_apply<true, PASSES, ROWS>), grid, dim3(kDenseThreads), 0, s, D,
-                           win, r, x, n, st);
-    else
-        hipLaunchKernelGGL((k_dense_apply<false, PASSES, ROWS>), grid, dim3(kDenseThreads), 0, s,
+        hipLaunchKernelGGL((k_dense_apply<true, PASSES, ROWS, THREADS>), grid, dim3(THREADS), 0, s,
                            D, win, r, x, n, st);
+    else
+        hipLaunchKernelGGL((k_dense_apply<false, PASSES, ROWS, THREADS>), grid, dim3(THREADS), 0,
+                           s, D, win, r, x, n, st);
 }
 
+// ROWS rows per work-group of kDenseThreads threads, the passes covering
+// the widest span a group of kDenseRows rows loads (at most n), which
+// bounds the span of fewer rows.  One row per work-group whose span fits
+// four passes of a single wavefront runs on one wavefront.
 template <int ROWS>
 void launch_apply(const double *D, const int *win, const double *r, double *x, int64_t n,
                   const InstState *st, unsigned nop, hipStream_t s, int64_t width)
 {
     const dim3 grid((unsigned)((n + ROWS - 1) / ROWS), nop);
-    // the passes cover the widest span a group of kDenseRows rows loads (at
-    // most n), which bounds a single row's
-    switch (dense_passes(std::min<int64_t>(n, width))) {
-    case 1: launch_apply_p<1, ROWS>(D, win, r, x, n, st, grid, s); break;
-    case 2: launch_apply_p<2, ROWS>(D, win, r, x, n, st, grid, s); break;
-    case 4: launch_apply_p<4, ROWS>(D, win, r, x, n, st, grid, s); break;
-    default: launch_apply_p<kDensePasses, ROWS>(D, win, r, x, n, st, grid, s); break;
+    const int64_t span = std::min<int64_t>(n, width);
+    if (ROWS == 1 && span <= 4 * 2 * 64) {
+        if (span <= 2 * 64) launch_apply_p<1, 1, 64>(D, win, r, x, n, st, grid, s);
+        else if (span <= 2 * 2 * 64) launch_apply_p<2, 1, 64>(D, win, r, x, n, st, grid, s);
+        else launch_apply_p<4, 1, 64>(D, win, r, x, n, st, grid, s);
+        return;
+    }
+    switch (dense_passes(span)) {
+    case 1: launch_apply_p<1, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
+    case 2: launch_apply_p<2, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
+    case 4: launch_apply_p<4, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
+    default: launch_apply_p<kDensePasses, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
     }
 }
 
