@@ -671,7 +671,7 @@ int enqueue_bottom(tmg_ctx *c, const CycleIO &io, int level, const T *x_in, T *x
         if (c->dense_ok[d] && c->opt.gamma == 1 && !x_in && level == c->dense_level) {
             HIPCHK(c, launch_dense_apply(c->dense[d], c->dense_win[d], store<T>(c).f[level], x_out,
                                          c->dense_n, io.use_state ? c->st : nullptr, s,
-                                         c->dense_w[d], true));
+                                         c->dense_w[d]));
             return TMG_OK;
         }
     }
@@ -826,11 +826,8 @@ int enqueue_coarse_visits(tmg_ctx *c, const CycleIO &io, int l, hipStream_t s, b
         // the instance's gamma bottom visits from zero in one product
         const int d = io.trans ? 1 : 0;
         if (c->dense_ok[d] && l == c->dense_level) {
-            // a W-cycle's products follow each other with the operator in
-            // the L2 caches: one row per work-group
             HIPCHK(c, launch_dense_apply(c->dense[d], c->dense_win[d], L.f[l], L.x(l, 0), c->dense_n,
-                                         io.use_state ? c->st : nullptr, s, c->dense_w[d],
-                                         c->opt.gamma < 2));
+                                         io.use_state ? c->st : nullptr, s, c->dense_w[d]));
             return TMG_OK;
         }
         // one instance's streaming levels of a W-cycle in fused launches

@@ -13,10 +13,10 @@ namespace {
 
 constexpr int kDenseThreads = 256;          // four wavefronts
 constexpr int kDenseWaves = kDenseThreads / 64;
-// rows per work-group of the product: kDenseRows (one load of r feeds
-// them), or one, whose chain after the loads is a single row's reduction
-// (for products that follow each other with the operator in the L2 caches)
+// rows per work-group of the product's wide form (one load of r feeds
+// them); spans of up to kDenseWaveSpan columns take one row per wavefront
 constexpr int kDenseRows = 4;
+constexpr int kDenseWaveSpan = 4 * 2 * 64;
 // column pairs per thread that cover the largest operator's rows
 constexpr int kDensePasses = (int)(kDenseMaxN / (2 * kDenseThreads));
 // passes that cover n columns (1, 2, 4 or 8: fewer registers, more
@@ -254,27 +254,29 @@ void launch_apply_p(const double *D, const int *win, const double *r, double *x,
                            s, D, win, r, x, n, st);
 }
 
-// ROWS rows per work-group of kDenseThreads threads, the passes covering
-// the widest span a group of kDenseRows rows loads (at most n), which
-// bounds the span of fewer rows.  One row per work-group whose span fits
-// four passes of a single wavefront runs on one wavefront.
-template <int ROWS>
+// The passes cover the widest span a group of kDenseRows rows loads (at
+// most n), which bounds a single row's.  Up to kDenseWaveSpan columns: one
+// row per work-group of a single wavefront (a work-group's chain after its
+// loads is then one butterfly, with no exchange between wavefronts);
+// wider: kDenseRows rows per work-group of kDenseThreads threads.
 void launch_apply(const double *D, const int *win, const double *r, double *x, int64_t n,
                   const InstState *st, unsigned nop, hipStream_t s, int64_t width)
 {
-    const dim3 grid((unsigned)((n + ROWS - 1) / ROWS), nop);
     const int64_t span = std::min<int64_t>(n, width);
-    if (ROWS == 1 && span <= 4 * 2 * 64) {
+    if (span <= kDenseWaveSpan) {
+        const dim3 grid((unsigned)n, nop);
         if (span <= 2 * 64) launch_apply_p<1, 1, 64>(D, win, r, x, n, st, grid, s);
         else if (span <= 2 * 2 * 64) launch_apply_p<2, 1, 64>(D, win, r, x, n, st, grid, s);
         else launch_apply_p<4, 1, 64>(D, win, r, x, n, st, grid, s);
         return;
     }
-    switch (dense_passes(span)) {
-    case 1: launch_apply_p<1, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
-    case 2: launch_apply_p<2, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
-    case 4: launch_apply_p<4, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
-    default: launch_apply_p<kDensePasses, ROWS, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
+    const dim3 grid((unsigned)((n + kDenseRows - 1) / kDenseRows), nop);
+    switch (dense_passes(span)) {   // at least 2 here
+    case 2: launch_apply_p<2, kDenseRows, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
+    case 4: launch_apply_p<4, kDenseRows, kDenseThreads>(D, win, r, x, n, st, grid, s); break;
+    default:
+        launch_apply_p<kDensePasses, kDenseRows, kDenseThreads>(D, win, r, x, n, st, grid, s);
+        break;
     }
 }
 
@@ -300,7 +302,7 @@ hipError_t launch_dense_apply_batch(const double *D, const int *win, const doubl
                                     int64_t n, int nop, hipStream_t s, int64_t width)
 {
     if (n < 1 || n > kDenseMaxN || nop < 1 || nop > 65535) return hipErrorInvalidValue;
-    launch_apply<kDenseRows>(D, win, r, x, n, nullptr, (unsigned)nop, s, width);
+    launch_apply(D, win, r, x, n, nullptr, (unsigned)nop, s, width);
     return hipGetLastError();
 }
 
@@ -325,12 +327,10 @@ hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t
 }
 
 hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
-                              int64_t n, const InstState *st, hipStream_t s, int64_t width,
-                              bool row_groups)
+                              int64_t n, const InstState *st, hipStream_t s, int64_t width)
 {
     if (n < 1 || n > kDenseMaxN) return hipErrorInvalidValue;
-    if (row_groups) launch_apply<kDenseRows>(D, win, r, x, n, st, 1u, s, width);
-    else launch_apply<1>(D, win, r, x, n, st, 1u, s, width);
+    launch_apply(D, win, r, x, n, st, 1u, s, width);
     return hipGetLastError();
 }
 

@@ -325,13 +325,10 @@ hipError_t launch_dense_window(const double *D, int64_t n, int *win, hipStream_t
 // loads, over nop operators of n rows (their windows in win, in turn).
 hipError_t launch_dense_window_max(const int *win, int64_t n, int nop, int *wmax, hipStream_t s);
 // x = D r over the rows' windows (nothing when *st says finished); width:
-// launch_dense_window_max's span (n when unknown), which sets the passes;
-// row_groups: several rows per work-group, sharing their loads of r (false:
-// one row per work-group, the shortest chain, for products that follow
-// each other with the operator in the L2 caches).
+// launch_dense_window_max's span (n when unknown), which sets the passes
+// and the form (one row per wavefront up to 512 columns).
 hipError_t launch_dense_apply(const double *D, const int *win, const double *r, double *x,
-                              int64_t n, const InstState *st, hipStream_t s, int64_t width,
-                              bool row_groups);
+                              int64_t n, const InstState *st, hipStream_t s, int64_t width);
 // nop such products at once: operator y (D + y n^2, win + 2 y n) on
 // r + y n into x + y n.
 hipError_t launch_dense_apply_batch(const double *D, const int *win, const double *r, double *x,
